@@ -1,0 +1,290 @@
+/* rel.h - C-ABI of the MI355X (gfx950) relational hot path:
+ * filter -> hash join (build/probe) -> hash group-by aggregation.
+ *
+ * The operations follow the operator model of "Rethinking Analytical
+ * Processing in the GPU Era" (arXiv 2508.04701):
+ *   - operators are stateless calls; the executor owns all state
+ *     (Section 3.2.2, push-based execution);
+ *   - filter and join produce row ids rather than materialised columns
+ *     (late materialisation, Section 3.2.2; row-id type, Section 3.2.3);
+ *   - hash tables and other intermediates live in a processing region of
+ *     device memory that the caller provides (Section 3.2.3, "Data
+ *     Processing"); inputs stay resident in device memory (Section 3.2.3,
+ *     "Data Caching"; hot runs, Section 4.1).
+ *
+ * Conventions shared by every call:
+ *   Memory     All column data, row-id arrays, outputs, counts and workspaces
+ *              are DEVICE pointers owned by the caller. Descriptor structs
+ *              and the arrays of descriptors are HOST memory, read during
+ *              the call only. The library never allocates device memory.
+ *   Streams    `stream` is a hipStream_t passed as void* (NULL = the default
+ *              stream). Calls only enqueue work: they return before the GPU
+ *              finishes. Outputs and counts are valid once the stream has
+ *              reached that point.
+ *   Errors     Arguments are validated on the host before anything is
+ *              enqueued; on failure nothing is launched and a status other
+ *              than REL_OK is returned, with a message available from
+ *              rel_last_error() in the calling thread. REL_EDEVICE reports a
+ *              failed launch.
+ *   Counts     Result sizes are written to a device int64 (`d_count`,
+ *              `d_groups`) and are always the exact size, even when it
+ *              exceeds `out_cap`; at most `out_cap` items are written.
+ *   Rows       Row counts must be below 2^32 - 1. A row id is the original
+ *              position of a row in its table (uint32).
+ *   Workspace  `ws` must hold at least the bytes that the matching *_ws()
+ *              function returns (REL_ENOMEM otherwise) and be 256-byte
+ *              aligned. Calls that may overlap in time need distinct
+ *              workspaces; the workspace is scratch and its contents are
+ *              undefined after a call.
+ *   Columns    Non-nullable fixed-width integers (int8, int32, int64).
+ *              Decimals are int64 fixed-point values.
+ */
+#ifndef REL_H
+#define REL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define REL_VERSION 1
+
+typedef enum {
+  REL_OK = 0,
+  REL_EINVAL = 1,       /* malformed arguments */
+  REL_ENOMEM = 2,       /* workspace smaller than required */
+  REL_ECAPACITY = 3,    /* an output or table bound was exceeded (reported by helpers) */
+  REL_EDEVICE = 4,      /* a HIP runtime call or kernel launch failed */
+  REL_EUNSUPPORTED = 5  /* well-formed request outside what this build implements */
+} rel_status;
+
+typedef enum { REL_I8 = 1, REL_I32 = 2, REL_I64 = 3 } rel_dtype;
+
+typedef uint32_t rel_rowid;
+
+/* A logical column of `len` elements. Without `idx`, element i is data[i]
+ * and carries row id i. With `idx` (device array of `len` row ids), element
+ * i is data[idx[i]] and carries row id idx[i]: this is how a filter's or a
+ * join's row-id output feeds the next operator without materialising
+ * columns. */
+typedef struct {
+  const void* data;
+  const rel_rowid* idx;
+  int64_t len;
+  int32_t type; /* rel_dtype */
+  int32_t reserved;
+} rel_column;
+
+/* Comparison term; the value v is the element widened to int64 (signed).
+ * REL_RANGE holds when lo <= v < hi; every other operator compares v with
+ * lo (v < lo, v <= lo, v > lo, v >= lo, v == lo, v != lo). */
+typedef enum { REL_LT = 0, REL_LE = 1, REL_GT = 2, REL_GE = 3, REL_EQ = 4, REL_NE = 5, REL_RANGE = 6 } rel_cmp;
+
+typedef struct {
+  int32_t col; /* index into the call's column array */
+  int32_t op;  /* rel_cmp */
+  int64_t lo;
+  int64_t hi;
+} rel_pred;
+
+/* SUM wraps modulo 2^64; COUNT counts rows; MIN and MAX are signed; AVG is
+ * the binary64 quotient (double)SUM / (double)COUNT rounded to nearest even
+ * (an ungrouped AVG over no rows is the quiet NaN 0x7FF8000000000000).
+ * SUM, COUNT, MIN and MAX are written as int64, AVG as double. */
+typedef enum { REL_SUM = 0, REL_COUNT = 1, REL_MIN = 2, REL_MAX = 3, REL_AVG = 4 } rel_agg_op;
+
+typedef struct {
+  int32_t op;  /* rel_agg_op */
+  int32_t col; /* value column index (ignored for REL_COUNT) */
+} rel_agg;
+
+/* Optional tuning; pass NULL (or zero fields) for the defaults. */
+typedef struct {
+  float load_factor; /* hash-table fill target in (0, 0.9]; 0 = default (0.5) */
+  int32_t block;     /* threads per workgroup, a multiple of 64 up to 1024; 0 = default */
+  int32_t grid;      /* workgroups of persistent kernels; 0 = default (from the CU count) */
+  int32_t lds_slots; /* slots of the per-workgroup LDS group table; 0 = default, -1 = none */
+  int32_t flags;     /* reserved, must be 0 */
+  int32_t reserved[3];
+} rel_tuning;
+
+#define REL_MAX_TERMS 4
+#define REL_MAX_DIMS 2
+#define REL_MAX_KEYS 2
+#define REL_MAX_AGGS 8
+#define REL_MAX_FACT_COLS 8
+
+/* ----------------------------------------------------------------- basics */
+
+/* Static text for a status code. */
+const char* rel_status_str(rel_status s);
+
+/* Message of the last failed call made by this thread ("" if none). */
+const char* rel_last_error(void);
+
+/* REL_VERSION of the built library. */
+int rel_version(void);
+
+/* --------------------------------------------------------------- filter */
+
+/* Workspace bytes for rel_filter over n rows. */
+size_t rel_filter_ws(int64_t n);
+
+/* Selection (Section 4.2 names filters as the dominant cost of filter-heavy
+ * queries; Section 3.2.2 lists predicate pushdown among the custom kernels):
+ * writes the row ids of the elements of `cols` that satisfy every term of
+ * the conjunction `preds`, in ascending element order.
+ *   cols, ncols    1..REL_MAX_FACT_COLS columns of equal len; all share the
+ *                  same idx pointer (or all have none).
+ *   preds, npreds  1..REL_MAX_TERMS terms over those columns.
+ *   out, out_cap   device row-id array; the first min(count, out_cap) ids.
+ *   d_count        device int64: the number of passing elements.
+ * Errors: REL_EINVAL for mismatched lengths or idx, bad term columns or
+ * operators, NULL pointers; REL_ENOMEM for a short workspace. */
+rel_status rel_filter(const rel_column* cols, int ncols, const rel_pred* preds, int npreds,
+                      rel_rowid* out, int64_t out_cap, int64_t* d_count, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------ hash join */
+
+/* Workspace bytes for rel_hash_join with n_build build rows. */
+size_t rel_hash_join_ws(int32_t key_type, int64_t n_build, const rel_tuning* t);
+
+/* Inner equi-join (the hash join of Sections 1 and 4.2): builds an
+ * open-addressing hash table over build_keys in the workspace, then probes it
+ * with probe_keys and writes every matching pair (build row id, probe row
+ * id). Duplicate keys on either side yield every pair. Pair order is
+ * unspecified (compare after sorting by (probe, build)).
+ *   build_keys, probe_keys  int32 or int64 columns of the same type.
+ *   out_build, out_probe    device row-id arrays of out_cap entries.
+ *   d_count                 device int64: the exact number of pairs.
+ * Errors: REL_EINVAL for NULL or mismatched types; REL_ENOMEM for a short
+ * workspace. */
+rel_status rel_hash_join(const rel_column* build_keys, const rel_column* probe_keys,
+                         rel_rowid* out_build, rel_rowid* out_probe, int64_t out_cap,
+                         int64_t* d_count, const rel_tuning* t, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* ------------------------------------------------------------- group-by */
+
+/* Workspace bytes for rel_groupby_agg with at most max_groups groups. */
+size_t rel_groupby_ws(int nkeys, const int32_t* key_types, int naggs, const rel_agg* aggs,
+                      int64_t max_groups, const rel_tuning* t);
+
+/* Hash group-by aggregation (Section 4.2: hash-based grouping, with memory
+ * contention when there are few groups): one output row per distinct key
+ * tuple of `keys` (0..REL_MAX_KEYS columns; with none, exactly one row, even
+ * over no input rows), with the aggregates `aggs` over the value columns
+ * `vals`. Row order is unspecified (compare after sorting by key tuple).
+ *   keys, vals     columns of equal len (idx allowed). Key tuples must pack
+ *                  into 64 bits (int8 = 8, int32 = 32, int64 = 64 bits).
+ *   out_keys[k]    device array of out_cap elements of key k's own type.
+ *   out_aggs[a]    device array of out_cap int64 (AVG: double).
+ *   d_groups       device int64: the number of groups, or -1 when the input
+ *                  holds more distinct groups than the table sized for
+ *                  max_groups can take (outputs are then undefined).
+ * Errors: REL_EINVAL, REL_ENOMEM, REL_EUNSUPPORTED (key tuple wider than
+ * 64 bits). */
+rel_status rel_groupby_agg(const rel_column* keys, int nkeys, const rel_column* vals, int nvals,
+                           const rel_agg* aggs, int naggs, void* const* out_keys,
+                           void* const* out_aggs, int64_t out_cap, int64_t* d_groups,
+                           int64_t max_groups, const rel_tuning* t, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* ------------------------------------------------------------- pipeline */
+
+/* One dimension join of the fused plan: fact column `fact_col` is a foreign
+ * key into `key`; if `has_payload`, `payload` (int8 or int32, same len as
+ * `key`) is a dim attribute that a group key may use. Dim columns take no
+ * idx. */
+typedef struct {
+  int32_t fact_col;
+  int32_t has_payload;
+  rel_column key;
+  rel_column payload;
+} rel_dim;
+
+typedef enum { REL_KEY_FACT = 0, REL_KEY_DIM = 1 } rel_key_src;
+
+/* A group key: fact column `col` (REL_KEY_FACT) or the payload of dim `col`
+ * (REL_KEY_DIM). */
+typedef struct {
+  int32_t src;
+  int32_t col;
+} rel_key_ref;
+
+/* Fixed-shape plan: conjunctive filter on fact columns -> inner join with up
+ * to two dims -> group-by. Fact columns are plain (no idx). */
+typedef struct {
+  const rel_column* fact;
+  int32_t n_fact; /* 1..REL_MAX_FACT_COLS */
+  const rel_pred* preds;
+  int32_t n_preds; /* 0..REL_MAX_TERMS, over fact columns */
+  const rel_dim* dims;
+  int32_t n_dims; /* 0..REL_MAX_DIMS */
+  const rel_key_ref* keys;
+  int32_t n_keys; /* 0..REL_MAX_KEYS */
+  const rel_agg* aggs;
+  int32_t n_aggs; /* 1..REL_MAX_AGGS, over fact columns */
+  int64_t max_groups;
+  const rel_tuning* tuning; /* NULL = defaults */
+} rel_pipeline_desc;
+
+/* Group outputs: keys[k] has the type of its source column; aggs[a] is
+ * int64 (AVG: double); cap entries each; d_groups as in rel_groupby_agg. */
+typedef struct {
+  void* keys[REL_MAX_KEYS];
+  void* aggs[REL_MAX_AGGS];
+  int64_t cap;
+  int64_t* d_groups;
+} rel_outputs;
+
+/* Workspace bytes for rel_pipeline on plan d. */
+size_t rel_pipeline_ws(const rel_pipeline_desc* d);
+
+/* The whole plan on the GPU, from scan to result (Section 3.1): builds the
+ * dim hash tables, then one fused pass over the fact table evaluates the
+ * predicate, probes the dims and aggregates; a last pass writes the groups.
+ * Per fact row passing the predicate, each combination of matching dim rows
+ * contributes once (inner-join semantics; no match drops the row).
+ * Errors: REL_EINVAL, REL_ENOMEM, REL_EUNSUPPORTED (key tuple wider than
+ * 64 bits, int64 dim payloads). */
+rel_status rel_pipeline(const rel_pipeline_desc* d, const rel_outputs* o, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------- profiling */
+
+/* Kernel classes timed by the per-kernel profiler (the per-operator time
+ * breakdown of Section 4.2, "Performance Breakdown"). */
+typedef enum {
+  REL_K_FILL = 0,        /* workspace initialisation (tables, counters) */
+  REL_K_FILTER = 1,      /* rel_filter's compaction kernel */
+  REL_K_MAP_BUILD = 2,   /* hash-table build (join build side, dims) */
+  REL_K_MAP_PROBE = 3,   /* join probe with pair output */
+  REL_K_GROUP_AGG = 4,   /* rel_groupby_agg's aggregation kernel */
+  REL_K_PIPELINE = 5,    /* rel_pipeline's fused filter-probe-aggregate kernel */
+  REL_K_FINALIZE = 6,    /* group compaction into the outputs */
+  REL_K_COUNT = 7
+} rel_kernel_class;
+
+/* Static name of a kernel class. */
+const char* rel_kernel_name(int k);
+
+/* Turns per-kernel timing on (1) or off (0) for calls made afterwards from
+ * any thread. While on, every kernel launch is bracketed by two HIP events
+ * recorded on the caller's stream. */
+void rel_profile_enable(int on);
+
+/* Waits for the recorded events, then writes, for each kernel class k <
+ * REL_K_COUNT (host arrays of REL_K_COUNT entries), the summed device time
+ * in milliseconds and the number of launches since the last read, and
+ * clears them. Returns REL_EDEVICE if an event query fails. */
+rel_status rel_profile_read(double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REL_H */

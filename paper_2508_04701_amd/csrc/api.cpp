@@ -1,0 +1,712 @@
+// C-ABI entry points of librel.so (declared in include/rel.h).
+//
+// Every call validates its arguments on the host before touching the HIP
+// runtime, so malformed requests fail without a GPU. It then carves the
+// caller's workspace into the operator's hash tables and counters, and
+// enqueues the kernels on the caller's stream. Nothing here allocates device
+// memory and nothing here falls back to the CPU.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+#include "rel.h"
+
+namespace rel {
+
+namespace {
+
+thread_local std::string g_error;
+
+rel_status fail(rel_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return s;
+}
+
+constexpr int64_t kMaxRows = 0xFFFFFFFELL;  // row ids must stay below the all-ones value
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+uint64_t next_pow2(uint64_t v) {
+  uint64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+bool valid_type(int32_t t) { return t == REL_I8 || t == REL_I32 || t == REL_I64; }
+int type_bits(int32_t t) { return t == REL_I8 ? 8 : (t == REL_I32 ? 32 : 64); }
+
+float load_factor(const rel_tuning* t) {
+  float lf = (t && t->load_factor > 0.0f) ? t->load_factor : 0.5f;
+  return lf > 0.9f ? 0.9f : lf;
+}
+
+rel_status check_tuning(const rel_tuning* t) {
+  if (!t) return REL_OK;
+  if (t->load_factor < 0.0f || t->load_factor > 0.9f || std::isnan(t->load_factor))
+    return fail(REL_EINVAL, "tuning.load_factor must be in (0, 0.9] (or 0 for the default)");
+  if (t->block < 0 || t->block > 1024 || t->block % 64 != 0)
+    return fail(REL_EINVAL, "tuning.block must be a multiple of 64 up to 1024 (or 0)");
+  if (t->grid < 0) return fail(REL_EINVAL, "tuning.grid must be >= 0");
+  if (t->lds_slots < -1 || (t->lds_slots > 0 && (t->lds_slots & (t->lds_slots - 1)) != 0))
+    return fail(REL_EINVAL, "tuning.lds_slots must be -1, 0 or a power of two");
+  if (t->flags != 0) return fail(REL_EINVAL, "tuning.flags must be 0");
+  return REL_OK;
+}
+
+rel_status check_column(const rel_column* c, const char* what) {
+  if (!c) return fail(REL_EINVAL, "%s: NULL column", what);
+  if (!valid_type(c->type)) return fail(REL_EINVAL, "%s: invalid type %d", what, c->type);
+  if (c->len < 0 || c->len > kMaxRows)
+    return fail(REL_EUNSUPPORTED, "%s: length %lld outside [0, 2^32-2]", what, (long long)c->len);
+  if (c->len > 0 && !c->data) return fail(REL_EINVAL, "%s: NULL data", what);
+  return REL_OK;
+}
+
+rel_status check_ws(void* ws, size_t ws_bytes, size_t need) {
+  if (ws_bytes < need)
+    return fail(REL_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  if (!ws) return fail(REL_EINVAL, "NULL workspace");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0)
+    return fail(REL_EINVAL, "workspace must be 256-byte aligned");
+  return REL_OK;
+}
+
+bool debug_sync() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("REL_DEBUG_SYNC");
+    v = (e && e[0] == '1') ? 1 : 0;
+  }
+  return v == 1;
+}
+
+rel_status after_launch(hipStream_t s, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && debug_sync()) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(REL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return REL_OK;
+}
+
+// ---------------------------------------------------------- hash map sizes
+
+struct MapLayout {
+  uint64_t cap;
+  size_t slots_off, oob_count_off, oob_vals_off, end;
+};
+
+MapLayout map_layout(int32_t key_type, int64_t n, float lf, size_t base) {
+  MapLayout m;
+  uint64_t want = static_cast<uint64_t>(std::ceil(static_cast<double>(n) / lf));
+  m.cap = next_pow2(want < 64 ? 64 : want);
+  if (m.cap <= static_cast<uint64_t>(n)) m.cap = next_pow2(static_cast<uint64_t>(n) + 1);
+  size_t slot = key_type == REL_I64 ? 16 : 8;
+  m.slots_off = base;
+  m.oob_count_off = align_up(m.slots_off + m.cap * slot);
+  m.oob_vals_off = m.oob_count_off + kAlign;
+  m.end = align_up(m.oob_vals_off + static_cast<size_t>(n > 0 ? n : 1) * 4);
+  return m;
+}
+
+MapDesc map_desc(const MapLayout& l, int32_t key_type, unsigned char* ws) {
+  MapDesc d;
+  d.key_type = key_type == REL_I64 ? kI64 : kI32;
+  d.cap = l.cap;
+  d.slots = ws + l.slots_off;
+  d.oob_count = reinterpret_cast<unsigned long long*>(ws + l.oob_count_off);
+  d.oob_vals = reinterpret_cast<uint32_t*>(ws + l.oob_vals_off);
+  return d;
+}
+
+// ---------------------------------------------------------- group tables
+
+struct GroupPlan {
+  GroupKeyPack kp;
+  AccPlan ap;
+  int32_t agg_acc[REL_MAX_AGGS];
+  int32_t words;
+};
+
+int acc_index(AccPlan& ap, int32_t kind, int32_t col) {
+  for (int a = 0; a < ap.nacc; ++a)
+    if (ap.kind[a] == kind && ap.col[a] == col) return a;
+  ap.kind[ap.nacc] = kind;
+  ap.col[ap.nacc] = col;
+  return ap.nacc++;
+}
+
+// Key types and aggregates -> packing and accumulators (validated already).
+rel_status group_plan(int nkeys, const int32_t* key_types, int naggs, const rel_agg* aggs,
+                      GroupPlan& gp) {
+  std::memset(&gp, 0, sizeof gp);
+  gp.kp.nkeys = nkeys;
+  int bits = 0;
+  for (int k = 0; k < nkeys; ++k) {
+    gp.kp.type[k] = key_types[k];
+    bits += type_bits(key_types[k]);
+  }
+  if (bits > 64)
+    return fail(REL_EUNSUPPORTED, "group key tuple of %d bits; at most 64 are supported", bits);
+  gp.kp.shift0 = nkeys == 2 ? type_bits(key_types[1]) : 0;
+  for (int a = 0; a < naggs; ++a) {
+    switch (aggs[a].op) {
+      case REL_SUM:
+      case REL_AVG: gp.agg_acc[a] = acc_index(gp.ap, kAccSum, aggs[a].col); break;
+      case REL_MIN: gp.agg_acc[a] = acc_index(gp.ap, kAccMin, aggs[a].col); break;
+      case REL_MAX: gp.agg_acc[a] = acc_index(gp.ap, kAccMax, aggs[a].col); break;
+      default: gp.agg_acc[a] = -1; break;
+    }
+  }
+  gp.words = 2 + gp.ap.nacc;
+  gp.words += gp.words & 1;
+  return REL_OK;
+}
+
+struct GroupLayout {
+  uint64_t cap;
+  size_t slots_off, overflow_off, end;
+};
+
+GroupLayout group_layout(const GroupPlan& gp, int64_t max_groups, float lf, size_t base) {
+  GroupLayout g;
+  uint64_t want = static_cast<uint64_t>(std::ceil(static_cast<double>(max_groups < 1 ? 1 : max_groups) / lf));
+  g.cap = next_pow2(want < 64 ? 64 : want);
+  g.slots_off = base;
+  g.overflow_off = align_up(g.slots_off + (g.cap + 1) * gp.words * 8);
+  g.end = g.overflow_off + kAlign;
+  return g;
+}
+
+GroupDesc group_desc(const GroupPlan& gp, const GroupLayout& l, unsigned char* ws,
+                     int64_t* d_groups) {
+  GroupDesc g;
+  g.kp = gp.kp;
+  g.ap = gp.ap;
+  g.cap = l.cap;
+  g.words = gp.words;
+  g.slots = reinterpret_cast<uint64_t*>(ws + l.slots_off);
+  g.overflow = reinterpret_cast<int32_t*>(ws + l.overflow_off);
+  g.d_groups = reinterpret_cast<unsigned long long*>(d_groups);
+  return g;
+}
+
+rel_status check_aggs(const rel_agg* aggs, int naggs, int ncols, const char* what) {
+  if (naggs < 1 || naggs > REL_MAX_AGGS)
+    return fail(REL_EINVAL, "%s: 1..%d aggregates required", what, REL_MAX_AGGS);
+  if (!aggs) return fail(REL_EINVAL, "%s: NULL aggregates", what);
+  for (int a = 0; a < naggs; ++a) {
+    if (aggs[a].op < REL_SUM || aggs[a].op > REL_AVG)
+      return fail(REL_EINVAL, "%s: aggregate %d has invalid op %d", what, a, aggs[a].op);
+    if (aggs[a].op != REL_COUNT && (aggs[a].col < 0 || aggs[a].col >= ncols))
+      return fail(REL_EINVAL, "%s: aggregate %d reads column %d of %d", what, a, aggs[a].col, ncols);
+  }
+  return REL_OK;
+}
+
+int default_lds_slots(const rel_tuning* t, int64_t max_groups, int words, size_t budget) {
+  if (t && t->lds_slots == -1) return 0;
+  uint64_t max_by_lds = next_pow2(budget / (static_cast<size_t>(words) * 8) + 1) / 2;
+  uint64_t want = (t && t->lds_slots > 0) ? static_cast<uint64_t>(t->lds_slots)
+                                          : next_pow2(2 * static_cast<uint64_t>(max_groups < 32 ? 32 : max_groups));
+  if (want > max_by_lds) want = max_by_lds;
+  return static_cast<int>(want);
+}
+
+FinalizeParams finalize_params(const GroupDesc& g, const GroupPlan& gp, const rel_agg* aggs,
+                               int naggs, void* const* out_keys, const int32_t* key_types,
+                               void* const* out_aggs, int64_t cap) {
+  FinalizeParams f;
+  std::memset(&f, 0, sizeof f);
+  f.g = g;
+  f.naggs = naggs;
+  for (int a = 0; a < naggs; ++a) {
+    f.op[a] = aggs[a].op;
+    f.acc[a] = gp.agg_acc[a] < 0 ? 0 : gp.agg_acc[a];
+    f.out_aggs[a] = out_aggs ? out_aggs[a] : nullptr;
+  }
+  for (int k = 0; k < gp.kp.nkeys; ++k) {
+    f.out_keys[k] = out_keys ? out_keys[k] : nullptr;
+    f.out_key_type[k] = key_types[k];
+  }
+  f.cap = cap;
+  return f;
+}
+
+rel_status check_outputs(void* const* out_keys, int nkeys, void* const* out_aggs, int naggs,
+                         int64_t cap, const void* d_groups) {
+  if (cap < 0) return fail(REL_EINVAL, "negative output capacity");
+  if (!d_groups) return fail(REL_EINVAL, "NULL group count");
+  if (cap > 0) {
+    if (nkeys > 0 && !out_keys) return fail(REL_EINVAL, "NULL key outputs");
+    for (int k = 0; k < nkeys; ++k)
+      if (!out_keys[k]) return fail(REL_EINVAL, "NULL output for key %d", k);
+    if (!out_aggs) return fail(REL_EINVAL, "NULL aggregate outputs");
+    for (int a = 0; a < naggs; ++a)
+      if (!out_aggs[a]) return fail(REL_EINVAL, "NULL output for aggregate %d", a);
+  }
+  return REL_OK;
+}
+
+// ---------------------------------------------------------- pipeline plan
+
+struct PipeLayout {
+  MapLayout dim[REL_MAX_DIMS];
+  GroupPlan gp;
+  GroupLayout group;
+  int32_t key_types[REL_MAX_KEYS];
+  size_t end;
+};
+
+rel_status check_pipeline(const rel_pipeline_desc* d) {
+  if (!d) return fail(REL_EINVAL, "NULL pipeline description");
+  if (d->n_fact < 1 || d->n_fact > REL_MAX_FACT_COLS || !d->fact)
+    return fail(REL_EINVAL, "pipeline: 1..%d fact columns required", REL_MAX_FACT_COLS);
+  for (int c = 0; c < d->n_fact; ++c) {
+    rel_status st = check_column(&d->fact[c], "pipeline fact column");
+    if (st) return st;
+    if (d->fact[c].idx) return fail(REL_EUNSUPPORTED, "pipeline: fact columns take no idx");
+    if (d->fact[c].len != d->fact[0].len)
+      return fail(REL_EINVAL, "pipeline: fact columns differ in length");
+  }
+  if (d->n_preds < 0 || d->n_preds > REL_MAX_TERMS || (d->n_preds > 0 && !d->preds))
+    return fail(REL_EINVAL, "pipeline: 0..%d predicate terms", REL_MAX_TERMS);
+  for (int t = 0; t < d->n_preds; ++t) {
+    if (d->preds[t].col < 0 || d->preds[t].col >= d->n_fact)
+      return fail(REL_EINVAL, "pipeline: term %d reads column %d", t, d->preds[t].col);
+    if (d->preds[t].op < REL_LT || d->preds[t].op > REL_RANGE)
+      return fail(REL_EINVAL, "pipeline: term %d has invalid op %d", t, d->preds[t].op);
+  }
+  if (d->n_dims < 0 || d->n_dims > REL_MAX_DIMS || (d->n_dims > 0 && !d->dims))
+    return fail(REL_EINVAL, "pipeline: 0..%d dims", REL_MAX_DIMS);
+  for (int i = 0; i < d->n_dims; ++i) {
+    const rel_dim& dm = d->dims[i];
+    if (dm.fact_col < 0 || dm.fact_col >= d->n_fact)
+      return fail(REL_EINVAL, "pipeline: dim %d foreign key column %d", i, dm.fact_col);
+    rel_status st = check_column(&dm.key, "pipeline dim key");
+    if (st) return st;
+    if (dm.key.idx) return fail(REL_EUNSUPPORTED, "pipeline: dim columns take no idx");
+    if (dm.key.type == REL_I8) return fail(REL_EUNSUPPORTED, "pipeline: int8 dim keys");
+    int32_t fk = d->fact[dm.fact_col].type;
+    if (!(fk == dm.key.type || (fk == REL_I8 && dm.key.type == REL_I32) ||
+          (fk == REL_I8 && dm.key.type == REL_I64) || (fk == REL_I32 && dm.key.type == REL_I64)))
+      return fail(REL_EINVAL, "pipeline: dim %d key type %d cannot hold foreign keys of type %d", i,
+                  dm.key.type, fk);
+    if (dm.has_payload) {
+      st = check_column(&dm.payload, "pipeline dim payload");
+      if (st) return st;
+      if (dm.payload.idx) return fail(REL_EUNSUPPORTED, "pipeline: dim columns take no idx");
+      if (dm.payload.type == REL_I64) return fail(REL_EUNSUPPORTED, "pipeline: int64 dim payloads");
+      if (dm.payload.len != dm.key.len)
+        return fail(REL_EINVAL, "pipeline: dim %d payload and key lengths differ", i);
+    }
+  }
+  if (d->n_keys < 0 || d->n_keys > REL_MAX_KEYS || (d->n_keys > 0 && !d->keys))
+    return fail(REL_EINVAL, "pipeline: 0..%d group keys", REL_MAX_KEYS);
+  for (int k = 0; k < d->n_keys; ++k) {
+    const rel_key_ref& kr = d->keys[k];
+    if (kr.src == REL_KEY_FACT) {
+      if (kr.col < 0 || kr.col >= d->n_fact) return fail(REL_EINVAL, "pipeline: key %d column", k);
+    } else if (kr.src == REL_KEY_DIM) {
+      if (kr.col < 0 || kr.col >= d->n_dims || !d->dims[kr.col].has_payload)
+        return fail(REL_EINVAL, "pipeline: key %d needs a dim with a payload", k);
+    } else {
+      return fail(REL_EINVAL, "pipeline: key %d has invalid source %d", k, kr.src);
+    }
+  }
+  rel_status st = check_aggs(d->aggs, d->n_aggs, d->n_fact, "pipeline");
+  if (st) return st;
+  if (d->max_groups < 0) return fail(REL_EINVAL, "pipeline: negative max_groups");
+  return check_tuning(d->tuning);
+}
+
+rel_status pipeline_layout(const rel_pipeline_desc* d, PipeLayout& L) {
+  const float lf = load_factor(d->tuning);
+  size_t off = 0;
+  for (int i = 0; i < d->n_dims; ++i) {
+    L.dim[i] = map_layout(d->dims[i].key.type, d->dims[i].key.len, lf < 0.75f ? 0.75f : lf, off);
+    off = L.dim[i].end;
+  }
+  for (int k = 0; k < d->n_keys; ++k) {
+    const rel_key_ref& kr = d->keys[k];
+    L.key_types[k] = kr.src == REL_KEY_FACT ? d->fact[kr.col].type : d->dims[kr.col].payload.type;
+  }
+  rel_status st = group_plan(d->n_keys, L.key_types, d->n_aggs, d->aggs, L.gp);
+  if (st) return st;
+  L.group = group_layout(L.gp, d->max_groups, lf, off);
+  L.end = L.group.end;
+  return REL_OK;
+}
+
+}  // namespace
+
+const DeviceInfo& device_info() {
+  static DeviceInfo info[64];
+  static bool have[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (!have[dev]) {
+    int cus = 0, lds = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        lds <= 0)
+      lds = 65536;
+    info[dev].cu_count = cus;
+    info[dev].lds_per_block = lds;
+    have[dev] = true;
+  }
+  return info[dev];
+}
+
+}  // namespace rel
+
+using namespace rel;
+
+extern "C" {
+
+const char* rel_status_str(rel_status s) {
+  switch (s) {
+    case REL_OK: return "ok";
+    case REL_EINVAL: return "invalid argument";
+    case REL_ENOMEM: return "workspace too small";
+    case REL_ECAPACITY: return "capacity exceeded";
+    case REL_EDEVICE: return "device error";
+    case REL_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* rel_last_error(void) { return g_error.c_str(); }
+
+int rel_version(void) { return REL_VERSION; }
+
+// ------------------------------------------------------------------ filter
+
+size_t rel_filter_ws(int64_t n) {
+  int64_t tiles = n > 0 ? (n + kFilterTile - 1) / kFilterTile : 1;
+  return align_up(kAlign + static_cast<size_t>(tiles) * 8);
+}
+
+rel_status rel_filter(const rel_column* cols, int ncols, const rel_pred* preds, int npreds,
+                      rel_rowid* out, int64_t out_cap, int64_t* d_count, void* ws,
+                      size_t ws_bytes, void* stream) {
+  g_error.clear();
+  if (!cols || ncols < 1 || ncols > REL_MAX_FACT_COLS)
+    return fail(REL_EINVAL, "filter: 1..%d columns required", REL_MAX_FACT_COLS);
+  for (int c = 0; c < ncols; ++c) {
+    rel_status st = check_column(&cols[c], "filter column");
+    if (st) return st;
+    if (cols[c].len != cols[0].len) return fail(REL_EINVAL, "filter: columns differ in length");
+    if (cols[c].idx != cols[0].idx) return fail(REL_EINVAL, "filter: columns must share one idx");
+  }
+  if (!preds || npreds < 1 || npreds > REL_MAX_TERMS)
+    return fail(REL_EINVAL, "filter: 1..%d terms required", REL_MAX_TERMS);
+  for (int t = 0; t < npreds; ++t) {
+    if (preds[t].col < 0 || preds[t].col >= ncols)
+      return fail(REL_EINVAL, "filter: term %d reads column %d of %d", t, preds[t].col, ncols);
+    if (preds[t].op < REL_LT || preds[t].op > REL_RANGE)
+      return fail(REL_EINVAL, "filter: term %d has invalid op %d", t, preds[t].op);
+  }
+  if (out_cap < 0 || (out_cap > 0 && !out)) return fail(REL_EINVAL, "filter: bad output");
+  if (!d_count) return fail(REL_EINVAL, "filter: NULL count");
+  const int64_t n = cols[0].len;
+  rel_status st = check_ws(ws, ws_bytes, rel_filter_ws(n));
+  if (st) return st;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  FilterParams p;
+  std::memset(&p, 0, sizeof p);
+  for (int t = 0; t < npreds; ++t) {
+    const rel_column& c = cols[preds[t].col];
+    p.term[t].data = c.data;
+    p.term[t].type = c.type;
+    p.term[t].op = preds[t].op;
+    p.term[t].lo = preds[t].lo;
+    p.term[t].hi = preds[t].hi;
+    p.term[t].vec = (reinterpret_cast<uintptr_t>(c.data) % 16) == 0;
+  }
+  p.nterms = npreds;
+  p.idx = cols[0].idx;
+  p.n = n;
+  p.out = out;
+  p.cap = out_cap;
+  p.d_count = reinterpret_cast<long long*>(d_count);
+  p.ticket = reinterpret_cast<uint32_t*>(w);
+  p.tile_state = reinterpret_cast<uint64_t*>(w + kAlign);
+  p.ntiles = n > 0 ? (n + kFilterTile - 1) / kFilterTile : 1;
+  launch_fill64(reinterpret_cast<uint64_t*>(w), (kAlign + p.ntiles * 8) / 8, 0, s);
+  launch_filter(p, s);
+  return after_launch(s, "filter");
+}
+
+// --------------------------------------------------------------- hash join
+
+size_t rel_hash_join_ws(int32_t key_type, int64_t n_build, const rel_tuning* t) {
+  if ((key_type != REL_I32 && key_type != REL_I64) || n_build < 0) return 0;
+  return map_layout(key_type, n_build, load_factor(t), 0).end;
+}
+
+rel_status rel_hash_join(const rel_column* build_keys, const rel_column* probe_keys,
+                         rel_rowid* out_build, rel_rowid* out_probe, int64_t out_cap,
+                         int64_t* d_count, const rel_tuning* t, void* ws, size_t ws_bytes,
+                         void* stream) {
+  g_error.clear();
+  rel_status st = check_column(build_keys, "join build keys");
+  if (st) return st;
+  st = check_column(probe_keys, "join probe keys");
+  if (st) return st;
+  if (build_keys->type != probe_keys->type)
+    return fail(REL_EINVAL, "join: build and probe key types differ");
+  if (build_keys->type == REL_I8) return fail(REL_EUNSUPPORTED, "join: int8 keys");
+  if (out_cap < 0 || (out_cap > 0 && (!out_build || !out_probe)))
+    return fail(REL_EINVAL, "join: bad outputs");
+  if (!d_count) return fail(REL_EINVAL, "join: NULL count");
+  st = check_tuning(t);
+  if (st) return st;
+  const MapLayout L = map_layout(build_keys->type, build_keys->len, load_factor(t), 0);
+  st = check_ws(ws, ws_bytes, L.end);
+  if (st) return st;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  const MapDesc m = map_desc(L, build_keys->type, w);
+  launch_map_init(m, s);
+  MapBuildParams b;
+  std::memset(&b, 0, sizeof b);
+  b.map = m;
+  b.keys = build_keys->data;
+  b.idx = build_keys->idx;
+  b.type = build_keys->type;
+  b.n = build_keys->len;
+  launch_map_build(b, s);
+  launch_fill64(reinterpret_cast<uint64_t*>(d_count), 1, 0, s);
+  MapProbeParams p;
+  std::memset(&p, 0, sizeof p);
+  p.map = m;
+  p.keys = probe_keys->data;
+  p.idx = probe_keys->idx;
+  p.type = probe_keys->type;
+  p.n = probe_keys->len;
+  p.out_build = out_build;
+  p.out_probe = out_probe;
+  p.cap = out_cap;
+  p.d_count = reinterpret_cast<unsigned long long*>(d_count);
+  const DeviceInfo& di = device_info();
+  int64_t blocks = (p.n + 255) / 256;
+  int64_t limit = (t && t->grid > 0) ? t->grid : static_cast<int64_t>(di.cu_count) * 16;
+  if (blocks > limit) blocks = limit;
+  launch_map_probe(p, static_cast<int>(blocks < 1 ? 1 : blocks), 256, s);
+  return after_launch(s, "hash join");
+}
+
+// ---------------------------------------------------------------- group-by
+
+size_t rel_groupby_ws(int nkeys, const int32_t* key_types, int naggs, const rel_agg* aggs,
+                      int64_t max_groups, const rel_tuning* t) {
+  if (nkeys < 0 || nkeys > REL_MAX_KEYS || naggs < 1 || naggs > REL_MAX_AGGS || !aggs ||
+      (nkeys > 0 && !key_types) || max_groups < 0)
+    return 0;
+  for (int k = 0; k < nkeys; ++k)
+    if (!valid_type(key_types[k])) return 0;
+  GroupPlan gp;
+  if (group_plan(nkeys, key_types, naggs, aggs, gp) != REL_OK) return 0;
+  return group_layout(gp, max_groups, load_factor(t), 0).end;
+}
+
+rel_status rel_groupby_agg(const rel_column* keys, int nkeys, const rel_column* vals, int nvals,
+                           const rel_agg* aggs, int naggs, void* const* out_keys,
+                           void* const* out_aggs, int64_t out_cap, int64_t* d_groups,
+                           int64_t max_groups, const rel_tuning* t, void* ws, size_t ws_bytes,
+                           void* stream) {
+  g_error.clear();
+  if (nkeys < 0 || nkeys > REL_MAX_KEYS || (nkeys > 0 && !keys))
+    return fail(REL_EINVAL, "groupby: 0..%d key columns", REL_MAX_KEYS);
+  if (nvals < 0 || nvals > REL_MAX_AGGS || (nvals > 0 && !vals))
+    return fail(REL_EINVAL, "groupby: 0..%d value columns", REL_MAX_AGGS);
+  if (nkeys == 0 && nvals == 0) return fail(REL_EINVAL, "groupby: no input columns");
+  const int64_t n = nkeys > 0 ? keys[0].len : vals[0].len;
+  int32_t key_types[REL_MAX_KEYS] = {0, 0};
+  for (int k = 0; k < nkeys; ++k) {
+    rel_status st = check_column(&keys[k], "groupby key");
+    if (st) return st;
+    if (keys[k].len != n) return fail(REL_EINVAL, "groupby: columns differ in length");
+    key_types[k] = keys[k].type;
+  }
+  for (int v = 0; v < nvals; ++v) {
+    rel_status st = check_column(&vals[v], "groupby value");
+    if (st) return st;
+    if (vals[v].len != n) return fail(REL_EINVAL, "groupby: columns differ in length");
+  }
+  rel_status st = check_aggs(aggs, naggs, nvals, "groupby");
+  if (st) return st;
+  st = check_outputs(out_keys, nkeys, out_aggs, naggs, out_cap, d_groups);
+  if (st) return st;
+  if (max_groups < 0) return fail(REL_EINVAL, "groupby: negative max_groups");
+  st = check_tuning(t);
+  if (st) return st;
+  GroupPlan gp;
+  st = group_plan(nkeys, key_types, naggs, aggs, gp);
+  if (st) return st;
+  const GroupLayout L = group_layout(gp, max_groups, load_factor(t), 0);
+  st = check_ws(ws, ws_bytes, L.end);
+  if (st) return st;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  const GroupDesc g = group_desc(gp, L, w, d_groups);
+  launch_group_init(g, s);
+  if (n > 0) {
+    GroupAggParams p;
+    std::memset(&p, 0, sizeof p);
+    p.g = g;
+    for (int k = 0; k < nkeys; ++k) {
+      p.key_data[k] = keys[k].data;
+      p.key_idx[k] = keys[k].idx;
+    }
+    for (int a = 0; a < gp.ap.nacc; ++a) {
+      const rel_column& c = vals[gp.ap.col[a]];
+      p.val_data[a] = c.data;
+      p.val_idx[a] = c.idx;
+      p.val_type[a] = c.type;
+    }
+    p.n = n;
+    const DeviceInfo& di = device_info();
+    const int block = (t && t->block > 0) ? (t->block > 256 ? 256 : t->block) : 256;
+    p.lds_slots = default_lds_slots(t, max_groups, gp.words, 32768);
+    int64_t blocks = (n + block - 1) / block;
+    int64_t limit = (t && t->grid > 0) ? t->grid : static_cast<int64_t>(di.cu_count) * 4;
+    if (blocks > limit) blocks = limit;
+    launch_group_agg(p, static_cast<int>(blocks), block, s);
+  }
+  launch_group_finalize(
+      finalize_params(g, gp, aggs, naggs, out_keys, key_types, out_aggs, out_cap), s);
+  return after_launch(s, "groupby");
+}
+
+// ---------------------------------------------------------------- pipeline
+
+size_t rel_pipeline_ws(const rel_pipeline_desc* d) {
+  if (check_pipeline(d) != REL_OK) return 0;
+  PipeLayout L;
+  if (pipeline_layout(d, L) != REL_OK) return 0;
+  return L.end;
+}
+
+rel_status rel_pipeline(const rel_pipeline_desc* d, const rel_outputs* o, void* ws,
+                        size_t ws_bytes, void* stream) {
+  g_error.clear();
+  rel_status st = check_pipeline(d);
+  if (st) return st;
+  if (!o) return fail(REL_EINVAL, "pipeline: NULL outputs");
+  st = check_outputs(o->keys, d->n_keys, o->aggs, d->n_aggs, o->cap, o->d_groups);
+  if (st) return st;
+  PipeLayout L;
+  st = pipeline_layout(d, L);
+  if (st) return st;
+  st = check_ws(ws, ws_bytes, L.end);
+  if (st) return st;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  const DeviceInfo& di = device_info();
+  const rel_tuning* t = d->tuning;
+
+  PipelineParams p;
+  std::memset(&p, 0, sizeof p);
+  const int64_t n = d->fact[0].len;
+  for (int c = 0; c < d->n_fact; ++c) {
+    p.fact[c] = d->fact[c].data;
+    p.fact_type[c] = d->fact[c].type;
+    p.fact_vec[c] = (reinterpret_cast<uintptr_t>(d->fact[c].data) % 16) == 0;
+  }
+  p.n = n;
+  p.nterms = d->n_preds;
+  for (int i = 0; i < d->n_preds; ++i) {
+    p.term_col[i] = d->preds[i].col;
+    p.term_op[i] = d->preds[i].op;
+    p.term_lo[i] = d->preds[i].lo;
+    p.term_hi[i] = d->preds[i].hi;
+  }
+  p.g = group_desc(L.gp, L.group, w, o->d_groups);
+  for (int a = 0; a < L.gp.ap.nacc; ++a) p.acc_col[a] = L.gp.ap.col[a];
+  for (int k = 0; k < d->n_keys; ++k) {
+    p.key_src[k] = d->keys[k].src == REL_KEY_FACT ? 0 : 1 + d->keys[k].col;
+    p.key_col[k] = d->keys[k].src == REL_KEY_FACT ? d->keys[k].col : 0;
+  }
+
+  // LDS: per-wave row queues, the group table, then dim tables that fit.
+  const size_t budget = static_cast<size_t>(di.lds_per_block);
+  const size_t queue_bytes = static_cast<size_t>(kPipeThreads / kWave) * kPipeQueue * 4;
+  p.lds_slots = default_lds_slots(t, d->max_groups, L.gp.words, 16384);
+  size_t lds = 0;
+  p.lds_queue_offset = 0;
+  lds += queue_bytes;
+  p.lds_group_offset = static_cast<uint32_t>(lds);
+  lds += static_cast<size_t>(p.lds_slots) * L.gp.words * 8;
+  p.ndims = d->n_dims;
+  // Smaller dims claim LDS first.
+  int order[REL_MAX_DIMS] = {0, 1};
+  if (d->n_dims == 2 && L.dim[1].cap < L.dim[0].cap) {
+    order[0] = 1;
+    order[1] = 0;
+  }
+  for (int oi = 0; oi < d->n_dims; ++oi) {
+    const int i = order[oi];
+    const rel_dim& dm = d->dims[i];
+    p.dim[i].map = map_desc(L.dim[i], dm.key.type, w);
+    p.dim[i].fk_col = dm.fact_col;
+    const size_t bytes = L.dim[i].cap * 8;
+    if (dm.key.type == REL_I32 && lds + bytes <= budget) {
+      p.dim[i].in_lds = 1;
+      p.dim[i].lds_offset = static_cast<uint32_t>(lds);
+      lds += bytes;
+    }
+  }
+  p.lds_bytes = static_cast<uint32_t>(lds);
+  p.ntiles = n > 0 ? (n + kPipeTile - 1) / kPipeTile : 0;
+
+  for (int i = 0; i < d->n_dims; ++i) {
+    const rel_dim& dm = d->dims[i];
+    launch_map_init(p.dim[i].map, s);
+    MapBuildParams b;
+    std::memset(&b, 0, sizeof b);
+    b.map = p.dim[i].map;
+    b.keys = dm.key.data;
+    b.type = dm.key.type;
+    b.n = dm.key.len;
+    if (dm.has_payload) {
+      b.val_col = dm.payload.data;
+      b.val_type = dm.payload.type;
+    }
+    launch_map_build(b, s);
+  }
+  launch_group_init(p.g, s);
+  if (p.ntiles > 0) {
+    int per_cu = static_cast<int>(budget / (lds > 0 ? lds : 1));
+    if (per_cu > 2) per_cu = 2;
+    if (per_cu < 1) per_cu = 1;
+    int64_t grid = (t && t->grid > 0) ? t->grid : static_cast<int64_t>(di.cu_count) * per_cu;
+    if (grid > p.ntiles) grid = p.ntiles;
+    launch_pipeline(p, static_cast<int>(grid), s);
+  }
+  launch_group_finalize(finalize_params(p.g, L.gp, d->aggs, d->n_aggs, o->keys, L.key_types,
+                                        o->aggs, o->cap),
+                        s);
+  return after_launch(s, "pipeline");
+}
+
+}  // extern "C"

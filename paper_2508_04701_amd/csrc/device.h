@@ -1,0 +1,366 @@
+// Device helpers shared by the gfx950 kernels: hashing, wave64 ballot
+// arithmetic, typed column access and the open-addressing slot formats.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rel {
+
+constexpr int kWave = 64;
+
+// Key sentinel of every hash table: a slot whose key word holds it is empty.
+// A real key equal to it never enters the open-addressing array; it goes to
+// an out-of-band area instead, so the key domain is not restricted.
+constexpr int32_t kEmpty32 = INT32_MIN;
+constexpr uint64_t kEmpty64 = 0x8000000000000000ULL;
+
+// MurmurHash3 finalisers (Appleby, public domain): full avalanche, cheap.
+__device__ __forceinline__ uint32_t hash32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+__device__ __forceinline__ uint64_t hash64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdULL;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ULL;
+  k ^= k >> 33;
+  return k;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Number of set bits of `m` held by lanes below this one.
+__device__ __forceinline__ uint32_t rank_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+}
+
+__device__ __forceinline__ uint32_t popc64(uint64_t m) { return __popcll(m); }
+
+template <typename T>
+__device__ __forceinline__ T first_lane(T v) {
+  return __shfl(v, 0, kWave);
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Agent-scope atomic loads/stores: coherent across the eight XCD L2s.
+__device__ __forceinline__ uint64_t load_agent(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Column element types (numerically equal to rel_dtype).
+enum : int32_t { kI8 = 1, kI32 = 2, kI64 = 3 };
+
+__device__ __forceinline__ int64_t load_elem(const void* p, int32_t type, int64_t i) {
+  if (type == kI32) return static_cast<const int32_t*>(p)[i];
+  if (type == kI64) return static_cast<const int64_t*>(p)[i];
+  return static_cast<const int8_t*>(p)[i];
+}
+
+// Four consecutive elements starting at r0 (a multiple of 4) of a plain
+// column, with one vector load when the chunk is whole and the column is
+// 16-byte aligned (`vec`).
+__device__ __forceinline__ void load4(const void* p, int32_t type, bool vec, int64_t r0,
+                                      int64_t n, int64_t v[4]) {
+  if (vec && r0 + 4 <= n) {
+    if (type == kI32) {
+      int4 x = *reinterpret_cast<const int4*>(static_cast<const int32_t*>(p) + r0);
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    } else if (type == kI64) {
+      const longlong2* q = reinterpret_cast<const longlong2*>(static_cast<const int64_t*>(p) + r0);
+      longlong2 a = q[0], b = q[1];
+      v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    } else {
+      int32_t w = *reinterpret_cast<const int32_t*>(static_cast<const int8_t*>(p) + r0);
+      v[0] = static_cast<int8_t>(w); v[1] = static_cast<int8_t>(w >> 8);
+      v[2] = static_cast<int8_t>(w >> 16); v[3] = static_cast<int8_t>(w >> 24);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (r0 + e < n) ? load_elem(p, type, r0 + e) : 0;
+  }
+}
+
+// Comparison term on a widened value (operators numerically equal to rel_cmp).
+__device__ __forceinline__ bool term_holds(int32_t op, int64_t v, int64_t lo, int64_t hi) {
+  switch (op) {
+    case 0: return v < lo;
+    case 1: return v <= lo;
+    case 2: return v > lo;
+    case 3: return v >= lo;
+    case 4: return v == lo;
+    case 5: return v != lo;
+    default: return v >= lo && v < hi;
+  }
+}
+
+// ---------------------------------------------------------------- hash maps
+//
+// Multimap key -> 32-bit value with linear probing over a power-of-two slot
+// array. int32 keys: one 64-bit word per slot, key in the low half and value
+// in the high half, published by a single 64-bit CAS. int64 keys: 16-byte
+// slots {key, value, pad}; the key word is claimed by CAS and the value is
+// stored after it (readers only run in later kernels). Entries whose key is
+// the sentinel are appended to an out-of-band list {count, values[]}.
+
+struct Map32 {
+  uint64_t* slots;
+  uint64_t mask;
+  unsigned long long* oob_count;
+  uint32_t* oob_vals;
+};
+
+struct Map64 {
+  ulonglong2* slots;  // .x = key bits, .y = value (low 32 bits)
+  uint64_t mask;
+  unsigned long long* oob_count;
+  uint32_t* oob_vals;
+};
+
+__device__ __forceinline__ uint64_t pack32(int32_t key, uint32_t val) {
+  return static_cast<uint64_t>(static_cast<uint32_t>(key)) | (static_cast<uint64_t>(val) << 32);
+}
+
+constexpr uint64_t kEmptySlot32 = 0x0000000080000000ULL;  // pack32(kEmpty32, 0)
+
+__device__ __forceinline__ void map_insert(const Map32& m, int32_t key, uint32_t val) {
+  if (key == kEmpty32) {
+    unsigned long long pos = atomicAdd(m.oob_count, 1ULL);
+    m.oob_vals[pos] = val;
+    return;
+  }
+  uint64_t h = hash32(static_cast<uint32_t>(key)) & m.mask;
+  const unsigned long long want = pack32(key, val);
+  while (true) {
+    unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(m.slots + h),
+                                        static_cast<unsigned long long>(kEmptySlot32), want);
+    if (prev == kEmptySlot32) return;
+    h = (h + 1) & m.mask;
+  }
+}
+
+__device__ __forceinline__ void map_insert(const Map64& m, int64_t key, uint32_t val) {
+  if (static_cast<uint64_t>(key) == kEmpty64) {
+    unsigned long long pos = atomicAdd(m.oob_count, 1ULL);
+    m.oob_vals[pos] = val;
+    return;
+  }
+  uint64_t h = hash64(static_cast<uint64_t>(key)) & m.mask;
+  while (true) {
+    unsigned long long* kw = reinterpret_cast<unsigned long long*>(&m.slots[h].x);
+    unsigned long long prev = atomicCAS(kw, static_cast<unsigned long long>(kEmpty64),
+                                        static_cast<unsigned long long>(key));
+    if (prev == kEmpty64) {
+      m.slots[h].y = val;
+      return;
+    }
+    h = (h + 1) & m.mask;
+  }
+}
+
+// Cursor over the matches of one key: `pos` walks the probe chain (or the
+// out-of-band list when `oob`); next() yields one match per call.
+struct MapCursor {
+  uint64_t pos;
+  bool oob;
+  bool live;
+};
+
+__device__ __forceinline__ MapCursor map_start32(const Map32& m, int32_t key) {
+  MapCursor c;
+  c.oob = (key == kEmpty32);
+  c.pos = c.oob ? 0 : (hash32(static_cast<uint32_t>(key)) & m.mask);
+  c.live = true;
+  return c;
+}
+
+__device__ __forceinline__ MapCursor map_start64(const Map64& m, int64_t key) {
+  MapCursor c;
+  c.oob = (static_cast<uint64_t>(key) == kEmpty64);
+  c.pos = c.oob ? 0 : (hash64(static_cast<uint64_t>(key)) & m.mask);
+  c.live = true;
+  return c;
+}
+
+// Advances to the next match of `key`; returns false (and ends the cursor)
+// when there is none. `slots` may point to an LDS copy of the table.
+__device__ __forceinline__ bool map_next(const uint64_t* slots, uint64_t mask,
+                                         const unsigned long long* oob_count,
+                                         const uint32_t* oob_vals, int32_t key, MapCursor& c,
+                                         uint32_t& val) {
+  if (!c.live) return false;
+  if (c.oob) {
+    if (c.pos < *oob_count) {
+      val = oob_vals[c.pos++];
+      return true;
+    }
+    c.live = false;
+    return false;
+  }
+  while (true) {
+    uint64_t s = slots[c.pos];
+    c.pos = (c.pos + 1) & mask;
+    int32_t k = static_cast<int32_t>(static_cast<uint32_t>(s));
+    if (k == kEmpty32) {
+      c.live = false;
+      return false;
+    }
+    if (k == key) {
+      val = static_cast<uint32_t>(s >> 32);
+      return true;
+    }
+  }
+}
+
+__device__ __forceinline__ bool map_next(const ulonglong2* slots, uint64_t mask,
+                                         const unsigned long long* oob_count,
+                                         const uint32_t* oob_vals, int64_t key, MapCursor& c,
+                                         uint32_t& val) {
+  if (!c.live) return false;
+  if (c.oob) {
+    if (c.pos < *oob_count) {
+      val = oob_vals[c.pos++];
+      return true;
+    }
+    c.live = false;
+    return false;
+  }
+  while (true) {
+    ulonglong2 s = slots[c.pos];
+    c.pos = (c.pos + 1) & mask;
+    if (s.x == kEmpty64) {
+      c.live = false;
+      return false;
+    }
+    if (static_cast<int64_t>(s.x) == key) {
+      val = static_cast<uint32_t>(s.y);
+      return true;
+    }
+  }
+}
+
+// ---------------------------------------------------------- group tables
+//
+// A group slot is `words` 64-bit words: [0] packed key, [1] COUNT, then one
+// accumulator per (op, value column): SUM adds modulo 2^64, MIN/MAX keep the
+// signed extreme. The packed key of a key tuple is injective (see
+// GroupKeyPack); the sentinel pattern goes to one extra slot after the array.
+
+enum : int32_t { kAccSum = 0, kAccMin = 1, kAccMax = 2 };
+
+constexpr int kMaxAcc = 8;
+
+struct AccPlan {
+  int32_t nacc;
+  int32_t kind[kMaxAcc];
+  int32_t col[kMaxAcc];  // index of the value column
+};
+
+struct GroupTable {
+  uint64_t* slots;  // (mask + 2) slots; slot mask + 1 is the out-of-band slot
+  uint64_t mask;
+  int32_t words;
+  int32_t* overflow;
+};
+
+__device__ __forceinline__ uint64_t acc_identity(int32_t kind) {
+  return kind == kAccMin ? 0x7FFFFFFFFFFFFFFFULL : (kind == kAccMax ? 0x8000000000000000ULL : 0ULL);
+}
+
+// Finds or claims the slot of packed key pk; NULL if the table is full.
+__device__ __forceinline__ uint64_t* group_slot(const GroupTable& t, uint64_t pk) {
+  if (pk == kEmpty64) return t.slots + (t.mask + 1) * t.words;
+  uint64_t h = hash64(pk) & t.mask;
+  for (uint64_t probes = 0; probes <= t.mask; ++probes) {
+    uint64_t* s = t.slots + h * t.words;
+    uint64_t cur = __hip_atomic_load(s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == pk) return s;
+    if (cur == kEmpty64) {
+      unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(s),
+                                          static_cast<unsigned long long>(kEmpty64),
+                                          static_cast<unsigned long long>(pk));
+      if (prev == kEmpty64 || prev == pk) return s;
+    }
+    h = (h + 1) & t.mask;
+  }
+  atomicOr(t.overflow, 1);
+  return nullptr;
+}
+
+// Adds `cnt` rows with accumulator contributions acc[] to slot s (HBM).
+__device__ __forceinline__ void group_update_global(uint64_t* s, const AccPlan& ap, uint64_t cnt,
+                                                    const uint64_t* acc) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(s + 1), static_cast<unsigned long long>(cnt));
+  for (int a = 0; a < ap.nacc; ++a) {
+    uint64_t* w = s + 2 + a;
+    if (ap.kind[a] == kAccSum) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(acc[a]));
+    } else if (ap.kind[a] == kAccMin) {
+      atomicMin(reinterpret_cast<long long*>(w), static_cast<long long>(acc[a]));
+    } else {
+      atomicMax(reinterpret_cast<long long*>(w), static_cast<long long>(acc[a]));
+    }
+  }
+}
+
+// Key tuple packing: up to two keys of 8/32/64 bits whose widths sum to at
+// most 64. Key 0 occupies the high bits, key 1 the low bits; a single key is
+// its sign-extended value.
+struct GroupKeyPack {
+  int32_t nkeys;
+  int32_t type[2];
+  int32_t shift0;  // bit width of key 1 (key 0 is shifted left by it)
+};
+
+__device__ __forceinline__ uint64_t width_mask(int32_t type) {
+  return type == kI8 ? 0xFFULL : (type == kI32 ? 0xFFFFFFFFULL : ~0ULL);
+}
+
+__device__ __forceinline__ uint64_t pack_keys(const GroupKeyPack& kp, int64_t k0, int64_t k1) {
+  if (kp.nkeys == 0) return 0;
+  if (kp.nkeys == 1) return static_cast<uint64_t>(k0);
+  return ((static_cast<uint64_t>(k0) & width_mask(kp.type[0])) << kp.shift0) |
+         (static_cast<uint64_t>(k1) & width_mask(kp.type[1]));
+}
+
+__device__ __forceinline__ int64_t sign_extend(uint64_t v, int32_t type) {
+  if (type == kI8) return static_cast<int8_t>(v);
+  if (type == kI32) return static_cast<int32_t>(v);
+  return static_cast<int64_t>(v);
+}
+
+__device__ __forceinline__ void unpack_keys(const GroupKeyPack& kp, uint64_t pk, int64_t& k0,
+                                            int64_t& k1) {
+  if (kp.nkeys == 1) {
+    k0 = static_cast<int64_t>(pk);
+    k1 = 0;
+  } else {
+    k0 = sign_extend(kp.shift0 >= 64 ? 0 : (pk >> kp.shift0), kp.type[0]);
+    k1 = sign_extend(pk & width_mask(kp.type[1]), kp.type[1]);
+  }
+}
+
+__device__ __forceinline__ void store_elem(void* p, int32_t type, int64_t i, int64_t v) {
+  if (type == kI32) static_cast<int32_t*>(p)[i] = static_cast<int32_t>(v);
+  else if (type == kI64) static_cast<int64_t*>(p)[i] = v;
+  else static_cast<int8_t*>(p)[i] = static_cast<int8_t>(v);
+}
+
+}  // namespace rel

@@ -1,0 +1,155 @@
+// Selection with ordered stream compaction, one pass over the columns.
+//
+// A workgroup of 256 threads takes one tile of 4096 rows. Thread t of the
+// tile reads rows (j * 1024 + 4 t .. + 3) for j = 0..3, so every column read
+// is a coalesced 16-byte-per-lane vector load. Each passing row sets one bit;
+// per chunk a wave64 ballot per row position gives the wave's count (popcount)
+// and each lane's rank (mbcnt), which places every passing row id at its
+// ascending position inside the tile. The tile's base in the output comes
+// from a decoupled look-back over the preceding tiles: each tile publishes
+// its count (flag AGG) and later its inclusive prefix (flag PREFIX) in one
+// 64-bit word with agent-scope atomics, so the eight XCD L2 caches never hold
+// a stale state. Tiles are numbered by an atomic ticket in launch order, so
+// every tile that a look-back waits on has already started and will publish.
+// The ids of a tile are staged in LDS and written with coalesced stores.
+
+#include "internal.h"
+
+namespace rel {
+
+namespace {
+
+constexpr uint64_t kFlagAgg = 1ULL << 62;
+constexpr uint64_t kFlagPrefix = 2ULL << 62;
+constexpr uint64_t kValueMask = (1ULL << 62) - 1;
+
+__device__ __forceinline__ uint32_t eval_chunk(const FilterParams& p, int64_t r0) {
+  uint32_t bits = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) bits |= (r0 + e < p.n) ? (1u << e) : 0u;
+  if (bits == 0) return 0;
+  for (int t = 0; t < p.nterms; ++t) {
+    const FilterTerm& term = p.term[t];
+    int64_t v[4];
+    if (p.idx) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        v[e] = (r0 + e < p.n) ? load_elem(term.data, term.type, p.idx[r0 + e]) : 0;
+    } else {
+      load4(term.data, term.type, term.vec != 0, r0, p.n, v);
+    }
+    uint32_t m = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) m |= term_holds(term.op, v[e], term.lo, term.hi) ? (1u << e) : 0u;
+    bits &= m;
+  }
+  return bits;
+}
+
+__global__ void __launch_bounds__(kFilterThreads) filter_kernel(FilterParams p) {
+  __shared__ uint32_t s_rows[kFilterTile];
+  __shared__ uint32_t s_wave_total[4][kFilterThreads / kWave];
+  __shared__ int64_t s_tile;
+  __shared__ uint64_t s_excl;
+
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = lane_id();
+
+  if (tid == 0) s_tile = atomicAdd(p.ticket, 1u);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t base = tile * kFilterTile;
+
+  uint32_t bits[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) bits[j] = eval_chunk(p, base + j * (kFilterThreads * 4) + tid * 4);
+
+  // Per chunk: this lane's rank among the wave's passing rows, and the
+  // wave's count.
+  uint32_t lane_prefix[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      uint64_t b = ballot((bits[j] >> e) & 1u);
+      pre += rank_below(b);
+      tot += popc64(b);
+    }
+    lane_prefix[j] = pre;
+    if (lane == 0) s_wave_total[j][wave] = tot;
+  }
+  __syncthreads();
+
+  // Offsets in tile order (chunk, wave, lane, row).
+  uint32_t chunk_base[4];
+  uint32_t running = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    for (int w = 0; w < kFilterThreads / kWave; ++w) {
+      if (w == wave) chunk_base[j] = running;
+      running += s_wave_total[j][w];
+    }
+  }
+  const uint32_t total = running;
+
+  if (wave == 0) {
+    uint64_t excl = 0;
+    if (tile == 0) {
+      if (lane == 0) store_agent(&p.tile_state[0], kFlagPrefix | total);
+    } else {
+      if (lane == 0) store_agent(&p.tile_state[tile], kFlagAgg | total);
+      int64_t pos = tile - 1;
+      while (true) {
+        int64_t t = pos - lane;
+        uint64_t st = t >= 0 ? load_agent(&p.tile_state[t]) : kFlagPrefix;
+        uint64_t flag = st >> 62;
+        uint64_t pm = ballot(flag == 2);
+        uint64_t inv = ballot(flag == 0);
+        uint64_t upto = pm ? (((pm & (~pm + 1)) << 1) - 1) : ~0ULL;
+        if (inv & upto) {
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += wave_sum_u64(((upto >> lane) & 1ULL) ? (st & kValueMask) : 0ULL);
+        if (pm) break;
+        pos -= kWave;
+      }
+      if (lane == 0) store_agent(&p.tile_state[tile], kFlagPrefix | (excl + total));
+    }
+    if (lane == 0) s_excl = excl;
+  }
+
+  // Stage row ids in LDS at their tile positions.
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (bits[j] == 0) continue;
+    const int64_t r0 = base + j * (kFilterThreads * 4) + tid * 4;
+    uint32_t off = chunk_base[j] + lane_prefix[j];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if ((bits[j] >> e) & 1u) {
+        s_rows[off++] = p.idx ? p.idx[r0 + e] : static_cast<uint32_t>(r0 + e);
+      }
+    }
+  }
+  __syncthreads();
+
+  const uint64_t excl = s_excl;
+  for (uint32_t i = tid; i < total; i += kFilterThreads) {
+    uint64_t pos = excl + i;
+    if (static_cast<int64_t>(pos) < p.cap) p.out[pos] = s_rows[i];
+  }
+  if (tile == p.ntiles - 1 && tid == 0) *p.d_count = static_cast<long long>(excl + total);
+}
+
+}  // namespace
+
+void launch_filter(const FilterParams& p, hipStream_t s) {
+  ProfileScope ps(kKFilter, s);
+  hipLaunchKernelGGL(filter_kernel, dim3(static_cast<unsigned>(p.ntiles)), dim3(kFilterThreads), 0,
+                     s, p);
+}
+
+}  // namespace rel

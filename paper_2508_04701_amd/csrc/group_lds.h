@@ -1,0 +1,70 @@
+// Per-workgroup group tables in LDS, shared by the group-by and the fused
+// pipeline kernels. Slots use the same layout as the global table: [0] packed
+// key, [1] COUNT, then the accumulators. A key that finds no LDS slot within
+// a short probe window is aggregated in the global table instead.
+#pragma once
+
+#include "internal.h"
+
+namespace rel {
+
+constexpr int kLdsProbe = 16;
+
+__device__ __forceinline__ void lds_group_init(uint64_t* t, int slots, const GroupDesc& g) {
+  for (int i = threadIdx.x; i < slots * g.words; i += blockDim.x) {
+    const int w = i % g.words;
+    uint64_t v = 0;
+    if (w == 0) v = kEmpty64;
+    else if (w >= 2 && w - 2 < g.ap.nacc) v = acc_identity(g.ap.kind[w - 2]);
+    t[i] = v;
+  }
+}
+
+__device__ __forceinline__ uint64_t* lds_group_slot(uint64_t* t, int slots, int words, uint64_t pk) {
+  if (pk == kEmpty64 || slots == 0) return nullptr;
+  const uint32_t mask = static_cast<uint32_t>(slots - 1);
+  uint32_t h = static_cast<uint32_t>(hash64(pk)) & mask;
+  const int window = slots < kLdsProbe ? slots : kLdsProbe;
+  for (int probe = 0; probe < window; ++probe) {
+    uint64_t* s = t + static_cast<uint32_t>(h) * words;
+    uint64_t cur = *reinterpret_cast<volatile uint64_t*>(s);
+    if (cur == pk) return s;
+    if (cur == kEmpty64) {
+      unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(s),
+                                          static_cast<unsigned long long>(kEmpty64),
+                                          static_cast<unsigned long long>(pk));
+      if (prev == kEmpty64 || prev == pk) return s;
+    }
+    h = (h + 1) & mask;
+  }
+  return nullptr;
+}
+
+__device__ __forceinline__ void lds_group_update(uint64_t* s, const AccPlan& ap, const uint64_t* acc) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(s + 1), 1ULL);
+  for (int a = 0; a < ap.nacc; ++a) {
+    uint64_t* w = s + 2 + a;
+    if (ap.kind[a] == kAccSum) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(acc[a]));
+    } else if (ap.kind[a] == kAccMin) {
+      if (static_cast<long long>(acc[a]) < *reinterpret_cast<volatile long long*>(w))
+        atomicMin(reinterpret_cast<long long*>(w), static_cast<long long>(acc[a]));
+    } else {
+      if (static_cast<long long>(acc[a]) > *reinterpret_cast<volatile long long*>(w))
+        atomicMax(reinterpret_cast<long long*>(w), static_cast<long long>(acc[a]));
+    }
+  }
+}
+
+// Merges a workgroup's LDS table into the global table (call after a barrier).
+__device__ __forceinline__ void lds_group_flush(const uint64_t* t, int slots, const GroupDesc& g) {
+  GroupTable gt{g.slots, g.cap - 1, g.words, g.overflow};
+  for (int i = threadIdx.x; i < slots; i += blockDim.x) {
+    const uint64_t* s = t + i * g.words;
+    if (s[0] == kEmpty64) continue;
+    uint64_t* d = group_slot(gt, s[0]);
+    if (d) group_update_global(d, g.ap, s[1], s + 2);
+  }
+}
+
+}  // namespace rel

@@ -1,0 +1,156 @@
+// Hash group-by aggregation.
+//
+// Every workgroup keeps a private open-addressing group table in LDS (when
+// lds_slots > 0): a row whose key finds or claims an LDS slot within a short
+// probe window is aggregated there with LDS atomics, so few-group inputs
+// never touch HBM per row (the few-groups memory contention named in
+// Section 4.2). Rows whose key does not fit go straight to the global table
+// in HBM (CAS on the packed key, then device-scope atomics on COUNT and the
+// accumulators). At the end the workgroup merges its LDS table into the
+// global one with one update per occupied slot. With many groups the LDS
+// table still absorbs the keys a workgroup meets first, which under skew are
+// the hot ones. A finalize pass compacts occupied global slots into the
+// output columns with a ballot and one atomic per wave.
+
+#include "internal.h"
+#include "group_lds.h"
+
+namespace rel {
+
+namespace {
+
+__global__ void group_init_kernel(GroupDesc g) {
+  const uint64_t total = (g.cap + 1) * static_cast<uint64_t>(g.words);
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const int w = static_cast<int>(i % g.words);
+    uint64_t v = 0;
+    if (w == 0) v = kEmpty64;
+    else if (w >= 2 && w - 2 < g.ap.nacc) v = acc_identity(g.ap.kind[w - 2]);
+    g.slots[i] = v;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *g.overflow = 0;
+    *g.d_groups = 0;
+  }
+}
+
+__global__ void __launch_bounds__(256) group_agg_kernel(GroupAggParams p) {
+  extern __shared__ uint64_t lds_table[];
+  const GroupDesc& g = p.g;
+  GroupTable gt{g.slots, g.cap - 1, g.words, g.overflow};
+  if (p.lds_slots > 0) {
+    lds_group_init(lds_table, p.lds_slots, g);
+    __syncthreads();
+  }
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+       i < static_cast<uint64_t>(p.n); i += stride) {
+    int64_t k[2] = {0, 0};
+    for (int j = 0; j < g.kp.nkeys; ++j) {
+      int64_t r = p.key_idx[j] ? static_cast<int64_t>(p.key_idx[j][i]) : static_cast<int64_t>(i);
+      k[j] = load_elem(p.key_data[j], g.kp.type[j], r);
+    }
+    const uint64_t pk = pack_keys(g.kp, k[0], k[1]);
+    uint64_t acc[kMaxAcc];
+    for (int a = 0; a < g.ap.nacc; ++a) {
+      int64_t r = p.val_idx[a] ? static_cast<int64_t>(p.val_idx[a][i]) : static_cast<int64_t>(i);
+      acc[a] = static_cast<uint64_t>(load_elem(p.val_data[a], p.val_type[a], r));
+    }
+    uint64_t* ls = lds_group_slot(lds_table, p.lds_slots, g.words, pk);
+    if (ls) {
+      lds_group_update(ls, g.ap, acc);
+    } else {
+      uint64_t* gs = group_slot(gt, pk);
+      if (gs) group_update_global(gs, g.ap, 1, acc);
+    }
+  }
+  if (p.lds_slots > 0) {
+    __syncthreads();
+    lds_group_flush(lds_table, p.lds_slots, g);
+  }
+}
+
+__global__ void __launch_bounds__(256) group_finalize_kernel(FinalizeParams p) {
+  const GroupDesc& g = p.g;
+  if (*g.overflow) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *g.d_groups = static_cast<unsigned long long>(-1LL);
+    return;
+  }
+  const int lane = lane_id();
+  const uint64_t nslots = g.kp.nkeys == 0 ? 1 : g.cap + 1;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t base = blockIdx.x * static_cast<uint64_t>(blockDim.x); base < nslots;
+       base += stride) {
+    const uint64_t i = base + threadIdx.x;
+    bool occ = false;
+    const uint64_t* s = nullptr;
+    if (i < nslots) {
+      s = g.slots + i * g.words;
+      if (g.kp.nkeys == 0) occ = true;                 // the one ungrouped row
+      else if (i < g.cap) occ = (s[0] != kEmpty64);
+      else occ = (s[1] != 0);                          // out-of-band slot
+    }
+    uint64_t m = ballot(occ);
+    if (m == 0) continue;
+    unsigned long long at = 0;
+    if (lane == 0) at = atomicAdd(g.d_groups, static_cast<unsigned long long>(popc64(m)));
+    at = first_lane(at);
+    if (!occ) continue;
+    const unsigned long long pos = at + rank_below(m);
+    if (pos >= static_cast<unsigned long long>(p.cap)) continue;
+    const uint64_t pk = (g.kp.nkeys > 0 && i == g.cap) ? kEmpty64 : s[0];
+    if (g.kp.nkeys > 0) {
+      int64_t k0, k1;
+      unpack_keys(g.kp, pk, k0, k1);
+      store_elem(p.out_keys[0], p.out_key_type[0], pos, k0);
+      if (g.kp.nkeys > 1) store_elem(p.out_keys[1], p.out_key_type[1], pos, k1);
+    }
+    const uint64_t count = s[1];
+    for (int a = 0; a < p.naggs; ++a) {
+      const int op = p.op[a];
+      int64_t* out = static_cast<int64_t*>(p.out_aggs[a]);
+      if (op == 1) {
+        out[pos] = static_cast<int64_t>(count);
+      } else if (op == 4) {
+        double avg;
+        if (count == 0) {
+          avg = __longlong_as_double(0x7FF8000000000000LL);
+        } else {
+          avg = static_cast<double>(static_cast<int64_t>(s[2 + p.acc[a]])) /
+                static_cast<double>(static_cast<int64_t>(count));
+        }
+        static_cast<double*>(p.out_aggs[a])[pos] = avg;
+      } else {
+        out[pos] = static_cast<int64_t>(s[2 + p.acc[a]]);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+void launch_group_init(const GroupDesc& g, hipStream_t s) {
+  ProfileScope ps(kKFill, s);
+  uint64_t total = (g.cap + 1) * static_cast<uint64_t>(g.words);
+  uint64_t blocks = (total + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(group_init_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, g);
+}
+
+void launch_group_agg(const GroupAggParams& p, int grid, int block, hipStream_t s) {
+  ProfileScope ps(kKGroupAgg, s);
+  size_t lds = static_cast<size_t>(p.lds_slots) * p.g.words * sizeof(uint64_t);
+  hipLaunchKernelGGL(group_agg_kernel, dim3(grid), dim3(block), lds, s, p);
+}
+
+void launch_group_finalize(const FinalizeParams& p, hipStream_t s) {
+  ProfileScope ps(kKFinalize, s);
+  uint64_t nslots = p.g.kp.nkeys == 0 ? 1 : p.g.cap + 1;
+  uint64_t blocks = (nslots + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(group_finalize_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                     p);
+}
+
+}  // namespace rel

@@ -1,0 +1,187 @@
+// Host <-> kernel interface of the library: launch parameter blocks and the
+// launcher entry points implemented next to each kernel. The public C-ABI in
+// api.cpp validates arguments, carves the workspace and calls these.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+
+namespace rel {
+
+// ------------------------------------------------------------------ common
+
+struct DeviceInfo {
+  int cu_count;
+  int lds_per_block;  // bytes of LDS one workgroup may use
+};
+const DeviceInfo& device_info();
+
+// Per-kernel timing: when enabled, launch sites bracket each kernel with a
+// pair of events on the launch stream (kernel classes as in rel.h).
+enum KernelClass : int {
+  kKFill = 0, kKFilter, kKMapBuild, kKMapProbe, kKGroupAgg, kKPipeline, kKFinalize, kKCount
+};
+struct ProfileScope {
+  ProfileScope(int kclass, hipStream_t s);
+  ~ProfileScope();
+  int k;
+  hipStream_t s;
+  void* start;
+};
+
+// Fills n 64-bit words with `pattern` (graph-safe replacement for memset).
+void launch_fill64(uint64_t* p, uint64_t n, uint64_t pattern, hipStream_t s);
+
+// --------------------------------------------------------------- filter
+
+constexpr int kFilterThreads = 256;
+constexpr int kFilterTile = kFilterThreads * 16;  // 4 chunks of 4 rows per thread
+
+struct FilterTerm {
+  const void* data;
+  int32_t type;
+  int32_t op;
+  int64_t lo, hi;
+  int32_t vec;  // data is 16-byte aligned
+};
+
+struct FilterParams {
+  FilterTerm term[4];
+  int32_t nterms;
+  const uint32_t* idx;  // optional gather
+  int64_t n;
+  uint32_t* out;
+  int64_t cap;
+  long long* d_count;
+  uint64_t* tile_state;  // one word per tile, zeroed
+  uint32_t* ticket;      // zeroed
+  int64_t ntiles;
+};
+
+void launch_filter(const FilterParams& p, hipStream_t s);
+
+// ------------------------------------------------------------- hash maps
+
+// Geometry of one multimap in the workspace.
+struct MapDesc {
+  int32_t key_type;   // kI32 or kI64
+  uint64_t cap;       // slots (power of two)
+  void* slots;        // cap * 8 (int32 keys) or cap * 16 (int64 keys) bytes
+  unsigned long long* oob_count;
+  uint32_t* oob_vals;  // n entries
+};
+
+// Inserts n keys of column (data, idx, type); value of element i is
+// val_col[i] widened to 32 bits when val_col is set, else its row id.
+struct MapBuildParams {
+  MapDesc map;
+  const void* keys;
+  const uint32_t* idx;
+  int32_t type;
+  int64_t n;
+  const void* val_col;
+  int32_t val_type;
+};
+
+void launch_map_init(const MapDesc& m, hipStream_t s);
+void launch_map_build(const MapBuildParams& p, hipStream_t s);
+
+// Probe: emits (value, probe row id) for every match, with a wave-aggregated
+// cursor in d_count (zeroed by launch_map_init's companion below).
+struct MapProbeParams {
+  MapDesc map;
+  const void* keys;
+  const uint32_t* idx;
+  int32_t type;
+  int64_t n;
+  uint32_t* out_build;
+  uint32_t* out_probe;
+  int64_t cap;
+  unsigned long long* d_count;
+};
+
+void launch_map_probe(const MapProbeParams& p, int grid, int block, hipStream_t s);
+
+// ------------------------------------------------------------- group-by
+
+struct GroupDesc {
+  GroupKeyPack kp;
+  AccPlan ap;
+  uint64_t cap;     // slots of the open-addressing array (power of two)
+  int32_t words;    // 64-bit words per slot
+  uint64_t* slots;  // (cap + 1) * words words
+  int32_t* overflow;
+  unsigned long long* d_groups;  // output count (zeroed by init)
+};
+
+void launch_group_init(const GroupDesc& g, hipStream_t s);
+
+struct GroupAggParams {
+  GroupDesc g;
+  const void* key_data[2];
+  const uint32_t* key_idx[2];
+  const void* val_data[kMaxAcc];
+  const uint32_t* val_idx[kMaxAcc];
+  int32_t val_type[kMaxAcc];
+  int64_t n;
+  int32_t lds_slots;  // 0: no LDS table
+};
+
+void launch_group_agg(const GroupAggParams& p, int grid, int block, hipStream_t s);
+
+// Output agg a: op (rel_agg_op) and the accumulator it reads.
+struct FinalizeParams {
+  GroupDesc g;
+  int32_t naggs;
+  int32_t op[8];
+  int32_t acc[8];  // accumulator index (SUM/MIN/MAX/AVG)
+  void* out_keys[2];
+  int32_t out_key_type[2];
+  void* out_aggs[8];
+  int64_t cap;
+};
+
+void launch_group_finalize(const FinalizeParams& p, hipStream_t s);
+
+// ------------------------------------------------------------- pipeline
+
+struct PipeDim {
+  MapDesc map;
+  int32_t fk_col;
+  int32_t in_lds;        // copy the slot array into LDS
+  uint32_t lds_offset;   // byte offset of the copy in dynamic LDS
+};
+
+struct PipelineParams {
+  const void* fact[8];
+  int32_t fact_type[8];
+  int32_t fact_vec[8];
+  int64_t n;
+  int32_t nterms;
+  int32_t term_col[4];
+  int32_t term_op[4];
+  int64_t term_lo[4], term_hi[4];
+  int32_t ndims;
+  PipeDim dim[2];
+  // group key k: fact column (src 0) or dim payload (src 1 + d)
+  int32_t key_src[2];
+  int32_t key_col[2];
+  GroupDesc g;
+  int32_t acc_col[kMaxAcc];  // fact column of each accumulator
+  int32_t lds_slots;          // LDS group table slots (0: none)
+  uint32_t lds_group_offset;  // byte offset of the LDS group table
+  uint32_t lds_queue_offset;  // byte offset of the per-wave row queues
+  uint32_t lds_bytes;
+  int64_t ntiles;
+};
+
+constexpr int kPipeThreads = 1024;
+constexpr int kPipeChunks = 1;                                 // chunks of 4 rows per thread
+constexpr int kPipeTile = kPipeThreads * 4 * kPipeChunks;      // rows per tile
+constexpr int kPipeQueue = 128;                                // row slots per wave queue
+
+void launch_pipeline(const PipelineParams& p, int grid, hipStream_t s);
+
+}  // namespace rel

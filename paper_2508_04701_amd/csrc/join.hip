@@ -1,0 +1,150 @@
+// Hash join: open-addressing multimap build and probe with pair output.
+//
+// Build: each element claims the first empty slot of its linear-probe chain
+// with one CAS (int32 keys publish key and value in the same 64-bit word).
+// Probe: each lane walks its key's chain; the wave advances in rounds, each
+// round giving every lane at most one match, so the output position of a
+// match comes from one wave ballot (mbcnt rank) and one atomic add per wave
+// on the global cursor. The cursor always ends at the exact pair count; pairs
+// beyond the output capacity are counted but not written.
+
+#include "internal.h"
+
+namespace rel {
+
+namespace {
+
+__global__ void fill64_kernel(uint64_t* p, uint64_t n, uint64_t pattern) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    p[i] = pattern;
+}
+
+__global__ void fill_map64_kernel(ulonglong2* p, uint64_t n) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    p[i] = make_ulonglong2(kEmpty64, 0ULL);
+}
+
+__device__ __forceinline__ uint32_t element_value(const MapBuildParams& p, int64_t i) {
+  if (p.val_col) {
+    int64_t r = p.idx ? static_cast<int64_t>(p.idx[i]) : i;
+    return static_cast<uint32_t>(load_elem(p.val_col, p.val_type, r));
+  }
+  return p.idx ? p.idx[i] : static_cast<uint32_t>(i);
+}
+
+template <typename K>
+__global__ void __launch_bounds__(256) map_build_kernel(MapBuildParams p) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+       i < static_cast<uint64_t>(p.n); i += stride) {
+    int64_t r = p.idx ? static_cast<int64_t>(p.idx[i]) : static_cast<int64_t>(i);
+    K key = static_cast<K>(load_elem(p.keys, p.type, r));
+    uint32_t val = element_value(p, static_cast<int64_t>(i));
+    if constexpr (sizeof(K) == 4) {
+      Map32 m{static_cast<uint64_t*>(p.map.slots), p.map.cap - 1, p.map.oob_count, p.map.oob_vals};
+      map_insert(m, key, val);
+    } else {
+      Map64 m{static_cast<ulonglong2*>(p.map.slots), p.map.cap - 1, p.map.oob_count, p.map.oob_vals};
+      map_insert(m, key, val);
+    }
+  }
+}
+
+template <typename K>
+__global__ void __launch_bounds__(256) map_probe_kernel(MapProbeParams p) {
+  using Slot = typename std::conditional<sizeof(K) == 4, uint64_t, ulonglong2>::type;
+  const Slot* slots = static_cast<const Slot*>(p.map.slots);
+  const uint64_t mask = p.map.cap - 1;
+  const int lane = lane_id();
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  // The loop bound is uniform across the workgroup, so whole waves stay
+  // together through the ballots below.
+  for (uint64_t base = blockIdx.x * static_cast<uint64_t>(blockDim.x);
+       base < static_cast<uint64_t>(p.n); base += stride) {
+    const uint64_t i = base + threadIdx.x;
+    bool active = i < static_cast<uint64_t>(p.n);
+    K key = 0;
+    uint32_t prow = 0;
+    MapCursor cur{0, false, false};
+    if (active) {
+      int64_t r = p.idx ? static_cast<int64_t>(p.idx[i]) : static_cast<int64_t>(i);
+      key = static_cast<K>(load_elem(p.keys, p.type, r));
+      prow = static_cast<uint32_t>(r);
+      if constexpr (sizeof(K) == 4) {
+        Map32 m{nullptr, mask, nullptr, nullptr};
+        cur = map_start32(m, key);
+      } else {
+        Map64 m{nullptr, mask, nullptr, nullptr};
+        cur = map_start64(m, key);
+      }
+    }
+    while (ballot(cur.live) != 0) {
+      uint32_t bval = 0;
+      bool found = map_next(slots, mask, p.map.oob_count, p.map.oob_vals, key, cur, bval);
+      uint64_t m = ballot(found);
+      if (m == 0) continue;
+      unsigned long long at = 0;
+      if (lane == 0) at = atomicAdd(p.d_count, static_cast<unsigned long long>(popc64(m)));
+      at = first_lane(at);
+      if (found) {
+        unsigned long long pos = at + rank_below(m);
+        if (pos < static_cast<unsigned long long>(p.cap)) {
+          p.out_build[pos] = bval;
+          p.out_probe[pos] = prow;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+void launch_fill64(uint64_t* p, uint64_t n, uint64_t pattern, hipStream_t s) {
+  if (n == 0) return;
+  ProfileScope ps(kKFill, s);
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill64_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, p, n,
+                     pattern);
+}
+
+void launch_map_init(const MapDesc& m, hipStream_t s) {
+  if (m.key_type == kI32) {
+    launch_fill64(static_cast<uint64_t*>(m.slots), m.cap, kEmptySlot32, s);
+  } else {
+    ProfileScope ps(kKFill, s);
+    uint64_t blocks = (m.cap + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_map64_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                       static_cast<ulonglong2*>(m.slots), m.cap);
+  }
+  launch_fill64(reinterpret_cast<uint64_t*>(m.oob_count), 1, 0, s);
+}
+
+void launch_map_build(const MapBuildParams& p, hipStream_t s) {
+  if (p.n == 0) return;
+  ProfileScope ps(kKMapBuild, s);
+  const DeviceInfo& di = device_info();
+  uint64_t blocks = (static_cast<uint64_t>(p.n) + 255) / 256;
+  uint64_t limit = static_cast<uint64_t>(di.cu_count) * 8;
+  if (blocks > limit) blocks = limit;
+  if (p.map.key_type == kI32)
+    hipLaunchKernelGGL(map_build_kernel<int32_t>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                       s, p);
+  else
+    hipLaunchKernelGGL(map_build_kernel<int64_t>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                       s, p);
+}
+
+void launch_map_probe(const MapProbeParams& p, int grid, int block, hipStream_t s) {
+  if (p.n == 0) return;
+  ProfileScope ps(kKMapProbe, s);
+  if (p.map.key_type == kI32)
+    hipLaunchKernelGGL(map_probe_kernel<int32_t>, dim3(grid), dim3(block), 0, s, p);
+  else
+    hipLaunchKernelGGL(map_probe_kernel<int64_t>, dim3(grid), dim3(block), 0, s, p);
+}
+
+}  // namespace rel

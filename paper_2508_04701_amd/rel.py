@@ -1,0 +1,379 @@
+"""Python binding of librel.so (include/rel.h): argument marshalling only.
+
+Torch supplies device memory and the current stream; every step of the
+relational path runs in the library's HIP kernels. The library must have
+been built (``__graft_entry__.build()``); importing this module on a machine
+without it, or calling an operator without a GPU, raises an error rather than
+computing anything on the CPU.
+
+Plans use plain Python values:
+    preds : [(col, op, lo[, hi])]         op in lt le gt ge eq ne range
+    aggs  : [(op, col)]                   op in sum count min max avg
+    dims  : [dict(fk=fact col, key=tensor, payload=tensor or None)]
+    keys  : [("fact", col) | ("dim", d)]
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librel.so")
+
+REL_OK, REL_EINVAL, REL_ENOMEM, REL_ECAPACITY, REL_EDEVICE, REL_EUNSUPPORTED = range(6)
+DTYPES = {torch.int8: 1, torch.int32: 2, torch.int64: 3}
+TORCH_DTYPE = {1: torch.int8, 2: torch.int32, 3: torch.int64}
+CMP = {"lt": 0, "le": 1, "gt": 2, "ge": 3, "eq": 4, "ne": 5, "range": 6}
+AGG = {"sum": 0, "count": 1, "min": 2, "max": 3, "avg": 4}
+MAX_TERMS, MAX_DIMS, MAX_KEYS, MAX_AGGS, MAX_FACT_COLS = 4, 2, 2, 8, 8
+
+
+class RelError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"rel status {status}: {message}")
+        self.status = status
+
+
+class Column(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("idx", ctypes.c_void_p), ("len", ctypes.c_int64),
+                ("type", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Pred(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_int32), ("op", ctypes.c_int32), ("lo", ctypes.c_int64),
+                ("hi", ctypes.c_int64)]
+
+
+class Agg(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("col", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("load_factor", ctypes.c_float), ("block", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("lds_slots", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class Dim(ctypes.Structure):
+    _fields_ = [("fact_col", ctypes.c_int32), ("has_payload", ctypes.c_int32), ("key", Column),
+                ("payload", Column)]
+
+
+class KeyRef(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_int32), ("col", ctypes.c_int32)]
+
+
+class PipelineDesc(ctypes.Structure):
+    _fields_ = [("fact", ctypes.POINTER(Column)), ("n_fact", ctypes.c_int32),
+                ("preds", ctypes.POINTER(Pred)), ("n_preds", ctypes.c_int32),
+                ("dims", ctypes.POINTER(Dim)), ("n_dims", ctypes.c_int32),
+                ("keys", ctypes.POINTER(KeyRef)), ("n_keys", ctypes.c_int32),
+                ("aggs", ctypes.POINTER(Agg)), ("n_aggs", ctypes.c_int32),
+                ("max_groups", ctypes.c_int64), ("tuning", ctypes.POINTER(Tuning))]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("keys", ctypes.c_void_p * MAX_KEYS), ("aggs", ctypes.c_void_p * MAX_AGGS),
+                ("cap", ctypes.c_int64), ("d_groups", ctypes.c_void_p)]
+
+
+# Every symbol include/rel.h declares: (name, restype, argtypes).
+_P, _I, _L, _S = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+SIGNATURES = {
+    "rel_status_str": (ctypes.c_char_p, [_I]),
+    "rel_last_error": (ctypes.c_char_p, []),
+    "rel_version": (_I, []),
+    "rel_filter_ws": (_S, [_L]),
+    "rel_filter": (_I, [_P, _I, _P, _I, _P, _L, _P, _P, _S, _P]),
+    "rel_hash_join_ws": (_S, [ctypes.c_int32, _L, _P]),
+    "rel_hash_join": (_I, [_P, _P, _P, _P, _L, _P, _P, _P, _S, _P]),
+    "rel_groupby_ws": (_S, [_I, _P, _I, _P, _L, _P]),
+    "rel_groupby_agg": (_I, [_P, _I, _P, _I, _P, _I, _P, _P, _L, _P, _L, _P, _P, _S, _P]),
+    "rel_pipeline_ws": (_S, [_P]),
+    "rel_pipeline": (_I, [_P, _P, _P, _S, _P]),
+    "rel_kernel_name": (ctypes.c_char_p, [_I]),
+    "rel_profile_enable": (None, [_I]),
+    "rel_profile_read": (_I, [_P, _P]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded librel.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def _check(status: int):
+    if status != REL_OK:
+        raise RelError(status, lib().rel_last_error().decode())
+
+
+def _require_gpu(*tensors):
+    if not torch.cuda.is_available():
+        raise RuntimeError("the relational kernels need a ROCm GPU; none is visible")
+    for t in tensors:
+        if t is not None and not t.is_cuda:
+            raise ValueError("inputs must be device tensors")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _addr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def column(t: torch.Tensor, idx: torch.Tensor | None = None) -> Column:
+    if t.dtype not in DTYPES:
+        raise TypeError(f"columns must be int8/int32/int64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("columns must be contiguous")
+    if idx is not None:
+        if idx.dtype != torch.int32 or not idx.is_contiguous():
+            raise TypeError("row ids must be a contiguous int32 tensor holding uint32 values")
+        return Column(t.data_ptr() if t.numel() else None, idx.data_ptr() if idx.numel() else None,
+                      idx.numel(), DTYPES[t.dtype], 0)
+    return Column(t.data_ptr() if t.numel() else None, None, t.numel(), DTYPES[t.dtype], 0)
+
+
+def tuning(load_factor=0.0, block=0, grid=0, lds_slots=0) -> Tuning:
+    return Tuning(load_factor, block, grid, lds_slots, 0, (ctypes.c_int32 * 3)())
+
+
+def _tuning_ptr(t):
+    return ctypes.byref(t) if t is not None else None
+
+
+def _arr(ctype, items):
+    return (ctype * max(1, len(items)))(*items)
+
+
+def _preds(preds):
+    return _arr(Pred, [Pred(int(p[0]), CMP[p[1]], int(p[2]),
+                            int(p[3]) if len(p) > 3 and p[3] is not None else 0) for p in preds])
+
+
+def _aggs(aggs):
+    return _arr(Agg, [Agg(AGG[op], int(col) if col is not None else 0) for op, col in aggs])
+
+
+def workspace(nbytes: int, device=None) -> torch.Tensor:
+    """A 256-byte aligned device buffer (torch's caching allocator aligns to 512)."""
+    return torch.empty(max(256, int(nbytes)), dtype=torch.uint8, device=device or "cuda")
+
+
+def _count(t: torch.Tensor) -> int:
+    return int(t.item())
+
+
+# -------------------------------------------------------------------- filter
+
+def filter_ws(n: int) -> int:
+    return int(lib().rel_filter_ws(n))
+
+
+def filter_async(cols, preds, out, d_count, ws, idx=None):
+    """Enqueues rel_filter; no allocation, no synchronisation."""
+    ccols = _arr(Column, [column(c, idx) for c in cols])
+    cp = _preds(preds)
+    _check(lib().rel_filter(ccols, len(cols), cp, len(preds), _addr(out), out.numel(),
+                            _addr(d_count), _addr(ws), ws.numel(), _stream()))
+
+
+def filter(cols, preds, idx=None) -> torch.Tensor:
+    """Row ids (int32 tensor holding uint32 values) of the passing elements,
+    ascending."""
+    _require_gpu(*cols)
+    n = idx.numel() if idx is not None else cols[0].numel()
+    out = torch.empty(max(1, n), dtype=torch.int32, device=cols[0].device)
+    d_count = torch.zeros(1, dtype=torch.int64, device=cols[0].device)
+    ws = workspace(filter_ws(n), cols[0].device)
+    filter_async(cols, preds, out, d_count, ws, idx)
+    return out[:_count(d_count)]
+
+
+# ----------------------------------------------------------------- hash join
+
+def hash_join_ws(key_type: torch.dtype, n_build: int, t: Tuning | None = None) -> int:
+    return int(lib().rel_hash_join_ws(DTYPES[key_type], n_build, _tuning_ptr(t)))
+
+
+def hash_join_async(build, probe, out_build, out_probe, d_count, ws, build_idx=None,
+                    probe_idx=None, t: Tuning | None = None):
+    cb, cp = column(build, build_idx), column(probe, probe_idx)
+    _check(lib().rel_hash_join(ctypes.byref(cb), ctypes.byref(cp), _addr(out_build),
+                               _addr(out_probe), out_build.numel(), _addr(d_count),
+                               _tuning_ptr(t), _addr(ws), ws.numel(), _stream()))
+
+
+def hash_join(build, probe, build_idx=None, probe_idx=None, out_cap=None,
+              t: Tuning | None = None):
+    """(build row ids, probe row ids) of every matching pair, unordered."""
+    _require_gpu(build, probe)
+    dev = probe.device
+    n_build = build_idx.numel() if build_idx is not None else build.numel()
+    n_probe = probe_idx.numel() if probe_idx is not None else probe.numel()
+    ws = workspace(hash_join_ws(build.dtype, n_build, t), dev)
+    d_count = torch.zeros(1, dtype=torch.int64, device=dev)
+    cap = max(1, n_probe if out_cap is None else out_cap)
+    while True:
+        ob = torch.empty(cap, dtype=torch.int32, device=dev)
+        op = torch.empty(cap, dtype=torch.int32, device=dev)
+        hash_join_async(build, probe, ob, op, d_count, ws, build_idx, probe_idx, t)
+        total = _count(d_count)
+        if total <= cap:
+            return ob[:total], op[:total]
+        cap = total
+
+
+# ------------------------------------------------------------------ group-by
+
+def _out_tensors(key_dtypes, aggs, cap, dev):
+    out_keys = [torch.empty(cap, dtype=dt, device=dev) for dt in key_dtypes]
+    out_aggs = [torch.empty(cap, dtype=torch.float64 if op == "avg" else torch.int64, device=dev)
+                for op, _ in aggs]
+    return out_keys, out_aggs
+
+
+def groupby_ws(key_dtypes, aggs, max_groups: int, t: Tuning | None = None) -> int:
+    kt = _arr(ctypes.c_int32, [DTYPES[d] for d in key_dtypes])
+    return int(lib().rel_groupby_ws(len(key_dtypes), kt, len(aggs), _aggs(aggs), max_groups,
+                                    _tuning_ptr(t)))
+
+
+def groupby_agg_async(keys, vals, aggs, out_keys, out_aggs, d_groups, max_groups, ws,
+                      key_idx=None, val_idx=None, t: Tuning | None = None):
+    ck = _arr(Column, [column(k, key_idx) for k in keys])
+    cv = _arr(Column, [column(v, val_idx) for v in vals])
+    ok = _arr(ctypes.c_void_p, [o.data_ptr() for o in out_keys])
+    oa = _arr(ctypes.c_void_p, [o.data_ptr() for o in out_aggs])
+    cap = out_aggs[0].numel() if out_aggs else 0
+    _check(lib().rel_groupby_agg(ck, len(keys), cv, len(vals), _aggs(aggs), len(aggs), ok, oa, cap,
+                                 _addr(d_groups), max_groups, _tuning_ptr(t), _addr(ws),
+                                 ws.numel(), _stream()))
+
+
+def groupby_agg(keys, vals, aggs, max_groups: int | None = None, key_idx=None, val_idx=None,
+                t: Tuning | None = None):
+    """(key columns, aggregate columns) of every group, unordered."""
+    _require_gpu(*keys, *vals)
+    dev = (keys or vals)[0].device
+    n = key_idx.numel() if key_idx is not None else (keys or vals)[0].numel()
+    max_groups = max(1, n) if max_groups is None else max_groups
+    key_dtypes = [k.dtype for k in keys]
+    ws = workspace(groupby_ws(key_dtypes, aggs, max_groups, t), dev)
+    d_groups = torch.zeros(1, dtype=torch.int64, device=dev)
+    cap = max(1, min(max_groups, max(1, n)))
+    while True:
+        out_keys, out_aggs = _out_tensors(key_dtypes, aggs, cap, dev)
+        groupby_agg_async(keys, vals, aggs, out_keys, out_aggs, d_groups, max_groups, ws,
+                          key_idx, val_idx, t)
+        ng = _count(d_groups)
+        if ng < 0:
+            raise RelError(REL_ECAPACITY, f"more than max_groups={max_groups} groups")
+        if ng <= cap:
+            return [k[:ng] for k in out_keys], [a[:ng] for a in out_aggs]
+        cap = ng
+
+
+# ------------------------------------------------------------------ pipeline
+
+class PreparedPipeline:
+    """A fused plan bound to its inputs, workspace and output buffers.
+    ``launch()`` only enqueues kernels (no allocation, no synchronisation)."""
+
+    def __init__(self, fact, preds, dims, keys, aggs, max_groups: int, t: Tuning | None = None,
+                 out_cap: int | None = None):
+        _require_gpu(*fact)
+        dev = fact[0].device
+        self._keep = [fact, dims]
+        self.aggs = aggs
+        self._fact = _arr(Column, [column(c) for c in fact])
+        self._preds = _preds(preds)
+        cdims = []
+        for d in dims:
+            pay = d.get("payload")
+            cdims.append(Dim(int(d["fk"]), 1 if pay is not None else 0, column(d["key"]),
+                             column(pay) if pay is not None else Column()))
+        self._dims = _arr(Dim, cdims)
+        self._keys = _arr(KeyRef, [KeyRef(0 if src == "fact" else 1, int(c)) for src, c in keys])
+        self._aggs = _aggs(aggs)
+        self._tuning = t
+        self.desc = PipelineDesc(
+            ctypes.cast(self._fact, ctypes.POINTER(Column)), len(fact),
+            ctypes.cast(self._preds, ctypes.POINTER(Pred)), len(preds),
+            ctypes.cast(self._dims, ctypes.POINTER(Dim)), len(dims),
+            ctypes.cast(self._keys, ctypes.POINTER(KeyRef)), len(keys),
+            ctypes.cast(self._aggs, ctypes.POINTER(Agg)), len(aggs), int(max_groups),
+            ctypes.pointer(t) if t is not None else None)
+        nbytes = lib().rel_pipeline_ws(ctypes.byref(self.desc))
+        if nbytes == 0:
+            # the same validation, run again, names the problem
+            _check(lib().rel_pipeline(ctypes.byref(self.desc), None, None, 0, None))
+        self.ws = workspace(nbytes, dev)
+        key_dtypes = [fact[c].dtype if src == "fact" else dims[c]["payload"].dtype
+                      for src, c in keys]
+        self.key_dtypes = key_dtypes
+        self.cap = max(1, int(max_groups) if out_cap is None else out_cap)
+        self.out_keys, self.out_aggs = _out_tensors(key_dtypes, aggs, self.cap, dev)
+        self.d_groups = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.outputs = Outputs()
+        for i, k in enumerate(self.out_keys):
+            self.outputs.keys[i] = k.data_ptr()
+        for i, a in enumerate(self.out_aggs):
+            self.outputs.aggs[i] = a.data_ptr()
+        self.outputs.cap = self.cap
+        self.outputs.d_groups = self.d_groups.data_ptr()
+
+    def launch(self):
+        _check(lib().rel_pipeline(ctypes.byref(self.desc), ctypes.byref(self.outputs),
+                                  _addr(self.ws), self.ws.numel(), _stream()))
+
+    def result(self):
+        """Synchronises on the group count and returns (keys, aggs)."""
+        ng = _count(self.d_groups)
+        if ng < 0:
+            raise RelError(REL_ECAPACITY, "more groups than max_groups")
+        if ng > self.cap:
+            raise RelError(REL_ECAPACITY, f"{ng} groups exceed the output capacity {self.cap}")
+        return [k[:ng] for k in self.out_keys], [a[:ng] for a in self.out_aggs]
+
+
+def pipeline(fact, preds, dims, keys, aggs, max_groups: int, t: Tuning | None = None):
+    """Runs the fused plan and returns (key columns, aggregate columns)."""
+    p = PreparedPipeline(fact, preds, dims, keys, aggs, max_groups, t)
+    p.launch()
+    return p.result()
+
+
+# ------------------------------------------------------------------ profiling
+
+KERNEL_CLASSES = 7
+
+
+def profile_enable(on: bool = True):
+    """Brackets every kernel launched afterwards with HIP events."""
+    lib().rel_profile_enable(1 if on else 0)
+
+
+def profile_read() -> dict:
+    """{kernel class: (total ms, launches)} since the last read (synchronises)."""
+    ms = (ctypes.c_double * KERNEL_CLASSES)()
+    n = (ctypes.c_int64 * KERNEL_CLASSES)()
+    _check(lib().rel_profile_read(ms, n))
+    return {lib().rel_kernel_name(k).decode(): (ms[k], n[k]) for k in range(KERNEL_CLASSES)}

@@ -1,0 +1,353 @@
+"""GPU parity: every entry point of the C-ABI against the oracle on the same
+seeded inputs. Filter output must match exactly (ascending row ids); join
+pairs and groups must match exactly after canonical sorting, AVG bit for
+bit (tolerance 0)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import announce, assert_groups, assert_pairs, dev, rowids
+from paper_2508_04701_amd import datagen, rel
+
+pytestmark = pytest.mark.gpu
+
+I32_MIN, I32_MAX = -(2**31), 2**31 - 1
+I64_MIN, I64_MAX = -(2**63), 2**63 - 1
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+def col_with_extremes(r, n, dtype, lo, hi, frac=0.05):
+    v = r.integers(lo, hi, size=n).astype(dtype)
+    info = np.iinfo(dtype)
+    pick = r.random(n) < frac
+    v[pick] = r.choice(np.array([info.min, info.max, -1, 0], dtype=dtype), size=int(pick.sum()))
+    return v
+
+
+# ------------------------------------------------------------------ filter
+
+@pytest.mark.parametrize("n", [0, 1, 7, 4095, 4096, 4097, 100_003, 1_000_000])
+def test_filter_sizes(n):
+    announce("filter sizes", n)
+    r = rng(n)
+    date = r.integers(0, 2557, size=n).astype(np.int32)
+    got = rel.filter([dev(date)], [(0, "lt", 767)])
+    want = oracle.filter([date], [(0, "lt", 767)])
+    assert np.array_equal(rowids(got), want)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_filter_mixed_terms(seed):
+    r = rng(100 + seed)
+    n = int(r.integers(20_000, 120_000))
+    cols = [col_with_extremes(r, n, np.int8, -20, 20), col_with_extremes(r, n, np.int32, -50, 50),
+            col_with_extremes(r, n, np.int64, -10**6, 10**6)]
+    ops = list(rel.CMP)
+    terms = []
+    for _ in range(int(r.integers(1, 5))):
+        c = int(r.integers(0, 3))
+        op = ops[int(r.integers(0, len(ops)))]
+        scale = [20, 50, 10**6][c]
+        lo = int(r.integers(-scale, scale))
+        terms.append((c, op, lo, lo + int(r.integers(0, scale))))
+    announce("filter mixed", seed, n, terms)
+    # unaligned views exercise the scalar load path
+    offset = seed % 2
+    dcols = [dev(c) for c in cols] if not offset else [dev(np.concatenate([c[:1], c]))[1:] for c in cols]
+    got = rel.filter(dcols, terms)
+    want = oracle.filter(cols, terms)
+    assert np.array_equal(rowids(got), want)
+
+
+def test_filter_selection_vectors():
+    r = rng(7)
+    n = 300_000
+    x = r.integers(-100, 100, size=n).astype(np.int64)
+    y = r.integers(0, 10, size=n).astype(np.int32)
+    terms = [(0, "range", -30, 40), (1, "ne", 3)]
+    for name, sel in (("sorted", np.sort(r.choice(n, size=n // 3, replace=False))),
+                      ("shuffled", r.permutation(n)[: n // 2]),
+                      ("empty", np.zeros(0, np.int64))):
+        announce("filter selection", name)
+        sel = sel.astype(np.uint32)
+        got = rel.filter([dev(x), dev(y)], terms, idx=dev(sel.view(np.int32)))
+        want = oracle.filter([x, y], terms, sel=sel)
+        assert np.array_equal(rowids(got), want), name
+
+
+def test_filter_output_capacity():
+    announce("filter capacity")
+    r = rng(9)
+    n = 50_000
+    x = r.integers(0, 100, size=n).astype(np.int32)
+    want = oracle.filter([x], [(0, "lt", 50)])
+    out = torch.full((1000,), -7, dtype=torch.int32, device="cuda")
+    d_count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ws = rel.workspace(rel.filter_ws(n))
+    rel.filter_async([dev(x)], [(0, "lt", 50)], out, d_count, ws)
+    assert int(d_count.item()) == len(want)
+    assert np.array_equal(rowids(out), want[:1000])
+
+
+def test_filter_all_and_nothing():
+    x = np.arange(-5000, 5000, dtype=np.int64)
+    announce("filter all/nothing")
+    every = rel.filter([dev(x)], [(0, "range", I64_MIN, I64_MAX)])
+    assert np.array_equal(rowids(every), np.arange(10_000, dtype=np.uint32))
+    assert rel.filter([dev(x)], [(0, "gt", I64_MAX)]).numel() == 0
+
+
+# --------------------------------------------------------------- hash join
+
+def join_case(case, dtype, r):
+    info = np.iinfo(dtype)
+    if case == "unique":
+        b = r.permutation(20_000).astype(dtype) * 7 - 3
+        p = r.integers(-10, 160_000, size=90_000).astype(dtype)
+    elif case == "dups":
+        b = r.integers(0, 3000, size=12_000).astype(dtype)
+        p = r.integers(0, 4000, size=30_000).astype(dtype)
+    elif case == "sentinel":
+        b = r.choice(np.array([info.min, info.max, -1, 0, 5], dtype=dtype), size=300)
+        p = r.choice(np.array([info.min, info.max, -1, 0, 7], dtype=dtype), size=500)
+    elif case == "empty_build":
+        b = np.zeros(0, dtype)
+        p = r.integers(0, 10, size=1000).astype(dtype)
+    else:
+        b = r.integers(0, 10, size=1000).astype(dtype)
+        p = np.zeros(0, dtype)
+    return b, p
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64], ids=["i32", "i64"])
+@pytest.mark.parametrize("case", ["unique", "dups", "sentinel", "empty_build", "empty_probe"])
+def test_hash_join(case, dtype):
+    announce("join", case, np.dtype(dtype).name)
+    seed = {"unique": 1, "dups": 2, "sentinel": 3, "empty_build": 4, "empty_probe": 5}[case]
+    b, p = join_case(case, dtype, rng(seed))
+    got = rel.hash_join(dev(b), dev(p))
+    assert_pairs(got, oracle.hash_join(b, p), case)
+
+
+def test_hash_join_with_row_ids():
+    announce("join with idx")
+    r = rng(3)
+    b = r.integers(0, 5000, size=8000).astype(np.int64)
+    p = r.integers(0, 6000, size=40_000).astype(np.int64)
+    bsel = np.sort(r.choice(8000, size=3000, replace=False)).astype(np.uint32)
+    psel = r.permutation(40_000)[:25_000].astype(np.uint32)
+    got = rel.hash_join(dev(b), dev(p), build_idx=dev(bsel.view(np.int32)),
+                        probe_idx=dev(psel.view(np.int32)))
+    wb, wp = oracle.hash_join(b[bsel], p[psel])
+    wb2, wp2 = bsel[wb], psel[wp]     # row ids are original positions
+    order = np.lexsort((wb2, wp2))
+    assert_pairs(got, (wb2[order], wp2[order]), "idx")
+
+
+def test_hash_join_capacity():
+    announce("join capacity")
+    r = rng(4)
+    b = r.integers(0, 100, size=2000).astype(np.int32)
+    p = r.integers(0, 100, size=2000).astype(np.int32)
+    wb, wp = oracle.hash_join(b, p)
+    ws = rel.workspace(rel.hash_join_ws(torch.int32, 2000))
+    ob = torch.empty(100, dtype=torch.int32, device="cuda")
+    op = torch.empty(100, dtype=torch.int32, device="cuda")
+    d = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rel.hash_join_async(dev(b), dev(p), ob, op, d, ws)
+    assert int(d.item()) == len(wb)
+    # every written pair is a true match
+    gb, gp = rowids(ob), rowids(op)
+    assert np.array_equal(b[gb], p[gp])
+
+
+# ---------------------------------------------------------------- group-by
+
+ALL_AGGS = [("sum", 0), ("count", None), ("min", 0), ("max", 0), ("avg", 0), ("sum", 1),
+            ("avg", 1), ("min", 2)]
+
+
+def groupby_inputs(r, n, key_dtypes, ngroups):
+    keys = []
+    for dt in key_dtypes:
+        hi = min(ngroups, np.iinfo(dt).max)
+        keys.append(r.integers(-hi // 2, hi - hi // 2, size=n).astype(dt))
+    vals = [col_with_extremes(r, n, np.int64, -10**12, 10**12, 0.01),
+            r.integers(-1000, 1000, size=n).astype(np.int32),
+            r.integers(-100, 100, size=n).astype(np.int8)]
+    return keys, vals
+
+
+@pytest.mark.parametrize("key_dtypes", [[], [np.int32], [np.int64], [np.int8, np.int32],
+                                        [np.int32, np.int32], [np.int32, np.int8]],
+                         ids=["none", "i32", "i64", "i8+i32", "i32+i32", "i32+i8"])
+@pytest.mark.parametrize("ngroups,lds", [(3, 0), (75, 0), (5000, 0), (200_000, 0), (75, -1),
+                                         (5000, -1)])
+def test_groupby(key_dtypes, ngroups, lds):
+    r = rng(ngroups + 10 * len(key_dtypes))
+    n = 150_001
+    keys, vals = groupby_inputs(r, n, key_dtypes, ngroups)
+    announce("groupby", [np.dtype(d).name for d in key_dtypes], ngroups, lds)
+    t = rel.tuning(lds_slots=lds)
+    got = rel.groupby_agg([dev(k) for k in keys], [dev(v) for v in vals], ALL_AGGS,
+                          max_groups=min(n, ngroups ** max(1, len(key_dtypes))), t=t)
+    assert_groups(got, oracle.groupby(keys, vals, ALL_AGGS), ALL_AGGS,
+                  f"groupby {key_dtypes} {ngroups}")
+
+
+def test_groupby_sentinel_patterns():
+    announce("groupby sentinel keys")
+    r = rng(5)
+    n = 20_000
+    v = r.integers(-50, 50, size=n).astype(np.int64)
+    k64 = r.choice(np.array([I64_MIN, I64_MAX, -1, 0, 3], dtype=np.int64), size=n)
+    aggs = [("sum", 0), ("count", None), ("avg", 0), ("max", 0)]
+    got = rel.groupby_agg([dev(k64)], [dev(v)], aggs, max_groups=16)
+    assert_groups(got, oracle.groupby([k64], [v], aggs), aggs, "int64 sentinel")
+    # (INT32_MIN, 0) packs to the sentinel pattern of two int32 keys
+    a = r.choice(np.array([I32_MIN, 0, 1], dtype=np.int32), size=n)
+    b = r.choice(np.array([0, I32_MIN, -1], dtype=np.int32), size=n)
+    got = rel.groupby_agg([dev(a), dev(b)], [dev(v)], aggs, max_groups=16)
+    assert_groups(got, oracle.groupby([a, b], [v], aggs), aggs, "int32 pair sentinel")
+
+
+def test_groupby_empty_inputs():
+    announce("groupby empty")
+    aggs = [("sum", 0), ("count", None), ("min", 0), ("max", 0), ("avg", 0)]
+    e32, e64 = np.zeros(0, np.int32), np.zeros(0, np.int64)
+    got = rel.groupby_agg([dev(e32)], [dev(e64)], aggs, max_groups=8)
+    assert got[1][0].numel() == 0
+    got = rel.groupby_agg([], [dev(e64)], aggs, max_groups=1)
+    assert_groups(got, oracle.groupby([], [e64], aggs), aggs, "ungrouped empty")
+
+
+def test_groupby_too_many_groups():
+    announce("groupby overflow")
+    k = np.arange(10_000, dtype=np.int32)
+    v = np.ones(10_000, np.int64)
+    with pytest.raises(rel.RelError) as e:
+        rel.groupby_agg([dev(k)], [dev(v)], [("sum", 0)], max_groups=1)
+    assert e.value.status == rel.REL_ECAPACITY
+
+
+def test_groupby_with_row_ids():
+    announce("groupby idx")
+    r = rng(6)
+    n = 100_000
+    k = r.integers(0, 300, size=n).astype(np.int32)
+    v = r.integers(0, 10**6, size=n).astype(np.int64)
+    sel = r.permutation(n)[: n // 2].astype(np.uint32)
+    aggs = [("sum", 0), ("count", None), ("avg", 0)]
+    si = dev(sel.view(np.int32))
+    got = rel.groupby_agg([dev(k)], [dev(v)], aggs, max_groups=300, key_idx=si, val_idx=si)
+    assert_groups(got, oracle.groupby([k[sel]], [v[sel]], aggs), aggs, "idx")
+
+
+# ---------------------------------------------------------------- pipeline
+
+STAR_AGGS = [("sum", 3), ("count", None), ("avg", 3), ("min", 3), ("max", 3)]
+
+
+def star_plan(d):
+    fact = [d["fk_a"], d["fk_b"], d["date"], d["price"], d["flag"]]
+    dims = [dict(fk=0, key=d["dim_a_key"], payload=None),
+            dict(fk=1, key=d["dim_b_key"], payload=d["dim_b_region"])]
+    return fact, [(2, "lt", 767)], dims, [("dim", 1), ("fact", 4)], STAR_AGGS
+
+
+def run_both(fact, terms, dims, keys, aggs, max_groups, t=None):
+    ddims = [dict(fk=x["fk"], key=dev(x["key"]),
+                  payload=None if x.get("payload") is None else dev(x["payload"])) for x in dims]
+    got = rel.pipeline([dev(c) for c in fact], terms, ddims, keys, aggs, max_groups, t)
+    want = oracle.pipeline(fact, terms, dims, keys, aggs)
+    return got, want
+
+
+@pytest.mark.parametrize("n", [0, 1, 4095, 4097, 300_001])
+def test_pipeline_star_schema(n):
+    announce("pipeline star", n)
+    d = datagen.star_schema(seed=11, n_fact=n, n_dim_a=30_000, n_dim_b=2_000)
+    fact, terms, dims, keys, aggs = star_plan(d)
+    got, want = run_both(fact, terms, dims, keys, aggs, max_groups=128)
+    assert_groups(got, want, aggs, f"star {n}")
+
+
+@pytest.mark.parametrize("lds", [0, -1])
+def test_pipeline_dims_with_duplicates_and_sentinels(lds):
+    announce("pipeline dup dims", lds)
+    r = rng(21)
+    n = 60_000
+    fk0 = r.choice(np.array([I32_MIN, -1, 0, 1, 2, 3, 4, 5], dtype=np.int32), size=n)
+    fk1 = r.integers(-2, 40, size=n).astype(np.int64)
+    date = r.integers(0, 100, size=n).astype(np.int32)
+    price = col_with_extremes(r, n, np.int64, -10**9, 10**9, 0.01)
+    flag = r.integers(0, 3, size=n).astype(np.int8)
+    fact = [fk0, fk1, date, price, flag]
+    dims = [dict(fk=0, key=np.array([I32_MIN, 0, 0, 1, 3, 3, 3, 9], np.int32),
+                 payload=np.array([7, -1, 2, 2, 5, -128, 0, 1], np.int8)),
+            dict(fk=1, key=r.integers(-2, 30, size=50).astype(np.int64),
+                 payload=r.integers(-5, 5, size=50).astype(np.int32))]
+    keys = [("dim", 0), ("fact", 4)]
+    got, want = run_both(fact, [(2, "range", 10, 70), (3, "ne", 0)], dims, keys, STAR_AGGS,
+                         max_groups=256, t=rel.tuning(lds_slots=lds))
+    assert_groups(got, want, STAR_AGGS, "dup dims")
+
+
+def test_pipeline_shapes():
+    r = rng(22)
+    n = 80_000
+    a = r.integers(0, 50_000, size=n).astype(np.int32)
+    g = r.integers(0, 1000, size=n).astype(np.int32)
+    v = r.integers(-10**6, 10**6, size=n).astype(np.int64)
+    fact = [a, g, v]
+    aggs = [("sum", 2), ("count", None), ("max", 2)]
+    big_dim = dict(fk=0, key=r.permutation(60_000).astype(np.int32),
+                   payload=r.integers(0, 70_000, size=60_000).astype(np.int32))
+    cases = {
+        "no dims, fact key": ([], [("fact", 1)], [(2, "gt", 0)]),
+        "no dims, no keys": ([], [], [(2, "gt", 0)]),
+        "no predicate": ([big_dim], [("dim", 0)], []),
+        "HBM dim, dim key": ([big_dim], [("dim", 0)], [(1, "lt", 500)]),
+        "dim key + fact key": ([big_dim], [("dim", 0), ("fact", 1)], [(1, "lt", 500)]),
+    }
+    for name, (dims, keys, terms) in cases.items():
+        announce("pipeline shape", name)
+        got, want = run_both(fact, terms, dims, keys, aggs, max_groups=80_000)
+        assert_groups(got, want, aggs, name)
+
+
+def test_pipeline_int64_dim_keys():
+    announce("pipeline int64 dims")
+    d = datagen.skewed(n_build=20_000, n_probe=200_000, n_groups=500)
+    fact = [d["probe_key"], d["probe_grp"], d["probe_val"]]
+    dims = [dict(fk=0, key=d["build_key"], payload=None)]
+    aggs = [("sum", 2), ("count", None)]
+    got, want = run_both(fact, [], dims, [("fact", 1)], aggs, max_groups=1000)
+    assert_groups(got, want, aggs, "int64 dims")
+
+
+# ------------------------------------------------------------ workload sizes
+
+def test_join_groupby_workload_full_size():
+    """65,536 build rows x 1,048,576 probe rows, SUM/COUNT by a 64-value
+    build attribute: as the fused plan, and as join -> group-by chained
+    through row ids."""
+    announce("join+groupby 64k x 1M")
+    d = datagen.join_groupby()
+    fact = [d["probe_key"], d["probe_val"]]
+    dims = [dict(fk=0, key=d["build_key"], payload=d["build_grp"])]
+    aggs = [("sum", 1), ("count", None)]
+    got, want = run_both(fact, [], dims, [("dim", 0)], aggs, max_groups=64)
+    assert_groups(got, want, aggs, "fused")
+    # chained: pairs -> gather build attribute and probe value by row id
+    ob, op = rel.hash_join(dev(d["build_key"]), dev(d["probe_key"]))
+    assert_pairs((ob, op), oracle.hash_join(d["build_key"], d["probe_key"]), "join")
+    chained_aggs = [("sum", 0), ("count", None)]
+    got2 = rel.groupby_agg([dev(d["build_grp"])], [dev(d["probe_val"])], chained_aggs,
+                           max_groups=64, key_idx=ob, val_idx=op)
+    assert_groups(got2, want, chained_aggs, "chained")
