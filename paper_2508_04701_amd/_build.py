@@ -30,9 +30,16 @@ HIP_FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, "-x", "hip", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+# The fused pipeline kernel is instantiated per first-dim access mode in
+# separate objects (see pipeline.hip) so that the variants compile in parallel.
+UNITS = [(s, s.replace(".hip", "").replace(".cpp", ""), []) for s in SOURCES] + [
+    ("pipeline.hip", f"pipeline_d{m}", [f"-DREL_PIPE_D0={m}"]) for m in range(1, 6)]
+
+
+def _compile(unit) -> str:
+    src, name, defs = unit
+    obj = os.path.join(BUILD_DIR, name + ".o")
+    cmd = [HIPCC, "-x", "hip", *HIP_FLAGS, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
@@ -41,8 +48,9 @@ def _compile(src: str) -> str:
 
 def build_rel(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    workers = min(len(UNITS), max(1, os.cpu_count() or 1))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(_compile, UNITS))
     tmp = LIB_PATH + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -104,15 +104,17 @@ rel_status after_launch(hipStream_t s, const char* what) {
 
 struct MapLayout {
   uint64_t cap;
+  size_t slot_bytes;
   size_t slots_off, oob_count_off, oob_vals_off, end;
 };
 
-MapLayout map_layout(int32_t key_type, int64_t n, float lf, size_t base) {
+MapLayout map_layout(int32_t key_type, int64_t n, float lf, size_t base, bool key_only = false) {
   MapLayout m;
   uint64_t want = static_cast<uint64_t>(std::ceil(static_cast<double>(n) / lf));
   m.cap = next_pow2(want < 64 ? 64 : want);
   if (m.cap <= static_cast<uint64_t>(n)) m.cap = next_pow2(static_cast<uint64_t>(n) + 1);
-  size_t slot = key_type == REL_I64 ? 16 : 8;
+  size_t slot = key_type == REL_I64 ? 16 : (key_only ? 4 : 8);
+  m.slot_bytes = slot;
   m.slots_off = base;
   m.oob_count_off = align_up(m.slots_off + m.cap * slot);
   m.oob_vals_off = m.oob_count_off + kAlign;
@@ -123,9 +125,11 @@ MapLayout map_layout(int32_t key_type, int64_t n, float lf, size_t base) {
 MapDesc map_desc(const MapLayout& l, int32_t key_type, unsigned char* ws) {
   MapDesc d;
   d.key_type = key_type == REL_I64 ? kI64 : kI32;
+  d.key_only = (key_type != REL_I64 && l.slot_bytes == 4) ? 1 : 0;
   d.cap = l.cap;
   d.slots = ws + l.slots_off;
   d.oob_count = reinterpret_cast<unsigned long long*>(ws + l.oob_count_off);
+  d.dup = reinterpret_cast<int32_t*>(ws + l.oob_count_off + 8);
   d.oob_vals = reinterpret_cast<uint32_t*>(ws + l.oob_vals_off);
   return d;
 }
@@ -176,15 +180,22 @@ rel_status group_plan(int nkeys, const int32_t* key_types, int naggs, const rel_
 
 struct GroupLayout {
   uint64_t cap;
+  int replicas;
   size_t slots_off, overflow_off, end;
 };
 
-GroupLayout group_layout(const GroupPlan& gp, int64_t max_groups, float lf, size_t base) {
+// Replicas of the global group table: with few groups (all of them fit the
+// per-workgroup LDS tables) merges are spread over kGroupReplicas copies.
+constexpr int kGroupReplicas = 64;
+
+GroupLayout group_layout(const GroupPlan& gp, int64_t max_groups, float lf, size_t base,
+                         int replicas = 1) {
   GroupLayout g;
   uint64_t want = static_cast<uint64_t>(std::ceil(static_cast<double>(max_groups < 1 ? 1 : max_groups) / lf));
   g.cap = next_pow2(want < 64 ? 64 : want);
+  g.replicas = replicas;
   g.slots_off = base;
-  g.overflow_off = align_up(g.slots_off + (g.cap + 1) * gp.words * 8);
+  g.overflow_off = align_up(g.slots_off + replicas * (g.cap + 1) * gp.words * 8);
   g.end = g.overflow_off + kAlign;
   return g;
 }
@@ -196,6 +207,7 @@ GroupDesc group_desc(const GroupPlan& gp, const GroupLayout& l, unsigned char* w
   g.ap = gp.ap;
   g.cap = l.cap;
   g.words = gp.words;
+  g.replicas = l.replicas;
   g.slots = reinterpret_cast<uint64_t*>(ws + l.slots_off);
   g.overflow = reinterpret_cast<int32_t*>(ws + l.overflow_off);
   g.d_groups = reinterpret_cast<unsigned long long*>(d_groups);
@@ -222,6 +234,11 @@ int default_lds_slots(const rel_tuning* t, int64_t max_groups, int words, size_t
                                           : next_pow2(2 * static_cast<uint64_t>(max_groups < 32 ? 32 : max_groups));
   if (want > max_by_lds) want = max_by_lds;
   return static_cast<int>(want);
+}
+
+int groupby_replicas(const rel_tuning* t, int64_t max_groups, const GroupPlan& gp) {
+  const int lds = default_lds_slots(t, max_groups, gp.words, 32768);
+  return (lds > 0 && 2 * max_groups <= lds) ? kGroupReplicas : 1;
 }
 
 FinalizeParams finalize_params(const GroupDesc& g, const GroupPlan& gp, const rel_agg* aggs,
@@ -266,6 +283,7 @@ struct PipeLayout {
   GroupPlan gp;
   GroupLayout group;
   int32_t key_types[REL_MAX_KEYS];
+  int lds_slots;
   size_t end;
 };
 
@@ -335,7 +353,10 @@ rel_status pipeline_layout(const rel_pipeline_desc* d, PipeLayout& L) {
   const float lf = load_factor(d->tuning);
   size_t off = 0;
   for (int i = 0; i < d->n_dims; ++i) {
-    L.dim[i] = map_layout(d->dims[i].key.type, d->dims[i].key.len, lf < 0.75f ? 0.75f : lf, off);
+    // membership-only int32 dims keep keys alone (4-byte slots)
+    const bool key_only = d->dims[i].key.type == REL_I32 && !d->dims[i].has_payload;
+    L.dim[i] = map_layout(d->dims[i].key.type, d->dims[i].key.len, lf < 0.75f ? 0.75f : lf, off,
+                          key_only);
     off = L.dim[i].end;
   }
   for (int k = 0; k < d->n_keys; ++k) {
@@ -344,7 +365,9 @@ rel_status pipeline_layout(const rel_pipeline_desc* d, PipeLayout& L) {
   }
   rel_status st = group_plan(d->n_keys, L.key_types, d->n_aggs, d->aggs, L.gp);
   if (st) return st;
-  L.group = group_layout(L.gp, d->max_groups, lf, off);
+  L.lds_slots = default_lds_slots(d->tuning, d->max_groups, L.gp.words, 16384);
+  const bool few = L.lds_slots > 0 && 2 * d->max_groups <= L.lds_slots;
+  L.group = group_layout(L.gp, d->max_groups, lf, off, few ? kGroupReplicas : 1);
   L.end = L.group.end;
   return REL_OK;
 }
@@ -524,7 +547,7 @@ size_t rel_groupby_ws(int nkeys, const int32_t* key_types, int naggs, const rel_
     if (!valid_type(key_types[k])) return 0;
   GroupPlan gp;
   if (group_plan(nkeys, key_types, naggs, aggs, gp) != REL_OK) return 0;
-  return group_layout(gp, max_groups, load_factor(t), 0).end;
+  return group_layout(gp, max_groups, load_factor(t), 0, groupby_replicas(t, max_groups, gp)).end;
 }
 
 rel_status rel_groupby_agg(const rel_column* keys, int nkeys, const rel_column* vals, int nvals,
@@ -561,7 +584,8 @@ rel_status rel_groupby_agg(const rel_column* keys, int nkeys, const rel_column* 
   GroupPlan gp;
   st = group_plan(nkeys, key_types, naggs, aggs, gp);
   if (st) return st;
-  const GroupLayout L = group_layout(gp, max_groups, load_factor(t), 0);
+  const GroupLayout L =
+      group_layout(gp, max_groups, load_factor(t), 0, groupby_replicas(t, max_groups, gp));
   st = check_ws(ws, ws_bytes, L.end);
   if (st) return st;
 
@@ -592,6 +616,7 @@ rel_status rel_groupby_agg(const rel_column* keys, int nkeys, const rel_column* 
     if (blocks > limit) blocks = limit;
     launch_group_agg(p, static_cast<int>(blocks), block, s);
   }
+  launch_group_merge(g, s);
   launch_group_finalize(
       finalize_params(g, gp, aggs, naggs, out_keys, key_types, out_aggs, out_cap), s);
   return after_launch(s, "groupby");
@@ -642,38 +667,75 @@ rel_status rel_pipeline(const rel_pipeline_desc* d, const rel_outputs* o, void* 
     p.term_hi[i] = d->preds[i].hi;
   }
   p.g = group_desc(L.gp, L.group, w, o->d_groups);
-  for (int a = 0; a < L.gp.ap.nacc; ++a) p.acc_col[a] = L.gp.ap.col[a];
   for (int k = 0; k < d->n_keys; ++k) {
     p.key_src[k] = d->keys[k].src == REL_KEY_FACT ? 0 : 1 + d->keys[k].col;
     p.key_col[k] = d->keys[k].src == REL_KEY_FACT ? d->keys[k].col : 0;
   }
 
-  // LDS: per-wave row queues, the group table, then dim tables that fit.
+  // LDS: the group table, the per-wave row queues, then dim tables that fit
+  // (smaller dims first).
   const size_t budget = static_cast<size_t>(di.lds_per_block);
-  const size_t queue_bytes = static_cast<size_t>(kPipeThreads / kWave) * kPipeQueue * 4;
-  p.lds_slots = default_lds_slots(t, d->max_groups, L.gp.words, 16384);
+  p.lds_slots = L.lds_slots;
   size_t lds = 0;
-  p.lds_queue_offset = 0;
-  lds += queue_bytes;
-  p.lds_group_offset = static_cast<uint32_t>(lds);
+  p.lds_group_offset = 0;
   lds += static_cast<size_t>(p.lds_slots) * L.gp.words * 8;
+  lds = (lds + 15) / 16 * 16;
+  {
+    // queued row fields: width 8 for int64 columns, else 4
+    bool present[kQueueFields] = {};
+    bool wide[kQueueFields] = {};
+    present[kQRow] = true;
+    for (int i = 0; i < d->n_dims; ++i) {
+      present[kQFk0 + i] = true;
+      wide[kQFk0 + i] = d->dims[i].key.type == REL_I64;
+    }
+    // The first two distinct value columns are gathered with the probes.
+    int early[2] = {-1, -1};
+    for (int a = 0; a < L.gp.ap.nacc; ++a) {
+      const int c = L.gp.ap.col[a];
+      p.acc_col[a] = c;
+      p.acc_src[a] = -1;
+      for (int k = 0; k < 2; ++k) {
+        if (early[k] == c || early[k] < 0) {
+          early[k] = c;
+          p.acc_src[a] = k;
+          break;
+        }
+      }
+    }
+    for (int k = 0; k < 2; ++k) p.early_col[k] = early[k];
+    uint32_t stride = 0;
+    for (int f = 0; f < kQueueFields; ++f) {
+      p.field_offset[f] = stride;
+      p.field_wide[f] = wide[f] ? 1 : 0;
+      if (present[f]) stride += kPipeQueue * (wide[f] ? 8 : 4);
+    }
+    p.queue_offset = static_cast<uint32_t>(lds);
+    p.queue_stride = stride;
+    lds += static_cast<size_t>(kPipeThreads / kWave) * stride;
+  }
+  size_t dim_budget = budget > lds ? budget - lds : 0;
+  if (t && t->dim_lds_bytes < 0) dim_budget = 0;
+  else if (t && t->dim_lds_bytes > 0 && static_cast<size_t>(t->dim_lds_bytes) < dim_budget)
+    dim_budget = static_cast<size_t>(t->dim_lds_bytes);
   p.ndims = d->n_dims;
-  // Smaller dims claim LDS first.
   int order[REL_MAX_DIMS] = {0, 1};
-  if (d->n_dims == 2 && L.dim[1].cap < L.dim[0].cap) {
+  if (d->n_dims == 2 && L.dim[1].cap * L.dim[1].slot_bytes < L.dim[0].cap * L.dim[0].slot_bytes) {
     order[0] = 1;
     order[1] = 0;
   }
+  size_t dim_used = 0;
   for (int oi = 0; oi < d->n_dims; ++oi) {
     const int i = order[oi];
     const rel_dim& dm = d->dims[i];
     p.dim[i].map = map_desc(L.dim[i], dm.key.type, w);
     p.dim[i].fk_col = dm.fact_col;
-    const size_t bytes = L.dim[i].cap * 8;
-    if (dm.key.type == REL_I32 && lds + bytes <= budget) {
+    const size_t bytes = L.dim[i].cap * L.dim[i].slot_bytes;
+    if (dm.key.type == REL_I32 && dim_used + bytes <= dim_budget) {
       p.dim[i].in_lds = 1;
       p.dim[i].lds_offset = static_cast<uint32_t>(lds);
       lds += bytes;
+      dim_used += bytes;
     }
   }
   p.lds_bytes = static_cast<uint32_t>(lds);
@@ -696,13 +758,12 @@ rel_status rel_pipeline(const rel_pipeline_desc* d, const rel_outputs* o, void* 
   }
   launch_group_init(p.g, s);
   if (p.ntiles > 0) {
-    int per_cu = static_cast<int>(budget / (lds > 0 ? lds : 1));
-    if (per_cu > 2) per_cu = 2;
-    if (per_cu < 1) per_cu = 1;
-    int64_t grid = (t && t->grid > 0) ? t->grid : static_cast<int64_t>(di.cu_count) * per_cu;
-    if (grid > p.ntiles) grid = p.ntiles;
-    launch_pipeline(p, static_cast<int>(grid), s);
+    const hipError_t e = launch_pipeline(p, (t && t->grid > 0) ? t->grid : 0, s);
+    if (e != hipSuccess)
+      return fail(REL_EDEVICE, "pipeline: fused kernel launch (%u bytes of LDS): %s", p.lds_bytes,
+                  hipGetErrorString(e));
   }
+  launch_group_merge(p.g, s);
   launch_group_finalize(finalize_params(p.g, L.gp, d->aggs, d->n_aggs, o->keys, L.key_types,
                                         o->aggs, o->cap),
                         s);

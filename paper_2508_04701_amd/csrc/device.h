@@ -98,6 +98,34 @@ __device__ __forceinline__ void load4(const void* p, int32_t type, bool vec, int
   }
 }
 
+// As load4, for columns read once: the vector loads are marked
+// non-temporal so that streamed data does not displace hash tables in the
+// caches.
+__device__ __forceinline__ void load4s(const void* p, int32_t type, bool vec, int64_t r0,
+                                       int64_t n, int64_t v[4]) {
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  typedef long long v2l __attribute__((ext_vector_type(2)));
+  if (vec && r0 + 4 <= n) {
+    if (type == kI32) {
+      const v4i x = __builtin_nontemporal_load(
+          reinterpret_cast<const v4i*>(static_cast<const int32_t*>(p) + r0));
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    } else if (type == kI64) {
+      const v2l* q = reinterpret_cast<const v2l*>(static_cast<const int64_t*>(p) + r0);
+      const v2l a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + 1);
+      v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    } else {
+      const int32_t w = __builtin_nontemporal_load(
+          reinterpret_cast<const int32_t*>(static_cast<const int8_t*>(p) + r0));
+      v[0] = static_cast<int8_t>(w); v[1] = static_cast<int8_t>(w >> 8);
+      v[2] = static_cast<int8_t>(w >> 16); v[3] = static_cast<int8_t>(w >> 24);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (r0 + e < n) ? load_elem(p, type, r0 + e) : 0;
+  }
+}
+
 // Comparison term on a widened value (operators numerically equal to rel_cmp).
 __device__ __forceinline__ bool term_holds(int32_t op, int64_t v, int64_t lo, int64_t hi) {
   switch (op) {
@@ -134,35 +162,53 @@ struct Map64 {
   uint32_t* oob_vals;
 };
 
+// Probe runs start at the first slot of the 16-byte bucket holding the hash
+// slot, so one aligned 16-byte read covers the first two key/value slots (or
+// four key-only slots) of every run.
+__device__ __forceinline__ uint64_t home32(int32_t key, uint64_t mask) {
+  return (hash32(static_cast<uint32_t>(key)) & mask) & ~1ULL;
+}
+__device__ __forceinline__ uint64_t home_set(int32_t key, uint64_t mask) {
+  return (hash32(static_cast<uint32_t>(key)) & mask) & ~3ULL;
+}
+__device__ __forceinline__ uint64_t home64(int64_t key, uint64_t mask) {
+  return hash64(static_cast<uint64_t>(key)) & mask;
+}
+
 __device__ __forceinline__ uint64_t pack32(int32_t key, uint32_t val) {
   return static_cast<uint64_t>(static_cast<uint32_t>(key)) | (static_cast<uint64_t>(val) << 32);
 }
 
 constexpr uint64_t kEmptySlot32 = 0x0000000080000000ULL;  // pack32(kEmpty32, 0)
 
-__device__ __forceinline__ void map_insert(const Map32& m, int32_t key, uint32_t val) {
+// Inserts report a duplicate key through *dup: a CAS that loses returns the
+// occupant, and an equal occupant on the probe path is a duplicate.
+__device__ __forceinline__ void map_insert(const Map32& m, int32_t key, uint32_t val, int32_t* dup) {
   if (key == kEmpty32) {
     unsigned long long pos = atomicAdd(m.oob_count, 1ULL);
     m.oob_vals[pos] = val;
+    if (pos > 0) *dup = 1;
     return;
   }
-  uint64_t h = hash32(static_cast<uint32_t>(key)) & m.mask;
+  uint64_t h = home32(key, m.mask);
   const unsigned long long want = pack32(key, val);
   while (true) {
     unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(m.slots + h),
                                         static_cast<unsigned long long>(kEmptySlot32), want);
     if (prev == kEmptySlot32) return;
+    if (static_cast<int32_t>(static_cast<uint32_t>(prev)) == key) *dup = 1;
     h = (h + 1) & m.mask;
   }
 }
 
-__device__ __forceinline__ void map_insert(const Map64& m, int64_t key, uint32_t val) {
+__device__ __forceinline__ void map_insert(const Map64& m, int64_t key, uint32_t val, int32_t* dup) {
   if (static_cast<uint64_t>(key) == kEmpty64) {
     unsigned long long pos = atomicAdd(m.oob_count, 1ULL);
     m.oob_vals[pos] = val;
+    if (pos > 0) *dup = 1;
     return;
   }
-  uint64_t h = hash64(static_cast<uint64_t>(key)) & m.mask;
+  uint64_t h = home64(key, m.mask);
   while (true) {
     unsigned long long* kw = reinterpret_cast<unsigned long long*>(&m.slots[h].x);
     unsigned long long prev = atomicCAS(kw, static_cast<unsigned long long>(kEmpty64),
@@ -171,7 +217,26 @@ __device__ __forceinline__ void map_insert(const Map64& m, int64_t key, uint32_t
       m.slots[h].y = val;
       return;
     }
+    if (static_cast<int64_t>(prev) == key) *dup = 1;
     h = (h + 1) & m.mask;
+  }
+}
+
+// Key-only multiset of int32 keys (membership dims): one 32-bit word per
+// slot, claimed by a 32-bit CAS; sentinel keys are only counted out of band.
+__device__ __forceinline__ void set_insert(uint32_t* slots, uint64_t mask,
+                                           unsigned long long* oob_count, int32_t key,
+                                           int32_t* dup) {
+  if (key == kEmpty32) {
+    if (atomicAdd(oob_count, 1ULL) > 0) *dup = 1;
+    return;
+  }
+  uint64_t h = home_set(key, mask);
+  while (true) {
+    uint32_t prev = atomicCAS(slots + h, static_cast<uint32_t>(kEmpty32), static_cast<uint32_t>(key));
+    if (prev == static_cast<uint32_t>(kEmpty32)) return;
+    if (static_cast<int32_t>(prev) == key) *dup = 1;
+    h = (h + 1) & mask;
   }
 }
 
@@ -186,7 +251,7 @@ struct MapCursor {
 __device__ __forceinline__ MapCursor map_start32(const Map32& m, int32_t key) {
   MapCursor c;
   c.oob = (key == kEmpty32);
-  c.pos = c.oob ? 0 : (hash32(static_cast<uint32_t>(key)) & m.mask);
+  c.pos = c.oob ? 0 : home32(key, m.mask);
   c.live = true;
   return c;
 }
@@ -194,7 +259,7 @@ __device__ __forceinline__ MapCursor map_start32(const Map32& m, int32_t key) {
 __device__ __forceinline__ MapCursor map_start64(const Map64& m, int64_t key) {
   MapCursor c;
   c.oob = (static_cast<uint64_t>(key) == kEmpty64);
-  c.pos = c.oob ? 0 : (hash64(static_cast<uint64_t>(key)) & m.mask);
+  c.pos = c.oob ? 0 : home64(key, m.mask);
   c.live = true;
   return c;
 }
@@ -226,6 +291,30 @@ __device__ __forceinline__ bool map_next(const uint64_t* slots, uint64_t mask,
       val = static_cast<uint32_t>(s >> 32);
       return true;
     }
+  }
+}
+
+// Next occurrence of `key` in a key-only set (`val` is left unchanged).
+__device__ __forceinline__ bool set_next(const uint32_t* slots, uint64_t mask,
+                                         const unsigned long long* oob_count, int32_t key,
+                                         MapCursor& c) {
+  if (!c.live) return false;
+  if (c.oob) {
+    if (c.pos < *oob_count) {
+      ++c.pos;
+      return true;
+    }
+    c.live = false;
+    return false;
+  }
+  while (true) {
+    int32_t k = static_cast<int32_t>(slots[c.pos]);
+    c.pos = (c.pos + 1) & mask;
+    if (k == kEmpty32) {
+      c.live = false;
+      return false;
+    }
+    if (k == key) return true;
   }
 }
 

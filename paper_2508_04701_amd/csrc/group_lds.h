@@ -20,24 +20,37 @@ __device__ __forceinline__ void lds_group_init(uint64_t* t, int slots, const Gro
   }
 }
 
-__device__ __forceinline__ uint64_t* lds_group_slot(uint64_t* t, int slots, int words, uint64_t pk) {
-  if (pk == kEmpty64 || slots == 0) return nullptr;
+// Hash of a packed key for the LDS table (32-bit arithmetic only).
+__device__ __forceinline__ uint32_t lds_hash(uint64_t pk) {
+  return hash32(static_cast<uint32_t>(pk) ^ hash32(static_cast<uint32_t>(pk >> 32) + 0x9e3779b9u));
+}
+
+// Index of the LDS slot holding (or newly claimed for) packed key pk, or -1
+// when the key is the sentinel pattern, there is no LDS table, or no slot is
+// free within the probe window.
+__device__ __forceinline__ int32_t lds_group_find(uint64_t* t, int slots, int words, uint64_t pk) {
+  if (pk == kEmpty64 || slots == 0) return -1;
   const uint32_t mask = static_cast<uint32_t>(slots - 1);
-  uint32_t h = static_cast<uint32_t>(hash64(pk)) & mask;
+  uint32_t h = lds_hash(pk) & mask;
   const int window = slots < kLdsProbe ? slots : kLdsProbe;
   for (int probe = 0; probe < window; ++probe) {
-    uint64_t* s = t + static_cast<uint32_t>(h) * words;
-    uint64_t cur = *reinterpret_cast<volatile uint64_t*>(s);
-    if (cur == pk) return s;
+    uint64_t* s = t + h * words;
+    const uint64_t cur = __hip_atomic_load(s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (cur == pk) return static_cast<int32_t>(h);
     if (cur == kEmpty64) {
       unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long*>(s),
                                           static_cast<unsigned long long>(kEmpty64),
                                           static_cast<unsigned long long>(pk));
-      if (prev == kEmpty64 || prev == pk) return s;
+      if (prev == kEmpty64 || prev == pk) return static_cast<int32_t>(h);
     }
     h = (h + 1) & mask;
   }
-  return nullptr;
+  return -1;
+}
+
+__device__ __forceinline__ uint64_t* lds_group_slot(uint64_t* t, int slots, int words, uint64_t pk) {
+  const int32_t i = lds_group_find(t, slots, words, pk);
+  return i < 0 ? nullptr : t + i * words;
 }
 
 __device__ __forceinline__ void lds_group_update(uint64_t* s, const AccPlan& ap, const uint64_t* acc) {
@@ -47,18 +60,19 @@ __device__ __forceinline__ void lds_group_update(uint64_t* s, const AccPlan& ap,
     if (ap.kind[a] == kAccSum) {
       atomicAdd(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(acc[a]));
     } else if (ap.kind[a] == kAccMin) {
-      if (static_cast<long long>(acc[a]) < *reinterpret_cast<volatile long long*>(w))
+      if (static_cast<long long>(acc[a]) < *reinterpret_cast<long long*>(w))
         atomicMin(reinterpret_cast<long long*>(w), static_cast<long long>(acc[a]));
     } else {
-      if (static_cast<long long>(acc[a]) > *reinterpret_cast<volatile long long*>(w))
+      if (static_cast<long long>(acc[a]) > *reinterpret_cast<long long*>(w))
         atomicMax(reinterpret_cast<long long*>(w), static_cast<long long>(acc[a]));
     }
   }
 }
 
-// Merges a workgroup's LDS table into the global table (call after a barrier).
+// Merges a workgroup's LDS table into its replica of the global table (call
+// after a barrier).
 __device__ __forceinline__ void lds_group_flush(const uint64_t* t, int slots, const GroupDesc& g) {
-  GroupTable gt{g.slots, g.cap - 1, g.words, g.overflow};
+  const GroupTable gt = group_replica(g, blockIdx.x % g.replicas);
   for (int i = threadIdx.x; i < slots; i += blockDim.x) {
     const uint64_t* s = t + i * g.words;
     if (s[0] == kEmpty64) continue;

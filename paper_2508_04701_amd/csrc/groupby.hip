@@ -20,7 +20,7 @@ namespace rel {
 namespace {
 
 __global__ void group_init_kernel(GroupDesc g) {
-  const uint64_t total = (g.cap + 1) * static_cast<uint64_t>(g.words);
+  const uint64_t total = g.replicas * (g.cap + 1) * static_cast<uint64_t>(g.words);
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < total;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
     const int w = static_cast<int>(i % g.words);
@@ -38,7 +38,7 @@ __global__ void group_init_kernel(GroupDesc g) {
 __global__ void __launch_bounds__(256) group_agg_kernel(GroupAggParams p) {
   extern __shared__ uint64_t lds_table[];
   const GroupDesc& g = p.g;
-  GroupTable gt{g.slots, g.cap - 1, g.words, g.overflow};
+  const GroupTable gt = group_replica(g, blockIdx.x % g.replicas);
   if (p.lds_slots > 0) {
     lds_group_init(lds_table, p.lds_slots, g);
     __syncthreads();
@@ -68,6 +68,22 @@ __global__ void __launch_bounds__(256) group_agg_kernel(GroupAggParams p) {
   if (p.lds_slots > 0) {
     __syncthreads();
     lds_group_flush(lds_table, p.lds_slots, g);
+  }
+}
+
+// Folds every occupied slot of replicas 1.. into replica 0.
+__global__ void __launch_bounds__(256) group_merge_kernel(GroupDesc g) {
+  const uint64_t per = g.cap + 1;
+  const uint64_t total = (g.replicas - 1) * per;
+  const GroupTable dst = group_replica(g, 0);
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t r = 1 + i / per, slot = i % per;
+    const uint64_t* s = g.slots + (r * per + slot) * g.words;
+    const bool oob = slot == g.cap;
+    if (oob ? s[1] == 0 : s[0] == kEmpty64) continue;
+    uint64_t* d = group_slot(dst, oob ? kEmpty64 : s[0]);
+    if (d) group_update_global(d, g.ap, s[1], s + 2);
   }
 }
 
@@ -132,7 +148,7 @@ __global__ void __launch_bounds__(256) group_finalize_kernel(FinalizeParams p) {
 
 void launch_group_init(const GroupDesc& g, hipStream_t s) {
   ProfileScope ps(kKFill, s);
-  uint64_t total = (g.cap + 1) * static_cast<uint64_t>(g.words);
+  uint64_t total = g.replicas * (g.cap + 1) * static_cast<uint64_t>(g.words);
   uint64_t blocks = (total + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(group_init_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, g);
@@ -142,6 +158,15 @@ void launch_group_agg(const GroupAggParams& p, int grid, int block, hipStream_t 
   ProfileScope ps(kKGroupAgg, s);
   size_t lds = static_cast<size_t>(p.lds_slots) * p.g.words * sizeof(uint64_t);
   hipLaunchKernelGGL(group_agg_kernel, dim3(grid), dim3(block), lds, s, p);
+}
+
+void launch_group_merge(const GroupDesc& g, hipStream_t s) {
+  if (g.replicas <= 1) return;
+  ProfileScope ps(kKFinalize, s);
+  uint64_t total = (g.replicas - 1) * (g.cap + 1);
+  uint64_t blocks = (total + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(group_merge_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, g);
 }
 
 void launch_group_finalize(const FinalizeParams& p, hipStream_t s) {

@@ -67,10 +67,12 @@ void launch_filter(const FilterParams& p, hipStream_t s);
 // Geometry of one multimap in the workspace.
 struct MapDesc {
   int32_t key_type;   // kI32 or kI64
+  int32_t key_only;   // int32 keys without values (membership): 4-byte slots
   uint64_t cap;       // slots (power of two)
-  void* slots;        // cap * 8 (int32 keys) or cap * 16 (int64 keys) bytes
+  void* slots;        // cap * 4 (key-only), 8 (int32 keys) or 16 (int64 keys) bytes
   unsigned long long* oob_count;
   uint32_t* oob_vals;  // n entries
+  int32_t* dup;        // set by the build when a key occurs twice
 };
 
 // Inserts n keys of column (data, idx, type); value of element i is
@@ -106,15 +108,25 @@ void launch_map_probe(const MapProbeParams& p, int grid, int block, hipStream_t 
 
 // ------------------------------------------------------------- group-by
 
+// The global group table may be replicated: workgroup w merges into replica
+// w mod `replicas`, which divides the same-address atomic contention of few
+// groups by the replica count; a merge pass folds the replicas into replica
+// 0 before the finalize reads it.
 struct GroupDesc {
   GroupKeyPack kp;
   AccPlan ap;
-  uint64_t cap;     // slots of the open-addressing array (power of two)
-  int32_t words;    // 64-bit words per slot
-  uint64_t* slots;  // (cap + 1) * words words
+  uint64_t cap;      // slots of the open-addressing array (power of two)
+  int32_t words;     // 64-bit words per slot
+  int32_t replicas;  // >= 1
+  uint64_t* slots;   // replicas * (cap + 1) * words words
   int32_t* overflow;
   unsigned long long* d_groups;  // output count (zeroed by init)
 };
+
+__device__ __forceinline__ GroupTable group_replica(const GroupDesc& g, uint32_t r) {
+  return GroupTable{g.slots + static_cast<uint64_t>(r) * (g.cap + 1) * g.words, g.cap - 1, g.words,
+                    g.overflow};
+}
 
 void launch_group_init(const GroupDesc& g, hipStream_t s);
 
@@ -143,6 +155,9 @@ struct FinalizeParams {
   int64_t cap;
 };
 
+// Folds replicas 1.. of the global group table into replica 0.
+void launch_group_merge(const GroupDesc& g, hipStream_t s);
+
 void launch_group_finalize(const FinalizeParams& p, hipStream_t s);
 
 // ------------------------------------------------------------- pipeline
@@ -153,6 +168,10 @@ struct PipeDim {
   int32_t in_lds;        // copy the slot array into LDS
   uint32_t lds_offset;   // byte offset of the copy in dynamic LDS
 };
+
+// Queued row fields: row id, the two foreign keys, two fact group-key
+// columns and two value columns.
+enum QueueField : int { kQRow = 0, kQFk0, kQFk1, kQKey0, kQKey1, kQValA, kQValB, kQueueFields };
 
 struct PipelineParams {
   const void* fact[8];
@@ -170,18 +189,26 @@ struct PipelineParams {
   int32_t key_col[2];
   GroupDesc g;
   int32_t acc_col[kMaxAcc];  // fact column of each accumulator
+  int32_t early_col[2];       // value columns loaded with the keys (-1: none)
+  int32_t acc_src[kMaxAcc];   // 0/1: value from early_col[k]; -1: loaded late
   int32_t lds_slots;          // LDS group table slots (0: none)
   uint32_t lds_group_offset;  // byte offset of the LDS group table
-  uint32_t lds_queue_offset;  // byte offset of the per-wave row queues
   uint32_t lds_bytes;
   int64_t ntiles;
+  // Per-wave row queues in LDS: field f of queued row i lives at
+  // queue_offset + wave * queue_stride + field_offset[f] + i * (4 or 8).
+  uint32_t queue_offset;
+  uint32_t queue_stride;
+  uint32_t field_offset[kQueueFields];
+  int32_t field_wide[kQueueFields];   // 8-byte (1) or 4-byte (0) elements
 };
 
-constexpr int kPipeThreads = 1024;
-constexpr int kPipeChunks = 1;                                 // chunks of 4 rows per thread
-constexpr int kPipeTile = kPipeThreads * 4 * kPipeChunks;      // rows per tile
-constexpr int kPipeQueue = 128;                                // row slots per wave queue
+constexpr int kPipeThreads = 512;
+constexpr int kPipeTile = kPipeThreads * 4;  // rows per tile: four per thread
+constexpr int kPipeQueue = 128;              // queued rows per wave (one batch + one push)
+constexpr int kMaxPipeGrid = 2048;           // bound on the persistent grid
 
-void launch_pipeline(const PipelineParams& p, int grid, hipStream_t s);
+// Returns the first failing HIP status of the launch.
+hipError_t launch_pipeline(const PipelineParams& p, int grid, hipStream_t s);
 
 }  // namespace rel

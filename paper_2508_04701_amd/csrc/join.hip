@@ -41,13 +41,20 @@ __global__ void __launch_bounds__(256) map_build_kernel(MapBuildParams p) {
        i < static_cast<uint64_t>(p.n); i += stride) {
     int64_t r = p.idx ? static_cast<int64_t>(p.idx[i]) : static_cast<int64_t>(i);
     K key = static_cast<K>(load_elem(p.keys, p.type, r));
+    if constexpr (sizeof(K) == 4) {
+      if (p.map.key_only) {
+        set_insert(static_cast<uint32_t*>(p.map.slots), p.map.cap - 1, p.map.oob_count, key,
+                   p.map.dup);
+        continue;
+      }
+    }
     uint32_t val = element_value(p, static_cast<int64_t>(i));
     if constexpr (sizeof(K) == 4) {
       Map32 m{static_cast<uint64_t*>(p.map.slots), p.map.cap - 1, p.map.oob_count, p.map.oob_vals};
-      map_insert(m, key, val);
+      map_insert(m, key, val, p.map.dup);
     } else {
       Map64 m{static_cast<ulonglong2*>(p.map.slots), p.map.cap - 1, p.map.oob_count, p.map.oob_vals};
-      map_insert(m, key, val);
+      map_insert(m, key, val, p.map.dup);
     }
   }
 }
@@ -111,7 +118,10 @@ void launch_fill64(uint64_t* p, uint64_t n, uint64_t pattern, hipStream_t s) {
 }
 
 void launch_map_init(const MapDesc& m, hipStream_t s) {
-  if (m.key_type == kI32) {
+  if (m.key_only) {
+    // two empty 32-bit slots per word (cap >= 64 is even)
+    launch_fill64(static_cast<uint64_t*>(m.slots), m.cap / 2, 0x8000000080000000ULL, s);
+  } else if (m.key_type == kI32) {
     launch_fill64(static_cast<uint64_t*>(m.slots), m.cap, kEmptySlot32, s);
   } else {
     ProfileScope ps(kKFill, s);
@@ -120,7 +130,8 @@ void launch_map_init(const MapDesc& m, hipStream_t s) {
     hipLaunchKernelGGL(fill_map64_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
                        static_cast<ulonglong2*>(m.slots), m.cap);
   }
-  launch_fill64(reinterpret_cast<uint64_t*>(m.oob_count), 1, 0, s);
+  // the out-of-band count and the duplicate flag share the header
+  launch_fill64(reinterpret_cast<uint64_t*>(m.oob_count), 2, 0, s);
 }
 
 void launch_map_build(const MapBuildParams& p, hipStream_t s) {

@@ -1,0 +1,479 @@
+// Fused plan: conjunctive filter -> inner join with up to two dims ->
+// group-by, in one pass over the fact table ("the entire query plan on the
+// GPU, from scan to result", Section 3.1).
+//
+// Persistent workgroups walk fact tiles. Each thread owns four consecutive
+// rows of a tile and streams the predicate column (one tile ahead) and the
+// foreign keys with coalesced vector loads marked non-temporal (16 bytes per
+// lane for int32 columns). Passing rows are then compacted per wave:
+// a ballot per row position and the lanes' mbcnt ranks place each passing
+// row's id and foreign keys in a small LDS queue. Every time 64 rows are
+// queued the wave takes them as one batch with all 64 lanes active: one probe
+// read per lane and dim (the 16-byte bucket where the key's run starts, so
+// the first read nearly always decides), issued together with the gathers of
+// the row's group-key and value columns, then the group update. Random reads and LDS atomics therefore run
+// at full lane occupancy whatever the selectivity, which is what bounds
+// their throughput. Small dim tables can live in an LDS copy, large ones are
+// read from HBM; membership-only dims use key-only tables. Groups are
+// aggregated in a per-workgroup LDS table (keys that do not fit go to the
+// global table), then merged into one of several replicas of the global
+// table, so that few groups do not serialise every workgroup's merge on the
+// same global slots; a separate pass folds the replicas. Rows whose dim keys
+// match more than once
+// (duplicate dim keys) take a row-at-a-time path that enumerates every
+// combination.
+
+#pragma once
+
+#include "group_lds.h"
+#include "internal.h"
+
+namespace rel {
+namespace pipe {
+
+// Dim table access modes (template arguments).
+enum : int {
+  kNone = 0,
+  kMap = 1,     // int32 key -> value, HBM
+  kMapLds = 2,  // int32 key -> value, LDS copy
+  kSet = 3,     // int32 key only, HBM
+  kSetLds = 4,  // int32 key only, LDS copy
+  kMap64 = 5,   // int64 key -> value, HBM
+};
+
+template <int D>
+__device__ __forceinline__ const void* dim_slots(const PipeDim& d, const void* lds_copy) {
+  if constexpr (D == kMapLds || D == kSetLds) return lds_copy;
+  return d.map.slots;
+}
+
+// Split probe: probe_first() loads the aligned 16-byte bucket where the
+// key's probe run starts (two key/value slots, four key-only slots or one
+// int64 slot), so that the first reads of all rows and dims are in flight
+// together; probe_finish() scans it and walks on in the rare case that the
+// run continues. It returns the number of matches capped at `limit` (1 when
+// the build saw no duplicate key, else 2) and the value of the first match
+// (key-only sets leave `val` unchanged).
+template <int D>
+__device__ __forceinline__ uint64_t probe_home(const PipeDim& d, int64_t key) {
+  const uint64_t mask = d.map.cap - 1;
+  if constexpr (D == kMap64) return home64(key, mask);
+  else if constexpr (D == kSet || D == kSetLds) return home_set(static_cast<int32_t>(key), mask);
+  else return home32(static_cast<int32_t>(key), mask);
+}
+
+template <int D>
+__device__ __forceinline__ uint4 probe_first(const PipeDim& d, const void* lds_copy, int64_t key) {
+  const uint4* groups = static_cast<const uint4*>(dim_slots<D>(d, lds_copy));
+  const uint64_t h = probe_home<D>(d, key);
+  if constexpr (D == kMap64) return groups[h];
+  else if constexpr (D == kSet || D == kSetLds) return groups[h >> 2];
+  else return groups[h >> 1];
+}
+
+template <int D>
+__device__ __forceinline__ int probe_finish(const PipeDim& d, const void* lds_copy, int64_t key,
+                                            int limit, uint4 first, uint32_t& val) {
+  const uint64_t mask = d.map.cap - 1;
+  const uint4* groups = static_cast<const uint4*>(dim_slots<D>(d, lds_copy));
+  int found = 0;
+  if constexpr (D == kMap64) {
+    if (static_cast<uint64_t>(key) == kEmpty64) {
+      const unsigned long long c = *d.map.oob_count;
+      if (c) val = d.map.oob_vals[0];
+      return c > 1 ? 2 : static_cast<int>(c);
+    }
+    uint64_t h = probe_home<D>(d, key);
+    uint4 q = first;
+    while (true) {
+      const uint64_t sk = static_cast<uint64_t>(q.x) | (static_cast<uint64_t>(q.y) << 32);
+      if (sk == kEmpty64) break;
+      if (static_cast<int64_t>(sk) == key) {
+        if (found == 0) val = q.z;
+        if (++found == limit) break;
+      }
+      h = (h + 1) & mask;
+      q = groups[h];
+    }
+  } else {
+    const int32_t k = static_cast<int32_t>(key);
+    if (k == kEmpty32) {
+      const unsigned long long c = *d.map.oob_count;
+      if constexpr (D == kMap || D == kMapLds)
+        if (c) val = d.map.oob_vals[0];
+      return c > 1 ? 2 : static_cast<int>(c);
+    }
+    constexpr int per = (D == kSet || D == kSetLds) ? 4 : 2;  // slots per bucket
+    const uint64_t gmask = mask / per;
+    uint64_t g = probe_home<D>(d, key) / per;
+    uint4 q = first;
+    bool done = false;
+    while (true) {
+      if constexpr (per == 4) {
+        const int32_t sv[4] = {static_cast<int32_t>(q.x), static_cast<int32_t>(q.y),
+                               static_cast<int32_t>(q.z), static_cast<int32_t>(q.w)};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (done) continue;
+          if (sv[i] == kEmpty32) done = true;
+          else if (sv[i] == k && ++found == limit) done = true;
+        }
+      } else {
+        const int32_t sk[2] = {static_cast<int32_t>(q.x), static_cast<int32_t>(q.z)};
+        const uint32_t sval[2] = {q.y, q.w};
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          if (done) continue;
+          if (sk[i] == kEmpty32) {
+            done = true;
+          } else if (sk[i] == k) {
+            if (found == 0) val = sval[i];
+            if (++found == limit) done = true;
+          }
+        }
+      }
+      if (done) break;
+      g = (g + 1) & gmask;
+      q = groups[g];
+    }
+  }
+  return found;
+}
+
+template <int D>
+__device__ __forceinline__ MapCursor dim_start(const PipeDim& d, int64_t key) {
+  MapCursor c;
+  c.live = true;
+  if constexpr (D == kMap64) {
+    c.oob = static_cast<uint64_t>(key) == kEmpty64;
+    c.pos = c.oob ? 0 : home64(key, d.map.cap - 1);
+  } else {
+    const int32_t k = static_cast<int32_t>(key);
+    c.oob = k == kEmpty32;
+    c.pos = c.oob ? 0 : ((D == kSet || D == kSetLds) ? home_set(k, d.map.cap - 1)
+                                                       : home32(k, d.map.cap - 1));
+  }
+  return c;
+}
+
+template <int D>
+__device__ __forceinline__ bool dim_next(const PipeDim& d, const void* lds_copy, int64_t key,
+                                         MapCursor& c, uint32_t& val) {
+  const uint64_t mask = d.map.cap - 1;
+  const void* base = dim_slots<D>(d, lds_copy);
+  if constexpr (D == kMap64) {
+    return map_next(static_cast<const ulonglong2*>(base), mask, d.map.oob_count, d.map.oob_vals,
+                    key, c, val);
+  } else if constexpr (D == kSet || D == kSetLds) {
+    return set_next(static_cast<const uint32_t*>(base), mask, d.map.oob_count,
+                    static_cast<int32_t>(key), c);
+  } else {
+    return map_next(static_cast<const uint64_t*>(base), mask, d.map.oob_count, d.map.oob_vals,
+                    static_cast<int32_t>(key), c, val);
+  }
+}
+
+__device__ __forceinline__ uint64_t row_key(const PipelineParams& p, int64_t r, uint32_t v0,
+                                            uint32_t v1) {
+  int64_t k[2] = {0, 0};
+  for (int j = 0; j < p.g.kp.nkeys; ++j) {
+    const int src = p.key_src[j];
+    if (src == 0) k[j] = load_elem(p.fact[p.key_col[j]], p.fact_type[p.key_col[j]], r);
+    else k[j] = static_cast<int32_t>(src == 1 ? v0 : v1);
+  }
+  return pack_keys(p.g.kp, k[0], k[1]);
+}
+
+// Adds one row (count 1, accumulator inputs read from the fact table) to the
+// group of packed key pk.
+__device__ __forceinline__ void add_row(const PipelineParams& p, int64_t r, uint64_t pk,
+                                        uint64_t* lds_group, const GroupTable& gt) {
+  uint64_t acc[kMaxAcc];
+  for (int a = 0; a < p.g.ap.nacc; ++a)
+    acc[a] = static_cast<uint64_t>(load_elem(p.fact[p.acc_col[a]], p.fact_type[p.acc_col[a]], r));
+  uint64_t* ls = lds_group_slot(lds_group, p.lds_slots, p.g.words, pk);
+  if (ls) {
+    lds_group_update(ls, p.g.ap, acc);
+  } else {
+    uint64_t* gs = group_slot(gt, pk);
+    if (gs) group_update_global(gs, p.g.ap, 1, acc);
+  }
+}
+
+// Row-at-a-time path: every combination of matching dim rows.
+template <int D0, int D1>
+__device__ __forceinline__ void enumerate_row(const PipelineParams& p, int64_t r, const void* ld0,
+                                           const void* ld1, uint64_t* lds_group,
+                                           const GroupTable& gt) {
+  const int64_t fk0 = load_elem(p.fact[p.dim[0].fk_col], p.fact_type[p.dim[0].fk_col], r);
+  int64_t fk1 = 0;
+  if constexpr (D1 != kNone)
+    fk1 = load_elem(p.fact[p.dim[1].fk_col], p.fact_type[p.dim[1].fk_col], r);
+  MapCursor c0 = dim_start<D0>(p.dim[0], fk0);
+  uint32_t v0 = 0;
+  while (dim_next<D0>(p.dim[0], ld0, fk0, c0, v0)) {
+    if constexpr (D1 == kNone) {
+      add_row(p, r, row_key(p, r, v0, 0), lds_group, gt);
+    } else {
+      MapCursor c1 = dim_start<D1>(p.dim[1], fk1);
+      uint32_t v1 = 0;
+      while (dim_next<D1>(p.dim[1], ld1, fk1, c1, v1))
+        add_row(p, r, row_key(p, r, v0, v1), lds_group, gt);
+    }
+  }
+}
+
+// Predicate of four rows whose first term's column was already loaded into
+// `first` (the remaining terms are loaded here).
+__device__ __forceinline__ uint32_t eval_prefetched(const PipelineParams& p, int64_t r0,
+                                                    const int64_t first[4]) {
+  uint32_t bits = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) bits |= (r0 + e < p.n) ? (1u << e) : 0u;
+  for (int t = 0; t < p.nterms; ++t) {
+    int64_t v[4];
+    if (t == 0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = first[e];
+    } else {
+      const int c = p.term_col[t];
+      load4(p.fact[c], p.fact_type[c], p.fact_vec[c] != 0, r0, p.n, v);
+    }
+    uint32_t m = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      m |= term_holds(p.term_op[t], v[e], p.term_lo[t], p.term_hi[t]) ? (1u << e) : 0u;
+    bits &= m;
+  }
+  return bits;
+}
+
+__device__ __forceinline__ void load_col4(const PipelineParams& p, int c, int64_t r0,
+                                          int64_t v[4]) {
+  load4(p.fact[c], p.fact_type[c], p.fact_vec[c] != 0, r0, p.n, v);
+}
+
+template <int D>
+__device__ __forceinline__ void copy_dim_to_lds(const PipeDim& d, void* lds_copy) {
+  if constexpr (D == kMapLds || D == kSetLds) {
+    const uint64_t n16 = d.map.cap * (D == kSetLds ? 4 : 8) / 16;
+    const uint4* src = static_cast<const uint4*>(d.map.slots);
+    uint4* dst = static_cast<uint4*>(lds_copy);
+    for (uint64_t i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+  }
+}
+
+__device__ __forceinline__ void queue_put(const PipelineParams& p, unsigned char* wq, int f,
+                                          uint32_t i, int64_t v) {
+  unsigned char* a = wq + p.field_offset[f];
+  if (p.field_wide[f]) reinterpret_cast<int64_t*>(a)[i] = v;
+  else reinterpret_cast<int32_t*>(a)[i] = static_cast<int32_t>(v);
+}
+
+__device__ __forceinline__ int64_t queue_get(const PipelineParams& p, const unsigned char* wq,
+                                             int f, uint32_t i) {
+  const unsigned char* a = wq + p.field_offset[f];
+  if (p.field_wide[f]) return reinterpret_cast<const int64_t*>(a)[i];
+  return reinterpret_cast<const int32_t*>(a)[i];
+}
+
+// One queued row per lane: probe the dims, then update the row's group.
+template <int D0, int D1>
+__device__ __forceinline__ void process_queued(const PipelineParams& p, const unsigned char* wq,
+                                               uint32_t i, const void* ld0, const void* ld1,
+                                               uint64_t* lg, const GroupTable& gt, int limit0,
+                                               int limit1) {
+  const int64_t r = static_cast<uint32_t>(queue_get(p, wq, kQRow, i));
+  int64_t fk0 = 0, fk1 = 0;
+  uint4 q0 = make_uint4(0, 0, 0, 0), q1 = make_uint4(0, 0, 0, 0);
+  if constexpr (D0 != kNone) {
+    fk0 = queue_get(p, wq, kQFk0, i);
+    q0 = probe_first<D0>(p.dim[0], ld0, fk0);
+  }
+  if constexpr (D1 != kNone) {
+    fk1 = queue_get(p, wq, kQFk1, i);
+    q1 = probe_first<D1>(p.dim[1], ld1, fk1);
+  }
+  // Group-key and value columns are gathered by row id while the probe
+  // reads are in flight.
+  int64_t k0 = 0, k1 = 0;
+  if (p.g.kp.nkeys > 0 && p.key_src[0] == 0)
+    k0 = load_elem(p.fact[p.key_col[0]], p.fact_type[p.key_col[0]], r);
+  if (p.g.kp.nkeys > 1 && p.key_src[1] == 0)
+    k1 = load_elem(p.fact[p.key_col[1]], p.fact_type[p.key_col[1]], r);
+  int64_t va = 0, vb = 0;
+  if (p.early_col[0] >= 0) va = load_elem(p.fact[p.early_col[0]], p.fact_type[p.early_col[0]], r);
+  if (p.early_col[1] >= 0) vb = load_elem(p.fact[p.early_col[1]], p.fact_type[p.early_col[1]], r);
+
+  uint32_t v0 = 0, v1 = 0;
+  bool multi = false;
+  if constexpr (D0 != kNone) {
+    const int m = probe_finish<D0>(p.dim[0], ld0, fk0, limit0, q0, v0);
+    if (m == 0) return;
+    multi |= m == 2;
+  }
+  if constexpr (D1 != kNone) {
+    const int m = probe_finish<D1>(p.dim[1], ld1, fk1, limit1, q1, v1);
+    if (m == 0) return;
+    multi |= m == 2;
+  }
+  if constexpr (D0 != kNone) {
+    if (multi) {
+      enumerate_row<D0, D1>(p, r, ld0, ld1, lg, gt);
+      return;
+    }
+  }
+  if (p.g.kp.nkeys > 0 && p.key_src[0] != 0) k0 = static_cast<int32_t>(p.key_src[0] == 1 ? v0 : v1);
+  if (p.g.kp.nkeys > 1 && p.key_src[1] != 0) k1 = static_cast<int32_t>(p.key_src[1] == 1 ? v0 : v1);
+  const uint64_t pk = pack_keys(p.g.kp, k0, k1);
+  const int words = p.g.words;
+  const int32_t li = lds_group_find(lg, p.lds_slots, words, pk);
+  uint64_t* gs = nullptr;
+  if (li >= 0) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(lg + li * words + 1), 1ULL);
+  } else {
+    gs = group_slot(gt, pk);
+    if (!gs) return;
+    atomicAdd(reinterpret_cast<unsigned long long*>(gs + 1), 1ULL);
+  }
+  for (int a = 0; a < p.g.ap.nacc; ++a) {
+    const int src = p.acc_src[a];
+    const int64_t v = src == 0 ? va
+                    : src == 1 ? vb
+                               : load_elem(p.fact[p.acc_col[a]], p.fact_type[p.acc_col[a]], r);
+    const int kind = p.g.ap.kind[a];
+    if (li >= 0) {
+      uint64_t* w = lg + li * words + 2 + a;
+      if (kind == kAccSum) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(v));
+      } else if (kind == kAccMin) {
+        if (v < *reinterpret_cast<long long*>(w))
+          atomicMin(reinterpret_cast<long long*>(w), static_cast<long long>(v));
+      } else {
+        if (v > *reinterpret_cast<long long*>(w))
+          atomicMax(reinterpret_cast<long long*>(w), static_cast<long long>(v));
+      }
+    } else {
+      uint64_t* w = gs + 2 + a;
+      if (kind == kAccSum)
+        atomicAdd(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(v));
+      else if (kind == kAccMin)
+        atomicMin(reinterpret_cast<long long*>(w), static_cast<long long>(v));
+      else
+        atomicMax(reinterpret_cast<long long*>(w), static_cast<long long>(v));
+    }
+  }
+}
+
+template <int D0, int D1>
+__global__ void __launch_bounds__(kPipeThreads) fused_kernel(PipelineParams p) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  void* ld0 = lds + p.dim[0].lds_offset;
+  void* ld1 = lds + p.dim[1].lds_offset;
+  uint64_t* lg = reinterpret_cast<uint64_t*>(lds + p.lds_group_offset);
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  unsigned char* wq = lds + p.queue_offset + (tid / kWave) * p.queue_stride;
+  copy_dim_to_lds<D0>(p.dim[0], ld0);
+  copy_dim_to_lds<D1>(p.dim[1], ld1);
+  if (p.lds_slots > 0) lds_group_init(lg, p.lds_slots, p.g);
+  __syncthreads();
+
+  const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
+  // Dims built without duplicate keys stop probing at the first match.
+  int limit0 = 1, limit1 = 1;
+  if constexpr (D0 != kNone) limit0 = *p.dim[0].map.dup ? 2 : 1;
+  if constexpr (D1 != kNone) limit1 = *p.dim[1].map.dup ? 2 : 1;
+
+  const int c_pred = p.nterms > 0 ? p.term_col[0] : 0;
+  int64_t tile = blockIdx.x;
+  int64_t pre[4] = {0, 0, 0, 0};
+  if (p.nterms > 0 && tile < p.ntiles)
+    load4s(p.fact[c_pred], p.fact_type[c_pred], p.fact_vec[c_pred] != 0,
+           tile * static_cast<int64_t>(kPipeTile) + tid * 4, p.n, pre);
+  uint32_t queued = 0;  // wave-uniform
+  for (; tile < p.ntiles; tile += gridDim.x) {
+    const int64_t r0 = tile * static_cast<int64_t>(kPipeTile) + tid * 4;
+    const uint32_t bits = eval_prefetched(p, r0, pre);
+    const int64_t next = tile + gridDim.x;
+    // Foreign keys of the passing rows, streamed; lanes without a passing
+    // row skip them.
+    int64_t fk0[4] = {0, 0, 0, 0}, fk1[4] = {0, 0, 0, 0};
+    if (bits) {
+      if constexpr (D0 != kNone) {
+        const int c = p.dim[0].fk_col;
+        load4s(p.fact[c], p.fact_type[c], p.fact_vec[c] != 0, r0, p.n, fk0);
+      }
+      if constexpr (D1 != kNone) {
+        const int c = p.dim[1].fk_col;
+        load4s(p.fact[c], p.fact_type[c], p.fact_vec[c] != 0, r0, p.n, fk1);
+      }
+    }
+    if (p.nterms > 0 && next < p.ntiles)
+      load4s(p.fact[c_pred], p.fact_type[c_pred], p.fact_vec[c_pred] != 0,
+             next * static_cast<int64_t>(kPipeTile) + tid * 4, p.n, pre);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const bool pass = (bits >> e) & 1u;
+      const uint64_t b = ballot(pass);
+      if (b == 0) continue;
+      if (pass) {
+        const uint32_t at = queued + rank_below(b);
+        queue_put(p, wq, kQRow, at, r0 + e);
+        if constexpr (D0 != kNone) queue_put(p, wq, kQFk0, at, fk0[e]);
+        if constexpr (D1 != kNone) queue_put(p, wq, kQFk1, at, fk1[e]);
+      }
+      queued += popc64(b);
+      if (queued >= kWave) {
+        __builtin_amdgcn_wave_barrier();
+        queued -= kWave;
+        process_queued<D0, D1>(p, wq, queued + lane, ld0, ld1, lg, gt, limit0, limit1);
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+  }
+  if (queued > 0) {
+    __builtin_amdgcn_wave_barrier();
+    if (static_cast<uint32_t>(lane) < queued)
+      process_queued<D0, D1>(p, wq, lane, ld0, ld1, lg, gt, limit0, limit1);
+  }
+  if (p.lds_slots == 0) return;
+  __syncthreads();
+  lds_group_flush(lg, p.lds_slots, p.g);
+}
+
+// grid <= 0 sizes the persistent grid to the workgroups that can be resident
+// at once (registers and LDS of this variant), capped by the tile count.
+// Returns the first failing HIP status.
+template <int D0, int D1>
+hipError_t launch_fused(const PipelineParams& p, int grid, hipStream_t s) {
+  auto k = fused_kernel<D0, D1>;
+  static int max_dynamic = -1;
+  if (max_dynamic < 0) {
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(k));
+    if (e != hipSuccess) return e;
+    max_dynamic = device_info().lds_per_block - static_cast<int>(attr.sharedSizeBytes);
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_dynamic);
+    if (e != hipSuccess) return e;
+  }
+  if (static_cast<int>(p.lds_bytes) > max_dynamic) return hipErrorInvalidValue;
+  if (grid <= 0) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kPipeThreads,
+                                                                p.lds_bytes);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    int64_t g = static_cast<int64_t>(device_info().cu_count) * per_cu;
+    if (g > p.ntiles) g = p.ntiles;
+    if (g > kMaxPipeGrid) g = kMaxPipeGrid;
+    grid = static_cast<int>(g < 1 ? 1 : g);
+  }
+  if (grid > kMaxPipeGrid) grid = kMaxPipeGrid;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kPipeThreads), p.lds_bytes, s, p);
+  return hipGetLastError();
+}
+
+}  // namespace pipe
+}  // namespace rel

@@ -54,7 +54,8 @@ class Agg(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("load_factor", ctypes.c_float), ("block", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("lds_slots", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("flags", ctypes.c_int32), ("dim_lds_bytes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Dim(ctypes.Structure):
@@ -151,8 +152,8 @@ def column(t: torch.Tensor, idx: torch.Tensor | None = None) -> Column:
     return Column(t.data_ptr() if t.numel() else None, None, t.numel(), DTYPES[t.dtype], 0)
 
 
-def tuning(load_factor=0.0, block=0, grid=0, lds_slots=0) -> Tuning:
-    return Tuning(load_factor, block, grid, lds_slots, 0, (ctypes.c_int32 * 3)())
+def tuning(load_factor=0.0, block=0, grid=0, lds_slots=0, dim_lds_bytes=0) -> Tuning:
+    return Tuning(load_factor, block, grid, lds_slots, 0, dim_lds_bytes, (ctypes.c_int32 * 2)())
 
 
 def _tuning_ptr(t):

@@ -308,12 +308,16 @@ def test_pipeline_shapes():
     aggs = [("sum", 2), ("count", None), ("max", 2)]
     big_dim = dict(fk=0, key=r.permutation(60_000).astype(np.int32),
                    payload=r.integers(0, 70_000, size=60_000).astype(np.int32))
+    dup_member = dict(fk=0, key=r.integers(0, 40_000, size=30_000).astype(np.int32), payload=None)
+    uniq_member = dict(fk=1, key=r.permutation(800).astype(np.int32), payload=None)
     cases = {
         "no dims, fact key": ([], [("fact", 1)], [(2, "gt", 0)]),
         "no dims, no keys": ([], [], [(2, "gt", 0)]),
         "no predicate": ([big_dim], [("dim", 0)], []),
         "HBM dim, dim key": ([big_dim], [("dim", 0)], [(1, "lt", 500)]),
         "dim key + fact key": ([big_dim], [("dim", 0), ("fact", 1)], [(1, "lt", 500)]),
+        "membership dim with duplicate keys": ([dup_member], [("fact", 1)], [(1, "lt", 900)]),
+        "two membership dims": ([dup_member, uniq_member], [("fact", 1)], []),
     }
     for name, (dims, keys, terms) in cases.items():
         announce("pipeline shape", name)
