@@ -107,7 +107,8 @@ typedef struct {
   int32_t grid;      /* workgroups of persistent kernels; 0 = default (from the CU count) */
   int32_t lds_slots; /* slots of the per-workgroup LDS group table; 0 = default, -1 = none */
   int32_t flags;     /* reserved, must be 0 */
-  int32_t dim_lds_bytes; /* LDS bytes rel_pipeline may give to dim tables; 0 = default, -1 = none */
+  int32_t dim_lds_bytes; /* LDS bytes rel_pipeline may give to dim tables; 0 = default (32 KB),
+                            -1 = none */
   int32_t reserved[2];
 } rel_tuning;
 

@@ -33,7 +33,7 @@ HIP_FLAGS = [
 # The fused pipeline kernel is instantiated per first-dim access mode in
 # separate objects (see pipeline.hip) so that the variants compile in parallel.
 UNITS = [(s, s.replace(".hip", "").replace(".cpp", ""), []) for s in SOURCES] + [
-    ("pipeline.hip", f"pipeline_d{m}", [f"-DREL_PIPE_D0={m}"]) for m in range(1, 6)]
+    ("pipeline.hip", f"pipeline_d{m}", [f"-DREL_PIPE_D0={m}"]) for m in range(1, 7)]
 
 
 def _compile(unit) -> str:

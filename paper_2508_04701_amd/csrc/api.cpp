@@ -105,11 +105,42 @@ rel_status after_launch(hipStream_t s, const char* what) {
 struct MapLayout {
   uint64_t cap;
   size_t slot_bytes;
+  bool compact;  // 16-byte buckets of 16-bit entries; cap counts buckets
+  int rbits;
+  uint64_t over_cap;  // compact: overflow set slots (at oob_vals_off)
   size_t slots_off, oob_count_off, oob_vals_off, end;
 };
 
-MapLayout map_layout(int32_t key_type, int64_t n, float lf, size_t base, bool key_only = false) {
+// Compact membership sets: eight 16-bit entries per 16-byte bucket, filled
+// to at most this load factor; used when the remainder fits 14 bits.
+constexpr double kCsetLoad = 0.75;
+constexpr int kCsetMinBucketBits = 18;
+
+MapLayout map_layout(int32_t key_type, int64_t n, float lf, size_t base, bool key_only = false,
+                     bool allow_compact = false) {
   MapLayout m;
+  m.compact = false;
+  m.rbits = 0;
+  m.over_cap = 0;
+  if (key_only && allow_compact && key_type == REL_I32) {
+    const uint64_t buckets = next_pow2(static_cast<uint64_t>(std::ceil(n / (8 * kCsetLoad))));
+    int bits = 0;
+    while ((1ULL << bits) < buckets) ++bits;
+    if (bits >= kCsetMinBucketBits && bits <= 31) {
+      // buckets, then the header (overflow sentinel count, duplicate flag),
+      // then the overflow set, sized so that even every key would fit
+      m.compact = true;
+      m.rbits = 32 - bits;
+      m.cap = buckets;
+      m.slot_bytes = 16;
+      m.slots_off = base;
+      m.oob_count_off = align_up(m.slots_off + m.cap * 16);
+      m.over_cap = next_pow2(2 * static_cast<uint64_t>(n) + 64);
+      m.oob_vals_off = m.oob_count_off + kAlign;
+      m.end = align_up(m.oob_vals_off + m.over_cap * 4);
+      return m;
+    }
+  }
   uint64_t want = static_cast<uint64_t>(std::ceil(static_cast<double>(n) / lf));
   m.cap = next_pow2(want < 64 ? 64 : want);
   if (m.cap <= static_cast<uint64_t>(n)) m.cap = next_pow2(static_cast<uint64_t>(n) + 1);
@@ -125,7 +156,11 @@ MapLayout map_layout(int32_t key_type, int64_t n, float lf, size_t base, bool ke
 MapDesc map_desc(const MapLayout& l, int32_t key_type, unsigned char* ws) {
   MapDesc d;
   d.key_type = key_type == REL_I64 ? kI64 : kI32;
-  d.key_only = (key_type != REL_I64 && l.slot_bytes == 4) ? 1 : 0;
+  d.key_only = (key_type != REL_I64 && (l.slot_bytes == 4 || l.compact)) ? 1 : 0;
+  d.compact = l.compact ? 1 : 0;
+  d.rbits = l.rbits;
+  d.over = l.compact ? reinterpret_cast<uint32_t*>(ws + l.oob_vals_off) : nullptr;
+  d.over_cap = l.compact ? l.over_cap : 0;
   d.cap = l.cap;
   d.slots = ws + l.slots_off;
   d.oob_count = reinterpret_cast<unsigned long long*>(ws + l.oob_count_off);
@@ -187,6 +222,9 @@ struct GroupLayout {
 // Replicas of the global group table: with few groups (all of them fit the
 // per-workgroup LDS tables) merges are spread over kGroupReplicas copies.
 constexpr int kGroupReplicas = 64;
+
+// Default LDS bytes for dim tables in the fused pipeline.
+constexpr size_t kDimLdsDefault = 32768;
 
 GroupLayout group_layout(const GroupPlan& gp, int64_t max_groups, float lf, size_t base,
                          int replicas = 1) {
@@ -356,7 +394,7 @@ rel_status pipeline_layout(const rel_pipeline_desc* d, PipeLayout& L) {
     // membership-only int32 dims keep keys alone (4-byte slots)
     const bool key_only = d->dims[i].key.type == REL_I32 && !d->dims[i].has_payload;
     L.dim[i] = map_layout(d->dims[i].key.type, d->dims[i].key.len, lf < 0.75f ? 0.75f : lf, off,
-                          key_only);
+                          key_only, true);
     off = L.dim[i].end;
   }
   for (int k = 0; k < d->n_keys; ++k) {
@@ -714,10 +752,13 @@ rel_status rel_pipeline(const rel_pipeline_desc* d, const rel_outputs* o, void* 
     p.queue_stride = stride;
     lds += static_cast<size_t>(kPipeThreads / kWave) * stride;
   }
-  size_t dim_budget = budget > lds ? budget - lds : 0;
+  // Dim tables go to LDS only when small: a large LDS copy costs resident
+  // workgroups, and occupancy is what hides the probe latency.
+  const size_t avail = budget > lds ? budget - lds : 0;
+  size_t dim_budget = kDimLdsDefault;
+  if (t && t->dim_lds_bytes > 0) dim_budget = static_cast<size_t>(t->dim_lds_bytes);
   if (t && t->dim_lds_bytes < 0) dim_budget = 0;
-  else if (t && t->dim_lds_bytes > 0 && static_cast<size_t>(t->dim_lds_bytes) < dim_budget)
-    dim_budget = static_cast<size_t>(t->dim_lds_bytes);
+  if (dim_budget > avail) dim_budget = avail;
   p.ndims = d->n_dims;
   int order[REL_MAX_DIMS] = {0, 1};
   if (d->n_dims == 2 && L.dim[1].cap * L.dim[1].slot_bytes < L.dim[0].cap * L.dim[0].slot_bytes) {
@@ -731,7 +772,7 @@ rel_status rel_pipeline(const rel_pipeline_desc* d, const rel_outputs* o, void* 
     p.dim[i].map = map_desc(L.dim[i], dm.key.type, w);
     p.dim[i].fk_col = dm.fact_col;
     const size_t bytes = L.dim[i].cap * L.dim[i].slot_bytes;
-    if (dm.key.type == REL_I32 && dim_used + bytes <= dim_budget) {
+    if (dm.key.type == REL_I32 && !L.dim[i].compact && dim_used + bytes <= dim_budget) {
       p.dim[i].in_lds = 1;
       p.dim[i].lds_offset = static_cast<uint32_t>(lds);
       lds += bytes;

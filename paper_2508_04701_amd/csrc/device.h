@@ -240,6 +240,97 @@ __device__ __forceinline__ void set_insert(uint32_t* slots, uint64_t mask,
   }
 }
 
+// ---------------------------------------------------------- compact sets
+//
+// Exact multiset of int32 keys in 16-bit entries, for large membership dims.
+// hash32 (the MurmurHash3 finaliser) is a bijection on 32-bit words, so a key
+// is determined by its home bucket (the top `32 - rbits` hash bits) and the
+// remaining `rbits` <= 14 hash bits. A bucket is 16 bytes: eight entries of
+// (displacement:2 | remainder:14); 0xFFFF marks an empty entry. A key lives in
+// its home bucket or one of the next two (displacement 1, 2); a key finding
+// no room there goes to an out-of-band key list. Reading the home bucket with
+// one 16-byte load resolves nearly every probe, from a table of two bytes per
+// slot (4 MB for 1.5M keys).
+
+constexpr uint32_t kCsetEmpty = 0xFFFFu;
+constexpr int kCsetMaxDisp = 2;
+
+struct CsetDesc {
+  uint32_t* words;     // buckets * 4 words
+  uint64_t bmask;      // buckets - 1
+  int32_t rbits;       // remainder bits (<= 14)
+  int32_t* dup;
+  // Keys that find no room within the displacement window go to a plain
+  // key-only set (4-byte slots) with its own sentinel count.
+  uint32_t* over;
+  uint64_t over_mask;
+  unsigned long long* over_sentinel;
+};
+
+__device__ __forceinline__ void cset_split(const CsetDesc& c, int32_t key, uint64_t& b, uint32_t& r) {
+  const uint32_t h = hash32(static_cast<uint32_t>(key));
+  b = (h >> c.rbits) & c.bmask;
+  r = h & ((1u << c.rbits) - 1u);
+}
+
+__device__ __forceinline__ void cset_insert(const CsetDesc& c, int32_t key) {
+  uint64_t b0;
+  uint32_t r;
+  cset_split(c, key, b0, r);
+  for (int d = 0; d <= kCsetMaxDisp; ++d) {
+    uint32_t* w = c.words + ((b0 + d) & c.bmask) * 4;
+    const uint32_t mine = (static_cast<uint32_t>(d) << 14) | r;
+    for (int i = 0; i < 4; ++i) {
+      uint32_t cur = __hip_atomic_load(w + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      while (true) {
+        const uint32_t lo = cur & 0xFFFFu, hi = cur >> 16;
+        if (lo == mine || hi == mine) *c.dup = 1;
+        uint32_t want;
+        if (lo == kCsetEmpty) want = (cur & 0xFFFF0000u) | mine;
+        else if (hi == kCsetEmpty) want = (cur & 0x0000FFFFu) | (mine << 16);
+        else break;  // both entries taken: next word
+        const uint32_t prev = atomicCAS(w + i, cur, want);
+        if (prev == cur) return;
+        cur = prev;  // lost a race: re-examine the word
+      }
+    }
+  }
+  set_insert(c.over, c.over_mask, c.over_sentinel, key, c.dup);
+}
+
+// Matches of `key` in the overflow set, counted up to `limit`.
+__device__ __forceinline__ int cset_over_count(const CsetDesc& c, int32_t key, int limit) {
+  if (key == kEmpty32) {
+    const unsigned long long n = *c.over_sentinel;
+    return n < static_cast<unsigned long long>(limit) ? static_cast<int>(n) : limit;
+  }
+  int found = 0;
+  uint64_t h = home_set(key, c.over_mask);
+  while (found < limit) {
+    const int32_t s = static_cast<int32_t>(c.over[h]);
+    if (s == kEmpty32) break;
+    found += s == key;
+    h = (h + 1) & c.over_mask;
+  }
+  return found;
+}
+
+// Counts the entries of `key` in one 16-byte bucket at displacement d;
+// `open` tells whether the bucket still has an empty entry (then no key of
+// this home lies further on).
+__device__ __forceinline__ int cset_bucket_count(uint4 q, uint32_t target, bool& open) {
+  const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+  int n = 0;
+  open = false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t lo = w[i] & 0xFFFFu, hi = w[i] >> 16;
+    n += (lo == target) + (hi == target);
+    open |= (lo == kCsetEmpty) | (hi == kCsetEmpty);
+  }
+  return n;
+}
+
 // Cursor over the matches of one key: `pos` walks the probe chain (or the
 // out-of-band list when `oob`); next() yields one match per call.
 struct MapCursor {

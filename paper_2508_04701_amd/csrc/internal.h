@@ -68,11 +68,15 @@ void launch_filter(const FilterParams& p, hipStream_t s);
 struct MapDesc {
   int32_t key_type;   // kI32 or kI64
   int32_t key_only;   // int32 keys without values (membership): 4-byte slots
+  int32_t compact;    // membership set in 16-bit entries (CsetDesc layout)
+  int32_t rbits;      // compact: remainder bits
   uint64_t cap;       // slots (power of two)
   void* slots;        // cap * 4 (key-only), 8 (int32 keys) or 16 (int64 keys) bytes
   unsigned long long* oob_count;
   uint32_t* oob_vals;  // n entries
   int32_t* dup;        // set by the build when a key occurs twice
+  uint32_t* over;      // compact: overflow key-only set
+  uint64_t over_cap;   // compact: its slots (power of two)
 };
 
 // Inserts n keys of column (data, idx, type); value of element i is

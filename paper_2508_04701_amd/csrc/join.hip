@@ -42,6 +42,12 @@ __global__ void __launch_bounds__(256) map_build_kernel(MapBuildParams p) {
     int64_t r = p.idx ? static_cast<int64_t>(p.idx[i]) : static_cast<int64_t>(i);
     K key = static_cast<K>(load_elem(p.keys, p.type, r));
     if constexpr (sizeof(K) == 4) {
+      if (p.map.compact) {
+        CsetDesc c{static_cast<uint32_t*>(p.map.slots), p.map.cap - 1, p.map.rbits, p.map.dup,
+                   p.map.over, p.map.over_cap - 1, p.map.oob_count};
+        cset_insert(c, key);
+        continue;
+      }
       if (p.map.key_only) {
         set_insert(static_cast<uint32_t*>(p.map.slots), p.map.cap - 1, p.map.oob_count, key,
                    p.map.dup);
@@ -118,7 +124,11 @@ void launch_fill64(uint64_t* p, uint64_t n, uint64_t pattern, hipStream_t s) {
 }
 
 void launch_map_init(const MapDesc& m, hipStream_t s) {
-  if (m.key_only) {
+  if (m.compact) {
+    // every 16-bit entry empty (0xFFFF); cap counts 16-byte buckets
+    launch_fill64(static_cast<uint64_t*>(m.slots), m.cap * 2, ~0ULL, s);
+    launch_fill64(reinterpret_cast<uint64_t*>(m.over), m.over_cap / 2, 0x8000000080000000ULL, s);
+  } else if (m.key_only) {
     // two empty 32-bit slots per word (cap >= 64 is even)
     launch_fill64(static_cast<uint64_t*>(m.slots), m.cap / 2, 0x8000000080000000ULL, s);
   } else if (m.key_type == kI32) {

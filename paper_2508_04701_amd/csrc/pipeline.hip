@@ -10,7 +10,8 @@
 namespace rel {
 namespace pipe {
 
-#define REL_FOR_EACH_D1(M, D0) M(D0, kNone) M(D0, kMap) M(D0, kMapLds) M(D0, kSet) M(D0, kSetLds) M(D0, kMap64)
+#define REL_FOR_EACH_D1(M, D0) \
+  M(D0, kNone) M(D0, kMap) M(D0, kMapLds) M(D0, kSet) M(D0, kSetLds) M(D0, kMap64) M(D0, kCSet)
 
 #if defined(REL_PIPE_D0)
 
@@ -25,6 +26,7 @@ REL_FOR_EACH_D1(REL_DECLARE, kMapLds)
 REL_FOR_EACH_D1(REL_DECLARE, kSet)
 REL_FOR_EACH_D1(REL_DECLARE, kSetLds)
 REL_FOR_EACH_D1(REL_DECLARE, kMap64)
+REL_FOR_EACH_D1(REL_DECLARE, kCSet)
 
 namespace {
 
@@ -32,6 +34,7 @@ int dim_mode(const PipelineParams& p, int d) {
   if (d >= p.ndims) return kNone;
   const PipeDim& dm = p.dim[d];
   if (dm.map.key_type == kI64) return kMap64;
+  if (dm.map.compact) return kCSet;
   if (dm.map.key_only) return dm.in_lds ? kSetLds : kSet;
   return dm.in_lds ? kMapLds : kMap;
 }
@@ -44,6 +47,7 @@ hipError_t launch_second(const PipelineParams& p, int grid, hipStream_t s) {
     case kMapLds: return launch_fused<D0, kMapLds>(p, grid, s);
     case kSet: return launch_fused<D0, kSet>(p, grid, s);
     case kSetLds: return launch_fused<D0, kSetLds>(p, grid, s);
+    case kCSet: return launch_fused<D0, kCSet>(p, grid, s);
     default: return launch_fused<D0, kMap64>(p, grid, s);
   }
 }
@@ -61,6 +65,7 @@ hipError_t launch_pipeline(const PipelineParams& p, int grid, hipStream_t s) {
     case kMapLds: return launch_second<kMapLds>(p, grid, s);
     case kSet: return launch_second<kSet>(p, grid, s);
     case kSetLds: return launch_second<kSetLds>(p, grid, s);
+    case kCSet: return launch_second<kCSet>(p, grid, s);
     default: return launch_second<kMap64>(p, grid, s);
   }
 }

@@ -39,7 +39,32 @@ enum : int {
   kSet = 3,     // int32 key only, HBM
   kSetLds = 4,  // int32 key only, LDS copy
   kMap64 = 5,   // int64 key -> value, HBM
+  kCSet = 6,    // int32 key only, compact 16-bit entries, HBM
 };
+
+__device__ __forceinline__ CsetDesc cset_of(const PipeDim& d) {
+  return CsetDesc{static_cast<uint32_t*>(d.map.slots), d.map.cap - 1, d.map.rbits, d.map.dup,
+                  d.map.over, d.map.over_cap - 1, d.map.oob_count};
+}
+
+// Matches of `key` in a compact set, counted up to `limit`.
+__device__ __forceinline__ int cset_matches(const PipeDim& d, int32_t key, uint4 first, int limit) {
+  const CsetDesc c = cset_of(d);
+  uint64_t b0;
+  uint32_t r;
+  cset_split(c, key, b0, r);
+  const uint4* buckets = reinterpret_cast<const uint4*>(c.words);
+  int found = 0;
+  uint4 q = first;
+  for (int disp = 0; disp <= kCsetMaxDisp; ++disp) {
+    bool open;
+    found += cset_bucket_count(q, (static_cast<uint32_t>(disp) << 14) | r, open);
+    if (found >= limit || open) return found < limit ? found : limit;
+    if (disp < kCsetMaxDisp) q = buckets[(b0 + disp + 1) & c.bmask];
+  }
+  // all three buckets full: the key may have been placed in the overflow set
+  return found + cset_over_count(c, key, limit - found);
+}
 
 template <int D>
 __device__ __forceinline__ const void* dim_slots(const PipeDim& d, const void* lds_copy) {
@@ -65,6 +90,12 @@ __device__ __forceinline__ uint64_t probe_home(const PipeDim& d, int64_t key) {
 template <int D>
 __device__ __forceinline__ uint4 probe_first(const PipeDim& d, const void* lds_copy, int64_t key) {
   const uint4* groups = static_cast<const uint4*>(dim_slots<D>(d, lds_copy));
+  if constexpr (D == kCSet) {
+    uint64_t b0;
+    uint32_t r;
+    cset_split(cset_of(d), static_cast<int32_t>(key), b0, r);
+    return groups[b0];
+  }
   const uint64_t h = probe_home<D>(d, key);
   if constexpr (D == kMap64) return groups[h];
   else if constexpr (D == kSet || D == kSetLds) return groups[h >> 2];
@@ -77,7 +108,13 @@ __device__ __forceinline__ int probe_finish(const PipeDim& d, const void* lds_co
   const uint64_t mask = d.map.cap - 1;
   const uint4* groups = static_cast<const uint4*>(dim_slots<D>(d, lds_copy));
   int found = 0;
-  if constexpr (D == kMap64) {
+  if constexpr (D == kCSet) {
+    (void)mask;
+    (void)groups;
+    (void)val;
+    const int m = cset_matches(d, static_cast<int32_t>(key), first, limit);
+    return m > 2 ? 2 : m;
+  } else if constexpr (D == kMap64) {
     if (static_cast<uint64_t>(key) == kEmpty64) {
       const unsigned long long c = *d.map.oob_count;
       if (c) val = d.map.oob_vals[0];
@@ -144,7 +181,17 @@ template <int D>
 __device__ __forceinline__ MapCursor dim_start(const PipeDim& d, int64_t key) {
   MapCursor c;
   c.live = true;
-  if constexpr (D == kMap64) {
+  if constexpr (D == kCSet) {
+    // the cursor counts down the key's multiplicity
+    const CsetDesc cs = cset_of(d);
+    uint64_t b0;
+    uint32_t r;
+    cset_split(cs, static_cast<int32_t>(key), b0, r);
+    const uint4 first = reinterpret_cast<const uint4*>(cs.words)[b0];
+    c.oob = false;
+    c.pos = static_cast<uint64_t>(cset_matches(d, static_cast<int32_t>(key), first, 1 << 30));
+    return c;
+  } else if constexpr (D == kMap64) {
     c.oob = static_cast<uint64_t>(key) == kEmpty64;
     c.pos = c.oob ? 0 : home64(key, d.map.cap - 1);
   } else {
@@ -161,7 +208,18 @@ __device__ __forceinline__ bool dim_next(const PipeDim& d, const void* lds_copy,
                                          MapCursor& c, uint32_t& val) {
   const uint64_t mask = d.map.cap - 1;
   const void* base = dim_slots<D>(d, lds_copy);
-  if constexpr (D == kMap64) {
+  if constexpr (D == kCSet) {
+    (void)mask;
+    (void)base;
+    (void)key;
+    (void)val;
+    if (!c.live || c.pos == 0) {
+      c.live = false;
+      return false;
+    }
+    --c.pos;
+    return true;
+  } else if constexpr (D == kMap64) {
     return map_next(static_cast<const ulonglong2*>(base), mask, d.map.oob_count, d.map.oob_vals,
                     key, c, val);
   } else if constexpr (D == kSet || D == kSetLds) {

@@ -355,3 +355,43 @@ def test_join_groupby_workload_full_size():
     got2 = rel.groupby_agg([dev(d["build_grp"])], [dev(d["probe_val"])], chained_aggs,
                            max_groups=64, key_idx=ob, val_idx=op)
     assert_groups(got2, want, chained_aggs, "chained")
+
+
+def _fmix32_inverse(h):
+    """Inverse of the MurmurHash3 32-bit finaliser (test-side, to craft keys
+    whose hashes fall in one bucket of a compact membership set)."""
+    m = 0xFFFFFFFF
+    h ^= h >> 16
+    h = (h * pow(0xC2B2AE35, -1, 2**32)) & m
+    h ^= (h >> 13) ^ (h >> 26)
+    h = (h * pow(0x85EBCA6B, -1, 2**32)) & m
+    h ^= h >> 16
+    return h
+
+
+def test_pipeline_large_membership_dim():
+    """A membership dim large enough for the 16-bit compact set (> 786k keys),
+    with duplicate keys and 40 keys crafted to share one bucket, so that
+    displaced entries and the out-of-band list are exercised."""
+    announce("pipeline compact membership dim")
+    r = rng(31)
+    nd = 900_000
+    keys = r.choice(2**31 - 1, size=nd, replace=False).astype(np.int64) - 2**30
+    bucket = 12345
+    crafted = []
+    for rem in range(40):
+        k = _fmix32_inverse((bucket << 14) | rem)
+        crafted.append(k - 2**32 if k >= 2**31 else k)
+    keys = np.concatenate([keys, np.array(crafted, np.int64), keys[:500]])  # + 500 duplicates
+    dim_key = keys.astype(np.int32)
+    n = 400_000
+    fk = np.concatenate([r.choice(dim_key, size=n - 2000), r.integers(-2**31, 2**31 - 1, size=1000),
+                         np.repeat(np.array(crafted, np.int64), 25)]).astype(np.int32)
+    r.shuffle(fk)
+    g = r.integers(0, 50, size=n).astype(np.int32)
+    v = r.integers(-10**6, 10**6, size=n).astype(np.int64)
+    fact = [fk, g, v]
+    dims = [dict(fk=0, key=dim_key, payload=None)]
+    aggs = [("sum", 2), ("count", None), ("min", 2)]
+    got, want = run_both(fact, [], dims, [("fact", 1)], aggs, max_groups=64)
+    assert_groups(got, want, aggs, "compact set")
