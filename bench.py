@@ -39,8 +39,37 @@ TERMS = [(2, "lt", 767)]
 KEYS = [("dim", 1), ("fact", 4)]
 
 
+# Sources that define the fused kernel; a traffic figure taken with
+# rocprofv3 counters is reported only while they are unchanged.
+KERNEL_SOURCES = ["device.h", "internal.h", "group_lds.h", "pipeline_kernel.h", "pipeline.hip"]
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pipeline_fused_star600m.json")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2508_04701_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n: int):
+    """HBM bytes per launch of the fused kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size),
+    or None if it was taken on other kernel sources or another size."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            prof = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if prof.get("kernel_sources_sha256") != kernel_sources_sha256() or prof.get("fact_rows") != n:
+        return None
+    return prof["fetch_bytes"] + prof["write_bytes"]
 
 
 def cpu_model() -> str:
@@ -176,7 +205,7 @@ def main() -> int:
         "roofline": {"bound": "hbm", "kernel": "pipeline_fused", "achieved": achieved_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
                      "kernel_ms": fused_avg_ms, "algorithmic_bytes": alg_bytes,
-                     "traffic": None},
+                     "traffic": measured_traffic(n)},
     }
     if not args.no_cpu_baseline:
         host = {k: v for k, v in d.items()}

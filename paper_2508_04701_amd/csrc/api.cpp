@@ -726,6 +726,7 @@ rel_status rel_pipeline(const rel_pipeline_desc* d, const rel_outputs* o, void* 
     for (int i = 0; i < d->n_dims; ++i) {
       present[kQFk0 + i] = true;
       wide[kQFk0 + i] = d->dims[i].key.type == REL_I64;
+      present[kQSt0 + i] = true;
     }
     // The first two distinct value columns are gathered with the probes.
     int early[2] = {-1, -1};

@@ -173,9 +173,10 @@ struct PipeDim {
   uint32_t lds_offset;   // byte offset of the copy in dynamic LDS
 };
 
-// Queued row fields: row id, the two foreign keys, two fact group-key
-// columns and two value columns.
-enum QueueField : int { kQRow = 0, kQFk0, kQFk1, kQKey0, kQKey1, kQValA, kQValB, kQueueFields };
+// Queued row fields: row id, the two foreign keys and the resume state of
+// each dim's probe (0: not started; k: k buckets already scanned;
+// kResolved | slot: found at that slot).
+enum QueueField : int { kQRow = 0, kQFk0, kQFk1, kQSt0, kQSt1, kQueueFields };
 
 struct PipelineParams {
   const void* fact[8];

@@ -311,6 +311,25 @@ __device__ __forceinline__ void load_col4(const PipelineParams& p, int c, int64_
   load4(p.fact[c], p.fact_type[c], p.fact_vec[c] != 0, r0, p.n, v);
 }
 
+// Foreign keys are held in the width of the dim's keys.
+template <int D>
+struct KeyOf {
+  using T = int32_t;
+};
+template <>
+struct KeyOf<kMap64> {
+  using T = int64_t;
+};
+
+template <int D>
+__device__ __forceinline__ void load_keys4(const PipelineParams& p, int c, int64_t r0,
+                                           typename KeyOf<D>::T k[4]) {
+  int64_t v[4];
+  load4s(p.fact[c], p.fact_type[c], p.fact_vec[c] != 0, r0, p.n, v);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) k[e] = static_cast<typename KeyOf<D>::T>(v[e]);
+}
+
 template <int D>
 __device__ __forceinline__ void copy_dim_to_lds(const PipeDim& d, void* lds_copy) {
   if constexpr (D == kMapLds || D == kSetLds) {
@@ -335,25 +354,182 @@ __device__ __forceinline__ int64_t queue_get(const PipelineParams& p, const unsi
   return reinterpret_cast<const int32_t*>(a)[i];
 }
 
-// One queued row per lane: probe the dims, then update the row's group.
+// ------------------------------------------------------ resumable probes
+//
+// A probe of an HBM dim without duplicate keys reads one bucket per batch.
+// If the key's run continues past that bucket, the row goes back to the
+// queue with the number of buckets scanned, and is resumed in a later batch.
+// With 64 lanes per batch, waiting for the longest run of the batch would
+// otherwise cost several dependent reads per batch even when few runs are
+// long. A dim whose key was found keeps the slot index, and a resumed row
+// rereads only that slot's bucket (maps) or nothing (sets).
+
+constexpr uint32_t kResolved = 0x80000000u;
+
+template <int D>
+constexpr bool kResumable = (D == kMap || D == kSet || D == kCSet || D == kMap64);
+
+template <int D>
+__device__ __forceinline__ uint64_t start_bucket(const PipeDim& d, int64_t key) {
+  if constexpr (D == kMap64) {
+    return home64(key, d.map.cap - 1);
+  } else if constexpr (D == kCSet) {
+    uint64_t b0;
+    uint32_t r;
+    cset_split(cset_of(d), static_cast<int32_t>(key), b0, r);
+    return b0;
+  } else if constexpr (D == kSet) {
+    return home_set(static_cast<int32_t>(key), d.map.cap - 1) >> 2;
+  } else {
+    return home32(static_cast<int32_t>(key), d.map.cap - 1) >> 1;
+  }
+}
+
+template <int D>
+__device__ __forceinline__ uint64_t bucket_mask(const PipeDim& d) {
+  if constexpr (D == kMap64 || D == kCSet) return d.map.cap - 1;
+  else if constexpr (D == kSet) return (d.map.cap - 1) >> 2;
+  else return (d.map.cap - 1) >> 1;
+}
+
+// The bucket a probe in state `st` reads next (sets that are resolved need none).
+template <int D>
+__device__ __forceinline__ uint4 probe_load(const PipeDim& d, int64_t key, uint32_t st) {
+  const uint4* buckets = static_cast<const uint4*>(d.map.slots);
+  if (st & kResolved) {
+    const uint32_t slot = st & ~kResolved;
+    if constexpr (D == kMap) return buckets[slot >> 1];
+    else if constexpr (D == kMap64) return buckets[slot];
+    else return make_uint4(0, 0, 0, 0);
+  }
+  return buckets[(start_bucket<D>(d, key) + st) & bucket_mask<D>(d)];
+}
+
+// Examines the bucket read for state `st`: 0 = no match, 1 = match (`val`
+// set, `st` resolved), 2 = the run continues (`st` advanced).
+template <int D>
+__device__ __forceinline__ int probe_examine(const PipeDim& d, int64_t key, uint4 q, uint32_t& st,
+                                             uint32_t& val) {
+  if (st & kResolved) {
+    const uint32_t slot = st & ~kResolved;
+    if constexpr (D == kMap) val = (slot & 1) ? q.w : q.y;
+    else if constexpr (D == kMap64) val = q.z;
+    return 1;
+  }
+  const uint64_t g = (start_bucket<D>(d, key) + st) & bucket_mask<D>(d);
+  if constexpr (D == kCSet) {
+    const CsetDesc c = cset_of(d);
+    uint64_t b0;
+    uint32_t r;
+    cset_split(c, static_cast<int32_t>(key), b0, r);
+    bool open;
+    if (cset_bucket_count(q, (st << 14) | r, open) > 0) {
+      st = kResolved;
+      return 1;
+    }
+    if (open) return 0;
+    if (st == kCsetMaxDisp) {
+      if (cset_over_count(c, static_cast<int32_t>(key), 1) > 0) {
+        st = kResolved;
+        return 1;
+      }
+      return 0;
+    }
+    ++st;
+    return 2;
+  } else if constexpr (D == kMap64) {
+    if (static_cast<uint64_t>(key) == kEmpty64) {  // out-of-band key, unique build
+      if (*d.map.oob_count == 0) return 0;
+      val = d.map.oob_vals[0];
+      return 1;
+    }
+    const uint64_t sk = static_cast<uint64_t>(q.x) | (static_cast<uint64_t>(q.y) << 32);
+    if (sk == kEmpty64) return 0;
+    if (static_cast<int64_t>(sk) == key) {
+      val = q.z;
+      st = kResolved | static_cast<uint32_t>(g);
+      return 1;
+    }
+    ++st;
+    return 2;
+  } else {
+    const int32_t k = static_cast<int32_t>(key);
+    if (k == kEmpty32) {
+      if (*d.map.oob_count == 0) return 0;
+      if constexpr (D == kMap) val = d.map.oob_vals[0];
+      return 1;
+    }
+    if constexpr (D == kSet) {
+      const int32_t sv[4] = {static_cast<int32_t>(q.x), static_cast<int32_t>(q.y),
+                             static_cast<int32_t>(q.z), static_cast<int32_t>(q.w)};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (sv[i] == k) {
+          st = kResolved;
+          return 1;
+        }
+        if (sv[i] == kEmpty32) return 0;
+      }
+    } else {
+      const int32_t sk[2] = {static_cast<int32_t>(q.x), static_cast<int32_t>(q.z)};
+      const uint32_t sval[2] = {q.y, q.w};
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if (sk[i] == k) {
+          val = sval[i];
+          st = kResolved | static_cast<uint32_t>(g * 2 + i);
+          return 1;
+        }
+        if (sk[i] == kEmpty32) return 0;
+      }
+    }
+    ++st;
+    return 2;
+  }
+}
+
+// One queued row: probe the dims and update the row's group. Returns true
+// when the row has to go back to the queue (a resumable probe continues).
 template <int D0, int D1>
-__device__ __forceinline__ void process_queued(const PipelineParams& p, const unsigned char* wq,
-                                               uint32_t i, const void* ld0, const void* ld1,
-                                               uint64_t* lg, const GroupTable& gt, int limit0,
-                                               int limit1) {
-  const int64_t r = static_cast<uint32_t>(queue_get(p, wq, kQRow, i));
-  int64_t fk0 = 0, fk1 = 0;
+__device__ __forceinline__ bool process_row(const PipelineParams& p, int64_t r, int64_t fk0,
+                                            int64_t fk1, uint32_t& st0, uint32_t& st1,
+                                            const void* ld0, const void* ld1, uint64_t* lg,
+                                            const GroupTable& gt, int limit0, int limit1) {
+  const bool res0 = kResumable<D0> && limit0 == 1;
+  const bool res1 = kResumable<D1> && limit1 == 1;
   uint4 q0 = make_uint4(0, 0, 0, 0), q1 = make_uint4(0, 0, 0, 0);
+  if constexpr (D0 != kNone)
+    q0 = res0 ? probe_load<D0>(p.dim[0], fk0, st0) : probe_first<D0>(p.dim[0], ld0, fk0);
+  if constexpr (D1 != kNone)
+    q1 = res1 ? probe_load<D1>(p.dim[1], fk1, st1) : probe_first<D1>(p.dim[1], ld1, fk1);
+  uint32_t v0 = 0, v1 = 0;
+  bool more = false, multi = false;
   if constexpr (D0 != kNone) {
-    fk0 = queue_get(p, wq, kQFk0, i);
-    q0 = probe_first<D0>(p.dim[0], ld0, fk0);
+    if (res0) {
+      const int m = probe_examine<D0>(p.dim[0], fk0, q0, st0, v0);
+      if (m == 0) return false;
+      more |= m == 2;
+    } else {
+      const int m = probe_finish<D0>(p.dim[0], ld0, fk0, limit0, q0, v0);
+      if (m == 0) return false;
+      multi |= m == 2;
+    }
   }
   if constexpr (D1 != kNone) {
-    fk1 = queue_get(p, wq, kQFk1, i);
-    q1 = probe_first<D1>(p.dim[1], ld1, fk1);
+    if (res1) {
+      const int m = probe_examine<D1>(p.dim[1], fk1, q1, st1, v1);
+      if (m == 0) return false;
+      more |= m == 2;
+    } else {
+      const int m = probe_finish<D1>(p.dim[1], ld1, fk1, limit1, q1, v1);
+      if (m == 0) return false;
+      multi |= m == 2;
+    }
   }
-  // Group-key and value columns are gathered by row id while the probe
-  // reads are in flight.
+  if (more) return true;
+  if (multi) return false;  // several dim matches: left to the enumeration pass
+  // Group-key and value columns of the rows that survived the joins,
+  // gathered by row id (lines the batch shares are fetched once).
   int64_t k0 = 0, k1 = 0;
   if (p.g.kp.nkeys > 0 && p.key_src[0] == 0)
     k0 = load_elem(p.fact[p.key_col[0]], p.fact_type[p.key_col[0]], r);
@@ -362,25 +538,6 @@ __device__ __forceinline__ void process_queued(const PipelineParams& p, const un
   int64_t va = 0, vb = 0;
   if (p.early_col[0] >= 0) va = load_elem(p.fact[p.early_col[0]], p.fact_type[p.early_col[0]], r);
   if (p.early_col[1] >= 0) vb = load_elem(p.fact[p.early_col[1]], p.fact_type[p.early_col[1]], r);
-
-  uint32_t v0 = 0, v1 = 0;
-  bool multi = false;
-  if constexpr (D0 != kNone) {
-    const int m = probe_finish<D0>(p.dim[0], ld0, fk0, limit0, q0, v0);
-    if (m == 0) return;
-    multi |= m == 2;
-  }
-  if constexpr (D1 != kNone) {
-    const int m = probe_finish<D1>(p.dim[1], ld1, fk1, limit1, q1, v1);
-    if (m == 0) return;
-    multi |= m == 2;
-  }
-  if constexpr (D0 != kNone) {
-    if (multi) {
-      enumerate_row<D0, D1>(p, r, ld0, ld1, lg, gt);
-      return;
-    }
-  }
   if (p.g.kp.nkeys > 0 && p.key_src[0] != 0) k0 = static_cast<int32_t>(p.key_src[0] == 1 ? v0 : v1);
   if (p.g.kp.nkeys > 1 && p.key_src[1] != 0) k1 = static_cast<int32_t>(p.key_src[1] == 1 ? v0 : v1);
   const uint64_t pk = pack_keys(p.g.kp, k0, k1);
@@ -391,7 +548,7 @@ __device__ __forceinline__ void process_queued(const PipelineParams& p, const un
     atomicAdd(reinterpret_cast<unsigned long long*>(lg + li * words + 1), 1ULL);
   } else {
     gs = group_slot(gt, pk);
-    if (!gs) return;
+    if (!gs) return false;
     atomicAdd(reinterpret_cast<unsigned long long*>(gs + 1), 1ULL);
   }
   for (int a = 0; a < p.g.ap.nacc; ++a) {
@@ -421,6 +578,50 @@ __device__ __forceinline__ void process_queued(const PipelineParams& p, const un
         atomicMax(reinterpret_cast<long long*>(w), static_cast<long long>(v));
     }
   }
+  return false;
+}
+
+// Processes the top `take` (<= 64) rows of the wave's queue, one per lane;
+// rows whose probes continue are written back. Returns the new queue length.
+template <int D0, int D1>
+__device__ __forceinline__ uint32_t drain(const PipelineParams& p, unsigned char* wq,
+                                          uint32_t queued, uint32_t take, int lane,
+                                          const void* ld0, const void* ld1, uint64_t* lg,
+                                          const GroupTable& gt, int limit0, int limit1) {
+  const uint32_t base = queued - take;
+  const bool mine = static_cast<uint32_t>(lane) < take;
+  int64_t r = 0, fk0 = 0, fk1 = 0;
+  uint32_t st0 = 0, st1 = 0;
+  if (mine) {
+    const uint32_t i = base + lane;
+    r = static_cast<uint32_t>(queue_get(p, wq, kQRow, i));
+    if constexpr (D0 != kNone) {
+      fk0 = queue_get(p, wq, kQFk0, i);
+      st0 = static_cast<uint32_t>(queue_get(p, wq, kQSt0, i));
+    }
+    if constexpr (D1 != kNone) {
+      fk1 = queue_get(p, wq, kQFk1, i);
+      st1 = static_cast<uint32_t>(queue_get(p, wq, kQSt1, i));
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  bool again = false;
+  if (mine) again = process_row<D0, D1>(p, r, fk0, fk1, st0, st1, ld0, ld1, lg, gt, limit0, limit1);
+  const uint64_t b = ballot(again);
+  if (again) {
+    const uint32_t at = base + rank_below(b);
+    queue_put(p, wq, kQRow, at, r);
+    if constexpr (D0 != kNone) {
+      queue_put(p, wq, kQFk0, at, fk0);
+      queue_put(p, wq, kQSt0, at, static_cast<int32_t>(st0));
+    }
+    if constexpr (D1 != kNone) {
+      queue_put(p, wq, kQFk1, at, fk1);
+      queue_put(p, wq, kQSt1, at, static_cast<int32_t>(st1));
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  return base + popc64(b);
 }
 
 template <int D0, int D1>
@@ -454,18 +655,13 @@ __global__ void __launch_bounds__(kPipeThreads) fused_kernel(PipelineParams p) {
     const int64_t r0 = tile * static_cast<int64_t>(kPipeTile) + tid * 4;
     const uint32_t bits = eval_prefetched(p, r0, pre);
     const int64_t next = tile + gridDim.x;
-    // Foreign keys of the passing rows, streamed; lanes without a passing
-    // row skip them.
-    int64_t fk0[4] = {0, 0, 0, 0}, fk1[4] = {0, 0, 0, 0};
+    // Foreign keys of the passing rows, streamed and held in the dim's key
+    // width; lanes without a passing row skip them.
+    typename KeyOf<D0>::T fk0[4] = {0, 0, 0, 0};
+    typename KeyOf<D1>::T fk1[4] = {0, 0, 0, 0};
     if (bits) {
-      if constexpr (D0 != kNone) {
-        const int c = p.dim[0].fk_col;
-        load4s(p.fact[c], p.fact_type[c], p.fact_vec[c] != 0, r0, p.n, fk0);
-      }
-      if constexpr (D1 != kNone) {
-        const int c = p.dim[1].fk_col;
-        load4s(p.fact[c], p.fact_type[c], p.fact_vec[c] != 0, r0, p.n, fk1);
-      }
+      if constexpr (D0 != kNone) load_keys4<D0>(p, p.dim[0].fk_col, r0, fk0);
+      if constexpr (D1 != kNone) load_keys4<D1>(p, p.dim[1].fk_col, r0, fk1);
     }
     if (p.nterms > 0 && next < p.ntiles)
       load4s(p.fact[c_pred], p.fact_type[c_pred], p.fact_vec[c_pred] != 0,
@@ -478,26 +674,103 @@ __global__ void __launch_bounds__(kPipeThreads) fused_kernel(PipelineParams p) {
       if (pass) {
         const uint32_t at = queued + rank_below(b);
         queue_put(p, wq, kQRow, at, r0 + e);
-        if constexpr (D0 != kNone) queue_put(p, wq, kQFk0, at, fk0[e]);
-        if constexpr (D1 != kNone) queue_put(p, wq, kQFk1, at, fk1[e]);
+        if constexpr (D0 != kNone) {
+          queue_put(p, wq, kQFk0, at, fk0[e]);
+          queue_put(p, wq, kQSt0, at, 0);
+        }
+        if constexpr (D1 != kNone) {
+          queue_put(p, wq, kQFk1, at, fk1[e]);
+          queue_put(p, wq, kQSt1, at, 0);
+        }
       }
       queued += popc64(b);
-      if (queued >= kWave) {
-        __builtin_amdgcn_wave_barrier();
-        queued -= kWave;
-        process_queued<D0, D1>(p, wq, queued + lane, ld0, ld1, lg, gt, limit0, limit1);
-        __builtin_amdgcn_wave_barrier();
-      }
+      __builtin_amdgcn_wave_barrier();
+      while (queued >= kWave)
+        queued = drain<D0, D1>(p, wq, queued, kWave, lane, ld0, ld1, lg, gt, limit0, limit1);
     }
   }
-  if (queued > 0) {
-    __builtin_amdgcn_wave_barrier();
-    if (static_cast<uint32_t>(lane) < queued)
-      process_queued<D0, D1>(p, wq, lane, ld0, ld1, lg, gt, limit0, limit1);
+  __builtin_amdgcn_wave_barrier();
+  while (queued > 0)
+    queued = drain<D0, D1>(p, wq, queued, queued < kWave ? queued : kWave, lane, ld0, ld1, lg, gt,
+                           limit0, limit1);
+  if (p.lds_slots == 0) return;
+  __syncthreads();
+  lds_group_flush(lg, p.lds_slots, p.g);
+}
+
+// ------------------------------------------------------ enumeration pass
+//
+// Rows with several matches in a dim (duplicate dim keys) are skipped by the
+// fused kernel and handled here, one row per thread: every combination of
+// matching dim rows is aggregated. The pass returns at once when no dim build
+// saw a duplicate key, so plans over unique dims pay only a launch.
+
+template <int D>
+struct HbmMode {
+  static constexpr int value = D == kMapLds ? kMap : (D == kSetLds ? kSet : D);
+};
+
+__device__ __forceinline__ bool row_passes(const PipelineParams& p, int64_t r) {
+  for (int t = 0; t < p.nterms; ++t) {
+    const int c = p.term_col[t];
+    if (!term_holds(p.term_op[t], load_elem(p.fact[c], p.fact_type[c], r), p.term_lo[t],
+                    p.term_hi[t]))
+      return false;
+  }
+  return true;
+}
+
+template <int D>
+__device__ __forceinline__ int count_upto2(const PipeDim& d, int64_t key) {
+  uint32_t v = 0;
+  return probe_finish<D>(d, nullptr, key, 2, probe_first<D>(d, nullptr, key), v);
+}
+
+template <int D0, int D1>
+__global__ void __launch_bounds__(256) multi_kernel(PipelineParams p) {
+  constexpr int H0 = HbmMode<D0>::value, H1 = HbmMode<D1>::value;
+  const bool dup0 = *p.dim[0].map.dup != 0;
+  const bool dup1 = D1 != kNone && *p.dim[1].map.dup != 0;
+  if (!dup0 && !dup1) return;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  uint64_t* lg = reinterpret_cast<uint64_t*>(lds);
+  if (p.lds_slots > 0) lds_group_init(lg, p.lds_slots, p.g);
+  __syncthreads();
+  const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; r < p.n;
+       r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    if (!row_passes(p, r)) continue;
+    const int64_t fk0 = load_elem(p.fact[p.dim[0].fk_col], p.fact_type[p.dim[0].fk_col], r);
+    const int m0 = count_upto2<H0>(p.dim[0], fk0);
+    if (m0 == 0) continue;
+    int m1 = 1;
+    if constexpr (D1 != kNone) {
+      const int64_t fk1 = load_elem(p.fact[p.dim[1].fk_col], p.fact_type[p.dim[1].fk_col], r);
+      m1 = count_upto2<H1>(p.dim[1], fk1);
+      if (m1 == 0) continue;
+    }
+    if (m0 < 2 && m1 < 2) continue;  // single match: aggregated by the fused kernel
+    enumerate_row<H0, H1>(p, r, nullptr, nullptr, lg, gt);
   }
   if (p.lds_slots == 0) return;
   __syncthreads();
   lds_group_flush(lg, p.lds_slots, p.g);
+}
+
+template <int D0, int D1>
+hipError_t launch_multi(const PipelineParams& p, hipStream_t s) {
+  if constexpr (D0 == kNone) {
+    return hipSuccess;
+  } else {
+    const size_t lds = static_cast<size_t>(p.lds_slots) * p.g.words * 8;
+    int64_t blocks = (p.n + 255) / 256;
+    const int64_t limit = static_cast<int64_t>(device_info().cu_count) * 8;
+    if (blocks > limit) blocks = limit;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((multi_kernel<D0, D1>), dim3(static_cast<unsigned>(blocks)), dim3(256), lds,
+                       s, p);
+    return hipGetLastError();
+  }
 }
 
 // grid <= 0 sizes the persistent grid to the workgroups that can be resident
@@ -530,7 +803,9 @@ hipError_t launch_fused(const PipelineParams& p, int grid, hipStream_t s) {
   }
   if (grid > kMaxPipeGrid) grid = kMaxPipeGrid;
   hipLaunchKernelGGL(k, dim3(grid), dim3(kPipeThreads), p.lds_bytes, s, p);
-  return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_multi<D0, D1>(p, s);
 }
 
 }  // namespace pipe
