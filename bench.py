@@ -96,13 +96,104 @@ def cpu_baseline(d: dict, n_fact: int, target_s: float) -> dict:
         oracle.pipeline(fact, TERMS, dims, KEYS, AGGS)
         return time.perf_counter() - t0
 
+    # two short runs separate the fixed cost (building the dim maps) from
+    # the per-row cost, so that the sample lands near target_s
     probe = min(n_fact, 2_000_000)
-    t = run(probe)
-    s = int(min(n_fact, max(probe, probe * target_s / max(t, 1e-6))))
-    t = run(s) if s != probe else t
+    t1 = run(probe)
+    t2 = run(min(n_fact, 2 * probe)) if n_fact > probe else t1
+    per_row = max((t2 - t1) / probe, 1e-9) if n_fact > probe else t1 / max(probe, 1)
+    fixed = max(t1 - per_row * probe, 0.0)
+    s = int(min(n_fact, max(probe, (target_s - fixed) / per_row)))
+    t = run(s) if s != probe else t1
     return {"value": s / t, "unit": "rows/s", "cores": 1, "kind": "oracle",
             "sample": f"first {s} of {n_fact} fact rows of the same star schema, same plan, "
                       f"{t:.1f} s on one core of {cpu_model()} ({os.cpu_count()} cores visible)"}
+
+
+def bench_batch(args, torch, datagen, rel) -> dict:
+    """256 join + group-by instances of log-uniform sizes (build 1k-4M rows,
+    probe 10k-50M rows, 8-100k groups; SUM(value), COUNT(*) by the build
+    side's group attribute): one rel_pipeline_batch launch sequence, its
+    captured graph, and 256 sequential rel_pipeline calls, on the same
+    resident inputs. Results must be identical."""
+    seed = datagen.SEED0 + 4
+    shapes = datagen.batch_shapes(seed=seed, n_inst=args.batch_instances)
+    aggs = [("sum", 1), ("count", None)]
+    t0 = time.perf_counter()
+    singles, plans = [], []
+    n_probe = n_build = 0
+    for i, s in enumerate(shapes):
+        d = datagen.batch_instance(seed, i, **s)
+        fact = [torch.from_numpy(d["probe_key"]).cuda(), torch.from_numpy(d["probe_val"]).cuda()]
+        dims = [dict(fk=0, key=torch.from_numpy(d["build_key"]).cuda(),
+                     payload=torch.from_numpy(d["build_grp"]).cuda())]
+        mg = max(1, s["n_groups"])
+        singles.append(rel.PreparedPipeline(fact, [], dims, [("dim", 0)], aggs, mg))
+        plans.append(rel.Plan(fact, [], dims, [("dim", 0)], aggs, mg))
+        n_probe += s["n_probe"]
+        n_build += s["n_build"]
+    batch = rel.PreparedBatch(plans)
+    torch.cuda.synchronize()
+    log(f"batch: {len(shapes)} instances, {n_build} build rows, {n_probe} probe rows "
+        f"ready in {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, steps):
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(steps):
+            fn()
+        stop.record(stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / steps
+
+    def sequential():
+        for p in singles:
+            p.launch()
+
+    steps = args.batch_steps
+    sequential()
+    batch.launch()
+    torch.cuda.synchronize()
+    seq_ms = timed(sequential, steps)
+    batch_ms = timed(batch.launch, steps)
+    rel.profile_read()
+    rel.profile_enable(True)
+    batch.launch()
+    torch.cuda.synchronize()
+    rel.profile_enable(False)
+    prof = rel.profile_read()
+    batch.capture()
+    batch.launch_graph()
+    graph_ms = timed(batch.launch_graph, steps)
+    # identical results: every instance of the graph replay against its
+    # sequential call
+    identical = True
+    for a, b in zip(singles, plans):
+        ka, aa = a.result()
+        kb, ab = b.result()
+        oa, ob = torch.argsort(ka[0]), torch.argsort(kb[0])
+        if not (torch.equal(ka[0][oa], kb[0][ob]) and
+                all(torch.equal(x[oa], y[ob]) for x, y in zip(aa, ab))):
+            identical = False
+    batch.release()
+    fused_ms, fused_n = prof["pipeline_fused"]
+    alg = 12 * n_probe + 8 * n_build
+    best = min(batch_ms, graph_ms)
+    return {
+        "workload": f"{len(shapes)} join+group-by instances, log-uniform build 1k-4M, "
+                    f"probe 10k-50M, groups 8-100k",
+        "instances": len(shapes), "probe_rows": n_probe, "build_rows": n_build,
+        "sequential_ms": seq_ms, "batched_ms": batch_ms, "graph_ms": graph_ms,
+        "sequential_rows_per_s": n_probe / (seq_ms * 1e-3),
+        "batched_rows_per_s": n_probe / (best * 1e-3),
+        "speedup_vs_sequential": seq_ms / best,
+        "identical_results": identical,
+        "algorithmic_bytes": alg, "hbm_frac_step": alg / (best * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "fused_kernel_ms": fused_ms / max(1, fused_n),
+        "breakdown_ms": {k: round(v[0], 4) for k, v in prof.items() if v[1]},
+    }
 
 
 def main() -> int:
@@ -114,6 +205,10 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances section")
+    ap.add_argument("--batch-only", action="store_true")
+    ap.add_argument("--batch-instances", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -139,6 +234,9 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 4, "launches": 3}), flush=True)
+        return 0
+    if args.batch_only:
+        print(json.dumps({"batch": bench_batch(args, torch, datagen, rel)}), flush=True)
         return 0
     seed = datagen.SEED0 + 2 if args.seed is None else args.seed
     n = args.n_fact
@@ -210,6 +308,12 @@ def main() -> int:
     if not args.no_cpu_baseline:
         host = {k: v for k, v in d.items()}
         out["cpu_baseline"] = cpu_baseline(host, n, args.cpu_seconds)
+        del host
+    if not args.no_batch:
+        del plan, fact, dims, dev, d, keys, aggs
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out["batch"] = bench_batch(args, torch, datagen, rel)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -109,7 +109,9 @@ typedef struct {
   int32_t flags;     /* reserved, must be 0 */
   int32_t dim_lds_bytes; /* LDS bytes rel_pipeline may give to dim tables; 0 = default (32 KB),
                             -1 = none */
-  int32_t reserved[2];
+  int32_t chunk_tiles;   /* rel_pipeline_batch: fact tiles (2048 rows) per work item of the
+                            fused pass; 0 = default (from the batch's total size, at most 8) */
+  int32_t reserved;
 } rel_tuning;
 
 #define REL_MAX_TERMS 4
@@ -255,6 +257,57 @@ size_t rel_pipeline_ws(const rel_pipeline_desc* d);
  * 64 bits, int64 dim payloads). */
 rel_status rel_pipeline(const rel_pipeline_desc* d, const rel_outputs* o, void* ws,
                         size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------- batches */
+
+/* Workspace bytes for rel_pipeline_batch over the n plans d[0..n-1]
+ * (0 if the plans are invalid or differ in shape). */
+size_t rel_pipeline_batch_ws(const rel_pipeline_desc* d, int n);
+
+/* Batch execution (Section 5 names it as future work for the many small
+ * queries that leave a GPU underused): n independent plans, each with the
+ * semantics of rel_pipeline and its own inputs and outputs o[i], run with
+ * one launch per phase rather than n sequences of launches. Every phase
+ * splits each plan into work items (build rows, runs of 2048-row fact tiles,
+ * group slots); the fused pass is a persistent kernel whose workgroups take
+ * the items of all plans in order from a device counter, so that one large
+ * plan is spread over the chip and many small ones share it. Results are
+ * identical to n rel_pipeline calls.
+ *   d, n     1..65536 plans of one shape: the same number of dims, and for
+ *            each dim the same key type and payload presence. Per-plan
+ *            tuning (load factor, LDS group slots) is honoured; grid and
+ *            chunk_tiles come from d[0].tuning. Dim tables are always read
+ *            from HBM (no LDS copies, no compact sets).
+ *   o        n outputs, as for rel_pipeline.
+ *   ws       rel_pipeline_batch_ws(d, n) bytes.
+ * The call builds the plans' kernel parameters and work lists on the host
+ * and uploads them in one stream-ordered copy from a pinned staging buffer
+ * that the library keeps per calling thread (host memory, allocated on
+ * first use and grown as needed, never freed before the process ends).
+ * Errors: as rel_pipeline, naming the failing plan; REL_EINVAL when plans
+ * differ in shape. */
+rel_status rel_pipeline_batch(const rel_pipeline_desc* d, int n, const rel_outputs* o, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* A batch captured once as a HIP graph (descriptor upload from pinned host
+ * memory owned by the graph, then the six launches), for replay with one
+ * hipGraphLaunch. Inputs, outputs and ws are bound at capture: they must
+ * stay allocated, and their contents at each launch are the inputs. */
+typedef struct rel_graph rel_graph;
+
+/* Captures rel_pipeline_batch(d, n, o, ws, ws_bytes) into *out. Nothing is
+ * executed. Errors: as rel_pipeline_batch; REL_EDEVICE if capture or
+ * instantiation fails (nothing is then kept). */
+rel_status rel_pipeline_batch_graph(const rel_pipeline_desc* d, int n, const rel_outputs* o,
+                                    void* ws, size_t ws_bytes, rel_graph** out);
+
+/* Enqueues one replay of g on `stream`. Replays that may overlap in time
+ * race on the bound workspace and outputs. */
+rel_status rel_graph_launch(rel_graph* g, void* stream);
+
+/* Releases g (NULL is ignored); the caller makes sure no replay is still
+ * running. */
+void rel_graph_destroy(rel_graph* g);
 
 /* ------------------------------------------------------------- profiling */
 

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(PKG, "librel.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "profile.cpp", "filter.hip", "join.hip", "groupby.hip", "pipeline.hip"]
+SOURCES = ["api.cpp", "profile.cpp", "filter.hip", "join.hip", "groupby.hip", "pipeline.hip",
+           "pipeline_batch.hip"]
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -30,10 +31,12 @@ HIP_FLAGS = [
 ]
 
 
-# The fused pipeline kernel is instantiated per first-dim access mode in
-# separate objects (see pipeline.hip) so that the variants compile in parallel.
+# The fused pipeline kernels are instantiated per first-dim access mode in
+# separate objects (see pipeline.hip, pipeline_batch.hip) so that the variants
+# compile in parallel.
 UNITS = [(s, s.replace(".hip", "").replace(".cpp", ""), []) for s in SOURCES] + [
-    ("pipeline.hip", f"pipeline_d{m}", [f"-DREL_PIPE_D0={m}"]) for m in range(1, 7)]
+    ("pipeline.hip", f"pipeline_d{m}", [f"-DREL_PIPE_D0={m}"]) for m in range(1, 7)] + [
+    ("pipeline_batch.hip", f"pipeline_batch_d{m}", [f"-DREL_BATCH_D0={m}"]) for m in (0, 1, 3, 5)]
 
 
 def _compile(unit) -> str:

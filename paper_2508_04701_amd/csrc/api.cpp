@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 #include "rel.h"
@@ -63,6 +64,7 @@ rel_status check_tuning(const rel_tuning* t) {
   if (t->lds_slots < -1 || (t->lds_slots > 0 && (t->lds_slots & (t->lds_slots - 1)) != 0))
     return fail(REL_EINVAL, "tuning.lds_slots must be -1, 0 or a power of two");
   if (t->flags != 0) return fail(REL_EINVAL, "tuning.flags must be 0");
+  if (t->chunk_tiles < 0) return fail(REL_EINVAL, "tuning.chunk_tiles must be >= 0");
   return REL_OK;
 }
 
@@ -387,14 +389,18 @@ rel_status check_pipeline(const rel_pipeline_desc* d) {
   return check_tuning(d->tuning);
 }
 
-rel_status pipeline_layout(const rel_pipeline_desc* d, PipeLayout& L) {
+// Workspace layout of plan d from byte offset `base`. Batched plans keep
+// every dim in plain slot arrays (no compact sets), so that all instances of
+// a shape share one kernel variant.
+rel_status pipeline_layout(const rel_pipeline_desc* d, PipeLayout& L, bool batch = false,
+                           size_t base = 0) {
   const float lf = load_factor(d->tuning);
-  size_t off = 0;
+  size_t off = base;
   for (int i = 0; i < d->n_dims; ++i) {
     // membership-only int32 dims keep keys alone (4-byte slots)
     const bool key_only = d->dims[i].key.type == REL_I32 && !d->dims[i].has_payload;
     L.dim[i] = map_layout(d->dims[i].key.type, d->dims[i].key.len, lf < 0.75f ? 0.75f : lf, off,
-                          key_only, true);
+                          key_only, !batch);
     off = L.dim[i].end;
   }
   for (int k = 0; k < d->n_keys; ++k) {
@@ -407,6 +413,397 @@ rel_status pipeline_layout(const rel_pipeline_desc* d, PipeLayout& L) {
   const bool few = L.lds_slots > 0 && 2 * d->max_groups <= L.lds_slots;
   L.group = group_layout(L.gp, d->max_groups, lf, off, few ? kGroupReplicas : 1);
   L.end = L.group.end;
+  return REL_OK;
+}
+
+// Kernel parameters of plan d (layout L) over workspace w, and the builds of
+// its dims. Batched plans keep every dim in HBM.
+void plan_params(const rel_pipeline_desc* d, const PipeLayout& L, unsigned char* w,
+                 int64_t* d_groups, bool batch, PipelineParams& p,
+                 MapBuildParams b[REL_MAX_DIMS]) {
+  const DeviceInfo& di = device_info();
+  const rel_tuning* t = d->tuning;
+  std::memset(&p, 0, sizeof p);
+  const int64_t n = d->fact[0].len;
+  for (int c = 0; c < d->n_fact; ++c) {
+    p.fact[c] = d->fact[c].data;
+    p.fact_type[c] = d->fact[c].type;
+    p.fact_vec[c] = (reinterpret_cast<uintptr_t>(d->fact[c].data) % 16) == 0;
+  }
+  p.n = n;
+  p.nterms = d->n_preds;
+  for (int i = 0; i < d->n_preds; ++i) {
+    p.term_col[i] = d->preds[i].col;
+    p.term_op[i] = d->preds[i].op;
+    p.term_lo[i] = d->preds[i].lo;
+    p.term_hi[i] = d->preds[i].hi;
+  }
+  p.g = group_desc(L.gp, L.group, w, d_groups);
+  for (int k = 0; k < d->n_keys; ++k) {
+    p.key_src[k] = d->keys[k].src == REL_KEY_FACT ? 0 : 1 + d->keys[k].col;
+    p.key_col[k] = d->keys[k].src == REL_KEY_FACT ? d->keys[k].col : 0;
+  }
+
+  // LDS: the group table, the per-wave row queues, then dim tables that fit
+  // (smaller dims first).
+  const size_t budget = static_cast<size_t>(di.lds_per_block);
+  p.lds_slots = L.lds_slots;
+  size_t lds = 0;
+  p.lds_group_offset = 0;
+  lds += static_cast<size_t>(p.lds_slots) * L.gp.words * 8;
+  lds = (lds + 15) / 16 * 16;
+  {
+    // queued row fields: width 8 for int64 columns, else 4
+    bool present[kQueueFields] = {};
+    bool wide[kQueueFields] = {};
+    present[kQRow] = true;
+    for (int i = 0; i < d->n_dims; ++i) {
+      present[kQFk0 + i] = true;
+      wide[kQFk0 + i] = d->dims[i].key.type == REL_I64;
+      present[kQSt0 + i] = true;
+    }
+    // The first two distinct value columns are gathered with the probes.
+    int early[2] = {-1, -1};
+    for (int a = 0; a < L.gp.ap.nacc; ++a) {
+      const int c = L.gp.ap.col[a];
+      p.acc_col[a] = c;
+      p.acc_src[a] = -1;
+      for (int k = 0; k < 2; ++k) {
+        if (early[k] == c || early[k] < 0) {
+          early[k] = c;
+          p.acc_src[a] = k;
+          break;
+        }
+      }
+    }
+    for (int k = 0; k < 2; ++k) p.early_col[k] = early[k];
+    uint32_t stride = 0;
+    for (int f = 0; f < kQueueFields; ++f) {
+      p.field_offset[f] = stride;
+      p.field_wide[f] = wide[f] ? 1 : 0;
+      if (present[f]) stride += kPipeQueue * (wide[f] ? 8 : 4);
+    }
+    p.queue_offset = static_cast<uint32_t>(lds);
+    p.queue_stride = stride;
+    lds += static_cast<size_t>(kPipeThreads / kWave) * stride;
+  }
+  // Dim tables go to LDS only when small: a large LDS copy costs resident
+  // workgroups, and occupancy is what hides the probe latency.
+  const size_t avail = budget > lds ? budget - lds : 0;
+  size_t dim_budget = kDimLdsDefault;
+  if (t && t->dim_lds_bytes > 0) dim_budget = static_cast<size_t>(t->dim_lds_bytes);
+  if (t && t->dim_lds_bytes < 0) dim_budget = 0;
+  if (dim_budget > avail) dim_budget = avail;
+  p.ndims = d->n_dims;
+  int order[REL_MAX_DIMS] = {0, 1};
+  if (d->n_dims == 2 && L.dim[1].cap * L.dim[1].slot_bytes < L.dim[0].cap * L.dim[0].slot_bytes) {
+    order[0] = 1;
+    order[1] = 0;
+  }
+  size_t dim_used = 0;
+  for (int oi = 0; oi < d->n_dims; ++oi) {
+    const int i = order[oi];
+    const rel_dim& dm = d->dims[i];
+    p.dim[i].map = map_desc(L.dim[i], dm.key.type, w);
+    p.dim[i].fk_col = dm.fact_col;
+    const size_t bytes = L.dim[i].cap * L.dim[i].slot_bytes;
+    if (!batch && dm.key.type == REL_I32 && !L.dim[i].compact && dim_used + bytes <= dim_budget) {
+      p.dim[i].in_lds = 1;
+      p.dim[i].lds_offset = static_cast<uint32_t>(lds);
+      lds += bytes;
+      dim_used += bytes;
+    }
+  }
+  p.lds_bytes = static_cast<uint32_t>(lds);
+  p.ntiles = n > 0 ? (n + kPipeTile - 1) / kPipeTile : 0;
+  for (int i = 0; i < d->n_dims; ++i) {
+    const rel_dim& dm = d->dims[i];
+    std::memset(&b[i], 0, sizeof b[i]);
+    b[i].map = p.dim[i].map;
+    b[i].keys = dm.key.data;
+    b[i].type = dm.key.type;
+    b[i].n = dm.key.len;
+    if (dm.has_payload) {
+      b[i].val_col = dm.payload.data;
+      b[i].val_type = dm.payload.type;
+    }
+  }
+}
+
+// ------------------------------------------------------------ batch layout
+
+// Units per work item of the batched phases.
+constexpr uint64_t kFillChunk = 32768;   // words
+constexpr uint64_t kBuildChunk = 8192;   // build rows
+constexpr uint64_t kSlotChunk = 16384;   // group slots (a multiple of the block size)
+constexpr int kMaxChunkTiles = 8;
+constexpr int kMaxBatch = 1 << 16;
+
+uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Words of a dim's slot array.
+uint64_t map_words(const MapLayout& m, int32_t key_type) {
+  if (key_type == REL_I64) return 2 * m.cap;
+  return m.slot_bytes == 4 ? m.cap / 2 : m.cap;
+}
+
+// The workspace of a batch: first a block uploaded from the host in one
+// copy (the fused-pass counter, then the per-instance kernel parameters and
+// the work-item lists), then each instance's dim and group tables.
+struct BatchLayout {
+  std::vector<PipeLayout> L;
+  std::vector<size_t> base;
+  size_t off_plans, off_builds, off_fins, off_fill, off_build_items, off_tile_items;
+  size_t off_merge_items, off_fin_items, blob;
+  uint64_t nfill, nbuild, ntile, nmerge, nfin;
+  int chunk_tiles;
+  size_t end;
+};
+
+// Instances of one batch must share the kernel variant: the same number of
+// dims, and per dim the same key type and payload presence.
+rel_status check_batch(const rel_pipeline_desc* d, int n) {
+  if (n < 1 || n > kMaxBatch) return fail(REL_EINVAL, "batch: 1..%d plans required", kMaxBatch);
+  if (!d) return fail(REL_EINVAL, "batch: NULL descriptions");
+  for (int i = 0; i < n; ++i) {
+    rel_status st = check_pipeline(&d[i]);
+    if (st) return fail(st, "batch plan %d: %s", i, g_error.c_str());
+    if (d[i].n_dims != d[0].n_dims)
+      return fail(REL_EINVAL, "batch plan %d joins %d dims, plan 0 joins %d", i, d[i].n_dims,
+                  d[0].n_dims);
+    for (int k = 0; k < d[0].n_dims; ++k) {
+      if (d[i].dims[k].key.type != d[0].dims[k].key.type ||
+          (d[i].dims[k].has_payload != 0) != (d[0].dims[k].has_payload != 0))
+        return fail(REL_EINVAL, "batch plan %d: dim %d differs in key type or payload from plan 0",
+                    i, k);
+    }
+  }
+  return REL_OK;
+}
+
+rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
+  B.L.resize(n);
+  B.base.resize(n);
+  B.nfill = B.nbuild = B.ntile = B.nmerge = B.nfin = 0;
+  uint64_t tiles = 0;
+  for (int i = 0; i < n; ++i) tiles += ceil_div(static_cast<uint64_t>(d[i].fact[0].len), kPipeTile);
+  const rel_tuning* t0 = d[0].tuning;
+  if (t0 && t0->chunk_tiles > 0) {
+    B.chunk_tiles = t0->chunk_tiles;
+  } else {
+    // about eight items per resident workgroup, at most kMaxChunkTiles tiles each
+    const uint64_t want = static_cast<uint64_t>(device_info().cu_count) * 4 * 8;
+    uint64_t c = tiles / (want ? want : 1);
+    B.chunk_tiles = static_cast<int>(c < 1 ? 1 : (c > kMaxChunkTiles ? kMaxChunkTiles : c));
+  }
+  // instance tables after the uploaded block, whose size depends on the item
+  // counts: lay the tables out from 0 first, count, then shift
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    rel_status st = pipeline_layout(&d[i], B.L[i], true, off);
+    if (st) return fail(st, "batch plan %d: %s", i, g_error.c_str());
+    B.base[i] = off;
+    off = B.L[i].end;
+    for (int k = 0; k < d[i].n_dims; ++k) {
+      B.nfill += ceil_div(map_words(B.L[i].dim[k], d[i].dims[k].key.type), kFillChunk) + 1;
+      B.nbuild += ceil_div(static_cast<uint64_t>(d[i].dims[k].key.len), kBuildChunk);
+    }
+    const GroupLayout& g = B.L[i].group;
+    B.nfill += ceil_div(g.replicas * (g.cap + 1) * B.L[i].gp.words, kFillChunk) + 2;
+    B.ntile += ceil_div(ceil_div(static_cast<uint64_t>(d[i].fact[0].len), kPipeTile),
+                        B.chunk_tiles);
+    if (g.replicas > 1) B.nmerge += ceil_div((g.replicas - 1) * (g.cap + 1), kSlotChunk);
+    B.nfin += ceil_div(d[i].n_keys == 0 ? 1 : g.cap + 1, kSlotChunk);
+  }
+  const uint64_t most = 0xFFFFFFFFull;
+  if (B.nfill > most || B.nbuild > most || B.ntile > most || B.nmerge > most || B.nfin > most)
+    return fail(REL_EUNSUPPORTED, "batch: more than 2^32 - 1 work items in a phase");
+  size_t h = kAlign;  // the counter
+  B.off_plans = h;
+  h = align_up(h + n * sizeof(PipelineParams));
+  B.off_builds = h;
+  h = align_up(h + 2 * n * sizeof(MapBuildParams));
+  B.off_fins = h;
+  h = align_up(h + n * sizeof(FinalizeParams));
+  B.off_fill = h;
+  h = align_up(h + B.nfill * sizeof(FillItem));
+  B.off_build_items = h;
+  h = align_up(h + B.nbuild * sizeof(BatchItem));
+  B.off_tile_items = h;
+  h = align_up(h + B.ntile * sizeof(BatchItem));
+  B.off_merge_items = h;
+  h = align_up(h + B.nmerge * sizeof(BatchItem));
+  B.off_fin_items = h;
+  h = align_up(h + B.nfin * sizeof(BatchItem));
+  B.blob = h;
+  for (int i = 0; i < n; ++i) {
+    rel_status st = pipeline_layout(&d[i], B.L[i], true, B.blob + B.base[i]);
+    if (st) return st;
+    B.base[i] += B.blob;
+  }
+  B.end = B.blob + off;
+  return REL_OK;
+}
+
+void push_fill(std::vector<FillItem>& v, uint64_t* p, uint64_t words, int32_t kind,
+               uint64_t pattern, uint32_t inst) {
+  for (uint64_t b = 0; b < words; b += kFillChunk) {
+    FillItem f;
+    f.p = p;
+    f.begin = b;
+    f.end = b + kFillChunk < words ? b + kFillChunk : words;
+    f.pattern = pattern;
+    f.kind = kind;
+    f.inst = inst;
+    v.push_back(f);
+  }
+}
+
+void push_items(std::vector<BatchItem>& v, uint32_t inst, uint32_t aux, uint64_t units,
+                uint64_t chunk) {
+  for (uint64_t b = 0; b < units; b += chunk) {
+    BatchItem it;
+    it.inst = inst;
+    it.aux = aux;
+    it.begin = b;
+    it.end = b + chunk < units ? b + chunk : units;
+    v.push_back(it);
+  }
+}
+
+// Writes the uploaded block of batch B over workspace w into `host` (B.blob
+// bytes), returns instance 0's plan in `shape` and the kernel arguments.
+void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const BatchLayout& B,
+                unsigned char* w, unsigned char* host, PipelineParams& shape, BatchParams& bp) {
+  std::memset(host, 0, B.blob);
+  PipelineParams* plans = reinterpret_cast<PipelineParams*>(host + B.off_plans);
+  MapBuildParams* builds = reinterpret_cast<MapBuildParams*>(host + B.off_builds);
+  FinalizeParams* fins = reinterpret_cast<FinalizeParams*>(host + B.off_fins);
+  std::vector<FillItem> fill;
+  std::vector<BatchItem> build_items, tile_items, merge_items, fin_items;
+  fill.reserve(B.nfill);
+  build_items.reserve(B.nbuild);
+  tile_items.reserve(B.ntile);
+  merge_items.reserve(B.nmerge);
+  fin_items.reserve(B.nfin);
+  uint32_t group_lds = 0;
+  for (int i = 0; i < n; ++i) {
+    const PipeLayout& L = B.L[i];
+    PipelineParams& p = plans[i];
+    plan_params(&d[i], L, w, o[i].d_groups, true, p, &builds[2 * i]);
+    const uint32_t gl = static_cast<uint32_t>((static_cast<size_t>(p.lds_slots) * L.gp.words * 8 + 15) / 16 * 16);
+    if (gl > group_lds) group_lds = gl;
+    fins[i] = finalize_params(p.g, L.gp, d[i].aggs, d[i].n_aggs, o[i].keys, L.key_types, o[i].aggs,
+                              o[i].cap);
+    for (int k = 0; k < d[i].n_dims; ++k) {
+      const MapDesc& m = p.dim[k].map;
+      const uint64_t words = map_words(L.dim[k], d[i].dims[k].key.type);
+      if (d[i].dims[k].key.type == REL_I64)
+        push_fill(fill, static_cast<uint64_t*>(m.slots), words, kFillPairs, 0, i);
+      else if (m.key_only)
+        push_fill(fill, static_cast<uint64_t*>(m.slots), words, kFillConst, 0x8000000080000000ULL, i);
+      else
+        push_fill(fill, static_cast<uint64_t*>(m.slots), words, kFillConst, kEmptySlot32, i);
+      // the out-of-band count and the duplicate flag
+      push_fill(fill, reinterpret_cast<uint64_t*>(m.oob_count), 2, kFillConst, 0, i);
+      push_items(build_items, i, k, static_cast<uint64_t>(d[i].dims[k].key.len), kBuildChunk);
+    }
+    const GroupDesc& g = p.g;
+    push_fill(fill, g.slots, g.replicas * (g.cap + 1) * g.words, kFillGroup, 0, i);
+    push_fill(fill, reinterpret_cast<uint64_t*>(g.overflow), 1, kFillConst, 0, i);
+    push_fill(fill, reinterpret_cast<uint64_t*>(g.d_groups), 1, kFillConst, 0, i);
+    push_items(tile_items, i, 0, static_cast<uint64_t>(p.ntiles), B.chunk_tiles);
+    if (g.replicas > 1) push_items(merge_items, i, 0, (g.replicas - 1) * (g.cap + 1), kSlotChunk);
+    push_items(fin_items, i, 0, d[i].n_keys == 0 ? 1 : g.cap + 1, kSlotChunk);
+  }
+  // one LDS layout for every instance: the largest group table, then the queues
+  for (int i = 0; i < n; ++i) {
+    plans[i].lds_group_offset = 0;
+    plans[i].queue_offset = group_lds;
+    plans[i].lds_bytes = group_lds + (kPipeThreads / kWave) * plans[i].queue_stride;
+  }
+  std::memcpy(host + B.off_fill, fill.data(), fill.size() * sizeof(FillItem));
+  std::memcpy(host + B.off_build_items, build_items.data(), build_items.size() * sizeof(BatchItem));
+  std::memcpy(host + B.off_tile_items, tile_items.data(), tile_items.size() * sizeof(BatchItem));
+  std::memcpy(host + B.off_merge_items, merge_items.data(), merge_items.size() * sizeof(BatchItem));
+  std::memcpy(host + B.off_fin_items, fin_items.data(), fin_items.size() * sizeof(BatchItem));
+  shape = plans[0];
+  std::memset(&bp, 0, sizeof bp);
+  bp.plans = reinterpret_cast<const PipelineParams*>(w + B.off_plans);
+  bp.builds = reinterpret_cast<const MapBuildParams*>(w + B.off_builds);
+  bp.fins = reinterpret_cast<const FinalizeParams*>(w + B.off_fins);
+  bp.fill = reinterpret_cast<const FillItem*>(w + B.off_fill);
+  bp.build_items = reinterpret_cast<const BatchItem*>(w + B.off_build_items);
+  bp.tile_items = reinterpret_cast<const BatchItem*>(w + B.off_tile_items);
+  bp.merge_items = reinterpret_cast<const BatchItem*>(w + B.off_merge_items);
+  bp.fin_items = reinterpret_cast<const BatchItem*>(w + B.off_fin_items);
+  bp.nfill = static_cast<uint32_t>(fill.size());
+  bp.nbuild = static_cast<uint32_t>(build_items.size());
+  bp.ntile = static_cast<uint32_t>(tile_items.size());
+  bp.nmerge = static_cast<uint32_t>(merge_items.size());
+  bp.nfin = static_cast<uint32_t>(fin_items.size());
+  bp.lds_bytes = plans[0].lds_bytes;
+  bp.group_lds_bytes = group_lds;
+  bp.counter = reinterpret_cast<unsigned long long*>(w);
+}
+
+// Enqueues the upload of the block at `host` and the six batch launches.
+rel_status batch_enqueue(const BatchLayout& B, const BatchParams& bp, const PipelineParams& shape,
+                         unsigned char* w, const void* host, int grid, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(w, host, B.blob, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return fail(REL_EDEVICE, "batch: descriptor upload: %s", hipGetErrorString(e));
+  launch_batch_fill(bp, s);
+  launch_batch_build(bp, s);
+  e = launch_batch_pipeline(bp, shape, grid, s);
+  if (e != hipSuccess)
+    return fail(REL_EDEVICE, "batch: fused kernel launch (%u bytes of LDS): %s", bp.lds_bytes,
+                hipGetErrorString(e));
+  launch_batch_merge(bp, s);
+  launch_batch_finalize(bp, s);
+  return after_launch(s, "batch");
+}
+
+// Pinned host staging for the batch uploads: a small ring per thread; a
+// slot is written again only once the copy that read it has completed. The
+// buffers live until the process ends.
+struct StagingSlot {
+  void* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+constexpr int kStagingSlots = 4;
+thread_local StagingSlot g_staging[kStagingSlots];
+thread_local int g_staging_next = 0;
+
+rel_status staging_take(size_t bytes, StagingSlot*& out) {
+  StagingSlot& sl = g_staging[g_staging_next];
+  g_staging_next = (g_staging_next + 1) % kStagingSlots;
+  if (sl.pending) {
+    const hipError_t e = hipEventSynchronize(sl.done);
+    if (e != hipSuccess) return fail(REL_EDEVICE, "batch: staging wait: %s", hipGetErrorString(e));
+    sl.pending = false;
+  }
+  if (!sl.done) {
+    const hipError_t e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      sl.done = nullptr;
+      return fail(REL_EDEVICE, "batch: staging event: %s", hipGetErrorString(e));
+    }
+  }
+  if (sl.cap < bytes) {
+    if (sl.host) (void)hipHostFree(sl.host);
+    sl.host = nullptr;
+    sl.cap = 0;
+    const size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+    const hipError_t e = hipHostMalloc(&sl.host, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      sl.host = nullptr;
+      return fail(REL_EDEVICE, "batch: %zu bytes of pinned staging: %s", want, hipGetErrorString(e));
+    }
+    sl.cap = want;
+  }
+  out = &sl;
   return REL_OK;
 }
 
@@ -685,118 +1082,13 @@ rel_status rel_pipeline(const rel_pipeline_desc* d, const rel_outputs* o, void* 
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   unsigned char* w = static_cast<unsigned char*>(ws);
-  const DeviceInfo& di = device_info();
   const rel_tuning* t = d->tuning;
-
   PipelineParams p;
-  std::memset(&p, 0, sizeof p);
-  const int64_t n = d->fact[0].len;
-  for (int c = 0; c < d->n_fact; ++c) {
-    p.fact[c] = d->fact[c].data;
-    p.fact_type[c] = d->fact[c].type;
-    p.fact_vec[c] = (reinterpret_cast<uintptr_t>(d->fact[c].data) % 16) == 0;
-  }
-  p.n = n;
-  p.nterms = d->n_preds;
-  for (int i = 0; i < d->n_preds; ++i) {
-    p.term_col[i] = d->preds[i].col;
-    p.term_op[i] = d->preds[i].op;
-    p.term_lo[i] = d->preds[i].lo;
-    p.term_hi[i] = d->preds[i].hi;
-  }
-  p.g = group_desc(L.gp, L.group, w, o->d_groups);
-  for (int k = 0; k < d->n_keys; ++k) {
-    p.key_src[k] = d->keys[k].src == REL_KEY_FACT ? 0 : 1 + d->keys[k].col;
-    p.key_col[k] = d->keys[k].src == REL_KEY_FACT ? d->keys[k].col : 0;
-  }
-
-  // LDS: the group table, the per-wave row queues, then dim tables that fit
-  // (smaller dims first).
-  const size_t budget = static_cast<size_t>(di.lds_per_block);
-  p.lds_slots = L.lds_slots;
-  size_t lds = 0;
-  p.lds_group_offset = 0;
-  lds += static_cast<size_t>(p.lds_slots) * L.gp.words * 8;
-  lds = (lds + 15) / 16 * 16;
-  {
-    // queued row fields: width 8 for int64 columns, else 4
-    bool present[kQueueFields] = {};
-    bool wide[kQueueFields] = {};
-    present[kQRow] = true;
-    for (int i = 0; i < d->n_dims; ++i) {
-      present[kQFk0 + i] = true;
-      wide[kQFk0 + i] = d->dims[i].key.type == REL_I64;
-      present[kQSt0 + i] = true;
-    }
-    // The first two distinct value columns are gathered with the probes.
-    int early[2] = {-1, -1};
-    for (int a = 0; a < L.gp.ap.nacc; ++a) {
-      const int c = L.gp.ap.col[a];
-      p.acc_col[a] = c;
-      p.acc_src[a] = -1;
-      for (int k = 0; k < 2; ++k) {
-        if (early[k] == c || early[k] < 0) {
-          early[k] = c;
-          p.acc_src[a] = k;
-          break;
-        }
-      }
-    }
-    for (int k = 0; k < 2; ++k) p.early_col[k] = early[k];
-    uint32_t stride = 0;
-    for (int f = 0; f < kQueueFields; ++f) {
-      p.field_offset[f] = stride;
-      p.field_wide[f] = wide[f] ? 1 : 0;
-      if (present[f]) stride += kPipeQueue * (wide[f] ? 8 : 4);
-    }
-    p.queue_offset = static_cast<uint32_t>(lds);
-    p.queue_stride = stride;
-    lds += static_cast<size_t>(kPipeThreads / kWave) * stride;
-  }
-  // Dim tables go to LDS only when small: a large LDS copy costs resident
-  // workgroups, and occupancy is what hides the probe latency.
-  const size_t avail = budget > lds ? budget - lds : 0;
-  size_t dim_budget = kDimLdsDefault;
-  if (t && t->dim_lds_bytes > 0) dim_budget = static_cast<size_t>(t->dim_lds_bytes);
-  if (t && t->dim_lds_bytes < 0) dim_budget = 0;
-  if (dim_budget > avail) dim_budget = avail;
-  p.ndims = d->n_dims;
-  int order[REL_MAX_DIMS] = {0, 1};
-  if (d->n_dims == 2 && L.dim[1].cap * L.dim[1].slot_bytes < L.dim[0].cap * L.dim[0].slot_bytes) {
-    order[0] = 1;
-    order[1] = 0;
-  }
-  size_t dim_used = 0;
-  for (int oi = 0; oi < d->n_dims; ++oi) {
-    const int i = order[oi];
-    const rel_dim& dm = d->dims[i];
-    p.dim[i].map = map_desc(L.dim[i], dm.key.type, w);
-    p.dim[i].fk_col = dm.fact_col;
-    const size_t bytes = L.dim[i].cap * L.dim[i].slot_bytes;
-    if (dm.key.type == REL_I32 && !L.dim[i].compact && dim_used + bytes <= dim_budget) {
-      p.dim[i].in_lds = 1;
-      p.dim[i].lds_offset = static_cast<uint32_t>(lds);
-      lds += bytes;
-      dim_used += bytes;
-    }
-  }
-  p.lds_bytes = static_cast<uint32_t>(lds);
-  p.ntiles = n > 0 ? (n + kPipeTile - 1) / kPipeTile : 0;
-
+  MapBuildParams b[REL_MAX_DIMS];
+  plan_params(d, L, w, o->d_groups, false, p, b);
   for (int i = 0; i < d->n_dims; ++i) {
-    const rel_dim& dm = d->dims[i];
     launch_map_init(p.dim[i].map, s);
-    MapBuildParams b;
-    std::memset(&b, 0, sizeof b);
-    b.map = p.dim[i].map;
-    b.keys = dm.key.data;
-    b.type = dm.key.type;
-    b.n = dm.key.len;
-    if (dm.has_payload) {
-      b.val_col = dm.payload.data;
-      b.val_type = dm.payload.type;
-    }
-    launch_map_build(b, s);
+    launch_map_build(b[i], s);
   }
   launch_group_init(p.g, s);
   if (p.ntiles > 0) {
@@ -810,6 +1102,123 @@ rel_status rel_pipeline(const rel_pipeline_desc* d, const rel_outputs* o, void* 
                                         o->aggs, o->cap),
                         s);
   return after_launch(s, "pipeline");
+}
+
+// ------------------------------------------------------------------ batches
+
+size_t rel_pipeline_batch_ws(const rel_pipeline_desc* d, int n) {
+  if (check_batch(d, n) != REL_OK) return 0;
+  BatchLayout B;
+  if (batch_layout(d, n, B) != REL_OK) return 0;
+  return B.end;
+}
+
+namespace {
+
+rel_status batch_prepare(const rel_pipeline_desc* d, int n, const rel_outputs* o, void* ws,
+                         size_t ws_bytes, BatchLayout& B) {
+  g_error.clear();
+  rel_status st = check_batch(d, n);
+  if (st) return st;
+  if (!o) return fail(REL_EINVAL, "batch: NULL outputs");
+  for (int i = 0; i < n; ++i) {
+    st = check_outputs(o[i].keys, d[i].n_keys, o[i].aggs, d[i].n_aggs, o[i].cap, o[i].d_groups);
+    if (st) return fail(st, "batch plan %d: %s", i, g_error.c_str());
+  }
+  st = batch_layout(d, n, B);
+  if (st) return st;
+  return check_ws(ws, ws_bytes, B.end);
+}
+
+int batch_grid(const rel_pipeline_desc* d) {
+  return (d[0].tuning && d[0].tuning->grid > 0) ? d[0].tuning->grid : 0;
+}
+
+}  // namespace
+
+rel_status rel_pipeline_batch(const rel_pipeline_desc* d, int n, const rel_outputs* o, void* ws,
+                              size_t ws_bytes, void* stream) {
+  BatchLayout B;
+  rel_status st = batch_prepare(d, n, o, ws, ws_bytes, B);
+  if (st) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  StagingSlot* sl = nullptr;
+  st = staging_take(B.blob, sl);
+  if (st) return st;
+  PipelineParams shape;
+  BatchParams bp;
+  batch_blob(d, n, o, B, w, static_cast<unsigned char*>(sl->host), shape, bp);
+  st = batch_enqueue(B, bp, shape, w, sl->host, batch_grid(d), s);
+  // the slot is reused once the stream is past the upload (or at once when
+  // nothing was enqueued)
+  if (hipEventRecord(sl->done, s) == hipSuccess) sl->pending = true;
+  return st;
+}
+
+struct rel_graph {
+  void* host;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+rel_status rel_pipeline_batch_graph(const rel_pipeline_desc* d, int n, const rel_outputs* o,
+                                    void* ws, size_t ws_bytes, rel_graph** out) {
+  if (!out) return fail(REL_EINVAL, "batch graph: NULL result pointer");
+  *out = nullptr;
+  BatchLayout B;
+  rel_status st = batch_prepare(d, n, o, ws, ws_bytes, B);
+  if (st) return st;
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  rel_graph* g = new rel_graph{nullptr, nullptr, nullptr};
+  hipStream_t cs = nullptr;
+  auto bail = [&](rel_status code, const char* what, hipError_t e) {
+    if (cs) (void)hipStreamDestroy(cs);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->host) (void)hipHostFree(g->host);
+    delete g;
+    return code == REL_EDEVICE ? fail(code, "batch graph: %s: %s", what, hipGetErrorString(e))
+                               : code;
+  };
+  hipError_t e = hipHostMalloc(&g->host, B.blob, hipHostMallocDefault);
+  if (e != hipSuccess) return bail(REL_EDEVICE, "pinned descriptor block", e);
+  PipelineParams shape;
+  BatchParams bp;
+  batch_blob(d, n, o, B, w, static_cast<unsigned char*>(g->host), shape, bp);
+  e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return bail(REL_EDEVICE, "capture stream", e);
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return bail(REL_EDEVICE, "begin capture", e);
+  g_capturing = true;
+  st = batch_enqueue(B, bp, shape, w, g->host, batch_grid(d), cs);
+  g_capturing = false;
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  g->graph = graph;
+  if (st) return bail(st, nullptr, hipSuccess);
+  if (e != hipSuccess) return bail(REL_EDEVICE, "end capture", e);
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return bail(REL_EDEVICE, "instantiate", e);
+  (void)hipStreamDestroy(cs);
+  *out = g;
+  return REL_OK;
+}
+
+rel_status rel_graph_launch(rel_graph* g, void* stream) {
+  g_error.clear();
+  if (!g || !g->exec) return fail(REL_EINVAL, "graph launch: NULL graph");
+  const hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(REL_EDEVICE, "graph launch: %s", hipGetErrorString(e));
+  return REL_OK;
+}
+
+void rel_graph_destroy(rel_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->host) (void)hipHostFree(g->host);
+  delete g;
 }
 
 }  // extern "C"

@@ -72,12 +72,13 @@ __global__ void __launch_bounds__(256) group_agg_kernel(GroupAggParams p) {
 }
 
 // Folds every occupied slot of replicas 1.. into replica 0.
-__global__ void __launch_bounds__(256) group_merge_kernel(GroupDesc g) {
+// Folds entries i, i + stride, ... below `end` of replicas 1.. (numbered
+// from the start of replica 1) into replica 0.
+__device__ __forceinline__ void merge_range(const GroupDesc& g, uint64_t i, uint64_t end,
+                                            uint64_t stride) {
   const uint64_t per = g.cap + 1;
-  const uint64_t total = (g.replicas - 1) * per;
   const GroupTable dst = group_replica(g, 0);
-  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < total;
-       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+  for (; i < end; i += stride) {
     const uint64_t r = 1 + i / per, slot = i % per;
     const uint64_t* s = g.slots + (r * per + slot) * g.words;
     const bool oob = slot == g.cap;
@@ -87,21 +88,25 @@ __global__ void __launch_bounds__(256) group_merge_kernel(GroupDesc g) {
   }
 }
 
-__global__ void __launch_bounds__(256) group_finalize_kernel(FinalizeParams p) {
+__global__ void __launch_bounds__(256) group_merge_kernel(GroupDesc g) {
+  merge_range(g, blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x,
+              (g.replicas - 1) * (g.cap + 1), static_cast<uint64_t>(gridDim.x) * blockDim.x);
+}
+
+// Writes the occupied slots among [base, end) (base a multiple of the wave
+// size; the workgroup steps by `stride`) to the outputs, each at a position
+// taken from the group counter with one atomic per wave.
+__device__ __forceinline__ void finalize_range(const FinalizeParams& p, uint64_t base,
+                                               uint64_t end, uint64_t stride) {
   const GroupDesc& g = p.g;
-  if (*g.overflow) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *g.d_groups = static_cast<unsigned long long>(-1LL);
-    return;
-  }
   const int lane = lane_id();
   const uint64_t nslots = g.kp.nkeys == 0 ? 1 : g.cap + 1;
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t base = blockIdx.x * static_cast<uint64_t>(blockDim.x); base < nslots;
-       base += stride) {
+  if (end > nslots) end = nslots;
+  for (; base < end; base += stride) {
     const uint64_t i = base + threadIdx.x;
     bool occ = false;
     const uint64_t* s = nullptr;
-    if (i < nslots) {
+    if (i < end) {
       s = g.slots + i * g.words;
       if (g.kp.nkeys == 0) occ = true;                 // the one ungrouped row
       else if (i < g.cap) occ = (s[0] != kEmpty64);
@@ -144,6 +149,31 @@ __global__ void __launch_bounds__(256) group_finalize_kernel(FinalizeParams p) {
   }
 }
 
+__global__ void __launch_bounds__(256) group_finalize_kernel(FinalizeParams p) {
+  if (*p.g.overflow) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p.g.d_groups = static_cast<unsigned long long>(-1LL);
+    return;
+  }
+  finalize_range(p, blockIdx.x * static_cast<uint64_t>(blockDim.x), ~0ULL,
+                 static_cast<uint64_t>(gridDim.x) * blockDim.x);
+}
+
+// One workgroup per item of the batch's merge and finalize lists.
+__global__ void __launch_bounds__(256) batch_merge_kernel(BatchParams b) {
+  const BatchItem& it = batch_at(b.merge_items, blockIdx.x);
+  merge_range(batch_at(b.plans, it.inst).g, it.begin + threadIdx.x, it.end, blockDim.x);
+}
+
+__global__ void __launch_bounds__(256) batch_finalize_kernel(BatchParams b) {
+  const BatchItem& it = batch_at(b.fin_items, blockIdx.x);
+  const FinalizeParams& p = batch_at(b.fins, it.inst);
+  if (*p.g.overflow) {
+    if (it.begin == 0 && threadIdx.x == 0) *p.g.d_groups = static_cast<unsigned long long>(-1LL);
+    return;
+  }
+  finalize_range(p, it.begin, it.end, blockDim.x);
+}
+
 }  // namespace
 
 void launch_group_init(const GroupDesc& g, hipStream_t s) {
@@ -176,6 +206,18 @@ void launch_group_finalize(const FinalizeParams& p, hipStream_t s) {
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(group_finalize_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
                      p);
+}
+
+void launch_batch_merge(const BatchParams& b, hipStream_t s) {
+  if (b.nmerge == 0) return;
+  ProfileScope ps(kKFinalize, s);
+  hipLaunchKernelGGL(batch_merge_kernel, dim3(b.nmerge), dim3(256), 0, s, b);
+}
+
+void launch_batch_finalize(const BatchParams& b, hipStream_t s) {
+  if (b.nfin == 0) return;
+  ProfileScope ps(kKFinalize, s);
+  hipLaunchKernelGGL(batch_finalize_kernel, dim3(b.nfin), dim3(256), 0, s, b);
 }
 
 }  // namespace rel

@@ -216,4 +216,75 @@ constexpr int kMaxPipeGrid = 2048;           // bound on the persistent grid
 // Returns the first failing HIP status of the launch.
 hipError_t launch_pipeline(const PipelineParams& p, int grid, hipStream_t s);
 
+// --------------------------------------------------------------- batches
+//
+// A batch runs n plans of one shape (same dim count, dim key types and
+// payload presence) with one launch per phase: fill, build, fused pass,
+// duplicate-key pass, replica merge, finalize. Each phase walks a list of
+// work items, each naming an instance and a half-open range of that phase's
+// units (words, build rows, fact tiles, group slots). The fused pass is
+// persistent and takes its items in order from a device counter; the other
+// phases run one workgroup per item, handed out in order by the dispatcher.
+// Either way a large instance is spread over the whole chip and many small
+// ones share it.
+
+// Units: tiles (fused and duplicate passes), rows (builds; aux = dim),
+// slots (merge: replica slots 1.., finalize: replica 0).
+struct BatchItem {
+  uint32_t inst;
+  uint32_t aux;
+  uint64_t begin, end;
+};
+
+enum FillKind : int32_t { kFillConst = 0, kFillPairs = 1, kFillGroup = 2 };
+
+// Words [begin, end) of the region at p: the constant `pattern`, key/value
+// pairs (kEmpty64, 0) of an int64 map, or the empty slots of instance
+// `inst`'s group table (key kEmpty64, COUNT 0, accumulator identities).
+struct FillItem {
+  uint64_t* p;
+  uint64_t begin, end;
+  uint64_t pattern;
+  int32_t kind;
+  uint32_t inst;
+};
+
+// Device arrays (read-only during the batch) and item lists of one batch.
+struct BatchParams {
+  const PipelineParams* plans;   // n
+  const MapBuildParams* builds;  // 2n: dim d of instance i at 2i + d
+  const FinalizeParams* fins;    // n
+  const FillItem* fill;
+  const BatchItem* build_items;
+  const BatchItem* tile_items;
+  const BatchItem* merge_items;
+  const BatchItem* fin_items;
+  uint32_t nfill, nbuild, ntile, nmerge, nfin;
+  uint32_t lds_bytes;        // dynamic LDS of the fused pass (same for every plan)
+  uint32_t group_lds_bytes;  // LDS group table bytes of the largest plan
+  unsigned long long* counter;  // fused-pass item counter, zero at the start
+};
+
+// Reference to element i of a batch array: read through the constant address
+// space, so that uniform reads become scalar loads hoisted out of the loops.
+template <typename T>
+__device__ __forceinline__ const T& batch_at(const T* base, uint64_t i) {
+  typedef const __attribute__((address_space(4))) T ConstT;
+  return *(const T*)((ConstT*)base + i);
+}
+
+void launch_batch_fill(const BatchParams& b, hipStream_t s);
+void launch_batch_build(const BatchParams& b, hipStream_t s);
+// Fused and duplicate-key passes; `shape` is any instance's plan (host copy),
+// whose dims select the kernel variant (dims stay in HBM). grid <= 0 sizes
+// the persistent grid by occupancy. Returns the first failing HIP status.
+hipError_t launch_batch_pipeline(const BatchParams& b, const PipelineParams& shape, int grid,
+                                 hipStream_t s);
+void launch_batch_merge(const BatchParams& b, hipStream_t s);
+void launch_batch_finalize(const BatchParams& b, hipStream_t s);
+
+// Set while a batch is being captured into a graph: profiling events are
+// then not recorded.
+extern thread_local bool g_capturing;
+
 }  // namespace rel

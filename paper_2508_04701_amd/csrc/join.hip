@@ -34,11 +34,11 @@ __device__ __forceinline__ uint32_t element_value(const MapBuildParams& p, int64
   return p.idx ? p.idx[i] : static_cast<uint32_t>(i);
 }
 
+// Inserts elements i, i + stride, ... below `end` of build p.
 template <typename K>
-__global__ void __launch_bounds__(256) map_build_kernel(MapBuildParams p) {
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
-       i < static_cast<uint64_t>(p.n); i += stride) {
+__device__ __forceinline__ void build_rows(const MapBuildParams& p, uint64_t i, uint64_t end,
+                                           uint64_t stride) {
+  for (; i < end; i += stride) {
     int64_t r = p.idx ? static_cast<int64_t>(p.idx[i]) : static_cast<int64_t>(i);
     K key = static_cast<K>(load_elem(p.keys, p.type, r));
     if constexpr (sizeof(K) == 4) {
@@ -62,6 +62,44 @@ __global__ void __launch_bounds__(256) map_build_kernel(MapBuildParams p) {
       Map64 m{static_cast<ulonglong2*>(p.map.slots), p.map.cap - 1, p.map.oob_count, p.map.oob_vals};
       map_insert(m, key, val, p.map.dup);
     }
+  }
+}
+
+template <typename K>
+__global__ void __launch_bounds__(256) map_build_kernel(MapBuildParams p) {
+  build_rows<K>(p, blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x,
+                static_cast<uint64_t>(p.n), static_cast<uint64_t>(gridDim.x) * blockDim.x);
+}
+
+// One workgroup per build item: rows [begin, end) of one dim of one instance.
+__global__ void __launch_bounds__(256) batch_build_kernel(BatchParams b) {
+  const BatchItem& it = batch_at(b.build_items, blockIdx.x);
+  const MapBuildParams& p = batch_at(b.builds, 2 * static_cast<uint64_t>(it.inst) + it.aux);
+  if (p.map.key_type == kI32)
+    build_rows<int32_t>(p, it.begin + threadIdx.x, it.end, blockDim.x);
+  else
+    build_rows<int64_t>(p, it.begin + threadIdx.x, it.end, blockDim.x);
+}
+
+// One workgroup per fill item.
+__global__ void __launch_bounds__(256) batch_fill_kernel(BatchParams b) {
+  const FillItem& f = batch_at(b.fill, blockIdx.x);
+  const int32_t kind = f.kind;
+  uint64_t* out = f.p;
+  if (kind == kFillGroup) {
+    const GroupDesc& g = batch_at(b.plans, f.inst).g;
+    const uint32_t words = static_cast<uint32_t>(g.words);
+    for (uint64_t i = f.begin + threadIdx.x; i < f.end; i += blockDim.x) {
+      const uint32_t w = static_cast<uint32_t>(i % words);
+      uint64_t v = 0;
+      if (w == 0) v = kEmpty64;
+      else if (w >= 2 && static_cast<int>(w) - 2 < g.ap.nacc) v = acc_identity(g.ap.kind[w - 2]);
+      out[i] = v;
+    }
+  } else {
+    const uint64_t pattern = f.pattern;
+    for (uint64_t i = f.begin + threadIdx.x; i < f.end; i += blockDim.x)
+      out[i] = kind == kFillPairs ? ((i & 1) ? 0ULL : kEmpty64) : pattern;
   }
 }
 
@@ -157,6 +195,18 @@ void launch_map_build(const MapBuildParams& p, hipStream_t s) {
   else
     hipLaunchKernelGGL(map_build_kernel<int64_t>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
                        s, p);
+}
+
+void launch_batch_fill(const BatchParams& b, hipStream_t s) {
+  if (b.nfill == 0) return;
+  ProfileScope ps(kKFill, s);
+  hipLaunchKernelGGL(batch_fill_kernel, dim3(b.nfill), dim3(256), 0, s, b);
+}
+
+void launch_batch_build(const BatchParams& b, hipStream_t s) {
+  if (b.nbuild == 0) return;
+  ProfileScope ps(kKMapBuild, s);
+  hipLaunchKernelGGL(batch_build_kernel, dim3(b.nbuild), dim3(256), 0, s, b);
 }
 
 void launch_map_probe(const MapProbeParams& p, int grid, int block, hipStream_t s) {

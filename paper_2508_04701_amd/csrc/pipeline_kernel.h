@@ -624,37 +624,26 @@ __device__ __forceinline__ uint32_t drain(const PipelineParams& p, unsigned char
   return base + popc64(b);
 }
 
+// Walks tiles `tile`, `tile + step`, ... below `end` of plan p: streams the
+// predicate column (one tile ahead) and the foreign keys, queues the passing
+// rows per wave and drains them in full-lane batches. Returns with the
+// wave's queue empty.
 template <int D0, int D1>
-__global__ void __launch_bounds__(kPipeThreads) fused_kernel(PipelineParams p) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  void* ld0 = lds + p.dim[0].lds_offset;
-  void* ld1 = lds + p.dim[1].lds_offset;
-  uint64_t* lg = reinterpret_cast<uint64_t*>(lds + p.lds_group_offset);
+__device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile, int64_t end,
+                                          int64_t step, unsigned char* wq, int lane,
+                                          const void* ld0, const void* ld1, uint64_t* lg,
+                                          const GroupTable& gt, int limit0, int limit1) {
   const int tid = threadIdx.x;
-  const int lane = lane_id();
-  unsigned char* wq = lds + p.queue_offset + (tid / kWave) * p.queue_stride;
-  copy_dim_to_lds<D0>(p.dim[0], ld0);
-  copy_dim_to_lds<D1>(p.dim[1], ld1);
-  if (p.lds_slots > 0) lds_group_init(lg, p.lds_slots, p.g);
-  __syncthreads();
-
-  const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
-  // Dims built without duplicate keys stop probing at the first match.
-  int limit0 = 1, limit1 = 1;
-  if constexpr (D0 != kNone) limit0 = *p.dim[0].map.dup ? 2 : 1;
-  if constexpr (D1 != kNone) limit1 = *p.dim[1].map.dup ? 2 : 1;
-
   const int c_pred = p.nterms > 0 ? p.term_col[0] : 0;
-  int64_t tile = blockIdx.x;
   int64_t pre[4] = {0, 0, 0, 0};
-  if (p.nterms > 0 && tile < p.ntiles)
+  if (p.nterms > 0 && tile < end)
     load4s(p.fact[c_pred], p.fact_type[c_pred], p.fact_vec[c_pred] != 0,
            tile * static_cast<int64_t>(kPipeTile) + tid * 4, p.n, pre);
   uint32_t queued = 0;  // wave-uniform
-  for (; tile < p.ntiles; tile += gridDim.x) {
+  for (; tile < end; tile += step) {
     const int64_t r0 = tile * static_cast<int64_t>(kPipeTile) + tid * 4;
     const uint32_t bits = eval_prefetched(p, r0, pre);
-    const int64_t next = tile + gridDim.x;
+    const int64_t next = tile + step;
     // Foreign keys of the passing rows, streamed and held in the dim's key
     // width; lanes without a passing row skip them.
     typename KeyOf<D0>::T fk0[4] = {0, 0, 0, 0};
@@ -663,7 +652,7 @@ __global__ void __launch_bounds__(kPipeThreads) fused_kernel(PipelineParams p) {
       if constexpr (D0 != kNone) load_keys4<D0>(p, p.dim[0].fk_col, r0, fk0);
       if constexpr (D1 != kNone) load_keys4<D1>(p, p.dim[1].fk_col, r0, fk1);
     }
-    if (p.nterms > 0 && next < p.ntiles)
+    if (p.nterms > 0 && next < end)
       load4s(p.fact[c_pred], p.fact_type[c_pred], p.fact_vec[c_pred] != 0,
              next * static_cast<int64_t>(kPipeTile) + tid * 4, p.n, pre);
 #pragma unroll
@@ -693,6 +682,30 @@ __global__ void __launch_bounds__(kPipeThreads) fused_kernel(PipelineParams p) {
   while (queued > 0)
     queued = drain<D0, D1>(p, wq, queued, queued < kWave ? queued : kWave, lane, ld0, ld1, lg, gt,
                            limit0, limit1);
+}
+
+// Dims built without duplicate keys stop probing at the first match.
+template <int D>
+__device__ __forceinline__ int match_limit(const PipeDim& d) {
+  if constexpr (D == kNone) return 1;
+  else return *d.map.dup ? 2 : 1;
+}
+
+template <int D0, int D1>
+__global__ void __launch_bounds__(kPipeThreads) fused_kernel(PipelineParams p) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  void* ld0 = lds + p.dim[0].lds_offset;
+  void* ld1 = lds + p.dim[1].lds_offset;
+  uint64_t* lg = reinterpret_cast<uint64_t*>(lds + p.lds_group_offset);
+  const int lane = lane_id();
+  unsigned char* wq = lds + p.queue_offset + (threadIdx.x / kWave) * p.queue_stride;
+  copy_dim_to_lds<D0>(p.dim[0], ld0);
+  copy_dim_to_lds<D1>(p.dim[1], ld1);
+  if (p.lds_slots > 0) lds_group_init(lg, p.lds_slots, p.g);
+  __syncthreads();
+  const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
+  run_tiles<D0, D1>(p, blockIdx.x, p.ntiles, gridDim.x, wq, lane, ld0, ld1, lg, gt,
+                    match_limit<D0>(p.dim[0]), match_limit<D1>(p.dim[1]));
   if (p.lds_slots == 0) return;
   __syncthreads();
   lds_group_flush(lg, p.lds_slots, p.g);
@@ -727,18 +740,19 @@ __device__ __forceinline__ int count_upto2(const PipeDim& d, int64_t key) {
 }
 
 template <int D0, int D1>
-__global__ void __launch_bounds__(256) multi_kernel(PipelineParams p) {
+__device__ __forceinline__ bool has_dup_dims(const PipelineParams& p) {
+  if constexpr (D0 == kNone) return false;
+  else if constexpr (D1 == kNone) return *p.dim[0].map.dup != 0;
+  else return *p.dim[0].map.dup != 0 || *p.dim[1].map.dup != 0;
+}
+
+// Rows r, r + stride, ... below `end`: aggregates every row that passes and
+// matches some dim more than once.
+template <int D0, int D1>
+__device__ __forceinline__ void multi_rows(const PipelineParams& p, int64_t r, int64_t end,
+                                           int64_t stride, uint64_t* lg, const GroupTable& gt) {
   constexpr int H0 = HbmMode<D0>::value, H1 = HbmMode<D1>::value;
-  const bool dup0 = *p.dim[0].map.dup != 0;
-  const bool dup1 = D1 != kNone && *p.dim[1].map.dup != 0;
-  if (!dup0 && !dup1) return;
-  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  uint64_t* lg = reinterpret_cast<uint64_t*>(lds);
-  if (p.lds_slots > 0) lds_group_init(lg, p.lds_slots, p.g);
-  __syncthreads();
-  const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
-  for (int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; r < p.n;
-       r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+  for (; r < end; r += stride) {
     if (!row_passes(p, r)) continue;
     const int64_t fk0 = load_elem(p.fact[p.dim[0].fk_col], p.fact_type[p.dim[0].fk_col], r);
     const int m0 = count_upto2<H0>(p.dim[0], fk0);
@@ -752,6 +766,18 @@ __global__ void __launch_bounds__(256) multi_kernel(PipelineParams p) {
     if (m0 < 2 && m1 < 2) continue;  // single match: aggregated by the fused kernel
     enumerate_row<H0, H1>(p, r, nullptr, nullptr, lg, gt);
   }
+}
+
+template <int D0, int D1>
+__global__ void __launch_bounds__(256) multi_kernel(PipelineParams p) {
+  if (!has_dup_dims<D0, D1>(p)) return;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  uint64_t* lg = reinterpret_cast<uint64_t*>(lds);
+  if (p.lds_slots > 0) lds_group_init(lg, p.lds_slots, p.g);
+  __syncthreads();
+  const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
+  multi_rows<D0, D1>(p, blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x, p.n,
+                     static_cast<int64_t>(gridDim.x) * blockDim.x, lg, gt);
   if (p.lds_slots == 0) return;
   __syncthreads();
   lds_group_flush(lg, p.lds_slots, p.g);
@@ -806,6 +832,98 @@ hipError_t launch_fused(const PipelineParams& p, int grid, hipStream_t s) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_multi<D0, D1>(p, s);
+}
+
+// ------------------------------------------------------------ batched plans
+//
+// Persistent workgroups take (instance, tile range) items from the batch's
+// device counter and walk the tiles of that instance's plan exactly as the
+// single-plan kernel does; the LDS group table is set up and flushed per
+// item. Dim tables stay in HBM, where L2 keeps the small ones.
+
+template <int D0, int D1>
+__global__ void __launch_bounds__(kPipeThreads) batch_fused_kernel(BatchParams b) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  __shared__ uint32_t s_item;
+  uint64_t* lg = reinterpret_cast<uint64_t*>(lds);
+  const int lane = lane_id();
+  for (;;) {
+    if (threadIdx.x == 0) s_item = static_cast<uint32_t>(atomicAdd(b.counter, 1ULL));
+    __syncthreads();
+    const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
+    if (item >= b.ntile) return;
+    const BatchItem& it = batch_at(b.tile_items, item);
+    const PipelineParams& p = batch_at(b.plans, it.inst);
+    unsigned char* wq = lds + p.queue_offset + (threadIdx.x / kWave) * p.queue_stride;
+    if (p.lds_slots > 0) lds_group_init(lg, p.lds_slots, p.g);
+    __syncthreads();
+    const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
+    run_tiles<D0, D1>(p, it.begin, it.end, 1, wq, lane, nullptr, nullptr, lg, gt,
+                      match_limit<D0>(p.dim[0]), match_limit<D1>(p.dim[1]));
+    __syncthreads();
+    if (p.lds_slots > 0) {
+      lds_group_flush(lg, p.lds_slots, p.g);
+      __syncthreads();
+    }
+  }
+}
+
+// One workgroup per tile item: the rows of duplicate-key matches.
+template <int D0, int D1>
+__global__ void __launch_bounds__(256) batch_multi_kernel(BatchParams b) {
+  const BatchItem& it = batch_at(b.tile_items, blockIdx.x);
+  const PipelineParams& p = batch_at(b.plans, it.inst);
+  if (!has_dup_dims<D0, D1>(p)) return;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  uint64_t* lg = reinterpret_cast<uint64_t*>(lds);
+  if (p.lds_slots > 0) lds_group_init(lg, p.lds_slots, p.g);
+  __syncthreads();
+  const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
+  int64_t end = static_cast<int64_t>(it.end) * kPipeTile;
+  if (end > p.n) end = p.n;
+  multi_rows<D0, D1>(p, static_cast<int64_t>(it.begin) * kPipeTile + threadIdx.x, end, blockDim.x,
+                     lg, gt);
+  if (p.lds_slots == 0) return;
+  __syncthreads();
+  lds_group_flush(lg, p.lds_slots, p.g);
+}
+
+template <int D0, int D1>
+hipError_t launch_batch_fused(const BatchParams& b, int grid, hipStream_t s) {
+  auto k = batch_fused_kernel<D0, D1>;
+  static int max_dynamic = -1;
+  if (max_dynamic < 0) {
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(k));
+    if (e != hipSuccess) return e;
+    const int dyn = device_info().lds_per_block - static_cast<int>(attr.sharedSizeBytes);
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    if (e != hipSuccess) return e;
+    max_dynamic = dyn;
+  }
+  if (static_cast<int>(b.lds_bytes) > max_dynamic) return hipErrorInvalidValue;
+  if (b.ntile == 0) return hipSuccess;
+  if (grid <= 0) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kPipeThreads,
+                                                                b.lds_bytes);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    int64_t g = static_cast<int64_t>(device_info().cu_count) * per_cu;
+    if (g > b.ntile) g = b.ntile;
+    grid = static_cast<int>(g < 1 ? 1 : g);
+  }
+  if (grid > kMaxPipeGrid) grid = kMaxPipeGrid;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kPipeThreads), b.lds_bytes, s, b);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if constexpr (D0 != kNone) {
+    hipLaunchKernelGGL((batch_multi_kernel<D0, D1>), dim3(b.ntile), dim3(256), b.group_lds_bytes,
+                       s, b);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 }  // namespace pipe

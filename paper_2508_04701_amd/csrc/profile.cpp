@@ -42,8 +42,10 @@ hipEvent_t take_event() {
 
 }  // namespace
 
+thread_local bool g_capturing = false;
+
 ProfileScope::ProfileScope(int kclass, hipStream_t stream) : k(kclass), s(stream), start(nullptr) {
-  if (!g_enabled.load(std::memory_order_relaxed)) return;
+  if (g_capturing || !g_enabled.load(std::memory_order_relaxed)) return;
   hipEvent_t e = take_event();
   if (e && hipEventRecord(e, s) == hipSuccess) start = e;
 }

@@ -55,7 +55,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("load_factor", ctypes.c_float), ("block", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("lds_slots", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("dim_lds_bytes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("chunk_tiles", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Dim(ctypes.Structure):
@@ -95,6 +95,11 @@ SIGNATURES = {
     "rel_groupby_agg": (_I, [_P, _I, _P, _I, _P, _I, _P, _P, _L, _P, _L, _P, _P, _S, _P]),
     "rel_pipeline_ws": (_S, [_P]),
     "rel_pipeline": (_I, [_P, _P, _P, _S, _P]),
+    "rel_pipeline_batch_ws": (_S, [_P, _I]),
+    "rel_pipeline_batch": (_I, [_P, _I, _P, _P, _S, _P]),
+    "rel_pipeline_batch_graph": (_I, [_P, _I, _P, _P, _S, _P]),
+    "rel_graph_launch": (_I, [_P, _P]),
+    "rel_graph_destroy": (None, [_P]),
     "rel_kernel_name": (ctypes.c_char_p, [_I]),
     "rel_profile_enable": (None, [_I]),
     "rel_profile_read": (_I, [_P, _P]),
@@ -152,8 +157,9 @@ def column(t: torch.Tensor, idx: torch.Tensor | None = None) -> Column:
     return Column(t.data_ptr() if t.numel() else None, None, t.numel(), DTYPES[t.dtype], 0)
 
 
-def tuning(load_factor=0.0, block=0, grid=0, lds_slots=0, dim_lds_bytes=0) -> Tuning:
-    return Tuning(load_factor, block, grid, lds_slots, 0, dim_lds_bytes, (ctypes.c_int32 * 2)())
+def tuning(load_factor=0.0, block=0, grid=0, lds_slots=0, dim_lds_bytes=0,
+           chunk_tiles=0) -> Tuning:
+    return Tuning(load_factor, block, grid, lds_slots, 0, dim_lds_bytes, chunk_tiles, 0)
 
 
 def _tuning_ptr(t):
@@ -294,14 +300,14 @@ def groupby_agg(keys, vals, aggs, max_groups: int | None = None, key_idx=None, v
 
 # ------------------------------------------------------------------ pipeline
 
-class PreparedPipeline:
-    """A fused plan bound to its inputs, workspace and output buffers.
-    ``launch()`` only enqueues kernels (no allocation, no synchronisation)."""
+class Plan:
+    """A fused plan bound to its inputs and output buffers (no workspace)."""
 
     def __init__(self, fact, preds, dims, keys, aggs, max_groups: int, t: Tuning | None = None,
                  out_cap: int | None = None):
         _require_gpu(*fact)
         dev = fact[0].device
+        self.device = dev
         self._keep = [fact, dims]
         self.aggs = aggs
         self._fact = _arr(Column, [column(c) for c in fact])
@@ -322,11 +328,6 @@ class PreparedPipeline:
             ctypes.cast(self._keys, ctypes.POINTER(KeyRef)), len(keys),
             ctypes.cast(self._aggs, ctypes.POINTER(Agg)), len(aggs), int(max_groups),
             ctypes.pointer(t) if t is not None else None)
-        nbytes = lib().rel_pipeline_ws(ctypes.byref(self.desc))
-        if nbytes == 0:
-            # the same validation, run again, names the problem
-            _check(lib().rel_pipeline(ctypes.byref(self.desc), None, None, 0, None))
-        self.ws = workspace(nbytes, dev)
         key_dtypes = [fact[c].dtype if src == "fact" else dims[c]["payload"].dtype
                       for src, c in keys]
         self.key_dtypes = key_dtypes
@@ -341,10 +342,6 @@ class PreparedPipeline:
         self.outputs.cap = self.cap
         self.outputs.d_groups = self.d_groups.data_ptr()
 
-    def launch(self):
-        _check(lib().rel_pipeline(ctypes.byref(self.desc), ctypes.byref(self.outputs),
-                                  _addr(self.ws), self.ws.numel(), _stream()))
-
     def result(self):
         """Synchronises on the group count and returns (keys, aggs)."""
         ng = _count(self.d_groups)
@@ -353,6 +350,77 @@ class PreparedPipeline:
         if ng > self.cap:
             raise RelError(REL_ECAPACITY, f"{ng} groups exceed the output capacity {self.cap}")
         return [k[:ng] for k in self.out_keys], [a[:ng] for a in self.out_aggs]
+
+
+class PreparedPipeline(Plan):
+    """A fused plan with its own workspace. ``launch()`` only enqueues
+    kernels (no allocation, no synchronisation)."""
+
+    def __init__(self, *args, **kwargs):
+        super().__init__(*args, **kwargs)
+        nbytes = lib().rel_pipeline_ws(ctypes.byref(self.desc))
+        if nbytes == 0:
+            # the same validation, run again, names the problem
+            _check(lib().rel_pipeline(ctypes.byref(self.desc), None, None, 0, None))
+        self.ws = workspace(nbytes, self.device)
+
+    def launch(self):
+        _check(lib().rel_pipeline(ctypes.byref(self.desc), ctypes.byref(self.outputs),
+                                  _addr(self.ws), self.ws.numel(), _stream()))
+
+
+class PreparedBatch:
+    """Plans of one shape run together by rel_pipeline_batch, sharing one
+    workspace; each plan keeps its own outputs (``Plan.result()``).
+    ``launch()`` enqueues the batch; ``capture()`` records it once as a graph
+    that ``launch_graph()`` replays."""
+
+    def __init__(self, plans: list):
+        if not plans:
+            raise ValueError("a batch needs at least one plan")
+        self.plans = plans
+        n = len(plans)
+        self.n = n
+        self.descs = (PipelineDesc * n)(*[p.desc for p in plans])
+        self.outs = (Outputs * n)(*[p.outputs for p in plans])
+        nbytes = lib().rel_pipeline_batch_ws(self.descs, n)
+        if nbytes == 0:
+            _check(lib().rel_pipeline_batch(self.descs, n, None, None, 0, None))
+        self.ws = workspace(nbytes, plans[0].device)
+        self._graph = None
+
+    def launch(self):
+        _check(lib().rel_pipeline_batch(self.descs, self.n, self.outs, _addr(self.ws),
+                                        self.ws.numel(), _stream()))
+
+    def capture(self):
+        """Captures the batch as a graph (nothing runs)."""
+        self.release()
+        g = ctypes.c_void_p()
+        _check(lib().rel_pipeline_batch_graph(self.descs, self.n, self.outs, _addr(self.ws),
+                                              self.ws.numel(), ctypes.byref(g)))
+        self._graph = g
+
+    def launch_graph(self):
+        if self._graph is None:
+            raise RuntimeError("capture() the batch first")
+        _check(lib().rel_graph_launch(self._graph, _stream()))
+
+    def release(self):
+        """Destroys the captured graph (after synchronising the device)."""
+        if self._graph is not None:
+            torch.cuda.synchronize(self.plans[0].device)
+            lib().rel_graph_destroy(self._graph)
+            self._graph = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+    def results(self):
+        return [p.result() for p in self.plans]
 
 
 def pipeline(fact, preds, dims, keys, aggs, max_groups: int, t: Tuning | None = None):

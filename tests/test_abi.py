@@ -151,3 +151,62 @@ def test_binding_refuses_cpu_tensors():
     import torch
     with pytest.raises((RuntimeError, ValueError)):
         rel.filter([torch.zeros(10, dtype=torch.int32)], [(0, "lt", 3)])
+
+
+def _batch_descs(n, dim_types, payloads, fact_len=1000, dim_len=30):
+    keep = []
+    descs = (rel.PipelineDesc * n)()
+    for i in range(n):
+        fact = (rel.Column * 2)(col(fact_len + i, 2), col(fact_len + i, 3, data=0x2000))
+        dims = (rel.Dim * 1)(rel.Dim(0, payloads[i], col(dim_len * (i + 1), dim_types[i], data=0x3000),
+                                     col(dim_len * (i + 1), 2, data=0x4000) if payloads[i]
+                                     else rel.Column()))
+        keys = (rel.KeyRef * 1)(rel.KeyRef(1, 0) if payloads[i] else rel.KeyRef(0, 0))
+        aggs = (rel.Agg * 2)(rel.Agg(0, 1), rel.Agg(1, 0))
+        keep += [fact, dims, keys, aggs]
+        descs[i] = rel.PipelineDesc(ctypes.cast(fact, ctypes.POINTER(rel.Column)), 2, None, 0,
+                                    ctypes.cast(dims, ctypes.POINTER(rel.Dim)), 1,
+                                    ctypes.cast(keys, ctypes.POINTER(rel.KeyRef)), 1,
+                                    ctypes.cast(aggs, ctypes.POINTER(rel.Agg)), 2, 64 * (i + 1),
+                                    None)
+    return descs, keep
+
+
+def test_batch_validation_and_workspace():
+    L = rel.lib()
+    descs, keep = _batch_descs(3, [2, 2, 2], [1, 1, 1])
+    total = L.rel_pipeline_batch_ws(descs, 3)
+    # at least every plan's own tables
+    assert total > sum(L.rel_pipeline_ws(ctypes.byref(descs[i])) for i in range(3)) // 2
+    one = L.rel_pipeline_batch_ws(descs, 1)
+    assert 0 < one < total
+    assert L.rel_pipeline_batch_ws(descs, 0) == 0
+    # plans must share a shape: dim key type, payload presence
+    mixed, keep2 = _batch_descs(3, [2, 3, 2], [1, 1, 1])
+    assert L.rel_pipeline_batch_ws(mixed, 3) == 0
+    rc = L.rel_pipeline_batch(mixed, 3, None, None, 0, None)
+    assert rc == rel.REL_EINVAL and b"differs" in L.rel_last_error()
+    mixed, keep3 = _batch_descs(2, [2, 2], [1, 0])
+    assert L.rel_pipeline_batch_ws(mixed, 2) == 0
+    # outputs are required, and a short workspace is refused before any launch
+    rc = L.rel_pipeline_batch(descs, 3, None, ctypes.c_void_p(0x10000), total, None)
+    assert rc == rel.REL_EINVAL
+    outs = (rel.Outputs * 3)()
+    for o in outs:
+        o.keys[0] = 0x100
+        o.aggs[0] = 0x100
+        o.aggs[1] = 0x100
+        o.cap = 10
+        o.d_groups = 0x200
+    rc = L.rel_pipeline_batch(descs, 3, outs, ctypes.c_void_p(0x10000), total - 1, None)
+    assert rc == rel.REL_ENOMEM
+    g = ctypes.c_void_p()
+    rc = L.rel_pipeline_batch_graph(descs, 3, outs, ctypes.c_void_p(0x10000), total - 1,
+                                    ctypes.byref(g))
+    assert rc == rel.REL_ENOMEM and not g.value
+    assert L.rel_graph_launch(None, None) == rel.REL_EINVAL
+    L.rel_graph_destroy(None)
+    # chunk size is a tuning field that must not be negative
+    t = rel.tuning(chunk_tiles=-1)
+    descs[0].tuning = ctypes.pointer(t)
+    assert L.rel_pipeline_batch_ws(descs, 3) == 0

@@ -1,0 +1,190 @@
+"""GPU parity of batched plans (rel_pipeline_batch and its captured graph):
+every instance of a batch must equal the same plan run alone through
+rel_pipeline and the oracle, exactly (AVG bit for bit), whatever the work
+split (chunk size, grid) and across graph replays."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import announce, assert_groups, canon_groups, dev
+from paper_2508_04701_amd import datagen, rel
+
+pytestmark = pytest.mark.gpu
+
+AGGS = [("sum", 1), ("count", None), ("avg", 1), ("min", 1), ("max", 1)]
+
+
+def join_instances(seed, n_inst, build_range, probe_range, group_range):
+    shapes = datagen.batch_shapes(seed=seed, n_inst=n_inst, build_range=build_range,
+                                  probe_range=probe_range, group_range=group_range)
+    return [dict(shape=s, **datagen.batch_instance(seed, i, **s)) for i, s in enumerate(shapes)]
+
+
+def join_spec(inst):
+    """(fact, terms, dims, keys, aggs, max_groups) of a join + group-by
+    instance: probe side as the fact table, build side as the dim."""
+    fact = [inst["probe_key"], inst["probe_val"]]
+    dims = [dict(fk=0, key=inst["build_key"], payload=inst["build_grp"])]
+    return fact, [], dims, [("dim", 0)], AGGS, max(1, inst["shape"]["n_groups"])
+
+
+def device_plan(spec, t=None):
+    fact, terms, dims, keys, aggs, max_groups = spec
+    ddims = [dict(fk=x["fk"], key=dev(x["key"]),
+                  payload=None if x.get("payload") is None else dev(x["payload"])) for x in dims]
+    return rel.Plan([dev(c) for c in fact], terms, ddims, keys, aggs, max_groups, t)
+
+
+def oracle_of(spec):
+    fact, terms, dims, keys, aggs, _ = spec
+    return oracle.pipeline(fact, terms, dims, keys, aggs)
+
+
+def assert_same(a, b, what):
+    ka, aa = canon_groups(*a)
+    kb, ab = canon_groups(*b)
+    assert len(aa[0]) == len(ab[0]), f"{what}: {len(aa[0])} vs {len(ab[0])} groups"
+    for x, y in zip(ka + aa, kb + ab):
+        assert np.array_equal(x, y), what
+
+
+def run_batch(specs, t0=None, graph=False):
+    plans = [device_plan(s, t0 if i == 0 else None) for i, s in enumerate(specs)]
+    b = rel.PreparedBatch(plans)
+    if graph:
+        b.capture()
+        b.launch_graph()
+    else:
+        b.launch()
+    torch.cuda.synchronize()
+    return b
+
+
+def test_batch_join_instances_match_single_calls_and_oracle():
+    announce("batch join instances", 24)
+    insts = join_instances(101, 24, (100, 40_000), (1_000, 400_000), (8, 5_000))
+    # edge instances: no probe rows, one build row, no build rows
+    insts[3]["probe_key"] = insts[3]["probe_key"][:0]
+    insts[3]["probe_val"] = insts[3]["probe_val"][:0]
+    insts[5].update(build_key=np.array([7], np.int32), build_grp=np.array([2], np.int32))
+    insts[9].update(build_key=np.zeros(0, np.int32), build_grp=np.zeros(0, np.int32))
+    specs = [join_spec(i) for i in insts]
+    b = run_batch(specs)
+    for i, (spec, plan) in enumerate(zip(specs, b.plans)):
+        got = plan.result()
+        fact, terms, dims, keys, aggs, mg = spec
+        single = rel.pipeline([dev(c) for c in fact], terms,
+                              [dict(fk=0, key=dev(dims[0]["key"]), payload=dev(dims[0]["payload"]))],
+                              keys, aggs, mg)
+        assert_same(got, single, f"instance {i}: batch vs single call")
+        assert_groups(got, oracle_of(spec), aggs, f"instance {i}")
+
+
+def mixed_specs(seed, n):
+    """Plans of one two-dim shape (an int32 membership dim, then an int32 dim
+    with a payload) that differ in everything else: sizes (empty included),
+    duplicate dim keys, predicates, group keys (none, fact, dim, both) and
+    aggregates."""
+    r = np.random.default_rng(seed)
+    specs = []
+    key_sets = [[("dim", 1)], [("fact", 2)], [], [("dim", 1), ("fact", 2)]]
+    agg_sets = [AGGS, [("count", None)], [("sum", 1), ("max", 1)], [("min", 1), ("avg", 1)]]
+    for i in range(n):
+        nf = [0, 1, 2047, 2049, 50_000, 123_457][i % 6]
+        nd0 = [0, 5, 300, 4_000][i % 4]
+        nd1 = [1, 64, 2_500][i % 3]
+        dup = i % 2 == 1
+        k0 = r.integers(-50, 4_000, size=nd0).astype(np.int32) if dup else \
+            r.permutation(5_000)[:nd0].astype(np.int32)
+        k1 = r.integers(0, 3_000, size=nd1).astype(np.int32) if dup else \
+            r.permutation(3_000)[:nd1].astype(np.int32)
+        if nd1 > 2 and i % 3 == 0:
+            k1[0] = -(2**31)  # the sentinel pattern as a real key
+        pay1 = r.integers(-20, 20 + i, size=nd1).astype(np.int32)
+        fk0 = r.integers(-60, 5_000, size=nf).astype(np.int32)
+        fk1 = r.integers(-5, 3_000, size=nf).astype(np.int32)
+        if nf > 10 and i % 3 == 0:
+            fk1[:5] = -(2**31)
+        g = r.integers(0, 40, size=nf).astype(np.int32)
+        v = r.integers(-10**9, 10**9, size=nf).astype(np.int64)
+        terms = [[], [(2, "lt", 30)], [(2, "range", 5, 35), (1, "ne", 7)]][i % 3]
+        fact = [fk0, v, g, fk1]
+        dims = [dict(fk=0, key=k0, payload=None), dict(fk=3, key=k1, payload=pay1)]
+        specs.append((fact, terms, dims, key_sets[i % 4], agg_sets[(i // 2) % 4], 4_096))
+    return specs
+
+
+def test_batch_mixed_plans_of_one_shape():
+    announce("batch mixed two-dim plans", 24)
+    specs = mixed_specs(202, 24)
+    b = run_batch(specs)
+    for i, (spec, plan) in enumerate(zip(specs, b.plans)):
+        assert_groups(plan.result(), oracle_of(spec), spec[4], f"mixed instance {i}")
+
+
+def test_batch_int64_dims_and_no_dims():
+    announce("batch int64 dims")
+    r = np.random.default_rng(303)
+    specs64, specs0 = [], []
+    for i in range(6):
+        n, nd = [10, 5_000, 70_001][i % 3], [1, 3_000][i % 2]
+        key = r.integers(-2**62, 2**62, size=nd).astype(np.int64)
+        key[::7] = np.iinfo(np.int64).min
+        fk = np.where(r.random(n) < 0.7, r.choice(key, size=n), r.integers(-5, 5, size=n))
+        g = r.integers(0, 30, size=n).astype(np.int32)
+        v = r.integers(-10**6, 10**6, size=n).astype(np.int64)
+        specs64.append(([fk.astype(np.int64), g, v], [], [dict(fk=0, key=key, payload=None)],
+                        [("fact", 1)], [("sum", 2), ("count", None)], 64))
+        specs0.append(([fk.astype(np.int64), g, v], [(1, "ge", 3)], [], [("fact", 1)] if i % 2 else [],
+                       [("sum", 2), ("min", 2)], 64))
+    for name, specs in (("int64 dims", specs64), ("no dims", specs0)):
+        b = run_batch(specs)
+        for i, (spec, plan) in enumerate(zip(specs, b.plans)):
+            assert_groups(plan.result(), oracle_of(spec), spec[4], f"{name} instance {i}")
+
+
+@pytest.mark.parametrize("chunk,grid", [(1, 0), (3, 7), (8, 0), (64, 1)])
+def test_batch_work_split_does_not_change_results(chunk, grid):
+    announce("batch work split", chunk, grid)
+    insts = join_instances(404, 12, (100, 20_000), (1_000, 200_000), (8, 2_000))
+    specs = [join_spec(i) for i in insts]
+    b = run_batch(specs, t0=rel.tuning(chunk_tiles=chunk, grid=grid))
+    for i, (spec, plan) in enumerate(zip(specs, b.plans)):
+        assert_groups(plan.result(), oracle_of(spec), AGGS, f"chunk {chunk} grid {grid} inst {i}")
+
+
+def test_batch_graph_replays():
+    """The captured graph replayed several times, with eager work and
+    synchronisations between replays, and after the inputs change in place:
+    every replay equals the oracle on the inputs current at its launch."""
+    announce("batch graph replays")
+    insts = join_instances(505, 10, (100, 20_000), (1_000, 150_000), (8, 1_000))
+    specs = [join_spec(i) for i in insts]
+    plans = [device_plan(s) for s in specs]
+    b = rel.PreparedBatch(plans)
+    b.capture()
+    want = [oracle_of(s) for s in specs]
+    for rep in range(3):
+        b.launch_graph()
+        torch.cuda.synchronize()
+        for i, plan in enumerate(b.plans):
+            assert_groups(plan.result(), want[i], AGGS, f"replay {rep} instance {i}")
+        # unrelated eager work between replays
+        x = torch.arange(1 << 20, device="cuda", dtype=torch.int64)
+        assert int(x.sum().item()) == (1 << 20) * ((1 << 20) - 1) // 2
+    # change every probe value in place; the next replay reads the new values
+    for plan, spec in zip(plans, specs):
+        plan._keep[0][1].add_(3)
+        spec[0][1] = spec[0][1] + 3
+    b.launch_graph()
+    torch.cuda.synchronize()
+    for i, (plan, spec) in enumerate(zip(b.plans, specs)):
+        assert_groups(plan.result(), oracle_of(spec), AGGS, f"replay after update, instance {i}")
+    # the eager path on the same batch agrees as well
+    b.launch()
+    torch.cuda.synchronize()
+    for i, (plan, spec) in enumerate(zip(b.plans, specs)):
+        assert_groups(plan.result(), oracle_of(spec), AGGS, f"eager after graph, instance {i}")
+    b.release()
