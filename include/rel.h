@@ -111,7 +111,9 @@ typedef struct {
                             -1 = none */
   int32_t chunk_tiles;   /* rel_pipeline_batch: fact tiles (2048 rows) per work item of the
                             fused pass; 0 = default (from the batch's total size, at most 8) */
-  int32_t reserved;
+  int32_t replicas;      /* copies of the global group table; workgroup w updates copy
+                            w mod replicas (w mod 8 is its XCD) and a last pass folds them;
+                            0 = default (64 when all groups fit the LDS tables, else 1) */
 } rel_tuning;
 
 #define REL_MAX_TERMS 4

@@ -65,6 +65,8 @@ rel_status check_tuning(const rel_tuning* t) {
     return fail(REL_EINVAL, "tuning.lds_slots must be -1, 0 or a power of two");
   if (t->flags != 0) return fail(REL_EINVAL, "tuning.flags must be 0");
   if (t->chunk_tiles < 0) return fail(REL_EINVAL, "tuning.chunk_tiles must be >= 0");
+  if (t->replicas < 0 || t->replicas > 256)
+    return fail(REL_EINVAL, "tuning.replicas must be in [0, 256]");
   return REL_OK;
 }
 
@@ -276,9 +278,28 @@ int default_lds_slots(const rel_tuning* t, int64_t max_groups, int words, size_t
   return static_cast<int>(want);
 }
 
+// Replicas of the global group table: a tuned count, else kGroupReplicas
+// when every group fits the LDS tables (only their flushes reach the global
+// table), else as many as keep the copies within kReplicaBytes (at most
+// kSpillReplicas): rows that spill from LDS update the global table with
+// device-scope atomics, which serialise per cache line, so copies spread the
+// hot lines (workgroup w updates copy w mod replicas, and w mod 8 is its XCD).
+constexpr int kSpillReplicas = 32;
+constexpr uint64_t kReplicaBytes = 256ull << 20;
+
+int group_replicas(const rel_tuning* t, int64_t max_groups, int lds_slots, int words, float lf) {
+  if (t && t->replicas > 0) return t->replicas;
+  if (lds_slots > 0 && 2 * max_groups <= lds_slots) return kGroupReplicas;
+  const uint64_t want = static_cast<uint64_t>(std::ceil(static_cast<double>(max_groups < 1 ? 1 : max_groups) / lf));
+  const uint64_t table = next_pow2(want < 64 ? 64 : want) * static_cast<uint64_t>(words) * 8;
+  int r = 1;
+  while (r < kSpillReplicas && 2 * r * table <= kReplicaBytes) r *= 2;
+  return r;
+}
+
 int groupby_replicas(const rel_tuning* t, int64_t max_groups, const GroupPlan& gp) {
-  const int lds = default_lds_slots(t, max_groups, gp.words, 32768);
-  return (lds > 0 && 2 * max_groups <= lds) ? kGroupReplicas : 1;
+  return group_replicas(t, max_groups, default_lds_slots(t, max_groups, gp.words, 32768), gp.words,
+                        load_factor(t));
 }
 
 FinalizeParams finalize_params(const GroupDesc& g, const GroupPlan& gp, const rel_agg* aggs,
@@ -410,8 +431,8 @@ rel_status pipeline_layout(const rel_pipeline_desc* d, PipeLayout& L, bool batch
   rel_status st = group_plan(d->n_keys, L.key_types, d->n_aggs, d->aggs, L.gp);
   if (st) return st;
   L.lds_slots = default_lds_slots(d->tuning, d->max_groups, L.gp.words, 16384);
-  const bool few = L.lds_slots > 0 && 2 * d->max_groups <= L.lds_slots;
-  L.group = group_layout(L.gp, d->max_groups, lf, off, few ? kGroupReplicas : 1);
+  L.group = group_layout(L.gp, d->max_groups, lf, off,
+                         group_replicas(d->tuning, d->max_groups, L.lds_slots, L.gp.words, lf));
   L.end = L.group.end;
   return REL_OK;
 }
@@ -645,6 +666,17 @@ rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
   return REL_OK;
 }
 
+// True when every plan scans the same fact columns.
+bool shared_scan(const rel_pipeline_desc* d, int n) {
+  for (int i = 1; i < n; ++i) {
+    if (d[i].n_fact != d[0].n_fact) return false;
+    for (int c = 0; c < d[0].n_fact; ++c)
+      if (d[i].fact[c].data != d[0].fact[c].data || d[i].fact[c].len != d[0].fact[c].len)
+        return false;
+  }
+  return n > 1;
+}
+
 void push_fill(std::vector<FillItem>& v, uint64_t* p, uint64_t words, int32_t kind,
                uint64_t pattern, uint32_t inst) {
   for (uint64_t b = 0; b < words; b += kFillChunk) {
@@ -712,9 +744,24 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
     push_fill(fill, g.slots, g.replicas * (g.cap + 1) * g.words, kFillGroup, 0, i);
     push_fill(fill, reinterpret_cast<uint64_t*>(g.overflow), 1, kFillConst, 0, i);
     push_fill(fill, reinterpret_cast<uint64_t*>(g.d_groups), 1, kFillConst, 0, i);
-    push_items(tile_items, i, 0, static_cast<uint64_t>(p.ntiles), B.chunk_tiles);
+    if (!shared_scan(d, n)) push_items(tile_items, i, 0, static_cast<uint64_t>(p.ntiles), B.chunk_tiles);
     if (g.replicas > 1) push_items(merge_items, i, 0, (g.replicas - 1) * (g.cap + 1), kSlotChunk);
     push_items(fin_items, i, 0, d[i].n_keys == 0 ? 1 : g.cap + 1, kSlotChunk);
+  }
+  if (shared_scan(d, n)) {
+    // plans over one fact table: tile range j of every plan, then range j + 1,
+    // so that the plans' passes over a range run together and share its
+    // columns through the caches
+    const uint64_t ntiles = static_cast<uint64_t>(plans[0].ntiles);
+    for (uint64_t b = 0; b < ntiles; b += B.chunk_tiles)
+      for (int i = 0; i < n; ++i) {
+        BatchItem it;
+        it.inst = i;
+        it.aux = 0;
+        it.begin = b;
+        it.end = b + B.chunk_tiles < ntiles ? b + B.chunk_tiles : ntiles;
+        tile_items.push_back(it);
+      }
   }
   // one LDS layout for every instance: the largest group table, then the queues
   for (int i = 0; i < n; ++i) {

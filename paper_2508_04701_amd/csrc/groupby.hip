@@ -71,7 +71,6 @@ __global__ void __launch_bounds__(256) group_agg_kernel(GroupAggParams p) {
   }
 }
 
-// Folds every occupied slot of replicas 1.. into replica 0.
 // Folds entries i, i + stride, ... below `end` of replicas 1.. (numbered
 // from the start of replica 1) into replica 0.
 __device__ __forceinline__ void merge_range(const GroupDesc& g, uint64_t i, uint64_t end,

@@ -55,7 +55,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("load_factor", ctypes.c_float), ("block", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("lds_slots", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("dim_lds_bytes", ctypes.c_int32),
-                ("chunk_tiles", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("chunk_tiles", ctypes.c_int32), ("replicas", ctypes.c_int32)]
 
 
 class Dim(ctypes.Structure):
@@ -158,8 +158,8 @@ def column(t: torch.Tensor, idx: torch.Tensor | None = None) -> Column:
 
 
 def tuning(load_factor=0.0, block=0, grid=0, lds_slots=0, dim_lds_bytes=0,
-           chunk_tiles=0) -> Tuning:
-    return Tuning(load_factor, block, grid, lds_slots, 0, dim_lds_bytes, chunk_tiles, 0)
+           chunk_tiles=0, replicas=0) -> Tuning:
+    return Tuning(load_factor, block, grid, lds_slots, 0, dim_lds_bytes, chunk_tiles, replicas)
 
 
 def _tuning_ptr(t):

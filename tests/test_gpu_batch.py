@@ -188,3 +188,40 @@ def test_batch_graph_replays():
     for i, (plan, spec) in enumerate(zip(b.plans, specs)):
         assert_groups(plan.result(), oracle_of(spec), AGGS, f"eager after graph, instance {i}")
     b.release()
+
+
+def test_batch_plans_sharing_one_fact_table():
+    """Plans over the same resident fact columns (their tile ranges are
+    interleaved across plans): different date ranges, dims and group
+    attributes, each equal to the oracle."""
+    announce("batch shared fact table")
+    d = datagen.star_schema(seed=17, n_fact=250_001, n_dim_a=20_000, n_dim_b=1_000)
+    r = np.random.default_rng(606)
+    city = (r.permutation(1_000) % 200).astype(np.int32)
+    segment = (r.permutation(20_000) % 5_000).astype(np.int32)
+    fact = [d["fk_a"], d["fk_b"], d["date"], d["price"], d["flag"]]
+    dfact = [dev(c) for c in fact]
+    attrs = [(1, d["dim_b_key"], d["dim_b_region"]), (1, d["dim_b_key"], city),
+             (0, d["dim_a_key"], segment)]
+    ddims = {k: dev(a) for k, a in [("a", d["dim_a_key"]), ("b", d["dim_b_key"]),
+                                     ("region", d["dim_b_region"]), ("city", city),
+                                     ("segment", segment)]}
+    dev_attr = [(1, ddims["b"], ddims["region"]), (1, ddims["b"], ddims["city"]),
+                (0, ddims["a"], ddims["segment"])]
+    aggs = [("sum", 3), ("count", None)]
+    specs, plans = [], []
+    for q in range(9):
+        w = int(r.integers(25, 1_300))
+        lo = int(r.integers(0, 2_557 - w))
+        a = q % 3
+        fk, key, pay = attrs[a]
+        terms = [(2, "range", lo, lo + w)]
+        specs.append((fact, terms, [dict(fk=fk, key=key, payload=pay)], [("dim", 0)], aggs, 5_000))
+        fk_d, key_d, pay_d = dev_attr[a]
+        plans.append(rel.Plan(dfact, terms, [dict(fk=fk_d, key=key_d, payload=pay_d)],
+                              [("dim", 0)], aggs, 5_000))
+    b = rel.PreparedBatch(plans)
+    b.launch()
+    torch.cuda.synchronize()
+    for q, (spec, plan) in enumerate(zip(specs, b.plans)):
+        assert_groups(plan.result(), oracle_of(spec), aggs, f"shared-scan query {q}")
