@@ -311,6 +311,102 @@ rel_status rel_graph_launch(rel_graph* g, void* stream);
  * running. */
 void rel_graph_destroy(rel_graph* g);
 
+/* -------------------------------------------------------------- serving */
+
+/* A query server over resident tables (the pipeline tasks of Section 3.2.2
+ * drawn from a global queue; hot data kept in device memory, Section 4.1):
+ * queries are submitted as fused plans over device columns that stay
+ * allocated, wait in a FIFO, and are admitted as lanes, query slots and
+ * workspace bytes free up. Whenever a lane is free, a scheduler thread packs
+ * the oldest waiting queries of one shape (as in rel_pipeline_batch) into a
+ * batch, takes its workspace from the arena (first fit) and launches it, so
+ * that queries arriving while others run are batched and overlap them on the
+ * device. A query completes once its batch has finished and its results are
+ * in the host buffers given at submission; then its slot, lane and bytes are
+ * released. Each query's results are those of rel_pipeline on its plan. */
+typedef struct rel_server rel_server;
+
+/* Runs batches for a server; NULL in the config selects the GPU executor
+ * (rel_pipeline_batch on one HIP stream per lane, completion by event
+ * polling, then copies of the result rows to the host buffers). A custom
+ * executor lets the scheduler run anywhere (tests drive it with one that
+ * computes on the host). All three are called from the scheduler thread,
+ * batch_ws also from rel_server_submit.
+ *   batch_ws  workspace bytes for plans d[0..n-1] (0: invalid plans).
+ *   launch    starts the batch on `lane` (idle), with n plans, their device
+ *             outputs o and host outputs host (entries with NULL d_groups
+ *             take no copy); returns REL_OK or a failure of the batch.
+ *   poll      1 once the lane's batch and its copies are done, 0 while they
+ *             run, -status on failure. */
+typedef struct {
+  void* user;
+  size_t (*batch_ws)(void* user, const rel_pipeline_desc* d, int n);
+  rel_status (*launch)(void* user, int lane, const rel_pipeline_desc* d, int n,
+                       const rel_outputs* o, const rel_outputs* host, void* ws, size_t ws_bytes);
+  int (*poll)(void* user, int lane);
+} rel_executor;
+
+typedef struct {
+  void* arena;           /* device memory for batch workspaces, 256-byte aligned: the budget
+                            for hash tables and per-batch state */
+  size_t arena_bytes;
+  int32_t max_slots;     /* queries in flight at once */
+  int32_t max_batch;     /* queries per batch (1: one at a time) */
+  int32_t lanes;         /* batches in flight at once, 1..64 */
+  int32_t reserved;
+  const rel_executor* executor; /* NULL: the GPU executor on the current device */
+} rel_server_config;
+
+/* A completed query: status (REL_OK or the failure of its batch), the size
+ * of its batch, and times on the rel_server_now_ns() clock. */
+typedef struct {
+  uint64_t ticket;
+  int32_t status;
+  int32_t batch_size;
+  int64_t t_submit_ns;
+  int64_t t_launch_ns;
+  int64_t t_done_ns;
+} rel_completion;
+
+typedef struct {
+  int64_t submitted, completed, failed, rejected, batches, batched_queries;
+} rel_server_counts;
+
+/* Starts a server (and its scheduler thread). The environment variable
+ * REL_FAULT=launch:N makes the N-th batch launch fail with REL_EDEVICE
+ * without running (failure handling tests): its queries fail, the server
+ * goes on. Errors: REL_EINVAL (bad config), REL_EDEVICE (streams, events or
+ * pinned memory of the GPU executor). */
+rel_status rel_server_create(const rel_server_config* c, rel_server** out);
+
+/* Queues plan d (copied; its columns stay caller-owned and allocated until
+ * the query completes) with device outputs o and optional host outputs
+ * `host` (pinned host memory, same layout; NULL: results stay on the
+ * device). Returns the query's ticket. Errors: REL_EINVAL (invalid plan,
+ * server stopping), REL_ENOMEM (the query alone needs more workspace than the
+ * whole arena: rejected, others go on). */
+rel_status rel_server_submit(rel_server* s, const rel_pipeline_desc* d, const rel_outputs* o,
+                             const rel_outputs* host, uint64_t* ticket);
+
+/* Moves up to max completions (in completion order) into out; returns the
+ * count. */
+int rel_server_poll(rel_server* s, rel_completion* out, int max);
+
+/* Waits until every submitted query has completed; REL_ECAPACITY if
+ * timeout_ms passes first. */
+rel_status rel_server_drain(rel_server* s, int64_t timeout_ms);
+
+/* Counters, and the 50th and 99th percentile (nearest rank) of submit-to-done
+ * latency over the successful queries so far (-1 if none). */
+rel_status rel_server_stats(rel_server* s, rel_server_counts* counts, int64_t* p50_ns,
+                            int64_t* p99_ns);
+
+/* The server clock: a steady clock in nanoseconds. */
+int64_t rel_server_now_ns(void);
+
+/* Completes every queued query, stops the scheduler and frees the server. */
+void rel_server_destroy(rel_server* s);
+
 /* ------------------------------------------------------------- profiling */
 
 /* Kernel classes timed by the per-kernel profiler (the per-operator time

@@ -100,6 +100,13 @@ SIGNATURES = {
     "rel_pipeline_batch_graph": (_I, [_P, _I, _P, _P, _S, _P]),
     "rel_graph_launch": (_I, [_P, _P]),
     "rel_graph_destroy": (None, [_P]),
+    "rel_server_create": (_I, [_P, _P]),
+    "rel_server_submit": (_I, [_P, _P, _P, _P, _P]),
+    "rel_server_poll": (_I, [_P, _P, _I]),
+    "rel_server_drain": (_I, [_P, _L]),
+    "rel_server_stats": (_I, [_P, _P, _P, _P]),
+    "rel_server_now_ns": (_L, []),
+    "rel_server_destroy": (None, [_P]),
     "rel_kernel_name": (ctypes.c_char_p, [_I]),
     "rel_profile_enable": (None, [_I]),
     "rel_profile_read": (_I, [_P, _P]),
