@@ -196,6 +196,113 @@ def bench_batch(args, torch, datagen, rel) -> dict:
     }
 
 
+SERVE_AGGS = [("sum", 3), ("count", None)]
+
+
+class QueryPool:
+    """Plans of the served queries, recycled: per grouping attribute a fixed
+    set of plans with device and pinned host outputs; query i takes a free one
+    of its attribute and sets its date range (the server copies the plan at
+    submission), and gives it back when it completes. With none free the
+    query waits on the client (its latency still counts from its arrival)."""
+
+    def __init__(self, rel, serve, fact, dims, groups, attr, lo, hi, per_attr):
+        self.attr, self.lo, self.hi = attr, lo, hi
+        self.free = {}
+        for a in range(len(dims)):
+            self.free[a] = []
+            for _ in range(per_attr):
+                plan = rel.Plan(fact, [(2, "range", 0, 1)], [dims[a]], [("dim", 0)], SERVE_AGGS,
+                                groups[a])
+                self.free[a].append((plan, serve.HostResult(plan)))
+        self.busy = {}
+
+    def make(self, i):
+        a = int(self.attr[i])
+        if not self.free[a]:
+            return None
+        plan, host = self.free[a].pop()
+        plan._preds[0].lo = int(self.lo[i])
+        plan._preds[0].hi = int(self.hi[i])
+        self.busy[i] = (a, plan, host)
+        return plan, host
+
+    def done(self, i, completion):
+        a, plan, host = self.busy.pop(i)
+        self.free[a].append((plan, host))
+
+
+def bench_serve(args, torch, datagen, rel) -> dict:
+    """Queries over a resident 200M-row star schema: date range of 1-50%
+    selectivity, join with the dim holding the grouping attribute (dim B
+    region: 25 groups, dim B city: 5,000, dim A segment: 1,000,000),
+    SUM(price) and COUNT(*). A seeded Poisson trace at multiples of the
+    measured one-at-a-time capacity is replayed against the server serving
+    one query at a time and with continuous batching."""
+    from paper_2508_04701_amd import serve
+
+    seed = datagen.SEED0 + 5
+    n_fact = args.serve_rows
+    t0 = time.perf_counter()
+    d = datagen.star_schema(seed=seed, n_fact=n_fact)
+    nb, na = len(d["dim_b_key"]), len(d["dim_a_key"])
+    city = (datagen.permutation(seed, 70, nb) % 5_000).astype(np.int32)
+    segment = (datagen.permutation(seed, 71, na) % 1_000_000).astype(np.int32)
+    cols = {k: torch.from_numpy(v).cuda() for k, v in d.items()}
+    fact = [cols[k] for k in ("fk_a", "fk_b", "date", "price", "flag")]
+    dims = [dict(fk=1, key=cols["dim_b_key"], payload=cols["dim_b_region"]),
+            dict(fk=1, key=cols["dim_b_key"], payload=torch.from_numpy(city).cuda()),
+            dict(fk=0, key=cols["dim_a_key"], payload=torch.from_numpy(segment).cuda())]
+    groups = [25, 5_000, 1_000_000]
+    del d
+    nq = args.serve_queries
+    u = (datagen.raw_u64(seed, 72, nq) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    w = np.rint((0.01 + 0.49 * u) * 2557).astype(np.int64)
+    v = (datagen.raw_u64(seed, 74, nq) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    lo = np.floor(v * (2557 - w + 1)).astype(np.int64)
+    attr = (datagen.raw_u64(seed, 75, nq) % np.uint64(3)).astype(np.int64)
+    hi = lo + w
+    pool = QueryPool(rel, serve, fact, dims, groups, attr, lo, hi, args.serve_pool)
+    torch.cuda.synchronize()
+    log(f"serve: {n_fact} resident fact rows, {nq} queries, ready in "
+        f"{time.perf_counter() - t0:.1f} s")
+    arena_bytes = args.serve_arena_gb << 30
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+
+    modes = {"one_at_a_time": dict(max_slots=1, max_batch=1, lanes=1),
+             "continuous": dict(max_slots=64, max_batch=16, lanes=2)}
+
+    def run(mode, arrivals, count):
+        srv = serve.Server(arena_bytes, arena_ptr=arena.data_ptr(), **modes[mode])
+        out = serve.replay(srv, pool.make, arrivals[:count], on_done=pool.done)
+        st = srv.stats()
+        srv.close()
+        out.pop("tickets")
+        out["rows_per_s"] = count * n_fact / out["wall_s"]
+        out["batches"] = st["batches"]
+        return out
+
+    # capacity: a burst served one query at a time, warm
+    run("one_at_a_time", np.zeros(32), 32)
+    burst = run("one_at_a_time", np.zeros(args.serve_calib), args.serve_calib)
+    capacity = args.serve_calib / burst["wall_s"]
+    log(f"serve: one-at-a-time capacity {capacity:.1f} queries/s")
+    result = {"workload": f"{n_fact}-row resident star schema, date range 1-50% selectivity, "
+                          "group by dim B region (25) / city (5k) / dim A segment (1M), "
+                          "SUM(price), COUNT(*); seeded Poisson arrivals",
+              "fact_rows": n_fact, "capacity_one_at_a_time_qps": capacity, "rates": []}
+    for x in args.serve_rates:
+        count = nq if x == 0.8 else min(nq, args.serve_sweep_queries)
+        arrivals = serve.poisson_arrivals(seed, count, x * capacity)
+        point = {"x_capacity": x, "qps": x * capacity, "queries": count}
+        for mode in modes:
+            point[mode] = run(mode, arrivals, count)
+            log(f"serve: {x}x {mode}: p50 {point[mode]['p50_ms']:.2f} ms, p99 "
+                f"{point[mode]['p99_ms']:.2f} ms, {point[mode]['rows_per_s'] / 1e9:.1f} G rows/s")
+        result["rates"].append(point)
+    return result
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +316,15 @@ def main() -> int:
     ap.add_argument("--batch-only", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--serve-rows", type=int, default=200_000_000)
+    ap.add_argument("--serve-queries", type=int, default=2000)
+    ap.add_argument("--serve-sweep-queries", type=int, default=400)
+    ap.add_argument("--serve-calib", type=int, default=100)
+    ap.add_argument("--serve-pool", type=int, default=96)
+    ap.add_argument("--serve-arena-gb", type=int, default=64)
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[0.5, 0.8, 1.2, 2.0])
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -237,6 +353,9 @@ def main() -> int:
         return 0
     if args.batch_only:
         print(json.dumps({"batch": bench_batch(args, torch, datagen, rel)}), flush=True)
+        return 0
+    if args.serve_only:
+        print(json.dumps({"serving": bench_serve(args, torch, datagen, rel)}), flush=True)
         return 0
     seed = datagen.SEED0 + 2 if args.seed is None else args.seed
     n = args.n_fact
@@ -314,6 +433,10 @@ def main() -> int:
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         out["batch"] = bench_batch(args, torch, datagen, rel)
+    if not args.no_serve:
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out["serving"] = bench_serve(args, torch, datagen, rel)
     print(json.dumps(out), flush=True)
     return 0
 

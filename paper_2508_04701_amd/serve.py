@@ -155,24 +155,37 @@ def poisson_arrivals(seed: int, n: int, qps: float) -> np.ndarray:
     return np.cumsum(-np.log1p(-u) / qps)
 
 
-def replay(server: Server, plans: list, arrivals: np.ndarray, hosts: list | None = None) -> dict:
-    """Submits plans[i] at arrivals[i] seconds after the start (busy-waiting
-    between arrivals, collecting completions meanwhile), waits for all, and
-    returns per-query latency (arrival -> done, server clock) and the wall
-    time from the first arrival to the last completion."""
-    n = len(plans)
+def replay(server: Server, plans, arrivals: np.ndarray, hosts: list | None = None,
+           on_done=None) -> dict:
+    """Submits query i at arrivals[i] seconds after the start, collecting
+    completions meanwhile; returns per-query latency statistics (scheduled
+    arrival -> done on the server clock, so a late submission counts against
+    the query) and the wall time from the start to the last completion.
+
+    plans: a list of plans (with `hosts` their host buffers), or a callable
+    make(i) -> (plan, host) or None when query i cannot be formed yet (it is
+    retried); on_done(i, completion) is called as each query completes."""
+    n = len(arrivals)
+    make = plans if callable(plans) else (lambda i: (plans[i], hosts[i] if hosts else None))
     t0 = now_ns() + 2_000_000
     due = t0 + (np.asarray(arrivals) * 1e9).astype(np.int64)
     done = {}
-    tickets = []
+    index = {}
+    tickets = [None] * n
     i = 0
     while i < n or len(done) < n:
         now = now_ns()
         while i < n and due[i] <= now:
-            tickets.append(server.submit(plans[i], hosts[i] if hosts else None))
+            q = make(i)
+            if q is None:
+                break
+            tickets[i] = server.submit(q[0], q[1])
+            index[tickets[i]] = i
             i += 1
         for c in server.poll():
             done[c["ticket"]] = c
+            if on_done is not None:
+                on_done(index[c["ticket"]], c)
         if i < n and due[i] - now_ns() > 200_000:
             time.sleep(50e-6)
     lat = np.array([done[t]["t_done_ns"] - due[k] for k, t in enumerate(tickets)], np.int64)
@@ -180,7 +193,8 @@ def replay(server: Server, plans: list, arrivals: np.ndarray, hosts: list | None
     batch = np.array([done[t]["batch_size"] for t in tickets])
     wall = max(c["t_done_ns"] for c in done.values()) - t0
     ok = lat[status == 0]
-    return dict(n=n, ok=int((status == 0).sum()), wall_s=wall / 1e9,
-                p50_ms=float(np.percentile(ok, 50, method="inverted_cdf")) / 1e6 if len(ok) else None,
-                p99_ms=float(np.percentile(ok, 99, method="inverted_cdf")) / 1e6 if len(ok) else None,
+    pct = (lambda q: float(np.percentile(ok, q, method="inverted_cdf")) / 1e6) if len(ok) else \
+        (lambda q: None)
+    return dict(n=n, ok=int((status == 0).sum()), wall_s=wall / 1e9, p50_ms=pct(50),
+                p99_ms=pct(99), max_ms=float(ok.max()) / 1e6 if len(ok) else None,
                 mean_batch=float(batch.mean()), tickets=tickets)
