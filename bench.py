@@ -113,26 +113,26 @@ def cpu_baseline(d: dict, n_fact: int, target_s: float) -> dict:
 def bench_batch(args, torch, datagen, rel) -> dict:
     """256 join + group-by instances of log-uniform sizes (build 1k-4M rows,
     probe 10k-50M rows, 8-100k groups; SUM(value), COUNT(*) by the build
-    side's group attribute): one rel_pipeline_batch launch sequence, its
-    captured graph, and 256 sequential rel_pipeline calls, on the same
-    resident inputs. Results must be identical."""
+    side's group attribute): 256 sequential rel_pipeline calls, one
+    rel_pipeline_batch launch sequence and its captured graph, on the same
+    resident inputs, first with default tuning, then with per-instance
+    records from the autotuner. Results must be identical throughout."""
+    from paper_2508_04701_amd import autotune
+
     seed = datagen.SEED0 + 4
     shapes = datagen.batch_shapes(seed=seed, n_inst=args.batch_instances)
     aggs = [("sum", 1), ("count", None)]
     t0 = time.perf_counter()
-    singles, plans = [], []
+    inputs = []
     n_probe = n_build = 0
     for i, s in enumerate(shapes):
         d = datagen.batch_instance(seed, i, **s)
         fact = [torch.from_numpy(d["probe_key"]).cuda(), torch.from_numpy(d["probe_val"]).cuda()]
         dims = [dict(fk=0, key=torch.from_numpy(d["build_key"]).cuda(),
                      payload=torch.from_numpy(d["build_grp"]).cuda())]
-        mg = max(1, s["n_groups"])
-        singles.append(rel.PreparedPipeline(fact, [], dims, [("dim", 0)], aggs, mg))
-        plans.append(rel.Plan(fact, [], dims, [("dim", 0)], aggs, mg))
+        inputs.append((fact, dims, max(1, s["n_groups"])))
         n_probe += s["n_probe"]
         n_build += s["n_build"]
-    batch = rel.PreparedBatch(plans)
     torch.cuda.synchronize()
     log(f"batch: {len(shapes)} instances, {n_build} build rows, {n_probe} probe rows "
         f"ready in {time.perf_counter() - t0:.1f} s")
@@ -148,51 +148,100 @@ def bench_batch(args, torch, datagen, rel) -> dict:
         torch.cuda.synchronize()
         return start.elapsed_time(stop) / steps
 
-    def sequential():
-        for p in singles:
-            p.launch()
+    def canon(plan):
+        k, a = plan.result()
+        o = torch.argsort(k[0])
+        return [k[0][o]] + [x[o] for x in a]
 
-    steps = args.batch_steps
-    sequential()
-    batch.launch()
-    torch.cuda.synchronize()
-    seq_ms = timed(sequential, steps)
-    batch_ms = timed(batch.launch, steps)
-    rel.profile_read()
-    rel.profile_enable(True)
-    batch.launch()
-    torch.cuda.synchronize()
-    rel.profile_enable(False)
-    prof = rel.profile_read()
-    batch.capture()
-    batch.launch_graph()
-    graph_ms = timed(batch.launch_graph, steps)
-    # identical results: every instance of the graph replay against its
-    # sequential call
-    identical = True
-    for a, b in zip(singles, plans):
-        ka, aa = a.result()
-        kb, ab = b.result()
-        oa, ob = torch.argsort(ka[0]), torch.argsort(kb[0])
-        if not (torch.equal(ka[0][oa], kb[0][ob]) and
-                all(torch.equal(x[oa], y[ob]) for x, y in zip(aa, ab))):
-            identical = False
-    batch.release()
-    fused_ms, fused_n = prof["pipeline_fused"]
+    def measure(tunings, chunk=0):
+        singles = [rel.PreparedPipeline(f, [], dm, [("dim", 0)], aggs, g, t)
+                   for (f, dm, g), t in zip(inputs, tunings)]
+        t_first = rel.tuning(chunk_tiles=chunk) if tunings[0] is None else \
+            rel.tuning(**{**{k: getattr(tunings[0], k) for k in autotune.FIELDS}, "chunk_tiles": chunk})
+        plans = [rel.Plan(f, [], dm, [("dim", 0)], aggs, g, t_first if i == 0 else t)
+                 for i, ((f, dm, g), t) in enumerate(zip(inputs, tunings))]
+        batch = rel.PreparedBatch(plans)
+
+        def sequential():
+            for p in singles:
+                p.launch()
+
+        sequential()
+        batch.launch()
+        torch.cuda.synchronize()
+        seq_ms = timed(sequential, args.batch_steps)
+        batch_ms = timed(batch.launch, args.batch_steps)
+        rel.profile_read()
+        rel.profile_enable(True)
+        batch.launch()
+        torch.cuda.synchronize()
+        rel.profile_enable(False)
+        prof = rel.profile_read()
+        batch.capture()
+        batch.launch_graph()
+        graph_ms = timed(batch.launch_graph, args.batch_steps)
+        results = [canon(p) for p in plans]
+        same = all(len(x) == len(y) and all(torch.equal(u, v) for u, v in zip(x, y))
+                   for x, y in zip(results, [canon(p) for p in singles]))
+        batch.release()
+        out = {"sequential_ms": seq_ms, "batched_ms": batch_ms, "graph_ms": graph_ms,
+               "speedup_vs_sequential": seq_ms / min(batch_ms, graph_ms),
+               "fused_kernel_ms": prof["pipeline_fused"][0] / max(1, prof["pipeline_fused"][1]),
+               "breakdown_ms": {k: round(v[0], 4) for k, v in prof.items() if v[1]}}
+        del singles, plans, batch
+        torch.cuda.empty_cache()
+        return out, results, same
+
+    default, ref, same_default = measure([None] * len(inputs))
+    log(f"batch default: {default['sequential_ms']:.1f} ms sequential, "
+        f"{default['batched_ms']:.1f} ms batched, {default['graph_ms']:.1f} ms graph")
+
+    # autotuner: one record per size bucket, tuned on its median instance
+    # (probe side cut to at most 8M rows)
+    t0 = time.perf_counter()
+    cache = autotune.Cache()
+    by_bucket = {}
+    for i, (f, dm, g) in enumerate(inputs):
+        b = autotune.plan_bucket(f[0].numel(), [dm[0]["key"].numel()], g)
+        by_bucket.setdefault(b, []).append(i)
+    for b, members in by_bucket.items():
+        members.sort(key=lambda i: inputs[i][0][0].numel())
+        f, dm, g = inputs[members[len(members) // 2]]
+        cut = min(f[0].numel(), 8_000_000)
+        sample = [f[0][:cut], f[1][:cut]]
+        rec = autotune.tune_plan(lambda t: rel.PreparedPipeline(sample, [], dm, [("dim", 0)],
+                                                                aggs, g, t))
+        cache.put(autotune.cache_key("join_groupby", b), rec)
+    tune_s = time.perf_counter() - t0
+    tunings = [autotune.tuning_for(cache, "join_groupby", f[0].numel(), [dm[0]["key"].numel()], g)
+               for f, dm, g in inputs]
+    best = None
+    for chunk in args.batch_chunks:
+        res, got, same = measure(tunings, chunk)
+        same = same and all(all(torch.equal(u, v) for u, v in zip(x, y)) for x, y in zip(got, ref))
+        res["chunk_tiles"] = chunk
+        res["identical_results"] = same
+        log(f"batch tuned (chunk {chunk}): {res['sequential_ms']:.1f} ms sequential, "
+            f"{res['batched_ms']:.1f} ms batched, {res['graph_ms']:.1f} ms graph, same {same}")
+        if best is None or min(res["batched_ms"], res["graph_ms"]) < \
+                min(best["batched_ms"], best["graph_ms"]):
+            best = res
+    if args.tune_cache_out:
+        cache.save(args.tune_cache_out)
     alg = 12 * n_probe + 8 * n_build
-    best = min(batch_ms, graph_ms)
+    best_ms = min(best["batched_ms"], best["graph_ms"])
     return {
         "workload": f"{len(shapes)} join+group-by instances, log-uniform build 1k-4M, "
                     f"probe 10k-50M, groups 8-100k",
         "instances": len(shapes), "probe_rows": n_probe, "build_rows": n_build,
-        "sequential_ms": seq_ms, "batched_ms": batch_ms, "graph_ms": graph_ms,
-        "sequential_rows_per_s": n_probe / (seq_ms * 1e-3),
-        "batched_rows_per_s": n_probe / (best * 1e-3),
-        "speedup_vs_sequential": seq_ms / best,
-        "identical_results": identical,
-        "algorithmic_bytes": alg, "hbm_frac_step": alg / (best * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "fused_kernel_ms": fused_ms / max(1, fused_n),
-        "breakdown_ms": {k: round(v[0], 4) for k, v in prof.items() if v[1]},
+        "default": {**default, "identical_results": same_default},
+        "tuned": best,
+        "autotune": {"buckets": len(by_bucket), "seconds": tune_s},
+        "batched_rows_per_s": n_probe / (best_ms * 1e-3),
+        "sequential_rows_per_s": n_probe / (best["sequential_ms"] * 1e-3),
+        "speedup_vs_sequential": best["sequential_ms"] / best_ms,
+        "identical_results": same_default and best["identical_results"],
+        "algorithmic_bytes": alg, "hbm_frac_step": alg / (best_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
     }
 
 
@@ -316,6 +365,9 @@ def main() -> int:
     ap.add_argument("--batch-only", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--batch-chunks", type=int, nargs="*", default=[0, 2])
+    ap.add_argument("--tune-cache-out", default=None,
+                    help="write the autotuner records of the batched section to this JSON file")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-rows", type=int, default=200_000_000)

@@ -1,0 +1,137 @@
+"""Autotuner of the fused plans: per size bucket, the tuning record (global
+group-table replicas, LDS group table on or off, group-table load factor)
+with the lowest measured device time among candidates that all return
+identical results (any difference is a race and raises). Records persist
+as JSON keyed by (GPU architecture, operation, size bucket) and are applied
+per plan, also to each instance of a batch.
+
+A bucket is the magnitude (in steps of 4x) of the fact rows, the largest dim
+and the group bound: plans within a bucket share the behaviour the knobs trade off
+(how many rows reach the group table, whether the groups fit the LDS
+table, how many hot lines the global atomics meet).
+"""
+
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+import torch
+
+from . import rel
+
+CANDIDATES = [
+    {},
+    {"replicas": 1},
+    {"replicas": 8},
+    {"replicas": 32},
+    {"replicas": 64},
+    {"lds_slots": -1, "replicas": 32},
+    {"load_factor": 0.3},
+    {"load_factor": 0.3, "replicas": 32},
+]
+
+FIELDS = ("load_factor", "lds_slots", "replicas", "chunk_tiles", "dim_lds_bytes", "grid")
+
+
+def arch() -> str:
+    if not torch.cuda.is_available():
+        return "none"
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def _mag(x: int) -> int:
+    return 0 if x <= 1 else int(math.ceil(math.log2(x)))
+
+
+def bucket(n_fact: int, n_dim: int, max_groups: int) -> str:
+    """Magnitudes in steps of 4x: f/d/g name the even exponent at or below
+    the ceiling log2 of each size."""
+    step = lambda x: 2 * (_mag(x) // 2)  # noqa: E731
+    return f"f{step(n_fact)}-d{step(n_dim)}-g{step(max_groups)}"
+
+
+def cache_key(op: str, b: str, gpu: str | None = None) -> str:
+    return f"{gpu or arch()}/{op}/{b}"
+
+
+class Cache:
+    """Tuning records: {key: {"tuning": {field: value}, "ms": best time,
+    "candidates": {candidate: ms}}}."""
+
+    def __init__(self, path: str | None = None):
+        self.path = path
+        self.records = {}
+        if path and os.path.exists(path):
+            with open(path) as f:
+                self.records = json.load(f)
+
+    def get(self, key: str):
+        r = self.records.get(key)
+        return None if r is None else r["tuning"]
+
+    def put(self, key: str, record: dict):
+        self.records[key] = record
+
+    def save(self, path: str | None = None):
+        path = path or self.path
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(self.records, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+
+
+def to_tuning(fields: dict | None) -> rel.Tuning | None:
+    if not fields:
+        return None
+    unknown = set(fields) - set(FIELDS)
+    if unknown:
+        raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+    return rel.tuning(**fields)
+
+
+def _canon(keys, aggs):
+    hk = [k.cpu().numpy().astype(np.int64) for k in keys]
+    ha = [a.cpu().numpy().view(np.int64) for a in aggs]
+    if hk:
+        order = np.lexsort(hk[::-1])
+        hk = [k[order] for k in hk]
+        ha = [a[order] for a in ha]
+    return hk + ha
+
+
+def tune_plan(make, candidates=CANDIDATES, reps: int = 3) -> dict:
+    """make(tuning) -> rel.PreparedPipeline. Times every candidate (after one
+    warm launch) with events on the current stream and checks that all return
+    the same groups. Returns {"tuning", "ms", "candidates"}."""
+    stream = torch.cuda.current_stream()
+    times, ref = {}, None
+    for cand in candidates:
+        plan = make(to_tuning(cand))
+        plan.launch()
+        got = _canon(*plan.result())
+        if ref is None:
+            ref = got
+        elif len(got) != len(ref) or not all(np.array_equal(a, b) for a, b in zip(got, ref)):
+            raise RuntimeError(f"tuning candidate {cand} changed the result: a race")
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(reps):
+            plan.launch()
+        stop.record(stream)
+        stop.synchronize()
+        times[json.dumps(cand, sort_keys=True)] = start.elapsed_time(stop) / reps
+        del plan
+    best = min(times, key=times.get)
+    return {"tuning": json.loads(best), "ms": times[best], "candidates": times}
+
+
+def plan_bucket(n_fact: int, dim_rows: list, max_groups: int) -> str:
+    return bucket(n_fact, max(dim_rows) if dim_rows else 0, max_groups)
+
+
+def tuning_for(cache: Cache, op: str, n_fact: int, dim_rows: list, max_groups: int):
+    """The cached record of the plan's bucket as a rel.Tuning (None: defaults)."""
+    return to_tuning(cache.get(cache_key(op, plan_bucket(n_fact, dim_rows, max_groups))))

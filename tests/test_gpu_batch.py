@@ -225,3 +225,35 @@ def test_batch_plans_sharing_one_fact_table():
     torch.cuda.synchronize()
     for q, (spec, plan) in enumerate(zip(specs, b.plans)):
         assert_groups(plan.result(), oracle_of(spec), aggs, f"shared-scan query {q}")
+
+
+def test_autotuner_candidates_agree_and_records_apply_to_batches():
+    """Every tuning candidate returns the same groups (the tuner raises
+    otherwise: a race detector), and a batch whose instances carry the tuned
+    records still equals the oracle."""
+    import json
+
+    from paper_2508_04701_amd import autotune
+    announce("autotuner")
+    insts = join_instances(707, 6, (1_000, 20_000), (10_000, 300_000), (8, 5_000))
+    specs = [join_spec(i) for i in insts]
+    cache = autotune.Cache()
+    tunings = []
+    for spec in specs:
+        fact, terms, dims, keys, aggs, mg = spec
+        dfact = [dev(c) for c in fact]
+        ddims = [dict(fk=0, key=dev(dims[0]["key"]), payload=dev(dims[0]["payload"]))]
+        rec = autotune.tune_plan(
+            lambda t: rel.PreparedPipeline(dfact, terms, ddims, keys, aggs, mg, t))
+        assert set(rec["candidates"]) == {json.dumps(c, sort_keys=True)
+                                          for c in autotune.CANDIDATES}
+        b = autotune.plan_bucket(len(fact[0]), [len(dims[0]["key"])], mg)
+        cache.put(autotune.cache_key("join_groupby", b), rec)
+        tunings.append(autotune.tuning_for(cache, "join_groupby", len(fact[0]),
+                                           [len(dims[0]["key"])], mg))
+    plans = [device_plan(s, t) for s, t in zip(specs, tunings)]
+    b = rel.PreparedBatch(plans)
+    b.launch()
+    torch.cuda.synchronize()
+    for i, (spec, plan) in enumerate(zip(specs, b.plans)):
+        assert_groups(plan.result(), oracle_of(spec), AGGS, f"tuned instance {i}")
