@@ -106,7 +106,7 @@ typedef struct {
   int32_t block;     /* threads per workgroup, a multiple of 64 up to 1024; 0 = default */
   int32_t grid;      /* workgroups of persistent kernels; 0 = default (from the CU count) */
   int32_t lds_slots; /* slots of the per-workgroup LDS group table; 0 = default, -1 = none */
-  int32_t flags;     /* reserved, must be 0 */
+  int32_t flags;     /* REL_TUNE_* bits; 0 = none */
   int32_t dim_lds_bytes; /* LDS bytes rel_pipeline may give to dim tables; 0 = default (32 KB),
                             -1 = none */
   int32_t chunk_tiles;   /* rel_pipeline_batch: fact tiles (2048 rows) per work item of the
@@ -115,6 +115,10 @@ typedef struct {
                             w mod replicas (w mod 8 is its XCD) and a last pass folds them;
                             0 = default (64 when all groups fit the LDS tables, else 1) */
 } rel_tuning;
+
+/* rel_tuning.flags: keep dims of rel_pipeline in their hash tables even when
+ * the build keys are dense (see rel_pipeline). */
+#define REL_TUNE_NO_DIRECT 1
 
 #define REL_MAX_TERMS 4
 #define REL_MAX_DIMS 2

@@ -63,7 +63,7 @@ rel_status check_tuning(const rel_tuning* t) {
   if (t->grid < 0) return fail(REL_EINVAL, "tuning.grid must be >= 0");
   if (t->lds_slots < -1 || (t->lds_slots > 0 && (t->lds_slots & (t->lds_slots - 1)) != 0))
     return fail(REL_EINVAL, "tuning.lds_slots must be -1, 0 or a power of two");
-  if (t->flags != 0) return fail(REL_EINVAL, "tuning.flags must be 0");
+  if (t->flags & ~REL_TUNE_NO_DIRECT) return fail(REL_EINVAL, "tuning.flags: unknown bits");
   if (t->chunk_tiles < 0) return fail(REL_EINVAL, "tuning.chunk_tiles must be >= 0");
   if (t->replicas < 0 || t->replicas > 256)
     return fail(REL_EINVAL, "tuning.replicas must be in [0, 256]");
@@ -113,7 +113,26 @@ struct MapLayout {
   int rbits;
   uint64_t over_cap;  // compact: overflow set slots (at oob_vals_off)
   size_t slots_off, oob_count_off, oob_vals_off, end;
+  uint64_t nkeys;
+  uint64_t direct_cap;          // 0: none
+  size_t dbits_off, dvals_off;  // dvals_off 0: no payload array
 };
+
+// Direct tables cover key ranges up to this many times the build size.
+constexpr uint64_t kDirectSpan = 2;
+
+// Reserves a direct table after layout m (int32 keys): a presence bitmap and,
+// with a payload, 4 bytes per entry; the build uses it if the keys allow.
+void add_direct(MapLayout& m, int64_t n, bool payload) {
+  m.direct_cap = (kDirectSpan * static_cast<uint64_t>(n > 0 ? n : 1) + 63) / 64 * 64;
+  m.dbits_off = m.end;
+  m.end = align_up(m.dbits_off + m.direct_cap / 8);
+  m.dvals_off = 0;
+  if (payload) {
+    m.dvals_off = m.end;
+    m.end = align_up(m.dvals_off + m.direct_cap * 4);
+  }
+}
 
 // Compact membership sets: eight 16-bit entries per 16-byte bucket, filled
 // to at most this load factor; used when the remainder fits 14 bits.
@@ -126,6 +145,9 @@ MapLayout map_layout(int32_t key_type, int64_t n, float lf, size_t base, bool ke
   m.compact = false;
   m.rbits = 0;
   m.over_cap = 0;
+  m.nkeys = static_cast<uint64_t>(n > 0 ? n : 0);
+  m.direct_cap = 0;
+  m.dbits_off = m.dvals_off = 0;
   if (key_only && allow_compact && key_type == REL_I32) {
     const uint64_t buckets = next_pow2(static_cast<uint64_t>(std::ceil(n / (8 * kCsetLoad))));
     int bits = 0;
@@ -170,6 +192,11 @@ MapDesc map_desc(const MapLayout& l, int32_t key_type, unsigned char* ws) {
   d.oob_count = reinterpret_cast<unsigned long long*>(ws + l.oob_count_off);
   d.dup = reinterpret_cast<int32_t*>(ws + l.oob_count_off + 8);
   d.oob_vals = reinterpret_cast<uint32_t*>(ws + l.oob_vals_off);
+  d.nkeys = l.nkeys;
+  d.direct_cap = l.direct_cap;
+  d.dstate = reinterpret_cast<int32_t*>(ws + l.oob_count_off + 16);
+  d.dbits = l.direct_cap ? reinterpret_cast<uint32_t*>(ws + l.dbits_off) : nullptr;
+  d.dvals = (l.direct_cap && l.dvals_off) ? static_cast<void*>(ws + l.dvals_off) : nullptr;
   return d;
 }
 
@@ -422,6 +449,9 @@ rel_status pipeline_layout(const rel_pipeline_desc* d, PipeLayout& L, bool batch
     const bool key_only = d->dims[i].key.type == REL_I32 && !d->dims[i].has_payload;
     L.dim[i] = map_layout(d->dims[i].key.type, d->dims[i].key.len, lf < 0.75f ? 0.75f : lf, off,
                           key_only, !batch);
+    const bool no_direct = d->tuning && (d->tuning->flags & REL_TUNE_NO_DIRECT);
+    if (d->dims[i].key.type == REL_I32 && !no_direct)
+      add_direct(L.dim[i], d->dims[i].key.len, d->dims[i].has_payload != 0);
     off = L.dim[i].end;
   }
   for (int k = 0; k < d->n_keys; ++k) {
@@ -529,6 +559,8 @@ void plan_params(const rel_pipeline_desc* d, const PipeLayout& L, unsigned char*
     p.dim[i].fk_col = dm.fact_col;
     const size_t bytes = L.dim[i].cap * L.dim[i].slot_bytes;
     if (!batch && dm.key.type == REL_I32 && !L.dim[i].compact && dim_used + bytes <= dim_budget) {
+      // the LDS copy is of the slot array, which must then always be built
+      p.dim[i].map.direct_cap = 0;
       p.dim[i].in_lds = 1;
       p.dim[i].lds_offset = static_cast<uint32_t>(lds);
       lds += bytes;
@@ -627,6 +659,8 @@ rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
     off = B.L[i].end;
     for (int k = 0; k < d[i].n_dims; ++k) {
       B.nfill += ceil_div(map_words(B.L[i].dim[k], d[i].dims[k].key.type), kFillChunk) + 1;
+      if (B.L[i].dim[k].direct_cap)
+        B.nfill += 1 + ceil_div(B.L[i].dim[k].direct_cap / 64, kFillChunk);
       B.nbuild += ceil_div(static_cast<uint64_t>(d[i].dims[k].key.len), kBuildChunk);
     }
     const GroupLayout& g = B.L[i].group;
@@ -738,6 +772,10 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
         push_fill(fill, static_cast<uint64_t*>(m.slots), words, kFillConst, kEmptySlot32, i);
       // the out-of-band count and the duplicate flag
       push_fill(fill, reinterpret_cast<uint64_t*>(m.oob_count), 2, kFillConst, 0, i);
+      if (m.direct_cap) {
+        push_fill(fill, reinterpret_cast<uint64_t*>(m.dstate), 2, kFillConst, kDirectStateInit, i);
+        push_fill(fill, reinterpret_cast<uint64_t*>(m.dbits), m.direct_cap / 64, kFillConst, 0, i);
+      }
       push_items(build_items, i, k, static_cast<uint64_t>(d[i].dims[k].key.len), kBuildChunk);
     }
     const GroupDesc& g = p.g;

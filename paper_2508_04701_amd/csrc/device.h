@@ -337,6 +337,7 @@ struct MapCursor {
   uint64_t pos;
   bool oob;
   bool live;
+  bool direct;  // pipeline dims held as a direct table: pos = found << 32 | payload
 };
 
 __device__ __forceinline__ MapCursor map_start32(const Map32& m, int32_t key) {
@@ -344,6 +345,7 @@ __device__ __forceinline__ MapCursor map_start32(const Map32& m, int32_t key) {
   c.oob = (key == kEmpty32);
   c.pos = c.oob ? 0 : home32(key, m.mask);
   c.live = true;
+  c.direct = false;
   return c;
 }
 
@@ -352,6 +354,7 @@ __device__ __forceinline__ MapCursor map_start64(const Map64& m, int64_t key) {
   c.oob = (static_cast<uint64_t>(key) == kEmpty64);
   c.pos = c.oob ? 0 : home64(key, m.mask);
   c.live = true;
+  c.direct = false;
   return c;
 }
 

@@ -77,7 +77,84 @@ struct MapDesc {
   int32_t* dup;        // set by the build when a key occurs twice
   uint32_t* over;      // compact: overflow key-only set
   uint64_t over_cap;   // compact: its slots (power of two)
+  // Dense keys (int32 only): when the build keys span at most direct_cap
+  // values and none repeats, key k is held at index k - kmin of a presence
+  // bitmap and, with a payload, of a payload array, instead of the slot
+  // array. The build decides on the device; see DirectState.
+  uint64_t direct_cap;   // 0: no direct table reserved
+  uint64_t nkeys;        // build keys
+  uint32_t* dbits;       // direct_cap bits
+  void* dvals;           // direct_cap payload entries (1, 2 or 4 bytes each), or NULL
+  int32_t* dstate;       // DirectState
 };
+
+// Key and payload ranges of a build (device, reduced by the first build
+// pass; kmin/pmin start at INT32_MAX, kmax/pmax at INT32_MIN).
+enum DirectState : int { kDKmin = 0, kDKmax = 1, kDPmin = 2, kDPmax = 3 };
+// Two 64-bit words that initialise a DirectState: (INT32_MAX, INT32_MIN) twice.
+constexpr uint64_t kDirectStateInit = 0x800000007FFFFFFFULL;
+
+// A direct table as its readers see it (uniform values). Payload entries
+// hold payload - pmin in the fewest bytes (1, 2 or 4) that cover the range.
+struct DirectView {
+  int32_t use;    // the table holds every build key exactly once
+  int32_t full;   // the keys are exactly [kmin, kmin + range): presence needs no read
+  int32_t width;  // payload bytes (0: no payload)
+  int32_t kmin, pmin;
+  uint64_t range;
+  const uint32_t* bits;
+  const void* vals;
+};
+
+__device__ __forceinline__ int direct_width(int32_t pmin, int32_t pmax) {
+  const int64_t span = static_cast<int64_t>(pmax) - pmin;
+  return span < 256 ? 1 : (span < 65536 ? 2 : 4);
+}
+
+// The key range of a build once its range pass is done (0: no keys), and
+// whether it fits the reserved table.
+__device__ __forceinline__ uint64_t direct_range(const MapDesc& m) {
+  const int32_t kmin = m.dstate[kDKmin], kmax = m.dstate[kDKmax];
+  if (kmax < kmin) return 0;
+  return static_cast<uint64_t>(static_cast<int64_t>(kmax) - kmin + 1);
+}
+
+// Valid after the build: duplicates send the dim back to its slot array.
+__device__ __forceinline__ DirectView direct_view(const MapDesc& m) {
+  DirectView v;
+  v.use = 0;
+  v.full = 0;
+  v.width = 0;
+  v.kmin = 0;
+  v.pmin = 0;
+  v.range = 0;
+  v.bits = m.dbits;
+  v.vals = m.dvals;
+  if (m.direct_cap == 0) return v;
+  const uint64_t range = direct_range(m);
+  if (range == 0 || range > m.direct_cap || *m.dup) return v;
+  v.use = 1;
+  v.range = range;
+  v.full = range == m.nkeys;
+  v.kmin = m.dstate[kDKmin];
+  if (m.dvals) {
+    v.pmin = m.dstate[kDPmin];
+    v.width = direct_width(v.pmin, m.dstate[kDPmax]);
+  }
+  return v;
+}
+
+// Probe of a direct table: whether `key` is present, and its payload.
+__device__ __forceinline__ bool direct_probe(const DirectView& v, int64_t key, uint32_t& val) {
+  const uint64_t off = static_cast<uint64_t>(key - static_cast<int64_t>(v.kmin));
+  if (off >= v.range) return false;
+  const uint32_t i = static_cast<uint32_t>(off);
+  if (!v.full && !((v.bits[i >> 5] >> (i & 31)) & 1u)) return false;
+  if (v.width == 1) val = static_cast<uint32_t>(static_cast<const uint8_t*>(v.vals)[i]) + v.pmin;
+  else if (v.width == 2) val = static_cast<uint32_t>(static_cast<const uint16_t*>(v.vals)[i]) + v.pmin;
+  else if (v.width == 4) val = static_cast<const uint32_t*>(v.vals)[i] + static_cast<uint32_t>(v.pmin);
+  return true;
+}
 
 // Inserts n keys of column (data, idx, type); value of element i is
 // val_col[i] widened to 32 bits when val_col is set, else its row id.
@@ -92,6 +169,8 @@ struct MapBuildParams {
 };
 
 void launch_map_init(const MapDesc& m, hipStream_t s);
+// Three passes: key (and payload) ranges, the direct table if the range
+// allows, the slot array unless the direct table holds every key once.
 void launch_map_build(const MapBuildParams& p, hipStream_t s);
 
 // Probe: emits (value, probe row id) for every match, with a wave-aggregated

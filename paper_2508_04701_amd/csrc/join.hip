@@ -65,20 +65,109 @@ __device__ __forceinline__ void build_rows(const MapBuildParams& p, uint64_t i, 
   }
 }
 
+__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// Build pass 1 over elements i, i + stride, ... (the workgroup's loop bound
+// is uniform): key and payload ranges, reduced per wave, then one atomic
+// per wave and bound.
+__device__ __forceinline__ void range_rows(const MapBuildParams& p, uint64_t base, uint64_t end,
+                                           uint64_t stride) {
+  if (p.map.direct_cap == 0) return;
+  for (; base < end; base += stride) {
+    const uint64_t i = base + threadIdx.x;
+    int32_t kmin = INT32_MAX, kmax = INT32_MIN, pmin = INT32_MAX, pmax = INT32_MIN;
+    if (i < end) {
+      const int64_t r = p.idx ? static_cast<int64_t>(p.idx[i]) : static_cast<int64_t>(i);
+      kmin = kmax = static_cast<int32_t>(load_elem(p.keys, p.type, r));
+      if (p.val_col) pmin = pmax = static_cast<int32_t>(load_elem(p.val_col, p.val_type, r));
+    }
+    kmin = wave_min_i32(kmin);
+    kmax = wave_max_i32(kmax);
+    if (p.val_col) {
+      pmin = wave_min_i32(pmin);
+      pmax = wave_max_i32(pmax);
+    }
+    if (lane_id() == 0) {
+      int32_t* st = p.map.dstate;
+      if (kmin < st[kDKmin]) atomicMin(st + kDKmin, kmin);
+      if (kmax > st[kDKmax]) atomicMax(st + kDKmax, kmax);
+      if (p.val_col) {
+        if (pmin < st[kDPmin]) atomicMin(st + kDPmin, pmin);
+        if (pmax > st[kDPmax]) atomicMax(st + kDPmax, pmax);
+      }
+    }
+  }
+}
+
+// Build pass 2: when the key range fits, set each key's presence bit and
+// store its narrowed payload; a bit already set means a duplicate key.
+__device__ __forceinline__ void direct_rows(const MapBuildParams& p, uint64_t i, uint64_t end,
+                                            uint64_t stride) {
+  const MapDesc& m = p.map;
+  if (m.direct_cap == 0) return;
+  const uint64_t range = direct_range(m);
+  if (range == 0 || range > m.direct_cap) return;
+  const int32_t kmin = m.dstate[kDKmin];
+  const int32_t pmin = m.dstate[kDPmin];
+  const int width = p.val_col ? direct_width(pmin, m.dstate[kDPmax]) : 0;
+  for (; i < end; i += stride) {
+    const int64_t r = p.idx ? static_cast<int64_t>(p.idx[i]) : static_cast<int64_t>(i);
+    const uint32_t k = static_cast<uint32_t>(load_elem(p.keys, p.type, r) - kmin);
+    const uint32_t bit = 1u << (k & 31);
+    if (atomicOr(m.dbits + (k >> 5), bit) & bit) {
+      *m.dup = 1;
+      continue;
+    }
+    if (width == 0) continue;
+    const uint32_t v = static_cast<uint32_t>(load_elem(p.val_col, p.val_type, r)) -
+                       static_cast<uint32_t>(pmin);
+    if (width == 1) static_cast<uint8_t*>(m.dvals)[k] = static_cast<uint8_t>(v);
+    else if (width == 2) static_cast<uint16_t*>(m.dvals)[k] = static_cast<uint16_t>(v);
+    else static_cast<uint32_t*>(m.dvals)[k] = v;
+  }
+}
+
+// Build pass 3 (the slot array) is skipped when the direct table took every
+// key exactly once.
+__device__ __forceinline__ bool slots_needed(const MapDesc& m) { return !direct_view(m).use; }
+
 template <typename K>
-__global__ void __launch_bounds__(256) map_build_kernel(MapBuildParams p) {
-  build_rows<K>(p, blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x,
-                static_cast<uint64_t>(p.n), static_cast<uint64_t>(gridDim.x) * blockDim.x);
+__global__ void __launch_bounds__(256) map_build_kernel(MapBuildParams p, int pass) {
+  const uint64_t first = blockIdx.x * static_cast<uint64_t>(blockDim.x);
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  if (pass == 0) {
+    range_rows(p, first, static_cast<uint64_t>(p.n), stride);
+  } else if (pass == 1) {
+    direct_rows(p, first + threadIdx.x, static_cast<uint64_t>(p.n), stride);
+  } else if (slots_needed(p.map)) {
+    build_rows<K>(p, first + threadIdx.x, static_cast<uint64_t>(p.n), stride);
+  }
 }
 
 // One workgroup per build item: rows [begin, end) of one dim of one instance.
-__global__ void __launch_bounds__(256) batch_build_kernel(BatchParams b) {
+__global__ void __launch_bounds__(256) batch_build_kernel(BatchParams b, int pass) {
   const BatchItem& it = batch_at(b.build_items, blockIdx.x);
   const MapBuildParams& p = batch_at(b.builds, 2 * static_cast<uint64_t>(it.inst) + it.aux);
-  if (p.map.key_type == kI32)
-    build_rows<int32_t>(p, it.begin + threadIdx.x, it.end, blockDim.x);
-  else
-    build_rows<int64_t>(p, it.begin + threadIdx.x, it.end, blockDim.x);
+  if (pass == 0) {
+    range_rows(p, it.begin, it.end, blockDim.x);
+  } else if (pass == 1) {
+    direct_rows(p, it.begin + threadIdx.x, it.end, blockDim.x);
+  } else if (slots_needed(p.map)) {
+    if (p.map.key_type == kI32)
+      build_rows<int32_t>(p, it.begin + threadIdx.x, it.end, blockDim.x);
+    else
+      build_rows<int64_t>(p, it.begin + threadIdx.x, it.end, blockDim.x);
+  }
 }
 
 // One workgroup per fill item.
@@ -180,6 +269,11 @@ void launch_map_init(const MapDesc& m, hipStream_t s) {
   }
   // the out-of-band count and the duplicate flag share the header
   launch_fill64(reinterpret_cast<uint64_t*>(m.oob_count), 2, 0, s);
+  if (m.direct_cap) {
+    // empty key and payload ranges, no key present
+    launch_fill64(reinterpret_cast<uint64_t*>(m.dstate), 2, kDirectStateInit, s);
+    launch_fill64(reinterpret_cast<uint64_t*>(m.dbits), m.direct_cap / 64, 0, s);
+  }
 }
 
 void launch_map_build(const MapBuildParams& p, hipStream_t s) {
@@ -189,12 +283,15 @@ void launch_map_build(const MapBuildParams& p, hipStream_t s) {
   uint64_t blocks = (static_cast<uint64_t>(p.n) + 255) / 256;
   uint64_t limit = static_cast<uint64_t>(di.cu_count) * 8;
   if (blocks > limit) blocks = limit;
-  if (p.map.key_type == kI32)
-    hipLaunchKernelGGL(map_build_kernel<int32_t>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
-                       s, p);
-  else
-    hipLaunchKernelGGL(map_build_kernel<int64_t>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
-                       s, p);
+  // the range and direct passes only for maps with a direct table
+  for (int pass = p.map.direct_cap ? 0 : 2; pass < 3; ++pass) {
+    if (p.map.key_type == kI32)
+      hipLaunchKernelGGL(map_build_kernel<int32_t>, dim3(static_cast<unsigned>(blocks)), dim3(256),
+                         0, s, p, pass);
+    else
+      hipLaunchKernelGGL(map_build_kernel<int64_t>, dim3(static_cast<unsigned>(blocks)), dim3(256),
+                         0, s, p, pass);
+  }
 }
 
 void launch_batch_fill(const BatchParams& b, hipStream_t s) {
@@ -206,7 +303,8 @@ void launch_batch_fill(const BatchParams& b, hipStream_t s) {
 void launch_batch_build(const BatchParams& b, hipStream_t s) {
   if (b.nbuild == 0) return;
   ProfileScope ps(kKMapBuild, s);
-  hipLaunchKernelGGL(batch_build_kernel, dim3(b.nbuild), dim3(256), 0, s, b);
+  for (int pass = 0; pass < 3; ++pass)
+    hipLaunchKernelGGL(batch_build_kernel, dim3(b.nbuild), dim3(256), 0, s, b, pass);
 }
 
 void launch_map_probe(const MapProbeParams& p, int grid, int block, hipStream_t s) {

@@ -181,6 +181,17 @@ template <int D>
 __device__ __forceinline__ MapCursor dim_start(const PipeDim& d, int64_t key) {
   MapCursor c;
   c.live = true;
+  c.direct = false;
+  if constexpr (D == kMap || D == kSet || D == kCSet) {
+    const DirectView v = direct_view(d.map);
+    if (v.use) {
+      uint32_t val = 0;
+      c.direct = true;
+      c.oob = false;
+      c.pos = direct_probe(v, key, val) ? ((1ull << 32) | val) : 0;
+      return c;
+    }
+  }
   if constexpr (D == kCSet) {
     // the cursor counts down the key's multiplicity
     const CsetDesc cs = cset_of(d);
@@ -208,6 +219,15 @@ __device__ __forceinline__ bool dim_next(const PipeDim& d, const void* lds_copy,
                                          MapCursor& c, uint32_t& val) {
   const uint64_t mask = d.map.cap - 1;
   const void* base = dim_slots<D>(d, lds_copy);
+  if (c.direct) {
+    if (!c.live || (c.pos >> 32) == 0) {
+      c.live = false;
+      return false;
+    }
+    val = static_cast<uint32_t>(c.pos);
+    c.pos = 0;
+    return true;
+  }
   if constexpr (D == kCSet) {
     (void)mask;
     (void)base;
@@ -369,6 +389,21 @@ constexpr uint32_t kResolved = 0x80000000u;
 template <int D>
 constexpr bool kResumable = (D == kMap || D == kSet || D == kCSet || D == kMap64);
 
+// Dims whose build may pick a direct table (int32 keys read from HBM).
+template <int D>
+constexpr bool kDirectable = (D == kMap || D == kSet || D == kCSet);
+
+template <int D>
+__device__ __forceinline__ DirectView dim_direct(const PipeDim& d) {
+  if constexpr (kDirectable<D>) {
+    return direct_view(d.map);
+  } else {
+    DirectView v;
+    v.use = 0;
+    return v;
+  }
+}
+
 template <int D>
 __device__ __forceinline__ uint64_t start_bucket(const PipeDim& d, int64_t key) {
   if constexpr (D == kMap64) {
@@ -494,18 +529,23 @@ template <int D0, int D1>
 __device__ __forceinline__ bool process_row(const PipelineParams& p, int64_t r, int64_t fk0,
                                             int64_t fk1, uint32_t& st0, uint32_t& st1,
                                             const void* ld0, const void* ld1, uint64_t* lg,
-                                            const GroupTable& gt, int limit0, int limit1) {
+                                            const GroupTable& gt, int limit0, int limit1,
+                                            const DirectView& dv0, const DirectView& dv1) {
+  const bool dir0 = kDirectable<D0> && dv0.use;
+  const bool dir1 = kDirectable<D1> && dv1.use;
   const bool res0 = kResumable<D0> && limit0 == 1;
   const bool res1 = kResumable<D1> && limit1 == 1;
   uint4 q0 = make_uint4(0, 0, 0, 0), q1 = make_uint4(0, 0, 0, 0);
   if constexpr (D0 != kNone)
-    q0 = res0 ? probe_load<D0>(p.dim[0], fk0, st0) : probe_first<D0>(p.dim[0], ld0, fk0);
+    if (!dir0) q0 = res0 ? probe_load<D0>(p.dim[0], fk0, st0) : probe_first<D0>(p.dim[0], ld0, fk0);
   if constexpr (D1 != kNone)
-    q1 = res1 ? probe_load<D1>(p.dim[1], fk1, st1) : probe_first<D1>(p.dim[1], ld1, fk1);
+    if (!dir1) q1 = res1 ? probe_load<D1>(p.dim[1], fk1, st1) : probe_first<D1>(p.dim[1], ld1, fk1);
   uint32_t v0 = 0, v1 = 0;
   bool more = false, multi = false;
   if constexpr (D0 != kNone) {
-    if (res0) {
+    if (dir0) {
+      if (!direct_probe(dv0, fk0, v0)) return false;
+    } else if (res0) {
       const int m = probe_examine<D0>(p.dim[0], fk0, q0, st0, v0);
       if (m == 0) return false;
       more |= m == 2;
@@ -516,7 +556,9 @@ __device__ __forceinline__ bool process_row(const PipelineParams& p, int64_t r, 
     }
   }
   if constexpr (D1 != kNone) {
-    if (res1) {
+    if (dir1) {
+      if (!direct_probe(dv1, fk1, v1)) return false;
+    } else if (res1) {
       const int m = probe_examine<D1>(p.dim[1], fk1, q1, st1, v1);
       if (m == 0) return false;
       more |= m == 2;
@@ -587,7 +629,8 @@ template <int D0, int D1>
 __device__ __forceinline__ uint32_t drain(const PipelineParams& p, unsigned char* wq,
                                           uint32_t queued, uint32_t take, int lane,
                                           const void* ld0, const void* ld1, uint64_t* lg,
-                                          const GroupTable& gt, int limit0, int limit1) {
+                                          const GroupTable& gt, int limit0, int limit1,
+                                          const DirectView& dv0, const DirectView& dv1) {
   const uint32_t base = queued - take;
   const bool mine = static_cast<uint32_t>(lane) < take;
   int64_t r = 0, fk0 = 0, fk1 = 0;
@@ -606,7 +649,9 @@ __device__ __forceinline__ uint32_t drain(const PipelineParams& p, unsigned char
   }
   __builtin_amdgcn_wave_barrier();
   bool again = false;
-  if (mine) again = process_row<D0, D1>(p, r, fk0, fk1, st0, st1, ld0, ld1, lg, gt, limit0, limit1);
+  if (mine)
+    again = process_row<D0, D1>(p, r, fk0, fk1, st0, st1, ld0, ld1, lg, gt, limit0, limit1, dv0,
+                                dv1);
   const uint64_t b = ballot(again);
   if (again) {
     const uint32_t at = base + rank_below(b);
@@ -633,6 +678,8 @@ __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile,
                                           int64_t step, unsigned char* wq, int lane,
                                           const void* ld0, const void* ld1, uint64_t* lg,
                                           const GroupTable& gt, int limit0, int limit1) {
+  const DirectView dv0 = dim_direct<D0>(p.dim[0]);
+  const DirectView dv1 = dim_direct<D1>(p.dim[1]);
   const int tid = threadIdx.x;
   const int c_pred = p.nterms > 0 ? p.term_col[0] : 0;
   int64_t pre[4] = {0, 0, 0, 0};
@@ -675,13 +722,14 @@ __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile,
       queued += popc64(b);
       __builtin_amdgcn_wave_barrier();
       while (queued >= kWave)
-        queued = drain<D0, D1>(p, wq, queued, kWave, lane, ld0, ld1, lg, gt, limit0, limit1);
+        queued = drain<D0, D1>(p, wq, queued, kWave, lane, ld0, ld1, lg, gt, limit0, limit1, dv0,
+                               dv1);
     }
   }
   __builtin_amdgcn_wave_barrier();
   while (queued > 0)
     queued = drain<D0, D1>(p, wq, queued, queued < kWave ? queued : kWave, lane, ld0, ld1, lg, gt,
-                           limit0, limit1);
+                           limit0, limit1, dv0, dv1);
 }
 
 // Dims built without duplicate keys stop probing at the first match.
@@ -736,6 +784,10 @@ __device__ __forceinline__ bool row_passes(const PipelineParams& p, int64_t r) {
 template <int D>
 __device__ __forceinline__ int count_upto2(const PipeDim& d, int64_t key) {
   uint32_t v = 0;
+  if constexpr (D == kMap || D == kSet || D == kCSet) {
+    const DirectView dv = direct_view(d.map);
+    if (dv.use) return direct_probe(dv, key, v) ? 1 : 0;
+  }
   return probe_finish<D>(d, nullptr, key, 2, probe_first<D>(d, nullptr, key), v);
 }
 

@@ -164,9 +164,12 @@ def column(t: torch.Tensor, idx: torch.Tensor | None = None) -> Column:
     return Column(t.data_ptr() if t.numel() else None, None, t.numel(), DTYPES[t.dtype], 0)
 
 
+TUNE_NO_DIRECT = 1
+
+
 def tuning(load_factor=0.0, block=0, grid=0, lds_slots=0, dim_lds_bytes=0,
-           chunk_tiles=0, replicas=0) -> Tuning:
-    return Tuning(load_factor, block, grid, lds_slots, 0, dim_lds_bytes, chunk_tiles, replicas)
+           chunk_tiles=0, replicas=0, flags=0) -> Tuning:
+    return Tuning(load_factor, block, grid, lds_slots, flags, dim_lds_bytes, chunk_tiles, replicas)
 
 
 def _tuning_ptr(t):

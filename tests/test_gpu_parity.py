@@ -395,3 +395,48 @@ def test_pipeline_large_membership_dim():
     aggs = [("sum", 2), ("count", None), ("min", 2)]
     got, want = run_both(fact, [], dims, [("fact", 1)], aggs, max_groups=64)
     assert_groups(got, want, aggs, "compact set")
+
+
+def _direct_case(r, name, n_dim=20_000, n_fact=150_000):
+    """A dim with int32 keys laid out to reach one path of the direct
+    tables: the full key range, a partial range (presence bitmap), payload
+    spans of 1, 2 and 4 bytes, keys at the int32 extremes, duplicates (back
+    to the hash table) and a range too wide for a direct table."""
+    base = {"full": 1_000, "partial": -7_000, "wide_payload": 0, "extreme_low": -(2**31),
+            "extreme_high": 2**31 - n_dim, "dups": 50, "too_wide": 0}[name]
+    if name == "partial":
+        key = (r.choice(2 * n_dim, size=n_dim, replace=False) + base).astype(np.int64)
+    elif name == "too_wide":
+        key = r.choice(50 * n_dim, size=n_dim, replace=False).astype(np.int64)
+    else:
+        key = r.permutation(n_dim).astype(np.int64) + base
+    if name == "dups":
+        key[:300] = key[300:600]
+    payload = {"wide_payload": r.integers(-2**31, 2**31 - 1, size=n_dim),
+               "partial": r.integers(-500, 40_000, size=n_dim)}.get(
+        name, r.integers(-3, 20, size=n_dim)).astype(np.int32)
+    lo, hi = int(key.min()) - 50, int(key.max()) + 50
+    fk = np.where(r.random(n_fact) < 0.8, r.choice(key, size=n_fact),
+                  r.integers(max(lo, -(2**31)), min(hi, 2**31 - 1), size=n_fact))
+    return key.astype(np.int32), payload, fk.astype(np.int32)
+
+
+@pytest.mark.parametrize("name", ["full", "partial", "wide_payload", "extreme_low",
+                                  "extreme_high", "dups", "too_wide"])
+def test_pipeline_direct_dims(name):
+    announce("pipeline direct dims", name)
+    r = rng(sum(map(ord, name)))
+    key0, pay0, fk0 = _direct_case(r, name)
+    # a second, membership-only dim over a dense range as well
+    key1 = r.permutation(3_000).astype(np.int32) + 17
+    fk1 = r.integers(0, 3_100, size=len(fk0)).astype(np.int32)
+    g = r.integers(0, 5, size=len(fk0)).astype(np.int32)
+    v = col_with_extremes(r, len(fk0), np.int64, -10**9, 10**9, 0.01)
+    fact = [fk0, fk1, g, v]
+    dims = [dict(fk=0, key=key0, payload=pay0), dict(fk=1, key=key1, payload=None)]
+    aggs = [("sum", 3), ("count", None), ("min", 3), ("max", 3), ("avg", 3)]
+    keys = [("dim", 0), ("fact", 2)]
+    want = oracle.pipeline(fact, [(2, "ne", 3)], dims, keys, aggs)
+    for t in (None, rel.tuning(flags=rel.TUNE_NO_DIRECT), rel.tuning(dim_lds_bytes=-1)):
+        got, _ = run_both(fact, [(2, "ne", 3)], dims, keys, aggs, max_groups=200_000, t=t)
+        assert_groups(got, want, aggs, f"direct {name} tuning {t and t.flags}")
