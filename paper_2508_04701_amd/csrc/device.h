@@ -126,6 +126,28 @@ __device__ __forceinline__ void load4s(const void* p, int32_t type, bool vec, in
   }
 }
 
+// As load4s for int8 and int32 columns, holding the values as int32.
+__device__ __forceinline__ void load4n(const void* p, int32_t type, bool vec, int64_t r0,
+                                       int64_t n, int32_t v[4]) {
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  if (vec && r0 + 4 <= n) {
+    if (type == kI32) {
+      const v4i x = __builtin_nontemporal_load(
+          reinterpret_cast<const v4i*>(static_cast<const int32_t*>(p) + r0));
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    } else {
+      const int32_t w = __builtin_nontemporal_load(
+          reinterpret_cast<const int32_t*>(static_cast<const int8_t*>(p) + r0));
+      v[0] = static_cast<int8_t>(w); v[1] = static_cast<int8_t>(w >> 8);
+      v[2] = static_cast<int8_t>(w >> 16); v[3] = static_cast<int8_t>(w >> 24);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      v[e] = (r0 + e < n) ? static_cast<int32_t>(load_elem(p, type, r0 + e)) : 0;
+  }
+}
+
 // Comparison term on a widened value (operators numerically equal to rel_cmp).
 __device__ __forceinline__ bool term_holds(int32_t op, int64_t v, int64_t lo, int64_t hi) {
   switch (op) {

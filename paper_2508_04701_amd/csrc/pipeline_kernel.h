@@ -304,13 +304,13 @@ __device__ __forceinline__ void enumerate_row(const PipelineParams& p, int64_t r
 // Predicate of four rows whose first term's column was already loaded into
 // `first` (the remaining terms are loaded here).
 __device__ __forceinline__ uint32_t eval_prefetched(const PipelineParams& p, int64_t r0,
-                                                    const int64_t first[4]) {
+                                                    const int32_t first[4], bool prefetched) {
   uint32_t bits = 0;
 #pragma unroll
   for (int e = 0; e < 4; ++e) bits |= (r0 + e < p.n) ? (1u << e) : 0u;
   for (int t = 0; t < p.nterms; ++t) {
     int64_t v[4];
-    if (t == 0) {
+    if (t == 0 && prefetched) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) v[e] = first[e];
     } else {
@@ -681,15 +681,18 @@ __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile,
   const DirectView dv0 = dim_direct<D0>(p.dim[0]);
   const DirectView dv1 = dim_direct<D1>(p.dim[1]);
   const int tid = threadIdx.x;
+  // The first term's column is read one tile ahead when its rows are at most
+  // four bytes wide (held as int32; an int64 column is read in place).
   const int c_pred = p.nterms > 0 ? p.term_col[0] : 0;
-  int64_t pre[4] = {0, 0, 0, 0};
-  if (p.nterms > 0 && tile < end)
-    load4s(p.fact[c_pred], p.fact_type[c_pred], p.fact_vec[c_pred] != 0,
+  const bool prefetch = p.nterms > 0 && p.fact_type[c_pred] != kI64;
+  int32_t pre[4] = {0, 0, 0, 0};
+  if (prefetch && tile < end)
+    load4n(p.fact[c_pred], p.fact_type[c_pred], p.fact_vec[c_pred] != 0,
            tile * static_cast<int64_t>(kPipeTile) + tid * 4, p.n, pre);
   uint32_t queued = 0;  // wave-uniform
   for (; tile < end; tile += step) {
     const int64_t r0 = tile * static_cast<int64_t>(kPipeTile) + tid * 4;
-    const uint32_t bits = eval_prefetched(p, r0, pre);
+    const uint32_t bits = eval_prefetched(p, r0, pre, prefetch);
     const int64_t next = tile + step;
     // Foreign keys of the passing rows, streamed and held in the dim's key
     // width; lanes without a passing row skip them.
@@ -699,8 +702,8 @@ __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile,
       if constexpr (D0 != kNone) load_keys4<D0>(p, p.dim[0].fk_col, r0, fk0);
       if constexpr (D1 != kNone) load_keys4<D1>(p, p.dim[1].fk_col, r0, fk1);
     }
-    if (p.nterms > 0 && next < end)
-      load4s(p.fact[c_pred], p.fact_type[c_pred], p.fact_vec[c_pred] != 0,
+    if (prefetch && next < end)
+      load4n(p.fact[c_pred], p.fact_type[c_pred], p.fact_vec[c_pred] != 0,
              next * static_cast<int64_t>(kPipeTile) + tid * 4, p.n, pre);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
