@@ -51,6 +51,19 @@ __device__ __forceinline__ T first_lane(T v) {
   return __shfl(v, 0, kWave);
 }
 
+// 64-bit atomic adds whose address space is explicit, so that the compiler
+// emits ds_add (LDS) or global_atomic_add (HBM) rather than one generic flat
+// atomic for a pointer that may be either.
+__device__ __forceinline__ void lds_add_u64(uint64_t* p, uint64_t v) {
+  typedef __attribute__((address_space(3))) uint64_t LdsU64;
+  __atomic_fetch_add((LdsU64*)p, v, __ATOMIC_RELAXED);
+}
+
+__device__ __forceinline__ void global_add_u64(uint64_t* p, uint64_t v) {
+  typedef __attribute__((address_space(1))) uint64_t GlobalU64;
+  __hip_atomic_fetch_add((GlobalU64*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
@@ -469,6 +482,16 @@ __device__ __forceinline__ bool map_next(const ulonglong2* slots, uint64_t mask,
 // GroupKeyPack); the sentinel pattern goes to one extra slot after the array.
 
 enum : int32_t { kAccSum = 0, kAccMin = 1, kAccMax = 2 };
+
+// An accumulator update in an LDS group slot (SUM: add; MIN, MAX: signed).
+__device__ __forceinline__ void lds_acc_update(uint64_t* p, int32_t kind, int64_t v) {
+  typedef __attribute__((address_space(3))) uint64_t LdsU64;
+  typedef __attribute__((address_space(3))) int64_t LdsI64;
+  if (kind == kAccSum) __atomic_fetch_add((LdsU64*)p, static_cast<uint64_t>(v), __ATOMIC_RELAXED);
+  else if (kind == kAccMin) __atomic_fetch_min((LdsI64*)p, v, __ATOMIC_RELAXED);
+  else __atomic_fetch_max((LdsI64*)p, v, __ATOMIC_RELAXED);
+}
+
 
 constexpr int kMaxAcc = 8;
 

@@ -96,12 +96,13 @@ constexpr uint64_t kDirectStateInit = 0x800000007FFFFFFFULL;
 
 // A direct table as its readers see it (uniform values). Payload entries
 // hold payload - pmin in the fewest bytes (1, 2 or 4) that cover the range.
+// mode: 0 = not in use (the dim's slot array holds the keys); otherwise
+// kDirectOn | (keys fill [kmin, kmin + range) ? kDirectFull : 0) | width << 2.
+constexpr uint32_t kDirectOn = 1, kDirectFull = 2;
 struct DirectView {
-  int32_t use;    // the table holds every build key exactly once
-  int32_t full;   // the keys are exactly [kmin, kmin + range): presence needs no read
-  int32_t width;  // payload bytes (0: no payload)
+  uint32_t mode;
   int32_t kmin, pmin;
-  uint64_t range;
+  uint32_t range;
   const uint32_t* bits;
   const void* vals;
 };
@@ -120,11 +121,11 @@ __device__ __forceinline__ uint64_t direct_range(const MapDesc& m) {
 }
 
 // Valid after the build: duplicates send the dim back to its slot array.
+// (A direct table needs its range below 2^32, which a build of fewer than
+// 2^31 keys guarantees; larger ranges keep the slot array.)
 __device__ __forceinline__ DirectView direct_view(const MapDesc& m) {
   DirectView v;
-  v.use = 0;
-  v.full = 0;
-  v.width = 0;
+  v.mode = 0;
   v.kmin = 0;
   v.pmin = 0;
   v.range = 0;
@@ -132,14 +133,13 @@ __device__ __forceinline__ DirectView direct_view(const MapDesc& m) {
   v.vals = m.dvals;
   if (m.direct_cap == 0) return v;
   const uint64_t range = direct_range(m);
-  if (range == 0 || range > m.direct_cap || *m.dup) return v;
-  v.use = 1;
-  v.range = range;
-  v.full = range == m.nkeys;
+  if (range == 0 || range > m.direct_cap || range >= (1ull << 32) || *m.dup) return v;
+  v.range = static_cast<uint32_t>(range);
   v.kmin = m.dstate[kDKmin];
+  v.mode = kDirectOn | (range == m.nkeys ? kDirectFull : 0u);
   if (m.dvals) {
     v.pmin = m.dstate[kDPmin];
-    v.width = direct_width(v.pmin, m.dstate[kDPmax]);
+    v.mode |= static_cast<uint32_t>(direct_width(v.pmin, m.dstate[kDPmax])) << 2;
   }
   return v;
 }
@@ -149,10 +149,11 @@ __device__ __forceinline__ bool direct_probe(const DirectView& v, int64_t key, u
   const uint64_t off = static_cast<uint64_t>(key - static_cast<int64_t>(v.kmin));
   if (off >= v.range) return false;
   const uint32_t i = static_cast<uint32_t>(off);
-  if (!v.full && !((v.bits[i >> 5] >> (i & 31)) & 1u)) return false;
-  if (v.width == 1) val = static_cast<uint32_t>(static_cast<const uint8_t*>(v.vals)[i]) + v.pmin;
-  else if (v.width == 2) val = static_cast<uint32_t>(static_cast<const uint16_t*>(v.vals)[i]) + v.pmin;
-  else if (v.width == 4) val = static_cast<const uint32_t*>(v.vals)[i] + static_cast<uint32_t>(v.pmin);
+  if (!(v.mode & kDirectFull) && !((v.bits[i >> 5] >> (i & 31)) & 1u)) return false;
+  const uint32_t width = v.mode >> 2;
+  if (width == 1) val = static_cast<uint32_t>(static_cast<const uint8_t*>(v.vals)[i]) + v.pmin;
+  else if (width == 2) val = static_cast<uint32_t>(static_cast<const uint16_t*>(v.vals)[i]) + v.pmin;
+  else if (width == 4) val = static_cast<const uint32_t*>(v.vals)[i] + static_cast<uint32_t>(v.pmin);
   return true;
 }
 

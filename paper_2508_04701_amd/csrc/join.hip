@@ -139,7 +139,7 @@ __device__ __forceinline__ void direct_rows(const MapBuildParams& p, uint64_t i,
 
 // Build pass 3 (the slot array) is skipped when the direct table took every
 // key exactly once.
-__device__ __forceinline__ bool slots_needed(const MapDesc& m) { return !direct_view(m).use; }
+__device__ __forceinline__ bool slots_needed(const MapDesc& m) { return direct_view(m).mode == 0; }
 
 template <typename K>
 __global__ void __launch_bounds__(256) map_build_kernel(MapBuildParams p, int pass) {

@@ -184,7 +184,7 @@ __device__ __forceinline__ MapCursor dim_start(const PipeDim& d, int64_t key) {
   c.direct = false;
   if constexpr (D == kMap || D == kSet || D == kCSet) {
     const DirectView v = direct_view(d.map);
-    if (v.use) {
+    if (v.mode) {
       uint32_t val = 0;
       c.direct = true;
       c.oob = false;
@@ -360,18 +360,45 @@ __device__ __forceinline__ void copy_dim_to_lds(const PipeDim& d, void* lds_copy
   }
 }
 
-__device__ __forceinline__ void queue_put(const PipelineParams& p, unsigned char* wq, int f,
-                                          uint32_t i, int64_t v) {
-  unsigned char* a = wq + p.field_offset[f];
-  if (p.field_wide[f]) reinterpret_cast<int64_t*>(a)[i] = v;
-  else reinterpret_cast<int32_t*>(a)[i] = static_cast<int32_t>(v);
+// Per-wave row queue in LDS: arrays of kPipeQueue entries for the row ids,
+// the foreign keys of dims 0 and 1 (8 bytes for int64 dims, else 4), then the
+// probe states of dims 0 and 1; fields of absent dims take no space. The
+// layout follows from the dim modes (the host sizes it by the same rule).
+template <int D0, int D1, int F>
+__device__ constexpr uint32_t queue_offset() {
+  uint32_t o = kPipeQueue * 4;
+  if (F == kQRow) return 0;
+  if (F == kQFk0) return o;
+  if (D0 != kNone) o += kPipeQueue * (D0 == kMap64 ? 8 : 4);
+  if (F == kQFk1) return o;
+  if (D1 != kNone) o += kPipeQueue * (D1 == kMap64 ? 8 : 4);
+  if (F == kQSt0) return o;
+  if (D0 != kNone) o += kPipeQueue * 4;
+  return o;
 }
 
-__device__ __forceinline__ int64_t queue_get(const PipelineParams& p, const unsigned char* wq,
-                                             int f, uint32_t i) {
-  const unsigned char* a = wq + p.field_offset[f];
-  if (p.field_wide[f]) return reinterpret_cast<const int64_t*>(a)[i];
-  return reinterpret_cast<const int32_t*>(a)[i];
+template <int D0, int D1>
+__device__ constexpr uint32_t queue_stride() {
+  return queue_offset<D0, D1, kQSt1>() + (D1 != kNone ? kPipeQueue * 4 : 0);
+}
+
+template <int D0, int D1, int F>
+struct QueueField {
+  typedef typename std::conditional<
+      F == kQFk0, typename KeyOf<D0>::T,
+      typename std::conditional<F == kQFk1, typename KeyOf<D1>::T, uint32_t>::type>::type T;
+};
+
+template <int D0, int D1, int F>
+__device__ __forceinline__ void qput(unsigned char* wq, uint32_t i, int64_t v) {
+  typedef typename QueueField<D0, D1, F>::T T;
+  reinterpret_cast<T*>(wq + queue_offset<D0, D1, F>())[i] = static_cast<T>(v);
+}
+
+template <int D0, int D1, int F>
+__device__ __forceinline__ int64_t qget(const unsigned char* wq, uint32_t i) {
+  typedef typename QueueField<D0, D1, F>::T T;
+  return reinterpret_cast<const T*>(wq + queue_offset<D0, D1, F>())[i];
 }
 
 // ------------------------------------------------------ resumable probes
@@ -399,7 +426,7 @@ __device__ __forceinline__ DirectView dim_direct(const PipeDim& d) {
     return direct_view(d.map);
   } else {
     DirectView v;
-    v.use = 0;
+    v.mode = 0;
     return v;
   }
 }
@@ -531,8 +558,8 @@ __device__ __forceinline__ bool process_row(const PipelineParams& p, int64_t r, 
                                             const void* ld0, const void* ld1, uint64_t* lg,
                                             const GroupTable& gt, int limit0, int limit1,
                                             const DirectView& dv0, const DirectView& dv1) {
-  const bool dir0 = kDirectable<D0> && dv0.use;
-  const bool dir1 = kDirectable<D1> && dv1.use;
+  const bool dir0 = kDirectable<D0> && dv0.mode != 0;
+  const bool dir1 = kDirectable<D1> && dv1.mode != 0;
   const bool res0 = kResumable<D0> && limit0 == 1;
   const bool res1 = kResumable<D1> && limit1 == 1;
   uint4 q0 = make_uint4(0, 0, 0, 0), q1 = make_uint4(0, 0, 0, 0);
@@ -540,6 +567,17 @@ __device__ __forceinline__ bool process_row(const PipelineParams& p, int64_t r, 
     if (!dir0) q0 = res0 ? probe_load<D0>(p.dim[0], fk0, st0) : probe_first<D0>(p.dim[0], ld0, fk0);
   if constexpr (D1 != kNone)
     if (!dir1) q1 = res1 ? probe_load<D1>(p.dim[1], fk1, st1) : probe_first<D1>(p.dim[1], ld1, fk1);
+  // Group-key and value columns, gathered by row id while the probe reads
+  // are in flight (lines the batch shares are fetched once); rows that the
+  // joins drop discard them.
+  int64_t k0 = 0, k1 = 0;
+  if (p.g.kp.nkeys > 0 && p.key_src[0] == 0)
+    k0 = load_elem(p.fact[p.key_col[0]], p.fact_type[p.key_col[0]], r);
+  if (p.g.kp.nkeys > 1 && p.key_src[1] == 0)
+    k1 = load_elem(p.fact[p.key_col[1]], p.fact_type[p.key_col[1]], r);
+  int64_t va = 0, vb = 0;
+  if (p.early_col[0] >= 0) va = load_elem(p.fact[p.early_col[0]], p.fact_type[p.early_col[0]], r);
+  if (p.early_col[1] >= 0) vb = load_elem(p.fact[p.early_col[1]], p.fact_type[p.early_col[1]], r);
   uint32_t v0 = 0, v1 = 0;
   bool more = false, multi = false;
   if constexpr (D0 != kNone) {
@@ -570,47 +608,32 @@ __device__ __forceinline__ bool process_row(const PipelineParams& p, int64_t r, 
   }
   if (more) return true;
   if (multi) return false;  // several dim matches: left to the enumeration pass
-  // Group-key and value columns of the rows that survived the joins,
-  // gathered by row id (lines the batch shares are fetched once).
-  int64_t k0 = 0, k1 = 0;
-  if (p.g.kp.nkeys > 0 && p.key_src[0] == 0)
-    k0 = load_elem(p.fact[p.key_col[0]], p.fact_type[p.key_col[0]], r);
-  if (p.g.kp.nkeys > 1 && p.key_src[1] == 0)
-    k1 = load_elem(p.fact[p.key_col[1]], p.fact_type[p.key_col[1]], r);
-  int64_t va = 0, vb = 0;
-  if (p.early_col[0] >= 0) va = load_elem(p.fact[p.early_col[0]], p.fact_type[p.early_col[0]], r);
-  if (p.early_col[1] >= 0) vb = load_elem(p.fact[p.early_col[1]], p.fact_type[p.early_col[1]], r);
   if (p.g.kp.nkeys > 0 && p.key_src[0] != 0) k0 = static_cast<int32_t>(p.key_src[0] == 1 ? v0 : v1);
   if (p.g.kp.nkeys > 1 && p.key_src[1] != 0) k1 = static_cast<int32_t>(p.key_src[1] == 1 ? v0 : v1);
   const uint64_t pk = pack_keys(p.g.kp, k0, k1);
   const int words = p.g.words;
   const int32_t li = lds_group_find(lg, p.lds_slots, words, pk);
-  uint64_t* gs = nullptr;
+  // One branch per row: the workgroup's LDS table, or its global replica.
   if (li >= 0) {
-    atomicAdd(reinterpret_cast<unsigned long long*>(lg + li * words + 1), 1ULL);
+    uint64_t* s = lg + li * words;
+    lds_add_u64(s + 1, 1);
+    for (int a = 0; a < p.g.ap.nacc; ++a) {
+      const int src = p.acc_src[a];
+      const int64_t v = src == 0 ? va
+                      : src == 1 ? vb
+                                 : load_elem(p.fact[p.acc_col[a]], p.fact_type[p.acc_col[a]], r);
+      lds_acc_update(s + 2 + a, p.g.ap.kind[a], v);
+    }
   } else {
-    gs = group_slot(gt, pk);
+    uint64_t* gs = group_slot(gt, pk);
     if (!gs) return false;
-    atomicAdd(reinterpret_cast<unsigned long long*>(gs + 1), 1ULL);
-  }
-  for (int a = 0; a < p.g.ap.nacc; ++a) {
-    const int src = p.acc_src[a];
-    const int64_t v = src == 0 ? va
-                    : src == 1 ? vb
-                               : load_elem(p.fact[p.acc_col[a]], p.fact_type[p.acc_col[a]], r);
-    const int kind = p.g.ap.kind[a];
-    if (li >= 0) {
-      uint64_t* w = lg + li * words + 2 + a;
-      if (kind == kAccSum) {
-        atomicAdd(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(v));
-      } else if (kind == kAccMin) {
-        if (v < *reinterpret_cast<long long*>(w))
-          atomicMin(reinterpret_cast<long long*>(w), static_cast<long long>(v));
-      } else {
-        if (v > *reinterpret_cast<long long*>(w))
-          atomicMax(reinterpret_cast<long long*>(w), static_cast<long long>(v));
-      }
-    } else {
+    global_add_u64(gs + 1, 1);
+    for (int a = 0; a < p.g.ap.nacc; ++a) {
+      const int src = p.acc_src[a];
+      const int64_t v = src == 0 ? va
+                      : src == 1 ? vb
+                                 : load_elem(p.fact[p.acc_col[a]], p.fact_type[p.acc_col[a]], r);
+      const int kind = p.g.ap.kind[a];
       uint64_t* w = gs + 2 + a;
       if (kind == kAccSum)
         atomicAdd(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(v));
@@ -637,14 +660,14 @@ __device__ __forceinline__ uint32_t drain(const PipelineParams& p, unsigned char
   uint32_t st0 = 0, st1 = 0;
   if (mine) {
     const uint32_t i = base + lane;
-    r = static_cast<uint32_t>(queue_get(p, wq, kQRow, i));
+    r = static_cast<uint32_t>(qget<D0, D1, kQRow>(wq, i));
     if constexpr (D0 != kNone) {
-      fk0 = queue_get(p, wq, kQFk0, i);
-      st0 = static_cast<uint32_t>(queue_get(p, wq, kQSt0, i));
+      fk0 = qget<D0, D1, kQFk0>(wq, i);
+      st0 = static_cast<uint32_t>(qget<D0, D1, kQSt0>(wq, i));
     }
     if constexpr (D1 != kNone) {
-      fk1 = queue_get(p, wq, kQFk1, i);
-      st1 = static_cast<uint32_t>(queue_get(p, wq, kQSt1, i));
+      fk1 = qget<D0, D1, kQFk1>(wq, i);
+      st1 = static_cast<uint32_t>(qget<D0, D1, kQSt1>(wq, i));
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -655,14 +678,14 @@ __device__ __forceinline__ uint32_t drain(const PipelineParams& p, unsigned char
   const uint64_t b = ballot(again);
   if (again) {
     const uint32_t at = base + rank_below(b);
-    queue_put(p, wq, kQRow, at, r);
+    qput<D0, D1, kQRow>(wq, at, r);
     if constexpr (D0 != kNone) {
-      queue_put(p, wq, kQFk0, at, fk0);
-      queue_put(p, wq, kQSt0, at, static_cast<int32_t>(st0));
+      qput<D0, D1, kQFk0>(wq, at, fk0);
+      qput<D0, D1, kQSt0>(wq, at, st0);
     }
     if constexpr (D1 != kNone) {
-      queue_put(p, wq, kQFk1, at, fk1);
-      queue_put(p, wq, kQSt1, at, static_cast<int32_t>(st1));
+      qput<D0, D1, kQFk1>(wq, at, fk1);
+      qput<D0, D1, kQSt1>(wq, at, st1);
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -670,7 +693,7 @@ __device__ __forceinline__ uint32_t drain(const PipelineParams& p, unsigned char
 }
 
 // Walks tiles `tile`, `tile + step`, ... below `end` of plan p: streams the
-// predicate column (one tile ahead) and the foreign keys, queues the passing
+// predicate column (two tiles ahead) and the foreign keys, queues the passing
 // rows per wave and drains them in full-lane batches. Returns with the
 // wave's queue empty.
 template <int D0, int D1>
@@ -681,30 +704,45 @@ __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile,
   const DirectView dv0 = dim_direct<D0>(p.dim[0]);
   const DirectView dv1 = dim_direct<D1>(p.dim[1]);
   const int tid = threadIdx.x;
-  // The first term's column is read one tile ahead when its rows are at most
-  // four bytes wide (held as int32; an int64 column is read in place).
+  // The first term's column is read two tiles ahead when its rows are at
+  // most four bytes wide (held as int32; an int64 column is read in place),
+  // so that each wave keeps several loads in flight.
   const int c_pred = p.nterms > 0 ? p.term_col[0] : 0;
   const bool prefetch = p.nterms > 0 && p.fact_type[c_pred] != kI64;
-  int32_t pre[4] = {0, 0, 0, 0};
+  const void* pcol = p.fact[c_pred];
+  const int32_t ptype = p.fact_type[c_pred];
+  const bool pvec = p.fact_vec[c_pred] != 0;
+  int32_t pre[4] = {0, 0, 0, 0}, pre2[4] = {0, 0, 0, 0};
   if (prefetch && tile < end)
-    load4n(p.fact[c_pred], p.fact_type[c_pred], p.fact_vec[c_pred] != 0,
-           tile * static_cast<int64_t>(kPipeTile) + tid * 4, p.n, pre);
+    load4n(pcol, ptype, pvec, tile * static_cast<int64_t>(kPipeTile) + tid * 4, p.n, pre);
+  if (prefetch && tile + step < end)
+    load4n(pcol, ptype, pvec, (tile + step) * static_cast<int64_t>(kPipeTile) + tid * 4, p.n,
+           pre2);
+  // While most lanes of a wave see passing rows, nearly every line of the
+  // foreign-key columns is needed: they are then loaded before the predicate
+  // is evaluated, overlapping both; otherwise only for lanes with passing
+  // rows (wave-uniform switch, updated per tile).
+  bool eager = true;
   uint32_t queued = 0;  // wave-uniform
   for (; tile < end; tile += step) {
     const int64_t r0 = tile * static_cast<int64_t>(kPipeTile) + tid * 4;
-    const uint32_t bits = eval_prefetched(p, r0, pre, prefetch);
-    const int64_t next = tile + step;
-    // Foreign keys of the passing rows, streamed and held in the dim's key
-    // width; lanes without a passing row skip them.
     typename KeyOf<D0>::T fk0[4] = {0, 0, 0, 0};
     typename KeyOf<D1>::T fk1[4] = {0, 0, 0, 0};
-    if (bits) {
+    if (eager) {
       if constexpr (D0 != kNone) load_keys4<D0>(p, p.dim[0].fk_col, r0, fk0);
       if constexpr (D1 != kNone) load_keys4<D1>(p, p.dim[1].fk_col, r0, fk1);
     }
-    if (prefetch && next < end)
-      load4n(p.fact[c_pred], p.fact_type[c_pred], p.fact_vec[c_pred] != 0,
-             next * static_cast<int64_t>(kPipeTile) + tid * 4, p.n, pre);
+    const uint32_t bits = eval_prefetched(p, r0, pre, prefetch);
+    const int64_t ahead = tile + 2 * step;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) pre[e] = pre2[e];
+    if (prefetch && ahead < end)
+      load4n(pcol, ptype, pvec, ahead * static_cast<int64_t>(kPipeTile) + tid * 4, p.n, pre2);
+    if (!eager && bits) {
+      if constexpr (D0 != kNone) load_keys4<D0>(p, p.dim[0].fk_col, r0, fk0);
+      if constexpr (D1 != kNone) load_keys4<D1>(p, p.dim[1].fk_col, r0, fk1);
+    }
+    eager = popc64(ballot(bits != 0)) >= kWave / 4;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const bool pass = (bits >> e) & 1u;
@@ -712,14 +750,14 @@ __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile,
       if (b == 0) continue;
       if (pass) {
         const uint32_t at = queued + rank_below(b);
-        queue_put(p, wq, kQRow, at, r0 + e);
+        qput<D0, D1, kQRow>(wq, at, r0 + e);
         if constexpr (D0 != kNone) {
-          queue_put(p, wq, kQFk0, at, fk0[e]);
-          queue_put(p, wq, kQSt0, at, 0);
+          qput<D0, D1, kQFk0>(wq, at, fk0[e]);
+          qput<D0, D1, kQSt0>(wq, at, 0);
         }
         if constexpr (D1 != kNone) {
-          queue_put(p, wq, kQFk1, at, fk1[e]);
-          queue_put(p, wq, kQSt1, at, 0);
+          qput<D0, D1, kQFk1>(wq, at, fk1[e]);
+          qput<D0, D1, kQSt1>(wq, at, 0);
         }
       }
       queued += popc64(b);
@@ -789,7 +827,7 @@ __device__ __forceinline__ int count_upto2(const PipeDim& d, int64_t key) {
   uint32_t v = 0;
   if constexpr (D == kMap || D == kSet || D == kCSet) {
     const DirectView dv = direct_view(d.map);
-    if (dv.use) return direct_probe(dv, key, v) ? 1 : 0;
+    if (dv.mode) return direct_probe(dv, key, v) ? 1 : 0;
   }
   return probe_finish<D>(d, nullptr, key, 2, probe_first<D>(d, nullptr, key), v);
 }
