@@ -780,8 +780,15 @@ __device__ __forceinline__ int match_limit(const PipeDim& d) {
   else return *d.map.dup ? 2 : 1;
 }
 
+// Eight waves per SIMD (four resident workgroups per CU) where the variant
+// fits 64 VGPRs without spilling; variants with an int64 dim or an LDS copy
+// as second dim keep the compiler's own register budget.
 template <int D0, int D1>
-__global__ void __launch_bounds__(kPipeThreads) fused_kernel(PipelineParams p) {
+constexpr int kFusedWaves = (D1 == kMapLds || D1 == kSetLds || D1 == kMap64) ? 1 : 8;
+
+template <int D0, int D1>
+__global__ void __launch_bounds__(kPipeThreads)
+__attribute__((amdgpu_waves_per_eu(kFusedWaves<D0, D1>))) fused_kernel(PipelineParams p) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   void* ld0 = lds + p.dim[0].lds_offset;
   void* ld1 = lds + p.dim[1].lds_offset;
@@ -934,8 +941,14 @@ hipError_t launch_fused(const PipelineParams& p, int grid, hipStream_t s) {
 // single-plan kernel does; the LDS group table is set up and flushed per
 // item. Dim tables stay in HBM, where L2 keeps the small ones.
 
+// The batched kernel keeps more per-item state: the eight-wave budget only
+// for plans with one dim.
 template <int D0, int D1>
-__global__ void __launch_bounds__(kPipeThreads) batch_fused_kernel(BatchParams b) {
+constexpr int kBatchWaves = D1 == kNone ? 8 : 1;
+
+template <int D0, int D1>
+__global__ void __launch_bounds__(kPipeThreads)
+__attribute__((amdgpu_waves_per_eu(kBatchWaves<D0, D1>))) batch_fused_kernel(BatchParams b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   __shared__ uint32_t s_item;
   uint64_t* lg = reinterpret_cast<uint64_t*>(lds);
