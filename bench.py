@@ -245,6 +245,83 @@ def bench_batch(args, torch, datagen, rel) -> dict:
     }
 
 
+def bench_ops(args, torch, datagen, rel) -> dict:
+    """Each standalone operator against its own HBM roofline, with the bytes
+    the operation must move (inputs read once, outputs written once; random
+    hash-table traffic is the method's cost, not counted): rel_filter on the
+    star schema's 600M-row date column (date < 767); rel_hash_join and
+    rel_groupby_agg on the skewed workload (100M unique int64 build keys,
+    400M Zipf(1) probe keys, every probe matching once; about 10M groups of
+    an int64 probe-side column). Device time per kernel class from HIP
+    events over the timed launches."""
+    reps = args.ops_reps
+
+    def kernel_ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        rel.profile_read()
+        rel.profile_enable(True)
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        rel.profile_enable(False)
+        return {k: v[0] / reps for k, v in rel.profile_read().items() if v[1]}
+
+    def line(ms, nbytes, **kw):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {**kw, "kernel_ms": ms, "algorithmic_bytes": nbytes, "achieved_gbs": gbs,
+                "frac": gbs / HBM_PEAK_GBS}
+
+    res = {}
+    n = args.n_fact
+    date = torch.from_numpy(datagen.uniform(datagen.SEED0 + 2, 12, 0, 2557, n, np.int32)).cuda()
+    ids = torch.empty(n, dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ws = rel.workspace(rel.filter_ws(n))
+    k = kernel_ms(lambda: rel.filter_async([date], [(0, "lt", 767)], ids, count, ws))
+    passing = int(count.item())
+    res["filter"] = line(k["filter"], 4 * n + 4 * passing, rows=n, passing=passing,
+                         workload=f"int32 date[{n}] < 767 -> ascending row ids")
+    del date, ids, ws
+    torch.cuda.empty_cache()
+
+    t0 = time.perf_counter()
+    sk = datagen.skewed(n_build=args.ops_build, n_probe=args.ops_probe, n_groups=args.ops_groups)
+    dev = {c: torch.from_numpy(v).cuda() for c, v in sk.items()}
+    del sk
+    log(f"ops: skewed workload ready in {time.perf_counter() - t0:.1f} s")
+    nb, npr = dev["build_key"].numel(), dev["probe_key"].numel()
+    ws = rel.workspace(rel.hash_join_ws(torch.int64, nb))
+    ob = torch.empty(npr, dtype=torch.int32, device="cuda")
+    op = torch.empty(npr, dtype=torch.int32, device="cuda")
+    k = kernel_ms(lambda: rel.hash_join_async(dev["build_key"], dev["probe_key"], ob, op, count, ws))
+    pairs = int(count.item())
+    res["hash_build"] = line(k["map_build"], 8 * nb, rows=nb,
+                             workload=f"{nb} unique int64 keys -> open-addressing table")
+    res["hash_probe"] = line(k["map_probe"], 8 * npr + 8 * pairs, rows=npr, pairs=pairs,
+                             workload=f"{npr} Zipf(1) int64 probe keys -> (build, probe) row-id pairs")
+    res["hash_join_fill_ms"] = k.get("fill", 0.0)
+    del ws, ob, op
+    torch.cuda.empty_cache()
+
+    aggs = [("sum", 0), ("count", None), ("avg", 0), ("min", 0), ("max", 0)]
+    mg = args.ops_groups
+    ws = rel.workspace(rel.groupby_ws([torch.int64], aggs, mg))
+    out_keys = [torch.empty(mg, dtype=torch.int64, device="cuda")]
+    out_aggs = [torch.empty(mg, dtype=torch.float64 if a == "avg" else torch.int64, device="cuda")
+                for a, _ in aggs]
+    k = kernel_ms(lambda: rel.groupby_agg_async([dev["probe_grp"]], [dev["probe_val"]], aggs,
+                                                out_keys, out_aggs, count, mg, ws))
+    groups = int(count.item())
+    res["group_by"] = line(k["group_agg"], 16 * npr, rows=npr, groups=groups,
+                           workload=f"{npr} rows, int64 Zipf-skewed key over {mg} values, "
+                                    "SUM/COUNT/AVG/MIN/MAX of an int64 column")
+    res["finalize"] = line(k["group_finalize"], groups * (8 + 8 * len(aggs)), groups=groups,
+                           workload="occupied group slots -> key and aggregate columns "
+                                    "(includes the replica merge)")
+    return res
+
+
 SERVE_AGGS = [("sum", 3), ("count", None)]
 
 
@@ -369,6 +446,12 @@ def main() -> int:
     ap.add_argument("--tune-cache-out", default=None,
                     help="write the autotuner records of the batched section to this JSON file")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--no-ops", action="store_true", help="skip the standalone-operator section")
+    ap.add_argument("--ops-only", action="store_true")
+    ap.add_argument("--ops-reps", type=int, default=3)
+    ap.add_argument("--ops-build", type=int, default=100_000_000)
+    ap.add_argument("--ops-probe", type=int, default=400_000_000)
+    ap.add_argument("--ops-groups", type=int, default=10_000_000)
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-rows", type=int, default=200_000_000)
     ap.add_argument("--serve-queries", type=int, default=2000)
@@ -405,6 +488,9 @@ def main() -> int:
         return 0
     if args.batch_only:
         print(json.dumps({"batch": bench_batch(args, torch, datagen, rel)}), flush=True)
+        return 0
+    if args.ops_only:
+        print(json.dumps({"ops": bench_ops(args, torch, datagen, rel)}), flush=True)
         return 0
     if args.serve_only:
         print(json.dumps({"serving": bench_serve(args, torch, datagen, rel)}), flush=True)
@@ -489,6 +575,10 @@ def main() -> int:
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         out["serving"] = bench_serve(args, torch, datagen, rel)
+    if not args.no_ops:
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out["ops"] = bench_ops(args, torch, datagen, rel)
     print(json.dumps(out), flush=True)
     return 0
 
