@@ -588,7 +588,7 @@ void plan_params(const rel_pipeline_desc* d, const PipeLayout& L, unsigned char*
 // Units per work item of the batched phases.
 constexpr uint64_t kFillChunk = 32768;   // words
 constexpr uint64_t kBuildChunk = 8192;   // build rows
-constexpr uint64_t kSlotChunk = 16384;   // group slots (a multiple of the block size)
+constexpr uint64_t kSlotChunk = 16384;   // group slots (a multiple of the finalize chunk, 2048)
 constexpr int kMaxChunkTiles = 8;
 constexpr int kMaxBatch = 1 << 16;
 

@@ -1,7 +1,7 @@
 // Selection with ordered stream compaction, one pass over the columns.
 //
-// A workgroup of 256 threads takes one tile of 4096 rows. Thread t of the
-// tile reads rows (j * 1024 + 4 t .. + 3) for j = 0..3, so every column read
+// A workgroup of 256 threads takes one tile of 8192 rows. Thread t of the
+// tile reads rows (j * 1024 + 4 t .. + 3) for j = 0..7, so every column read
 // is a coalesced 16-byte-per-lane vector load. Each passing row sets one bit;
 // per chunk a wave64 ballot per row position gives the wave's count (popcount)
 // and each lane's rank (mbcnt), which places every passing row id at its
@@ -48,7 +48,7 @@ __device__ __forceinline__ uint32_t eval_chunk(const FilterParams& p, int64_t r0
 
 __global__ void __launch_bounds__(kFilterThreads) filter_kernel(FilterParams p) {
   __shared__ uint32_t s_rows[kFilterTile];
-  __shared__ uint32_t s_wave_total[4][kFilterThreads / kWave];
+  __shared__ uint32_t s_wave_total[kFilterChunks][kFilterThreads / kWave];
   __shared__ int64_t s_tile;
   __shared__ uint64_t s_excl;
 
@@ -61,15 +61,16 @@ __global__ void __launch_bounds__(kFilterThreads) filter_kernel(FilterParams p) 
   const int64_t tile = s_tile;
   const int64_t base = tile * kFilterTile;
 
-  uint32_t bits[4];
+  uint32_t bits[kFilterChunks];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) bits[j] = eval_chunk(p, base + j * (kFilterThreads * 4) + tid * 4);
+  for (int j = 0; j < kFilterChunks; ++j)
+    bits[j] = eval_chunk(p, base + j * (kFilterThreads * 4) + tid * 4);
 
   // Per chunk: this lane's rank among the wave's passing rows, and the
   // wave's count.
-  uint32_t lane_prefix[4];
+  uint32_t lane_prefix[kFilterChunks];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < kFilterChunks; ++j) {
     uint32_t pre = 0, tot = 0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -83,10 +84,10 @@ __global__ void __launch_bounds__(kFilterThreads) filter_kernel(FilterParams p) 
   __syncthreads();
 
   // Offsets in tile order (chunk, wave, lane, row).
-  uint32_t chunk_base[4];
+  uint32_t chunk_base[kFilterChunks];
   uint32_t running = 0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < kFilterChunks; ++j) {
     for (int w = 0; w < kFilterThreads / kWave; ++w) {
       if (w == wave) chunk_base[j] = running;
       running += s_wave_total[j][w];
@@ -123,7 +124,7 @@ __global__ void __launch_bounds__(kFilterThreads) filter_kernel(FilterParams p) 
 
   // Stage row ids in LDS at their tile positions.
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < kFilterChunks; ++j) {
     if (bits[j] == 0) continue;
     const int64_t r0 = base + j * (kFilterThreads * 4) + tid * 4;
     uint32_t off = chunk_base[j] + lane_prefix[j];

@@ -92,59 +92,94 @@ __global__ void __launch_bounds__(256) group_merge_kernel(GroupDesc g) {
               (g.replicas - 1) * (g.cap + 1), static_cast<uint64_t>(gridDim.x) * blockDim.x);
 }
 
-// Writes the occupied slots among [base, end) (base a multiple of the wave
-// size; the workgroup steps by `stride`) to the outputs, each at a position
-// taken from the group counter with one atomic per wave.
-__device__ __forceinline__ void finalize_range(const FinalizeParams& p, uint64_t base,
+// Slots per thread in one finalize chunk (a chunk spans blockDim.x times as
+// many slots).
+constexpr int kFinalizeSlots = 8;
+
+__device__ __forceinline__ void write_group(const FinalizeParams& p, uint64_t i,
+                                            unsigned long long pos) {
+  const GroupDesc& g = p.g;
+  if (pos >= static_cast<unsigned long long>(p.cap)) return;
+  const uint64_t* s = g.slots + i * g.words;
+  const uint64_t pk = (g.kp.nkeys > 0 && i == g.cap) ? kEmpty64 : s[0];
+  if (g.kp.nkeys > 0) {
+    int64_t k0, k1;
+    unpack_keys(g.kp, pk, k0, k1);
+    store_elem(p.out_keys[0], p.out_key_type[0], pos, k0);
+    if (g.kp.nkeys > 1) store_elem(p.out_keys[1], p.out_key_type[1], pos, k1);
+  }
+  const uint64_t count = s[1];
+  for (int a = 0; a < p.naggs; ++a) {
+    const int op = p.op[a];
+    int64_t* out = static_cast<int64_t*>(p.out_aggs[a]);
+    if (op == 1) {
+      out[pos] = static_cast<int64_t>(count);
+    } else if (op == 4) {
+      double avg;
+      if (count == 0) {
+        avg = __longlong_as_double(0x7FF8000000000000LL);
+      } else {
+        avg = static_cast<double>(static_cast<int64_t>(s[2 + p.acc[a]])) /
+              static_cast<double>(static_cast<int64_t>(count));
+      }
+      static_cast<double*>(p.out_aggs[a])[pos] = avg;
+    } else {
+      out[pos] = static_cast<int64_t>(s[2 + p.acc[a]]);
+    }
+  }
+}
+
+// Writes the occupied slots of the chunks starting at `chunk`, `chunk +
+// stride`, ... below `end` (all uniform across the workgroup). Per chunk the
+// workgroup counts its occupied slots, takes their output positions with one
+// atomic on the group counter, then writes them: one atomic per chunk rather
+// than per wave, since every workgroup shares the counter.
+__device__ __forceinline__ void finalize_range(const FinalizeParams& p, uint64_t chunk,
                                                uint64_t end, uint64_t stride) {
+  __shared__ uint32_t s_wave[1024 / kWave];
+  __shared__ unsigned long long s_base;
   const GroupDesc& g = p.g;
   const int lane = lane_id();
+  const int wave = threadIdx.x / kWave;
+  const int nwaves = blockDim.x / kWave;
   const uint64_t nslots = g.kp.nkeys == 0 ? 1 : g.cap + 1;
   if (end > nslots) end = nslots;
-  for (; base < end; base += stride) {
-    const uint64_t i = base + threadIdx.x;
-    bool occ = false;
-    const uint64_t* s = nullptr;
-    if (i < end) {
-      s = g.slots + i * g.words;
-      if (g.kp.nkeys == 0) occ = true;                 // the one ungrouped row
-      else if (i < g.cap) occ = (s[0] != kEmpty64);
-      else occ = (s[1] != 0);                          // out-of-band slot
+  for (; chunk < end; chunk += stride) {
+    uint32_t occ = 0;
+#pragma unroll
+    for (int j = 0; j < kFinalizeSlots; ++j) {
+      const uint64_t i = chunk + static_cast<uint64_t>(j) * blockDim.x + threadIdx.x;
+      if (i >= end) continue;
+      const uint64_t* s = g.slots + i * g.words;
+      bool o;
+      if (g.kp.nkeys == 0) o = true;                 // the one ungrouped row
+      else if (i < g.cap) o = (s[0] != kEmpty64);
+      else o = (s[1] != 0);                          // out-of-band slot
+      occ |= o ? (1u << j) : 0u;
     }
-    uint64_t m = ballot(occ);
-    if (m == 0) continue;
-    unsigned long long at = 0;
-    if (lane == 0) at = atomicAdd(g.d_groups, static_cast<unsigned long long>(popc64(m)));
-    at = first_lane(at);
-    if (!occ) continue;
-    const unsigned long long pos = at + rank_below(m);
-    if (pos >= static_cast<unsigned long long>(p.cap)) continue;
-    const uint64_t pk = (g.kp.nkeys > 0 && i == g.cap) ? kEmpty64 : s[0];
-    if (g.kp.nkeys > 0) {
-      int64_t k0, k1;
-      unpack_keys(g.kp, pk, k0, k1);
-      store_elem(p.out_keys[0], p.out_key_type[0], pos, k0);
-      if (g.kp.nkeys > 1) store_elem(p.out_keys[1], p.out_key_type[1], pos, k1);
+    const uint32_t c = __popc(occ);
+    uint32_t incl = c;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t t = __shfl_up(incl, off, kWave);
+      if (lane >= off) incl += t;
     }
-    const uint64_t count = s[1];
-    for (int a = 0; a < p.naggs; ++a) {
-      const int op = p.op[a];
-      int64_t* out = static_cast<int64_t*>(p.out_aggs[a]);
-      if (op == 1) {
-        out[pos] = static_cast<int64_t>(count);
-      } else if (op == 4) {
-        double avg;
-        if (count == 0) {
-          avg = __longlong_as_double(0x7FF8000000000000LL);
-        } else {
-          avg = static_cast<double>(static_cast<int64_t>(s[2 + p.acc[a]])) /
-                static_cast<double>(static_cast<int64_t>(count));
-        }
-        static_cast<double*>(p.out_aggs[a])[pos] = avg;
-      } else {
-        out[pos] = static_cast<int64_t>(s[2 + p.acc[a]]);
-      }
+    if (lane == kWave - 1) s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < nwaves; ++w) {
+      if (w < wave) before += s_wave[w];
+      total += s_wave[w];
     }
+    if (threadIdx.x == 0)
+      s_base = total ? atomicAdd(g.d_groups, static_cast<unsigned long long>(total)) : 0ULL;
+    __syncthreads();
+    unsigned long long pos = s_base + before + incl - c;
+#pragma unroll
+    for (int j = 0; j < kFinalizeSlots; ++j)
+      if ((occ >> j) & 1u)
+        write_group(p, chunk + static_cast<uint64_t>(j) * blockDim.x + threadIdx.x, pos++);
+    __syncthreads();
   }
 }
 
@@ -153,8 +188,8 @@ __global__ void __launch_bounds__(256) group_finalize_kernel(FinalizeParams p) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *p.g.d_groups = static_cast<unsigned long long>(-1LL);
     return;
   }
-  finalize_range(p, blockIdx.x * static_cast<uint64_t>(blockDim.x), ~0ULL,
-                 static_cast<uint64_t>(gridDim.x) * blockDim.x);
+  const uint64_t span = static_cast<uint64_t>(blockDim.x) * kFinalizeSlots;
+  finalize_range(p, blockIdx.x * span, ~0ULL, static_cast<uint64_t>(gridDim.x) * span);
 }
 
 // One workgroup per item of the batch's merge and finalize lists.
@@ -170,7 +205,7 @@ __global__ void __launch_bounds__(256) batch_finalize_kernel(BatchParams b) {
     if (it.begin == 0 && threadIdx.x == 0) *p.g.d_groups = static_cast<unsigned long long>(-1LL);
     return;
   }
-  finalize_range(p, it.begin, it.end, blockDim.x);
+  finalize_range(p, it.begin, it.end, static_cast<uint64_t>(blockDim.x) * kFinalizeSlots);
 }
 
 }  // namespace
@@ -201,7 +236,7 @@ void launch_group_merge(const GroupDesc& g, hipStream_t s) {
 void launch_group_finalize(const FinalizeParams& p, hipStream_t s) {
   ProfileScope ps(kKFinalize, s);
   uint64_t nslots = p.g.kp.nkeys == 0 ? 1 : p.g.cap + 1;
-  uint64_t blocks = (nslots + 255) / 256;
+  uint64_t blocks = (nslots + 256 * kFinalizeSlots - 1) / (256 * kFinalizeSlots);
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(group_finalize_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
                      p);

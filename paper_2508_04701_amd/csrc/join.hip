@@ -192,12 +192,39 @@ __global__ void __launch_bounds__(256) batch_fill_kernel(BatchParams b) {
   }
 }
 
+// Matched pairs are staged per wave in LDS and written in runs: one cursor
+// atomic per run of at least kProbeFlush pairs instead of one per wave and
+// round (a single global counter shared by every wave serialises otherwise).
+constexpr int kProbeStage = 256;
+constexpr int kProbeFlush = kProbeStage - kWave;
+
+__device__ __forceinline__ void flush_pairs(const MapProbeParams& p, const uint32_t* sb,
+                                            const uint32_t* sp, uint32_t staged, int lane) {
+  __builtin_amdgcn_wave_barrier();
+  unsigned long long at = 0;
+  if (lane == 0) at = atomicAdd(p.d_count, static_cast<unsigned long long>(staged));
+  at = first_lane(at);
+  for (uint32_t i = lane; i < staged; i += kWave) {
+    const unsigned long long pos = at + i;
+    if (pos < static_cast<unsigned long long>(p.cap)) {
+      p.out_build[pos] = sb[i];
+      p.out_probe[pos] = sp[i];
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <typename K>
 __global__ void __launch_bounds__(256) map_probe_kernel(MapProbeParams p) {
+  __shared__ uint32_t s_build[256 / kWave][kProbeStage];
+  __shared__ uint32_t s_probe[256 / kWave][kProbeStage];
   using Slot = typename std::conditional<sizeof(K) == 4, uint64_t, ulonglong2>::type;
   const Slot* slots = static_cast<const Slot*>(p.map.slots);
   const uint64_t mask = p.map.cap - 1;
   const int lane = lane_id();
+  uint32_t* sb = s_build[threadIdx.x / kWave];
+  uint32_t* sp = s_probe[threadIdx.x / kWave];
+  uint32_t staged = 0;  // wave-uniform
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
   // The loop bound is uniform across the workgroup, so whole waves stay
   // together through the ballots below.
@@ -207,7 +234,7 @@ __global__ void __launch_bounds__(256) map_probe_kernel(MapProbeParams p) {
     bool active = i < static_cast<uint64_t>(p.n);
     K key = 0;
     uint32_t prow = 0;
-    MapCursor cur{0, false, false};
+    MapCursor cur{0, false, false, false};
     if (active) {
       int64_t r = p.idx ? static_cast<int64_t>(p.idx[i]) : static_cast<int64_t>(i);
       key = static_cast<K>(load_elem(p.keys, p.type, r));
@@ -225,18 +252,19 @@ __global__ void __launch_bounds__(256) map_probe_kernel(MapProbeParams p) {
       bool found = map_next(slots, mask, p.map.oob_count, p.map.oob_vals, key, cur, bval);
       uint64_t m = ballot(found);
       if (m == 0) continue;
-      unsigned long long at = 0;
-      if (lane == 0) at = atomicAdd(p.d_count, static_cast<unsigned long long>(popc64(m)));
-      at = first_lane(at);
       if (found) {
-        unsigned long long pos = at + rank_below(m);
-        if (pos < static_cast<unsigned long long>(p.cap)) {
-          p.out_build[pos] = bval;
-          p.out_probe[pos] = prow;
-        }
+        const uint32_t at = staged + rank_below(m);
+        sb[at] = bval;
+        sp[at] = prow;
+      }
+      staged += popc64(m);
+      if (staged > static_cast<uint32_t>(kProbeFlush)) {
+        flush_pairs(p, sb, sp, staged, lane);
+        staged = 0;
       }
     }
   }
+  if (staged > 0) flush_pairs(p, sb, sp, staged, lane);
 }
 
 }  // namespace

@@ -72,7 +72,7 @@ def test_filter_validation():
 def test_workspace_sizes():
     L = rel.lib()
     assert L.rel_filter_ws(0) >= 256 + 8
-    assert L.rel_filter_ws(600_000_000) >= 8 * (600_000_000 // 4096)
+    assert L.rel_filter_ws(600_000_000) >= 8 * (600_000_000 // 8192)  # a state word per tile
     small = L.rel_hash_join_ws(2, 10_000, None)
     big = L.rel_hash_join_ws(2, 1_000_000, None)
     assert 0 < small < big

@@ -31,7 +31,7 @@ def col_with_extremes(r, n, dtype, lo, hi, frac=0.05):
 
 # ------------------------------------------------------------------ filter
 
-@pytest.mark.parametrize("n", [0, 1, 7, 4095, 4096, 4097, 100_003, 1_000_000])
+@pytest.mark.parametrize("n", [0, 1, 7, 4095, 4097, 8191, 8192, 8193, 100_003, 1_000_000])
 def test_filter_sizes(n):
     announce("filter sizes", n)
     r = rng(n)
