@@ -1,7 +1,7 @@
 // Selection with ordered stream compaction, one pass over the columns.
 //
-// A workgroup of 256 threads takes one tile of 8192 rows. Thread t of the
-// tile reads rows (j * 1024 + 4 t .. + 3) for j = 0..7, so every column read
+// A workgroup of 512 threads takes one tile of 8192 rows. Thread t of the
+// tile reads rows (j * 2048 + 4 t .. + 3) for j = 0..3, so every column read
 // is a coalesced 16-byte-per-lane vector load. Each passing row sets one bit;
 // per chunk a wave64 ballot per row position gives the wave's count (popcount)
 // and each lane's rank (mbcnt), which places every passing row id at its

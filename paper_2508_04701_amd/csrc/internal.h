@@ -36,8 +36,8 @@ void launch_fill64(uint64_t* p, uint64_t n, uint64_t pattern, hipStream_t s);
 
 // --------------------------------------------------------------- filter
 
-constexpr int kFilterThreads = 256;
-constexpr int kFilterChunks = 8;                               // chunks of 4 rows per thread
+constexpr int kFilterThreads = 512;
+constexpr int kFilterChunks = 4;                               // chunks of 4 rows per thread
 constexpr int kFilterTile = kFilterThreads * 4 * kFilterChunks;  // rows per tile
 
 struct FilterTerm {
