@@ -307,12 +307,15 @@ int default_lds_slots(const rel_tuning* t, int64_t max_groups, int words, size_t
 
 // Replicas of the global group table: a tuned count, else kGroupReplicas
 // when every group fits the LDS tables (only their flushes reach the global
-// table), else as many as keep the copies within kReplicaBytes (at most
-// kSpillReplicas): rows that spill from LDS update the global table with
-// device-scope atomics, which serialise per cache line, so copies spread the
-// hot lines (workgroup w updates copy w mod replicas, and w mod 8 is its XCD).
+// table), else, for tables up to kSpillTableBytes, as many as keep the copies
+// within kReplicaBytes (at most kSpillReplicas): rows that spill from LDS
+// update the global table with device-scope atomics, which serialise per
+// cache line, so copies spread the hot lines (workgroup w updates copy
+// w mod replicas, and w mod 8 is its XCD). Larger tables already spread their
+// atomics over many lines; copies would only add fill and merge traffic.
 constexpr int kSpillReplicas = 32;
 constexpr uint64_t kReplicaBytes = 256ull << 20;
+constexpr uint64_t kSpillTableBytes = 1ull << 20;
 
 int group_replicas(const rel_tuning* t, int64_t max_groups, int lds_slots, int words, float lf) {
   if (t && t->replicas > 0) return t->replicas;
@@ -320,6 +323,7 @@ int group_replicas(const rel_tuning* t, int64_t max_groups, int lds_slots, int w
   const uint64_t want = static_cast<uint64_t>(std::ceil(static_cast<double>(max_groups < 1 ? 1 : max_groups) / lf));
   const uint64_t table = next_pow2(want < 64 ? 64 : want) * static_cast<uint64_t>(words) * 8;
   int r = 1;
+  if (table > kSpillTableBytes) return r;
   while (r < kSpillReplicas && 2 * r * table <= kReplicaBytes) r *= 2;
   return r;
 }

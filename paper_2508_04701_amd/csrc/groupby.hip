@@ -21,13 +21,19 @@ namespace {
 
 __global__ void group_init_kernel(GroupDesc g) {
   const uint64_t total = g.replicas * (g.cap + 1) * static_cast<uint64_t>(g.words);
-  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < total;
-       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const int w = static_cast<int>(i % g.words);
+  const uint64_t first = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  const uint32_t words = static_cast<uint32_t>(g.words);
+  // word index within the slot, stepped by the stride mod words
+  uint32_t w = static_cast<uint32_t>(first % words);
+  const uint32_t step = static_cast<uint32_t>(stride % words);
+  for (uint64_t i = first; i < total; i += stride) {
     uint64_t v = 0;
     if (w == 0) v = kEmpty64;
-    else if (w >= 2 && w - 2 < g.ap.nacc) v = acc_identity(g.ap.kind[w - 2]);
+    else if (w >= 2 && static_cast<int>(w) - 2 < g.ap.nacc) v = acc_identity(g.ap.kind[w - 2]);
     g.slots[i] = v;
+    w += step;
+    if (w >= words) w -= words;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *g.overflow = 0;

@@ -178,12 +178,18 @@ __global__ void __launch_bounds__(256) batch_fill_kernel(BatchParams b) {
   if (kind == kFillGroup) {
     const GroupDesc& g = batch_at(b.plans, f.inst).g;
     const uint32_t words = static_cast<uint32_t>(g.words);
-    for (uint64_t i = f.begin + threadIdx.x; i < f.end; i += blockDim.x) {
-      const uint32_t w = static_cast<uint32_t>(i % words);
+    // word index within the slot, stepped by blockDim mod words (no division
+    // in the loop)
+    const uint64_t first = f.begin + threadIdx.x;
+    uint32_t w = static_cast<uint32_t>(first % words);
+    const uint32_t step = blockDim.x % words;
+    for (uint64_t i = first; i < f.end; i += blockDim.x) {
       uint64_t v = 0;
       if (w == 0) v = kEmpty64;
       else if (w >= 2 && static_cast<int>(w) - 2 < g.ap.nacc) v = acc_identity(g.ap.kind[w - 2]);
       out[i] = v;
+      w += step;
+      if (w >= words) w -= words;
     }
   } else {
     const uint64_t pattern = f.pattern;
