@@ -114,6 +114,11 @@ typedef struct {
   int32_t replicas;      /* copies of the global group table; workgroup w updates copy
                             w mod replicas (w mod 8 is its XCD) and a last pass folds them;
                             0 = default (64 when all groups fit the LDS tables, else 1) */
+  int32_t fanout;        /* rel_groupby_agg: partitions of the radix-partitioned
+                            aggregation, a power of two in [4, 16384]; 0 = default
+                            (partitioned when the group table exceeds 64 MB, with as many
+                            partitions as keep each one's keys within an LDS table);
+                            -1 = never partition */
 } rel_tuning;
 
 /* rel_tuning.flags: keep dims of rel_pipeline in their hash tables even when
@@ -179,12 +184,16 @@ rel_status rel_hash_join(const rel_column* build_keys, const rel_column* probe_k
 
 /* ------------------------------------------------------------- group-by */
 
-/* Workspace bytes for rel_groupby_agg with at most max_groups groups. */
+/* Workspace bytes for rel_groupby_agg over at most n_rows rows with at most
+ * max_groups groups (0 for invalid arguments). With partitioning (see
+ * rel_tuning.fanout) it includes two buffers of n_rows records, each the key
+ * tuple and one int64 per distinct value column that an aggregate reads. */
 size_t rel_groupby_ws(int nkeys, const int32_t* key_types, int naggs, const rel_agg* aggs,
-                      int64_t max_groups, const rel_tuning* t);
+                      int64_t n_rows, int64_t max_groups, const rel_tuning* t);
 
 /* Hash group-by aggregation (Section 4.2: hash-based grouping, with memory
- * contention when there are few groups): one output row per distinct key
+ * contention when there are few groups; many groups are radix-partitioned
+ * first, see rel_tuning.fanout): one output row per distinct key
  * tuple of `keys` (0..REL_MAX_KEYS columns; with none, exactly one row, even
  * over no input rows), with the aggregates `aggs` over the value columns
  * `vals`. Row order is unspecified (compare after sorting by key tuple).
@@ -423,7 +432,8 @@ typedef enum {
   REL_K_GROUP_AGG = 4,   /* rel_groupby_agg's aggregation kernel */
   REL_K_PIPELINE = 5,    /* rel_pipeline's fused filter-probe-aggregate kernel */
   REL_K_FINALIZE = 6,    /* group compaction into the outputs */
-  REL_K_COUNT = 7
+  REL_K_GROUP_PARTITION = 7, /* rel_groupby_agg's counting and scatter passes */
+  REL_K_COUNT = 8
 } rel_kernel_class;
 
 /* Static name of a kernel class. */

@@ -67,6 +67,10 @@ rel_status check_tuning(const rel_tuning* t) {
   if (t->chunk_tiles < 0) return fail(REL_EINVAL, "tuning.chunk_tiles must be >= 0");
   if (t->replicas < 0 || t->replicas > 256)
     return fail(REL_EINVAL, "tuning.replicas must be in [0, 256]");
+  if (t->fanout < -1 || (t->fanout > 0 && (t->fanout < 4 || t->fanout > (1 << kPartMaxBits) ||
+                                          (t->fanout & (t->fanout - 1)) != 0)))
+    return fail(REL_EINVAL, "tuning.fanout must be -1, 0 or a power of two in [4, %d]",
+                1 << kPartMaxBits);
   return REL_OK;
 }
 
@@ -918,6 +922,68 @@ const DeviceInfo& device_info() {
   return info[dev];
 }
 
+// Radix-partitioned aggregation (see groupby_part.hip): used by default when
+// the group table exceeds kPartTableBytes, where rows would otherwise update
+// it with random read-modify-writes in HBM.
+constexpr uint64_t kPartTableBytes = 64ull << 20;
+constexpr size_t kPartAggLds = 128 * 1024;  // LDS of the aggregation pass
+constexpr uint32_t kPartPiece = 65536;       // records per aggregation work item
+constexpr double kPartFill = 0.6;            // target keys per LDS slot of a partition
+
+struct PartPlan {
+  bool on = false;
+  int b1 = 0, b2 = 0, pre_slots = 0, agg_slots = 0;
+  int ncols = 0, rw = 1;
+  int cols[kMaxAcc] = {};  // value column (of the call) of each record column
+  int src[kMaxAcc] = {};   // record column of each accumulator
+  size_t ctl_off = 0, a_off = 0, b_off = 0;
+};
+
+int log2_ceil(uint64_t v) {
+  int b = 0;
+  while ((1ull << b) < v) ++b;
+  return b;
+}
+
+// Layout of rel_groupby_agg over n rows: the group table, and with
+// partitioning its control words and two record buffers of n records.
+GroupLayout groupby_layout(const GroupPlan& gp, int64_t n, int64_t max_groups,
+                           const rel_tuning* t, PartPlan& pp) {
+  pp = PartPlan();
+  const int fan = t ? t->fanout : 0;
+  const float lf = load_factor(t);
+  GroupLayout one = group_layout(gp, max_groups, lf, 0, 1);
+  const uint64_t table = (one.cap + 1) * static_cast<uint64_t>(gp.words) * 8;
+  if (fan < 0 || gp.kp.nkeys == 0 || n <= 0 || (fan == 0 && table < kPartTableBytes))
+    return group_layout(gp, max_groups, lf, 0, groupby_replicas(t, max_groups, gp));
+  pp.on = true;
+  pp.agg_slots = static_cast<int>(next_pow2(kPartAggLds / (static_cast<size_t>(gp.words) * 8) + 1) / 2);
+  int pb;
+  if (fan > 0) {
+    pb = log2_ceil(static_cast<uint64_t>(fan));
+  } else {
+    const double per = kPartFill * pp.agg_slots;
+    pb = log2_ceil(static_cast<uint64_t>(std::ceil(static_cast<double>(max_groups) / per)));
+  }
+  if (pb < 2) pb = 2;
+  if (pb > kPartMaxBits) pb = kPartMaxBits;
+  pp.b1 = (pb + 1) / 2;
+  pp.b2 = pb - pp.b1;
+  pp.pre_slots = default_lds_slots(t, max_groups, gp.words, 32768);
+  for (int a = 0; a < gp.ap.nacc; ++a) {
+    int c = 0;
+    while (c < pp.ncols && pp.cols[c] != gp.ap.col[a]) ++c;
+    if (c == pp.ncols) pp.cols[pp.ncols++] = gp.ap.col[a];
+    pp.src[a] = c;
+  }
+  pp.rw = 1 + pp.ncols;
+  pp.ctl_off = one.end;
+  pp.a_off = align_up(pp.ctl_off + kCtlWords * 8);
+  pp.b_off = align_up(pp.a_off + static_cast<size_t>(n) * pp.rw * 8);
+  one.end = align_up(pp.b_off + static_cast<size_t>(n) * pp.rw * 8);
+  return one;
+}
+
 }  // namespace rel
 
 using namespace rel;
@@ -1063,15 +1129,17 @@ rel_status rel_hash_join(const rel_column* build_keys, const rel_column* probe_k
 // ---------------------------------------------------------------- group-by
 
 size_t rel_groupby_ws(int nkeys, const int32_t* key_types, int naggs, const rel_agg* aggs,
-                      int64_t max_groups, const rel_tuning* t) {
+                      int64_t n_rows, int64_t max_groups, const rel_tuning* t) {
   if (nkeys < 0 || nkeys > REL_MAX_KEYS || naggs < 1 || naggs > REL_MAX_AGGS || !aggs ||
-      (nkeys > 0 && !key_types) || max_groups < 0)
+      (nkeys > 0 && !key_types) || max_groups < 0 || n_rows < 0 || n_rows > kMaxRows)
     return 0;
   for (int k = 0; k < nkeys; ++k)
     if (!valid_type(key_types[k])) return 0;
+  if (t && check_tuning(t) != REL_OK) return 0;
   GroupPlan gp;
   if (group_plan(nkeys, key_types, naggs, aggs, gp) != REL_OK) return 0;
-  return group_layout(gp, max_groups, load_factor(t), 0, groupby_replicas(t, max_groups, gp)).end;
+  PartPlan pp;
+  return groupby_layout(gp, n_rows, max_groups, t, pp).end;
 }
 
 rel_status rel_groupby_agg(const rel_column* keys, int nkeys, const rel_column* vals, int nvals,
@@ -1108,8 +1176,8 @@ rel_status rel_groupby_agg(const rel_column* keys, int nkeys, const rel_column* 
   GroupPlan gp;
   st = group_plan(nkeys, key_types, naggs, aggs, gp);
   if (st) return st;
-  const GroupLayout L =
-      group_layout(gp, max_groups, load_factor(t), 0, groupby_replicas(t, max_groups, gp));
+  PartPlan pp;
+  const GroupLayout L = groupby_layout(gp, n, max_groups, t, pp);
   st = check_ws(ws, ws_bytes, L.end);
   if (st) return st;
 
@@ -1117,7 +1185,42 @@ rel_status rel_groupby_agg(const rel_column* keys, int nkeys, const rel_column* 
   unsigned char* w = static_cast<unsigned char*>(ws);
   const GroupDesc g = group_desc(gp, L, w, d_groups);
   launch_group_init(g, s);
-  if (n > 0) {
+  if (pp.on) {
+    PartParams p;
+    std::memset(&p, 0, sizeof p);
+    p.g = g;
+    for (int k = 0; k < nkeys; ++k) {
+      p.key_data[k] = keys[k].data;
+      p.key_idx[k] = keys[k].idx;
+    }
+    for (int c = 0; c < pp.ncols; ++c) {
+      const rel_column& col = vals[pp.cols[c]];
+      p.col_data[c] = col.data;
+      p.col_idx[c] = col.idx;
+      p.col_type[c] = col.type;
+    }
+    p.ncols = pp.ncols;
+    for (int a = 0; a < gp.ap.nacc; ++a) p.src[a] = pp.src[a];
+    p.rw = pp.rw;
+    p.n = n;
+    p.b1 = pp.b1;
+    p.b2 = pp.b2;
+    p.pre_slots = pp.pre_slots;
+    p.agg_slots = pp.agg_slots;
+    p.piece = kPartPiece;
+    p.ctl = reinterpret_cast<unsigned long long*>(w + pp.ctl_off);
+    p.rec_a = reinterpret_cast<uint64_t*>(w + pp.a_off);
+    p.rec_b = reinterpret_cast<uint64_t*>(w + pp.b_off);
+    const DeviceInfo& di = device_info();
+    const size_t scatter_lds = static_cast<size_t>(p.pre_slots) * gp.words * 8 +
+                               (sizeof(uint32_t) << (p.b1 + p.b2)) + 12 * (1u << kPartLevelBits);
+    if (scatter_lds > static_cast<size_t>(di.lds_per_block) ||
+        static_cast<size_t>(p.agg_slots) * gp.words * 8 > static_cast<size_t>(di.lds_per_block))
+      return fail(REL_EUNSUPPORTED, "groupby: the partitioned tables exceed the LDS of a workgroup");
+    launch_fill64(reinterpret_cast<uint64_t*>(p.ctl), kCtlZero, 0, s);
+    hipError_t e = launch_group_partitioned(p, s);
+    if (e != hipSuccess) return fail(REL_EDEVICE, "groupby: %s", hipGetErrorString(e));
+  } else if (n > 0) {
     GroupAggParams p;
     std::memset(&p, 0, sizeof p);
     p.g = g;

@@ -515,7 +515,9 @@ __device__ __forceinline__ uint64_t acc_identity(int32_t kind) {
 // Finds or claims the slot of packed key pk; NULL if the table is full.
 __device__ __forceinline__ uint64_t* group_slot(const GroupTable& t, uint64_t pk) {
   if (pk == kEmpty64) return t.slots + (t.mask + 1) * t.words;
-  uint64_t h = hash64(pk) & t.mask;
+  // The top hash bits index the slots: keys whose hashes share a prefix land
+  // in one range of the table (a partition of the partitioned aggregation).
+  uint64_t h = t.mask ? hash64(pk) >> __clzll(static_cast<long long>(t.mask)) : 0;
   for (uint64_t probes = 0; probes <= t.mask; ++probes) {
     uint64_t* s = t.slots + h * t.words;
     uint64_t cur = __hip_atomic_load(s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -536,7 +538,10 @@ __device__ __forceinline__ uint64_t* group_slot(const GroupTable& t, uint64_t pk
 __device__ __forceinline__ void group_update_global(uint64_t* s, const AccPlan& ap, uint64_t cnt,
                                                     const uint64_t* acc) {
   atomicAdd(reinterpret_cast<unsigned long long*>(s + 1), static_cast<unsigned long long>(cnt));
-  for (int a = 0; a < ap.nacc; ++a) {
+  // unrolled to the bound so that acc[] stays in registers
+#pragma unroll
+  for (int a = 0; a < kMaxAcc; ++a) {
+    if (a >= ap.nacc) break;
     uint64_t* w = s + 2 + a;
     if (ap.kind[a] == kAccSum) {
       atomicAdd(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(acc[a]));

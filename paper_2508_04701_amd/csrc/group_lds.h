@@ -28,11 +28,12 @@ __device__ __forceinline__ uint32_t lds_hash(uint64_t pk) {
 // Index of the LDS slot holding (or newly claimed for) packed key pk, or -1
 // when the key is the sentinel pattern, there is no LDS table, or no slot is
 // free within the probe window.
-__device__ __forceinline__ int32_t lds_group_find(uint64_t* t, int slots, int words, uint64_t pk) {
+__device__ __forceinline__ int32_t lds_group_find(uint64_t* t, int slots, int words, uint64_t pk,
+                                                  int window = kLdsProbe) {
   if (pk == kEmpty64 || slots == 0) return -1;
   const uint32_t mask = static_cast<uint32_t>(slots - 1);
   uint32_t h = lds_hash(pk) & mask;
-  const int window = slots < kLdsProbe ? slots : kLdsProbe;
+  if (window > slots) window = slots;
   for (int probe = 0; probe < window; ++probe) {
     uint64_t* s = t + h * words;
     const uint64_t cur = __hip_atomic_load(s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -55,7 +56,10 @@ __device__ __forceinline__ uint64_t* lds_group_slot(uint64_t* t, int slots, int 
 
 __device__ __forceinline__ void lds_group_update(uint64_t* s, const AccPlan& ap, const uint64_t* acc) {
   atomicAdd(reinterpret_cast<unsigned long long*>(s + 1), 1ULL);
-  for (int a = 0; a < ap.nacc; ++a) {
+  // unrolled to the bound so that acc[] stays in registers
+#pragma unroll
+  for (int a = 0; a < kMaxAcc; ++a) {
+    if (a >= ap.nacc) break;
     uint64_t* w = s + 2 + a;
     if (ap.kind[a] == kAccSum) {
       atomicAdd(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(acc[a]));

@@ -21,7 +21,8 @@ const DeviceInfo& device_info();
 // Per-kernel timing: when enabled, launch sites bracket each kernel with a
 // pair of events on the launch stream (kernel classes as in rel.h).
 enum KernelClass : int {
-  kKFill = 0, kKFilter, kKMapBuild, kKMapProbe, kKGroupAgg, kKPipeline, kKFinalize, kKCount
+  kKFill = 0, kKFilter, kKMapBuild, kKMapProbe, kKGroupAgg, kKPipeline, kKFinalize,
+  kKGroupPartition, kKCount
 };
 struct ProfileScope {
   ProfileScope(int kclass, hipStream_t s);
@@ -227,6 +228,58 @@ struct GroupAggParams {
 };
 
 void launch_group_agg(const GroupAggParams& p, int grid, int block, hipStream_t s);
+
+// Radix-partitioned aggregation for group tables far beyond the caches.
+// Rows are split by the top pb = b1 + b2 bits of the key hash into 2^pb
+// partitions in two scatter passes (2^b1 buckets, then 2^b2 partitions per
+// bucket), so that each partition holds few enough distinct keys for an LDS
+// table; the aggregation pass then folds each partition in LDS and merges the
+// table into the global one. The global table indexes its slots by the top
+// hash bits too, so partition q's merges stay within slot range q of the
+// table. The first scatter keeps a small LDS table of its own: rows whose key
+// it holds (the hot keys under skew) are aggregated there and never moved.
+// A record is the packed key followed by the row's value columns (int64).
+constexpr int kPartMaxBits = 14;     // at most 2^14 partitions
+constexpr int kPartLevelBits = 7;    // at most 2^7 ways per scatter pass
+constexpr int kPartThreads = 512;    // scatter workgroups
+constexpr int kPartRows = 16;        // rows (records) per thread and scatter tile
+constexpr int kPartTile = kPartThreads * kPartRows;
+constexpr int kPartAggThreads = 1024;
+constexpr int kPartPad = 16;         // words between claim cursors (one 128-byte line)
+// Control words: histograms, prefix sums and claim cursors.
+constexpr uint64_t kCtlHist1 = 0;                                  // 2^b1 bucket sizes
+constexpr uint64_t kCtlHist2 = 256;                                // 2^pb partition sizes
+constexpr uint64_t kCtlZero = kCtlHist2 + (1u << kPartMaxBits);    // words zeroed per call
+constexpr uint64_t kCtlStart1 = kCtlZero;                          // 2^b1 + 1 bucket starts
+constexpr uint64_t kCtlTiles = kCtlStart1 + 256;                   // 2^b1 + 1 tile prefix
+constexpr uint64_t kCtlStart2 = kCtlTiles + 256;                   // 2^pb + 1 partition starts
+constexpr uint64_t kCtlPieces = kCtlStart2 + (1u << kPartMaxBits) + 256;  // 2^pb + 1 piece prefix
+constexpr uint64_t kCtlCur1 = kCtlPieces + (1u << kPartMaxBits) + 256;    // 2^b1 padded cursors
+constexpr uint64_t kCtlCur2 = kCtlCur1 + (1u << kPartLevelBits) * kPartPad;  // 2^pb padded cursors
+constexpr uint64_t kCtlWords = kCtlCur2 + (1u << kPartMaxBits) * static_cast<uint64_t>(kPartPad);
+
+struct PartParams {
+  GroupDesc g;  // one replica
+  const void* key_data[2];
+  const uint32_t* key_idx[2];
+  const void* col_data[kMaxAcc];  // value columns copied into the records
+  const uint32_t* col_idx[kMaxAcc];
+  int32_t col_type[kMaxAcc];
+  int32_t ncols;
+  int32_t src[kMaxAcc];  // accumulator a aggregates record word 1 + src[a]
+  int32_t rw;            // record words: 1 + ncols
+  int64_t n;
+  int32_t b1, b2;
+  int32_t pre_slots;  // LDS table of the first scatter (0: none)
+  int32_t agg_slots;  // LDS table of the aggregation pass (power of two)
+  uint32_t piece;     // records per aggregation work item
+  uint64_t* rec_a;    // n * rw words: records grouped by bucket
+  uint64_t* rec_b;    // n * rw words: records grouped by partition
+  unsigned long long* ctl;  // kCtlWords control words
+};
+
+// Runs the counting, scatter and aggregation passes into p.g (initialised).
+hipError_t launch_group_partitioned(const PartParams& p, hipStream_t s);
 
 // Output agg a: op (rel_agg_op) and the accumulator it reads.
 struct FinalizeParams {

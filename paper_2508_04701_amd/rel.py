@@ -55,7 +55,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("load_factor", ctypes.c_float), ("block", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("lds_slots", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("dim_lds_bytes", ctypes.c_int32),
-                ("chunk_tiles", ctypes.c_int32), ("replicas", ctypes.c_int32)]
+                ("chunk_tiles", ctypes.c_int32), ("replicas", ctypes.c_int32),
+                ("fanout", ctypes.c_int32)]
 
 
 class Dim(ctypes.Structure):
@@ -91,7 +92,7 @@ SIGNATURES = {
     "rel_filter": (_I, [_P, _I, _P, _I, _P, _L, _P, _P, _S, _P]),
     "rel_hash_join_ws": (_S, [ctypes.c_int32, _L, _P]),
     "rel_hash_join": (_I, [_P, _P, _P, _P, _L, _P, _P, _P, _S, _P]),
-    "rel_groupby_ws": (_S, [_I, _P, _I, _P, _L, _P]),
+    "rel_groupby_ws": (_S, [_I, _P, _I, _P, _L, _L, _P]),
     "rel_groupby_agg": (_I, [_P, _I, _P, _I, _P, _I, _P, _P, _L, _P, _L, _P, _P, _S, _P]),
     "rel_pipeline_ws": (_S, [_P]),
     "rel_pipeline": (_I, [_P, _P, _P, _S, _P]),
@@ -168,8 +169,9 @@ TUNE_NO_DIRECT = 1
 
 
 def tuning(load_factor=0.0, block=0, grid=0, lds_slots=0, dim_lds_bytes=0,
-           chunk_tiles=0, replicas=0, flags=0) -> Tuning:
-    return Tuning(load_factor, block, grid, lds_slots, flags, dim_lds_bytes, chunk_tiles, replicas)
+           chunk_tiles=0, replicas=0, flags=0, fanout=0) -> Tuning:
+    return Tuning(load_factor, block, grid, lds_slots, flags, dim_lds_bytes, chunk_tiles, replicas,
+                  fanout)
 
 
 def _tuning_ptr(t):
@@ -267,10 +269,10 @@ def _out_tensors(key_dtypes, aggs, cap, dev):
     return out_keys, out_aggs
 
 
-def groupby_ws(key_dtypes, aggs, max_groups: int, t: Tuning | None = None) -> int:
+def groupby_ws(key_dtypes, aggs, n_rows: int, max_groups: int, t: Tuning | None = None) -> int:
     kt = _arr(ctypes.c_int32, [DTYPES[d] for d in key_dtypes])
-    return int(lib().rel_groupby_ws(len(key_dtypes), kt, len(aggs), _aggs(aggs), max_groups,
-                                    _tuning_ptr(t)))
+    return int(lib().rel_groupby_ws(len(key_dtypes), kt, len(aggs), _aggs(aggs), n_rows,
+                                    max_groups, _tuning_ptr(t)))
 
 
 def groupby_agg_async(keys, vals, aggs, out_keys, out_aggs, d_groups, max_groups, ws,
@@ -293,7 +295,7 @@ def groupby_agg(keys, vals, aggs, max_groups: int | None = None, key_idx=None, v
     n = key_idx.numel() if key_idx is not None else (keys or vals)[0].numel()
     max_groups = max(1, n) if max_groups is None else max_groups
     key_dtypes = [k.dtype for k in keys]
-    ws = workspace(groupby_ws(key_dtypes, aggs, max_groups, t), dev)
+    ws = workspace(groupby_ws(key_dtypes, aggs, n, max_groups, t), dev)
     d_groups = torch.zeros(1, dtype=torch.int64, device=dev)
     cap = max(1, min(max_groups, max(1, n)))
     while True:
@@ -442,7 +444,7 @@ def pipeline(fact, preds, dims, keys, aggs, max_groups: int, t: Tuning | None = 
 
 # ------------------------------------------------------------------ profiling
 
-KERNEL_CLASSES = 7
+KERNEL_CLASSES = 8
 
 
 def profile_enable(on: bool = True):

@@ -82,9 +82,23 @@ def test_workspace_sizes():
     assert L.rel_hash_join_ws(2, 600_000, ctypes.byref(t)) < L.rel_hash_join_ws(2, 600_000, None)
     aggs = (rel.Agg * 2)(rel.Agg(0, 0), rel.Agg(1, 0))
     kt = (ctypes.c_int32 * 2)(2, 1)
-    assert L.rel_groupby_ws(2, kt, 2, aggs, 100, None) > 0
+    assert L.rel_groupby_ws(2, kt, 2, aggs, 1000, 100, None) > 0
     kt64 = (ctypes.c_int32 * 2)(3, 2)
-    assert L.rel_groupby_ws(2, kt64, 2, aggs, 100, None) == 0   # 96-bit key tuple
+    assert L.rel_groupby_ws(2, kt64, 2, aggs, 1000, 100, None) == 0   # 96-bit key tuple
+    # many groups: the radix-partitioned path adds two buffers of n records
+    # (key + one value column = 16 bytes each), unless partitioning is off
+    k1 = (ctypes.c_int32 * 1)(3)
+    n, g = 40_000_000, 10_000_000
+    off = rel.tuning(fanout=-1)
+    single = L.rel_groupby_ws(1, k1, 2, aggs, n, g, ctypes.byref(off))
+    part = L.rel_groupby_ws(1, k1, 2, aggs, n, g, None)
+    assert part >= single + 2 * 16 * n
+    assert L.rel_groupby_ws(1, k1, 2, aggs, n, 1000, None) < 2 * 16 * n   # small tables: no buffers
+    forced = rel.tuning(fanout=64)
+    assert L.rel_groupby_ws(1, k1, 2, aggs, 1000, 100, ctypes.byref(forced)) >= 2 * 16 * 1000
+    for bad in (3, 2, 100, 1 << 15, -2):
+        t = rel.tuning(fanout=bad)
+        assert L.rel_groupby_ws(1, k1, 2, aggs, 1000, 100, ctypes.byref(t)) == 0
 
 
 def test_join_and_groupby_validation():

@@ -248,6 +248,110 @@ def test_groupby_with_row_ids():
     assert_groups(got, oracle.groupby([k[sel]], [v[sel]], aggs), aggs, "idx")
 
 
+# ------------------------------------------------- partitioned group-by
+
+PAIR_AGGS = [("sum", 0), ("count", None), ("avg", 0), ("min", 0), ("max", 0)]
+
+
+def partitioned_run(fn):
+    """fn() with the kernel profiler on; asserts that the partitioning passes ran."""
+    rel.profile_enable(True)
+    try:
+        out = fn()
+        prof = rel.profile_read()
+    finally:
+        rel.profile_enable(False)
+    assert prof["group_partition"][1] > 0, "the partitioned aggregation did not run"
+    return out
+
+
+@pytest.mark.parametrize("key_dtypes,ngroups,fanout,lds", [
+    ([np.int32], 5000, 64, 0),
+    ([np.int64], 200_000, 16384, 0),
+    ([np.int64], 200_000, 4, -1),        # partitions far beyond an LDS table
+    ([np.int8, np.int32], 5000, 256, 0),
+    ([np.int32, np.int32], 200_000, 1024, -1),
+    ([np.int32, np.int8], 3, 16, 0),
+], ids=["i32-5k-f64", "i64-200k-f16384", "i64-200k-f4-nolds", "i8+i32-5k-f256",
+        "i32+i32-200k-f1024-nolds", "i32+i8-3-f16"])
+def test_groupby_partitioned(key_dtypes, ngroups, fanout, lds):
+    """Radix-partitioned aggregation forced by the fan-out, over keys of
+    every width and three value columns (four-word records)."""
+    r = rng(ngroups + 7 * fanout)
+    n = 150_001
+    keys, vals = groupby_inputs(r, n, key_dtypes, ngroups)
+    announce("groupby partitioned", [np.dtype(d).name for d in key_dtypes], ngroups, fanout, lds)
+    t = rel.tuning(lds_slots=lds, fanout=fanout)
+    got = partitioned_run(lambda: rel.groupby_agg(
+        [dev(k) for k in keys], [dev(v) for v in vals], ALL_AGGS,
+        max_groups=min(n, ngroups ** len(key_dtypes)), t=t))
+    assert_groups(got, oracle.groupby(keys, vals, ALL_AGGS), ALL_AGGS,
+                  f"partitioned groupby {key_dtypes} {ngroups} fanout {fanout}")
+
+
+@pytest.mark.parametrize("n,fanout,lds", [(1, 16, 0), (8192, 64, 64), (8193, 64, -1),
+                                          (300_001, 4, -1), (1_000_003, 0, 0)])
+def test_groupby_partitioned_skew(n, fanout, lds):
+    """Zipf(1) int64 keys over 1M ranks and one value column (two-word
+    records): hot keys stay in the first scatter's LDS table and the tail is
+    partitioned; at fan-out 4 without that table a partition exceeds one
+    aggregation piece (65536 records); fan-out 0 with 3M groups takes the
+    automatic path (a group table above 64 MB)."""
+    seed = 90 + n
+    ranks = datagen.zipf_ranks(seed, 1, 1_000_000, 1.0, n)
+    k = ((ranks * 2654435761) % (1 << 40) - (1 << 39)).astype(np.int64)
+    v = datagen.uniform(seed, 2, -10**9, 10**9, n, np.int64)
+    announce("groupby partitioned skew", n, fanout, lds)
+    t = rel.tuning(lds_slots=lds, fanout=fanout)
+    got = partitioned_run(lambda: rel.groupby_agg(
+        [dev(k)], [dev(v)], PAIR_AGGS, max_groups=3_000_000 if fanout == 0 else n, t=t))
+    assert_groups(got, oracle.groupby([k], [v], PAIR_AGGS), PAIR_AGGS,
+                  f"partitioned skew n={n} fanout={fanout}")
+
+
+def test_groupby_partitioned_sentinels_idx_overflow():
+    announce("groupby partitioned sentinel/idx/overflow")
+    r = rng(9)
+    n = 60_000
+    v = r.integers(-50, 50, size=n).astype(np.int64)
+    k64 = r.integers(-5000, 5000, size=n).astype(np.int64)
+    pick = r.random(n) < 0.2
+    k64[pick] = r.choice(np.array([I64_MIN, I64_MAX, -1, 0], dtype=np.int64), size=int(pick.sum()))
+    got = partitioned_run(lambda: rel.groupby_agg([dev(k64)], [dev(v)], PAIR_AGGS, max_groups=n,
+                                                  t=rel.tuning(fanout=16)))
+    assert_groups(got, oracle.groupby([k64], [v], PAIR_AGGS), PAIR_AGGS, "partitioned sentinel")
+    # gathered columns
+    sel = r.permutation(n)[: n // 2].astype(np.uint32)
+    si = dev(sel.view(np.int32))
+    got = partitioned_run(lambda: rel.groupby_agg([dev(k64)], [dev(v)], PAIR_AGGS, max_groups=n,
+                                                  key_idx=si, val_idx=si,
+                                                  t=rel.tuning(fanout=64)))
+    assert_groups(got, oracle.groupby([k64[sel]], [v[sel]], PAIR_AGGS), PAIR_AGGS,
+                  "partitioned idx")
+    # more distinct keys than the table sized for max_groups holds
+    k = np.arange(10_000, dtype=np.int32)
+    with pytest.raises(rel.RelError) as e:
+        rel.groupby_agg([dev(k)], [dev(np.ones(10_000, np.int64))], [("sum", 0)], max_groups=1,
+                        t=rel.tuning(fanout=4))
+    assert e.value.status == rel.REL_ECAPACITY
+
+
+def test_groupby_partitioned_matches_single_pass():
+    """The same call with and without partitioning, COUNT only (one-word
+    records) and a pair of int32 keys: identical groups."""
+    announce("groupby partitioned vs single pass")
+    r = rng(12)
+    n = 500_000
+    a = r.integers(0, 700, size=n).astype(np.int32)
+    b = r.integers(0, 700, size=n).astype(np.int32)
+    aggs = [("count", None)]
+    one = rel.groupby_agg([dev(a), dev(b)], [], aggs, max_groups=n, t=rel.tuning(fanout=-1))
+    two = partitioned_run(lambda: rel.groupby_agg([dev(a), dev(b)], [], aggs, max_groups=n,
+                                                  t=rel.tuning(fanout=512)))
+    assert_groups(two, oracle.groupby([a, b], [], aggs), aggs, "partitioned count")
+    assert_groups(one, oracle.groupby([a, b], [], aggs), aggs, "single-pass count")
+
+
 # ---------------------------------------------------------------- pipeline
 
 STAR_AGGS = [("sum", 3), ("count", None), ("avg", 3), ("min", 3), ("max", 3)]
