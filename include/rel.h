@@ -105,7 +105,8 @@ typedef struct {
   float load_factor; /* hash-table fill target in (0, 0.9]; 0 = default (0.5) */
   int32_t block;     /* threads per workgroup, a multiple of 64 up to 1024; 0 = default */
   int32_t grid;      /* workgroups of persistent kernels; 0 = default (from the CU count) */
-  int32_t lds_slots; /* slots of the per-workgroup LDS group table; 0 = default, -1 = none */
+  int32_t lds_slots; /* slots of the per-workgroup LDS group table; 0 = default, -1 = none
+                        (partitioned rel_groupby_agg: the first scatter's table) */
   int32_t flags;     /* REL_TUNE_* bits; 0 = none */
   int32_t dim_lds_bytes; /* LDS bytes rel_pipeline may give to dim tables; 0 = default (32 KB),
                             -1 = none */

@@ -54,8 +54,11 @@ __device__ __forceinline__ uint64_t* lds_group_slot(uint64_t* t, int slots, int 
   return i < 0 ? nullptr : t + i * words;
 }
 
-__device__ __forceinline__ void lds_group_update(uint64_t* s, const AccPlan& ap, const uint64_t* acc) {
-  atomicAdd(reinterpret_cast<unsigned long long*>(s + 1), 1ULL);
+// Adds `cnt` rows (default one) with accumulator contributions acc[] to
+// LDS slot s.
+__device__ __forceinline__ void lds_group_update(uint64_t* s, const AccPlan& ap, const uint64_t* acc,
+                                                 uint64_t cnt = 1) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(s + 1), static_cast<unsigned long long>(cnt));
   // unrolled to the bound so that acc[] stays in registers
 #pragma unroll
   for (int a = 0; a < kMaxAcc; ++a) {

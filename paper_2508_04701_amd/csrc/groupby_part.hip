@@ -3,13 +3,16 @@
 // caches: there every row would otherwise pay a random read-modify-write of a
 // table line in HBM).
 //
-//   count     per bucket (top b1 hash bits), the rows: an upper bound of
-//             each bucket's records, so the first scatter has its regions;
-//   scatter 1 rows -> records grouped by bucket. A small per-workgroup LDS
-//             table aggregates the keys it already holds (under skew, the
-//             hot ones, met first); only the other rows become records. The
+//   count     workgroup w of kPartGroups takes a fixed range of rows and
+//             counts them per bucket (top b1 hash bits); a prefix sum over
+//             the (bucket, workgroup) counts places every segment;
+//   scatter 1 the same ranges: rows -> records in their segment, at the
+//             workgroup's own LDS cursor (no global atomics). A small LDS
+//             table aggregates the keys it already holds (under skew, the hot
+//             ones, met first); only the other rows become records, so a
+//             segment may end short of its count (its fill is recorded). The
 //             pass also counts the records of every partition;
-//   scatter 2 each bucket's records -> records grouped by partition (the
+//   scatter 2 each segment's records -> records grouped by partition (the
 //             next b2 hash bits), at exact offsets;
 //   aggregate each partition, in pieces of at most `piece` records, is
 //             folded into an LDS table sized to hold all of a partition's
@@ -17,12 +20,12 @@
 //             per key. A key that finds no LDS slot updates the global table
 //             directly, so results never depend on the sizing.
 //
-// Within a scatter tile, a record's position in its destination is the
-// tile's claim on that destination (one atomic per destination and tile on a
-// cursor of its own 128-byte line) plus the record's rank among the tile's
-// records for it (an LDS atomic). Record order inside a partition is
-// therefore arbitrary; the aggregates are exact integer sums, minima and
-// maxima, so they do not depend on it.
+// Within a tile of the second scatter, a record's position is the tile's
+// claim on its partition (one atomic per partition and tile, on a cursor of
+// its own 128-byte line) plus the record's rank among the tile's records for
+// it (an LDS atomic). Record order inside a partition is therefore
+// arbitrary; the aggregates are exact integer sums, minima and maxima, so
+// they do not depend on it.
 
 #include "internal.h"
 #include "group_lds.h"
@@ -37,19 +40,61 @@ constexpr uint32_t kNoRecord = 0xFFFFFFFFu;
 constexpr int kPreProbe = 8;
 constexpr int kAggProbe = 64;
 constexpr int kAggRows = 4;
-
-__device__ __forceinline__ uint64_t row_key(const PartParams& p, uint64_t r) {
-  int64_t k[2] = {0, 0};
-  for (int j = 0; j < p.g.kp.nkeys; ++j) {
-    const int64_t i = p.key_idx[j] ? static_cast<int64_t>(p.key_idx[j][r]) : static_cast<int64_t>(r);
-    k[j] = load_elem(p.key_data[j], p.g.kp.type[j], i);
-  }
-  return pack_keys(p.g.kp, k[0], k[1]);
-}
+// Rows per thread and step of the first scatter (16 would hold twice the
+// loads in flight per wave, but at its register count only one workgroup
+// fits a CU and the LDS table probes go unhidden).
+constexpr int kScatterRows = 8;
 
 __device__ __forceinline__ uint64_t row_col(const PartParams& p, int c, uint64_t r) {
   const int64_t i = p.col_idx[c] ? static_cast<int64_t>(p.col_idx[c][r]) : static_cast<int64_t>(r);
   return static_cast<uint64_t>(load_elem(p.col_data[c], p.col_type[c], i));
+}
+
+// Elements r0 + e * step (e < N) of a column, gathered through idx when
+// given. Rows at or past n read row 0 (callers ignore them; n > 0), and the
+// type test is outside the row loop, so the N loads issue back to back.
+template <int N>
+__device__ __forceinline__ void load_rows(const void* data, int32_t type, const uint32_t* idx,
+                                          uint64_t r0, uint64_t step, uint64_t n, int64_t* out) {
+  uint64_t at[N];
+#pragma unroll
+  for (int e = 0; e < N; ++e) {
+    const uint64_t r = r0 + static_cast<uint64_t>(e) * step;
+    at[e] = r < n ? r : 0;
+  }
+  if (idx) {
+#pragma unroll
+    for (int e = 0; e < N; ++e) at[e] = idx[at[e]];
+  }
+  if (type == kI64) {
+    const int64_t* d = static_cast<const int64_t*>(data);
+#pragma unroll
+    for (int e = 0; e < N; ++e) out[e] = d[at[e]];
+  } else if (type == kI32) {
+    const int32_t* d = static_cast<const int32_t*>(data);
+#pragma unroll
+    for (int e = 0; e < N; ++e) out[e] = d[at[e]];
+  } else {
+    const int8_t* d = static_cast<const int8_t*>(data);
+#pragma unroll
+    for (int e = 0; e < N; ++e) out[e] = d[at[e]];
+  }
+}
+
+// Packed keys of rows r0 + e * step (e < N; at least one key column).
+template <int N>
+__device__ __forceinline__ void load_keys(const PartParams& p, uint64_t r0, uint64_t step,
+                                          uint64_t n, uint64_t* pk) {
+  int64_t k0[N], k1[N];
+  load_rows<N>(p.key_data[0], p.g.kp.type[0], p.key_idx[0], r0, step, n, k0);
+  if (p.g.kp.nkeys > 1) {
+    load_rows<N>(p.key_data[1], p.g.kp.type[1], p.key_idx[1], r0, step, n, k1);
+  } else {
+#pragma unroll
+    for (int e = 0; e < N; ++e) k1[e] = 0;
+  }
+#pragma unroll
+  for (int e = 0; e < N; ++e) pk[e] = pack_keys(p.g.kp, k0[e], k1[e]);
 }
 
 __device__ __forceinline__ uint32_t part_of(uint64_t pk, int pb) {
@@ -80,34 +125,56 @@ __device__ __forceinline__ unsigned long long block_scan(unsigned long long v,
   return before + incl - v;
 }
 
-__global__ void __launch_bounds__(256) part_count_kernel(PartParams p) {
+// Tiles [*t0, *t1) of workgroup w (the same in the count and first scatter).
+__device__ __forceinline__ void group_tiles(uint64_t n, uint32_t w, uint64_t* t0, uint64_t* t1) {
+  const uint64_t ntiles = (n + kPartTile - 1) / kPartTile;
+  const uint64_t per = (ntiles + kPartGroups - 1) / kPartGroups;
+  *t0 = w * per;
+  *t1 = *t0 + per < ntiles ? *t0 + per : ntiles;
+}
+
+__global__ void __launch_bounds__(kPartThreads) part_count_kernel(PartParams p) {
   __shared__ uint32_t h[1 << kPartLevelBits];
   const int nb = 1 << p.b1;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) h[i] = 0;
   __syncthreads();
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  for (uint64_t r = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
-       r < static_cast<uint64_t>(p.n); r += stride)
-    atomicAdd(&h[part_of(row_key(p, r), p.b1)], 1u);
-  __syncthreads();
-  for (int i = threadIdx.x; i < nb; i += blockDim.x)
-    if (h[i]) atomicAdd(&p.ctl[kCtlHist1 + i], static_cast<unsigned long long>(h[i]));
-}
-
-// Bucket starts and cursors from the bucket counts (one workgroup of 256).
-__global__ void __launch_bounds__(256) part_scan1_kernel(PartParams p) {
-  const int nb = 1 << p.b1;
-  const int b = threadIdx.x;
-  const unsigned long long v = b < nb ? p.ctl[kCtlHist1 + b] : 0ULL;
-  unsigned long long total;
-  const unsigned long long excl = block_scan(v, &total);
-  if (b < nb) {
-    p.ctl[kCtlStart1 + b] = excl;
-    p.ctl[kCtlCur1 + static_cast<uint64_t>(b) * kPartPad] = excl;
+  const uint64_t n = static_cast<uint64_t>(p.n);
+  uint64_t t0, t1;
+  group_tiles(n, blockIdx.x, &t0, &t1);
+  for (uint64_t tile = t0; tile < t1; ++tile) {
+    const uint64_t r0 = tile * kPartTile + threadIdx.x;
+    uint64_t pk[kPartRows];
+    load_keys<kPartRows>(p, r0, kPartThreads, n, pk);
+#pragma unroll
+    for (int e = 0; e < kPartRows; ++e)
+      if (r0 + static_cast<uint64_t>(e) * kPartThreads < n) atomicAdd(&h[part_of(pk[e], p.b1)], 1u);
   }
-  if (b == 0) p.ctl[kCtlStart1 + nb] = total;
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
+    p.ctl[kCtlSegCount + static_cast<uint64_t>(b) * kPartGroups + blockIdx.x] = h[b];
 }
 
+// Segment starts from the segment counts, bucket-major (one workgroup of
+// 1024; 2^b1 * kPartGroups is a multiple of 1024).
+__global__ void __launch_bounds__(1024) part_scan1_kernel(PartParams p) {
+  const uint64_t segs = static_cast<uint64_t>(kPartGroups) << p.b1;
+  const uint64_t per = segs / blockDim.x;
+  const uint64_t lo = threadIdx.x * per;
+  unsigned long long sum = 0;
+  for (uint64_t i = lo; i < lo + per; ++i) sum += p.ctl[kCtlSegCount + i];
+  unsigned long long total;
+  unsigned long long at = block_scan(sum, &total);
+  for (uint64_t i = lo; i < lo + per; ++i) {
+    p.ctl[kCtlSegStart + i] = at;
+    at += p.ctl[kCtlSegCount + i];
+  }
+  if (threadIdx.x == 0) p.ctl[kCtlSegStart + segs] = total;
+}
+
+// kPair: one value column (two-word records); the values are loaded with
+// the keys, so that writing a record needs no load. kRows: rows per thread
+// and step; a tile is taken in kPartRows / kRows steps.
+template <bool kPair, int kRows>
 __global__ void __launch_bounds__(kPartThreads) part_scatter1_kernel(PartParams p) {
   extern __shared__ uint64_t lds[];
   const GroupDesc& g = p.g;
@@ -117,25 +184,29 @@ __global__ void __launch_bounds__(kPartThreads) part_scatter1_kernel(PartParams 
   uint64_t* pre = lds;
   uint32_t* h2 = reinterpret_cast<uint32_t*>(lds + static_cast<size_t>(p.pre_slots) * g.words);
   uint32_t* cnt = h2 + nparts;
-  unsigned long long* base = reinterpret_cast<unsigned long long*>(cnt + (1 << kPartLevelBits));
+  unsigned long long* cur = reinterpret_cast<unsigned long long*>(cnt + (1 << kPartLevelBits));
   if (p.pre_slots > 0) lds_group_init(pre, p.pre_slots, g);
   for (uint32_t i = threadIdx.x; i < nparts; i += blockDim.x) h2[i] = 0;
+  const uint64_t seg0 = blockIdx.x;  // segment of bucket b: seg0 + b * kPartGroups
+  if (threadIdx.x < nb) {
+    cnt[threadIdx.x] = 0;
+    cur[threadIdx.x] = p.ctl[kCtlSegStart + seg0 + static_cast<uint64_t>(threadIdx.x) * kPartGroups];
+  }
+  __syncthreads();
 
   const uint64_t n = static_cast<uint64_t>(p.n);
-  const uint64_t ntiles = (n + kPartTile - 1) / kPartTile;
-  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    if (threadIdx.x < nb) cnt[threadIdx.x] = 0;
-    __syncthreads();
-    const uint64_t r0 = tile * kPartTile + threadIdx.x;
-    uint64_t pk[kPartRows];
-    uint32_t code[kPartRows];
+  uint64_t t0, t1;
+  group_tiles(n, blockIdx.x, &t0, &t1);
+  for (uint64_t step = t0 * (kPartRows / kRows); step < t1 * (kPartRows / kRows); ++step) {
+    const uint64_t r0 = step * (kPartThreads * kRows) + threadIdx.x;
+    uint64_t pk[kRows];
+    int64_t val[kPair ? kRows : 1];
+    uint32_t code[kRows];
+    load_keys<kRows>(p, r0, kPartThreads, n, pk);
+    if constexpr (kPair)
+      load_rows<kRows>(p.col_data[0], p.col_type[0], p.col_idx[0], r0, kPartThreads, n, val);
 #pragma unroll
-    for (int e = 0; e < kPartRows; ++e) {
-      const uint64_t r = r0 + static_cast<uint64_t>(e) * kPartThreads;
-      pk[e] = r < n ? row_key(p, r) : 0;
-    }
-#pragma unroll
-    for (int e = 0; e < kPartRows; ++e) {
+    for (int e = 0; e < kRows; ++e) {
       const uint64_t r = r0 + static_cast<uint64_t>(e) * kPartThreads;
       code[e] = kNoRecord;
       if (r >= n) continue;
@@ -144,7 +215,7 @@ __global__ void __launch_bounds__(kPartThreads) part_scatter1_kernel(PartParams 
         uint64_t acc[kMaxAcc];
 #pragma unroll
         for (int a = 0; a < kMaxAcc; ++a)
-          if (a < g.ap.nacc) acc[a] = row_col(p, p.src[a], r);
+          if (a < g.ap.nacc) acc[a] = kPair ? static_cast<uint64_t>(val[e]) : row_col(p, p.src[a], r);
         lds_group_update(pre + static_cast<size_t>(s) * g.words, g.ap, acc);
       } else {
         const uint32_t q = part_of(pk[e], pb);
@@ -155,21 +226,31 @@ __global__ void __launch_bounds__(kPartThreads) part_scatter1_kernel(PartParams 
       }
     }
     __syncthreads();
-    if (threadIdx.x < nb && cnt[threadIdx.x])
-      base[threadIdx.x] = atomicAdd(&p.ctl[kCtlCur1 + static_cast<uint64_t>(threadIdx.x) * kPartPad],
-                                    static_cast<unsigned long long>(cnt[threadIdx.x]));
-    __syncthreads();
 #pragma unroll
-    for (int e = 0; e < kPartRows; ++e) {
+    for (int e = 0; e < kRows; ++e) {
       if (code[e] == kNoRecord) continue;
       const uint64_t r = r0 + static_cast<uint64_t>(e) * kPartThreads;
-      const uint64_t pos = base[code[e] >> 16] + (code[e] & 0xFFFFu);
-      uint64_t* w = p.rec_a + pos * p.rw;
-      w[0] = pk[e];
-      for (int c = 0; c < p.ncols; ++c) w[1 + c] = row_col(p, c, r);
+      const uint64_t pos = cur[code[e] >> 16] + (code[e] & 0xFFFFu);
+      if constexpr (kPair) {
+        *reinterpret_cast<ulonglong2*>(p.rec_a + 2 * pos) =
+            make_ulonglong2(pk[e], static_cast<uint64_t>(val[e]));
+      } else {
+        uint64_t* w = p.rec_a + pos * p.rw;
+        w[0] = pk[e];
+        for (int c = 0; c < p.ncols; ++c) w[1 + c] = row_col(p, c, r);
+      }
     }
+    __syncthreads();
+    if (threadIdx.x < nb) {
+      cur[threadIdx.x] += cnt[threadIdx.x];
+      cnt[threadIdx.x] = 0;
+    }
+    __syncthreads();
   }
-  __syncthreads();
+  if (threadIdx.x < nb) {
+    const uint64_t sg = seg0 + static_cast<uint64_t>(threadIdx.x) * kPartGroups;
+    p.ctl[kCtlSegFill + sg] = cur[threadIdx.x] - p.ctl[kCtlSegStart + sg];
+  }
   if (p.pre_slots > 0) lds_group_flush(pre, p.pre_slots, g);
   for (uint32_t i = threadIdx.x; i < nparts; i += blockDim.x)
     if (h2[i]) atomicAdd(&p.ctl[kCtlHist2 + i], static_cast<unsigned long long>(h2[i]));
@@ -203,18 +284,19 @@ __global__ void __launch_bounds__(1024) part_scan2_kernel(PartParams p) {
     p.ctl[kCtlStart2 + nparts] = total_recs;
     p.ctl[kCtlPieces + nparts] = total_pieces;
   }
-  const int nb = 1 << p.b1;
-  const int b = threadIdx.x;
+  // second-scatter tiles per segment
+  const uint64_t segs = static_cast<uint64_t>(kPartGroups) << p.b1;
+  const uint64_t sper = segs / blockDim.x;
+  const uint64_t slo = threadIdx.x * sper;
   unsigned long long tiles = 0;
-  if (b < nb) {
-    const unsigned long long filled =
-        p.ctl[kCtlCur1 + static_cast<uint64_t>(b) * kPartPad] - p.ctl[kCtlStart1 + b];
-    tiles = (filled + kPartTile - 1) / kPartTile;
-  }
+  for (uint64_t i = slo; i < slo + sper; ++i) tiles += (p.ctl[kCtlSegFill + i] + kPartTile - 1) / kPartTile;
   unsigned long long total_tiles;
-  const unsigned long long texcl = block_scan(tiles, &total_tiles);
-  if (b < nb) p.ctl[kCtlTiles + b] = texcl;
-  if (b == 0) p.ctl[kCtlTiles + nb] = total_tiles;
+  unsigned long long tat = block_scan(tiles, &total_tiles);
+  for (uint64_t i = slo; i < slo + sper; ++i) {
+    p.ctl[kCtlTiles + i] = tat;
+    tat += (p.ctl[kCtlSegFill + i] + kPartTile - 1) / kPartTile;
+  }
+  if (threadIdx.x == 0) p.ctl[kCtlTiles + segs] = total_tiles;
 }
 
 // kPair: records of two words (one value column), held in registers between
@@ -222,47 +304,40 @@ __global__ void __launch_bounds__(1024) part_scan2_kernel(PartParams p) {
 // (from L2) when written.
 template <bool kPair>
 __global__ void __launch_bounds__(kPartThreads) part_scatter2_kernel(PartParams p) {
-  __shared__ unsigned long long s_tiles[(1 << kPartLevelBits) + 1];
-  __shared__ unsigned long long s_start[1 << kPartLevelBits];
-  __shared__ unsigned long long s_end[1 << kPartLevelBits];
   __shared__ uint32_t cnt[1 << kPartLevelBits];
   __shared__ unsigned long long base[1 << kPartLevelBits];
-  const int nb = 1 << p.b1;
   const int n2 = 1 << p.b2;
   const int pb = p.b1 + p.b2;
-  for (int b = threadIdx.x; b <= nb; b += blockDim.x) s_tiles[b] = p.ctl[kCtlTiles + b];
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-    s_start[b] = p.ctl[kCtlStart1 + b];
-    s_end[b] = p.ctl[kCtlCur1 + static_cast<uint64_t>(b) * kPartPad];
-  }
-  __syncthreads();
-  const unsigned long long ntiles = s_tiles[nb];
+  const uint64_t segs = static_cast<uint64_t>(kPartGroups) << p.b1;
+  const unsigned long long* tiles = p.ctl + kCtlTiles;
+  const unsigned long long ntiles = tiles[segs];
   for (unsigned long long t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    // bucket b: the last with s_tiles[b] <= t
-    int lo = 0, hi = nb;
+    // segment sg: the last with tiles[sg] <= t
+    uint64_t lo = 0, hi = segs;
     while (hi - lo > 1) {
-      const int mid = (lo + hi) / 2;
-      if (s_tiles[mid] <= t) lo = mid;
+      const uint64_t mid = (lo + hi) / 2;
+      if (tiles[mid] <= t) lo = mid;
       else hi = mid;
     }
-    const int b = lo;
-    const uint64_t first = s_start[b] + (t - s_tiles[b]) * kPartTile;
-    const uint64_t end = s_end[b];
+    const uint64_t sg = lo;
+    const uint64_t b = sg / kPartGroups;
+    const uint64_t sstart = p.ctl[kCtlSegStart + sg];
+    const uint64_t first = sstart + (t - tiles[sg]) * kPartTile;
+    const uint64_t end = sstart + p.ctl[kCtlSegFill + sg];
     if (threadIdx.x < n2) cnt[threadIdx.x] = 0;
     __syncthreads();
     uint64_t pk[kPartRows], val[kPair ? kPartRows : 1];
     uint32_t code[kPartRows];
 #pragma unroll
     for (int e = 0; e < kPartRows; ++e) {
-      const uint64_t i = first + threadIdx.x + static_cast<uint64_t>(e) * kPartThreads;
-      if (i < end) {
-        if constexpr (kPair) {
-          const ulonglong2 r = *reinterpret_cast<const ulonglong2*>(p.rec_a + 2 * i);
-          pk[e] = r.x;
-          val[e] = r.y;
-        } else {
-          pk[e] = p.rec_a[i * p.rw];
-        }
+      uint64_t i = first + threadIdx.x + static_cast<uint64_t>(e) * kPartThreads;
+      i = i < end ? i : first;  // past the end: a valid record, ignored below
+      if constexpr (kPair) {
+        const ulonglong2 r = *reinterpret_cast<const ulonglong2*>(p.rec_a + 2 * i);
+        pk[e] = r.x;
+        val[e] = r.y;
+      } else {
+        pk[e] = p.rec_a[i * p.rw];
       }
     }
 #pragma unroll
@@ -275,7 +350,7 @@ __global__ void __launch_bounds__(kPartThreads) part_scatter2_kernel(PartParams 
     }
     __syncthreads();
     if (threadIdx.x < n2 && cnt[threadIdx.x]) {
-      const uint64_t q = (static_cast<uint64_t>(b) << p.b2) + threadIdx.x;
+      const uint64_t q = (b << p.b2) + threadIdx.x;
       base[threadIdx.x] = atomicAdd(&p.ctl[kCtlCur2 + q * kPartPad],
                                     static_cast<unsigned long long>(cnt[threadIdx.x]));
     }
@@ -298,6 +373,8 @@ __global__ void __launch_bounds__(kPartThreads) part_scatter2_kernel(PartParams 
   }
 }
 
+// kPair: two-word records, read with one 16-byte load each.
+template <bool kPair>
 __global__ void __launch_bounds__(kPartAggThreads) part_agg_kernel(PartParams p) {
   extern __shared__ uint64_t table[];
   const GroupDesc& g = p.g;
@@ -325,13 +402,20 @@ __global__ void __launch_bounds__(kPartAggThreads) part_agg_kernel(PartParams p)
       uint64_t pk[kAggRows], acc[kAggRows][kMaxAcc];
 #pragma unroll
       for (int e = 0; e < kAggRows; ++e) {
-        const uint64_t i = i0 + static_cast<uint64_t>(e) * blockDim.x;
-        if (i >= end) continue;
-        const uint64_t* rec = p.rec_b + i * p.rw;
-        pk[e] = rec[0];
+        uint64_t i = i0 + static_cast<uint64_t>(e) * blockDim.x;
+        i = i < end ? i : i0;  // past the end: a valid record, ignored below
+        if constexpr (kPair) {
+          const ulonglong2 r = *reinterpret_cast<const ulonglong2*>(p.rec_b + 2 * i);
+          pk[e] = r.x;
 #pragma unroll
-        for (int a = 0; a < kMaxAcc; ++a)
-          if (a < g.ap.nacc) acc[e][a] = rec[1 + p.src[a]];
+          for (int a = 0; a < kMaxAcc; ++a) acc[e][a] = r.y;
+        } else {
+          const uint64_t* rec = p.rec_b + i * p.rw;
+          pk[e] = rec[0];
+#pragma unroll
+          for (int a = 0; a < kMaxAcc; ++a)
+            if (a < g.ap.nacc) acc[e][a] = rec[1 + p.src[a]];
+        }
       }
 #pragma unroll
       for (int e = 0; e < kAggRows; ++e) {
@@ -352,18 +436,25 @@ __global__ void __launch_bounds__(kPartAggThreads) part_agg_kernel(PartParams p)
   }
 }
 
-template <typename K>
-hipError_t allow_dynamic_lds(K k) {
-  static int done = 0;
-  if (done) return hipSuccess;
+// Lets a kernel take up to all of a workgroup's LDS as dynamic LDS.
+hipError_t allow_dynamic_lds(const void* k) {
   hipFuncAttributes attr;
-  hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(k));
+  hipError_t e = hipFuncGetAttributes(&attr, k);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                          device_info().lds_per_block - static_cast<int>(attr.sharedSizeBytes));
-  if (e == hipSuccess) done = 1;
-  return e;
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             device_info().lds_per_block - static_cast<int>(attr.sharedSizeBytes));
+}
+
+hipError_t allow_dynamic_lds_all() {
+  const void* kernels[] = {reinterpret_cast<const void*>(part_scatter1_kernel<true, kScatterRows>),
+                           reinterpret_cast<const void*>(part_scatter1_kernel<false, kScatterRows>),
+                           reinterpret_cast<const void*>(part_agg_kernel<true>),
+                           reinterpret_cast<const void*>(part_agg_kernel<false>)};
+  for (const void* k : kernels) {
+    hipError_t e = allow_dynamic_lds(k);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -375,16 +466,18 @@ size_t part_scatter1_lds(const PartParams& p) {
 
 hipError_t launch_group_partitioned(const PartParams& p, hipStream_t s) {
   const int cus = device_info().cu_count;
-  hipError_t e = allow_dynamic_lds(part_scatter1_kernel);
-  if (e != hipSuccess) return e;
-  e = allow_dynamic_lds(part_agg_kernel);
-  if (e != hipSuccess) return e;
+  static const hipError_t attrs = allow_dynamic_lds_all();  // once per process
+  if (attrs != hipSuccess) return attrs;
   {
     ProfileScope ps(kKGroupPartition, s);
-    hipLaunchKernelGGL(part_count_kernel, dim3(cus * 8), dim3(256), 0, s, p);
-    hipLaunchKernelGGL(part_scan1_kernel, dim3(1), dim3(256), 0, s, p);
-    hipLaunchKernelGGL(part_scatter1_kernel, dim3(cus * 2), dim3(kPartThreads),
-                       part_scatter1_lds(p), s, p);
+    hipLaunchKernelGGL(part_count_kernel, dim3(kPartGroups), dim3(kPartThreads), 0, s, p);
+    hipLaunchKernelGGL(part_scan1_kernel, dim3(1), dim3(1024), 0, s, p);
+    if (p.rw == 2)
+      hipLaunchKernelGGL((part_scatter1_kernel<true, kScatterRows>), dim3(kPartGroups), dim3(kPartThreads),
+                         part_scatter1_lds(p), s, p);
+    else
+      hipLaunchKernelGGL((part_scatter1_kernel<false, kScatterRows>), dim3(kPartGroups), dim3(kPartThreads),
+                         part_scatter1_lds(p), s, p);
     hipLaunchKernelGGL(part_scan2_kernel, dim3(1), dim3(1024), 0, s, p);
     if (p.rw == 2)
       hipLaunchKernelGGL(part_scatter2_kernel<true>, dim3(cus * 2), dim3(kPartThreads), 0, s, p);
@@ -392,8 +485,11 @@ hipError_t launch_group_partitioned(const PartParams& p, hipStream_t s) {
       hipLaunchKernelGGL(part_scatter2_kernel<false>, dim3(cus * 2), dim3(kPartThreads), 0, s, p);
   }
   ProfileScope ps(kKGroupAgg, s);
-  hipLaunchKernelGGL(part_agg_kernel, dim3(cus), dim3(kPartAggThreads),
-                     static_cast<size_t>(p.agg_slots) * p.g.words * 8, s, p);
+  const size_t agg_lds = static_cast<size_t>(p.agg_slots) * p.g.words * 8;
+  if (p.rw == 2)
+    hipLaunchKernelGGL(part_agg_kernel<true>, dim3(cus), dim3(kPartAggThreads), agg_lds, s, p);
+  else
+    hipLaunchKernelGGL(part_agg_kernel<false>, dim3(cus), dim3(kPartAggThreads), agg_lds, s, p);
   return hipGetLastError();
 }
 

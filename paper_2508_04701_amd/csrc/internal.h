@@ -246,16 +246,22 @@ constexpr int kPartRows = 16;        // rows (records) per thread and scatter ti
 constexpr int kPartTile = kPartThreads * kPartRows;
 constexpr int kPartAggThreads = 1024;
 constexpr int kPartPad = 16;         // words between claim cursors (one 128-byte line)
-// Control words: histograms, prefix sums and claim cursors.
-constexpr uint64_t kCtlHist1 = 0;                                  // 2^b1 bucket sizes
-constexpr uint64_t kCtlHist2 = 256;                                // 2^pb partition sizes
-constexpr uint64_t kCtlZero = kCtlHist2 + (1u << kPartMaxBits);    // words zeroed per call
-constexpr uint64_t kCtlStart1 = kCtlZero;                          // 2^b1 + 1 bucket starts
-constexpr uint64_t kCtlTiles = kCtlStart1 + 256;                   // 2^b1 + 1 tile prefix
-constexpr uint64_t kCtlStart2 = kCtlTiles + 256;                   // 2^pb + 1 partition starts
-constexpr uint64_t kCtlPieces = kCtlStart2 + (1u << kPartMaxBits) + 256;  // 2^pb + 1 piece prefix
-constexpr uint64_t kCtlCur1 = kCtlPieces + (1u << kPartMaxBits) + 256;    // 2^b1 padded cursors
-constexpr uint64_t kCtlCur2 = kCtlCur1 + (1u << kPartLevelBits) * kPartPad;  // 2^pb padded cursors
+// The count and first scatter passes give workgroup w (of kPartGroups) the
+// same fixed range of rows; (bucket b, workgroup w) is segment b * kPartGroups
+// + w of the first record buffer, placed by a prefix sum over the counts, so
+// the first scatter needs no global atomics.
+constexpr int kPartGroups = 512;
+constexpr uint64_t kPartSegs = static_cast<uint64_t>(kPartGroups) << kPartLevelBits;
+// Control words: counts, prefix sums and claim cursors.
+constexpr uint64_t kCtlHist2 = 0;                                   // 2^pb partition sizes
+constexpr uint64_t kCtlZero = 1u << kPartMaxBits;                   // words zeroed per call
+constexpr uint64_t kCtlSegCount = kCtlZero;                         // rows per segment
+constexpr uint64_t kCtlSegStart = kCtlSegCount + kPartSegs;         // segment starts (+ total)
+constexpr uint64_t kCtlSegFill = kCtlSegStart + kPartSegs + 256;    // records per segment
+constexpr uint64_t kCtlTiles = kCtlSegFill + kPartSegs;             // second-scatter tile prefix
+constexpr uint64_t kCtlStart2 = kCtlTiles + kPartSegs + 256;        // partition starts (+ total)
+constexpr uint64_t kCtlPieces = kCtlStart2 + (1u << kPartMaxBits) + 256;  // piece prefix (+ total)
+constexpr uint64_t kCtlCur2 = kCtlPieces + (1u << kPartMaxBits) + 256;    // padded cursors
 constexpr uint64_t kCtlWords = kCtlCur2 + (1u << kPartMaxBits) * static_cast<uint64_t>(kPartPad);
 
 struct PartParams {

@@ -269,7 +269,7 @@ def partitioned_run(fn):
     ([np.int32], 5000, 64, 0),
     ([np.int64], 200_000, 16384, 0),
     ([np.int64], 200_000, 4, -1),        # partitions far beyond an LDS table
-    ([np.int8, np.int32], 5000, 256, 0),
+    ([np.int8, np.int32], 5000, 256, 256),  # with the first scatter's LDS table
     ([np.int32, np.int32], 200_000, 1024, -1),
     ([np.int32, np.int8], 3, 16, 0),
 ], ids=["i32-5k-f64", "i64-200k-f16384", "i64-200k-f4-nolds", "i8+i32-5k-f256",
