@@ -65,6 +65,127 @@ __device__ __forceinline__ void build_rows(const MapBuildParams& p, uint64_t i, 
   }
 }
 
+// Elements at[e] of a column; the type test is outside the element loop, so
+// the N loads issue back to back.
+template <int N>
+__device__ __forceinline__ void gather_elems(const void* data, int32_t type, const uint64_t* at,
+                                             int64_t* out) {
+  if (type == kI64) {
+#pragma unroll
+    for (int e = 0; e < N; ++e) out[e] = static_cast<const int64_t*>(data)[at[e]];
+  } else if (type == kI32) {
+#pragma unroll
+    for (int e = 0; e < N; ++e) out[e] = static_cast<const int32_t*>(data)[at[e]];
+  } else {
+#pragma unroll
+    for (int e = 0; e < N; ++e) out[e] = static_cast<const int8_t*>(data)[at[e]];
+  }
+}
+
+// Keys per lane and step of the batched map build.
+constexpr int kBuildKeys = 4;
+
+// Map (key -> value) inserts of elements i, i + stride, ... below `end`,
+// kBuildKeys per lane at a time: their loads, and each round's CAS on the
+// slot arrays, are independent and in flight together. Same slots, same
+// duplicate detection and out-of-band handling as map_insert.
+template <typename K>
+__device__ __forceinline__ void build_map_batched(const MapBuildParams& p, uint64_t i0, uint64_t end,
+                                                  uint64_t stride) {
+  constexpr int J = kBuildKeys;
+  const uint64_t mask = p.map.cap - 1;
+  for (; i0 < end; i0 += J * stride) {
+    uint64_t at[J];
+    bool pend[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const uint64_t i = i0 + static_cast<uint64_t>(j) * stride;
+      pend[j] = i < end;
+      at[j] = pend[j] ? i : i0;
+    }
+    uint32_t val[J];
+    if (p.idx) {
+#pragma unroll
+      for (int j = 0; j < J; ++j) at[j] = p.idx[at[j]];
+    }
+    int64_t kv[J];
+    gather_elems<J>(p.keys, p.type, at, kv);
+    if (p.val_col) {
+      int64_t pv[J];
+      gather_elems<J>(p.val_col, p.val_type, at, pv);
+#pragma unroll
+      for (int j = 0; j < J; ++j) val[j] = static_cast<uint32_t>(pv[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < J; ++j) val[j] = static_cast<uint32_t>(at[j]);
+    }
+    K key[J];
+    uint64_t h[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      key[j] = static_cast<K>(kv[j]);
+      h[j] = 0;
+      if (!pend[j]) continue;
+      if constexpr (sizeof(K) == 4) {
+        if (key[j] == kEmpty32) {
+          map_insert(Map32{nullptr, mask, p.map.oob_count, p.map.oob_vals}, key[j], val[j], p.map.dup);
+          pend[j] = false;
+        } else {
+          h[j] = home32(key[j], mask);
+        }
+      } else {
+        if (static_cast<uint64_t>(key[j]) == kEmpty64) {
+          map_insert(Map64{nullptr, mask, p.map.oob_count, p.map.oob_vals}, key[j], val[j], p.map.dup);
+          pend[j] = false;
+        } else {
+          h[j] = home64(key[j], mask);
+        }
+      }
+    }
+    while (true) {
+      bool any = false;
+#pragma unroll
+      for (int j = 0; j < J; ++j) any |= pend[j];
+      if (!any) break;
+      unsigned long long prev[J];
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        prev[j] = 0;
+        if (!pend[j]) continue;
+        if constexpr (sizeof(K) == 4) {
+          prev[j] = atomicCAS(static_cast<unsigned long long*>(p.map.slots) + h[j],
+                              static_cast<unsigned long long>(kEmptySlot32),
+                              static_cast<unsigned long long>(pack32(key[j], val[j])));
+        } else {
+          prev[j] = atomicCAS(reinterpret_cast<unsigned long long*>(
+                                  &static_cast<ulonglong2*>(p.map.slots)[h[j]].x),
+                              static_cast<unsigned long long>(kEmpty64),
+                              static_cast<unsigned long long>(key[j]));
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        if (!pend[j]) continue;
+        if constexpr (sizeof(K) == 4) {
+          if (prev[j] == kEmptySlot32) {
+            pend[j] = false;
+            continue;
+          }
+          if (static_cast<int32_t>(static_cast<uint32_t>(prev[j])) == key[j]) *p.map.dup = 1;
+        } else {
+          if (prev[j] == kEmpty64) {
+            static_cast<ulonglong2*>(p.map.slots)[h[j]].y = val[j];
+            pend[j] = false;
+            continue;
+          }
+          if (static_cast<int64_t>(prev[j]) == key[j]) *p.map.dup = 1;
+        }
+        h[j] = (h[j] + 1) & mask;
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
@@ -150,7 +271,10 @@ __global__ void __launch_bounds__(256) map_build_kernel(MapBuildParams p, int pa
   } else if (pass == 1) {
     direct_rows(p, first + threadIdx.x, static_cast<uint64_t>(p.n), stride);
   } else if (slots_needed(p.map)) {
-    build_rows<K>(p, first + threadIdx.x, static_cast<uint64_t>(p.n), stride);
+    if (p.map.compact || p.map.key_only)
+      build_rows<K>(p, first + threadIdx.x, static_cast<uint64_t>(p.n), stride);
+    else
+      build_map_batched<K>(p, first + threadIdx.x, static_cast<uint64_t>(p.n), stride);
   }
 }
 
@@ -201,8 +325,11 @@ __global__ void __launch_bounds__(256) batch_fill_kernel(BatchParams b) {
 // Matched pairs are staged per wave in LDS and written in runs: one cursor
 // atomic per run of at least kProbeFlush pairs instead of one per wave and
 // round (a single global counter shared by every wave serialises otherwise).
-constexpr int kProbeStage = 256;
-constexpr int kProbeFlush = kProbeStage - kWave;
+// Each lane walks kProbeKeys probe keys at once: their key loads, and every
+// round's slot loads, are independent and in flight together.
+constexpr int kProbeStage = 1024;
+constexpr int kProbeKeys = 4;
+constexpr int kProbeFlush = kProbeStage - kProbeKeys * kWave;
 
 __device__ __forceinline__ void flush_pairs(const MapProbeParams& p, const uint32_t* sb,
                                             const uint32_t* sp, uint32_t staged, int lane) {
@@ -220,50 +347,101 @@ __device__ __forceinline__ void flush_pairs(const MapProbeParams& p, const uint3
   __builtin_amdgcn_wave_barrier();
 }
 
+// Cursor states of a probe key.
+constexpr uint32_t kWalkDone = 0, kWalkSlots = 1, kWalkOob = 2;
+
 template <typename K>
 __global__ void __launch_bounds__(256) map_probe_kernel(MapProbeParams p) {
   __shared__ uint32_t s_build[256 / kWave][kProbeStage];
   __shared__ uint32_t s_probe[256 / kWave][kProbeStage];
   using Slot = typename std::conditional<sizeof(K) == 4, uint64_t, ulonglong2>::type;
   const Slot* slots = static_cast<const Slot*>(p.map.slots);
+  const K* keys = static_cast<const K*>(p.keys);
   const uint64_t mask = p.map.cap - 1;
+  // Without duplicate build keys a probe key has at most one match, and its
+  // walk ends there.
+  const bool unique = *p.map.dup == 0;
+  const unsigned long long oob_n = *p.map.oob_count;
   const int lane = lane_id();
   uint32_t* sb = s_build[threadIdx.x / kWave];
   uint32_t* sp = s_probe[threadIdx.x / kWave];
   uint32_t staged = 0;  // wave-uniform
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  const uint64_t n = static_cast<uint64_t>(p.n);
+  const uint64_t step = static_cast<uint64_t>(gridDim.x) * blockDim.x * kProbeKeys;
   // The loop bound is uniform across the workgroup, so whole waves stay
   // together through the ballots below.
-  for (uint64_t base = blockIdx.x * static_cast<uint64_t>(blockDim.x);
-       base < static_cast<uint64_t>(p.n); base += stride) {
-    const uint64_t i = base + threadIdx.x;
-    bool active = i < static_cast<uint64_t>(p.n);
-    K key = 0;
-    uint32_t prow = 0;
-    MapCursor cur{0, false, false, false};
-    if (active) {
-      int64_t r = p.idx ? static_cast<int64_t>(p.idx[i]) : static_cast<int64_t>(i);
-      key = static_cast<K>(load_elem(p.keys, p.type, r));
-      prow = static_cast<uint32_t>(r);
-      if constexpr (sizeof(K) == 4) {
-        Map32 m{nullptr, mask, nullptr, nullptr};
-        cur = map_start32(m, key);
-      } else {
-        Map64 m{nullptr, mask, nullptr, nullptr};
-        cur = map_start64(m, key);
-      }
+  for (uint64_t base = blockIdx.x * static_cast<uint64_t>(blockDim.x) * kProbeKeys; base < n;
+       base += step) {
+    uint64_t row[kProbeKeys], pos[kProbeKeys];
+    uint32_t state[kProbeKeys];
+    K key[kProbeKeys];
+#pragma unroll
+    for (int j = 0; j < kProbeKeys; ++j) {
+      const uint64_t i = base + static_cast<uint64_t>(j) * blockDim.x + threadIdx.x;
+      row[j] = i < n ? i : 0;
+      state[j] = i < n ? kWalkSlots : kWalkDone;
     }
-    while (ballot(cur.live) != 0) {
-      uint32_t bval = 0;
-      bool found = map_next(slots, mask, p.map.oob_count, p.map.oob_vals, key, cur, bval);
-      uint64_t m = ballot(found);
-      if (m == 0) continue;
-      if (found) {
-        const uint32_t at = staged + rank_below(m);
-        sb[at] = bval;
-        sp[at] = prow;
+    if (p.idx) {
+#pragma unroll
+      for (int j = 0; j < kProbeKeys; ++j) row[j] = p.idx[row[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < kProbeKeys; ++j) key[j] = keys[row[j]];
+#pragma unroll
+    for (int j = 0; j < kProbeKeys; ++j) {
+      bool oob;
+      if constexpr (sizeof(K) == 4) {
+        oob = key[j] == kEmpty32;
+        pos[j] = oob ? 0 : home32(key[j], mask);
+      } else {
+        oob = static_cast<uint64_t>(key[j]) == kEmpty64;
+        pos[j] = oob ? 0 : home64(key[j], mask);
       }
-      staged += popc64(m);
+      if (oob && state[j] != kWalkDone) state[j] = kWalkOob;
+    }
+    while (true) {
+      uint32_t any = kWalkDone;
+#pragma unroll
+      for (int j = 0; j < kProbeKeys; ++j) any |= state[j];
+      if (ballot(any != kWalkDone) == 0) break;
+      Slot sl[kProbeKeys];
+#pragma unroll
+      for (int j = 0; j < kProbeKeys; ++j)
+        if (state[j] == kWalkSlots) sl[j] = slots[pos[j]];
+#pragma unroll
+      for (int j = 0; j < kProbeKeys; ++j) {
+        bool found = false;
+        uint32_t val = 0;
+        if (state[j] == kWalkSlots) {
+          K k;
+          if constexpr (sizeof(K) == 4) {
+            k = static_cast<int32_t>(static_cast<uint32_t>(sl[j]));
+            val = static_cast<uint32_t>(sl[j] >> 32);
+          } else {
+            k = static_cast<int64_t>(sl[j].x);
+            val = static_cast<uint32_t>(sl[j].y);
+          }
+          const bool empty = sizeof(K) == 4 ? (k == static_cast<K>(kEmpty32))
+                                            : (static_cast<uint64_t>(k) == kEmpty64);
+          found = !empty && k == key[j];
+          if (empty || (found && unique)) state[j] = kWalkDone;
+          pos[j] = (pos[j] + 1) & mask;
+        } else if (state[j] == kWalkOob) {
+          if (pos[j] < oob_n) {
+            val = p.map.oob_vals[pos[j]++];
+            found = true;
+          } else {
+            state[j] = kWalkDone;
+          }
+        }
+        const uint64_t m = ballot(found);
+        if (found) {
+          const uint32_t at = staged + rank_below(m);
+          sb[at] = val;
+          sp[at] = static_cast<uint32_t>(row[j]);
+        }
+        staged += popc64(m);
+      }
       if (staged > static_cast<uint32_t>(kProbeFlush)) {
         flush_pairs(p, sb, sp, staged, lane);
         staged = 0;

@@ -109,6 +109,13 @@ def join_case(case, dtype, r):
     if case == "unique":
         b = r.permutation(20_000).astype(dtype) * 7 - 3
         p = r.integers(-10, 160_000, size=90_000).astype(dtype)
+    elif case == "unique_sentinel":
+        # unique build keys, one of them the sentinel pattern: the probe ends
+        # every walk at its first match, out-of-band keys included
+        b = r.permutation(20_000).astype(dtype) * 7 - 3
+        b[123] = info.min
+        p = r.integers(-10, 160_000, size=90_001).astype(dtype)
+        p[r.random(p.size) < 0.01] = info.min
     elif case == "dups":
         b = r.integers(0, 3000, size=12_000).astype(dtype)
         p = r.integers(0, 4000, size=30_000).astype(dtype)
@@ -125,10 +132,12 @@ def join_case(case, dtype, r):
 
 
 @pytest.mark.parametrize("dtype", [np.int32, np.int64], ids=["i32", "i64"])
-@pytest.mark.parametrize("case", ["unique", "dups", "sentinel", "empty_build", "empty_probe"])
+@pytest.mark.parametrize("case", ["unique", "unique_sentinel", "dups", "sentinel", "empty_build",
+                                  "empty_probe"])
 def test_hash_join(case, dtype):
     announce("join", case, np.dtype(dtype).name)
-    seed = {"unique": 1, "dups": 2, "sentinel": 3, "empty_build": 4, "empty_probe": 5}[case]
+    seed = {"unique": 1, "unique_sentinel": 6, "dups": 2, "sentinel": 3, "empty_build": 4,
+            "empty_probe": 5}[case]
     b, p = join_case(case, dtype, rng(seed))
     got = rel.hash_join(dev(b), dev(p))
     assert_pairs(got, oracle.hash_join(b, p), case)
