@@ -46,6 +46,64 @@ __device__ __forceinline__ uint32_t eval_chunk(const FilterParams& p, int64_t r0
   return bits;
 }
 
+// A whole tile of plain columns: per term, the loads of the thread's four
+// chunks are issued together (the type and alignment tests are uniform), and
+// only then compared.
+__device__ __forceinline__ void eval_whole(const FilterParams& p, int64_t r0,
+                                           uint32_t bits[kFilterChunks]) {
+  constexpr int64_t kChunk = kFilterThreads * 4;
+#pragma unroll
+  for (int j = 0; j < kFilterChunks; ++j) bits[j] = 0xFu;
+  for (int t = 0; t < p.nterms; ++t) {
+    const FilterTerm& term = p.term[t];
+    int64_t v[kFilterChunks][4];
+    if (term.vec && term.type == kI32) {
+      const int32_t* d = static_cast<const int32_t*>(term.data) + r0;
+      int4 x[kFilterChunks];
+#pragma unroll
+      for (int j = 0; j < kFilterChunks; ++j) x[j] = *reinterpret_cast<const int4*>(d + j * kChunk);
+#pragma unroll
+      for (int j = 0; j < kFilterChunks; ++j) {
+        v[j][0] = x[j].x; v[j][1] = x[j].y; v[j][2] = x[j].z; v[j][3] = x[j].w;
+      }
+    } else if (term.vec && term.type == kI64) {
+      const int64_t* d = static_cast<const int64_t*>(term.data) + r0;
+      longlong2 a[kFilterChunks], b[kFilterChunks];
+#pragma unroll
+      for (int j = 0; j < kFilterChunks; ++j) {
+        a[j] = reinterpret_cast<const longlong2*>(d + j * kChunk)[0];
+        b[j] = reinterpret_cast<const longlong2*>(d + j * kChunk)[1];
+      }
+#pragma unroll
+      for (int j = 0; j < kFilterChunks; ++j) {
+        v[j][0] = a[j].x; v[j][1] = a[j].y; v[j][2] = b[j].x; v[j][3] = b[j].y;
+      }
+    } else if (term.vec) {
+      const int8_t* d = static_cast<const int8_t*>(term.data) + r0;
+      int32_t w[kFilterChunks];
+#pragma unroll
+      for (int j = 0; j < kFilterChunks; ++j) w[j] = *reinterpret_cast<const int32_t*>(d + j * kChunk);
+#pragma unroll
+      for (int j = 0; j < kFilterChunks; ++j) {
+        v[j][0] = static_cast<int8_t>(w[j]); v[j][1] = static_cast<int8_t>(w[j] >> 8);
+        v[j][2] = static_cast<int8_t>(w[j] >> 16); v[j][3] = static_cast<int8_t>(w[j] >> 24);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kFilterChunks; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[j][e] = load_elem(term.data, term.type, r0 + j * kChunk + e);
+    }
+#pragma unroll
+    for (int j = 0; j < kFilterChunks; ++j) {
+      uint32_t m = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) m |= term_holds(term.op, v[j][e], term.lo, term.hi) ? (1u << e) : 0u;
+      bits[j] &= m;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kFilterThreads) filter_kernel(FilterParams p) {
   __shared__ uint32_t s_rows[kFilterTile];
   __shared__ uint32_t s_wave_total[kFilterChunks][kFilterThreads / kWave];
@@ -62,9 +120,13 @@ __global__ void __launch_bounds__(kFilterThreads) filter_kernel(FilterParams p) 
   const int64_t base = tile * kFilterTile;
 
   uint32_t bits[kFilterChunks];
+  if (!p.idx && base + kFilterTile <= p.n) {
+    eval_whole(p, base + tid * 4, bits);
+  } else {
 #pragma unroll
-  for (int j = 0; j < kFilterChunks; ++j)
-    bits[j] = eval_chunk(p, base + j * (kFilterThreads * 4) + tid * 4);
+    for (int j = 0; j < kFilterChunks; ++j)
+      bits[j] = eval_chunk(p, base + j * (kFilterThreads * 4) + tid * 4);
+  }
 
   // Per chunk: this lane's rank among the wave's passing rows, and the
   // wave's count.
