@@ -260,6 +260,8 @@ constexpr int kGroupReplicas = 64;
 
 // Default LDS bytes for dim tables in the fused pipeline.
 constexpr size_t kDimLdsDefault = 32768;
+// Largest LDS group table of the fused pipeline.
+constexpr size_t kGroupLdsMax = 131072;
 
 GroupLayout group_layout(const GroupPlan& gp, int64_t max_groups, float lf, size_t base,
                          int replicas = 1) {
@@ -468,7 +470,10 @@ rel_status pipeline_layout(const rel_pipeline_desc* d, PipeLayout& L, bool batch
   }
   rel_status st = group_plan(d->n_keys, L.key_types, d->n_aggs, d->aggs, L.gp);
   if (st) return st;
-  L.lds_slots = default_lds_slots(d->tuning, d->max_groups, L.gp.words, 16384);
+  // Up to kGroupLdsMax: rows of groups beyond the LDS table pay device-scope
+  // atomics in the global table, which costs more than the occupancy a large
+  // table takes (measured on join + group-by instances of 1k-80k groups).
+  L.lds_slots = default_lds_slots(d->tuning, d->max_groups, L.gp.words, kGroupLdsMax);
   L.group = group_layout(L.gp, d->max_groups, lf, off,
                          group_replicas(d->tuning, d->max_groups, L.lds_slots, L.gp.words, lf));
   L.end = L.group.end;
@@ -747,8 +752,18 @@ void push_items(std::vector<BatchItem>& v, uint32_t inst, uint32_t aux, uint64_t
 
 // Writes the uploaded block of batch B over workspace w into `host` (B.blob
 // bytes), returns instance 0's plan in `shape` and the kernel arguments.
+// Instances whose LDS group table fits kSmallGroupLds share the fused pass
+// at full occupancy; those with larger tables (one or two workgroups per CU)
+// take a second persistent launch, so that they do not lower the occupancy
+// of the others.
+constexpr uint32_t kSmallGroupLds = 16384;
+
+// Fills the uploaded block at `host`. `bp` covers every instance and the
+// fused pass of the small-table class; `big` the fused pass of the others
+// (big.ntile = 0 when there are none).
 void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const BatchLayout& B,
-                unsigned char* w, unsigned char* host, PipelineParams& shape, BatchParams& bp) {
+                unsigned char* w, unsigned char* host, PipelineParams& shape, BatchParams& bp,
+                BatchParams& big) {
   std::memset(host, 0, B.blob);
   PipelineParams* plans = reinterpret_cast<PipelineParams*>(host + B.off_plans);
   MapBuildParams* builds = reinterpret_cast<MapBuildParams*>(host + B.off_builds);
@@ -760,13 +775,15 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
   tile_items.reserve(B.ntile);
   merge_items.reserve(B.nmerge);
   fin_items.reserve(B.nfin);
-  uint32_t group_lds = 0;
+  uint32_t group_lds[2] = {0, 0};
+  std::vector<int> cls(n);
   for (int i = 0; i < n; ++i) {
     const PipeLayout& L = B.L[i];
     PipelineParams& p = plans[i];
     plan_params(&d[i], L, w, o[i].d_groups, true, p, &builds[2 * i]);
     const uint32_t gl = static_cast<uint32_t>((static_cast<size_t>(p.lds_slots) * L.gp.words * 8 + 15) / 16 * 16);
-    if (gl > group_lds) group_lds = gl;
+    cls[i] = gl > kSmallGroupLds ? 1 : 0;
+    if (gl > group_lds[cls[i]]) group_lds[cls[i]] = gl;
     fins[i] = finalize_params(p.g, L.gp, d[i].aggs, d[i].n_aggs, o[i].keys, L.key_types, o[i].aggs,
                               o[i].cap);
     for (int k = 0; k < d[i].n_dims; ++k) {
@@ -790,30 +807,41 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
     push_fill(fill, g.slots, g.replicas * (g.cap + 1) * g.words, kFillGroup, 0, i);
     push_fill(fill, reinterpret_cast<uint64_t*>(g.overflow), 1, kFillConst, 0, i);
     push_fill(fill, reinterpret_cast<uint64_t*>(g.d_groups), 1, kFillConst, 0, i);
-    if (!shared_scan(d, n)) push_items(tile_items, i, 0, static_cast<uint64_t>(p.ntiles), B.chunk_tiles);
     if (g.replicas > 1) push_items(merge_items, i, 0, (g.replicas - 1) * (g.cap + 1), kSlotChunk);
     push_items(fin_items, i, 0, d[i].n_keys == 0 ? 1 : g.cap + 1, kSlotChunk);
   }
-  if (shared_scan(d, n)) {
-    // plans over one fact table: tile range j of every plan, then range j + 1,
-    // so that the plans' passes over a range run together and share its
-    // columns through the caches
-    const uint64_t ntiles = static_cast<uint64_t>(plans[0].ntiles);
-    for (uint64_t b = 0; b < ntiles; b += B.chunk_tiles)
-      for (int i = 0; i < n; ++i) {
-        BatchItem it;
-        it.inst = i;
-        it.aux = 0;
-        it.begin = b;
-        it.end = b + B.chunk_tiles < ntiles ? b + B.chunk_tiles : ntiles;
-        tile_items.push_back(it);
-      }
+  // the fused-pass items of the small-table class, then of the other
+  size_t nsmall = 0;
+  for (int c = 0; c < 2; ++c) {
+    if (shared_scan(d, n)) {
+      // plans over one fact table: tile range j of every plan, then range
+      // j + 1, so that the plans' passes over a range run together and share
+      // its columns through the caches
+      const uint64_t ntiles = static_cast<uint64_t>(plans[0].ntiles);
+      for (uint64_t b = 0; b < ntiles; b += B.chunk_tiles)
+        for (int i = 0; i < n; ++i) {
+          if (cls[i] != c) continue;
+          BatchItem it;
+          it.inst = i;
+          it.aux = 0;
+          it.begin = b;
+          it.end = b + B.chunk_tiles < ntiles ? b + B.chunk_tiles : ntiles;
+          tile_items.push_back(it);
+        }
+    } else {
+      for (int i = 0; i < n; ++i)
+        if (cls[i] == c)
+          push_items(tile_items, i, 0, static_cast<uint64_t>(plans[i].ntiles), B.chunk_tiles);
+    }
+    if (c == 0) nsmall = tile_items.size();
   }
-  // one LDS layout for every instance: the largest group table, then the queues
+  // one LDS layout per class: its largest group table, then the queues
+  uint32_t lds_bytes[2] = {0, 0};
   for (int i = 0; i < n; ++i) {
     plans[i].lds_group_offset = 0;
-    plans[i].queue_offset = group_lds;
-    plans[i].lds_bytes = group_lds + (kPipeThreads / kWave) * plans[i].queue_stride;
+    plans[i].queue_offset = group_lds[cls[i]];
+    plans[i].lds_bytes = group_lds[cls[i]] + (kPipeThreads / kWave) * plans[i].queue_stride;
+    if (plans[i].lds_bytes > lds_bytes[cls[i]]) lds_bytes[cls[i]] = plans[i].lds_bytes;
   }
   std::memcpy(host + B.off_fill, fill.data(), fill.size() * sizeof(FillItem));
   std::memcpy(host + B.off_build_items, build_items.data(), build_items.size() * sizeof(BatchItem));
@@ -832,25 +860,35 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
   bp.fin_items = reinterpret_cast<const BatchItem*>(w + B.off_fin_items);
   bp.nfill = static_cast<uint32_t>(fill.size());
   bp.nbuild = static_cast<uint32_t>(build_items.size());
-  bp.ntile = static_cast<uint32_t>(tile_items.size());
+  bp.ntile = static_cast<uint32_t>(nsmall);
   bp.nmerge = static_cast<uint32_t>(merge_items.size());
   bp.nfin = static_cast<uint32_t>(fin_items.size());
-  bp.lds_bytes = plans[0].lds_bytes;
-  bp.group_lds_bytes = group_lds;
+  bp.lds_bytes = lds_bytes[0];
+  bp.group_lds_bytes = group_lds[0];
   bp.counter = reinterpret_cast<unsigned long long*>(w);
+  big = bp;
+  big.tile_items = bp.tile_items + nsmall;
+  big.ntile = static_cast<uint32_t>(tile_items.size() - nsmall);
+  big.lds_bytes = lds_bytes[1];
+  big.group_lds_bytes = group_lds[1];
+  big.counter = reinterpret_cast<unsigned long long*>(w) + 1;  // zeroed by the upload too
 }
 
 // Enqueues the upload of the block at `host` and the six batch launches.
-rel_status batch_enqueue(const BatchLayout& B, const BatchParams& bp, const PipelineParams& shape,
-                         unsigned char* w, const void* host, int grid, hipStream_t s) {
+rel_status batch_enqueue(const BatchLayout& B, const BatchParams& bp, const BatchParams& big,
+                         const PipelineParams& shape, unsigned char* w, const void* host, int grid,
+                         hipStream_t s) {
   hipError_t e = hipMemcpyAsync(w, host, B.blob, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return fail(REL_EDEVICE, "batch: descriptor upload: %s", hipGetErrorString(e));
   launch_batch_fill(bp, s);
   launch_batch_build(bp, s);
-  e = launch_batch_pipeline(bp, shape, grid, s);
-  if (e != hipSuccess)
-    return fail(REL_EDEVICE, "batch: fused kernel launch (%u bytes of LDS): %s", bp.lds_bytes,
-                hipGetErrorString(e));
+  for (const BatchParams* f : {&bp, &big}) {
+    if (f->ntile == 0) continue;
+    e = launch_batch_pipeline(*f, shape, grid, s);
+    if (e != hipSuccess)
+      return fail(REL_EDEVICE, "batch: fused kernel launch (%u bytes of LDS): %s", f->lds_bytes,
+                  hipGetErrorString(e));
+  }
   launch_batch_merge(bp, s);
   launch_batch_finalize(bp, s);
   return after_launch(s, "batch");
@@ -1339,9 +1377,9 @@ rel_status rel_pipeline_batch(const rel_pipeline_desc* d, int n, const rel_outpu
   st = staging_take(B.blob, sl);
   if (st) return st;
   PipelineParams shape;
-  BatchParams bp;
-  batch_blob(d, n, o, B, w, static_cast<unsigned char*>(sl->host), shape, bp);
-  st = batch_enqueue(B, bp, shape, w, sl->host, batch_grid(d), s);
+  BatchParams bp, big;
+  batch_blob(d, n, o, B, w, static_cast<unsigned char*>(sl->host), shape, bp, big);
+  st = batch_enqueue(B, bp, big, shape, w, sl->host, batch_grid(d), s);
   // the slot is reused once the stream is past the upload (or at once when
   // nothing was enqueued)
   if (hipEventRecord(sl->done, s) == hipSuccess) sl->pending = true;
@@ -1376,14 +1414,14 @@ rel_status rel_pipeline_batch_graph(const rel_pipeline_desc* d, int n, const rel
   hipError_t e = hipHostMalloc(&g->host, B.blob, hipHostMallocDefault);
   if (e != hipSuccess) return bail(REL_EDEVICE, "pinned descriptor block", e);
   PipelineParams shape;
-  BatchParams bp;
-  batch_blob(d, n, o, B, w, static_cast<unsigned char*>(g->host), shape, bp);
+  BatchParams bp, big;
+  batch_blob(d, n, o, B, w, static_cast<unsigned char*>(g->host), shape, bp, big);
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) return bail(REL_EDEVICE, "capture stream", e);
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return bail(REL_EDEVICE, "begin capture", e);
   g_capturing = true;
-  st = batch_enqueue(B, bp, shape, w, g->host, batch_grid(d), cs);
+  st = batch_enqueue(B, bp, big, shape, w, g->host, batch_grid(d), cs);
   g_capturing = false;
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(cs, &graph);
