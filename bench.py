@@ -327,6 +327,14 @@ def bench_ops(args, torch, datagen, rel) -> dict:
     part_ms = k.get("group_partition", 0.0)
     res["group_by"] = line(k["group_agg"] + part_ms, 16 * npr, rows=npr, groups=groups,
                            partition_ms=part_ms, aggregate_ms=k["group_agg"], workload=wl)
+    del ws
+    torch.cuda.empty_cache()
+    # the autotuner's group-by record for this size bucket (fan-out, first
+    # scatter's LDS table), every candidate checked for identical groups
+    from paper_2508_04701_amd import autotune
+    rec = autotune.tune_groupby([dev["probe_grp"]], [dev["probe_val"]], aggs, mg)
+    res["group_by_autotune"] = {"bucket": autotune.bucket(npr, 0, mg), "tuning": rec["tuning"],
+                                "ms": rec["ms"], "candidates_ms": rec["candidates"]}
     res["finalize"] = line(k["group_finalize"], groups * (8 + 8 * len(aggs)), groups=groups,
                            workload="occupied group slots -> key and aggregate columns "
                                     "(includes the replica merge)")

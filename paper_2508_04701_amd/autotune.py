@@ -1,9 +1,13 @@
-"""Autotuner of the fused plans: per size bucket, the tuning record (global
-group-table replicas, LDS group table on or off, group-table load factor)
-with the lowest measured device time among candidates that all return
-identical results (any difference is a race and raises). Records persist
-as JSON keyed by (GPU architecture, operation, size bucket) and are applied
-per plan, also to each instance of a batch.
+"""Autotuner: per size bucket, the tuning record with the lowest measured
+device time among candidates that all return identical results (any
+difference is a race and raises). For fused plans the candidates vary the
+global group-table replicas, the LDS group table (off, 1024 or 4096 slots:
+the workgroup's LDS shape, which sets how many workgroups share a CU) and the
+group-table load factor; for the standalone group-by they vary the partition
+fan-out (single pass, automatic, 2048 to 16384 partitions) and the first
+scatter's LDS table. Records persist as JSON keyed by (GPU architecture,
+operation, size bucket) and are applied per plan, also to each instance of a
+batch.
 
 A bucket is the magnitude (in steps of 4x) of the fact rows, the largest dim
 and the group bound: plans within a bucket share the behaviour the knobs trade off
@@ -31,9 +35,23 @@ CANDIDATES = [
     {"lds_slots": -1, "replicas": 32},
     {"load_factor": 0.3},
     {"load_factor": 0.3, "replicas": 32},
+    {"lds_slots": 1024},
+    {"lds_slots": 4096},
 ]
 
-FIELDS = ("load_factor", "lds_slots", "replicas", "chunk_tiles", "dim_lds_bytes", "grid")
+# rel_groupby_agg: partitions of the radix-partitioned aggregation (-1: one
+# pass over the global table; 0: from the group bound) and the first
+# scatter's LDS table.
+GROUPBY_CANDIDATES = [
+    {},
+    {"fanout": -1},
+    {"fanout": 2048},
+    {"fanout": 8192},
+    {"fanout": 16384},
+    {"lds_slots": -1},
+]
+
+FIELDS = ("load_factor", "lds_slots", "replicas", "chunk_tiles", "dim_lds_bytes", "grid", "fanout")
 
 
 def arch() -> str:
@@ -126,6 +144,36 @@ def tune_plan(make, candidates=CANDIDATES, reps: int = 3) -> dict:
         del plan
     best = min(times, key=times.get)
     return {"tuning": json.loads(best), "ms": times[best], "candidates": times}
+
+
+class GroupByCall:
+    """rel_groupby_agg on fixed inputs with its own workspace and outputs, in
+    the launch()/result() form that tune_plan times."""
+
+    def __init__(self, keys, vals, aggs, max_groups: int, t=None):
+        self.keys, self.vals, self.aggs, self.max_groups, self.t = keys, vals, aggs, max_groups, t
+        dev = (keys or vals)[0].device
+        n = (keys or vals)[0].numel()
+        self.ws = rel.workspace(rel.groupby_ws([k.dtype for k in keys], aggs, n, max_groups, t), dev)
+        cap = max(1, min(max_groups, n))
+        self.out_keys, self.out_aggs = rel._out_tensors([k.dtype for k in keys], aggs, cap, dev)
+        self.count = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def launch(self):
+        rel.groupby_agg_async(self.keys, self.vals, self.aggs, self.out_keys, self.out_aggs,
+                              self.count, self.max_groups, self.ws, t=self.t)
+
+    def result(self):
+        n = int(self.count.item())
+        if n < 0 or n > self.out_aggs[0].numel():
+            raise RuntimeError(f"group-by produced {n} groups for a bound of {self.max_groups}")
+        return [k[:n] for k in self.out_keys], [a[:n] for a in self.out_aggs]
+
+
+def tune_groupby(keys, vals, aggs, max_groups: int, candidates=GROUPBY_CANDIDATES,
+                 reps: int = 3) -> dict:
+    """tune_plan over rel_groupby_agg records for these inputs."""
+    return tune_plan(lambda t: GroupByCall(keys, vals, aggs, max_groups, t), candidates, reps)
 
 
 def plan_bucket(n_fact: int, dim_rows: list, max_groups: int) -> str:

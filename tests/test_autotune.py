@@ -36,5 +36,12 @@ def test_every_candidate_is_a_valid_tuning():
         # a valid record: the library accepts it for a plan's workspace size
         n = L.rel_hash_join_ws(2, 1000, rel.ctypes.byref(t))
         assert n > 0, cand
+    kt = (rel.ctypes.c_int32 * 1)(3)
+    aggs = (rel.Agg * 1)(rel.Agg(0, 0))
+    for cand in autotune.GROUPBY_CANDIDATES:
+        t = autotune.to_tuning(cand)
+        if t is None:
+            continue
+        assert L.rel_groupby_ws(1, kt, 1, aggs, 1_000_000, 200_000, rel.ctypes.byref(t)) > 0, cand
     with pytest.raises(ValueError):
         autotune.to_tuning({"warp_size": 32})

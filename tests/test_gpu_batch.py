@@ -257,3 +257,21 @@ def test_autotuner_candidates_agree_and_records_apply_to_batches():
     torch.cuda.synchronize()
     for i, (spec, plan) in enumerate(zip(specs, b.plans)):
         assert_groups(plan.result(), oracle_of(spec), AGGS, f"tuned instance {i}")
+
+
+def test_autotuner_groupby_fanout_candidates_agree():
+    """The group-by tuner's candidates (single pass, automatic and forced
+    partition fan-outs, no first-scatter LDS table) return the same groups,
+    and the kept record reproduces the oracle."""
+    from paper_2508_04701_amd import autotune
+    announce("autotuner group-by")
+    r = np.random.default_rng(808)
+    n = 1_000_003
+    k = r.integers(0, 200_000, size=n).astype(np.int64)
+    v = r.integers(-10**9, 10**9, size=n).astype(np.int64)
+    aggs = [("sum", 0), ("count", None), ("min", 0), ("max", 0)]
+    rec = autotune.tune_groupby([dev(k)], [dev(v)], aggs, 200_000)
+    assert len(rec["candidates"]) == len(autotune.GROUPBY_CANDIDATES)
+    got = rel.groupby_agg([dev(k)], [dev(v)], aggs, max_groups=200_000,
+                          t=autotune.to_tuning(rec["tuning"]))
+    assert_groups(got, oracle.groupby([k], [v], aggs), aggs, "tuned group-by")
