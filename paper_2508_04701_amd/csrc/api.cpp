@@ -960,7 +960,7 @@ const DeviceInfo& device_info() {
   return info[dev];
 }
 
-// Radix-partitioned aggregation (see groupby_part.hip): used by default when
+// Radix-partitioned aggregation (see partition.hip): used by default when
 // the group table exceeds kPartTableBytes, where rows would otherwise update
 // it with random read-modify-writes in HBM.
 constexpr uint64_t kPartTableBytes = 64ull << 20;
@@ -1020,6 +1020,49 @@ GroupLayout groupby_layout(const GroupPlan& gp, int64_t n, int64_t max_groups,
   pp.b_off = align_up(pp.a_off + static_cast<size_t>(n) * pp.rw * 8);
   one.end = align_up(pp.b_off + static_cast<size_t>(n) * pp.rw * 8);
   return one;
+}
+
+// Partitioned map build for rel_hash_join (see partition.hip): used by
+// default when the slot array exceeds kPartTableBytes, where inserts would
+// otherwise be random device-scope CAS into HBM. Ranges of kMapSpanBytes of
+// slots are built in LDS; the slot array needs at least 4 of them.
+constexpr size_t kMapSpanBytes = 128 * 1024;
+
+struct JoinPart {
+  bool on = false;
+  int span_log2 = 0, sub = 1, b1 = 0, b2 = 0;
+  size_t ctl_off = 0, a_off = 0, b_off = 0, end = 0;
+};
+
+JoinPart join_part(const MapLayout& L, int32_t key_type, int64_t n, const rel_tuning* t) {
+  JoinPart jp;
+  jp.end = L.end;
+  const int fan = t ? t->fanout : 0;
+  const uint64_t bytes = L.cap * L.slot_bytes;
+  int span_log2 = 0;
+  while ((static_cast<size_t>(1) << (span_log2 + 1)) * L.slot_bytes <= kMapSpanBytes) ++span_log2;
+  if (L.compact || n <= 0 || fan < 0 || (fan == 0 && bytes < kPartTableBytes) ||
+      L.cap < (4ULL << span_log2))
+    return jp;
+  int cap_log2 = 0;
+  while ((1ULL << cap_log2) < L.cap) ++cap_log2;
+  int pb = cap_log2 - span_log2;  // one partition per range
+  if (fan > 0) {
+    const int want = log2_ceil(static_cast<uint64_t>(fan));
+    if (want < pb) pb = want;
+  }
+  if (pb > kPartMaxBits) pb = kPartMaxBits;
+  jp.on = true;
+  jp.span_log2 = span_log2;
+  jp.sub = 1 << (cap_log2 - span_log2 - pb);
+  jp.b1 = (pb + 1) / 2;
+  jp.b2 = pb - jp.b1;
+  (void)key_type;
+  jp.ctl_off = align_up(L.end);
+  jp.a_off = align_up(jp.ctl_off + kCtlAll * 8);
+  jp.b_off = align_up(jp.a_off + static_cast<size_t>(n) * 16);
+  jp.end = align_up(jp.b_off + static_cast<size_t>(n) * 16);
+  return jp;
 }
 
 }  // namespace rel
@@ -1107,8 +1150,10 @@ rel_status rel_filter(const rel_column* cols, int ncols, const rel_pred* preds, 
 // --------------------------------------------------------------- hash join
 
 size_t rel_hash_join_ws(int32_t key_type, int64_t n_build, const rel_tuning* t) {
-  if ((key_type != REL_I32 && key_type != REL_I64) || n_build < 0) return 0;
-  return map_layout(key_type, n_build, load_factor(t), 0).end;
+  if ((key_type != REL_I32 && key_type != REL_I64) || n_build < 0 || n_build > kMaxRows) return 0;
+  if (t && check_tuning(t) != REL_OK) return 0;
+  const MapLayout L = map_layout(key_type, n_build, load_factor(t), 0);
+  return join_part(L, key_type, n_build, t).end;
 }
 
 rel_status rel_hash_join(const rel_column* build_keys, const rel_column* probe_keys,
@@ -1129,21 +1174,56 @@ rel_status rel_hash_join(const rel_column* build_keys, const rel_column* probe_k
   st = check_tuning(t);
   if (st) return st;
   const MapLayout L = map_layout(build_keys->type, build_keys->len, load_factor(t), 0);
-  st = check_ws(ws, ws_bytes, L.end);
+  const JoinPart jp = join_part(L, build_keys->type, build_keys->len, t);
+  st = check_ws(ws, ws_bytes, jp.end);
   if (st) return st;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   unsigned char* w = static_cast<unsigned char*>(ws);
   const MapDesc m = map_desc(L, build_keys->type, w);
-  launch_map_init(m, s);
-  MapBuildParams b;
-  std::memset(&b, 0, sizeof b);
-  b.map = m;
-  b.keys = build_keys->data;
-  b.idx = build_keys->idx;
-  b.type = build_keys->type;
-  b.n = build_keys->len;
-  launch_map_build(b, s);
+  if (jp.on) {
+    // every slot is written by the range builds: only the header starts at zero
+    launch_fill64(reinterpret_cast<uint64_t*>(m.oob_count), 2, 0, s);
+    PartParams p;
+    std::memset(&p, 0, sizeof p);
+    p.g.kp.nkeys = 1;
+    p.g.kp.type[0] = build_keys->type;
+    p.g.words = 2;
+    p.g.replicas = 1;
+    p.key_data[0] = build_keys->data;
+    p.key_idx[0] = build_keys->idx;
+    p.ncols = 1;
+    p.rw = 2;
+    p.value_row = 1;
+    p.n = build_keys->len;
+    p.b1 = jp.b1;
+    p.b2 = jp.b2;
+    p.piece = kPartPiece;
+    p.ctl = reinterpret_cast<unsigned long long*>(w + jp.ctl_off);
+    p.rec_a = reinterpret_cast<uint64_t*>(w + jp.a_off);
+    p.rec_b = reinterpret_cast<uint64_t*>(w + jp.b_off);
+    p.map_key = build_keys->type;
+    p.oob_count = m.oob_count;
+    p.oob_vals = m.oob_vals;
+    p.dup = m.dup;
+    if ((static_cast<size_t>(1) << jp.span_log2) * L.slot_bytes >
+        static_cast<size_t>(device_info().lds_per_block))
+      return fail(REL_EUNSUPPORTED, "join: the partitioned build exceeds the LDS of a workgroup");
+    launch_fill64(reinterpret_cast<uint64_t*>(p.ctl), kCtlZero, 0, s);
+    launch_fill64(reinterpret_cast<uint64_t*>(p.ctl + kCtlSpill), 1, 0, s);
+    hipError_t e = launch_map_partitioned(p, m, jp.span_log2, jp.sub, s);
+    if (e != hipSuccess) return fail(REL_EDEVICE, "join: %s", hipGetErrorString(e));
+  } else {
+    launch_map_init(m, s);
+    MapBuildParams b;
+    std::memset(&b, 0, sizeof b);
+    b.map = m;
+    b.keys = build_keys->data;
+    b.idx = build_keys->idx;
+    b.type = build_keys->type;
+    b.n = build_keys->len;
+    launch_map_build(b, s);
+  }
   launch_fill64(reinterpret_cast<uint64_t*>(d_count), 1, 0, s);
   MapProbeParams p;
   std::memset(&p, 0, sizeof p);

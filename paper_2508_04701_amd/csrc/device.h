@@ -199,15 +199,19 @@ struct Map64 {
 
 // Probe runs start at the first slot of the 16-byte bucket holding the hash
 // slot, so one aligned 16-byte read covers the first two key/value slots (or
-// four key-only slots) of every run.
+// four key-only slots) of every run. Key/value maps take their home slot from
+// the top hash bits, so that the keys of one range of the slot array share a
+// hash prefix (the partitioned build builds each range on its own).
 __device__ __forceinline__ uint64_t home32(int32_t key, uint64_t mask) {
-  return (hash32(static_cast<uint32_t>(key)) & mask) & ~1ULL;
+  const uint64_t h = hash32(static_cast<uint32_t>(key));
+  const int sh = __clzll(static_cast<long long>(mask | 1)) - 32;  // 32 - log2(slots)
+  return ((sh >= 0 ? h >> sh : h << -sh) & mask) & ~1ULL;
 }
 __device__ __forceinline__ uint64_t home_set(int32_t key, uint64_t mask) {
   return (hash32(static_cast<uint32_t>(key)) & mask) & ~3ULL;
 }
 __device__ __forceinline__ uint64_t home64(int64_t key, uint64_t mask) {
-  return hash64(static_cast<uint64_t>(key)) & mask;
+  return mask ? hash64(static_cast<uint64_t>(key)) >> __clzll(static_cast<long long>(mask)) : 0;
 }
 
 __device__ __forceinline__ uint64_t pack32(int32_t key, uint32_t val) {

@@ -282,10 +282,27 @@ struct PartParams {
   uint64_t* rec_a;    // n * rw words: records grouped by bucket
   uint64_t* rec_b;    // n * rw words: records grouped by partition
   unsigned long long* ctl;  // kCtlWords control words
+  // Map builds (map_key != 0): records are (key, row id or payload); the
+  // partition is the top bits of the map's home hash (the 32-bit key hash for
+  // int32 keys); sentinel keys go to the map's out-of-band list instead.
+  int32_t map_key;  // 0: group-by; kI32 or kI64: the map's key type
+  int32_t value_row;  // the record value is the row id (idx[r] or r)
+  unsigned long long* oob_count;
+  uint32_t* oob_vals;
+  int32_t* dup;
 };
+
+constexpr uint64_t kCtlSpill = kCtlWords;  // map builds: records spilled past their range
+constexpr uint64_t kCtlAll = kCtlWords + 32;
 
 // Runs the counting, scatter and aggregation passes into p.g (initialised).
 hipError_t launch_group_partitioned(const PartParams& p, hipStream_t s);
+
+// Partitioned map build: the counting and scatter passes, then each range of
+// 2^span_log2 slots built in LDS and written whole (`sub` ranges per
+// partition), then the spilled keys by global CAS. Every slot of m is written.
+hipError_t launch_map_partitioned(const PartParams& p, const MapDesc& m, int span_log2, int sub,
+                                  hipStream_t s);
 
 // Output agg a: op (rel_agg_op) and the accumulator it reads.
 struct FinalizeParams {

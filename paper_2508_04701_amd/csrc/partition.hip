@@ -20,6 +20,14 @@
 //             per key. A key that finds no LDS slot updates the global table
 //             directly, so results never depend on the sizing.
 //
+// The same counting and scatter passes serve the partitioned map build
+// (rel_hash_join over large build sides): records are (key, row id),
+// partitioned by the top bits of the map's home hash, so that a partition
+// holds exactly the keys whose home slots fall in its range of the slot
+// array. Each range is built in LDS by linear probing and written out whole;
+// a key whose probe run passes the end of its range is inserted afterwards by
+// global CAS, once every range is in place.
+//
 // Within a tile of the second scatter, a record's position is the tile's
 // claim on its partition (one atomic per partition and tile, on a cursor of
 // its own 128-byte line) plus the record's rank among the tile's records for
@@ -97,8 +105,22 @@ __device__ __forceinline__ void load_keys(const PartParams& p, uint64_t r0, uint
   for (int e = 0; e < N; ++e) pk[e] = pack_keys(p.g.kp, k0[e], k1[e]);
 }
 
-__device__ __forceinline__ uint32_t part_of(uint64_t pk, int pb) {
-  return static_cast<uint32_t>(hash64(pk) >> (64 - pb));
+// The hash whose top bits pick a record's partition: the map's home hash for
+// map builds of int32 keys, else hash64 of the packed key (which is also the
+// home hash of int64 maps and of group tables).
+__device__ __forceinline__ uint64_t part_hash(const PartParams& p, uint64_t pk) {
+  if (p.map_key == kI32) return static_cast<uint64_t>(hash32(static_cast<uint32_t>(pk))) << 32;
+  return hash64(pk);
+}
+
+__device__ __forceinline__ uint32_t part_of(const PartParams& p, uint64_t pk, int bits) {
+  return static_cast<uint32_t>(part_hash(p, pk) >> (64 - bits));
+}
+
+// Map builds: the sentinel key pattern never enters a slot array.
+__device__ __forceinline__ bool map_sentinel(const PartParams& p, uint64_t pk) {
+  if (p.map_key == kI64) return pk == kEmpty64;
+  return p.map_key == kI32 && static_cast<int32_t>(static_cast<uint32_t>(pk)) == kEmpty32;
 }
 
 // Exclusive prefix of v over the workgroup (thread order); *total gets the
@@ -147,7 +169,7 @@ __global__ void __launch_bounds__(kPartThreads) part_count_kernel(PartParams p) 
     load_keys<kPartRows>(p, r0, kPartThreads, n, pk);
 #pragma unroll
     for (int e = 0; e < kPartRows; ++e)
-      if (r0 + static_cast<uint64_t>(e) * kPartThreads < n) atomicAdd(&h[part_of(pk[e], p.b1)], 1u);
+      if (r0 + static_cast<uint64_t>(e) * kPartThreads < n) atomicAdd(&h[part_of(p, pk[e], p.b1)], 1u);
   }
   __syncthreads();
   for (int b = threadIdx.x; b < nb; b += blockDim.x)
@@ -203,13 +225,30 @@ __global__ void __launch_bounds__(kPartThreads) part_scatter1_kernel(PartParams 
     int64_t val[kPair ? kRows : 1];
     uint32_t code[kRows];
     load_keys<kRows>(p, r0, kPartThreads, n, pk);
-    if constexpr (kPair)
-      load_rows<kRows>(p.col_data[0], p.col_type[0], p.col_idx[0], r0, kPartThreads, n, val);
+    if constexpr (kPair) {
+      if (p.value_row) {
+#pragma unroll
+        for (int e = 0; e < kRows; ++e) {
+          const uint64_t r = r0 + static_cast<uint64_t>(e) * kPartThreads;
+          const uint64_t at = r < n ? r : 0;
+          val[e] = p.key_idx[0] ? static_cast<int64_t>(p.key_idx[0][at]) : static_cast<int64_t>(at);
+        }
+      } else {
+        load_rows<kRows>(p.col_data[0], p.col_type[0], p.col_idx[0], r0, kPartThreads, n, val);
+      }
+    }
 #pragma unroll
     for (int e = 0; e < kRows; ++e) {
       const uint64_t r = r0 + static_cast<uint64_t>(e) * kPartThreads;
       code[e] = kNoRecord;
       if (r >= n) continue;
+      if (kPair && map_sentinel(p, pk[e])) {
+        // out of band, as the map's own inserts do
+        const unsigned long long pos = atomicAdd(p.oob_count, 1ULL);
+        p.oob_vals[pos] = static_cast<uint32_t>(val[e]);
+        if (pos > 0) *p.dup = 1;
+        continue;
+      }
       const int32_t s = lds_group_find(pre, p.pre_slots, g.words, pk[e], kPreProbe);
       if (s >= 0) {
         uint64_t acc[kMaxAcc];
@@ -218,7 +257,7 @@ __global__ void __launch_bounds__(kPartThreads) part_scatter1_kernel(PartParams 
           if (a < g.ap.nacc) acc[a] = kPair ? static_cast<uint64_t>(val[e]) : row_col(p, p.src[a], r);
         lds_group_update(pre + static_cast<size_t>(s) * g.words, g.ap, acc);
       } else {
-        const uint32_t q = part_of(pk[e], pb);
+        const uint32_t q = part_of(p, pk[e], pb);
         const uint32_t b = q >> p.b2;
         const uint32_t rank = atomicAdd(&cnt[b], 1u);
         atomicAdd(&h2[q], 1u);
@@ -345,7 +384,7 @@ __global__ void __launch_bounds__(kPartThreads) part_scatter2_kernel(PartParams 
       const uint64_t i = first + threadIdx.x + static_cast<uint64_t>(e) * kPartThreads;
       code[e] = kNoRecord;
       if (i >= end) continue;
-      const uint32_t j = part_of(pk[e], pb) & static_cast<uint32_t>(n2 - 1);
+      const uint32_t j = part_of(p, pk[e], pb) & static_cast<uint32_t>(n2 - 1);
       code[e] = (j << 16) | atomicAdd(&cnt[j], 1u);
     }
     __syncthreads();
@@ -436,6 +475,99 @@ __global__ void __launch_bounds__(kPartAggThreads) part_agg_kernel(PartParams p)
   }
 }
 
+// Map builds: partition q covers `sub` consecutive ranges of 2^span_log2
+// slots; each range is built in LDS from the partition's records whose home
+// slot lies in it, then written out whole.
+template <typename K>
+__global__ void __launch_bounds__(kPartAggThreads) part_build_kernel(PartParams p, MapDesc m,
+                                                                     int span_log2, int sub) {
+  extern __shared__ uint64_t slots[];  // 2^span_log2 slots of 16 (int64) or 8 (int32) bytes
+  constexpr bool k64 = sizeof(K) == 8;
+  const uint32_t nparts = 1u << (p.b1 + p.b2);
+  const uint64_t mask = m.cap - 1;
+  const uint32_t span = 1u << span_log2;
+  for (uint32_t q = blockIdx.x; q < nparts; q += gridDim.x) {
+    const uint64_t first = p.ctl[kCtlStart2 + q];
+    const uint64_t end = first + p.ctl[kCtlHist2 + q];
+    for (int g = 0; g < sub; ++g) {
+      const uint64_t range = static_cast<uint64_t>(q) * sub + g;
+      const uint64_t base = range << span_log2;
+      for (uint32_t i = threadIdx.x; i < span; i += blockDim.x) {
+        if constexpr (k64) {
+          slots[2 * i] = kEmpty64;
+          slots[2 * i + 1] = 0;
+        } else {
+          slots[i] = kEmptySlot32;
+        }
+      }
+      __syncthreads();
+      for (uint64_t i = first + threadIdx.x; i < end; i += blockDim.x) {
+        const ulonglong2 rec = reinterpret_cast<const ulonglong2*>(p.rec_b)[i];
+        const K key = static_cast<K>(rec.x);
+        const uint32_t val = static_cast<uint32_t>(rec.y);
+        const uint64_t home = k64 ? home64(key, mask) : home32(static_cast<int32_t>(key), mask);
+        if ((home >> span_log2) != range) continue;
+        bool placed = false;
+        for (uint32_t at = static_cast<uint32_t>(home - base); at < span; ++at) {
+          if constexpr (k64) {
+            const unsigned long long prev =
+                atomicCAS(reinterpret_cast<unsigned long long*>(slots + 2 * at),
+                          static_cast<unsigned long long>(kEmpty64), static_cast<unsigned long long>(key));
+            if (prev == kEmpty64) {
+              slots[2 * at + 1] = val;
+              placed = true;
+              break;
+            }
+            if (static_cast<int64_t>(prev) == static_cast<int64_t>(key)) *p.dup = 1;
+          } else {
+            const unsigned long long prev =
+                atomicCAS(reinterpret_cast<unsigned long long*>(slots + at),
+                          static_cast<unsigned long long>(kEmptySlot32),
+                          static_cast<unsigned long long>(pack32(static_cast<int32_t>(key), val)));
+            if (prev == kEmptySlot32) {
+              placed = true;
+              break;
+            }
+            if (static_cast<int32_t>(static_cast<uint32_t>(prev)) == static_cast<int32_t>(key)) *p.dup = 1;
+          }
+        }
+        if (!placed) {
+          const unsigned long long pos = atomicAdd(&p.ctl[kCtlSpill], 1ULL);
+          reinterpret_cast<ulonglong2*>(p.rec_a)[pos] = rec;
+        }
+      }
+      __syncthreads();
+      if constexpr (k64) {
+        ulonglong2* dst = static_cast<ulonglong2*>(m.slots) + base;
+        for (uint32_t i = threadIdx.x; i < span; i += blockDim.x)
+          dst[i] = make_ulonglong2(slots[2 * i], slots[2 * i + 1]);
+      } else {
+        uint64_t* dst = static_cast<uint64_t*>(m.slots) + base;
+        for (uint32_t i = threadIdx.x; i < span; i += blockDim.x) dst[i] = slots[i];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Map builds: keys whose probe run left their range, inserted into the
+// finished slot array from their home slot on.
+template <typename K>
+__global__ void __launch_bounds__(256) part_spill_kernel(PartParams p, MapDesc m) {
+  const unsigned long long n = p.ctl[kCtlSpill];
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n; i += stride) {
+    const ulonglong2 rec = reinterpret_cast<const ulonglong2*>(p.rec_a)[i];
+    if constexpr (sizeof(K) == 8) {
+      map_insert(Map64{static_cast<ulonglong2*>(m.slots), m.cap - 1, m.oob_count, m.oob_vals},
+                 static_cast<int64_t>(rec.x), static_cast<uint32_t>(rec.y), m.dup);
+    } else {
+      map_insert(Map32{static_cast<uint64_t*>(m.slots), m.cap - 1, m.oob_count, m.oob_vals},
+                 static_cast<int32_t>(rec.x), static_cast<uint32_t>(rec.y), m.dup);
+    }
+  }
+}
+
 // Lets a kernel take up to all of a workgroup's LDS as dynamic LDS.
 hipError_t allow_dynamic_lds(const void* k) {
   hipFuncAttributes attr;
@@ -449,7 +581,9 @@ hipError_t allow_dynamic_lds_all() {
   const void* kernels[] = {reinterpret_cast<const void*>(part_scatter1_kernel<true, kScatterRows>),
                            reinterpret_cast<const void*>(part_scatter1_kernel<false, kScatterRows>),
                            reinterpret_cast<const void*>(part_agg_kernel<true>),
-                           reinterpret_cast<const void*>(part_agg_kernel<false>)};
+                           reinterpret_cast<const void*>(part_agg_kernel<false>),
+                           reinterpret_cast<const void*>(part_build_kernel<int32_t>),
+                           reinterpret_cast<const void*>(part_build_kernel<int64_t>)};
   for (const void* k : kernels) {
     hipError_t e = allow_dynamic_lds(k);
     if (e != hipSuccess) return e;
@@ -464,25 +598,32 @@ size_t part_scatter1_lds(const PartParams& p) {
          (sizeof(uint32_t) + sizeof(unsigned long long)) * (1u << kPartLevelBits);
 }
 
+// The counting and scatter passes (records end up grouped by partition in
+// rec_b, with their starts and counts in the control words).
+void launch_partition_passes(const PartParams& p, hipStream_t s) {
+  hipLaunchKernelGGL(part_count_kernel, dim3(kPartGroups), dim3(kPartThreads), 0, s, p);
+  hipLaunchKernelGGL(part_scan1_kernel, dim3(1), dim3(1024), 0, s, p);
+  if (p.rw == 2)
+    hipLaunchKernelGGL((part_scatter1_kernel<true, kScatterRows>), dim3(kPartGroups),
+                       dim3(kPartThreads), part_scatter1_lds(p), s, p);
+  else
+    hipLaunchKernelGGL((part_scatter1_kernel<false, kScatterRows>), dim3(kPartGroups),
+                       dim3(kPartThreads), part_scatter1_lds(p), s, p);
+  hipLaunchKernelGGL(part_scan2_kernel, dim3(1), dim3(1024), 0, s, p);
+  const int grid = device_info().cu_count * 2;
+  if (p.rw == 2)
+    hipLaunchKernelGGL(part_scatter2_kernel<true>, dim3(grid), dim3(kPartThreads), 0, s, p);
+  else
+    hipLaunchKernelGGL(part_scatter2_kernel<false>, dim3(grid), dim3(kPartThreads), 0, s, p);
+}
+
 hipError_t launch_group_partitioned(const PartParams& p, hipStream_t s) {
   const int cus = device_info().cu_count;
   static const hipError_t attrs = allow_dynamic_lds_all();  // once per process
   if (attrs != hipSuccess) return attrs;
   {
     ProfileScope ps(kKGroupPartition, s);
-    hipLaunchKernelGGL(part_count_kernel, dim3(kPartGroups), dim3(kPartThreads), 0, s, p);
-    hipLaunchKernelGGL(part_scan1_kernel, dim3(1), dim3(1024), 0, s, p);
-    if (p.rw == 2)
-      hipLaunchKernelGGL((part_scatter1_kernel<true, kScatterRows>), dim3(kPartGroups), dim3(kPartThreads),
-                         part_scatter1_lds(p), s, p);
-    else
-      hipLaunchKernelGGL((part_scatter1_kernel<false, kScatterRows>), dim3(kPartGroups), dim3(kPartThreads),
-                         part_scatter1_lds(p), s, p);
-    hipLaunchKernelGGL(part_scan2_kernel, dim3(1), dim3(1024), 0, s, p);
-    if (p.rw == 2)
-      hipLaunchKernelGGL(part_scatter2_kernel<true>, dim3(cus * 2), dim3(kPartThreads), 0, s, p);
-    else
-      hipLaunchKernelGGL(part_scatter2_kernel<false>, dim3(cus * 2), dim3(kPartThreads), 0, s, p);
+    launch_partition_passes(p, s);
   }
   ProfileScope ps(kKGroupAgg, s);
   const size_t agg_lds = static_cast<size_t>(p.agg_slots) * p.g.words * 8;
@@ -490,6 +631,26 @@ hipError_t launch_group_partitioned(const PartParams& p, hipStream_t s) {
     hipLaunchKernelGGL(part_agg_kernel<true>, dim3(cus), dim3(kPartAggThreads), agg_lds, s, p);
   else
     hipLaunchKernelGGL(part_agg_kernel<false>, dim3(cus), dim3(kPartAggThreads), agg_lds, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_partitioned(const PartParams& p, const MapDesc& m, int span_log2, int sub,
+                                  hipStream_t s) {
+  const int cus = device_info().cu_count;
+  static const hipError_t attrs = allow_dynamic_lds_all();  // once per process
+  if (attrs != hipSuccess) return attrs;
+  ProfileScope ps(kKMapBuild, s);
+  launch_partition_passes(p, s);
+  const size_t lds = (static_cast<size_t>(1) << span_log2) * (m.key_type == kI64 ? 16 : 8);
+  if (m.key_type == kI64) {
+    hipLaunchKernelGGL(part_build_kernel<int64_t>, dim3(cus), dim3(kPartAggThreads), lds, s, p, m,
+                       span_log2, sub);
+    hipLaunchKernelGGL(part_spill_kernel<int64_t>, dim3(cus), dim3(256), 0, s, p, m);
+  } else {
+    hipLaunchKernelGGL(part_build_kernel<int32_t>, dim3(cus), dim3(kPartAggThreads), lds, s, p, m,
+                       span_log2, sub);
+    hipLaunchKernelGGL(part_spill_kernel<int32_t>, dim3(cus), dim3(256), 0, s, p, m);
+  }
   return hipGetLastError();
 }
 

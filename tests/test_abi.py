@@ -78,8 +78,14 @@ def test_workspace_sizes():
     assert 0 < small < big
     assert L.rel_hash_join_ws(3, 10_000, None) > small   # 16-byte slots for int64 keys
     assert L.rel_hash_join_ws(1, 10, None) == 0           # int8 keys are not joinable
-    t = rel.tuning(load_factor=0.9)
-    assert L.rel_hash_join_ws(2, 600_000, ctypes.byref(t)) < L.rel_hash_join_ws(2, 600_000, None)
+    t = rel.tuning(load_factor=0.9, fanout=-1)
+    off = rel.tuning(fanout=-1)
+    assert L.rel_hash_join_ws(2, 600_000, ctypes.byref(t)) < L.rel_hash_join_ws(2, 600_000, ctypes.byref(off))
+    # large build sides: the partitioned build adds two buffers of 16-byte records
+    big = 100_000_000
+    assert L.rel_hash_join_ws(3, big, None) >= L.rel_hash_join_ws(3, big, ctypes.byref(off)) + 32 * big
+    assert L.rel_hash_join_ws(3, 1000, rel.ctypes.byref(rel.tuning(fanout=64))) == \
+        L.rel_hash_join_ws(3, 1000, ctypes.byref(off))   # too small for four LDS ranges
     aggs = (rel.Agg * 2)(rel.Agg(0, 0), rel.Agg(1, 0))
     kt = (ctypes.c_int32 * 2)(2, 1)
     assert L.rel_groupby_ws(2, kt, 2, aggs, 1000, 100, None) > 0

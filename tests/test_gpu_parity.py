@@ -143,6 +143,60 @@ def test_hash_join(case, dtype):
     assert_pairs(got, oracle.hash_join(b, p), case)
 
 
+def partitioned_build_case(case, dtype, r):
+    """Build sides of at least 4 LDS ranges (32768 int32 / 16384 int64 keys
+    and more), with runs that cross range ends."""
+    info = np.iinfo(dtype)
+    if case == "unique":
+        b = r.permutation(70_000).astype(dtype) * 3 - 7
+        p = r.integers(-100, 215_000, size=200_001).astype(dtype)
+    elif case == "dups":
+        # ~23 copies per key: long runs, spills past range ends
+        b = r.integers(0, 3000, size=70_000).astype(dtype)
+        p = r.integers(0, 3500, size=20_000).astype(dtype)
+    elif case == "sentinel":
+        b = r.integers(-50_000, 50_000, size=70_000).astype(dtype)
+        b[r.random(b.size) < 0.05] = info.min
+        p = r.integers(-60_000, 60_000, size=50_000).astype(dtype)
+        p[r.random(p.size) < 0.05] = info.min
+    else:  # one key repeated 6000 times among unique keys
+        b = r.permutation(70_000).astype(dtype)
+        b[r.choice(b.size, 6000, replace=False)] = 12345
+        p = r.integers(0, 80_000, size=100_000).astype(dtype)
+    return b, p
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64], ids=["i32", "i64"])
+@pytest.mark.parametrize("case", ["unique", "dups", "sentinel", "hot"])
+@pytest.mark.parametrize("fanout", [4, 16384])
+def test_hash_join_partitioned_build(case, dtype, fanout):
+    """The partitioned build (ranges of the slot array built in LDS, runs past
+    a range end inserted afterwards), forced by the fan-out: 4 partitions of
+    several ranges each, or one partition per range."""
+    announce("join partitioned build", case, np.dtype(dtype).name, fanout)
+    seed = {"unique": 11, "dups": 12, "sentinel": 13, "hot": 14}[case]
+    b, p = partitioned_build_case(case, dtype, rng(seed))
+    t = rel.tuning(fanout=fanout)
+    single = rel.hash_join_ws(torch.from_numpy(b).dtype, b.size, rel.tuning(fanout=-1))
+    assert rel.hash_join_ws(torch.from_numpy(b).dtype, b.size, t) >= single + 32 * b.size
+    got = rel.hash_join(dev(b), dev(p), t=t)
+    assert_pairs(got, oracle.hash_join(b, p), f"partitioned {case}")
+
+
+def test_hash_join_partitioned_build_with_row_ids():
+    announce("join partitioned build idx")
+    r = rng(15)
+    b = r.integers(0, 40_000, size=90_000).astype(np.int64)
+    p = r.integers(0, 45_000, size=60_000).astype(np.int64)
+    bsel = np.sort(r.choice(90_000, size=50_000, replace=False)).astype(np.uint32)
+    got = rel.hash_join(dev(b), dev(p), build_idx=dev(bsel.view(np.int32)),
+                        t=rel.tuning(fanout=8))
+    wb, wp = oracle.hash_join(b[bsel], p)
+    wb2 = bsel[wb]
+    order = np.lexsort((wb2, wp))
+    assert_pairs(got, (wb2[order], wp[order]), "partitioned idx")
+
+
 def test_hash_join_with_row_ids():
     announce("join with idx")
     r = rng(3)
