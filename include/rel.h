@@ -115,11 +115,12 @@ typedef struct {
   int32_t replicas;      /* copies of the global group table; workgroup w updates copy
                             w mod replicas (w mod 8 is its XCD) and a last pass folds them;
                             0 = default (64 when all groups fit the LDS tables, else 1) */
-  int32_t fanout;        /* rel_groupby_agg: partitions of the radix-partitioned
-                            aggregation, a power of two in [4, 16384]; 0 = default
-                            (partitioned when the group table exceeds 64 MB, with as many
-                            partitions as keep each one's keys within an LDS table);
-                            -1 = never partition */
+  int32_t fanout;        /* partitions of the radix-partitioned rel_groupby_agg and
+                            rel_hash_join build, a power of two in [4, 16384]; 0 = default
+                            (partitioned when the group table or the join's slot array
+                            exceeds 64 MB: a group-by with as many partitions as keep each
+                            one's keys within an LDS table, a build with one partition per
+                            128 KB range of slots); -1 = never partition */
 } rel_tuning;
 
 /* rel_tuning.flags: keep dims of rel_pipeline in their hash tables even when
@@ -165,11 +166,14 @@ rel_status rel_filter(const rel_column* cols, int ncols, const rel_pred* preds, 
 
 /* ------------------------------------------------------------ hash join */
 
-/* Workspace bytes for rel_hash_join with n_build build rows. */
+/* Workspace bytes for rel_hash_join with n_build build rows (with a
+ * partitioned build, see rel_tuning.fanout, two buffers of 16-byte records
+ * per build row on top of the slot array). */
 size_t rel_hash_join_ws(int32_t key_type, int64_t n_build, const rel_tuning* t);
 
 /* Inner equi-join (the hash join of Sections 1 and 4.2): builds an
- * open-addressing hash table over build_keys in the workspace, then probes it
+ * open-addressing hash table over build_keys in the workspace (large build
+ * sides range by range in LDS, see rel_tuning.fanout), then probes it
  * with probe_keys and writes every matching pair (build row id, probe row
  * id). Duplicate keys on either side yield every pair. Pair order is
  * unspecified (compare after sorting by (probe, build)).

@@ -1034,7 +1034,7 @@ struct JoinPart {
   size_t ctl_off = 0, a_off = 0, b_off = 0, end = 0;
 };
 
-JoinPart join_part(const MapLayout& L, int32_t key_type, int64_t n, const rel_tuning* t) {
+JoinPart join_part(const MapLayout& L, int64_t n, const rel_tuning* t) {
   JoinPart jp;
   jp.end = L.end;
   const int fan = t ? t->fanout : 0;
@@ -1057,7 +1057,6 @@ JoinPart join_part(const MapLayout& L, int32_t key_type, int64_t n, const rel_tu
   jp.sub = 1 << (cap_log2 - span_log2 - pb);
   jp.b1 = (pb + 1) / 2;
   jp.b2 = pb - jp.b1;
-  (void)key_type;
   jp.ctl_off = align_up(L.end);
   jp.a_off = align_up(jp.ctl_off + kCtlAll * 8);
   jp.b_off = align_up(jp.a_off + static_cast<size_t>(n) * 16);
@@ -1153,7 +1152,7 @@ size_t rel_hash_join_ws(int32_t key_type, int64_t n_build, const rel_tuning* t) 
   if ((key_type != REL_I32 && key_type != REL_I64) || n_build < 0 || n_build > kMaxRows) return 0;
   if (t && check_tuning(t) != REL_OK) return 0;
   const MapLayout L = map_layout(key_type, n_build, load_factor(t), 0);
-  return join_part(L, key_type, n_build, t).end;
+  return join_part(L, n_build, t).end;
 }
 
 rel_status rel_hash_join(const rel_column* build_keys, const rel_column* probe_keys,
@@ -1174,7 +1173,7 @@ rel_status rel_hash_join(const rel_column* build_keys, const rel_column* probe_k
   st = check_tuning(t);
   if (st) return st;
   const MapLayout L = map_layout(build_keys->type, build_keys->len, load_factor(t), 0);
-  const JoinPart jp = join_part(L, build_keys->type, build_keys->len, t);
+  const JoinPart jp = join_part(L, build_keys->len, t);
   st = check_ws(ws, ws_bytes, jp.end);
   if (st) return st;
 
