@@ -752,18 +752,24 @@ void push_items(std::vector<BatchItem>& v, uint32_t inst, uint32_t aux, uint64_t
 
 // Writes the uploaded block of batch B over workspace w into `host` (B.blob
 // bytes), returns instance 0's plan in `shape` and the kernel arguments.
-// Instances whose LDS group table fits kSmallGroupLds share the fused pass
-// at full occupancy; those with larger tables (one or two workgroups per CU)
-// take a second persistent launch, so that they do not lower the occupancy
-// of the others.
-constexpr uint32_t kSmallGroupLds = 16384;
+// The fused pass runs one persistent launch per class of LDS group-table
+// size (up to 16, 32, 64 and 128 KB), so that instances with small tables
+// keep the occupancy their LDS allows instead of the largest table's.
+constexpr int kLdsClasses = 4;
+constexpr uint32_t kClassGroupLds[kLdsClasses] = {16384, 32768, 65536, 1u << 30};
+
+int lds_class(uint32_t group_lds) {
+  int c = 0;
+  while (group_lds > kClassGroupLds[c]) ++c;
+  return c;
+}
 
 // Fills the uploaded block at `host`. `bp` covers every instance and the
-// fused pass of the small-table class; `big` the fused pass of the others
-// (big.ntile = 0 when there are none).
+// fused pass of class 0; fused[c] the fused pass of class c (fused[c].ntile
+// = 0 when the class is empty; fused[0] = bp).
 void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const BatchLayout& B,
                 unsigned char* w, unsigned char* host, PipelineParams& shape, BatchParams& bp,
-                BatchParams& big) {
+                BatchParams fused[kLdsClasses]) {
   std::memset(host, 0, B.blob);
   PipelineParams* plans = reinterpret_cast<PipelineParams*>(host + B.off_plans);
   MapBuildParams* builds = reinterpret_cast<MapBuildParams*>(host + B.off_builds);
@@ -775,14 +781,14 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
   tile_items.reserve(B.ntile);
   merge_items.reserve(B.nmerge);
   fin_items.reserve(B.nfin);
-  uint32_t group_lds[2] = {0, 0};
+  uint32_t group_lds[kLdsClasses] = {};
   std::vector<int> cls(n);
   for (int i = 0; i < n; ++i) {
     const PipeLayout& L = B.L[i];
     PipelineParams& p = plans[i];
     plan_params(&d[i], L, w, o[i].d_groups, true, p, &builds[2 * i]);
     const uint32_t gl = static_cast<uint32_t>((static_cast<size_t>(p.lds_slots) * L.gp.words * 8 + 15) / 16 * 16);
-    cls[i] = gl > kSmallGroupLds ? 1 : 0;
+    cls[i] = lds_class(gl);
     if (gl > group_lds[cls[i]]) group_lds[cls[i]] = gl;
     fins[i] = finalize_params(p.g, L.gp, d[i].aggs, d[i].n_aggs, o[i].keys, L.key_types, o[i].aggs,
                               o[i].cap);
@@ -810,9 +816,9 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
     if (g.replicas > 1) push_items(merge_items, i, 0, (g.replicas - 1) * (g.cap + 1), kSlotChunk);
     push_items(fin_items, i, 0, d[i].n_keys == 0 ? 1 : g.cap + 1, kSlotChunk);
   }
-  // the fused-pass items of the small-table class, then of the other
-  size_t nsmall = 0;
-  for (int c = 0; c < 2; ++c) {
+  // the fused-pass items class by class
+  size_t class_end[kLdsClasses] = {};
+  for (int c = 0; c < kLdsClasses; ++c) {
     if (shared_scan(d, n)) {
       // plans over one fact table: tile range j of every plan, then range
       // j + 1, so that the plans' passes over a range run together and share
@@ -833,10 +839,10 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
         if (cls[i] == c)
           push_items(tile_items, i, 0, static_cast<uint64_t>(plans[i].ntiles), B.chunk_tiles);
     }
-    if (c == 0) nsmall = tile_items.size();
+    class_end[c] = tile_items.size();
   }
   // one LDS layout per class: its largest group table, then the queues
-  uint32_t lds_bytes[2] = {0, 0};
+  uint32_t lds_bytes[kLdsClasses] = {};
   for (int i = 0; i < n; ++i) {
     plans[i].lds_group_offset = 0;
     plans[i].queue_offset = group_lds[cls[i]];
@@ -860,34 +866,38 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
   bp.fin_items = reinterpret_cast<const BatchItem*>(w + B.off_fin_items);
   bp.nfill = static_cast<uint32_t>(fill.size());
   bp.nbuild = static_cast<uint32_t>(build_items.size());
-  bp.ntile = static_cast<uint32_t>(nsmall);
+  bp.ntile = static_cast<uint32_t>(class_end[0]);
   bp.nmerge = static_cast<uint32_t>(merge_items.size());
   bp.nfin = static_cast<uint32_t>(fin_items.size());
   bp.lds_bytes = lds_bytes[0];
   bp.group_lds_bytes = group_lds[0];
   bp.counter = reinterpret_cast<unsigned long long*>(w);
-  big = bp;
-  big.tile_items = bp.tile_items + nsmall;
-  big.ntile = static_cast<uint32_t>(tile_items.size() - nsmall);
-  big.lds_bytes = lds_bytes[1];
-  big.group_lds_bytes = group_lds[1];
-  big.counter = reinterpret_cast<unsigned long long*>(w) + 1;  // zeroed by the upload too
+  for (int c = 0; c < kLdsClasses; ++c) {
+    const size_t begin = c == 0 ? 0 : class_end[c - 1];
+    fused[c] = bp;
+    fused[c].tile_items = bp.tile_items + begin;
+    fused[c].ntile = static_cast<uint32_t>(class_end[c] - begin);
+    fused[c].lds_bytes = lds_bytes[c];
+    fused[c].group_lds_bytes = group_lds[c];
+    // one counter per class, in the uploaded (zeroed) first block
+    fused[c].counter = reinterpret_cast<unsigned long long*>(w) + c;
+  }
 }
 
 // Enqueues the upload of the block at `host` and the six batch launches.
-rel_status batch_enqueue(const BatchLayout& B, const BatchParams& bp, const BatchParams& big,
-                         const PipelineParams& shape, unsigned char* w, const void* host, int grid,
-                         hipStream_t s) {
+rel_status batch_enqueue(const BatchLayout& B, const BatchParams& bp,
+                         const BatchParams fused[kLdsClasses], const PipelineParams& shape,
+                         unsigned char* w, const void* host, int grid, hipStream_t s) {
   hipError_t e = hipMemcpyAsync(w, host, B.blob, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return fail(REL_EDEVICE, "batch: descriptor upload: %s", hipGetErrorString(e));
   launch_batch_fill(bp, s);
   launch_batch_build(bp, s);
-  for (const BatchParams* f : {&bp, &big}) {
-    if (f->ntile == 0) continue;
-    e = launch_batch_pipeline(*f, shape, grid, s);
+  for (int c = 0; c < kLdsClasses; ++c) {
+    if (fused[c].ntile == 0) continue;
+    e = launch_batch_pipeline(fused[c], shape, grid, s);
     if (e != hipSuccess)
-      return fail(REL_EDEVICE, "batch: fused kernel launch (%u bytes of LDS): %s", f->lds_bytes,
-                  hipGetErrorString(e));
+      return fail(REL_EDEVICE, "batch: fused kernel launch (%u bytes of LDS): %s",
+                  fused[c].lds_bytes, hipGetErrorString(e));
   }
   launch_batch_merge(bp, s);
   launch_batch_finalize(bp, s);
@@ -1456,9 +1466,9 @@ rel_status rel_pipeline_batch(const rel_pipeline_desc* d, int n, const rel_outpu
   st = staging_take(B.blob, sl);
   if (st) return st;
   PipelineParams shape;
-  BatchParams bp, big;
-  batch_blob(d, n, o, B, w, static_cast<unsigned char*>(sl->host), shape, bp, big);
-  st = batch_enqueue(B, bp, big, shape, w, sl->host, batch_grid(d), s);
+  BatchParams bp, fused[kLdsClasses];
+  batch_blob(d, n, o, B, w, static_cast<unsigned char*>(sl->host), shape, bp, fused);
+  st = batch_enqueue(B, bp, fused, shape, w, sl->host, batch_grid(d), s);
   // the slot is reused once the stream is past the upload (or at once when
   // nothing was enqueued)
   if (hipEventRecord(sl->done, s) == hipSuccess) sl->pending = true;
@@ -1493,14 +1503,14 @@ rel_status rel_pipeline_batch_graph(const rel_pipeline_desc* d, int n, const rel
   hipError_t e = hipHostMalloc(&g->host, B.blob, hipHostMallocDefault);
   if (e != hipSuccess) return bail(REL_EDEVICE, "pinned descriptor block", e);
   PipelineParams shape;
-  BatchParams bp, big;
-  batch_blob(d, n, o, B, w, static_cast<unsigned char*>(g->host), shape, bp, big);
+  BatchParams bp, fused[kLdsClasses];
+  batch_blob(d, n, o, B, w, static_cast<unsigned char*>(g->host), shape, bp, fused);
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) return bail(REL_EDEVICE, "capture stream", e);
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return bail(REL_EDEVICE, "begin capture", e);
   g_capturing = true;
-  st = batch_enqueue(B, bp, big, shape, w, g->host, batch_grid(d), cs);
+  st = batch_enqueue(B, bp, fused, shape, w, g->host, batch_grid(d), cs);
   g_capturing = false;
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(cs, &graph);
