@@ -1,12 +1,14 @@
 // Hash join: open-addressing multimap build and probe with pair output.
 //
 // Build: each element claims the first empty slot of its linear-probe chain
-// with one CAS (int32 keys publish key and value in the same 64-bit word).
-// Probe: each lane walks its key's chain; the wave advances in rounds, each
-// round giving every lane at most one match, so the output position of a
-// match comes from one wave ballot (mbcnt rank) and one atomic add per wave
-// on the global cursor. The cursor always ends at the exact pair count; pairs
-// beyond the output capacity are counted but not written.
+// with one CAS (int32 keys publish key and value in the same 64-bit word);
+// each lane keeps four elements' loads and CAS in flight. Large build sides
+// take the partitioned build instead (partition.hip).
+// Probe: each lane walks the chains of four probe keys, one slot per key and
+// round; a round's matches are ranked within the wave (ballot, mbcnt) and
+// staged in LDS, and a wave writes its staged pairs in runs, with one atomic
+// add per run on the global cursor. The cursor always ends at the exact pair
+// count; pairs beyond the output capacity are counted but not written.
 
 #include "internal.h"
 
@@ -241,20 +243,44 @@ __device__ __forceinline__ void direct_rows(const MapBuildParams& p, uint64_t i,
   const int32_t kmin = m.dstate[kDKmin];
   const int32_t pmin = m.dstate[kDPmin];
   const int width = p.val_col ? direct_width(pmin, m.dstate[kDPmax]) : 0;
-  for (; i < end; i += stride) {
-    const int64_t r = p.idx ? static_cast<int64_t>(p.idx[i]) : static_cast<int64_t>(i);
-    const uint32_t k = static_cast<uint32_t>(load_elem(p.keys, p.type, r) - kmin);
-    const uint32_t bit = 1u << (k & 31);
-    if (atomicOr(m.dbits + (k >> 5), bit) & bit) {
-      *m.dup = 1;
-      continue;
+  // kBuildKeys elements per lane and step: their loads, and their bitmap
+  // atomics, are in flight together
+  constexpr int J = kBuildKeys;
+  for (; i < end; i += J * stride) {
+    uint64_t at[J];
+    bool ok[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const uint64_t e = i + static_cast<uint64_t>(j) * stride;
+      ok[j] = e < end;
+      at[j] = ok[j] ? e : i;
     }
-    if (width == 0) continue;
-    const uint32_t v = static_cast<uint32_t>(load_elem(p.val_col, p.val_type, r)) -
-                       static_cast<uint32_t>(pmin);
-    if (width == 1) static_cast<uint8_t*>(m.dvals)[k] = static_cast<uint8_t>(v);
-    else if (width == 2) static_cast<uint16_t*>(m.dvals)[k] = static_cast<uint16_t>(v);
-    else static_cast<uint32_t*>(m.dvals)[k] = v;
+    if (p.idx) {
+#pragma unroll
+      for (int j = 0; j < J; ++j) at[j] = p.idx[at[j]];
+    }
+    int64_t kv[J], pv[J];
+    gather_elems<J>(p.keys, p.type, at, kv);
+    if (width) gather_elems<J>(p.val_col, p.val_type, at, pv);
+    uint32_t k[J], old[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      k[j] = static_cast<uint32_t>(kv[j] - kmin);
+      old[j] = ok[j] ? atomicOr(m.dbits + (k[j] >> 5), 1u << (k[j] & 31)) : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if (!ok[j]) continue;
+      if (old[j] & (1u << (k[j] & 31))) {
+        *m.dup = 1;
+        continue;
+      }
+      if (width == 0) continue;
+      const uint32_t v = static_cast<uint32_t>(pv[j]) - static_cast<uint32_t>(pmin);
+      if (width == 1) static_cast<uint8_t*>(m.dvals)[k[j]] = static_cast<uint8_t>(v);
+      else if (width == 2) static_cast<uint16_t*>(m.dvals)[k[j]] = static_cast<uint16_t>(v);
+      else static_cast<uint32_t*>(m.dvals)[k[j]] = v;
+    }
   }
 }
 
