@@ -371,7 +371,10 @@ typedef struct {
   int32_t max_slots;     /* queries in flight at once */
   int32_t max_batch;     /* queries per batch (1: one at a time) */
   int32_t lanes;         /* batches in flight at once, 1..64 */
-  int32_t reserved;
+  int32_t open_lane_at;  /* while a lane is busy, another starts a batch only when at least
+                            this many queries wait (0 or 1: whenever one waits). A backlog
+                            threshold keeps light load on one lane, whose next batch
+                            gathers the waiting queries */
   const rel_executor* executor; /* NULL: the GPU executor on the current device */
 } rel_server_config;
 

@@ -7,7 +7,9 @@
 // workspace from the arena with a first-fit allocator and launches it. A
 // query completes when its batch has finished and its results have been
 // copied to the caller's host buffers; then its lane, slots and bytes return
-// to the pool. The loop never waits on the device: it polls events.
+// to the pool. While a lane is busy, another lane starts a batch only when a
+// backlog of at least open_lane_at queries waits (by default one). The loop
+// never waits on the device: it polls events.
 //
 // The executor that runs a batch is an interface, so the same scheduler runs
 // on the GPU (streams and events) or on a test executor.
@@ -397,8 +399,17 @@ struct rel_server {
         complete_batch(i, r > 0 ? REL_OK : static_cast<rel_status>(-r));
         progress = true;
       }
-      for (int i = 0; i < static_cast<int>(lanes.size()) && !pending.empty(); ++i)
-        if (!lanes[i] && launch_one(i)) progress = true;
+      int busy = 0;
+      for (const auto& l : lanes) busy += l != nullptr;
+      const size_t open_at = static_cast<size_t>(cfg.open_lane_at > 1 ? cfg.open_lane_at : 1);
+      for (int i = 0; i < static_cast<int>(lanes.size()) && !pending.empty(); ++i) {
+        if (lanes[i]) continue;
+        if (busy > 0 && pending.size() < open_at) break;
+        if (launch_one(i)) {
+          progress = true;
+          ++busy;
+        }
+      }
       if (!progress) {
         std::unique_lock<std::mutex> lock(m);
         if (incoming.empty()) wake.wait_for(lock, std::chrono::microseconds(20));
@@ -414,7 +425,8 @@ int64_t rel_server_now_ns(void) { return clock_ns(); }
 rel_status rel_server_create(const rel_server_config* c, rel_server** out) {
   if (!out) return REL_EINVAL;
   *out = nullptr;
-  if (!c || c->max_slots < 1 || c->max_batch < 1 || c->lanes < 1 || c->lanes > 64)
+  if (!c || c->max_slots < 1 || c->max_batch < 1 || c->lanes < 1 || c->lanes > 64 ||
+      c->open_lane_at < 0)
     return REL_EINVAL;
   if (!c->arena || c->arena_bytes < kArenaAlign ||
       reinterpret_cast<uintptr_t>(c->arena) % kArenaAlign != 0)

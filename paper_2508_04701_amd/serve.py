@@ -33,7 +33,7 @@ class Executor(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
                 ("max_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("lanes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("lanes", ctypes.c_int32), ("open_lane_at", ctypes.c_int32),
                 ("executor", ctypes.POINTER(Executor))]
 
 
@@ -84,12 +84,14 @@ class Server:
     admission budget). ``max_batch=1, lanes=1`` serves one query at a time."""
 
     def __init__(self, arena_bytes: int, max_slots: int = 64, max_batch: int = 16,
-                 lanes: int = 2, executor: Executor | None = None, arena_ptr: int | None = None):
+                 lanes: int = 2, executor: Executor | None = None, arena_ptr: int | None = None,
+                 open_lane_at: int = 0):
         self._executor = executor
         if arena_ptr is None:
             self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
             arena_ptr = self.arena.data_ptr()
-        self.config = ServerConfig(arena_ptr, int(arena_bytes), max_slots, max_batch, lanes, 0,
+        self.config = ServerConfig(arena_ptr, int(arena_bytes), max_slots, max_batch, lanes,
+                                   open_lane_at,
                                    ctypes.pointer(executor) if executor is not None else None)
         h = ctypes.c_void_p()
         st = rel.lib().rel_server_create(ctypes.byref(self.config), ctypes.byref(h))

@@ -152,8 +152,9 @@ def query(data, lo, w, payload=True):
                     [("sum", 2), ("count", None)], 64)
 
 
-def make_server(ex, arena_bytes=1 << 30, max_slots=64, max_batch=8, lanes=2):
+def make_server(ex, arena_bytes=1 << 30, max_slots=64, max_batch=8, lanes=2, open_lane_at=0):
     return serve.Server(arena_bytes, max_slots=max_slots, max_batch=max_batch, lanes=lanes,
+                        open_lane_at=open_lane_at,
                         executor=ex.struct, arena_ptr=ARENA_BASE)
 
 
@@ -325,4 +326,21 @@ def test_replay_reports_latency_on_a_trace():
     srv.close()
     assert not ex.errors, ex.errors
     assert res["ok"] == 30 and res["p99_ms"] >= res["p50_ms"] >= 2.0 - 0.5
+    check_results(plans)
+
+
+def test_second_lane_opens_only_for_a_backlog():
+    """With a backlog threshold of 8 and one lane busy, a second starts only
+    when 8 queries wait: three queries never run on two lanes at once."""
+    data = star(5)
+    plans = [query(data, 60 * i, 300) for i in range(3)]
+    ex = OracleExecutor(plans, lanes=2, delay=0.01)
+    srv = make_server(ex, max_batch=8, lanes=2, open_lane_at=8)
+    for p in plans:
+        srv.submit(p)
+    got = wait_all(srv, len(plans))
+    srv.close()
+    assert not ex.errors, ex.errors
+    assert len(got) == 3 and all(c["status"] == 0 for c in got.values())
+    assert ex.max_active_lanes == 1
     check_results(plans)
