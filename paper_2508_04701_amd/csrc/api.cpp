@@ -243,8 +243,10 @@ rel_status group_plan(int nkeys, const int32_t* key_types, int naggs, const rel_
       default: gp.agg_acc[a] = -1; break;
     }
   }
+  // Not rounded to an even count: tables stay 1/(words + 1) smaller (fewer
+  // bytes to fill, scan and hold in LDS); an odd stride also spreads an LDS
+  // table over more banks, which measured neutral on the fused kernel.
   gp.words = 2 + gp.ap.nacc;
-  gp.words += gp.words & 1;
   return REL_OK;
 }
 
