@@ -299,10 +299,22 @@ def bench_ops(args, torch, datagen, rel) -> dict:
     k = kernel_ms(lambda: rel.hash_join_async(dev["build_key"], dev["probe_key"], ob, op, count, ws))
     pairs = int(count.item())
     res["hash_build"] = line(k["map_build"], 8 * nb, rows=nb,
-                             workload=f"{nb} unique int64 keys -> open-addressing table")
+                             workload=f"{nb} unique int64 keys -> open-addressing table "
+                                      "(partitioned: ranges built in LDS)")
     res["hash_probe"] = line(k["map_probe"], 8 * npr + 8 * pairs, rows=npr, pairs=pairs,
                              workload=f"{npr} Zipf(1) int64 probe keys -> (build, probe) row-id pairs")
     res["hash_join_fill_ms"] = k.get("fill", 0.0)
+    del ws
+    torch.cuda.empty_cache()
+    # the single-pass build (one device-scope CAS per key after filling the
+    # table) beside it
+    single = rel.tuning(fanout=-1)
+    ws = rel.workspace(rel.hash_join_ws(torch.int64, nb, single))
+    k = kernel_ms(lambda: rel.hash_join_async(dev["build_key"], dev["probe_key"], ob, op, count, ws,
+                                              t=single))
+    res["hash_build_single_pass"] = line(k["map_build"] + k.get("fill", 0.0), 8 * nb, rows=nb,
+                                         workload=f"{nb} unique int64 keys, table fill + one CAS "
+                                                  "per key")
     del ws, ob, op
     torch.cuda.empty_cache()
 
