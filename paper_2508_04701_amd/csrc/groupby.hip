@@ -151,16 +151,24 @@ __device__ __forceinline__ void finalize_range(const FinalizeParams& p, uint64_t
   const uint64_t nslots = g.kp.nkeys == 0 ? 1 : g.cap + 1;
   if (end > nslots) end = nslots;
   for (; chunk < end; chunk += stride) {
+    // the key words (COUNT for the out-of-band slot) of the thread's slots,
+    // loaded together; slots past the end read the chunk's first slot
+    uint64_t word[kFinalizeSlots];
+#pragma unroll
+    for (int j = 0; j < kFinalizeSlots; ++j) {
+      uint64_t i = chunk + static_cast<uint64_t>(j) * blockDim.x + threadIdx.x;
+      i = i < end ? i : chunk;
+      word[j] = g.slots[i * g.words + (i < g.cap ? 0 : 1)];
+    }
     uint32_t occ = 0;
 #pragma unroll
     for (int j = 0; j < kFinalizeSlots; ++j) {
       const uint64_t i = chunk + static_cast<uint64_t>(j) * blockDim.x + threadIdx.x;
       if (i >= end) continue;
-      const uint64_t* s = g.slots + i * g.words;
       bool o;
       if (g.kp.nkeys == 0) o = true;                 // the one ungrouped row
-      else if (i < g.cap) o = (s[0] != kEmpty64);
-      else o = (s[1] != 0);                          // out-of-band slot
+      else if (i < g.cap) o = (word[j] != kEmpty64);
+      else o = (word[j] != 0);                       // out-of-band slot
       occ |= o ? (1u << j) : 0u;
     }
     const uint32_t c = __popc(occ);
