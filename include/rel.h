@@ -117,10 +117,10 @@ typedef struct {
                             0 = default (64 when all groups fit the LDS tables, else 1) */
   int32_t fanout;        /* partitions of the radix-partitioned rel_groupby_agg and
                             rel_hash_join build, a power of two in [4, 16384]; 0 = default
-                            (partitioned when the group table or the join's slot array
-                            exceeds 64 MB: a group-by with as many partitions as keep each
-                            one's keys within an LDS table, a build with one partition per
-                            128 KB range of slots); -1 = never partition */
+                            (a group-by over at least 1M rows whose groups do not fit the
+                            single pass's LDS table, with as many partitions as keep each
+                            one's keys within an LDS table; a join whose slot array exceeds
+                            64 MB, one partition per 128 KB range of slots); -1 = never */
 } rel_tuning;
 
 /* rel_tuning.flags: keep dims of rel_pipeline in their hash tables even when

@@ -99,7 +99,13 @@ def test_workspace_sizes():
     single = L.rel_groupby_ws(1, k1, 2, aggs, n, g, ctypes.byref(off))
     part = L.rel_groupby_ws(1, k1, 2, aggs, n, g, None)
     assert part >= single + 2 * 16 * n
-    assert L.rel_groupby_ws(1, k1, 2, aggs, n, 1000, None) < 2 * 16 * n   # small tables: no buffers
+    # groups that fit the single pass's LDS table, or few rows: no buffers
+    assert L.rel_groupby_ws(1, k1, 2, aggs, n, 100, None) == \
+        L.rel_groupby_ws(1, k1, 2, aggs, n, 100, ctypes.byref(off))
+    assert L.rel_groupby_ws(1, k1, 2, aggs, 500_000, 10_000, None) == \
+        L.rel_groupby_ws(1, k1, 2, aggs, 500_000, 10_000, ctypes.byref(off))
+    # groups beyond it over many rows: partitioned
+    assert L.rel_groupby_ws(1, k1, 2, aggs, n, 10_000, None) >= 2 * 16 * n
     forced = rel.tuning(fanout=64)
     assert L.rel_groupby_ws(1, k1, 2, aggs, 1000, 100, ctypes.byref(forced)) >= 2 * 16 * 1000
     for bad in (3, 2, 100, 1 << 15, -2):
