@@ -262,8 +262,10 @@ constexpr int kGroupReplicas = 64;
 
 // Default LDS bytes for dim tables in the fused pipeline.
 constexpr size_t kDimLdsDefault = 32768;
-// Largest LDS group table of the fused pipeline.
+// Largest LDS group table of the fused pipeline, and the group count (in
+// multiples of its slots) beyond which the small default table is used.
 constexpr size_t kGroupLdsMax = 131072;
+constexpr int64_t kGroupLdsShare = 32;
 
 GroupLayout group_layout(const GroupPlan& gp, int64_t max_groups, float lf, size_t base,
                          int replicas = 1) {
@@ -474,8 +476,14 @@ rel_status pipeline_layout(const rel_pipeline_desc* d, PipeLayout& L, bool batch
   if (st) return st;
   // Up to kGroupLdsMax: rows of groups beyond the LDS table pay device-scope
   // atomics in the global table, which costs more than the occupancy a large
-  // table takes (measured on join + group-by instances of 1k-80k groups).
+  // table takes (measured on join + group-by instances of 1k-80k groups) -
+  // while the table holds a useful share of the groups. Beyond
+  // kGroupLdsShare times its slots (1M-group queries) the 16 KB table, at
+  // full occupancy, is faster.
   L.lds_slots = default_lds_slots(d->tuning, d->max_groups, L.gp.words, kGroupLdsMax);
+  if (!(d->tuning && d->tuning->lds_slots != 0) &&
+      d->max_groups > kGroupLdsShare * static_cast<int64_t>(L.lds_slots))
+    L.lds_slots = default_lds_slots(d->tuning, d->max_groups, L.gp.words, 16384);
   L.group = group_layout(L.gp, d->max_groups, lf, off,
                          group_replicas(d->tuning, d->max_groups, L.lds_slots, L.gp.words, lf));
   L.end = L.group.end;
