@@ -21,7 +21,10 @@
 // same global slots; a separate pass folds the replicas. Rows whose dim keys
 // match more than once
 // (duplicate dim keys) take a row-at-a-time path that enumerates every
-// combination.
+// combination. Plans whose dims all resolved to direct tables (dense unique
+// keys, decided by the builds on the device) run a twin kernel with a leaner
+// drain; each of the two kernels returns at once when the plan is the
+// other's.
 
 #pragma once
 
@@ -550,6 +553,44 @@ __device__ __forceinline__ int probe_examine(const PipeDim& d, int64_t key, uint
   }
 }
 
+// Adds row r to group pk (va, vb: the early-gathered value columns): one
+// branch per row, the workgroup's LDS table or its global replica.
+__device__ __forceinline__ void update_group(const PipelineParams& p, int64_t r, uint64_t pk,
+                                             int64_t va, int64_t vb, uint64_t* lg,
+                                             const GroupTable& gt) {
+  const int words = p.g.words;
+  const int32_t li = lds_group_find(lg, p.lds_slots, words, pk);
+  if (li >= 0) {
+    uint64_t* s = lg + li * words;
+    lds_add_u64(s + 1, 1);
+    for (int a = 0; a < p.g.ap.nacc; ++a) {
+      const int src = p.acc_src[a];
+      const int64_t v = src == 0 ? va
+                      : src == 1 ? vb
+                                 : load_elem(p.fact[p.acc_col[a]], p.fact_type[p.acc_col[a]], r);
+      lds_acc_update(s + 2 + a, p.g.ap.kind[a], v);
+    }
+  } else {
+    uint64_t* gs = group_slot(gt, pk);
+    if (!gs) return;
+    global_add_u64(gs + 1, 1);
+    for (int a = 0; a < p.g.ap.nacc; ++a) {
+      const int src = p.acc_src[a];
+      const int64_t v = src == 0 ? va
+                      : src == 1 ? vb
+                                 : load_elem(p.fact[p.acc_col[a]], p.fact_type[p.acc_col[a]], r);
+      const int kind = p.g.ap.kind[a];
+      uint64_t* w = gs + 2 + a;
+      if (kind == kAccSum)
+        atomicAdd(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(v));
+      else if (kind == kAccMin)
+        atomicMin(reinterpret_cast<long long*>(w), static_cast<long long>(v));
+      else
+        atomicMax(reinterpret_cast<long long*>(w), static_cast<long long>(v));
+    }
+  }
+}
+
 // One queued row: probe the dims and update the row's group. Returns true
 // when the row has to go back to the queue (a resumable probe continues).
 template <int D0, int D1>
@@ -610,39 +651,7 @@ __device__ __forceinline__ bool process_row(const PipelineParams& p, int64_t r, 
   if (multi) return false;  // several dim matches: left to the enumeration pass
   if (p.g.kp.nkeys > 0 && p.key_src[0] != 0) k0 = static_cast<int32_t>(p.key_src[0] == 1 ? v0 : v1);
   if (p.g.kp.nkeys > 1 && p.key_src[1] != 0) k1 = static_cast<int32_t>(p.key_src[1] == 1 ? v0 : v1);
-  const uint64_t pk = pack_keys(p.g.kp, k0, k1);
-  const int words = p.g.words;
-  const int32_t li = lds_group_find(lg, p.lds_slots, words, pk);
-  // One branch per row: the workgroup's LDS table, or its global replica.
-  if (li >= 0) {
-    uint64_t* s = lg + li * words;
-    lds_add_u64(s + 1, 1);
-    for (int a = 0; a < p.g.ap.nacc; ++a) {
-      const int src = p.acc_src[a];
-      const int64_t v = src == 0 ? va
-                      : src == 1 ? vb
-                                 : load_elem(p.fact[p.acc_col[a]], p.fact_type[p.acc_col[a]], r);
-      lds_acc_update(s + 2 + a, p.g.ap.kind[a], v);
-    }
-  } else {
-    uint64_t* gs = group_slot(gt, pk);
-    if (!gs) return false;
-    global_add_u64(gs + 1, 1);
-    for (int a = 0; a < p.g.ap.nacc; ++a) {
-      const int src = p.acc_src[a];
-      const int64_t v = src == 0 ? va
-                      : src == 1 ? vb
-                                 : load_elem(p.fact[p.acc_col[a]], p.fact_type[p.acc_col[a]], r);
-      const int kind = p.g.ap.kind[a];
-      uint64_t* w = gs + 2 + a;
-      if (kind == kAccSum)
-        atomicAdd(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(v));
-      else if (kind == kAccMin)
-        atomicMin(reinterpret_cast<long long*>(w), static_cast<long long>(v));
-      else
-        atomicMax(reinterpret_cast<long long*>(w), static_cast<long long>(v));
-    }
-  }
+  update_group(p, r, pack_keys(p.g.kp, k0, k1), va, vb, lg, gt);
   return false;
 }
 
@@ -692,11 +701,62 @@ __device__ __forceinline__ uint32_t drain(const PipelineParams& p, unsigned char
   return base + popc64(b);
 }
 
+// ------------------------------------------------------ direct dims
+//
+// When every dim of the plan resolved to a direct table at build time (dense
+// unique int32 keys), a probe is a range test plus at most a bit and a payload
+// read at computed addresses: no bucket walks, no row returns to the queue,
+// no probe states. run_tiles then takes a leaner drain whose queue entries
+// are the row id and the foreign keys only, which keeps the loop within its
+// register budget.
+
+template <int D>
+constexpr bool kDirectOk = D == kNone || kDirectable<D>;
+
+template <int D0, int D1>
+__device__ __forceinline__ void direct_row(const PipelineParams& p, int64_t r, int64_t fk0,
+                                           int64_t fk1, uint64_t* lg, const GroupTable& gt,
+                                           const DirectView& dv0, const DirectView& dv1) {
+  int64_t k0 = 0, k1 = 0;
+  if (p.g.kp.nkeys > 0 && p.key_src[0] == 0)
+    k0 = load_elem(p.fact[p.key_col[0]], p.fact_type[p.key_col[0]], r);
+  if (p.g.kp.nkeys > 1 && p.key_src[1] == 0)
+    k1 = load_elem(p.fact[p.key_col[1]], p.fact_type[p.key_col[1]], r);
+  int64_t va = 0, vb = 0;
+  if (p.early_col[0] >= 0) va = load_elem(p.fact[p.early_col[0]], p.fact_type[p.early_col[0]], r);
+  if (p.early_col[1] >= 0) vb = load_elem(p.fact[p.early_col[1]], p.fact_type[p.early_col[1]], r);
+  uint32_t v0 = 0, v1 = 0;
+  if constexpr (D0 != kNone)
+    if (!direct_probe(dv0, fk0, v0)) return;
+  if constexpr (D1 != kNone)
+    if (!direct_probe(dv1, fk1, v1)) return;
+  if (p.g.kp.nkeys > 0 && p.key_src[0] != 0) k0 = static_cast<int32_t>(p.key_src[0] == 1 ? v0 : v1);
+  if (p.g.kp.nkeys > 1 && p.key_src[1] != 0) k1 = static_cast<int32_t>(p.key_src[1] == 1 ? v0 : v1);
+  update_group(p, r, pack_keys(p.g.kp, k0, k1), va, vb, lg, gt);
+}
+
+// Processes queue entries [base, base + take), take <= 64, one per lane.
+template <int D0, int D1>
+__device__ __forceinline__ void drain_direct(const PipelineParams& p, const unsigned char* wq,
+                                             uint32_t base, uint32_t take, int lane,
+                                             uint64_t* lg, const GroupTable& gt,
+                                             const DirectView& dv0, const DirectView& dv1) {
+  if (static_cast<uint32_t>(lane) < take) {
+    const uint32_t i = base + lane;
+    const int64_t r = static_cast<uint32_t>(qget<D0, D1, kQRow>(wq, i));
+    int64_t fk0 = 0, fk1 = 0;
+    if constexpr (D0 != kNone) fk0 = qget<D0, D1, kQFk0>(wq, i);
+    if constexpr (D1 != kNone) fk1 = qget<D0, D1, kQFk1>(wq, i);
+    direct_row<D0, D1>(p, r, fk0, fk1, lg, gt, dv0, dv1);
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Walks tiles `tile`, `tile + step`, ... below `end` of plan p: streams the
 // predicate column (two tiles ahead) and the foreign keys, queues the passing
 // rows per wave and drains them in full-lane batches. Returns with the
 // wave's queue empty.
-template <int D0, int D1>
+template <int D0, int D1, bool kDirect>
 __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile, int64_t end,
                                           int64_t step, unsigned char* wq, int lane,
                                           const void* ld0, const void* ld1, uint64_t* lg,
@@ -753,24 +813,36 @@ __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile,
         qput<D0, D1, kQRow>(wq, at, r0 + e);
         if constexpr (D0 != kNone) {
           qput<D0, D1, kQFk0>(wq, at, fk0[e]);
-          qput<D0, D1, kQSt0>(wq, at, 0);
+          if constexpr (!kDirect) qput<D0, D1, kQSt0>(wq, at, 0);
         }
         if constexpr (D1 != kNone) {
           qput<D0, D1, kQFk1>(wq, at, fk1[e]);
-          qput<D0, D1, kQSt1>(wq, at, 0);
+          if constexpr (!kDirect) qput<D0, D1, kQSt1>(wq, at, 0);
         }
       }
       queued += popc64(b);
       __builtin_amdgcn_wave_barrier();
-      while (queued >= kWave)
-        queued = drain<D0, D1>(p, wq, queued, kWave, lane, ld0, ld1, lg, gt, limit0, limit1, dv0,
-                               dv1);
+      if constexpr (kDirect) {
+        // at most 127 rows are queued here: one batch leaves fewer than 64
+        if (queued >= kWave) {
+          queued -= kWave;
+          drain_direct<D0, D1>(p, wq, queued, kWave, lane, lg, gt, dv0, dv1);
+        }
+      } else {
+        while (queued >= kWave)
+          queued = drain<D0, D1>(p, wq, queued, kWave, lane, ld0, ld1, lg, gt, limit0, limit1,
+                                 dv0, dv1);
+      }
     }
   }
   __builtin_amdgcn_wave_barrier();
-  while (queued > 0)
-    queued = drain<D0, D1>(p, wq, queued, queued < kWave ? queued : kWave, lane, ld0, ld1, lg, gt,
-                           limit0, limit1, dv0, dv1);
+  if constexpr (kDirect) {
+    if (queued > 0) drain_direct<D0, D1>(p, wq, 0, queued, lane, lg, gt, dv0, dv1);
+  } else {
+    while (queued > 0)
+      queued = drain<D0, D1>(p, wq, queued, queued < kWave ? queued : kWave, lane, ld0, ld1, lg,
+                             gt, limit0, limit1, dv0, dv1);
+  }
 }
 
 // Dims built without duplicate keys stop probing at the first match.
@@ -778,6 +850,21 @@ template <int D>
 __device__ __forceinline__ int match_limit(const PipeDim& d) {
   if constexpr (D == kNone) return 1;
   else return *d.map.dup ? 2 : 1;
+}
+
+// Whether every dim of plan p resolved to a direct table (a plan without
+// dims qualifies); read by each workgroup from the builds' state.
+template <int D0, int D1>
+__device__ __forceinline__ bool all_direct(const PipelineParams& p) {
+  if constexpr (!kDirectOk<D0> || !kDirectOk<D1>) {
+    return false;
+  } else {
+    if constexpr (D0 != kNone)
+      if (!dim_direct<D0>(p.dim[0]).mode) return false;
+    if constexpr (D1 != kNone)
+      if (!dim_direct<D1>(p.dim[1]).mode) return false;
+    return true;
+  }
 }
 
 // Eight waves per SIMD (four resident workgroups per CU) where the variant
@@ -789,6 +876,7 @@ constexpr int kFusedWaves = (D1 == kMapLds || D1 == kSetLds || D1 == kMap64) ? 1
 template <int D0, int D1>
 __global__ void __launch_bounds__(kPipeThreads)
 __attribute__((amdgpu_waves_per_eu(kFusedWaves<D0, D1>))) fused_kernel(PipelineParams p) {
+  if (all_direct<D0, D1>(p)) return;  // fused_direct_kernel's case
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   void* ld0 = lds + p.dim[0].lds_offset;
   void* ld1 = lds + p.dim[1].lds_offset;
@@ -800,8 +888,28 @@ __attribute__((amdgpu_waves_per_eu(kFusedWaves<D0, D1>))) fused_kernel(PipelineP
   if (p.lds_slots > 0) lds_group_init(lg, p.lds_slots, p.g);
   __syncthreads();
   const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
-  run_tiles<D0, D1>(p, blockIdx.x, p.ntiles, gridDim.x, wq, lane, ld0, ld1, lg, gt,
-                    match_limit<D0>(p.dim[0]), match_limit<D1>(p.dim[1]));
+  run_tiles<D0, D1, false>(p, blockIdx.x, p.ntiles, gridDim.x, wq, lane, ld0, ld1, lg, gt,
+                           match_limit<D0>(p.dim[0]), match_limit<D1>(p.dim[1]));
+  if (p.lds_slots == 0) return;
+  __syncthreads();
+  lds_group_flush(lg, p.lds_slots, p.g);
+}
+
+// The same plan when all_direct holds (fused_kernel then returns at once):
+// its own kernel, so that the lean loop gets its own register allocation.
+template <int D0, int D1>
+__global__ void __launch_bounds__(kPipeThreads)
+__attribute__((amdgpu_waves_per_eu(8))) fused_direct_kernel(PipelineParams p) {
+  if (!all_direct<D0, D1>(p)) return;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  uint64_t* lg = reinterpret_cast<uint64_t*>(lds + p.lds_group_offset);
+  const int lane = lane_id();
+  unsigned char* wq = lds + p.queue_offset + (threadIdx.x / kWave) * p.queue_stride;
+  if (p.lds_slots > 0) lds_group_init(lg, p.lds_slots, p.g);
+  __syncthreads();
+  const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
+  run_tiles<D0, D1, true>(p, blockIdx.x, p.ntiles, gridDim.x, wq, lane, nullptr, nullptr, lg, gt,
+                          1, 1);
   if (p.lds_slots == 0) return;
   __syncthreads();
   lds_group_flush(lg, p.lds_slots, p.g);
@@ -899,21 +1007,19 @@ hipError_t launch_multi(const PipelineParams& p, hipStream_t s) {
   }
 }
 
-// grid <= 0 sizes the persistent grid to the workgroups that can be resident
-// at once (registers and LDS of this variant), capped by the tile count.
-// Returns the first failing HIP status.
-template <int D0, int D1>
-hipError_t launch_fused(const PipelineParams& p, int grid, hipStream_t s) {
-  auto k = fused_kernel<D0, D1>;
-  static int max_dynamic = -1;
+// grid <= 0 sizes the persistent grid of kernel k to the workgroups that can
+// be resident at once (registers and LDS), capped by the tile count.
+// `max_dynamic` caches the kernel's dynamic LDS limit (set on first use).
+inline hipError_t launch_persistent(const void* k, const PipelineParams& p, int grid,
+                                    int& max_dynamic, hipStream_t s) {
   if (max_dynamic < 0) {
     hipFuncAttributes attr;
-    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(k));
+    hipError_t e = hipFuncGetAttributes(&attr, k);
     if (e != hipSuccess) return e;
-    max_dynamic = device_info().lds_per_block - static_cast<int>(attr.sharedSizeBytes);
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, max_dynamic);
+    const int dyn = device_info().lds_per_block - static_cast<int>(attr.sharedSizeBytes);
+    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     if (e != hipSuccess) return e;
+    max_dynamic = dyn;
   }
   if (static_cast<int>(p.lds_bytes) > max_dynamic) return hipErrorInvalidValue;
   if (grid <= 0) {
@@ -928,9 +1034,27 @@ hipError_t launch_fused(const PipelineParams& p, int grid, hipStream_t s) {
     grid = static_cast<int>(g < 1 ? 1 : g);
   }
   if (grid > kMaxPipeGrid) grid = kMaxPipeGrid;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(kPipeThreads), p.lds_bytes, s, p);
-  const hipError_t e = hipGetLastError();
+  void* args[] = {const_cast<PipelineParams*>(&p)};
+  hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(kPipeThreads), args, p.lds_bytes, s);
   if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+// Launches the fused kernel, its direct-table twin where the dim modes allow
+// one (exactly one of the two does the work, decided on the device from the
+// builds), and the duplicate-key pass. Returns the first failing HIP status.
+template <int D0, int D1>
+hipError_t launch_fused(const PipelineParams& p, int grid, hipStream_t s) {
+  static int max_general = -1;
+  hipError_t e = launch_persistent(reinterpret_cast<const void*>(fused_kernel<D0, D1>), p, grid,
+                                   max_general, s);
+  if (e != hipSuccess) return e;
+  if constexpr (kDirectOk<D0> && kDirectOk<D1>) {
+    static int max_direct = -1;
+    e = launch_persistent(reinterpret_cast<const void*>(fused_direct_kernel<D0, D1>), p, grid,
+                          max_direct, s);
+    if (e != hipSuccess) return e;
+  }
   return launch_multi<D0, D1>(p, s);
 }
 
@@ -964,8 +1088,8 @@ __attribute__((amdgpu_waves_per_eu(kBatchWaves<D0, D1>))) batch_fused_kernel(Bat
     if (p.lds_slots > 0) lds_group_init(lg, p.lds_slots, p.g);
     __syncthreads();
     const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
-    run_tiles<D0, D1>(p, it.begin, it.end, 1, wq, lane, nullptr, nullptr, lg, gt,
-                      match_limit<D0>(p.dim[0]), match_limit<D1>(p.dim[1]));
+    run_tiles<D0, D1, false>(p, it.begin, it.end, 1, wq, lane, nullptr, nullptr, lg, gt,
+                             match_limit<D0>(p.dim[0]), match_limit<D1>(p.dim[1]));
     __syncthreads();
     if (p.lds_slots > 0) {
       lds_group_flush(lg, p.lds_slots, p.g);
