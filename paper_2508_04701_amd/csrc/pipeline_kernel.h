@@ -553,33 +553,53 @@ __device__ __forceinline__ int probe_examine(const PipeDim& d, int64_t key, uint
   }
 }
 
-// Adds row r to group pk (va, vb: the early-gathered value columns): one
-// branch per row, the workgroup's LDS table or its global replica.
+// The plan's accumulators packed four bits each, first in the low bits: one
+// plus (kind | source << 2), the source 0 or 1 for the early-gathered columns
+// and 2 for a late load; a zero field ends the list. Computed once per
+// workgroup, so that the update loop reads no memory between its atomics (a
+// scalar load there also waits on the LDS counter, which serialised the
+// atomics of a row).
+__device__ __forceinline__ uint32_t acc_code(const PipelineParams& p) {
+  uint32_t c = 0;
+  for (int a = 0; a < p.g.ap.nacc; ++a) {
+    const uint32_t src = p.acc_src[a] == 0 ? 0u : (p.acc_src[a] == 1 ? 1u : 2u);
+    c |= (1u + (static_cast<uint32_t>(p.g.ap.kind[a]) | (src << 2))) << (4 * a);
+  }
+  return c;
+}
+
+// Adds row r to group pk (va, vb: the early-gathered value columns; acode:
+// acc_code(p)): one branch per row, the workgroup's LDS table or its global
+// replica.
 __device__ __forceinline__ void update_group(const PipelineParams& p, int64_t r, uint64_t pk,
                                              int64_t va, int64_t vb, uint64_t* lg,
-                                             const GroupTable& gt) {
+                                             const GroupTable& gt, uint32_t acode) {
   const int words = p.g.words;
   const int32_t li = lds_group_find(lg, p.lds_slots, words, pk);
   if (li >= 0) {
     uint64_t* s = lg + li * words;
     lds_add_u64(s + 1, 1);
-    for (int a = 0; a < p.g.ap.nacc; ++a) {
-      const int src = p.acc_src[a];
+    int a = 0;
+    for (uint32_t code = acode; code != 0; code >>= 4, ++a) {
+      const uint32_t c = (code & 15u) - 1u;
+      const uint32_t src = c >> 2;
       const int64_t v = src == 0 ? va
                       : src == 1 ? vb
                                  : load_elem(p.fact[p.acc_col[a]], p.fact_type[p.acc_col[a]], r);
-      lds_acc_update(s + 2 + a, p.g.ap.kind[a], v);
+      lds_acc_update(s + 2 + a, static_cast<int>(c & 3u), v);
     }
   } else {
     uint64_t* gs = group_slot(gt, pk);
     if (!gs) return;
     global_add_u64(gs + 1, 1);
-    for (int a = 0; a < p.g.ap.nacc; ++a) {
-      const int src = p.acc_src[a];
+    int a = 0;
+    for (uint32_t code = acode; code != 0; code >>= 4, ++a) {
+      const uint32_t c = (code & 15u) - 1u;
+      const uint32_t src = c >> 2;
       const int64_t v = src == 0 ? va
                       : src == 1 ? vb
                                  : load_elem(p.fact[p.acc_col[a]], p.fact_type[p.acc_col[a]], r);
-      const int kind = p.g.ap.kind[a];
+      const int kind = static_cast<int>(c & 3u);
       uint64_t* w = gs + 2 + a;
       if (kind == kAccSum)
         atomicAdd(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(v));
@@ -598,7 +618,8 @@ __device__ __forceinline__ bool process_row(const PipelineParams& p, int64_t r, 
                                             int64_t fk1, uint32_t& st0, uint32_t& st1,
                                             const void* ld0, const void* ld1, uint64_t* lg,
                                             const GroupTable& gt, int limit0, int limit1,
-                                            const DirectView& dv0, const DirectView& dv1) {
+                                            const DirectView& dv0, const DirectView& dv1,
+                                            uint32_t acode) {
   const bool dir0 = kDirectable<D0> && dv0.mode != 0;
   const bool dir1 = kDirectable<D1> && dv1.mode != 0;
   const bool res0 = kResumable<D0> && limit0 == 1;
@@ -651,7 +672,7 @@ __device__ __forceinline__ bool process_row(const PipelineParams& p, int64_t r, 
   if (multi) return false;  // several dim matches: left to the enumeration pass
   if (p.g.kp.nkeys > 0 && p.key_src[0] != 0) k0 = static_cast<int32_t>(p.key_src[0] == 1 ? v0 : v1);
   if (p.g.kp.nkeys > 1 && p.key_src[1] != 0) k1 = static_cast<int32_t>(p.key_src[1] == 1 ? v0 : v1);
-  update_group(p, r, pack_keys(p.g.kp, k0, k1), va, vb, lg, gt);
+  update_group(p, r, pack_keys(p.g.kp, k0, k1), va, vb, lg, gt, acode);
   return false;
 }
 
@@ -662,7 +683,8 @@ __device__ __forceinline__ uint32_t drain(const PipelineParams& p, unsigned char
                                           uint32_t queued, uint32_t take, int lane,
                                           const void* ld0, const void* ld1, uint64_t* lg,
                                           const GroupTable& gt, int limit0, int limit1,
-                                          const DirectView& dv0, const DirectView& dv1) {
+                                          const DirectView& dv0, const DirectView& dv1,
+                                          uint32_t acode) {
   const uint32_t base = queued - take;
   const bool mine = static_cast<uint32_t>(lane) < take;
   int64_t r = 0, fk0 = 0, fk1 = 0;
@@ -683,7 +705,7 @@ __device__ __forceinline__ uint32_t drain(const PipelineParams& p, unsigned char
   bool again = false;
   if (mine)
     again = process_row<D0, D1>(p, r, fk0, fk1, st0, st1, ld0, ld1, lg, gt, limit0, limit1, dv0,
-                                dv1);
+                                dv1, acode);
   const uint64_t b = ballot(again);
   if (again) {
     const uint32_t at = base + rank_below(b);
@@ -716,7 +738,8 @@ constexpr bool kDirectOk = D == kNone || kDirectable<D>;
 template <int D0, int D1>
 __device__ __forceinline__ void direct_row(const PipelineParams& p, int64_t r, int64_t fk0,
                                            int64_t fk1, uint64_t* lg, const GroupTable& gt,
-                                           const DirectView& dv0, const DirectView& dv1) {
+                                           const DirectView& dv0, const DirectView& dv1,
+                                           uint32_t acode) {
   int64_t k0 = 0, k1 = 0;
   if (p.g.kp.nkeys > 0 && p.key_src[0] == 0)
     k0 = load_elem(p.fact[p.key_col[0]], p.fact_type[p.key_col[0]], r);
@@ -732,7 +755,7 @@ __device__ __forceinline__ void direct_row(const PipelineParams& p, int64_t r, i
     if (!direct_probe(dv1, fk1, v1)) return;
   if (p.g.kp.nkeys > 0 && p.key_src[0] != 0) k0 = static_cast<int32_t>(p.key_src[0] == 1 ? v0 : v1);
   if (p.g.kp.nkeys > 1 && p.key_src[1] != 0) k1 = static_cast<int32_t>(p.key_src[1] == 1 ? v0 : v1);
-  update_group(p, r, pack_keys(p.g.kp, k0, k1), va, vb, lg, gt);
+  update_group(p, r, pack_keys(p.g.kp, k0, k1), va, vb, lg, gt, acode);
 }
 
 // Processes queue entries [base, base + take), take <= 64, one per lane.
@@ -740,14 +763,15 @@ template <int D0, int D1>
 __device__ __forceinline__ void drain_direct(const PipelineParams& p, const unsigned char* wq,
                                              uint32_t base, uint32_t take, int lane,
                                              uint64_t* lg, const GroupTable& gt,
-                                             const DirectView& dv0, const DirectView& dv1) {
+                                             const DirectView& dv0, const DirectView& dv1,
+                                             uint32_t acode) {
   if (static_cast<uint32_t>(lane) < take) {
     const uint32_t i = base + lane;
     const int64_t r = static_cast<uint32_t>(qget<D0, D1, kQRow>(wq, i));
     int64_t fk0 = 0, fk1 = 0;
     if constexpr (D0 != kNone) fk0 = qget<D0, D1, kQFk0>(wq, i);
     if constexpr (D1 != kNone) fk1 = qget<D0, D1, kQFk1>(wq, i);
-    direct_row<D0, D1>(p, r, fk0, fk1, lg, gt, dv0, dv1);
+    direct_row<D0, D1>(p, r, fk0, fk1, lg, gt, dv0, dv1, acode);
   }
   __builtin_amdgcn_wave_barrier();
 }
@@ -763,6 +787,7 @@ __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile,
                                           const GroupTable& gt, int limit0, int limit1) {
   const DirectView dv0 = dim_direct<D0>(p.dim[0]);
   const DirectView dv1 = dim_direct<D1>(p.dim[1]);
+  const uint32_t acode = acc_code(p);
   const int tid = threadIdx.x;
   // The first term's column is read two tiles ahead when its rows are at
   // most four bytes wide (held as int32; an int64 column is read in place),
@@ -826,22 +851,22 @@ __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile,
         // at most 127 rows are queued here: one batch leaves fewer than 64
         if (queued >= kWave) {
           queued -= kWave;
-          drain_direct<D0, D1>(p, wq, queued, kWave, lane, lg, gt, dv0, dv1);
+          drain_direct<D0, D1>(p, wq, queued, kWave, lane, lg, gt, dv0, dv1, acode);
         }
       } else {
         while (queued >= kWave)
           queued = drain<D0, D1>(p, wq, queued, kWave, lane, ld0, ld1, lg, gt, limit0, limit1,
-                                 dv0, dv1);
+                                 dv0, dv1, acode);
       }
     }
   }
   __builtin_amdgcn_wave_barrier();
   if constexpr (kDirect) {
-    if (queued > 0) drain_direct<D0, D1>(p, wq, 0, queued, lane, lg, gt, dv0, dv1);
+    if (queued > 0) drain_direct<D0, D1>(p, wq, 0, queued, lane, lg, gt, dv0, dv1, acode);
   } else {
     while (queued > 0)
       queued = drain<D0, D1>(p, wq, queued, queued < kWave ? queued : kWave, lane, ld0, ld1, lg,
-                             gt, limit0, limit1, dv0, dv1);
+                             gt, limit0, limit1, dv0, dv1, acode);
   }
 }
 
