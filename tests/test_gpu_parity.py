@@ -492,6 +492,37 @@ def test_pipeline_shapes():
         assert_groups(got, want, aggs, name)
 
 
+@pytest.mark.parametrize("direct", [True, False])
+def test_pipeline_many_accumulators(direct):
+    """Eight accumulators over four value columns of three widths through the
+    fused pipeline: the first two distinct value columns are gathered with
+    the keys, the other two loaded late, and the update loop walks the whole
+    packed accumulator plan. With dense dim keys the direct-table kernel does
+    the work, with direct tables switched off the general one (HBM map)."""
+    announce("pipeline many accumulators", direct)
+    r = rng(31 if direct else 32)
+    n = 70_001
+    key = r.permutation(5_000).astype(np.int32)
+    pay = r.integers(0, 40, size=5_000).astype(np.int32)
+    fk = r.integers(-100, 5_100, size=n).astype(np.int32)
+    v0 = col_with_extremes(r, n, np.int64, -10**12, 10**12, 0.01)
+    v1 = col_with_extremes(r, n, np.int32, -10**6, 10**6, 0.01)
+    v2 = r.integers(-128, 128, size=n).astype(np.int8)
+    v3 = col_with_extremes(r, n, np.int64, -10**9, 10**9, 0.01)
+    flag = r.integers(0, 3, size=n).astype(np.int8)
+    fact = [fk, v0, v1, v2, v3, flag]
+    dims = [dict(fk=0, key=key, payload=pay)]
+    # eight aggregates, eight accumulators (AVG adds the sum of its column;
+    # the row count is always kept)
+    aggs = [("sum", 1), ("min", 2), ("max", 3), ("sum", 4), ("max", 1), ("min", 4), ("sum", 3),
+            ("avg", 2)]
+    keys = [("dim", 0), ("fact", 5)]
+    terms = [(5, "lt", 2)]
+    t = rel.tuning(dim_lds_bytes=-1, flags=0 if direct else rel.TUNE_NO_DIRECT)
+    got, want = run_both(fact, terms, dims, keys, aggs, max_groups=256, t=t)
+    assert_groups(got, want, aggs, f"many accumulators direct={direct}")
+
+
 def test_pipeline_int64_dim_keys():
     announce("pipeline int64 dims")
     d = datagen.skewed(n_build=20_000, n_probe=200_000, n_groups=500)
