@@ -39,9 +39,10 @@ TERMS = [(2, "lt", 767)]
 KEYS = [("dim", 1), ("fact", 4)]
 
 
-# Sources that define the fused kernel; a traffic figure taken with
-# rocprofv3 counters is reported only while they are unchanged.
-KERNEL_SOURCES = ["device.h", "internal.h", "group_lds.h", "pipeline_kernel.h", "pipeline.hip"]
+# Sources that define the fused kernel and its launch configuration; a
+# traffic figure taken with rocprofv3 counters is reported only while they
+# are unchanged.
+KERNEL_SOURCES = ["device.h", "internal.h", "group_lds.h", "pipeline_kernel.h", "pipeline.hip", "api.cpp"]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pipeline_fused_star600m.json")
 
 

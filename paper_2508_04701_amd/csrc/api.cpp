@@ -522,10 +522,7 @@ void plan_params(const rel_pipeline_desc* d, const PipeLayout& L, unsigned char*
   // (smaller dims first).
   const size_t budget = static_cast<size_t>(di.lds_per_block);
   p.lds_slots = L.lds_slots;
-  size_t lds = 0;
-  p.lds_group_offset = 0;
-  lds += static_cast<size_t>(p.lds_slots) * L.gp.words * 8;
-  lds = (lds + 15) / 16 * 16;
+  uint32_t stride = 0;  // bytes of one wave's row queue
   {
     // queued row fields: width 8 for int64 columns, else 4
     bool present[kQueueFields] = {};
@@ -551,16 +548,34 @@ void plan_params(const rel_pipeline_desc* d, const PipeLayout& L, unsigned char*
       }
     }
     for (int k = 0; k < 2; ++k) p.early_col[k] = early[k];
-    uint32_t stride = 0;
     for (int f = 0; f < kQueueFields; ++f) {
       p.field_offset[f] = stride;
       p.field_wide[f] = wide[f] ? 1 : 0;
       if (present[f]) stride += kPipeQueue * (wide[f] ? 8 : 4);
     }
-    p.queue_offset = static_cast<uint32_t>(lds);
-    p.queue_stride = stride;
-    lds += static_cast<size_t>(kPipeThreads / kWave) * stride;
   }
+  const size_t queues = static_cast<size_t>(kPipeThreads / kWave) * stride;
+  // A single plan's group table grows up to four slots per group while the
+  // table and the queues stay within the LDS share of a workgroup at full
+  // occupancy (four workgroups of eight waves per CU): shorter hash runs at
+  // no cost in resident waves (75 groups in 512 instead of 256 slots: the
+  // star-schema plan's fused pass 2.66 -> 2.51 ms; at 1024 slots only two
+  // workgroups fit and it takes 3.6 ms). Batched plans keep their LDS
+  // classes.
+  constexpr int kFusedBlocksPerCu = 4;
+  if (!batch && !(t && t->lds_slots != 0) && p.lds_slots > 0) {
+    const size_t share = budget / kFusedBlocksPerCu;
+    while (static_cast<int64_t>(p.lds_slots) * 2 <= 4 * d->max_groups &&
+           static_cast<size_t>(p.lds_slots) * 2 * L.gp.words * 8 + queues <= share)
+      p.lds_slots *= 2;
+  }
+  size_t lds = 0;
+  p.lds_group_offset = 0;
+  lds += static_cast<size_t>(p.lds_slots) * L.gp.words * 8;
+  lds = (lds + 15) / 16 * 16;
+  p.queue_offset = static_cast<uint32_t>(lds);
+  p.queue_stride = stride;
+  lds += queues;
   // Dim tables go to LDS only when small: a large LDS copy costs resident
   // workgroups, and occupancy is what hides the probe latency.
   const size_t avail = budget > lds ? budget - lds : 0;
