@@ -8,12 +8,16 @@ in {0, 1, 2}), filter date < 767 (about 30% of rows), inner join with both
 dims, group by (dim B region over 25 values, flag), SUM/COUNT/AVG/MIN/MAX of
 price. One step is one rel_pipeline call: build both dim hash tables, the
 fused filter-probe-aggregate pass over the fact table, and the group
-finalize. Inputs are generated (seeded, synthetic) and resident in HBM before
-timing starts.
+finalize. The headline keeps both dims in open-addressing hash tables
+(REL_TUNE_NO_DIRECT); the same plan with the dense dim keys in direct tables
+is reported beside it. Inputs are generated (seeded, synthetic) and resident
+in HBM before timing starts.
 
 Prints one JSON line: input rows/s over the whole step, the roofline of the
-dominant kernel (the fused pass) from HIP events on its launch stream, and
-the single-threaded CPU oracle timed on a bounded sample of the same rows.
+dominant kernel (the fused pass) from HIP events on its launch stream, the
+streaming-read ceiling measured in the same run, and the single-threaded CPU
+oracle timed on a bounded sample of the same rows; then the small join +
+group-by as latency, batches, serving and the standalone operators.
 """
 
 from __future__ import annotations
@@ -43,7 +47,8 @@ KEYS = [("dim", 1), ("fact", 4)]
 # traffic figure taken with rocprofv3 counters is reported only while they
 # are unchanged.
 KERNEL_SOURCES = ["device.h", "internal.h", "group_lds.h", "pipeline_kernel.h", "pipeline.hip", "api.cpp"]
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pipeline_fused_star600m.json")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pipeline_fused_hash_star600m.json")
+TRAFFIC_PROFILE_DIRECT = os.path.join(ROOT, "profiles", "pipeline_fused_star600m.json")
 
 
 def log(*a):
@@ -59,18 +64,132 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(n: int):
+def measured_traffic(n: int, path: str):
     """HBM bytes per launch of the fused kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size),
-    or None if it was taken on other kernel sources or another size."""
+    summary at `path` (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of
+    known size), or None if it was taken on other kernel sources or another
+    size."""
     try:
-        with open(TRAFFIC_PROFILE) as f:
+        with open(path) as f:
             prof = json.load(f)
     except (OSError, ValueError):
         return None
     if prof.get("kernel_sources_sha256") != kernel_sources_sha256() or prof.get("fact_rows") != n:
         return None
     return prof["fetch_bytes"] + prof["write_bytes"]
+
+
+def star_run(args, torch, rel, fact, dims, t) -> dict:
+    """Times the star-schema step (dim builds, fused pass, merge, finalize)
+    with HIP events over args.steps launches; the fused kernel class from the
+    library's per-kernel events on its launch stream."""
+    plan = rel.PreparedPipeline(fact, TERMS, dims, KEYS, AGGS, max_groups=128, t=t)
+    for _ in range(args.warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    keys, aggs = plan.result()
+    o = torch.argsort(keys[0].long() * 4 + keys[1].long())
+    result = [keys[0][o], keys[1][o]] + [a[o] for a in aggs]
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rel.profile_read()
+    rel.profile_enable(True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        plan.launch()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    rel.profile_enable(False)
+    prof = rel.profile_read()
+    fused_ms, fused_n = prof["pipeline_fused"]
+    del plan
+    return {"ms_per_step": start.elapsed_time(stop) / args.steps,
+            "fused_kernel_ms": fused_ms / max(1, fused_n), "groups": int(keys[0].numel()),
+            "breakdown_ms_per_step": {k: round(v[0] / max(1, args.steps), 4)
+                                      for k, v in prof.items() if v[1]},
+            "result": result}
+
+
+def stream_ceiling(args, torch, rel, cols) -> dict:
+    """The streaming-read ceiling measured in the same run: rel_stream_read
+    over the same columns (each byte read once, nothing else done), timed by
+    the library's per-kernel events."""
+    d = torch.zeros(1, dtype=torch.int64, device="cuda")
+    nbytes = sum(c.numel() * c.element_size() for c in cols)
+    for c in cols:
+        rel.stream_read_async(c, d)
+    torch.cuda.synchronize()
+    rel.profile_read()
+    rel.profile_enable(True)
+    for _ in range(args.stream_reps):
+        for c in cols:
+            rel.stream_read_async(c, d)
+    torch.cuda.synchronize()
+    rel.profile_enable(False)
+    ms, launches = rel.profile_read()["stream_read"]
+    per_pass = ms / args.stream_reps
+    gbs = nbytes / (per_pass * 1e-3) / 1e9
+    return {"bytes": nbytes, "ms": per_pass, "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "launches_per_pass": launches // args.stream_reps,
+            "workload": "rel_stream_read over the five fact columns, one launch per column"}
+
+
+def bench_c1(args, torch, datagen, rel) -> dict:
+    """The small join + group-by (65,536 build rows with unique int32 keys and
+    a 64-value group attribute; 1,048,576 probe rows over 72,090 key values;
+    SUM(value), COUNT(*) by group) as one rel_pipeline step with its build
+    side in a hash table. Its 13.1 MB fit the caches, so it is reported as
+    latency: warm (back-to-back steps) and cold (a 1 GiB buffer written
+    before each step evicts the Infinity Cache)."""
+    d = datagen.join_groupby()
+    fact = [torch.from_numpy(d["probe_key"]).cuda(), torch.from_numpy(d["probe_val"]).cuda()]
+    dims = [dict(fk=0, key=torch.from_numpy(d["build_key"]).cuda(),
+                 payload=torch.from_numpy(d["build_grp"]).cuda())]
+    aggs = [("sum", 1), ("count", None)]
+    n_probe, n_build = len(d["probe_key"]), len(d["build_key"])
+    alg = 12 * n_probe + 8 * n_build
+    out = {"workload": f"join {n_build} build x {n_probe} probe rows (int32 keys, hash table), "
+                       "group by the build side's attribute (64 groups), SUM(value), COUNT(*)",
+           "algorithmic_bytes": alg}
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    for name, t in (("hash", rel.tuning(flags=rel.TUNE_NO_DIRECT)), ("direct", None)):
+        plan = rel.PreparedPipeline(fact, [], dims, [("dim", 0)], aggs, 64, t)
+        for _ in range(3):
+            plan.launch()
+        torch.cuda.synchronize()
+        groups = int(plan.result()[0][0].numel())
+        res = {}
+        for mode in ("warm", "cold"):
+            times = []
+            prof = {}
+            for _ in range(args.c1_reps):
+                if mode == "cold":
+                    flush.fill_(len(times) & 0xFF)
+                start = torch.cuda.Event(enable_timing=True)
+                stop = torch.cuda.Event(enable_timing=True)
+                rel.profile_enable(True)
+                start.record(stream)
+                plan.launch()
+                stop.record(stream)
+                torch.cuda.synchronize()
+                rel.profile_enable(False)
+                for k, v in rel.profile_read().items():
+                    if v[1]:
+                        prof[k] = prof.get(k, 0.0) + v[0]
+                times.append(start.elapsed_time(stop))
+            med = float(np.median(times))
+            res[mode] = {"median_ms": med, "min_ms": float(min(times)),
+                         "rows_per_s": n_probe / (med * 1e-3),
+                         "frac": alg / (med * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "kernel_ms": {k: round(v / args.c1_reps, 5) for k, v in prof.items()}}
+        res["groups"] = groups
+        out[name] = res
+        del plan
+    del flush
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_model() -> str:
@@ -305,7 +424,41 @@ def bench_ops(args, torch, datagen, rel) -> dict:
     res["hash_probe"] = line(k["map_probe"], 8 * npr + 8 * pairs, rows=npr, pairs=pairs,
                              workload=f"{npr} Zipf(1) int64 probe keys -> (build, probe) row-id pairs")
     res["hash_join_fill_ms"] = k.get("fill", 0.0)
-    del ws
+
+    # join -> group-by as one composite step: the pairs' probe row ids feed
+    # the group-by as a gather-on-read selection of the probe side's group
+    # and payload columns (every probe row matches once here)
+    aggs2 = [("sum", 0), ("count", None)]
+    mg = args.ops_groups
+    gk = [torch.empty(mg, dtype=torch.int64, device="cuda")]
+    ga = [torch.empty(mg, dtype=torch.int64, device="cuda") for _ in aggs2]
+    gcount = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sel = op[:pairs]
+    wsg = rel.workspace(rel.groupby_ws([torch.int64], aggs2, pairs, mg))
+
+    def composite():
+        rel.hash_join_async(dev["build_key"], dev["probe_key"], ob, op, count, ws)
+        rel.groupby_agg_async([dev["probe_grp"]], [dev["probe_val"]], aggs2, gk, ga, gcount, mg,
+                              wsg, key_idx=sel, val_idx=sel)
+
+    composite()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        composite()
+    stop.record()
+    torch.cuda.synchronize()
+    cms = start.elapsed_time(stop) / reps
+    cbytes = 8 * nb + 8 * npr + 16 * pairs + int(gcount.item()) * 24
+    res["join_groupby_composite"] = {
+        "ms": cms, "rows": npr, "rows_per_s": npr / (cms * 1e-3), "groups": int(gcount.item()),
+        "algorithmic_bytes": cbytes,
+        "frac": cbytes / (cms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "workload": f"rel_hash_join ({nb} unique int64 build keys, {npr} Zipf(1) probes) then "
+                    "rel_groupby_agg of the matched rows' int64 group column (~10M groups), "
+                    "SUM/COUNT of the payload, selected through the probe row ids"}
+    del ws, wsg, gk, ga, sel
     torch.cuda.empty_cache()
     # the single-pass build (one device-scope CAS per key after filling the
     # table) beside it
@@ -472,6 +625,11 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stream-reps", type=int, default=5)
+    ap.add_argument("--no-c1", action="store_true", help="skip the 64k x 1M join + group-by")
+    ap.add_argument("--c1-reps", type=int, default=20)
+    ap.add_argument("--tables", choices=["hash", "direct"], default=None,
+                    help="only time the star-schema step with these dim tables (profiling)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances section")
     ap.add_argument("--batch-only", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=256)
@@ -543,33 +701,22 @@ def main() -> int:
     fact = [dev["fk_a"], dev["fk_b"], dev["date"], dev["price"], dev["flag"]]
     dims = [dict(fk=0, key=dev["dim_a_key"], payload=None),
             dict(fk=1, key=dev["dim_b_key"], payload=dev["dim_b_region"])]
-    plan = rel.PreparedPipeline(fact, TERMS, dims, KEYS, AGGS, max_groups=128)
-
-    for _ in range(args.warmup):
-        plan.launch()
-    torch.cuda.synchronize()
-    keys, aggs = plan.result()
-    n_groups = int(keys[0].numel())
-
-    stream = torch.cuda.current_stream()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    rel.profile_read()
-    rel.profile_enable(True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    for _ in range(args.steps):
-        plan.launch()
-    stop.record(stream)
-    torch.cuda.synchronize()
-    rel.profile_enable(False)
-    prof = rel.profile_read()
-    ms_per_step = start.elapsed_time(stop) / args.steps
-
-    fused_ms, fused_n = prof["pipeline_fused"]
-    fused_avg_ms = fused_ms / max(1, fused_n)
     alg_bytes = FACT_BYTES_PER_ROW * n
+    if args.tables:
+        t = rel.tuning(flags=rel.TUNE_NO_DIRECT) if args.tables == "hash" else None
+        r = star_run(args, torch, rel, fact, dims, t)
+        r.pop("result")
+        print(json.dumps({"tables": args.tables, **r}), flush=True)
+        return 0
+    # headline: both dims in open-addressing hash tables; beside it the
+    # same plan with the dense dim keys in direct tables
+    hashed = star_run(args, torch, rel, fact, dims, rel.tuning(flags=rel.TUNE_NO_DIRECT))
+    direct = star_run(args, torch, rel, fact, dims, None)
+    same = all(torch.equal(x, y) for x, y in zip(hashed.pop("result"), direct.pop("result")))
+    stream = stream_ceiling(args, torch, rel, fact)
+    fused_avg_ms = hashed["fused_kernel_ms"]
     achieved_gbs = alg_bytes / (fused_avg_ms * 1e-3) / 1e9
-    breakdown = {k: round(v[0] / max(1, args.steps), 4) for k, v in prof.items() if v[1]}
+    ms_per_step = hashed["ms_per_step"]
 
     out = {
         "metric": METRIC,
@@ -585,23 +732,37 @@ def main() -> int:
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": "star schema: 600M-row fact, date < 767, join dim A (1.5M) "
-                               "and dim B (10k), group by (region, flag), "
-                               "SUM/COUNT/AVG/MIN/MAX(price)" if n == 600_000_000 else
-                   f"star schema with {n} fact rows",
-                   "fact_rows": n, "groups": n_groups, "seed": seed},
+                               "and dim B (10k) through open-addressing hash tables, "
+                               "group by (region, flag), SUM/COUNT/AVG/MIN/MAX(price)"
+                   if n == 600_000_000 else f"star schema with {n} fact rows, hash-table dims",
+                   "fact_rows": n, "groups": hashed["groups"], "seed": seed,
+                   "dim_tables": "hash (rel_tuning.flags = REL_TUNE_NO_DIRECT)"},
         "hbm_frac_step": alg_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "breakdown_ms_per_step": breakdown,
+        "breakdown_ms_per_step": hashed["breakdown_ms_per_step"],
         "roofline": {"bound": "hbm", "kernel": "pipeline_fused", "achieved": achieved_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
+                     "frac_of_stream": achieved_gbs / stream["achieved_gbs"],
                      "kernel_ms": fused_avg_ms, "algorithmic_bytes": alg_bytes,
-                     "traffic": measured_traffic(n)},
+                     "traffic": measured_traffic(n, TRAFFIC_PROFILE)},
+        "stream_read": stream,
+        "direct_tables": {
+            "workload": "the same plan with both dims in direct tables (dense unique keys: "
+                        "dim A a range test, dim B a byte array)",
+            "ms_per_step": direct["ms_per_step"], "rows_per_s": n / (direct["ms_per_step"] * 1e-3),
+            "fused_kernel_ms": direct["fused_kernel_ms"],
+            "frac": alg_bytes / (direct["fused_kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "traffic": measured_traffic(n, TRAFFIC_PROFILE_DIRECT),
+            "breakdown_ms_per_step": direct["breakdown_ms_per_step"],
+            "identical_results": same},
     }
+    if not args.no_c1:
+        out["join_groupby_64k_1m"] = bench_c1(args, torch, datagen, rel)
     if not args.no_cpu_baseline:
         host = {k: v for k, v in d.items()}
         out["cpu_baseline"] = cpu_baseline(host, n, args.cpu_seconds)
         del host
     if not args.no_batch:
-        del plan, fact, dims, dev, d, keys, aggs
+        del fact, dims, dev, d
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         out["batch"] = bench_batch(args, torch, datagen, rel)

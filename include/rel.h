@@ -428,6 +428,22 @@ int64_t rel_server_now_ns(void);
 /* Completes every queued query, stops the scheduler and frees the server. */
 void rel_server_destroy(rel_server* s);
 
+/* ---------------------------------------------------------- stream read */
+
+/* The streaming-read ceiling that scan-bound operators are measured against
+ * beside the HBM specification (the paper's measurements run on data resident
+ * in device memory, Section 4.1 "hot runs"; Section 4.2 breaks query time
+ * down by operator): reads each of the `bytes` bytes at `data` exactly once
+ * with coalesced 16-byte non-temporal loads and writes to *d_xor the XOR of
+ * all 64-bit little-endian words of the buffer (a last partial word
+ * zero-padded), so that the reads cannot be elided and the result can be
+ * checked on a host.
+ *   data     device memory, 16-byte aligned (any size, 0 allowed).
+ *   d_xor    device uint64, overwritten (stream-ordered).
+ * Errors: REL_EINVAL for NULL or misaligned pointers or a negative size;
+ * REL_EDEVICE for a failed launch. */
+rel_status rel_stream_read(const void* data, int64_t bytes, uint64_t* d_xor, void* stream);
+
 /* ------------------------------------------------------------- profiling */
 
 /* Kernel classes timed by the per-kernel profiler (the per-operator time
@@ -441,7 +457,8 @@ typedef enum {
   REL_K_PIPELINE = 5,    /* rel_pipeline's fused filter-probe-aggregate kernel */
   REL_K_FINALIZE = 6,    /* group compaction into the outputs */
   REL_K_GROUP_PARTITION = 7, /* rel_groupby_agg's counting and scatter passes */
-  REL_K_COUNT = 8
+  REL_K_STREAM = 8,      /* rel_stream_read */
+  REL_K_COUNT = 9
 } rel_kernel_class;
 
 /* Static name of a kernel class. */

@@ -1126,6 +1126,23 @@ const char* rel_last_error(void) { return g_error.c_str(); }
 
 int rel_version(void) { return REL_VERSION; }
 
+// ----------------------------------------------------------- stream read
+
+rel_status rel_stream_read(const void* data, int64_t bytes, uint64_t* d_xor, void* stream) {
+  g_error.clear();
+  if (bytes < 0) return fail(REL_EINVAL, "stream_read: negative size");
+  if (bytes > 0 && !data) return fail(REL_EINVAL, "stream_read: NULL data");
+  if (reinterpret_cast<uintptr_t>(data) % 16 != 0)
+    return fail(REL_EINVAL, "stream_read: data must be 16-byte aligned");
+  if (!d_xor || reinterpret_cast<uintptr_t>(d_xor) % 8 != 0)
+    return fail(REL_EINVAL, "stream_read: NULL or misaligned result word");
+  hipError_t e = launch_stream_read(data, static_cast<uint64_t>(bytes),
+                                    reinterpret_cast<unsigned long long*>(d_xor),
+                                    static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(REL_EDEVICE, "stream_read: %s", hipGetErrorString(e));
+  return REL_OK;
+}
+
 // ------------------------------------------------------------------ filter
 
 size_t rel_filter_ws(int64_t n) {

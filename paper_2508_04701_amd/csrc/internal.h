@@ -22,7 +22,7 @@ const DeviceInfo& device_info();
 // pair of events on the launch stream (kernel classes as in rel.h).
 enum KernelClass : int {
   kKFill = 0, kKFilter, kKMapBuild, kKMapProbe, kKGroupAgg, kKPipeline, kKFinalize,
-  kKGroupPartition, kKCount
+  kKGroupPartition, kKStream, kKCount
 };
 struct ProfileScope {
   ProfileScope(int kclass, hipStream_t s);
@@ -34,6 +34,11 @@ struct ProfileScope {
 
 // Fills n 64-bit words with `pattern` (graph-safe replacement for memset).
 void launch_fill64(uint64_t* p, uint64_t n, uint64_t pattern, hipStream_t s);
+
+// Reads `bytes` bytes at `data` (16-byte aligned) once; *out = XOR of its
+// zero-padded 64-bit words.
+hipError_t launch_stream_read(const void* data, uint64_t bytes, unsigned long long* out,
+                              hipStream_t s);
 
 // --------------------------------------------------------------- filter
 

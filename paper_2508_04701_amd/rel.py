@@ -111,6 +111,7 @@ SIGNATURES = {
     "rel_kernel_name": (ctypes.c_char_p, [_I]),
     "rel_profile_enable": (None, [_I]),
     "rel_profile_read": (_I, [_P, _P]),
+    "rel_stream_read": (_I, [_P, _L, _P, _P]),
 }
 
 _lib = None
@@ -442,9 +443,26 @@ def pipeline(fact, preds, dims, keys, aggs, max_groups: int, t: Tuning | None = 
     return p.result()
 
 
+# ---------------------------------------------------------------- stream read
+
+def stream_read_async(t: torch.Tensor, d_xor: torch.Tensor, nbytes: int | None = None):
+    """Reads the first nbytes bytes of t's storage once (default: all of t);
+    d_xor (one int64 on the device) receives the XOR of its 64-bit words."""
+    _require_gpu(t, d_xor)
+    n = t.numel() * t.element_size() if nbytes is None else nbytes
+    _check(lib().rel_stream_read(_addr(t), n, _addr(d_xor), _stream()))
+
+
+def stream_read(t: torch.Tensor) -> int:
+    """XOR of the 64-bit words of t's bytes (zero-padded), read on the GPU."""
+    d = torch.zeros(1, dtype=torch.int64, device=t.device)
+    stream_read_async(t, d)
+    return int(d.item()) & ((1 << 64) - 1)
+
+
 # ------------------------------------------------------------------ profiling
 
-KERNEL_CLASSES = 8
+KERNEL_CLASSES = 9
 
 
 def profile_enable(on: bool = True):

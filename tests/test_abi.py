@@ -236,3 +236,15 @@ def test_batch_validation_and_workspace():
     t = rel.tuning(chunk_tiles=-1)
     descs[0].tuning = ctypes.pointer(t)
     assert L.rel_pipeline_batch_ws(descs, 3) == 0
+
+
+def test_stream_read_validation():
+    L = rel.lib()
+    P = ctypes.c_void_p
+    assert L.rel_stream_read(P(0x1000), -1, P(0x2000), None) == rel.REL_EINVAL
+    assert L.rel_stream_read(P(0), 16, P(0x2000), None) == rel.REL_EINVAL
+    assert L.rel_stream_read(P(0x1001), 16, P(0x2000), None) == rel.REL_EINVAL
+    assert b"16-byte aligned" in L.rel_last_error()
+    assert L.rel_stream_read(P(0x1000), 16, P(0), None) == rel.REL_EINVAL
+    assert L.rel_stream_read(P(0x1000), 16, P(0x2004), None) == rel.REL_EINVAL
+    assert L.rel_kernel_name(8) == b"stream_read"

@@ -18,6 +18,9 @@ STAR_AGGS = [("sum", 3), ("count", None), ("avg", 3), ("min", 3), ("max", 3)]
 
 
 def test_star_schema_600m_rows_against_oracle():
+    """The benchmark's plan with both dims in hash tables (the headline
+    configuration) and with direct tables, each launched twice, against one
+    oracle run over all 600M rows."""
     announce("full-size star schema 600M")
     d = datagen.star_schema(seed=datagen.SEED0 + 2, n_fact=600_000_000)
     fact = [d["fk_a"], d["fk_b"], d["date"], d["price"], d["flag"]]
@@ -29,19 +32,25 @@ def test_star_schema_600m_rows_against_oracle():
     ddims = [dict(fk=0, key=torch.from_numpy(d["dim_a_key"]).cuda(), payload=None),
              dict(fk=1, key=torch.from_numpy(d["dim_b_key"]).cuda(),
                   payload=torch.from_numpy(d["dim_b_region"]).cuda())]
-    plan = rel.PreparedPipeline(dev, terms, ddims, keys, STAR_AGGS, max_groups=128)
-    plan.launch()
-    got = plan.result()
-    # the same launch again: results must not depend on the run
-    plan.launch()
-    again = plan.result()
-    a, b = canon_groups(*got), canon_groups(*again)
-    assert all(np.array_equal(x, y) for x, y in zip(a[0] + a[1], b[0] + b[1]))
-    del dev, ddims, plan
+    results = {}
+    for name, t in (("hash tables", rel.tuning(flags=rel.TUNE_NO_DIRECT)), ("direct tables", None)):
+        announce("full-size star schema 600M,", name)
+        plan = rel.PreparedPipeline(dev, terms, ddims, keys, STAR_AGGS, max_groups=128, t=t)
+        plan.launch()
+        got = plan.result()
+        # the same launch again: results must not depend on the run
+        plan.launch()
+        again = plan.result()
+        a, b = canon_groups(*got), canon_groups(*again)
+        assert all(np.array_equal(x, y) for x, y in zip(a[0] + a[1], b[0] + b[1])), name
+        results[name] = got
+        del plan
+    del dev, ddims
     torch.cuda.empty_cache()
     want = oracle.pipeline(fact, terms, dims, keys, STAR_AGGS)
     assert len(want[1][0]) == 75
-    assert_groups(got, want, STAR_AGGS, "star schema 600M")
+    for name, got in results.items():
+        assert_groups(got, want, STAR_AGGS, f"star schema 600M, {name}")
 
 
 def test_batch_256_instances_full_size():
