@@ -164,6 +164,24 @@ rel_status rel_filter(const rel_column* cols, int ncols, const rel_pred* preds, 
                       rel_rowid* out, int64_t out_cap, int64_t* d_count, void* ws,
                       size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory or size a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): rel_filter with the same arguments, semantics and output,
+ * minus the workspace. The tile states live in a static device array that
+ * the library holds per GPU (1 MiB, kept until the process ends); the first
+ * call on a device looks up its address, later calls allocate nothing
+ * (no hipMalloc, no hipFree, no allocating library routine).
+ *   n (the columns' len) at most 1,073,479,680 rows.
+ * Every call on a GPU shares that GPU's array, and each call clears the part
+ * it uses first: calls that may overlap in time on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.
+ * Errors: as rel_filter (never REL_ENOMEM); REL_ECAPACITY when n exceeds the
+ * maximum above (nothing launched); REL_EDEVICE if the array's address
+ * cannot be looked up. */
+rel_status rel_filter_noalloc(const rel_column* cols, int ncols, const rel_pred* preds,
+                              int npreds, rel_rowid* out, int64_t out_cap, int64_t* d_count,
+                              void* stream);
+
 /* ------------------------------------------------------------ hash join */
 
 /* Workspace bytes for rel_hash_join with n_build build rows (with a

@@ -1150,10 +1150,13 @@ size_t rel_filter_ws(int64_t n) {
   return align_up(kAlign + static_cast<size_t>(tiles) * 8);
 }
 
-rel_status rel_filter(const rel_column* cols, int ncols, const rel_pred* preds, int npreds,
-                      rel_rowid* out, int64_t out_cap, int64_t* d_count, void* ws,
-                      size_t ws_bytes, void* stream) {
-  g_error.clear();
+}  // extern "C"
+
+namespace rel {
+namespace {
+
+rel_status filter_check(const rel_column* cols, int ncols, const rel_pred* preds, int npreds,
+                        rel_rowid* out, int64_t out_cap, int64_t* d_count) {
   if (!cols || ncols < 1 || ncols > REL_MAX_FACT_COLS)
     return fail(REL_EINVAL, "filter: 1..%d columns required", REL_MAX_FACT_COLS);
   for (int c = 0; c < ncols; ++c) {
@@ -1172,12 +1175,14 @@ rel_status rel_filter(const rel_column* cols, int ncols, const rel_pred* preds, 
   }
   if (out_cap < 0 || (out_cap > 0 && !out)) return fail(REL_EINVAL, "filter: bad output");
   if (!d_count) return fail(REL_EINVAL, "filter: NULL count");
-  const int64_t n = cols[0].len;
-  rel_status st = check_ws(ws, ws_bytes, rel_filter_ws(n));
-  if (st) return st;
+  return REL_OK;
+}
 
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  unsigned char* w = static_cast<unsigned char*>(ws);
+// Enqueues the filter with its tile states at w (rel_filter_ws(n) bytes).
+rel_status filter_enqueue(const rel_column* cols, const rel_pred* preds, int npreds,
+                          rel_rowid* out, int64_t out_cap, int64_t* d_count, unsigned char* w,
+                          hipStream_t s) {
+  const int64_t n = cols[0].len;
   FilterParams p;
   std::memset(&p, 0, sizeof p);
   for (int t = 0; t < npreds; ++t) {
@@ -1201,6 +1206,43 @@ rel_status rel_filter(const rel_column* cols, int ncols, const rel_pred* preds, 
   launch_fill64(reinterpret_cast<uint64_t*>(w), (kAlign + p.ntiles * 8) / 8, 0, s);
   launch_filter(p, s);
   return after_launch(s, "filter");
+}
+
+}  // namespace
+}  // namespace rel
+
+extern "C" {
+
+rel_status rel_filter(const rel_column* cols, int ncols, const rel_pred* preds, int npreds,
+                      rel_rowid* out, int64_t out_cap, int64_t* d_count, void* ws,
+                      size_t ws_bytes, void* stream) {
+  g_error.clear();
+  rel_status st = filter_check(cols, ncols, preds, npreds, out, out_cap, d_count);
+  if (st) return st;
+  st = check_ws(ws, ws_bytes, rel_filter_ws(cols[0].len));
+  if (st) return st;
+  return filter_enqueue(cols, preds, npreds, out, out_cap, d_count,
+                        static_cast<unsigned char*>(ws), static_cast<hipStream_t>(stream));
+}
+
+rel_status rel_filter_noalloc(const rel_column* cols, int ncols, const rel_pred* preds,
+                              int npreds, rel_rowid* out, int64_t out_cap, int64_t* d_count,
+                              void* stream) {
+  g_error.clear();
+  rel_status st = filter_check(cols, ncols, preds, npreds, out, out_cap, d_count);
+  if (st) return st;
+  const size_t need = rel_filter_ws(cols[0].len);
+  if (need > kFilterScratchBytes)
+    return fail(REL_ECAPACITY,
+                "filter_noalloc: %lld rows need %zu bytes of tile state, the static scratch "
+                "holds %zu (at most %lld rows)",
+                static_cast<long long>(cols[0].len), need, kFilterScratchBytes,
+                static_cast<long long>(kFilterNoallocMaxRows));
+  void* scratch = nullptr;
+  hipError_t e = filter_scratch(&scratch);
+  if (e != hipSuccess) return fail(REL_EDEVICE, "filter_noalloc: %s", hipGetErrorString(e));
+  return filter_enqueue(cols, preds, npreds, out, out_cap, d_count,
+                        static_cast<unsigned char*>(scratch), static_cast<hipStream_t>(stream));
 }
 
 // --------------------------------------------------------------- hash join

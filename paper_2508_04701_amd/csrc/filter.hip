@@ -13,9 +13,40 @@
 // every tile that a look-back waits on has already started and will publish.
 // The ids of a tile are staged in LDS and written with coalesced stores.
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace rel {
+
+// Tile states of rel_filter_noalloc (a file-scope device array: each GPU the
+// library runs on holds its own copy until the process ends). Host code
+// never passes this name to a kernel: it takes the device address that
+// filter_scratch() looks up.
+static __device__ __align__(256) unsigned char scratch[kFilterScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+}  // namespace
+
+hipError_t filter_scratch(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 namespace {
 

@@ -69,6 +69,17 @@ struct FilterParams {
 
 void launch_filter(const FilterParams& p, hipStream_t s);
 
+// Static scratch of the allocation-free filter: the ticket word's 256-byte
+// block plus one tile-state word per 8192-row tile. 1 MiB holds the states
+// of 131040 tiles, i.e. up to 1,073,479,680 rows.
+constexpr size_t kFilterScratchBytes = size_t(1) << 20;
+constexpr int64_t kFilterNoallocMaxRows =
+    static_cast<int64_t>((kFilterScratchBytes - 256) / 8) * kFilterTile;
+
+// Device address of the calling thread's current device's copy of the
+// filter scratch, looked up once per device.
+hipError_t filter_scratch(void** ptr);
+
 // ------------------------------------------------------------- hash maps
 
 // Geometry of one multimap in the workspace.

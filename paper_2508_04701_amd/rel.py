@@ -112,6 +112,7 @@ SIGNATURES = {
     "rel_profile_enable": (None, [_I]),
     "rel_profile_read": (_I, [_P, _P]),
     "rel_stream_read": (_I, [_P, _L, _P, _P]),
+    "rel_filter_noalloc": (_I, [_P, _I, _P, _I, _P, _L, _P, _P]),
 }
 
 _lib = None
@@ -213,6 +214,15 @@ def filter_async(cols, preds, out, d_count, ws, idx=None):
     cp = _preds(preds)
     _check(lib().rel_filter(ccols, len(cols), cp, len(preds), _addr(out), out.numel(),
                             _addr(d_count), _addr(ws), ws.numel(), _stream()))
+
+
+def filter_noalloc_async(cols, preds, out, d_count, idx=None):
+    """Enqueues rel_filter_noalloc (tile states in the library's static
+    device scratch; no workspace)."""
+    ccols = _arr(Column, [column(c, idx) for c in cols])
+    cp = _preds(preds)
+    _check(lib().rel_filter_noalloc(ccols, len(cols), cp, len(preds), _addr(out), out.numel(),
+                                    _addr(d_count), _stream()))
 
 
 def filter(cols, preds, idx=None) -> torch.Tensor:

@@ -248,3 +248,18 @@ def test_stream_read_validation():
     assert L.rel_stream_read(P(0x1000), 16, P(0), None) == rel.REL_EINVAL
     assert L.rel_stream_read(P(0x1000), 16, P(0x2004), None) == rel.REL_EINVAL
     assert L.rel_kernel_name(8) == b"stream_read"
+
+
+def test_filter_noalloc_validation():
+    L = rel.lib()
+    P = ctypes.c_void_p
+    ok_pred = (rel.Pred * 1)(rel.Pred(0, 0, 5, 0))
+
+    def call(n, d_count=0x2000):
+        ca = (rel.Column * 1)(col(n))
+        return L.rel_filter_noalloc(ca, 1, ok_pred, 1, P(0x3000), n, P(d_count), None)
+
+    assert call(10, d_count=0) == rel.REL_EINVAL
+    # beyond the static scratch's 131040 tile states: rejected before any HIP call
+    assert call(1_073_479_680 + 1) == rel.REL_ECAPACITY
+    assert b"static scratch" in L.rel_last_error()
