@@ -55,7 +55,8 @@ typedef enum {
   REL_OK = 0,
   REL_EINVAL = 1,       /* malformed arguments */
   REL_ENOMEM = 2,       /* workspace smaller than required */
-  REL_ECAPACITY = 3,    /* an output or table bound was exceeded (reported by helpers) */
+  REL_ECAPACITY = 3,    /* an output or table bound was exceeded (reported by the *_sync
+                           forms and rel_filter_noalloc) */
   REL_EDEVICE = 4,      /* a HIP runtime call or kernel launch failed */
   REL_EUNSUPPORTED = 5  /* well-formed request outside what this build implements */
 } rel_status;
@@ -347,6 +348,36 @@ rel_status rel_graph_launch(rel_graph* g, void* stream);
  * running. */
 void rel_graph_destroy(rel_graph* g);
 
+/* Autotuner (batch execution, Section 5; the load factor, fan-out and block
+ * shape of each batch instance per size bucket): for each sample plan, runs
+ * every candidate tuning record as a one-plan rel_pipeline_batch on the
+ * current device - the group-table load factor, the fan-out of an instance
+ * over the persistent workgroups (chunk_tiles), the block shape (resident
+ * workgroups per CU: grid, or the LDS group table's size, lds_slots) and the
+ * global group-table copies (replicas) - checks that every candidate returns
+ * the same groups (a difference is a race), and stores the fastest under the
+ * key "<gfx arch>/pipeline_batch/f<F>-d<D>-g<G>" of a JSON object in the
+ * file at cache_path (created if missing; other records are kept). F, D and
+ * G are the even exponents at or below the ceiling log2 of the fact rows,
+ * the largest dim and max_groups (buckets of 4x). Each record holds the
+ * chosen fields ("tuning"), its time ("ms") and every candidate's time.
+ * Samples of one bucket overwrite each other's record: pass one (a
+ * representative plan, for instance the median instance) per bucket.
+ * Unlike the operators, this offline call allocates and frees its own device
+ * memory (workspace and outputs of the sample runs) and synchronises.
+ * Errors: REL_EINVAL (invalid sample plan, unreadable or unwritable cache),
+ * REL_ECAPACITY (a sample with more groups than its max_groups),
+ * REL_EDEVICE (a failed run, or a candidate whose result differs). */
+rel_status rel_autotune(const rel_pipeline_desc* samples, int n, const char* cache_path);
+
+/* The record that rel_autotune stored for plan d's bucket on the current
+ * device's architecture: *out receives its fields (others zero, i.e. the
+ * defaults) and *found 1; with no record *found is 0 and *out all zero.
+ * Only host work. Errors: REL_EINVAL (NULL arguments, unreadable cache,
+ * unknown fields). */
+rel_status rel_autotune_lookup(const char* cache_path, const rel_pipeline_desc* d,
+                               rel_tuning* out, int* found);
+
 /* -------------------------------------------------------------- serving */
 
 /* A query server over resident tables (the pipeline tasks of Section 3.2.2
@@ -366,20 +397,26 @@ typedef struct rel_server rel_server;
  * (rel_pipeline_batch on one HIP stream per lane, completion by event
  * polling, then copies of the result rows to the host buffers). A custom
  * executor lets the scheduler run anywhere (tests drive it with one that
- * computes on the host). All three are called from the scheduler thread,
+ * computes on the host). All four are called from the scheduler thread,
  * batch_ws also from rel_server_submit.
  *   batch_ws  workspace bytes for plans d[0..n-1] (0: invalid plans).
  *   launch    starts the batch on `lane` (idle), with n plans, their device
  *             outputs o and host outputs host (entries with NULL d_groups
  *             take no copy); returns REL_OK or a failure of the batch.
  *   poll      1 once the lane's batch and its copies are done, 0 while they
- *             run, -status on failure. */
+ *             run, -status on failure.
+ *   quiesce   after a failed launch or poll, before the batch's workspace
+ *             goes back to the arena: returns once nothing the lane enqueued
+ *             can still touch it (the GPU executor synchronises the lane's
+ *             stream: a launch can fail after enqueueing some of its
+ *             kernels). May be NULL. */
 typedef struct {
   void* user;
   size_t (*batch_ws)(void* user, const rel_pipeline_desc* d, int n);
   rel_status (*launch)(void* user, int lane, const rel_pipeline_desc* d, int n,
                        const rel_outputs* o, const rel_outputs* host, void* ws, size_t ws_bytes);
   int (*poll)(void* user, int lane);
+  void (*quiesce)(void* user, int lane);
 } rel_executor;
 
 typedef struct {
@@ -435,16 +472,45 @@ int rel_server_poll(rel_server* s, rel_completion* out, int max);
  * timeout_ms passes first. */
 rel_status rel_server_drain(rel_server* s, int64_t timeout_ms);
 
-/* Counters, and the 50th and 99th percentile (nearest rank) of submit-to-done
- * latency over the successful queries so far (-1 if none). */
+/* Counters, the 50th and 99th percentile (nearest rank) of submit-to-done
+ * latency over the successful queries so far (-1 if none), and their
+ * throughput: the fact rows they scanned divided by the time from the first
+ * one's submission to the last one's completion (0 if none). Any output
+ * pointer may be NULL. */
 rel_status rel_server_stats(rel_server* s, rel_server_counts* counts, int64_t* p50_ns,
-                            int64_t* p99_ns);
+                            int64_t* p99_ns, double* rows_per_s);
 
 /* The server clock: a steady clock in nanoseconds. */
 int64_t rel_server_now_ns(void);
 
 /* Completes every queued query, stops the scheduler and frees the server. */
 void rel_server_destroy(rel_server* s);
+
+/* ---------------------------------------------------- synchronous forms */
+
+/* Each *_sync call makes the asynchronous call of the same name, waits for
+ * `stream`, and reads the exact result size (the value of d_count, d_groups
+ * or o->d_groups) into the host int64 *count / *groups (may be NULL). It
+ * returns REL_ECAPACITY when that size exceeds the output capacity (out_cap,
+ * o->cap: the first out_cap items were written, the caller grows its output
+ * and calls again) or, for group counts, is -1 (more distinct groups than
+ * max_groups: outputs undefined); otherwise the status of the call, or
+ * REL_EDEVICE if the copy or the wait fails. Nothing is read back when the
+ * call itself fails. */
+rel_status rel_filter_sync(const rel_column* cols, int ncols, const rel_pred* preds, int npreds,
+                           rel_rowid* out, int64_t out_cap, int64_t* d_count, void* ws,
+                           size_t ws_bytes, void* stream, int64_t* count);
+rel_status rel_hash_join_sync(const rel_column* build_keys, const rel_column* probe_keys,
+                              rel_rowid* out_build, rel_rowid* out_probe, int64_t out_cap,
+                              int64_t* d_count, const rel_tuning* t, void* ws, size_t ws_bytes,
+                              void* stream, int64_t* count);
+rel_status rel_groupby_agg_sync(const rel_column* keys, int nkeys, const rel_column* vals,
+                                int nvals, const rel_agg* aggs, int naggs, void* const* out_keys,
+                                void* const* out_aggs, int64_t out_cap, int64_t* d_groups,
+                                int64_t max_groups, const rel_tuning* t, void* ws,
+                                size_t ws_bytes, void* stream, int64_t* groups);
+rel_status rel_pipeline_sync(const rel_pipeline_desc* d, const rel_outputs* o, void* ws,
+                             size_t ws_bytes, void* stream, int64_t* groups);
 
 /* ---------------------------------------------------------- stream read */
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(PKG, "librel.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "profile.cpp", "server.cpp", "filter.hip", "join.hip", "groupby.hip", "partition.hip",
+SOURCES = ["api.cpp", "autotune.cpp", "profile.cpp", "server.cpp", "filter.hip", "join.hip", "groupby.hip", "partition.hip",
            "pipeline.hip",
            "pipeline_batch.hip", "stream.hip"]
 

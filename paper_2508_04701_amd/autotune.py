@@ -1,9 +1,13 @@
 """Autotuner: per size bucket, the tuning record with the lowest measured
 device time among candidates that all return identical results (any
-difference is a race and raises). For fused plans the candidates vary the
-global group-table replicas, the LDS group table (off, 1024 or 4096 slots:
-the workgroup's LDS shape, which sets how many workgroups share a CU) and the
-group-table load factor; for the standalone group-by they vary the partition
+difference is a race and raises). Batched plans are tuned natively by
+rel_autotune (tune_batch_plans here): the candidates vary the global
+group-table replicas, the LDS group table (off, 1024 or 4096 slots: the
+workgroup's LDS shape, which sets how many workgroups share a CU), the
+group-table load factor, the fan-out of an instance over the persistent
+workgroups (fact tiles per work item) and the block shape (one or two
+workgroups per CU); rel_autotune_lookup reads a record back (lookup here).
+For the standalone group-by (tune_groupby) the candidates vary the partition
 fan-out (single pass, automatic, 2048 to 16384 partitions) and the first
 scatter's LDS table. Records persist as JSON keyed by (GPU architecture,
 operation, size bucket) and are applied per plan, also to each instance of a
@@ -183,3 +187,22 @@ def plan_bucket(n_fact: int, dim_rows: list, max_groups: int) -> str:
 def tuning_for(cache: Cache, op: str, n_fact: int, dim_rows: list, max_groups: int):
     """The cached record of the plan's bucket as a rel.Tuning (None: defaults)."""
     return to_tuning(cache.get(cache_key(op, plan_bucket(n_fact, dim_rows, max_groups))))
+
+
+# ----------------------------------------------------------- batched plans
+
+def tune_batch_plans(plans, cache_path: str) -> None:
+    """rel_autotune over the plans (rel.Plan, one representative per size
+    bucket): times every candidate as a one-plan batch on the GPU and stores
+    the fastest record of each bucket in the JSON file at cache_path."""
+    descs = (rel.PipelineDesc * len(plans))(*[p.desc for p in plans])
+    rel._check(rel.lib().rel_autotune(descs, len(plans), cache_path.encode()))
+
+
+def lookup(cache_path: str, plan) -> rel.Tuning | None:
+    """The record rel_autotune stored for the plan's bucket (None: none)."""
+    t = rel.Tuning()
+    found = rel.ctypes.c_int(0)
+    rel._check(rel.lib().rel_autotune_lookup(cache_path.encode(), rel.ctypes.byref(plan.desc),
+                                             rel.ctypes.byref(t), rel.ctypes.byref(found)))
+    return t if found.value else None

@@ -35,6 +35,17 @@ rel_status fail(rel_status s, const char* fmt, ...) {
   return s;
 }
 
+}  // namespace
+
+int set_last_error(int status, const char* msg) {
+  g_error = msg ? msg : "";
+  return status;
+}
+
+void clear_last_error() { g_error.clear(); }
+
+namespace {
+
 constexpr int64_t kMaxRows = 0xFFFFFFFELL;  // row ids must stay below the all-ones value
 constexpr size_t kAlign = 256;
 
@@ -490,6 +501,63 @@ rel_status pipeline_layout(const rel_pipeline_desc* d, PipeLayout& L, bool batch
   return REL_OK;
 }
 
+// Row spec of a single plan (see the fused kernels): the sources of its group
+// keys and values when they fit a compile-time form, else 0 (generic). Dims
+// must be int32 hash tables read from HBM, every accumulator must read one
+// int64 fact column, and each group key must be a dim payload or an int8 or
+// int32 fact column. The launcher falls back to the generic kernel for a
+// spec it has not built.
+int row_spec(const rel_pipeline_desc* d, const PipeLayout& L, PipelineParams& p) {
+  for (int i = 0; i < d->n_dims; ++i) {
+    const int c = d->dims[i].fact_col;
+    if (d->dims[i].key.type != REL_I32 || p.dim[i].in_lds) return 0;
+    if (d->fact[c].type != REL_I32 || !p.fact_vec[c]) return 0;
+  }
+  // at most one predicate term, on an aligned int32 column, as a range of
+  // the widened value: [lo, hi) clamped to the int32 domain
+  if (d->n_preds > 1) return 0;
+  if (d->n_preds == 1) {
+    const rel_pred& t = d->preds[0];
+    if (d->fact[t.col].type != REL_I32 || !p.fact_vec[t.col]) return 0;
+    const int64_t dmin = INT32_MIN, dend = static_cast<int64_t>(INT32_MAX) + 1;
+    auto clamp = [&](int64_t v) { return v < dmin ? dmin : (v > dend ? dend : v); };
+    int64_t lo = dmin, hi = dend;
+    switch (t.op) {
+      case REL_LT: hi = clamp(t.lo); break;
+      case REL_LE: hi = t.lo >= INT32_MAX ? dend : clamp(t.lo + 1); break;
+      case REL_GT: lo = t.lo >= INT32_MAX ? dend : clamp(t.lo + 1); break;
+      case REL_GE: lo = clamp(t.lo); break;
+      case REL_EQ:
+        lo = clamp(t.lo);
+        hi = (t.lo < dmin || t.lo > INT32_MAX) ? lo : lo + 1;
+        break;
+      case REL_RANGE: lo = clamp(t.lo); hi = clamp(t.hi); break;
+      default: return 0;  // NE is no single range
+    }
+    if (hi < lo) hi = lo;
+    p.spec_lo = lo;
+    p.spec_span = static_cast<uint64_t>(hi - lo);
+  }
+  const AccPlan& ap = L.gp.ap;
+  if (ap.nacc < 1) return 0;
+  for (int a = 0; a < ap.nacc; ++a)
+    if (ap.col[a] != ap.col[0]) return 0;
+  if (d->fact[ap.col[0]].type != REL_I64) return 0;
+  int k[REL_MAX_KEYS] = {0, 0};  // 0 none, 1 dim 0, 2 dim 1, 3 int8 fact, 4 int32 fact
+  for (int j = 0; j < d->n_keys; ++j) {
+    const rel_key_ref& kr = d->keys[j];
+    if (kr.src == REL_KEY_DIM) {
+      k[j] = 1 + kr.col;
+    } else {
+      const int32_t t = d->fact[kr.col].type;
+      if (t == REL_I8) k[j] = 3;
+      else if (t == REL_I32) k[j] = 4;
+      else return 0;
+    }
+  }
+  return k[0] | (k[1] << 3) | (1 << 6);
+}
+
 // Kernel parameters of plan d (layout L) over workspace w, and the builds of
 // its dims. Batched plans keep every dim in HBM.
 void plan_params(const rel_pipeline_desc* d, const PipeLayout& L, unsigned char* w,
@@ -607,6 +675,10 @@ void plan_params(const rel_pipeline_desc* d, const PipeLayout& L, unsigned char*
   }
   p.lds_bytes = static_cast<uint32_t>(lds);
   p.ntiles = n > 0 ? (n + kPipeTile - 1) / kPipeTile : 0;
+  p.directable = 1;
+  for (int i = 0; i < d->n_dims; ++i)
+    if (p.dim[i].map.direct_cap == 0) p.directable = 0;
+  if (!batch) p.spec = row_spec(d, L, p);
   for (int i = 0; i < d->n_dims; ++i) {
     const rel_dim& dm = d->dims[i];
     std::memset(&b[i], 0, sizeof b[i]);
@@ -1627,6 +1699,70 @@ void rel_graph_destroy(rel_graph* g) {
   if (g->graph) (void)hipGraphDestroy(g->graph);
   if (g->host) (void)hipHostFree(g->host);
   delete g;
+}
+
+// ------------------------------------------------------- synchronous forms
+
+}  // extern "C"
+
+namespace rel {
+namespace {
+
+// Waits for `stream` and reads the device int64 at d_count into *count;
+// REL_ECAPACITY when it exceeds cap (or, for group counts, is -1).
+rel_status read_count(rel_status st, const int64_t* d_count, int64_t cap, void* stream,
+                      int64_t* count, const char* what) {
+  if (st != REL_OK) return st;
+  int64_t host = 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(&host, d_count, sizeof host, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(REL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  if (count) *count = host;
+  if (host < 0) return fail(REL_ECAPACITY, "%s: more groups than max_groups", what);
+  if (host > cap)
+    return fail(REL_ECAPACITY, "%s: %lld results exceed the output capacity %lld", what,
+                static_cast<long long>(host), static_cast<long long>(cap));
+  return REL_OK;
+}
+
+}  // namespace
+}  // namespace rel
+
+extern "C" {
+
+rel_status rel_filter_sync(const rel_column* cols, int ncols, const rel_pred* preds, int npreds,
+                           rel_rowid* out, int64_t out_cap, int64_t* d_count, void* ws,
+                           size_t ws_bytes, void* stream, int64_t* count) {
+  return read_count(rel_filter(cols, ncols, preds, npreds, out, out_cap, d_count, ws, ws_bytes,
+                               stream),
+                    d_count, out_cap, stream, count, "filter");
+}
+
+rel_status rel_hash_join_sync(const rel_column* build_keys, const rel_column* probe_keys,
+                              rel_rowid* out_build, rel_rowid* out_probe, int64_t out_cap,
+                              int64_t* d_count, const rel_tuning* t, void* ws, size_t ws_bytes,
+                              void* stream, int64_t* count) {
+  return read_count(rel_hash_join(build_keys, probe_keys, out_build, out_probe, out_cap, d_count, t,
+                                  ws, ws_bytes, stream),
+                    d_count, out_cap, stream, count, "hash join");
+}
+
+rel_status rel_groupby_agg_sync(const rel_column* keys, int nkeys, const rel_column* vals,
+                                int nvals, const rel_agg* aggs, int naggs, void* const* out_keys,
+                                void* const* out_aggs, int64_t out_cap, int64_t* d_groups,
+                                int64_t max_groups, const rel_tuning* t, void* ws,
+                                size_t ws_bytes, void* stream, int64_t* groups) {
+  return read_count(rel_groupby_agg(keys, nkeys, vals, nvals, aggs, naggs, out_keys, out_aggs,
+                                    out_cap, d_groups, max_groups, t, ws, ws_bytes, stream),
+                    d_groups, out_cap, stream, groups, "group-by");
+}
+
+rel_status rel_pipeline_sync(const rel_pipeline_desc* d, const rel_outputs* o, void* ws,
+                             size_t ws_bytes, void* stream, int64_t* groups) {
+  if (!o) return fail(REL_EINVAL, "pipeline: NULL outputs");
+  return read_count(rel_pipeline(d, o, ws, ws_bytes, stream), o->d_groups, o->cap, stream, groups,
+                    "pipeline");
 }
 
 }  // extern "C"

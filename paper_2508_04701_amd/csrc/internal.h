@@ -32,6 +32,11 @@ struct ProfileScope {
   void* start;
 };
 
+// The calling thread's rel_last_error() message: set_last_error stores msg
+// and returns status; clear_last_error empties it (api.cpp).
+int set_last_error(int status, const char* msg);
+void clear_last_error();
+
 // Fills n 64-bit words with `pattern` (graph-safe replacement for memset).
 void launch_fill64(uint64_t* p, uint64_t n, uint64_t pattern, hipStream_t s);
 
@@ -370,6 +375,10 @@ struct PipelineParams {
   int32_t early_col[2];       // value columns loaded with the keys (-1: none)
   int32_t acc_src[kMaxAcc];   // 0/1: value from early_col[k]; -1: loaded late
   int32_t lds_slots;          // LDS group table slots (0: none)
+  int32_t spec;               // row spec of the fused kernels (0: generic)
+  int64_t spec_lo;            // specialised kernels: the predicate term as the range
+  uint64_t spec_span;         //   [spec_lo, spec_lo + spec_span) of the widened value
+  int32_t directable;         // every dim reserved a direct table (or there are none)
   uint32_t lds_group_offset;  // byte offset of the LDS group table
   uint32_t lds_bytes;
   int64_t ntiles;

@@ -676,6 +676,151 @@ __device__ __forceinline__ bool process_row(const PipelineParams& p, int64_t r, 
   return false;
 }
 
+// ------------------------------------------------------ row specs
+//
+// A row spec fixes at compile time where a plan's group keys and values come
+// from, so that the per-row work of the drain (gathers, key packing, the
+// accumulator inputs) has no run-time type or source decisions: spec S packs
+// key source k0 (bits 0-2), key source k1 (bits 3-5) and the value source
+// (bit 6; 1 = every accumulator reads one int64 fact column). Key sources:
+// the payload of dim 0 or dim 1, or a fact column of int8 or int32. S = 0 is
+// the generic interpreter. The host derives S from the plan (PipelineParams::
+// spec) and launches the specialised kernel when its (dims, S) variant is
+// built; a plan whose dims turn out to hold duplicate keys leaves the work to
+// the generic kernel.
+
+enum : int { kKNone = 0, kKDim0 = 1, kKDim1 = 2, kKF8 = 3, kKF32 = 4 };
+
+constexpr int spec_of(int k0, int k1, int v) { return k0 | (k1 << 3) | (v << 6); }
+
+// The row specs that are built: (dim 1 payload, int8 fact column) keys, as
+// in a star join grouped by a dim attribute and a fact flag; one dim-payload
+// key, as in a join grouped by an attribute of the build side.
+constexpr int kSpecDim1F8 = spec_of(kKDim1, kKF8, 1);
+constexpr int kSpecDim0 = spec_of(kKDim0, kKNone, 1);
+constexpr int kSpecDim1 = spec_of(kKDim1, kKNone, 1);
+
+template <int S>
+struct RowSpec {
+  static constexpr int k0 = S & 7;
+  static constexpr int k1 = (S >> 3) & 7;
+  static constexpr int nkeys = (k0 != kKNone) + (k1 != kKNone);
+  static constexpr bool value = ((S >> 6) & 1) != 0;
+};
+
+// Whether spec S can run with dim modes D0, D1: dim-payload keys need that
+// dim to be a key -> value map, and only HBM hash tables are specialised.
+template <int D>
+constexpr bool kSpecDim = D == kNone || D == kMap || D == kSet || D == kCSet;
+
+template <int D0, int D1, int S>
+constexpr bool spec_ok() {
+  if (S == 0) return true;
+  if (!kSpecDim<D0> || !kSpecDim<D1> || D0 == kNone) return false;
+  constexpr int k0 = RowSpec<S>::k0, k1 = RowSpec<S>::k1;
+  if ((k0 == kKDim0 || k1 == kKDim0) && D0 != kMap) return false;
+  if ((k0 == kKDim1 || k1 == kKDim1) && D1 != kMap) return false;
+  return true;
+}
+
+// Key j of a specialised row (fact keys gathered by row id).
+template <int K>
+__device__ __forceinline__ int64_t spec_key(const PipelineParams& p, int j, int64_t r, uint32_t v0,
+                                            uint32_t v1) {
+  if constexpr (K == kKDim0) return static_cast<int32_t>(v0);
+  else if constexpr (K == kKDim1) return static_cast<int32_t>(v1);
+  else if constexpr (K == kKF8) return static_cast<const int8_t*>(p.fact[p.key_col[j]])[r];
+  else if constexpr (K == kKF32) return static_cast<const int32_t*>(p.fact[p.key_col[j]])[r];
+  else return 0;
+}
+
+template <int S>
+__device__ __forceinline__ uint64_t spec_pack(const GroupKeyPack& kp, int64_t k0, int64_t k1) {
+  if constexpr (RowSpec<S>::nkeys == 0) return 0;
+  else if constexpr (RowSpec<S>::nkeys == 1) return static_cast<uint64_t>(k0);
+  else
+    return ((static_cast<uint64_t>(k0) & width_mask(kp.type[0])) << kp.shift0) |
+           (static_cast<uint64_t>(k1) & width_mask(kp.type[1]));
+}
+
+// Adds a row with value v to group pk under a specialised plan: every
+// accumulator reads v (acode's sources are ignored).
+__device__ __forceinline__ void spec_update(const PipelineParams& p, uint64_t pk, int64_t v,
+                                            uint64_t* lg, const GroupTable& gt, uint32_t acode) {
+  const int words = p.g.words;
+  const int32_t li = lds_group_find(lg, p.lds_slots, words, pk);
+  if (li >= 0) {
+    uint64_t* s = lg + li * words;
+    lds_add_u64(s + 1, 1);
+    int a = 0;
+    for (uint32_t code = acode; code != 0; code >>= 4, ++a)
+      lds_acc_update(s + 2 + a, static_cast<int>(((code & 15u) - 1u) & 3u), v);
+  } else {
+    uint64_t* gs = group_slot(gt, pk);
+    if (!gs) return;
+    global_add_u64(gs + 1, 1);
+    int a = 0;
+    for (uint32_t code = acode; code != 0; code >>= 4, ++a) {
+      const int kind = static_cast<int>(((code & 15u) - 1u) & 3u);
+      uint64_t* w = gs + 2 + a;
+      if (kind == kAccSum)
+        atomicAdd(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(v));
+      else if (kind == kAccMin)
+        atomicMin(reinterpret_cast<long long*>(w), static_cast<long long>(v));
+      else
+        atomicMax(reinterpret_cast<long long*>(w), static_cast<long long>(v));
+    }
+  }
+}
+
+// process_row for spec S: hash-table dims without duplicate keys, so every
+// probe is resumable and stops at its first match.
+template <int D0, int D1, int S>
+__device__ __forceinline__ bool spec_row(const PipelineParams& p, int64_t r, int32_t fk0,
+                                         int32_t fk1, uint32_t& st0, uint32_t& st1,
+                                         uint64_t* lg, const GroupTable& gt, uint32_t acode) {
+  typedef RowSpec<S> R;
+  uint4 q0 = make_uint4(0, 0, 0, 0), q1 = make_uint4(0, 0, 0, 0);
+  if constexpr (D0 != kNone) q0 = probe_load<D0>(p.dim[0], fk0, st0);
+  if constexpr (D1 != kNone) q1 = probe_load<D1>(p.dim[1], fk1, st1);
+  // fact keys and the value, gathered while the probe reads are in flight
+  int64_t f0 = 0, f1 = 0, v = 0;
+  if constexpr (R::k0 == kKF8 || R::k0 == kKF32) f0 = spec_key<R::k0>(p, 0, r, 0, 0);
+  if constexpr (R::k1 == kKF8 || R::k1 == kKF32) f1 = spec_key<R::k1>(p, 1, r, 0, 0);
+  if constexpr (R::value) v = static_cast<const int64_t*>(p.fact[p.acc_col[0]])[r];
+  uint32_t v0 = 0, v1 = 0;
+  int m0 = 1, m1 = 1;
+  if constexpr (D0 != kNone) m0 = probe_examine<D0>(p.dim[0], fk0, q0, st0, v0);
+  if constexpr (D1 != kNone) m1 = probe_examine<D1>(p.dim[1], fk1, q1, st1, v1);
+  if (m0 == 0 || m1 == 0) return false;
+  if ((m0 | m1) & 2) return true;
+  const int64_t k0 = (R::k0 == kKF8 || R::k0 == kKF32) ? f0 : spec_key<R::k0>(p, 0, r, v0, v1);
+  const int64_t k1 = (R::k1 == kKF8 || R::k1 == kKF32) ? f1 : spec_key<R::k1>(p, 1, r, v0, v1);
+  spec_update(p, spec_pack<S>(p.g.kp, k0, k1), v, lg, gt, acode);
+  return false;
+}
+
+// direct_row for spec S.
+template <int D0, int D1, int S>
+__device__ __forceinline__ void spec_direct_row(const PipelineParams& p, int64_t r, int64_t fk0,
+                                                int64_t fk1, uint64_t* lg, const GroupTable& gt,
+                                                const DirectView& dv0, const DirectView& dv1,
+                                                uint32_t acode) {
+  typedef RowSpec<S> R;
+  int64_t f0 = 0, f1 = 0, v = 0;
+  if constexpr (R::k0 == kKF8 || R::k0 == kKF32) f0 = spec_key<R::k0>(p, 0, r, 0, 0);
+  if constexpr (R::k1 == kKF8 || R::k1 == kKF32) f1 = spec_key<R::k1>(p, 1, r, 0, 0);
+  if constexpr (R::value) v = static_cast<const int64_t*>(p.fact[p.acc_col[0]])[r];
+  uint32_t v0 = 0, v1 = 0;
+  if constexpr (D0 != kNone)
+    if (!direct_probe(dv0, fk0, v0)) return;
+  if constexpr (D1 != kNone)
+    if (!direct_probe(dv1, fk1, v1)) return;
+  const int64_t k0 = (R::k0 == kKF8 || R::k0 == kKF32) ? f0 : spec_key<R::k0>(p, 0, r, v0, v1);
+  const int64_t k1 = (R::k1 == kKF8 || R::k1 == kKF32) ? f1 : spec_key<R::k1>(p, 1, r, v0, v1);
+  spec_update(p, spec_pack<S>(p.g.kp, k0, k1), v, lg, gt, acode);
+}
+
 // Processes the top `take` (<= 64) rows of the wave's queue, one per lane;
 // rows whose probes continue are written back. Returns the new queue length.
 template <int D0, int D1>
@@ -759,7 +904,7 @@ __device__ __forceinline__ void direct_row(const PipelineParams& p, int64_t r, i
 }
 
 // Processes queue entries [base, base + take), take <= 64, one per lane.
-template <int D0, int D1>
+template <int D0, int D1, int S>
 __device__ __forceinline__ void drain_direct(const PipelineParams& p, const unsigned char* wq,
                                              uint32_t base, uint32_t take, int lane,
                                              uint64_t* lg, const GroupTable& gt,
@@ -771,7 +916,10 @@ __device__ __forceinline__ void drain_direct(const PipelineParams& p, const unsi
     int64_t fk0 = 0, fk1 = 0;
     if constexpr (D0 != kNone) fk0 = qget<D0, D1, kQFk0>(wq, i);
     if constexpr (D1 != kNone) fk1 = qget<D0, D1, kQFk1>(wq, i);
-    direct_row<D0, D1>(p, r, fk0, fk1, lg, gt, dv0, dv1, acode);
+    if constexpr (S != 0)
+      spec_direct_row<D0, D1, S>(p, r, fk0, fk1, lg, gt, dv0, dv1, acode);
+    else
+      direct_row<D0, D1>(p, r, fk0, fk1, lg, gt, dv0, dv1, acode);
   }
   __builtin_amdgcn_wave_barrier();
 }
@@ -780,7 +928,7 @@ __device__ __forceinline__ void drain_direct(const PipelineParams& p, const unsi
 // predicate column (two tiles ahead) and the foreign keys, queues the passing
 // rows per wave and drains them in full-lane batches. Returns with the
 // wave's queue empty.
-template <int D0, int D1, bool kDirect>
+template <int D0, int D1, bool kDirect, int S = 0>
 __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile, int64_t end,
                                           int64_t step, unsigned char* wq, int lane,
                                           const void* ld0, const void* ld1, uint64_t* lg,
@@ -851,7 +999,7 @@ __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile,
         // at most 127 rows are queued here: one batch leaves fewer than 64
         if (queued >= kWave) {
           queued -= kWave;
-          drain_direct<D0, D1>(p, wq, queued, kWave, lane, lg, gt, dv0, dv1, acode);
+          drain_direct<D0, D1, S>(p, wq, queued, kWave, lane, lg, gt, dv0, dv1, acode);
         }
       } else {
         while (queued >= kWave)
@@ -862,11 +1010,163 @@ __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile,
   }
   __builtin_amdgcn_wave_barrier();
   if constexpr (kDirect) {
-    if (queued > 0) drain_direct<D0, D1>(p, wq, 0, queued, lane, lg, gt, dv0, dv1, acode);
+    if (queued > 0) drain_direct<D0, D1, S>(p, wq, 0, queued, lane, lg, gt, dv0, dv1, acode);
   } else {
     while (queued > 0)
       queued = drain<D0, D1>(p, wq, queued, queued < kWave ? queued : kWave, lane, ld0, ld1, lg,
                              gt, limit0, limit1, dv0, dv1, acode);
+  }
+}
+
+// ------------------------------------------------------ specialised pass
+//
+// The tile loop of the specialised kernels: at most one predicate term, on
+// an int32 column, held as the half-open range [spec_lo, spec_lo + spec_span)
+// of the widened value (the host folds every comparison but NE into it);
+// int32 foreign keys; every column that is streamed is 16-byte aligned. The
+// queue holds row ids, foreign keys and probe states as in run_tiles.
+
+// Four consecutive int32 values from r0 (non-temporal), zero past n.
+__device__ __forceinline__ void spec_load4(const int32_t* c, int64_t r0, int64_t n, int32_t v[4]) {
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  if (r0 + 4 <= n) {
+    const v4i x = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(c + r0));
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = r0 + e < n ? c[r0 + e] : 0;
+  }
+}
+
+// Processes the top `take` (<= 64) rows of the wave's queue under spec S;
+// rows whose probes continue are written back. Returns the new queue length.
+template <int D0, int D1, int S>
+__device__ __forceinline__ uint32_t spec_drain(const PipelineParams& p, unsigned char* wq,
+                                               uint32_t queued, uint32_t take, int lane,
+                                               uint64_t* lg, const GroupTable& gt,
+                                               uint32_t acode) {
+  const uint32_t base = queued - take;
+  const bool mine = static_cast<uint32_t>(lane) < take;
+  int64_t r = 0;
+  int32_t fk0 = 0, fk1 = 0;
+  uint32_t st0 = 0, st1 = 0;
+  if (mine) {
+    const uint32_t i = base + lane;
+    r = static_cast<uint32_t>(qget<D0, D1, kQRow>(wq, i));
+    if constexpr (D0 != kNone) {
+      fk0 = static_cast<int32_t>(qget<D0, D1, kQFk0>(wq, i));
+      st0 = static_cast<uint32_t>(qget<D0, D1, kQSt0>(wq, i));
+    }
+    if constexpr (D1 != kNone) {
+      fk1 = static_cast<int32_t>(qget<D0, D1, kQFk1>(wq, i));
+      st1 = static_cast<uint32_t>(qget<D0, D1, kQSt1>(wq, i));
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  bool again = false;
+  if (mine) again = spec_row<D0, D1, S>(p, r, fk0, fk1, st0, st1, lg, gt, acode);
+  const uint64_t b = ballot(again);
+  if (again) {
+    const uint32_t at = base + rank_below(b);
+    qput<D0, D1, kQRow>(wq, at, r);
+    if constexpr (D0 != kNone) {
+      qput<D0, D1, kQFk0>(wq, at, fk0);
+      qput<D0, D1, kQSt0>(wq, at, st0);
+    }
+    if constexpr (D1 != kNone) {
+      qput<D0, D1, kQFk1>(wq, at, fk1);
+      qput<D0, D1, kQSt1>(wq, at, st1);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  return base + popc64(b);
+}
+
+// One of four register values by a wave-uniform index (no indexed
+// register access, which would go through scratch).
+__device__ __forceinline__ int32_t pick4(const int32_t v[4], int e) {
+  return e == 0 ? v[0] : (e == 1 ? v[1] : (e == 2 ? v[2] : v[3]));
+}
+
+// The loop is one state machine with a single drain site and a single tile
+// site (the drain is large; inlined once per row position it would fill the
+// instruction cache): each step either drains a full batch (or, once the
+// tiles are done, the rest of the queue), loads the next tile, or appends
+// the passing rows of one row position of the current tile.
+template <int D0, int D1, int S>
+__device__ __forceinline__ void spec_tiles(const PipelineParams& p, int64_t tile, int64_t end,
+                                           int64_t step, unsigned char* wq, int lane,
+                                           uint64_t* lg, const GroupTable& gt) {
+  const uint32_t acode = acc_code(p);
+  const int tid = threadIdx.x;
+  const int64_t n = p.n;
+  const bool has_pred = p.nterms > 0;
+  const int32_t* pcol = static_cast<const int32_t*>(p.fact[p.term_col[0]]);
+  const int64_t lo = p.spec_lo;
+  const uint64_t span = p.spec_span;
+  const int32_t* fc0 = static_cast<const int32_t*>(p.fact[p.dim[0].fk_col]);
+  const int32_t* fc1 = static_cast<const int32_t*>(p.fact[p.dim[1].fk_col]);
+  int32_t pre[4] = {0, 0, 0, 0}, pre2[4] = {0, 0, 0, 0};
+  if (has_pred && tile < end) spec_load4(pcol, tile * static_cast<int64_t>(kPipeTile) + tid * 4, n, pre);
+  if (has_pred && tile + step < end)
+    spec_load4(pcol, (tile + step) * static_cast<int64_t>(kPipeTile) + tid * 4, n, pre2);
+  bool eager = true;
+  uint32_t queued = 0;  // wave-uniform
+  int e = 4;            // next row position of the current tile (4: none left)
+  int64_t r0 = 0;
+  uint32_t bits = 0;
+  int32_t fk0[4] = {0, 0, 0, 0}, fk1[4] = {0, 0, 0, 0};
+  while (true) {
+    if (queued >= kWave || (e == 4 && tile >= end && queued > 0)) {
+      queued = spec_drain<D0, D1, S>(p, wq, queued, queued < kWave ? queued : kWave, lane, lg, gt,
+                                     acode);
+      continue;
+    }
+    if (e == 4) {
+      if (tile >= end) break;
+      r0 = tile * static_cast<int64_t>(kPipeTile) + tid * 4;
+      if (eager) {
+        if constexpr (D0 != kNone) spec_load4(fc0, r0, n, fk0);
+        if constexpr (D1 != kNone) spec_load4(fc1, r0, n, fk1);
+      }
+      bits = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bool in = r0 + k < n;
+        const bool ok = !has_pred || static_cast<uint64_t>(static_cast<int64_t>(pre[k]) - lo) < span;
+        bits |= (in && ok) ? (1u << k) : 0u;
+      }
+      const int64_t ahead = tile + 2 * step;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) pre[k] = pre2[k];
+      if (has_pred && ahead < end)
+        spec_load4(pcol, ahead * static_cast<int64_t>(kPipeTile) + tid * 4, n, pre2);
+      if (!eager && bits) {
+        if constexpr (D0 != kNone) spec_load4(fc0, r0, n, fk0);
+        if constexpr (D1 != kNone) spec_load4(fc1, r0, n, fk1);
+      }
+      eager = popc64(ballot(bits != 0)) >= kWave / 4;
+      tile += step;
+      e = 0;
+      continue;
+    }
+    const bool pass = (bits >> e) & 1u;
+    const uint64_t b = ballot(pass);
+    if (pass) {
+      const uint32_t at = queued + rank_below(b);
+      qput<D0, D1, kQRow>(wq, at, r0 + e);
+      if constexpr (D0 != kNone) {
+        qput<D0, D1, kQFk0>(wq, at, pick4(fk0, e));
+        qput<D0, D1, kQSt0>(wq, at, 0);
+      }
+      if constexpr (D1 != kNone) {
+        qput<D0, D1, kQFk1>(wq, at, pick4(fk1, e));
+        qput<D0, D1, kQSt1>(wq, at, 0);
+      }
+    }
+    queued += popc64(b);
+    ++e;
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -892,6 +1192,24 @@ __device__ __forceinline__ bool all_direct(const PipelineParams& p) {
   }
 }
 
+// Whether some dim resolved to a direct table.
+template <int D0, int D1>
+__device__ __forceinline__ bool any_direct(const PipelineParams& p) {
+  if constexpr (D0 != kNone)
+    if (dim_direct<D0>(p.dim[0]).mode) return true;
+  if constexpr (D1 != kNone)
+    if (dim_direct<D1>(p.dim[1]).mode) return true;
+  return false;
+}
+
+// Whether a dim build saw a duplicate key.
+template <int D0, int D1>
+__device__ __forceinline__ bool has_dup_dims(const PipelineParams& p) {
+  if constexpr (D0 == kNone) return false;
+  else if constexpr (D1 == kNone) return *p.dim[0].map.dup != 0;
+  else return *p.dim[0].map.dup != 0 || *p.dim[1].map.dup != 0;
+}
+
 // Eight waves per SIMD (four resident workgroups per CU) where the variant
 // fits 64 VGPRs without spilling; variants with an int64 dim or an LDS copy
 // as second dim keep the compiler's own register budget.
@@ -902,6 +1220,8 @@ template <int D0, int D1>
 __global__ void __launch_bounds__(kPipeThreads)
 __attribute__((amdgpu_waves_per_eu(kFusedWaves<D0, D1>))) fused_kernel(PipelineParams p) {
   if (all_direct<D0, D1>(p)) return;  // fused_direct_kernel's case
+  // fused_spec_kernel's case
+  if (p.spec != 0 && !has_dup_dims<D0, D1>(p) && !any_direct<D0, D1>(p)) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   void* ld0 = lds + p.dim[0].lds_offset;
   void* ld1 = lds + p.dim[1].lds_offset;
@@ -920,9 +1240,28 @@ __attribute__((amdgpu_waves_per_eu(kFusedWaves<D0, D1>))) fused_kernel(PipelineP
   lds_group_flush(lg, p.lds_slots, p.g);
 }
 
+// The plan under row spec S (p.spec == S) with hash-table dims free of
+// duplicate keys; fused_kernel then returns at once.
+template <int D0, int D1, int S>
+__global__ void __launch_bounds__(kPipeThreads)
+__attribute__((amdgpu_waves_per_eu(8, 8))) fused_spec_kernel(PipelineParams p) {
+  if (any_direct<D0, D1>(p) || has_dup_dims<D0, D1>(p)) return;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  uint64_t* lg = reinterpret_cast<uint64_t*>(lds + p.lds_group_offset);
+  const int lane = lane_id();
+  unsigned char* wq = lds + p.queue_offset + (threadIdx.x / kWave) * p.queue_stride;
+  if (p.lds_slots > 0) lds_group_init(lg, p.lds_slots, p.g);
+  __syncthreads();
+  const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
+  spec_tiles<D0, D1, S>(p, blockIdx.x, p.ntiles, gridDim.x, wq, lane, lg, gt);
+  if (p.lds_slots == 0) return;
+  __syncthreads();
+  lds_group_flush(lg, p.lds_slots, p.g);
+}
+
 // The same plan when all_direct holds (fused_kernel then returns at once):
 // its own kernel, so that the lean loop gets its own register allocation.
-template <int D0, int D1>
+template <int D0, int D1, int S = 0>
 __global__ void __launch_bounds__(kPipeThreads)
 __attribute__((amdgpu_waves_per_eu(8))) fused_direct_kernel(PipelineParams p) {
   if (!all_direct<D0, D1>(p)) return;
@@ -933,8 +1272,8 @@ __attribute__((amdgpu_waves_per_eu(8))) fused_direct_kernel(PipelineParams p) {
   if (p.lds_slots > 0) lds_group_init(lg, p.lds_slots, p.g);
   __syncthreads();
   const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
-  run_tiles<D0, D1, true>(p, blockIdx.x, p.ntiles, gridDim.x, wq, lane, nullptr, nullptr, lg, gt,
-                          1, 1);
+  run_tiles<D0, D1, true, S>(p, blockIdx.x, p.ntiles, gridDim.x, wq, lane, nullptr, nullptr, lg,
+                             gt, 1, 1);
   if (p.lds_slots == 0) return;
   __syncthreads();
   lds_group_flush(lg, p.lds_slots, p.g);
@@ -972,12 +1311,6 @@ __device__ __forceinline__ int count_upto2(const PipeDim& d, int64_t key) {
   return probe_finish<D>(d, nullptr, key, 2, probe_first<D>(d, nullptr, key), v);
 }
 
-template <int D0, int D1>
-__device__ __forceinline__ bool has_dup_dims(const PipelineParams& p) {
-  if constexpr (D0 == kNone) return false;
-  else if constexpr (D1 == kNone) return *p.dim[0].map.dup != 0;
-  else return *p.dim[0].map.dup != 0 || *p.dim[1].map.dup != 0;
-}
 
 // Rows r, r + stride, ... below `end`: aggregates every row that passes and
 // matches some dim more than once.
@@ -1067,20 +1400,46 @@ inline hipError_t launch_persistent(const void* k, const PipelineParams& p, int 
 
 // Launches the fused kernel, its direct-table twin where the dim modes allow
 // one (exactly one of the two does the work, decided on the device from the
-// builds), and the duplicate-key pass. Returns the first failing HIP status.
-template <int D0, int D1>
-hipError_t launch_fused(const PipelineParams& p, int grid, hipStream_t s) {
+// builds), and the duplicate-key pass; under row spec S (p.spec == S) the
+// specialised kernel and twin as well. Returns the first failing HIP status.
+template <int D0, int D1, int S>
+hipError_t launch_fused_spec(const PipelineParams& p, int grid, hipStream_t s) {
   static int max_general = -1;
   hipError_t e = launch_persistent(reinterpret_cast<const void*>(fused_kernel<D0, D1>), p, grid,
                                    max_general, s);
   if (e != hipSuccess) return e;
-  if constexpr (kDirectOk<D0> && kDirectOk<D1>) {
-    static int max_direct = -1;
-    e = launch_persistent(reinterpret_cast<const void*>(fused_direct_kernel<D0, D1>), p, grid,
-                          max_direct, s);
+  if constexpr (S != 0) {
+    static int max_spec = -1;
+    e = launch_persistent(reinterpret_cast<const void*>(fused_spec_kernel<D0, D1, S>), p, grid,
+                          max_spec, s);
     if (e != hipSuccess) return e;
   }
+  if constexpr (kDirectOk<D0> && kDirectOk<D1>) {
+    if (p.directable) {
+      static int max_direct = -1;
+      e = launch_persistent(reinterpret_cast<const void*>(fused_direct_kernel<D0, D1, S>), p, grid,
+                            max_direct, s);
+      if (e != hipSuccess) return e;
+    }
+  }
   return launch_multi<D0, D1>(p, s);
+}
+
+// Dispatch on the plan's row spec: the specialised variants built for dim
+// modes (D0, D1), else the generic kernel (p.spec is then cleared, so that
+// the generic kernel does the work).
+template <int D0, int D1>
+hipError_t launch_fused(const PipelineParams& p, int grid, hipStream_t s) {
+  if constexpr (spec_ok<D0, D1, kSpecDim1F8>())
+    if (p.spec == kSpecDim1F8) return launch_fused_spec<D0, D1, kSpecDim1F8>(p, grid, s);
+  if constexpr (spec_ok<D0, D1, kSpecDim0>())
+    if (p.spec == kSpecDim0) return launch_fused_spec<D0, D1, kSpecDim0>(p, grid, s);
+  if constexpr (spec_ok<D0, D1, kSpecDim1>())
+    if (p.spec == kSpecDim1) return launch_fused_spec<D0, D1, kSpecDim1>(p, grid, s);
+  if (p.spec == 0) return launch_fused_spec<D0, D1, 0>(p, grid, s);
+  PipelineParams q = p;
+  q.spec = 0;
+  return launch_fused_spec<D0, D1, 0>(q, grid, s);
 }
 
 // ------------------------------------------------------------ batched plans

@@ -96,6 +96,7 @@ struct Query {
   size_t est;
   uint32_t shape;
   int64_t t_submit;
+  int64_t rows;  // fact rows the plan scans
 };
 
 struct Batch {
@@ -219,6 +220,10 @@ struct GpuExecutor {
     l.host = host;
     return REL_OK;
   }
+  static void quiesce(void* user, int lane) {
+    GpuExecutor* g = static_cast<GpuExecutor*>(user);
+    (void)hipStreamSynchronize(g->lanes[lane].stream);
+  }
   // Key column k of plan d has the type of its source column.
   static int32_t key_type(const rel_pipeline_desc& d, int k) {
     const rel_key_ref& kr = d.keys[k];
@@ -273,6 +278,8 @@ struct rel_server {
   std::deque<rel_completion> done;
   std::vector<int64_t> latencies;  // successful queries, submit -> done
   rel_server_counts counts;
+  // successful queries: fact rows scanned, first submission, last completion
+  int64_t rows_done = 0, t_first = -1, t_last = -1;
   uint64_t next_ticket = 1;
   uint64_t open = 0;  // submitted and not yet completed
   bool stop = false;
@@ -300,6 +307,9 @@ struct rel_server {
     if (st == REL_OK) {
       latencies.push_back(c.t_done_ns - c.t_submit_ns);
       ++counts.completed;
+      rows_done += q->rows;
+      if (t_first < 0 || c.t_submit_ns < t_first) t_first = c.t_submit_ns;
+      if (c.t_done_ns > t_last) t_last = c.t_done_ns;
     } else {
       ++counts.failed;
     }
@@ -370,7 +380,12 @@ struct rel_server {
       counts.batched_queries += k;
     }
     lanes[lane] = std::move(b);
-    if (st != REL_OK) complete_batch(lane, st);
+    if (st != REL_OK) {
+      // the launch may have enqueued work before failing: the block goes
+      // back to the arena only once the lane can no longer touch it
+      if (exec.quiesce) exec.quiesce(exec.user, lane);
+      complete_batch(lane, st);
+    }
     return true;
   }
 
@@ -396,6 +411,7 @@ struct rel_server {
         if (!lanes[i]) continue;
         const int r = exec.poll(exec.user, i);
         if (r == 0) continue;
+        if (r < 0 && exec.quiesce) exec.quiesce(exec.user, i);
         complete_batch(i, r > 0 ? REL_OK : static_cast<rel_status>(-r));
         progress = true;
       }
@@ -449,6 +465,7 @@ rel_status rel_server_create(const rel_server_config* c, rel_server** out) {
     s->exec.batch_ws = &GpuExecutor::batch_ws;
     s->exec.launch = &GpuExecutor::launch;
     s->exec.poll = &GpuExecutor::poll;
+    s->exec.quiesce = &GpuExecutor::quiesce;
   }
   s->arena.init(c->arena_bytes);
   s->lanes.resize(c->lanes);
@@ -480,6 +497,7 @@ rel_status rel_server_submit(rel_server* s, const rel_pipeline_desc* d, const re
   q->est = est;
   q->shape = shape_of(*d);
   q->t_submit = clock_ns();
+  q->rows = d->fact[0].len;
   {
     std::lock_guard<std::mutex> lock(s->m);
     if (s->stop) return REL_EINVAL;
@@ -513,13 +531,17 @@ rel_status rel_server_drain(rel_server* s, int64_t timeout_ms) {
 }
 
 rel_status rel_server_stats(rel_server* s, rel_server_counts* counts, int64_t* p50_ns,
-                            int64_t* p99_ns) {
+                            int64_t* p99_ns, double* rows_per_s) {
   if (!s) return REL_EINVAL;
   std::vector<int64_t> lat;
+  int64_t rows = 0, t0 = -1, t1 = -1;
   {
     std::lock_guard<std::mutex> lock(s->m);
     if (counts) *counts = s->counts;
     lat = s->latencies;
+    rows = s->rows_done;
+    t0 = s->t_first;
+    t1 = s->t_last;
   }
   auto pct = [&lat](double q) -> int64_t {
     if (lat.empty()) return -1;
@@ -532,6 +554,9 @@ rel_status rel_server_stats(rel_server* s, rel_server_counts* counts, int64_t* p
   };
   if (p50_ns) *p50_ns = pct(0.50);
   if (p99_ns) *p99_ns = pct(0.99);
+  if (rows_per_s)
+    *rows_per_s = (t0 >= 0 && t1 > t0) ? static_cast<double>(rows) * 1e9 / static_cast<double>(t1 - t0)
+                                        : 0.0;
   return REL_OK;
 }
 

@@ -105,7 +105,7 @@ SIGNATURES = {
     "rel_server_submit": (_I, [_P, _P, _P, _P, _P]),
     "rel_server_poll": (_I, [_P, _P, _I]),
     "rel_server_drain": (_I, [_P, _L]),
-    "rel_server_stats": (_I, [_P, _P, _P, _P]),
+    "rel_server_stats": (_I, [_P, _P, _P, _P, _P]),
     "rel_server_now_ns": (_L, []),
     "rel_server_destroy": (None, [_P]),
     "rel_kernel_name": (ctypes.c_char_p, [_I]),
@@ -113,6 +113,13 @@ SIGNATURES = {
     "rel_profile_read": (_I, [_P, _P]),
     "rel_stream_read": (_I, [_P, _L, _P, _P]),
     "rel_filter_noalloc": (_I, [_P, _I, _P, _I, _P, _L, _P, _P]),
+    "rel_filter_sync": (_I, [_P, _I, _P, _I, _P, _L, _P, _P, _S, _P, _P]),
+    "rel_hash_join_sync": (_I, [_P, _P, _P, _P, _L, _P, _P, _P, _S, _P, _P]),
+    "rel_groupby_agg_sync": (_I, [_P, _I, _P, _I, _P, _I, _P, _P, _L, _P, _L, _P, _P, _S, _P,
+                                  _P]),
+    "rel_pipeline_sync": (_I, [_P, _P, _P, _S, _P, _P]),
+    "rel_autotune": (_I, [_P, _I, ctypes.c_char_p]),
+    "rel_autotune_lookup": (_I, [ctypes.c_char_p, _P, _P, _P]),
 }
 
 _lib = None
@@ -233,8 +240,12 @@ def filter(cols, preds, idx=None) -> torch.Tensor:
     out = torch.empty(max(1, n), dtype=torch.int32, device=cols[0].device)
     d_count = torch.zeros(1, dtype=torch.int64, device=cols[0].device)
     ws = workspace(filter_ws(n), cols[0].device)
-    filter_async(cols, preds, out, d_count, ws, idx)
-    return out[:_count(d_count)]
+    ccols = _arr(Column, [column(c, idx) for c in cols])
+    cnt = ctypes.c_int64()
+    _check(lib().rel_filter_sync(ccols, len(cols), _preds(preds), len(preds), _addr(out),
+                                 out.numel(), _addr(d_count), _addr(ws), ws.numel(), _stream(),
+                                 ctypes.byref(cnt)))
+    return out[:cnt.value]
 
 
 # ----------------------------------------------------------------- hash join
@@ -261,14 +272,19 @@ def hash_join(build, probe, build_idx=None, probe_idx=None, out_cap=None,
     ws = workspace(hash_join_ws(build.dtype, n_build, t), dev)
     d_count = torch.zeros(1, dtype=torch.int64, device=dev)
     cap = max(1, n_probe if out_cap is None else out_cap)
+    cb, cp = column(build, build_idx), column(probe, probe_idx)
+    total = ctypes.c_int64()
     while True:
         ob = torch.empty(cap, dtype=torch.int32, device=dev)
         op = torch.empty(cap, dtype=torch.int32, device=dev)
-        hash_join_async(build, probe, ob, op, d_count, ws, build_idx, probe_idx, t)
-        total = _count(d_count)
-        if total <= cap:
-            return ob[:total], op[:total]
-        cap = total
+        st = lib().rel_hash_join_sync(ctypes.byref(cb), ctypes.byref(cp), _addr(ob), _addr(op),
+                                      cap, _addr(d_count), _tuning_ptr(t), _addr(ws), ws.numel(),
+                                      _stream(), ctypes.byref(total))
+        if st == REL_ECAPACITY:
+            cap = total.value  # more pairs than the output holds: grow it and join again
+            continue
+        _check(st)
+        return ob[:total.value], op[:total.value]
 
 
 # ------------------------------------------------------------------ group-by
@@ -309,16 +325,23 @@ def groupby_agg(keys, vals, aggs, max_groups: int | None = None, key_idx=None, v
     ws = workspace(groupby_ws(key_dtypes, aggs, n, max_groups, t), dev)
     d_groups = torch.zeros(1, dtype=torch.int64, device=dev)
     cap = max(1, min(max_groups, max(1, n)))
+    ck = _arr(Column, [column(k, key_idx) for k in keys])
+    cv = _arr(Column, [column(v, val_idx) for v in vals])
+    ng = ctypes.c_int64()
     while True:
         out_keys, out_aggs = _out_tensors(key_dtypes, aggs, cap, dev)
-        groupby_agg_async(keys, vals, aggs, out_keys, out_aggs, d_groups, max_groups, ws,
-                          key_idx, val_idx, t)
-        ng = _count(d_groups)
-        if ng < 0:
+        ok = _arr(ctypes.c_void_p, [o.data_ptr() for o in out_keys])
+        oa = _arr(ctypes.c_void_p, [o.data_ptr() for o in out_aggs])
+        st = lib().rel_groupby_agg_sync(ck, len(keys), cv, len(vals), _aggs(aggs), len(aggs), ok,
+                                        oa, cap, _addr(d_groups), max_groups, _tuning_ptr(t),
+                                        _addr(ws), ws.numel(), _stream(), ctypes.byref(ng))
+        if st == REL_ECAPACITY and ng.value < 0:
             raise RelError(REL_ECAPACITY, f"more than max_groups={max_groups} groups")
-        if ng <= cap:
-            return [k[:ng] for k in out_keys], [a[:ng] for a in out_aggs]
-        cap = ng
+        if st == REL_ECAPACITY:
+            cap = ng.value
+            continue
+        _check(st)
+        return [k[:ng.value] for k in out_keys], [a[:ng.value] for a in out_aggs]
 
 
 # ------------------------------------------------------------------ pipeline
@@ -391,6 +414,14 @@ class PreparedPipeline(Plan):
         _check(lib().rel_pipeline(ctypes.byref(self.desc), ctypes.byref(self.outputs),
                                   _addr(self.ws), self.ws.numel(), _stream()))
 
+    def run(self):
+        """rel_pipeline_sync: runs the plan, waits, returns (keys, aggs)."""
+        ng = ctypes.c_int64()
+        _check(lib().rel_pipeline_sync(ctypes.byref(self.desc), ctypes.byref(self.outputs),
+                                       _addr(self.ws), self.ws.numel(), _stream(),
+                                       ctypes.byref(ng)))
+        return [k[:ng.value] for k in self.out_keys], [a[:ng.value] for a in self.out_aggs]
+
 
 class PreparedBatch:
     """Plans of one shape run together by rel_pipeline_batch, sharing one
@@ -448,9 +479,7 @@ class PreparedBatch:
 
 def pipeline(fact, preds, dims, keys, aggs, max_groups: int, t: Tuning | None = None):
     """Runs the fused plan and returns (key columns, aggregate columns)."""
-    p = PreparedPipeline(fact, preds, dims, keys, aggs, max_groups, t)
-    p.launch()
-    return p.result()
+    return PreparedPipeline(fact, preds, dims, keys, aggs, max_groups, t).run()
 
 
 # ---------------------------------------------------------------- stream read

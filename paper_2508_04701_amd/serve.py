@@ -23,11 +23,12 @@ LAUNCH = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_
                           ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                           ctypes.c_size_t)
 POLL = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int)
+QUIESCE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int)
 
 
 class Executor(ctypes.Structure):
     _fields_ = [("user", ctypes.c_void_p), ("batch_ws", BATCH_WS), ("launch", LAUNCH),
-                ("poll", POLL)]
+                ("poll", POLL), ("quiesce", QUIESCE)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -131,8 +132,11 @@ class Server:
     def stats(self) -> dict:
         c = Counts()
         p50, p99 = ctypes.c_int64(), ctypes.c_int64()
-        rel.lib().rel_server_stats(self._h, ctypes.byref(c), ctypes.byref(p50), ctypes.byref(p99))
+        rate = ctypes.c_double()
+        rel.lib().rel_server_stats(self._h, ctypes.byref(c), ctypes.byref(p50), ctypes.byref(p99),
+                                   ctypes.byref(rate))
         d = {n: getattr(c, n) for n, _ in Counts._fields_}
+        d["rows_per_s"] = rate.value
         d["p50_ms"] = p50.value / 1e6 if p50.value >= 0 else None
         d["p99_ms"] = p99.value / 1e6 if p99.value >= 0 else None
         return d

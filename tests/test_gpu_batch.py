@@ -275,3 +275,33 @@ def test_autotuner_groupby_fanout_candidates_agree():
     got = rel.groupby_agg([dev(k)], [dev(v)], aggs, max_groups=200_000,
                           t=autotune.to_tuning(rec["tuning"]))
     assert_groups(got, oracle.groupby([k], [v], aggs), aggs, "tuned group-by")
+
+
+def test_native_autotuner_records_and_lookups(tmp_path):
+    """rel_autotune through the C-ABI: every candidate (load factor, fan-out,
+    block shape, LDS group table, replicas) returns the same groups (it
+    fails otherwise), one record per bucket lands in the JSON cache with all
+    fifteen candidates timed, rel_autotune_lookup returns it, and a batch
+    whose instances carry the looked-up records equals the oracle."""
+    import json
+
+    from paper_2508_04701_amd import autotune
+    announce("native autotuner")
+    insts = join_instances(717, 4, (1_000, 200_000), (10_000, 2_000_000), (8, 20_000))
+    specs = [join_spec(i) for i in insts]
+    path = str(tmp_path / "tune.json")
+    plans = [device_plan(s) for s in specs]
+    autotune.tune_batch_plans(plans, path)
+    recs = json.load(open(path))
+    keys = {k for k in recs if "/pipeline_batch/" in k}
+    assert len(keys) == len({autotune.plan_bucket(len(s[0][0]), [len(s[2][0]["key"])], s[5])
+                             for s in specs})
+    for k in keys:
+        assert len(recs[k]["candidates"]) == 15 and recs[k]["ms"] > 0
+    tuned = [device_plan(s, autotune.lookup(path, p)) for s, p in zip(specs, plans)]
+    assert all(autotune.lookup(path, p) is not None for p in plans)
+    b = rel.PreparedBatch(tuned)
+    b.launch()
+    torch.cuda.synchronize()
+    for i, (spec, plan) in enumerate(zip(specs, b.plans)):
+        assert_groups(plan.result(), oracle_of(spec), AGGS, f"native-tuned instance {i}")

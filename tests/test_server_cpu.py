@@ -75,7 +75,7 @@ class OracleExecutor:
     """Runs a batch with the oracle when it is launched and reports it done
     `delay` seconds later; records what the scheduler asked for."""
 
-    def __init__(self, plans, lanes, delay=0.003, fail_poll_at=None):
+    def __init__(self, plans, lanes, delay=0.003, fail_poll_at=None, fail_launch_at=None):
         self.by_count = {p.count.ctypes.data: p for p in plans}
         self.delay = delay
         self.lane_until = [None] * lanes
@@ -86,9 +86,11 @@ class OracleExecutor:
         self.max_active_lanes = 0
         self.errors = []
         self.fail_poll_at = fail_poll_at
+        self.fail_launch_at = fail_launch_at
+        self.quiesced = []
         self.lock = threading.Lock()
         self.struct = serve.Executor(None, serve.BATCH_WS(self._ws), serve.LAUNCH(self._launch),
-                                     serve.POLL(self._poll))
+                                     serve.POLL(self._poll), serve.QUIESCE(self._quiesce))
 
     def _ws(self, user, d, n):
         return rel.lib().rel_pipeline_batch_ws(d, n)
@@ -120,10 +122,24 @@ class OracleExecutor:
                 self.max_active_lanes = max(self.max_active_lanes, len(self.active))
                 self.lane_until[lane] = time.monotonic() + self.delay
                 self.lane_fail[lane] = self.fail_poll_at == len(self.launches)
+                if self.fail_launch_at == len(self.launches):
+                    # fails after its work was enqueued: the lane stays busy
+                    # with this workspace until quiesce() has waited for it
+                    return rel.REL_EDEVICE
             return rel.REL_OK
         except Exception as e:  # reported by the test, never raised into C
             self.errors.append(repr(e))
             return rel.REL_EDEVICE
+
+    def _quiesce(self, user, lane):
+        with self.lock:
+            until = self.lane_until[lane]
+        if until is not None:
+            time.sleep(max(0.0, until - time.monotonic()))
+        with self.lock:
+            self.lane_until[lane] = None
+            self.active.pop(lane, None)
+            self.quiesced.append(lane)
 
     def _poll(self, user, lane):
         with self.lock:
@@ -182,9 +198,11 @@ def test_burst_is_batched_in_fifo_order_within_limits():
     plans = [query(data, 40 * i, 300 + i) for i in range(40)]
     ex = OracleExecutor(plans, lanes=2, delay=0.004)
     srv = make_server(ex, max_slots=12, max_batch=5, lanes=2)
+    t_start = time.monotonic()
     tickets = [srv.submit(p) for p in plans]
     got = wait_all(srv, len(plans))
     assert srv.drain(10)
+    t_end = time.monotonic()
     st = srv.stats()
     srv.close()
     assert not ex.errors, ex.errors
@@ -198,6 +216,9 @@ def test_burst_is_batched_in_fifo_order_within_limits():
     assert order == plans, "queries of one shape launch in submission order"
     assert st["completed"] == 40 and st["batches"] == len(ex.launches)
     assert st["p50_ms"] is not None and st["p99_ms"] >= st["p50_ms"]
+    # rows/s over the successful queries: 40 queries of 3000 fact rows, between
+    # the first submission and the last completion (inside the measured span)
+    assert 40 * 3000 / (t_end - t_start) <= st["rows_per_s"] < float("inf")
     check_results(plans)
 
 
@@ -344,3 +365,27 @@ def test_second_lane_opens_only_for_a_backlog():
     assert len(got) == 3 and all(c["status"] == 0 for c in got.values())
     assert ex.max_active_lanes == 1
     check_results(plans)
+
+
+def test_failed_launch_releases_its_workspace_only_after_quiesce():
+    """A launch that fails after enqueueing work: the scheduler waits for the
+    lane (executor quiesce) before the batch's arena block can be handed to
+    another batch; the executor reports any workspace overlap with a lane
+    whose work has not drained, and any launch on a lane still busy."""
+    data = star(5)
+    plans = [query(data, 30 * i, 200 + i) for i in range(12)]
+    ex = OracleExecutor(plans, lanes=2, delay=0.02, fail_launch_at=1)
+    srv = make_server(ex, max_slots=4, max_batch=2, lanes=2)
+    tickets = [srv.submit(p) for p in plans]
+    got = wait_all(srv, len(plans))
+    assert srv.drain(10)
+    st = srv.stats()
+    srv.close()
+    assert not ex.errors, ex.errors
+    assert ex.quiesced and ex.quiesced[0] == ex.launches[0][1]
+    first = {id(p) for p in ex.launches[0][2]}
+    for t, p in zip(tickets, plans):
+        assert (got[t]["status"] != 0) == (id(p) in first)
+    assert st["failed"] == len(first) and st["completed"] == 12 - len(first)
+    # the next batches reused the arena from offset 0 once the lane drained
+    assert any(off == ex.launches[0][3] for _, _, _, off, _ in ex.launches[1:])
