@@ -57,6 +57,14 @@ def _open(path: str):
     lib.oracle_pipeline.restype = L
     lib.oracle_pipeline.argtypes = [I, P, P, L, I, P, P, P, P, I, P, P, P, P, P, P,
                                     I, P, P, I, P, P, P, P, L]
+    lib.oracle_semi_join.restype = L
+    lib.oracle_semi_join.argtypes = [P, P, I, L, L, P]
+    lib.oracle_gather.restype = None
+    lib.oracle_gather.argtypes = [P, I, P, L, P]
+    lib.oracle_topn.restype = L
+    lib.oracle_topn.argtypes = [L, P, I, I, I, P, L, P]
+    lib.oracle_groupby_str.restype = L
+    lib.oracle_groupby_str.argtypes = [L, P, P, P, I, I, P, P, I, P, P, P, P, P, L]
     return lib
 
 
@@ -126,6 +134,24 @@ class Oracle:
         """Fused filter -> inner join with up to two dims -> group-by."""
         return _pipeline(self.lib, fact, terms, dims, keys, aggs)
 
+    def semi_join(self, build, probe):
+        """Probe row ids (uint32, ascending) with at least one equal build key."""
+        return _semi_join(self.lib, build, probe)
+
+    def gather(self, col, idx):
+        """col[idx[i]] widened to int64 (late materialisation)."""
+        return _gather(self.lib, col, idx)
+
+    def topn(self, order, keys, limit, desc=True):
+        """Row positions of the first `limit` rows ordered by `order` (int64
+        or float64; descending when desc), ties by the key tuple ascending."""
+        return _topn(self.lib, order, keys, limit, desc)
+
+    def groupby_str(self, offsets, data, vals, aggs, ikey=None):
+        """Group-by on the string key (Arrow offsets/bytes) and optional int
+        key: (first row ids, int keys, aggregate columns) by (string, int key)."""
+        return _groupby_str(self.lib, offsets, data, vals, aggs, ikey)
+
 
 _default = None
 
@@ -151,6 +177,81 @@ def groupby(keys, vals, aggs):
 
 def pipeline(fact, terms, dims, keys, aggs):
     return default().pipeline(fact, terms, dims, keys, aggs)
+
+
+def semi_join(build, probe):
+    return default().semi_join(build, probe)
+
+
+def gather(col, idx):
+    return default().gather(col, idx)
+
+
+def topn(order, keys, limit, desc=True):
+    return default().topn(order, keys, limit, desc)
+
+
+def groupby_str(offsets, data, vals, aggs, ikey=None):
+    return default().groupby_str(offsets, data, vals, aggs, ikey)
+
+
+def _semi_join(lib, build, probe) -> np.ndarray:
+    build, probe = _col(build), _col(probe)
+    if build.dtype != probe.dtype:
+        raise TypeError("build and probe key types differ")
+    k = _Arr()
+    out = np.empty(max(1, len(probe)), dtype=np.uint32)
+    cnt = lib.oracle_semi_join(k.ptr(build), k.ptr(probe), _TYPES[build.dtype], len(build),
+                               len(probe), k.ptr(out))
+    return out[:cnt].copy()
+
+
+def _gather(lib, col, idx) -> np.ndarray:
+    col = _col(col)
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    k = _Arr()
+    out = np.empty(max(1, len(idx)), dtype=np.int64)
+    lib.oracle_gather(k.ptr(col), _TYPES[col.dtype], k.ptr(idx), len(idx), k.ptr(out))
+    return out[:len(idx)].copy()
+
+
+def _topn(lib, order, keys, limit, desc=True) -> np.ndarray:
+    order = np.ascontiguousarray(order)
+    if order.dtype not in (np.dtype(np.int64), np.dtype(np.float64)):
+        raise TypeError("top-N orders by an int64 or float64 column")
+    keys = [np.ascontiguousarray(c, dtype=np.int64) for c in keys]
+    n = len(order)
+    k = _Arr()
+    out = np.empty(max(1, min(limit, n)), dtype=np.uint32)
+    m = lib.oracle_topn(n, k.ptr(order), 1 if order.dtype == np.float64 else 0, 1 if desc else 0,
+                        len(keys), k.ptrs(keys), int(limit), k.ptr(out))
+    return out[:m].copy()
+
+
+def _groupby_str(lib, offsets, data, vals, aggs, ikey=None):
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    data = np.ascontiguousarray(data, dtype=np.uint8)
+    n = len(offsets) - 1
+    vals = [_col(c) for c in vals]
+    ik = None if ikey is None else _col(ikey)
+    k = _Arr()
+    vp, vt = k.ptrs(vals), k.ints([_TYPES[c.dtype] for c in vals])
+    ao = k.ints([AGG_OPS[a[0]] for a in aggs])
+    ac = k.ints([a[1] if a[1] is not None else 0 for a in aggs])
+    cap = max(1, min(n, 1 << 16))
+    while True:
+        rows = np.zeros(cap, dtype=np.uint32)
+        iks = np.zeros(cap, dtype=np.int64)
+        out_aggs = np.zeros(max(1, len(aggs)) * cap, dtype=np.int64)
+        ng = lib.oracle_groupby_str(n, k.ptr(offsets), k.ptr(data if len(data) else
+                                                              np.zeros(1, np.uint8)),
+                                    k.ptr(ik), 0 if ik is None else _TYPES[ik.dtype], len(vals),
+                                    vp, vt, len(aggs), ao, ac, k.ptr(rows), k.ptr(iks),
+                                    k.ptr(out_aggs), cap)
+        if ng <= cap:
+            break
+        cap = ng
+    return rows[:ng].copy(), iks[:ng].copy(), _agg_results(aggs, out_aggs, ng, cap)
 
 
 def _filter(lib, cols, terms, sel=None) -> np.ndarray:

@@ -19,7 +19,19 @@
 //                     of 64-bit integer values;
 //   * pipeline      - filter -> inner join against up to two dimension
 //                     tables -> group-by, one fact row at a time, which is the
-//                     "whole query plan on the GPU" path of Section 3.1.
+//                     "whole query plan on the GPU" path of Section 3.1;
+//   * semi-join     - the probe rows that have at least one equal build key
+//                     (what a Bloom-filter predicate transfer approximates
+//                     from above, Section 3.4, "Performance Optimizations");
+//   * gather        - late materialisation of a column by row ids
+//                     (Section 3.2.2);
+//   * top-N         - the first N rows of a result table in the order of one
+//                     of its columns, ties broken by the key tuple (the
+//                     order-by / top-N operators named among ClickBench's
+//                     costs, Section 4.2);
+//   * string group-by - group-by on a variable-length string key (Arrow
+//                     offsets + bytes), optionally with one integer key
+//                     beside it (group-by cost on string keys, Section 4.2).
 // The join and group-by use std::unordered_map, as the operator semantics
 // require nothing more. Output order: filter follows scan order; join pairs
 // are emitted sorted by (probe row, build row); groups are emitted sorted by
@@ -39,7 +51,12 @@
 #include <cstring>
 #include <functional>
 #include <limits>
+#include <map>
+#include <numeric>
+#include <string>
 #include <unordered_map>
+#include <unordered_set>
+#include <utility>
 #include <vector>
 
 namespace {
@@ -285,6 +302,99 @@ int64_t oracle_pipeline(int nfact, const void* const* fact, const int* fact_type
     }
   }
   return emit_groups(groups, nkeys, naggs, agg_op, out_keys, out_aggs, cap);
+}
+
+// Semi-join: writes the probe row ids p (ascending) for which some build
+// row b has build[b] == probe[p]; returns their number (out holds np).
+int64_t oracle_semi_join(const void* build, const void* probe, int key_type, int64_t nb,
+                         int64_t np, uint32_t* out) {
+  std::unordered_set<int64_t> keys;
+  for (int64_t b = 0; b < nb; ++b) keys.insert(read_value(build, key_type, b));
+  int64_t written = 0;
+  for (int64_t p = 0; p < np; ++p)
+    if (keys.count(read_value(probe, key_type, p))) out[written++] = static_cast<uint32_t>(p);
+  return written;
+}
+
+// Late materialisation: out[i] = col[idx[i]] widened to int64, i < n.
+void oracle_gather(const void* col, int type, const uint32_t* idx, int64_t n, int64_t* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = read_value(col, type, idx[i]);
+}
+
+// Order-by / top-N over a result table of n rows: row r has the order value
+// order[r] (int64, or binary64 when order_is_double) and the key tuple
+// (keys[0][r], ..., keys[nkeys-1][r]). Rows are sorted by the order value,
+// descending when desc, ties by the key tuple ascending (signed,
+// lexicographic); the first min(limit, n) row positions go to out. Returns
+// that count.
+int64_t oracle_topn(int64_t n, const void* order, int order_is_double, int desc, int nkeys,
+                    const int64_t* const* keys, int64_t limit, uint32_t* out) {
+  std::vector<uint32_t> rows(static_cast<size_t>(n));
+  std::iota(rows.begin(), rows.end(), 0u);
+  auto value_less = [&](uint32_t a, uint32_t b) {
+    if (order_is_double) {
+      const double x = static_cast<const double*>(order)[a], y = static_cast<const double*>(order)[b];
+      return x < y;
+    }
+    return static_cast<const int64_t*>(order)[a] < static_cast<const int64_t*>(order)[b];
+  };
+  auto before = [&](uint32_t a, uint32_t b) {
+    const bool lt = value_less(a, b), gt = value_less(b, a);
+    if (lt || gt) return desc ? gt : lt;
+    for (int k = 0; k < nkeys; ++k)
+      if (keys[k][a] != keys[k][b]) return keys[k][a] < keys[k][b];
+    return a < b;
+  };
+  std::sort(rows.begin(), rows.end(), before);
+  const int64_t m = std::min<int64_t>(limit, n);
+  for (int64_t i = 0; i < m; ++i) out[i] = rows[i];
+  return m;
+}
+
+// Group-by on a string key, optionally with one integer key: row i's
+// string is bytes[offsets[i] .. offsets[i+1]) (Arrow layout), its integer
+// key ikey[i] when ikey_type != 0. Groups are ordered by (string, integer
+// key), strings byte-wise as unsigned bytes (a prefix first). Per group:
+// out_row = the smallest row id of the group, out_ikey = its integer key,
+// out_aggs[a * cap + g] = aggregate a as in oracle_groupby. Returns the group
+// count; writes the first cap groups.
+int64_t oracle_groupby_str(int64_t n, const int64_t* offsets, const uint8_t* bytes,
+                           const void* ikey, int ikey_type, int nvals, const void* const* vals,
+                           const int* val_types, int naggs, const int* agg_op,
+                           const int* agg_col, uint32_t* out_row, int64_t* out_ikey,
+                           int64_t* out_aggs, int64_t cap) {
+  (void)nvals;
+  struct Group {
+    uint32_t first;
+    std::vector<AggState> acc;
+  };
+  std::map<std::pair<std::string, int64_t>, Group> groups;
+  for (int64_t i = 0; i < n; ++i) {
+    std::string key(reinterpret_cast<const char*>(bytes + offsets[i]),
+                    static_cast<size_t>(offsets[i + 1] - offsets[i]));
+    const int64_t k2 = ikey_type ? read_value(ikey, ikey_type, i) : 0;
+    auto it = groups.find({key, k2});
+    if (it == groups.end()) {
+      Group g;
+      g.first = static_cast<uint32_t>(i);
+      g.acc.resize(naggs);
+      it = groups.emplace(std::make_pair(key, k2), std::move(g)).first;
+    }
+    for (int a = 0; a < naggs; ++a) {
+      const int64_t v = agg_op[a] == OA_COUNT ? 0 : read_value(vals[agg_col[a]], val_types[agg_col[a]], i);
+      it->second.acc[a].add(v);
+    }
+  }
+  int64_t g = 0;
+  for (const auto& kv : groups) {
+    if (g < cap) {
+      out_row[g] = kv.second.first;
+      out_ikey[g] = kv.first.second;
+      for (int a = 0; a < naggs; ++a) out_aggs[a * cap + g] = kv.second.acc[a].result(agg_op[a]);
+    }
+    ++g;
+  }
+  return g;
 }
 
 }  // extern "C"

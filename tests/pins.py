@@ -385,8 +385,148 @@ def pin_pipeline_invariants(orc):
         assert int(c[kr == g].sum()) == int(m.sum()), "region marginal"
 
 
+# ------------------------------------------------------------- semi-join
+
+def bf_semi_join(build, probe):
+    """Nested loop: probe rows with at least one equal build key."""
+    bl = [int(x) for x in build]
+    return np.array([p for p, k in enumerate(int(x) for x in probe) if any(k == b for b in bl)],
+                    dtype=np.uint32)
+
+
+def pin_semi_join_brute_force(orc):
+    for seed in range(12):
+        rng = _rng(400 + seed)
+        dtype = np.int32 if seed % 2 else np.int64
+        build = _tiny_col(rng, int(rng.integers(0, 100)), dtype, 8)
+        probe = _tiny_col(rng, int(rng.integers(0, 150)), dtype, 10)
+        assert np.array_equal(orc.semi_join(build, probe), bf_semi_join(build, probe)), \
+            f"semi-join seed {seed}"
+
+
+def pin_semi_join_closed_forms(orc):
+    # build = iota(nb), probe p = p mod K: p matches iff p mod K < nb
+    for nb, npr, K in ((1000, 10_000, 1500), (64, 5000, 64), (0, 100, 7), (10, 0, 3)):
+        got = orc.semi_join(np.arange(nb, dtype=np.int64), (np.arange(npr) % K).astype(np.int64))
+        expect = (npr // K) * min(nb, K) + min(npr % K, nb) if K else 0
+        assert len(got) == expect, "semi-join count"
+        assert np.all(got % K < nb) and np.all(np.diff(got.astype(np.int64)) > 0), "rows, order"
+    # duplicates on the build side do not repeat probe rows
+    b = np.array([5, 5, 5, 7], np.int32)
+    p = np.array([7, 5, 1, 5], np.int32)
+    assert np.array_equal(orc.semi_join(b, p), np.array([0, 1, 3], np.uint32)), "dup build keys"
+
+
+# --------------------------------------------------------------- gather
+
+def pin_gather(orc):
+    rng = _rng(8)
+    for dtype in (np.int8, np.int32, np.int64):
+        col = _tiny_col(rng, 500, dtype, 1000)
+        idx = rng.integers(0, 500, size=2000).astype(np.uint32)
+        got = orc.gather(col, idx)
+        assert got.dtype == np.int64
+        assert np.array_equal(got, col[idx].astype(np.int64)), f"gather {dtype}"  # numpy indexing
+    assert len(orc.gather(np.zeros(3, np.int32), np.zeros(0, np.uint32))) == 0
+
+
+# ---------------------------------------------------------------- top-N
+
+def _check_topn(order, keys, limit, desc, got):
+    """Selection property, without sorting: the result is ordered, and no
+    left-out row comes before the last one taken (order value, then key tuple)."""
+    n = len(order)
+    assert len(got) == min(limit, n), "top-N size"
+    assert len(set(got.tolist())) == len(got), "top-N rows distinct"
+
+    def before(a, b):
+        x, y = order[a], order[b]
+        if x != y:
+            return x > y if desc else x < y
+        return tuple(int(k[a]) for k in keys) < tuple(int(k[b]) for k in keys)
+
+    for i in range(1, len(got)):
+        assert before(got[i - 1], got[i]), "top-N ordered"
+    if len(got) and len(got) < n:
+        last = got[-1]
+        left = set(range(n)) - set(got.tolist())
+        assert not any(before(r, last) for r in left), "a left-out row belongs in the top-N"
+
+
+def pin_topn_selection(orc):
+    for seed in range(10):
+        rng = _rng(500 + seed)
+        n = int(rng.integers(0, 300))
+        keys = [rng.permutation(n).astype(np.int64)] if seed % 2 else \
+            [rng.integers(0, 5, size=n).astype(np.int64), rng.permutation(n).astype(np.int64)]
+        if seed % 3 == 0:
+            order = rng.normal(size=n).round(1)  # float64 with ties
+        else:
+            order = rng.integers(-5, 5, size=n).astype(np.int64)  # heavy ties
+        for limit in (0, 1, 7, n, n + 5):
+            for desc in (True, False):
+                _check_topn(order, keys, limit, desc, orc.topn(order, keys, limit, desc))
+    # all values distinct: the top-N of a permutation is closed-form
+    perm = _rng(9).permutation(1000).astype(np.int64)
+    got = orc.topn(perm, [np.arange(1000, dtype=np.int64)], 10)
+    assert np.array_equal(perm[got], np.arange(999, 989, -1)), "top-10 of a permutation"
+
+
+# ------------------------------------------------------ string group-by
+
+def _strings(rng, n, alphabet=3, maxlen=4):
+    words = ["".join(chr(97 + int(c)) for c in rng.integers(0, alphabet, size=int(rng.integers(0, maxlen + 1))))
+             for _ in range(n)]
+    data = "".join(words).encode()
+    offsets = np.zeros(n + 1, np.int64)
+    offsets[1:] = np.cumsum([len(w) for w in words])
+    return words, offsets, np.frombuffer(data, dtype=np.uint8).copy() if data else np.zeros(0, np.uint8)
+
+
+def pin_groupby_str_brute_force(orc):
+    aggs = [("sum", 0), ("count", None), ("min", 0), ("max", 0), ("avg", 0)]
+    for seed in range(10):
+        rng = _rng(600 + seed)
+        n = int(rng.integers(0, 150))
+        words, offsets, data = _strings(rng, n)
+        v = _tiny_col(rng, n, np.int64, 1000)
+        ik = rng.integers(-2, 2, size=n).astype(np.int32) if seed % 2 else None
+        rows, iks, got = orc.groupby_str(offsets, data, [v], aggs, ik)
+        # brute force: a dict keyed by (bytes, int key), ordered by sorting
+        groups = {}
+        for i, w in enumerate(words):
+            key = (w.encode(), int(ik[i]) if ik is not None else 0)
+            groups.setdefault(key, []).append(i)
+        order = sorted(groups)
+        assert len(rows) == len(order), f"string groups seed {seed}"
+        for g, key in enumerate(order):
+            members = groups[key]
+            assert rows[g] == members[0] and iks[g] == key[1], "first row and int key"
+            vals = [int(v[i]) for i in members]
+            assert got[0][g] == wrap64(sum(vals)) and got[1][g] == len(vals)
+            assert got[2][g] == min(vals) and got[3][g] == max(vals)
+            assert got[4][g] == avg_value(wrap64(sum(vals)), len(vals))
+
+
+def pin_groupby_str_invariants(orc):
+    rng = _rng(11)
+    words, offsets, data = _strings(rng, 20_000, alphabet=4, maxlen=6)
+    v = rng.integers(0, 10**6, size=20_000).astype(np.int64)
+    rows, _, (s, c) = orc.groupby_str(offsets, data, [v], [("sum", 0), ("count", None)])
+    assert int(c.sum()) == 20_000 and int(s.sum()) == int(v.sum()), "sum COUNT, sum SUM"
+    assert len(rows) == len(set(words)), "one group per distinct string"
+    firsts = {}
+    for i, w in enumerate(words):
+        firsts.setdefault(w, i)
+    assert sorted(rows.tolist()) == sorted(firsts.values()), "each group's first row"
+    keys = [words[r].encode() for r in rows]
+    assert keys == sorted(keys), "groups in byte order"
+
+
 ALL_PINS = [
     pin_filter_brute_force, pin_filter_closed_forms, pin_join_brute_force, pin_join_closed_forms,
     pin_join_invariants, pin_groupby_brute_force, pin_groupby_closed_forms, pin_groupby_arithmetic,
-    pin_pipeline_brute_force, pin_pipeline_invariants,
+    pin_pipeline_brute_force, pin_pipeline_invariants, pin_semi_join_brute_force,
+    pin_semi_join_closed_forms, pin_gather, pin_topn_selection, pin_groupby_str_brute_force,
+    pin_groupby_str_invariants,
 ]

@@ -32,6 +32,19 @@ MUTANTS = [
     ("pipeline_second_dim_ignored", "for (uint32_t b1 : *match[1]) {", "for (uint32_t b1 : no_dim) {"),
     ("pipeline_unmatched_rows_kept", "dropped = true;\n        break;", "continue;"),
     ("pipeline_filter_ignored", "if (!pred.holds(fact, fact_types, i)) continue;", ""),
+    ("semi_join_keeps_misses", "if (keys.count(read_value(probe, key_type, p))) out[written++]",
+     "if (!keys.count(read_value(probe, key_type, p))) out[written++]"),
+    ("gather_reads_row_id", "out[i] = read_value(col, type, idx[i]);", "out[i] = read_value(col, type, i);"),
+    ("topn_ascending_when_desc", "return desc ? gt : lt;", "return desc ? lt : gt;"),
+    ("topn_ties_by_position", "if (keys[k][a] != keys[k][b]) return keys[k][a] < keys[k][b];", ""),
+    ("topn_drops_last", "for (int64_t i = 0; i < m; ++i) out[i] = rows[i];",
+     "for (int64_t i = 0; i < m; ++i) out[i] = rows[i + (i + 1 == m && m < n ? 1 : 0)];"),
+    ("string_groups_ignore_int_key", "const int64_t k2 = ikey_type ? read_value(ikey, ikey_type, i) : 0;",
+     "const int64_t k2 = 0;"),
+    ("string_keys_truncated", "static_cast<size_t>(offsets[i + 1] - offsets[i]));",
+     "static_cast<size_t>(std::min<int64_t>(offsets[i + 1] - offsets[i], 2)));"),
+    ("string_group_last_row", "auto it = groups.find({key, k2});\n    if (it == groups.end()) {",
+     "auto it = groups.find({key, k2});\n    if (it != groups.end()) it->second.first = static_cast<uint32_t>(i);\n    if (it == groups.end()) {"),
     ("ungrouped_empty_has_no_row", "if (nkeys == 0) groups[std::vector<int64_t>()].resize(naggs);\n  std::vector<int64_t> key(nkeys);\n  for (int64_t i = 0; i < n; ++i) {\n    for (int k",
      "std::vector<int64_t> key(nkeys);\n  for (int64_t i = 0; i < n; ++i) {\n    for (int k"),
 ]
