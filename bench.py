@@ -472,6 +472,10 @@ def bench_ops(args, torch, datagen, rel) -> dict:
     del ws, ob, op
     torch.cuda.empty_cache()
 
+    res.update(bench_bloom(args, torch, datagen, rel, kernel_ms, line))
+    res.update(bench_strings(args, torch, datagen, rel, kernel_ms, line))
+    res.update(bench_topn(args, torch, datagen, rel, kernel_ms, line))
+
     aggs = [("sum", 0), ("count", None), ("avg", 0), ("min", 0), ("max", 0)]
     mg = args.ops_groups
     out_keys = [torch.empty(mg, dtype=torch.int64, device="cuda")]
@@ -507,6 +511,210 @@ def bench_ops(args, torch, datagen, rel) -> dict:
                            workload="occupied group slots -> key and aggregate columns "
                                     "(includes the replica merge)")
     return res
+
+
+def bench_bloom(args, torch, datagen, rel, kernel_ms, line) -> dict:
+    """Predicate transfer on a join with few partners: 10M unique int64 build
+    keys, 400M probe keys of which 5% are build keys and the rest draws from
+    the whole int64 range. The hash join with and without the Bloom filter
+    in front of its table walk, and the filter alone (rel_bloom_filter: the
+    probe rows that may have a partner)."""
+    seed = datagen.SEED0 + 6
+    nb, npr = args.bloom_build, args.bloom_probe
+    build = datagen.unique_i64(seed, 40, nb)
+    hit = datagen.uniform(seed, 41, 0, 100, npr, np.int32) < 5
+    pick = datagen.uniform(seed, 42, 0, nb, npr, np.int64)
+    probe = datagen.raw_u64(seed, 43, npr).view(np.int64)
+    probe[hit] = build[pick[hit]]
+    del hit, pick
+    bk, pk = torch.from_numpy(build).cuda(), torch.from_numpy(probe).cuda()
+    del build, probe
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cap = npr // 10
+    ob = torch.empty(cap, dtype=torch.int32, device="cuda")
+    op = torch.empty(cap, dtype=torch.int32, device="cuda")
+    out = {}
+    wl = f"{nb} unique int64 build keys, {npr} probe keys, 5% with a partner"
+    for name, t in (("join_low_match", None), ("join_low_match_bloom", rel.tuning(flags=rel.TUNE_BLOOM))):
+        ws = rel.workspace(rel.hash_join_ws(torch.int64, nb, t))
+        k = kernel_ms(lambda: rel.hash_join_async(bk, pk, ob, op, count, ws, t=t))
+        ms = sum(k.values())
+        out[name] = line(ms, 8 * nb + 8 * npr + 8 * int(count.item()), rows=npr,
+                         pairs=int(count.item()), rows_per_s=npr / (ms * 1e-3),
+                         breakdown_ms={kk: round(v, 4) for kk, v in k.items()},
+                         workload=wl + (", Bloom filter in front of the table" if t else ""))
+        del ws
+    f = rel.bloom_build(bk)
+    ids = torch.empty(npr, dtype=torch.int32, device="cuda")
+    ws = rel.workspace(rel.filter_ws(npr))
+    k = kernel_ms(lambda: rel.bloom_filter_async(pk, f, ids, count, ws))
+    kept = int(count.item())
+    out["bloom_filter"] = line(k["filter"], 8 * npr + 4 * kept, rows=npr, kept=kept,
+                               filter_bytes=int(f.numel()), rows_per_s=npr / (k["filter"] * 1e-3),
+                               workload=f"{npr} int64 probe keys through a 16-bit-per-key Bloom "
+                                        f"filter of {nb} build keys -> ascending row ids")
+    out["join_low_match_bloom"]["speedup_vs_plain"] = (
+        out["join_low_match"]["kernel_ms"] / out["join_low_match_bloom"]["kernel_ms"])
+    del bk, pk, ob, op, ids, ws, f
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_strings(args, torch, datagen, rel, kernel_ms, line) -> dict:
+    """Group-by on a string key (a stand-in for string-keyed ClickBench
+    group-bys; the suite itself is not used): a dictionary of 1M distinct
+    lowercase strings of 8-48 bytes, rows drawing their string by Zipf(1)
+    rank over it, COUNT(*) and SUM of an int64 column - dictionary-encoded
+    (int32 codes) over 100M rows, and materialised in the Arrow layout
+    (offsets + bytes) over 20M rows."""
+    seed = datagen.SEED0 + 7
+    nd = args.str_dict
+    lens = datagen.uniform(seed, 50, 8, 49, nd, np.int64)
+    offsets = np.zeros(nd + 1, np.int64)
+    offsets[1:] = np.cumsum(lens)
+    data = datagen.uniform(seed, 51, 97, 123, int(offsets[-1]), np.uint8)
+    out = {}
+    aggs = [("count", None), ("sum", 0)]
+    for name, n, plain in (("groupby_string_dict", args.str_rows, False),
+                           ("groupby_string_plain", args.str_rows // 5, True)):
+        codes = (datagen.zipf_ranks(seed, 52, nd, 1.0, n) - 1).astype(np.int32)
+        val = datagen.uniform(seed, 53, 0, 1_000_000, n, np.int64)
+        if plain:
+            lens_r = lens[codes]
+            off_r = np.zeros(n + 1, np.int64)
+            off_r[1:] = np.cumsum(lens_r)
+            # the rows' bytes, string by string (a gather of byte ranges)
+            starts = np.repeat(offsets[:-1][codes] - off_r[:-1], lens_r)
+            data_r = data[np.arange(int(off_r[-1]), dtype=np.int64) + starts]
+            del starts, lens_r
+            doff, ddata, dcodes = (torch.from_numpy(off_r).cuda(), torch.from_numpy(data_r).cuda(),
+                                   None)
+            nbytes = 8 * (n + 1) + int(off_r[-1]) + 8 * n
+            del off_r, data_r
+        else:
+            doff, ddata = torch.from_numpy(offsets).cuda(), torch.from_numpy(data).cuda()
+            dcodes = torch.from_numpy(codes).cuda()
+            nbytes = 4 * n + 8 * n  # codes and values; the dictionary stays in the caches
+        dval = torch.from_numpy(val).cuda()
+        del codes, val
+        mg = nd
+        ws = rel.workspace(rel.groupby_str_ws(aggs, mg))
+        st = rel.strings(doff, ddata, dcodes)
+        cv = rel._arr(rel.Column, [rel.column(dval)])
+        rows = torch.empty(mg, dtype=torch.int32, device="cuda")
+        oa = [torch.empty(mg, dtype=torch.int64, device="cuda") for _ in aggs]
+        oap = rel._arr(rel.ctypes.c_void_p, [o.data_ptr() for o in oa])
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+        def call():
+            rel._check(rel.lib().rel_groupby_str(rel.ctypes.byref(st), None, cv, 1, rel._aggs(aggs),
+                                                 len(aggs), rel._addr(rows), None, oap, mg,
+                                                 rel._addr(cnt), mg, rel._addr(ws), ws.numel(),
+                                                 rel._stream()))
+
+        k = kernel_ms(call)
+        ms = sum(k.values())
+        out[name] = line(ms, nbytes, rows=n, groups=int(cnt.item()), rows_per_s=n / (ms * 1e-3),
+                         breakdown_ms={kk: round(v, 4) for kk, v in k.items()},
+                         workload=f"{n} rows, Zipf(1) over {nd} distinct strings of 8-48 bytes, "
+                                  + ("Arrow offsets + bytes" if plain else "int32 dictionary codes")
+                                  + ", COUNT(*), SUM(int64)")
+        del doff, ddata, dcodes, dval, ws, rows, oa
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_topn(args, torch, datagen, rel, kernel_ms, line) -> dict:
+    """ORDER BY ... LIMIT over a large result table: 10M groups (int64 key,
+    int64 SUM with ties), the top 100 and the top 1000 by SUM descending, ties
+    by key, then the rows materialised by rel_gather."""
+    seed = datagen.SEED0 + 8
+    n = args.topn_rows
+    key = torch.from_numpy(datagen.unique_i64(seed, 60, n)).cuda()
+    val = torch.from_numpy(datagen.uniform(seed, 61, 0, 1_000_000, n, np.int64)).cuda()
+    out = {}
+    for limit in (100, 1000):
+        pos = torch.empty(limit, dtype=torch.int32, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ws = rel.workspace(rel.topn_ws(n, limit))
+        k = kernel_ms(lambda: rel.topn_async(val, [key], limit, pos, cnt, ws, desc=True))
+        dst = [torch.empty(limit, dtype=torch.int64, device="cuda") for _ in range(2)]
+        g = kernel_ms(lambda: rel.gather_async([key, val], pos, dst))
+        out[f"top_{limit}"] = line(k["top_n"], 16 * n, rows=n, limit=limit,
+                                   gather_ms=g["gather"], rows_per_s=n / (k["top_n"] * 1e-3),
+                                   workload=f"{n} rows (int64 key, int64 value), top {limit} by "
+                                            "value descending, ties by key; then the rows gathered")
+        del pos, ws, dst
+    del key, val
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_out_of_core(args, torch, datagen, rel) -> dict:
+    """The star-schema plan (hash-table dims) with the 600M-row fact table in
+    pinned host memory, streamed through the device in chunks while the
+    previous chunk is aggregated (rel_pipeline_stream), beside the plain
+    host-to-device copy of the same bytes (the link's ceiling) and the result
+    of the resident plan."""
+    seed = datagen.SEED0 + 2
+    n = args.n_fact
+    d = datagen.star_schema(seed=seed, n_fact=n)
+    t0 = time.perf_counter()
+    host = [torch.from_numpy(d[k]).pin_memory() for k in ("fk_a", "fk_b", "date", "price", "flag")]
+    log(f"out-of-core: {n} fact rows pinned in {time.perf_counter() - t0:.1f} s")
+    dims = [dict(fk=0, key=torch.from_numpy(d["dim_a_key"]).cuda(), payload=None),
+            dict(fk=1, key=torch.from_numpy(d["dim_b_key"]).cuda(),
+                 payload=torch.from_numpy(d["dim_b_region"]).cuda())]
+    del d
+    nbytes = sum(c.numel() * c.element_size() for c in host)
+    stream = torch.cuda.current_stream()
+    # the link's ceiling: one copy of every column to the device
+    dst = [torch.empty_like(c, device="cuda") for c in host]
+    for a, b in zip(dst, host):
+        a.copy_(b, non_blocking=True)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for a, b in zip(dst, host):
+        a.copy_(b, non_blocking=True)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = start.elapsed_time(stop)
+    resident = rel.PreparedPipeline(dst, TERMS, dims, KEYS, AGGS, 128,
+                                    rel.tuning(flags=rel.TUNE_NO_DIRECT))
+    resident.launch()
+    want = resident.result()
+    del resident, dst
+    torch.cuda.empty_cache()
+    res = {"workload": f"star schema, {n} fact rows ({nbytes / 1e9:.1f} GB) in pinned host memory, "
+                       "hash-table dims", "h2d_copy_ms": copy_ms,
+           "h2d_gbs": nbytes / (copy_ms * 1e-3) / 1e9, "chunks": {}}
+    for chunk in args.ooc_chunks:
+        plan = rel.StreamedPipeline(host, TERMS, dims, KEYS, AGGS, 128, chunk,
+                                    rel.tuning(flags=rel.TUNE_NO_DIRECT))
+        plan.launch()
+        got = plan.result()
+        same = all(torch.equal(x, y) for x, y in zip(sorted_groups(torch, *got),
+                                                     sorted_groups(torch, *want)))
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(args.ooc_steps):
+            plan.launch()
+        stop.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / args.ooc_steps
+        res["chunks"][str(chunk)] = {"ms": ms, "rows_per_s": n / (ms * 1e-3),
+                                     "gbs": nbytes / (ms * 1e-3) / 1e9,
+                                     "frac_of_h2d": copy_ms / ms, "identical_to_resident": same}
+        log(f"out-of-core: chunk {chunk}: {ms:.1f} ms ({copy_ms:.1f} ms to copy), same {same}")
+        del plan
+        torch.cuda.empty_cache()
+    return res
+
+
+def sorted_groups(torch, keys, aggs):
+    o = torch.argsort(keys[0].long() * 4 + keys[1].long())
+    return [k[o] for k in keys] + [a[o] for a in aggs]
 
 
 SERVE_AGGS = [("sum", 3), ("count", None)]
@@ -644,6 +852,15 @@ def main() -> int:
     ap.add_argument("--ops-build", type=int, default=100_000_000)
     ap.add_argument("--ops-probe", type=int, default=400_000_000)
     ap.add_argument("--ops-groups", type=int, default=10_000_000)
+    ap.add_argument("--bloom-build", type=int, default=1_000_000)
+    ap.add_argument("--bloom-probe", type=int, default=400_000_000)
+    ap.add_argument("--str-dict", type=int, default=1_000_000)
+    ap.add_argument("--str-rows", type=int, default=100_000_000)
+    ap.add_argument("--topn-rows", type=int, default=10_000_000)
+    ap.add_argument("--no-ooc", action="store_true", help="skip the out-of-core section")
+    ap.add_argument("--ooc-only", action="store_true")
+    ap.add_argument("--ooc-steps", type=int, default=2)
+    ap.add_argument("--ooc-chunks", type=int, nargs="*", default=[2048 * 4096, 2048 * 16384])
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-rows", type=int, default=200_000_000)
     ap.add_argument("--serve-queries", type=int, default=2000)
@@ -686,6 +903,9 @@ def main() -> int:
         return 0
     if args.serve_only:
         print(json.dumps({"serving": bench_serve(args, torch, datagen, rel)}), flush=True)
+        return 0
+    if args.ooc_only:
+        print(json.dumps({"out_of_core": bench_out_of_core(args, torch, datagen, rel)}), flush=True)
         return 0
     seed = datagen.SEED0 + 2 if args.seed is None else args.seed
     n = args.n_fact
@@ -774,6 +994,10 @@ def main() -> int:
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         out["ops"] = bench_ops(args, torch, datagen, rel)
+    if not args.no_ooc:
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out["out_of_core"] = bench_out_of_core(args, torch, datagen, rel)
     print(json.dumps(out), flush=True)
     return 0
 

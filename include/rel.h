@@ -61,7 +61,8 @@ typedef enum {
   REL_EUNSUPPORTED = 5  /* well-formed request outside what this build implements */
 } rel_status;
 
-typedef enum { REL_I8 = 1, REL_I32 = 2, REL_I64 = 3 } rel_dtype;
+typedef enum { REL_I8 = 1, REL_I32 = 2, REL_I64 = 3,
+               REL_F64 = 4 /* binary64: only the order column of rel_topn (AVG outputs) */ } rel_dtype;
 
 typedef uint32_t rel_rowid;
 
@@ -127,6 +128,11 @@ typedef struct {
 /* rel_tuning.flags: keep dims of rel_pipeline in their hash tables even when
  * the build keys are dense (see rel_pipeline). */
 #define REL_TUNE_NO_DIRECT 1
+/* rel_tuning.flags: rel_hash_join also builds a Bloom filter over the build
+ * keys (16 bits per key, in its workspace) and probes it before the hash
+ * table, so probe keys without a partner skip the table walk (see
+ * rel_bloom_build). */
+#define REL_TUNE_BLOOM 2
 
 #define REL_MAX_TERMS 4
 #define REL_MAX_DIMS 2
@@ -183,6 +189,70 @@ rel_status rel_filter_noalloc(const rel_column* cols, int ncols, const rel_pred*
                               int npreds, rel_rowid* out, int64_t out_cap, int64_t* d_count,
                               void* stream);
 
+/* --------------------------------------------------------- Bloom filters */
+
+/* Bytes of a Bloom filter for n_keys keys at bits_per_key bits each (0: 16,
+ * about 0.1% false positives; 4..64), rounded up to a power-of-two number of
+ * 32-byte blocks (0 for invalid arguments). */
+size_t rel_bloom_bytes(int64_t n_keys, int32_t bits_per_key);
+
+/* Predicate transfer (Section 3.4 plans it among the engine's performance
+ * optimizations): a Bloom filter over one table's join keys, built here, is
+ * carried to the other table, where rel_bloom_filter drops the rows that
+ * cannot find a partner before they reach a join.
+ * Builds into `filter` (filter_bytes = 32 * 2^k bytes, 32-byte aligned,
+ * device memory; its previous contents are cleared) the blocked Bloom filter
+ * of `keys` (any integer type; values compare as int64, so int32 and int64
+ * keys of equal value match). Each key sets one bit in each of the eight
+ * 32-bit words of one 32-byte block chosen by its hash.
+ * Errors: REL_EINVAL for a NULL or malformed column or filter. */
+rel_status rel_bloom_build(const rel_column* keys, void* filter, size_t filter_bytes,
+                           void* stream);
+
+/* Semi-join reduction: writes the row ids (ascending, like rel_filter) of
+ * the probe_keys elements whose value may be in the filter - every element
+ * whose value was inserted (no false negatives) and a small share of the
+ * others (false positives). Exactly the semi-join is then what a join with
+ * the filtered rows returns. ws: rel_filter_ws(probe_keys->len) bytes; other
+ * arguments as rel_filter.
+ * Errors: REL_EINVAL (malformed column, filter, outputs), REL_ENOMEM. */
+rel_status rel_bloom_filter(const rel_column* probe_keys, const void* filter, size_t filter_bytes,
+                            rel_rowid* out, int64_t out_cap, int64_t* d_count, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* --------------------------------------------------- late materialisation */
+
+/* Late materialisation (Section 3.2.2: operators pass row ids and a custom
+ * kernel materialises columns at the end): out[c][i] = cols[c][ids[i]] for
+ * i < n and each of the 1..8 columns, in the column's own type (out[c]:
+ * device array of n elements). Columns take no idx. Every id must be below
+ * its column's len (the outputs of rel_filter, rel_hash_join and rel_topn
+ * are); other ids read outside the column.
+ * Errors: REL_EINVAL (NULL arguments, bad column or count). */
+rel_status rel_gather(const rel_column* cols, int ncols, const rel_rowid* ids, int64_t n,
+                      void* const* out, void* stream);
+
+/* Workspace bytes for rel_topn over n rows with limit N (0 for invalid
+ * arguments). */
+size_t rel_topn_ws(int64_t n, int64_t limit);
+
+/* Order-by / top-N over a result table (Section 4.2 names it among
+ * ClickBench's costs beside scans and aggregation): writes to out the
+ * positions (row ids) of the first min(limit, n) of its n rows in the order
+ * of `order` - ascending, or descending when desc != 0 - ties broken by the
+ * key tuple ascending (signed, lexicographic) and then by the row position,
+ * so the answer is unique; *d_count (device int64) = min(limit, n).
+ *   order      device array of n values: REL_I64 (int64) or REL_F64
+ *              (binary64, e.g. an AVG column; no NaN), 8-byte aligned.
+ *   keys       0..2 key columns (len >= n, no idx): the tie-break.
+ *   limit      0..1024.
+ *   ws         rel_topn_ws(n, limit) bytes.
+ * Feed the positions to rel_gather to materialise the rows.
+ * Errors: REL_EINVAL, REL_ENOMEM, REL_EDEVICE (launch). */
+rel_status rel_topn(const void* order, int32_t order_type, int32_t desc, const rel_column* keys,
+                    int nkeys, int64_t n, int64_t limit, rel_rowid* out, int64_t* d_count,
+                    void* ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------ hash join */
 
 /* Workspace bytes for rel_hash_join with n_build build rows (with a
@@ -234,6 +304,46 @@ rel_status rel_groupby_agg(const rel_column* keys, int nkeys, const rel_column* 
                            const rel_agg* aggs, int naggs, void* const* out_keys,
                            void* const* out_aggs, int64_t out_cap, int64_t* d_groups,
                            int64_t max_groups, const rel_tuning* t, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* A string column in the Arrow layout: string j is bytes[offsets[j] ..
+ * offsets[j+1]) (n_strings + 1 ascending offsets). Without codes, row i is
+ * string i (len == n_strings); with codes (device int32 array of len
+ * entries, each in [0, n_strings)) the column is dictionary-encoded and row
+ * i is string codes[i]. All arrays are device memory; the bytes are read in
+ * aligned 4-byte words (a word holding a string byte is read whole). */
+typedef struct {
+  const int64_t* offsets;
+  const uint8_t* bytes;
+  const int32_t* codes;
+  int64_t len;
+  int64_t n_strings;
+} rel_strings;
+
+/* Workspace bytes for rel_groupby_str with at most max_groups groups (0 for
+ * invalid arguments). */
+size_t rel_groupby_str_ws(int64_t max_groups, int naggs, const rel_agg* aggs);
+
+/* Hash group-by on a string key (Section 4.2 reports the cost of string
+ * group keys on ClickBench), optionally with an integer key beside it (a
+ * two-column key): one output row per distinct (string, integer) pair - the
+ * string's bytes decide, so equal strings under different dictionary codes
+ * form one group - with the aggregates `aggs` over `vals` as in
+ * rel_groupby_agg. Instead of the string, a group reports the smallest row
+ * id holding it (out_rows; feed it to the codes or offsets to read the
+ * string, or to rel_gather), and its integer key (out_ikey, ikey's type).
+ * Row order is unspecified (compare after sorting by the key).
+ *   ikey      NULL or an int8/int32/int64 column of key->len rows (no idx).
+ *   vals      value columns of key->len rows (no idx).
+ *   d_groups  device int64: the number of groups, or -1 when they exceed
+ *             what a table sized for max_groups holds.
+ * Equal rows of a wave combine their updates before one atomic per group
+ * (wave-aggregated atomics).
+ * Errors: REL_EINVAL, REL_ENOMEM. */
+rel_status rel_groupby_str(const rel_strings* key, const rel_column* ikey, const rel_column* vals,
+                           int nvals, const rel_agg* aggs, int naggs, rel_rowid* out_rows,
+                           void* out_ikey, void* const* out_aggs, int64_t out_cap,
+                           int64_t* d_groups, int64_t max_groups, void* ws, size_t ws_bytes,
                            void* stream);
 
 /* ------------------------------------------------------------- pipeline */
@@ -296,6 +406,32 @@ size_t rel_pipeline_ws(const rel_pipeline_desc* d);
  * 64 bits, int64 dim payloads). */
 rel_status rel_pipeline(const rel_pipeline_desc* d, const rel_outputs* o, void* ws,
                         size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------------- out of core */
+
+/* Workspace bytes for rel_pipeline_stream on plan d with chunks of
+ * chunk_rows fact rows (0 for invalid arguments): rel_pipeline_ws(d) plus two
+ * staging slots of one chunk of every fact column. */
+size_t rel_pipeline_stream_ws(const rel_pipeline_desc* d, int64_t chunk_rows);
+
+/* Out-of-core execution (Section 3.4 plans it for data larger than device
+ * memory): rel_pipeline over fact columns that stay in host memory. The fact
+ * table goes through the device in chunks of chunk_rows rows: while the
+ * fused pass runs over chunk k on `stream`, chunk k+1 is copied into the
+ * other staging slot on a copy stream of the calling thread (created on
+ * first use, default priority, kept until the process ends); every chunk
+ * aggregates into the same group table, and the groups are written once at
+ * the end. Results equal rel_pipeline on the whole table.
+ *   d           as for rel_pipeline, except that the fact columns' data are
+ *               HOST pointers, best pinned (hipHostMalloc) so that the
+ *               copies run asynchronously at full speed; dims stay device
+ *               memory. The host buffers must stay valid until `stream`
+ *               has reached the end of the call.
+ *   chunk_rows  a positive multiple of 2048.
+ *   ws          rel_pipeline_stream_ws(d, chunk_rows) bytes.
+ * Errors: as rel_pipeline; REL_EDEVICE if a copy or event call fails. */
+rel_status rel_pipeline_stream(const rel_pipeline_desc* d, int64_t chunk_rows,
+                               const rel_outputs* o, void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------- batches */
 
@@ -542,7 +678,10 @@ typedef enum {
   REL_K_FINALIZE = 6,    /* group compaction into the outputs */
   REL_K_GROUP_PARTITION = 7, /* rel_groupby_agg's counting and scatter passes */
   REL_K_STREAM = 8,      /* rel_stream_read */
-  REL_K_COUNT = 9
+  REL_K_BLOOM = 9,       /* Bloom filter builds (rel_bloom_build, joins with REL_TUNE_BLOOM) */
+  REL_K_GATHER = 10,     /* rel_gather */
+  REL_K_TOPN = 11,       /* rel_topn */
+  REL_K_COUNT = 12
 } rel_kernel_class;
 
 /* Static name of a kernel class. */

@@ -47,6 +47,17 @@ void clear_last_error() { g_error.clear(); }
 namespace {
 
 constexpr int64_t kMaxRows = 0xFFFFFFFELL;  // row ids must stay below the all-ones value
+
+// Bloom filters: bits per key of the filter a join builds (about 0.1% false
+// positives), and the bytes of a filter of n keys at `bits` per key: a
+// power-of-two number of 32-byte blocks.
+constexpr int kBloomBitsPerKey = 16;
+size_t bloom_bytes(int64_t n, int bits) {
+  uint64_t want = (static_cast<uint64_t>(n > 0 ? n : 1) * static_cast<uint64_t>(bits) + 255) / 256;
+  uint64_t blocks = 1;
+  while (blocks < want) blocks <<= 1;
+  return static_cast<size_t>(blocks) * 32;
+}
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -74,7 +85,8 @@ rel_status check_tuning(const rel_tuning* t) {
   if (t->grid < 0) return fail(REL_EINVAL, "tuning.grid must be >= 0");
   if (t->lds_slots < -1 || (t->lds_slots > 0 && (t->lds_slots & (t->lds_slots - 1)) != 0))
     return fail(REL_EINVAL, "tuning.lds_slots must be -1, 0 or a power of two");
-  if (t->flags & ~REL_TUNE_NO_DIRECT) return fail(REL_EINVAL, "tuning.flags: unknown bits");
+  if (t->flags & ~(REL_TUNE_NO_DIRECT | REL_TUNE_BLOOM))
+    return fail(REL_EINVAL, "tuning.flags: unknown bits");
   if (t->chunk_tiles < 0) return fail(REL_EINVAL, "tuning.chunk_tiles must be >= 0");
   if (t->replicas < 0 || t->replicas > 256)
     return fail(REL_EINVAL, "tuning.replicas must be in [0, 256]");
@@ -472,8 +484,9 @@ rel_status pipeline_layout(const rel_pipeline_desc* d, PipeLayout& L, bool batch
   for (int i = 0; i < d->n_dims; ++i) {
     // membership-only int32 dims keep keys alone (4-byte slots)
     const bool key_only = d->dims[i].key.type == REL_I32 && !d->dims[i].has_payload;
-    L.dim[i] = map_layout(d->dims[i].key.type, d->dims[i].key.len, lf < 0.75f ? 0.75f : lf, off,
-                          key_only, !batch);
+    // dims fill their tables to 0.75 unless the tuning sets a load factor
+    const float dim_lf = (d->tuning && d->tuning->load_factor > 0.0f) ? lf : 0.75f;
+    L.dim[i] = map_layout(d->dims[i].key.type, d->dims[i].key.len, dim_lf, off, key_only, !batch);
     const bool no_direct = d->tuning && (d->tuning->flags & REL_TUNE_NO_DIRECT);
     if (d->dims[i].key.type == REL_I32 && !no_direct)
       add_direct(L.dim[i], d->dims[i].key.len, d->dims[i].has_payload != 0);
@@ -553,8 +566,10 @@ int row_spec(const rel_pipeline_desc* d, const PipeLayout& L, PipelineParams& p)
       if (t == REL_I8) k[j] = 3;
       else if (t == REL_I32) k[j] = 4;
       else return 0;
+      p.spec_key[j] = d->fact[kr.col].data;
     }
   }
+  p.spec_val = static_cast<const int64_t*>(d->fact[ap.col[0]].data);
   return k[0] | (k[1] << 3) | (1 << 6);
 }
 
@@ -1317,13 +1332,331 @@ rel_status rel_filter_noalloc(const rel_column* cols, int ncols, const rel_pred*
                         static_cast<unsigned char*>(scratch), static_cast<hipStream_t>(stream));
 }
 
+// ---------------------------------------------------------- Bloom filters
+
+size_t rel_bloom_bytes(int64_t n_keys, int32_t bits_per_key) {
+  if (n_keys < 0 || n_keys > kMaxRows) return 0;
+  if (bits_per_key == 0) bits_per_key = kBloomBitsPerKey;
+  if (bits_per_key < 4 || bits_per_key > 64) return 0;
+  return bloom_bytes(n_keys, bits_per_key);
+}
+
+}  // extern "C"
+
+namespace rel {
+namespace {
+
+rel_status check_bloom(const void* filter, size_t filter_bytes, const char* what) {
+  if (!filter) return fail(REL_EINVAL, "%s: NULL filter", what);
+  if (reinterpret_cast<uintptr_t>(filter) % 32 != 0)
+    return fail(REL_EINVAL, "%s: the filter must be 32-byte aligned", what);
+  const size_t blocks = filter_bytes / 32;
+  if (filter_bytes % 32 != 0 || blocks == 0 || (blocks & (blocks - 1)) != 0)
+    return fail(REL_EINVAL, "%s: filter_bytes must be 32 times a power of two", what);
+  return REL_OK;
+}
+
+}  // namespace
+}  // namespace rel
+
+extern "C" {
+
+rel_status rel_bloom_build(const rel_column* keys, void* filter, size_t filter_bytes,
+                           void* stream) {
+  g_error.clear();
+  rel_status st = check_column(keys, "bloom build keys");
+  if (st) return st;
+  st = check_bloom(filter, filter_bytes, "bloom build");
+  if (st) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  BloomBuildParams b;
+  std::memset(&b, 0, sizeof b);
+  b.words = static_cast<uint32_t*>(filter);
+  b.bmask = filter_bytes / 32 - 1;
+  b.keys = keys->data;
+  b.idx = keys->idx;
+  b.type = keys->type;
+  b.n = keys->len;
+  launch_bloom_build(b, s);
+  return after_launch(s, "bloom build");
+}
+
+rel_status rel_bloom_filter(const rel_column* probe_keys, const void* filter, size_t filter_bytes,
+                            rel_rowid* out, int64_t out_cap, int64_t* d_count, void* ws,
+                            size_t ws_bytes, void* stream) {
+  g_error.clear();
+  rel_status st = check_column(probe_keys, "bloom filter keys");
+  if (st) return st;
+  st = check_bloom(filter, filter_bytes, "bloom filter");
+  if (st) return st;
+  if (out_cap < 0 || (out_cap > 0 && !out)) return fail(REL_EINVAL, "bloom filter: bad output");
+  if (!d_count) return fail(REL_EINVAL, "bloom filter: NULL count");
+  const int64_t n = probe_keys->len;
+  st = check_ws(ws, ws_bytes, rel_filter_ws(n));
+  if (st) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  FilterParams p;
+  std::memset(&p, 0, sizeof p);
+  p.nterms = 0;
+  p.idx = probe_keys->idx;
+  p.n = n;
+  p.out = out;
+  p.cap = out_cap;
+  p.d_count = reinterpret_cast<long long*>(d_count);
+  p.ticket = reinterpret_cast<uint32_t*>(w);
+  p.tile_state = reinterpret_cast<uint64_t*>(w + kAlign);
+  p.ntiles = n > 0 ? (n + kFilterTile - 1) / kFilterTile : 1;
+  p.bloom.words = static_cast<const uint32_t*>(filter);
+  p.bloom.bmask = filter_bytes / 32 - 1;
+  p.bloom_keys = probe_keys->data;
+  p.bloom_type = probe_keys->type;
+  p.bloom_vec = (reinterpret_cast<uintptr_t>(probe_keys->data) % 16) == 0;
+  launch_fill64(reinterpret_cast<uint64_t*>(w), (kAlign + p.ntiles * 8) / 8, 0, s);
+  launch_filter(p, s);
+  return after_launch(s, "bloom filter");
+}
+
+// ---------------------------------------------------- late materialisation
+
+rel_status rel_gather(const rel_column* cols, int ncols, const rel_rowid* ids, int64_t n,
+                      void* const* out, void* stream) {
+  g_error.clear();
+  if (!cols || ncols < 1 || ncols > 8) return fail(REL_EINVAL, "gather: 1..8 columns required");
+  if (n < 0 || n > kMaxRows) return fail(REL_EINVAL, "gather: bad row count");
+  if (n > 0 && (!ids || !out)) return fail(REL_EINVAL, "gather: NULL ids or outputs");
+  GatherParams p;
+  std::memset(&p, 0, sizeof p);
+  for (int c = 0; c < ncols; ++c) {
+    rel_status st = check_column(&cols[c], "gather column");
+    if (st) return st;
+    if (cols[c].idx) return fail(REL_EINVAL, "gather: columns take no idx (the ids select)");
+    if (n > 0 && !out[c]) return fail(REL_EINVAL, "gather: NULL output %d", c);
+    p.src[c] = cols[c].data;
+    p.type[c] = cols[c].type;
+    p.dst[c] = n > 0 ? out[c] : nullptr;
+  }
+  p.ncols = ncols;
+  p.ids = ids;
+  p.ids_vec = (reinterpret_cast<uintptr_t>(ids) % 16) == 0;
+  p.n = n;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  launch_gather(p, s);
+  return after_launch(s, "gather");
+}
+
+}  // extern "C"
+
+namespace rel {
+namespace {
+
+struct TopLayout {
+  int pow2 = 1, lists = 0;
+  int64_t span = 0;
+  size_t list_bytes = 0, end = 0;
+};
+
+TopLayout top_layout(int64_t n, int64_t limit) {
+  TopLayout L;
+  while (L.pow2 < limit) L.pow2 <<= 1;
+  if (n <= 0) return L;
+  int64_t lists = static_cast<int64_t>(device_info().cu_count) * 2;
+  const int64_t chunks = (n + L.pow2 - 1) / L.pow2;
+  if (lists > chunks) lists = chunks;
+  int64_t per = (n + lists - 1) / lists;
+  L.span = (per + L.pow2 - 1) / L.pow2 * L.pow2;
+  L.lists = static_cast<int>((n + L.span - 1) / L.span);
+  L.list_bytes = static_cast<size_t>(L.lists) * L.pow2;  // entries per buffer
+  L.end = 2 * align_up(L.list_bytes * 8) * 3 + 2 * align_up(L.list_bytes * 4);
+  return L;
+}
+
+}  // namespace
+}  // namespace rel
+
+extern "C" {
+
+size_t rel_topn_ws(int64_t n, int64_t limit) {
+  if (n < 0 || n > kMaxRows || limit < 0 || limit > kTopMax) return 0;
+  return align_up(top_layout(n, limit).end + kAlign);
+}
+
+rel_status rel_topn(const void* order, int32_t order_type, int32_t desc, const rel_column* keys,
+                    int nkeys, int64_t n, int64_t limit, rel_rowid* out, int64_t* d_count,
+                    void* ws, size_t ws_bytes, void* stream) {
+  g_error.clear();
+  if (n < 0 || n > kMaxRows) return fail(REL_EINVAL, "top-N: bad row count");
+  if (limit < 0 || limit > kTopMax) return fail(REL_EINVAL, "top-N: limit must be in [0, %d]", kTopMax);
+  if (order_type != REL_I64 && order_type != REL_F64)
+    return fail(REL_EINVAL, "top-N: the order column is int64 or binary64");
+  if (n > 0 && !order) return fail(REL_EINVAL, "top-N: NULL order column");
+  if (reinterpret_cast<uintptr_t>(order) % 8 != 0) return fail(REL_EINVAL, "top-N: misaligned order column");
+  if (nkeys < 0 || nkeys > 2 || (nkeys > 0 && !keys)) return fail(REL_EINVAL, "top-N: 0..2 keys");
+  for (int k = 0; k < nkeys; ++k) {
+    rel_status st = check_column(&keys[k], "top-N key");
+    if (st) return st;
+    if (keys[k].idx || keys[k].len < n) return fail(REL_EINVAL, "top-N: key %d must cover the rows", k);
+  }
+  if (!d_count || (limit > 0 && n > 0 && !out)) return fail(REL_EINVAL, "top-N: NULL outputs");
+  rel_status st = check_ws(ws, ws_bytes, rel_topn_ws(n, limit));
+  if (st) return st;
+  const TopLayout L = top_layout(n, limit);
+  TopNParams p;
+  std::memset(&p, 0, sizeof p);
+  p.order = order;
+  p.order_is_double = order_type == REL_F64;
+  p.desc = desc != 0;
+  for (int k = 0; k < nkeys; ++k) {
+    p.keys[k] = keys[k].data;
+    p.key_type[k] = keys[k].type;
+  }
+  p.nkeys = nkeys;
+  p.pow2 = L.pow2;
+  p.n = n;
+  p.limit = limit;
+  p.span = L.span;
+  p.nlists = L.lists;
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  size_t off = 0;
+  for (int b = 0; b < 2; ++b) {
+    p.buf[b].a = reinterpret_cast<uint64_t*>(w + off);
+    off += align_up(L.list_bytes * 8);
+    p.buf[b].b = reinterpret_cast<uint64_t*>(w + off);
+    off += align_up(L.list_bytes * 8);
+    p.buf[b].c = reinterpret_cast<uint64_t*>(w + off);
+    off += align_up(L.list_bytes * 8);
+    p.buf[b].row = reinterpret_cast<uint32_t*>(w + off);
+    off += align_up(L.list_bytes * 4);
+  }
+  p.out = out;
+  p.d_count = reinterpret_cast<long long*>(d_count);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const hipError_t e = launch_topn(p, s);
+  if (e != hipSuccess) return fail(REL_EDEVICE, "top-N: %s", hipGetErrorString(e));
+  return after_launch(s, "top-N");
+}
+
+// ------------------------------------------------------ string group-by
+
+}  // extern "C"
+
+namespace rel {
+namespace {
+
+struct StrLayout {
+  uint64_t cap = 0;
+  int words = 0;
+  size_t slots_off = 0, overflow_off = 0, end = 0;
+};
+
+StrLayout str_layout(int64_t max_groups, int nacc) {
+  StrLayout L;
+  uint64_t want = static_cast<uint64_t>(max_groups > 0 ? max_groups : 1) * 2;
+  L.cap = next_pow2(want < 64 ? 64 : want);
+  L.words = 3 + nacc;
+  L.slots_off = 0;
+  L.overflow_off = align_up(L.cap * L.words * 8);
+  L.end = L.overflow_off + kAlign;
+  return L;
+}
+
+}  // namespace
+}  // namespace rel
+
+extern "C" {
+
+size_t rel_groupby_str_ws(int64_t max_groups, int naggs, const rel_agg* aggs) {
+  if (max_groups < 0 || max_groups > kMaxRows || naggs < 1 || naggs > REL_MAX_AGGS || !aggs)
+    return 0;
+  GroupPlan gp;
+  if (group_plan(0, nullptr, naggs, aggs, gp) != REL_OK) return 0;
+  return align_up(str_layout(max_groups, gp.ap.nacc).end);
+}
+
+rel_status rel_groupby_str(const rel_strings* key, const rel_column* ikey, const rel_column* vals,
+                           int nvals, const rel_agg* aggs, int naggs, rel_rowid* out_rows,
+                           void* out_ikey, void* const* out_aggs, int64_t out_cap,
+                           int64_t* d_groups, int64_t max_groups, void* ws, size_t ws_bytes,
+                           void* stream) {
+  g_error.clear();
+  if (!key) return fail(REL_EINVAL, "string group-by: NULL key");
+  const int64_t n = key->len;
+  if (n < 0 || n > kMaxRows) return fail(REL_EINVAL, "string group-by: bad row count");
+  if (key->n_strings < 0 || (key->n_strings > 0 && (!key->offsets || !key->bytes)))
+    return fail(REL_EINVAL, "string group-by: NULL offsets or bytes");
+  if (!key->codes && key->n_strings != n)
+    return fail(REL_EINVAL, "string group-by: without codes every row is one string");
+  if (n > 0 && key->n_strings == 0)
+    return fail(REL_EINVAL, "string group-by: rows without strings");
+  if (ikey) {
+    rel_status st = check_column(ikey, "string group-by int key");
+    if (st) return st;
+    if (ikey->idx || ikey->len != n) return fail(REL_EINVAL, "string group-by: int key length");
+  }
+  if (nvals < 0 || nvals > REL_MAX_FACT_COLS || (nvals > 0 && !vals))
+    return fail(REL_EINVAL, "string group-by: 0..%d value columns", REL_MAX_FACT_COLS);
+  for (int v = 0; v < nvals; ++v) {
+    rel_status st = check_column(&vals[v], "string group-by value");
+    if (st) return st;
+    if (vals[v].idx || vals[v].len != n) return fail(REL_EINVAL, "string group-by: value length");
+  }
+  rel_status st = check_aggs(aggs, naggs, nvals, "string group-by");
+  if (st) return st;
+  if (max_groups < 0) return fail(REL_EINVAL, "string group-by: negative max_groups");
+  if (!d_groups || out_cap < 0 || (out_cap > 0 && !out_rows))
+    return fail(REL_EINVAL, "string group-by: bad outputs");
+  for (int a = 0; a < naggs && out_cap > 0; ++a)
+    if (!out_aggs || !out_aggs[a]) return fail(REL_EINVAL, "string group-by: NULL output %d", a);
+  GroupPlan gp;
+  st = group_plan(0, nullptr, naggs, aggs, gp);
+  if (st) return st;
+  const StrLayout L = str_layout(max_groups, gp.ap.nacc);
+  st = check_ws(ws, ws_bytes, align_up(L.end));
+  if (st) return st;
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  StrGroupParams p;
+  std::memset(&p, 0, sizeof p);
+  p.offsets = key->offsets;
+  p.bytes = key->bytes;
+  p.codes = key->codes;
+  p.n = n;
+  if (ikey) {
+    p.ikey = ikey->data;
+    p.ikey_type = ikey->type;
+  }
+  for (int v = 0; v < nvals; ++v) {
+    p.val[v] = vals[v].data;
+    p.val_type[v] = vals[v].type;
+  }
+  p.ap = gp.ap;
+  p.slots = reinterpret_cast<uint64_t*>(w + L.slots_off);
+  p.mask = L.cap - 1;
+  p.words = L.words;
+  p.overflow = reinterpret_cast<int32_t*>(w + L.overflow_off);
+  p.naggs = naggs;
+  for (int a = 0; a < naggs; ++a) {
+    p.agg_op[a] = aggs[a].op;
+    p.agg_acc[a] = gp.agg_acc[a];
+    p.out_aggs[a] = out_cap > 0 ? out_aggs[a] : nullptr;
+  }
+  p.out_rows = out_rows;
+  p.out_ikey = out_ikey;
+  p.cap = out_cap;
+  p.d_groups = reinterpret_cast<unsigned long long*>(d_groups);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  launch_groupby_str(p, s);
+  return after_launch(s, "string group-by");
+}
+
 // --------------------------------------------------------------- hash join
 
 size_t rel_hash_join_ws(int32_t key_type, int64_t n_build, const rel_tuning* t) {
   if ((key_type != REL_I32 && key_type != REL_I64) || n_build < 0 || n_build > kMaxRows) return 0;
   if (t && check_tuning(t) != REL_OK) return 0;
   const MapLayout L = map_layout(key_type, n_build, load_factor(t), 0);
-  return join_part(L, n_build, t).end;
+  const size_t end = join_part(L, n_build, t).end;
+  if (t && (t->flags & REL_TUNE_BLOOM)) return align_up(end) + bloom_bytes(n_build, kBloomBitsPerKey);
+  return end;
 }
 
 rel_status rel_hash_join(const rel_column* build_keys, const rel_column* probe_keys,
@@ -1345,7 +1678,10 @@ rel_status rel_hash_join(const rel_column* build_keys, const rel_column* probe_k
   if (st) return st;
   const MapLayout L = map_layout(build_keys->type, build_keys->len, load_factor(t), 0);
   const JoinPart jp = join_part(L, build_keys->len, t);
-  st = check_ws(ws, ws_bytes, jp.end);
+  const bool bloom = t && (t->flags & REL_TUNE_BLOOM);
+  const size_t bloom_off = align_up(jp.end);
+  const size_t bloom_len = bloom ? bloom_bytes(build_keys->len, kBloomBitsPerKey) : 0;
+  st = check_ws(ws, ws_bytes, bloom ? bloom_off + bloom_len : jp.end);
   if (st) return st;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1406,6 +1742,21 @@ rel_status rel_hash_join(const rel_column* build_keys, const rel_column* probe_k
   p.out_probe = out_probe;
   p.cap = out_cap;
   p.d_count = reinterpret_cast<unsigned long long*>(d_count);
+  if (bloom) {
+    // the build side's keys also go into a Bloom filter that the probe
+    // consults before walking the table
+    BloomBuildParams bb;
+    std::memset(&bb, 0, sizeof bb);
+    bb.words = reinterpret_cast<uint32_t*>(w + bloom_off);
+    bb.bmask = bloom_len / 32 - 1;
+    bb.keys = build_keys->data;
+    bb.idx = build_keys->idx;
+    bb.type = build_keys->type;
+    bb.n = build_keys->len;
+    launch_bloom_build(bb, s);
+    p.bloom.words = bb.words;
+    p.bloom.bmask = bb.bmask;
+  }
   const DeviceInfo& di = device_info();
   int64_t blocks = (p.n + 255) / 256;
   int64_t limit = (t && t->grid > 0) ? t->grid : static_cast<int64_t>(di.cu_count) * 16;
@@ -1582,6 +1933,159 @@ rel_status rel_pipeline(const rel_pipeline_desc* d, const rel_outputs* o, void* 
                                         o->aggs, o->cap),
                         s);
   return after_launch(s, "pipeline");
+}
+
+// ---------------------------------------------------------- out of core
+
+}  // extern "C"
+
+namespace rel {
+namespace {
+
+int type_bytes(int32_t type) { return type == REL_I8 ? 1 : (type == REL_I32 ? 4 : 8); }
+
+// Staging of the streamed plan: two slots, each one chunk of every fact
+// column (each column's part 256-byte aligned), after the plan's workspace.
+struct StreamLayout {
+  PipeLayout pipe;
+  size_t col_off[REL_MAX_FACT_COLS];
+  size_t slot_bytes = 0, slots_off = 0, end = 0;
+};
+
+rel_status stream_layout(const rel_pipeline_desc* d, int64_t chunk, StreamLayout& S) {
+  rel_status st = pipeline_layout(d, S.pipe);
+  if (st) return st;
+  size_t off = 0;
+  for (int c = 0; c < d->n_fact; ++c) {
+    S.col_off[c] = off;
+    off = align_up(off + static_cast<size_t>(chunk) * type_bytes(d->fact[c].type));
+  }
+  S.slot_bytes = off;
+  S.slots_off = align_up(S.pipe.end);
+  S.end = S.slots_off + 2 * S.slot_bytes;
+  return REL_OK;
+}
+
+// The copy stream and events of the calling thread (created on first use,
+// default priority, kept until the process ends).
+struct StreamState {
+  hipStream_t copy = nullptr;
+  hipEvent_t copied[2] = {nullptr, nullptr};
+  hipEvent_t freed[2] = {nullptr, nullptr};
+  int device = -1;
+};
+thread_local StreamState g_stream_state;
+
+rel_status stream_state(StreamState*& out) {
+  StreamState& ss = g_stream_state;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(REL_EDEVICE, "pipeline stream: %s", hipGetErrorString(e));
+  if (ss.copy && ss.device != dev) {
+    // a different device from the last call: new stream and events there
+    ss = StreamState();
+  }
+  if (!ss.copy) {
+    e = hipStreamCreateWithFlags(&ss.copy, hipStreamNonBlocking);
+    for (int k = 0; e == hipSuccess && k < 2; ++k) {
+      e = hipEventCreateWithFlags(&ss.copied[k], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ss.freed[k], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) return fail(REL_EDEVICE, "pipeline stream: %s", hipGetErrorString(e));
+    ss.device = dev;
+  }
+  out = &ss;
+  return REL_OK;
+}
+
+}  // namespace
+}  // namespace rel
+
+extern "C" {
+
+size_t rel_pipeline_stream_ws(const rel_pipeline_desc* d, int64_t chunk_rows) {
+  if (check_pipeline(d) != REL_OK || chunk_rows < kPipeTile || chunk_rows % kPipeTile != 0)
+    return 0;
+  StreamLayout S;
+  if (stream_layout(d, chunk_rows, S) != REL_OK) return 0;
+  return S.end;
+}
+
+rel_status rel_pipeline_stream(const rel_pipeline_desc* d, int64_t chunk_rows,
+                               const rel_outputs* o, void* ws, size_t ws_bytes, void* stream) {
+  g_error.clear();
+  rel_status st = check_pipeline(d);
+  if (st) return st;
+  if (chunk_rows < kPipeTile || chunk_rows % kPipeTile != 0)
+    return fail(REL_EINVAL, "pipeline stream: chunk_rows must be a positive multiple of %d",
+                kPipeTile);
+  if (!o) return fail(REL_EINVAL, "pipeline stream: NULL outputs");
+  st = check_outputs(o->keys, d->n_keys, o->aggs, d->n_aggs, o->cap, o->d_groups);
+  if (st) return st;
+  StreamLayout S;
+  st = stream_layout(d, chunk_rows, S);
+  if (st) return st;
+  st = check_ws(ws, ws_bytes, S.end);
+  if (st) return st;
+  StreamState* ss = nullptr;
+  st = stream_state(ss);
+  if (st) return st;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  const int64_t n = d->fact[0].len;
+  // the plan over one chunk (fact columns in a staging slot): its layout
+  // does not depend on the fact length, so one workspace serves every chunk
+  rel_column cols[REL_MAX_FACT_COLS];
+  rel_pipeline_desc cd = *d;
+  cd.fact = cols;
+  for (int c = 0; c < d->n_fact; ++c) {
+    cols[c] = d->fact[c];
+    cols[c].data = w + S.slots_off + S.col_off[c];
+    cols[c].len = n < chunk_rows ? n : chunk_rows;
+  }
+  PipelineParams p;
+  MapBuildParams b[REL_MAX_DIMS];
+  plan_params(&cd, S.pipe, w, o->d_groups, false, p, b);
+  for (int i = 0; i < d->n_dims; ++i) {
+    launch_map_init(p.dim[i].map, s);
+    launch_map_build(b[i], s);
+  }
+  launch_group_init(p.g, s);
+  hipError_t e = hipSuccess;
+  for (int64_t k = 0, r0 = 0; r0 < n && e == hipSuccess; ++k, r0 += chunk_rows) {
+    const int slot = static_cast<int>(k & 1);
+    const int64_t rows = n - r0 < chunk_rows ? n - r0 : chunk_rows;
+    unsigned char* base = w + S.slots_off + slot * S.slot_bytes;
+    // copy stream: wait until the kernels that read this slot two chunks
+    // ago are done, then bring in the chunk
+    if (k >= 2) e = hipStreamWaitEvent(ss->copy, ss->freed[slot], 0);
+    for (int c = 0; e == hipSuccess && c < d->n_fact; ++c) {
+      const int wbytes = type_bytes(d->fact[c].type);
+      e = hipMemcpyAsync(base + S.col_off[c],
+                         static_cast<const unsigned char*>(d->fact[c].data) + r0 * wbytes,
+                         static_cast<size_t>(rows) * wbytes, hipMemcpyHostToDevice, ss->copy);
+    }
+    if (e == hipSuccess) e = hipEventRecord(ss->copied[slot], ss->copy);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, ss->copied[slot], 0);
+    if (e != hipSuccess) break;
+    // compute stream: the fused pass over the chunk, into the same groups
+    for (int c = 0; c < d->n_fact; ++c) {
+      cols[c].data = base + S.col_off[c];
+      cols[c].len = rows;
+    }
+    PipelineParams pk;
+    MapBuildParams unused[REL_MAX_DIMS];
+    plan_params(&cd, S.pipe, w, o->d_groups, false, pk, unused);
+    e = launch_pipeline(pk, (d->tuning && d->tuning->grid > 0) ? d->tuning->grid : 0, s);
+    if (e == hipSuccess) e = hipEventRecord(ss->freed[slot], s);
+  }
+  if (e != hipSuccess) return fail(REL_EDEVICE, "pipeline stream: %s", hipGetErrorString(e));
+  launch_group_merge(p.g, s);
+  launch_group_finalize(finalize_params(p.g, S.pipe.gp, d->aggs, d->n_aggs, o->keys,
+                                        S.pipe.key_types, o->aggs, o->cap),
+                        s);
+  return after_launch(s, "pipeline stream");
 }
 
 // ------------------------------------------------------------------ batches

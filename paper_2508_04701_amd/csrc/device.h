@@ -174,6 +174,56 @@ __device__ __forceinline__ bool term_holds(int32_t op, int64_t v, int64_t lo, in
   }
 }
 
+// ---------------------------------------------------------- Bloom filters
+//
+// Blocked Bloom filter over int32/int64 keys (blocked filters: Putze, Sanders
+// and Singler, "Cache-, Hash- and Space-Efficient Bloom Filters", 2007): a
+// power-of-two number of 32-byte blocks, each eight 32-bit words. A key's
+// 64-bit hash picks one block (high half) and, in each of the block's eight
+// words, one bit (five bits of the low half times a per-word odd multiplier),
+// so a test reads one 32-byte sector. Keys are widened to int64 before
+// hashing, so an int32 key and the int64 key of equal value hash alike.
+
+struct BloomDesc {
+  const uint32_t* words;  // blocks * 8 words
+  uint64_t bmask;         // blocks - 1
+};
+
+// Odd multipliers: the high halves of the first eight outputs of SplitMix64
+// from state 0, each made odd.
+__device__ __forceinline__ uint32_t bloom_salt(int w) {
+  switch (w) {
+    case 0: return 0xe220a839u;
+    case 1: return 0x6e789e6bu;
+    case 2: return 0x06c45d19u;
+    case 3: return 0xf88bb8a9u;
+    case 4: return 0x1b39896bu;
+    case 5: return 0x53cb9f0du;
+    case 6: return 0x2c829abfu;
+    default: return 0xc584133bu;
+  }
+}
+
+__device__ __forceinline__ uint64_t bloom_hash(int64_t key) {
+  return hash64(static_cast<uint64_t>(key) ^ 0x6a09e667f3bcc909ULL);
+}
+
+__device__ __forceinline__ uint64_t bloom_block(uint64_t h, uint64_t bmask) {
+  return (h >> 32) & bmask;
+}
+
+__device__ __forceinline__ uint32_t bloom_bit(uint64_t h, int w) {
+  return 1u << ((static_cast<uint32_t>(h) * bloom_salt(w)) >> 27);
+}
+
+// Whether the block q (words 0-3 in a, 4-7 in b) holds every bit of hash h.
+__device__ __forceinline__ bool bloom_match(uint64_t h, uint4 a, uint4 b) {
+  return ((a.x & bloom_bit(h, 0)) != 0) & ((a.y & bloom_bit(h, 1)) != 0) &
+         ((a.z & bloom_bit(h, 2)) != 0) & ((a.w & bloom_bit(h, 3)) != 0) &
+         ((b.x & bloom_bit(h, 4)) != 0) & ((b.y & bloom_bit(h, 5)) != 0) &
+         ((b.z & bloom_bit(h, 6)) != 0) & ((b.w & bloom_bit(h, 7)) != 0);
+}
+
 // ---------------------------------------------------------------- hash maps
 //
 // Multimap key -> 32-bit value with linear probing over a power-of-two slot

@@ -135,6 +135,39 @@ __device__ __forceinline__ void eval_whole(const FilterParams& p, int64_t r0,
   }
 }
 
+// Semi-join reduction of one chunk: clears the bits of rows r0..r0+3 whose
+// key is absent from the Bloom filter (the four rows' filter blocks are read
+// together).
+__device__ __forceinline__ uint32_t bloom_chunk(const FilterParams& p, int64_t r0, uint32_t bits) {
+  if (!p.bloom.words || bits == 0) return bits;
+  int64_t key[4];
+  if (!p.idx) {
+    load4(p.bloom_keys, p.bloom_type, p.bloom_vec != 0, r0, p.n, key);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      key[e] = (r0 + e < p.n) ? load_elem(p.bloom_keys, p.bloom_type, p.idx[r0 + e]) : 0;
+  }
+  uint64_t h[4];
+  uint4 a[4], b[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    h[e] = bloom_hash(key[e]);
+    a[e] = make_uint4(0, 0, 0, 0);
+    b[e] = a[e];
+    if ((bits >> e) & 1u) {
+      const uint4* q =
+          reinterpret_cast<const uint4*>(p.bloom.words + bloom_block(h[e], p.bloom.bmask) * 8);
+      a[e] = q[0];
+      b[e] = q[1];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (((bits >> e) & 1u) && !bloom_match(h[e], a[e], b[e])) bits &= ~(1u << e);
+  return bits;
+}
+
 __global__ void __launch_bounds__(kFilterThreads) filter_kernel(FilterParams p) {
   __shared__ uint32_t s_rows[kFilterTile];
   __shared__ uint32_t s_wave_total[kFilterChunks][kFilterThreads / kWave];
@@ -157,6 +190,11 @@ __global__ void __launch_bounds__(kFilterThreads) filter_kernel(FilterParams p) 
 #pragma unroll
     for (int j = 0; j < kFilterChunks; ++j)
       bits[j] = eval_chunk(p, base + j * (kFilterThreads * 4) + tid * 4);
+  }
+  if (p.bloom.words) {
+#pragma unroll
+    for (int j = 0; j < kFilterChunks; ++j)
+      bits[j] = bloom_chunk(p, base + j * (kFilterThreads * 4) + tid * 4, bits[j]);
   }
 
   // Per chunk: this lane's rank among the wave's passing rows, and the

@@ -22,7 +22,7 @@ const DeviceInfo& device_info();
 // pair of events on the launch stream (kernel classes as in rel.h).
 enum KernelClass : int {
   kKFill = 0, kKFilter, kKMapBuild, kKMapProbe, kKGroupAgg, kKPipeline, kKFinalize,
-  kKGroupPartition, kKStream, kKCount
+  kKGroupPartition, kKStream, kKBloom, kKGather, kKTopN, kKCount
 };
 struct ProfileScope {
   ProfileScope(int kclass, hipStream_t s);
@@ -70,6 +70,12 @@ struct FilterParams {
   uint64_t* tile_state;  // one word per tile, zeroed
   uint32_t* ticket;      // zeroed
   int64_t ntiles;
+  // Optional semi-join reduction: a row also needs its key (bloom_keys,
+  // gathered through idx like the terms' columns) to pass the Bloom filter.
+  BloomDesc bloom;       // words == NULL: none
+  const void* bloom_keys;
+  int32_t bloom_type;
+  int32_t bloom_vec;     // bloom_keys is 16-byte aligned
 };
 
 void launch_filter(const FilterParams& p, hipStream_t s);
@@ -84,6 +90,78 @@ constexpr int64_t kFilterNoallocMaxRows =
 // Device address of the calling thread's current device's copy of the
 // filter scratch, looked up once per device.
 hipError_t filter_scratch(void** ptr);
+
+// ------------------------------------------------- late materialisation
+
+// out dst[c][i] = src[c][ids[i]] (element type type[c]) for i < n.
+struct GatherParams {
+  const void* src[8];
+  int32_t type[8];
+  void* dst[8];
+  int32_t ncols;
+  int32_t ids_vec;  // ids is 16-byte aligned
+  const uint32_t* ids;
+  int64_t n;
+};
+void launch_gather(const GatherParams& p, hipStream_t s);
+
+// Top-N: composite sort keys (a, b, c, row) in two candidate buffers of
+// lists of `pow2` entries each.
+constexpr int kTopMax = 1024;   // largest N
+constexpr int kTopFanIn = 16;   // lists folded per workgroup in a merge round
+struct TopBuf {
+  uint64_t* a;
+  uint64_t* b;
+  uint64_t* c;
+  uint32_t* row;
+};
+struct TopNParams {
+  const void* order;        // int64 values or binary64 bit patterns
+  int32_t order_is_double;
+  int32_t desc;
+  const void* keys[2];
+  int32_t key_type[2];
+  int32_t nkeys;
+  int32_t pow2;             // power of two >= limit, <= kTopMax
+  int64_t n;
+  int64_t limit;
+  int64_t span;             // rows per workgroup of the first phase
+  int32_t nlists;           // workgroups of the first phase (0 when n == 0)
+  TopBuf buf[2];
+  uint32_t* out;
+  long long* d_count;
+};
+hipError_t launch_topn(const TopNParams& p, hipStream_t s);
+
+// ------------------------------------------------------ string group-by
+
+// Group-by on a string key (Arrow offsets/bytes, optionally through
+// dictionary codes) and an optional integer key; slots of `words` words:
+// claim word, COUNT, first row, accumulators.
+struct StrGroupParams {
+  const int64_t* offsets;
+  const uint8_t* bytes;
+  const int32_t* codes;  // NULL: row i is string i
+  int64_t n;
+  const void* ikey;      // NULL: no integer key
+  int32_t ikey_type;
+  const void* val[8];
+  int32_t val_type[8];
+  AccPlan ap;
+  uint64_t* slots;
+  uint64_t mask;
+  int32_t words;
+  int32_t* overflow;
+  int32_t naggs;
+  int32_t agg_op[8];
+  int32_t agg_acc[8];
+  uint32_t* out_rows;
+  void* out_ikey;
+  void* out_aggs[8];
+  int64_t cap;
+  unsigned long long* d_groups;
+};
+void launch_groupby_str(const StrGroupParams& p, hipStream_t s);
 
 // ------------------------------------------------------------- hash maps
 
@@ -209,7 +287,20 @@ struct MapProbeParams {
   uint32_t* out_probe;
   int64_t cap;
   unsigned long long* d_count;
+  BloomDesc bloom;  // words != NULL: probe keys absent from this filter skip the table
 };
+
+// Clears the filter (blocks * 32 bytes at words) and inserts the n keys of
+// column (keys, idx, type).
+struct BloomBuildParams {
+  uint32_t* words;
+  uint64_t bmask;
+  const void* keys;
+  const uint32_t* idx;
+  int32_t type;
+  int64_t n;
+};
+void launch_bloom_build(const BloomBuildParams& p, hipStream_t s);
 
 void launch_map_probe(const MapProbeParams& p, int grid, int block, hipStream_t s);
 
@@ -378,6 +469,8 @@ struct PipelineParams {
   int32_t spec;               // row spec of the fused kernels (0: generic)
   int64_t spec_lo;            // specialised kernels: the predicate term as the range
   uint64_t spec_span;         //   [spec_lo, spec_lo + spec_span) of the widened value
+  const void* spec_key[2];    //   the fact columns of fact keys (no indirection in the loop)
+  const int64_t* spec_val;    //   the value column
   int32_t directable;         // every dim reserved a direct table (or there are none)
   uint32_t lds_group_offset;  // byte offset of the LDS group table
   uint32_t lds_bytes;

@@ -413,6 +413,27 @@ __global__ void __launch_bounds__(256) map_probe_kernel(MapProbeParams p) {
     }
 #pragma unroll
     for (int j = 0; j < kProbeKeys; ++j) key[j] = keys[row[j]];
+    if (p.bloom.words) {
+      // semi-join reduction: keys absent from the build side's Bloom filter
+      // end here, before their walk through the table
+      uint64_t h[kProbeKeys];
+      uint4 qa[kProbeKeys], qb[kProbeKeys];
+#pragma unroll
+      for (int j = 0; j < kProbeKeys; ++j) {
+        h[j] = bloom_hash(static_cast<int64_t>(key[j]));
+        qa[j] = make_uint4(0, 0, 0, 0);
+        qb[j] = qa[j];
+        if (state[j] != kWalkDone) {
+          const uint4* q = reinterpret_cast<const uint4*>(
+              p.bloom.words + bloom_block(h[j], p.bloom.bmask) * 8);
+          qa[j] = q[0];
+          qb[j] = q[1];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kProbeKeys; ++j)
+        if (state[j] != kWalkDone && !bloom_match(h[j], qa[j], qb[j])) state[j] = kWalkDone;
+    }
 #pragma unroll
     for (int j = 0; j < kProbeKeys; ++j) {
       bool oob;

@@ -729,8 +729,8 @@ __device__ __forceinline__ int64_t spec_key(const PipelineParams& p, int j, int6
                                             uint32_t v1) {
   if constexpr (K == kKDim0) return static_cast<int32_t>(v0);
   else if constexpr (K == kKDim1) return static_cast<int32_t>(v1);
-  else if constexpr (K == kKF8) return static_cast<const int8_t*>(p.fact[p.key_col[j]])[r];
-  else if constexpr (K == kKF32) return static_cast<const int32_t*>(p.fact[p.key_col[j]])[r];
+  else if constexpr (K == kKF8) return static_cast<const int8_t*>(p.spec_key[j])[r];
+  else if constexpr (K == kKF32) return static_cast<const int32_t*>(p.spec_key[j])[r];
   else return 0;
 }
 
@@ -787,7 +787,7 @@ __device__ __forceinline__ bool spec_row(const PipelineParams& p, int64_t r, int
   int64_t f0 = 0, f1 = 0, v = 0;
   if constexpr (R::k0 == kKF8 || R::k0 == kKF32) f0 = spec_key<R::k0>(p, 0, r, 0, 0);
   if constexpr (R::k1 == kKF8 || R::k1 == kKF32) f1 = spec_key<R::k1>(p, 1, r, 0, 0);
-  if constexpr (R::value) v = static_cast<const int64_t*>(p.fact[p.acc_col[0]])[r];
+  if constexpr (R::value) v = p.spec_val[r];
   uint32_t v0 = 0, v1 = 0;
   int m0 = 1, m1 = 1;
   if constexpr (D0 != kNone) m0 = probe_examine<D0>(p.dim[0], fk0, q0, st0, v0);
@@ -810,7 +810,7 @@ __device__ __forceinline__ void spec_direct_row(const PipelineParams& p, int64_t
   int64_t f0 = 0, f1 = 0, v = 0;
   if constexpr (R::k0 == kKF8 || R::k0 == kKF32) f0 = spec_key<R::k0>(p, 0, r, 0, 0);
   if constexpr (R::k1 == kKF8 || R::k1 == kKF32) f1 = spec_key<R::k1>(p, 1, r, 0, 0);
-  if constexpr (R::value) v = static_cast<const int64_t*>(p.fact[p.acc_col[0]])[r];
+  if constexpr (R::value) v = p.spec_val[r];
   uint32_t v0 = 0, v1 = 0;
   if constexpr (D0 != kNone)
     if (!direct_probe(dv0, fk0, v0)) return;

@@ -67,7 +67,7 @@ extern "C" {
 const char* rel_kernel_name(int k) {
   static const char* names[] = {"fill", "filter", "map_build", "map_probe",
                                 "group_agg", "pipeline_fused", "group_finalize",
-                                "group_partition", "stream_read"};
+                                "group_partition", "stream_read", "bloom_build", "gather", "top_n"};
   return (k >= 0 && k < REL_K_COUNT) ? names[k] : "unknown";
 }
 

@@ -1,0 +1,299 @@
+// Hash group-by on a variable-length string key, optionally with one integer
+// key beside it: the group-by cost the paper reports on string-keyed
+// ClickBench queries (Section 4.2), done on the hash path rather than by
+// sorting. Strings come in the Arrow layout (row i = bytes[offsets[i] ..
+// offsets[i+1])), directly or dictionary-encoded (row i = dictionary entry
+// codes[i]); either way the group key is the string's bytes, so equal
+// strings under different codes fall into one group.
+//
+// Slots of the open-addressing table (words of 64 bits): [0] the claim word
+// (32-bit string hash << 32 | the row whose insert claimed the slot), [1]
+// COUNT, [2] the smallest row id of the group, then the accumulators. A
+// slot's key is the claiming row's string (and integer key): a row that
+// meets a claim word of equal hash compares its string with the claiming
+// row's, so hash collisions never merge groups. Claim word and claiming row
+// are one 64-bit CAS, so a reader never waits for a second store.
+//
+// Wave-aggregated updates: lanes whose rows landed in the same slot combine
+// their contributions with wave reductions and one lane issues the atomics.
+// A wave walks its distinct slots from the first active lane on while the
+// leading lane's slot is shared; the lanes left over (all in slots of their
+// own) then update directly, so few distinct keys cost one atomic per key
+// and wave, and many cost no more than plain atomics.
+
+#include "internal.h"
+
+namespace rel {
+
+namespace {
+
+constexpr int kStrThreads = 256;
+
+// String row i of the key column: byte offset and length.
+__device__ __forceinline__ void str_span(const StrGroupParams& p, int64_t row, int64_t& off,
+                                         int64_t& len) {
+  const int64_t e = p.codes ? static_cast<int64_t>(p.codes[row]) : row;
+  off = p.offsets[e];
+  len = p.offsets[e + 1] - off;
+}
+
+// Four string bytes from byte position a (little-endian), read as aligned
+// words: both words hold bytes of the string, so they lie inside the buffer.
+__device__ __forceinline__ uint32_t str_word(const uint8_t* bytes, int64_t a) {
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(bytes + (a & ~int64_t(3)));
+  const uint32_t m = static_cast<uint32_t>(a & 3);
+  const uint32_t lo = w[0];
+  if (m == 0) return lo;
+  const uint32_t hi = w[1];
+  return (lo >> (8 * m)) | (hi << (32 - 8 * m));
+}
+
+__device__ __forceinline__ uint32_t str_byte(const uint8_t* bytes, int64_t a) { return bytes[a]; }
+
+// 64-bit hash of the string bytes (whole 32-bit words, then the tail bytes,
+// then the length), mixed with the integer key.
+__device__ __forceinline__ uint64_t str_hash(const uint8_t* bytes, int64_t off, int64_t len,
+                                             int64_t ikey) {
+  uint64_t h = 0x243f6a8885a308d3ULL ^ static_cast<uint64_t>(len);
+  int64_t k = 0;
+  for (; k + 4 <= len; k += 4) {
+    h ^= str_word(bytes, off + k);
+    h *= 0x9e3779b97f4a7c15ULL;
+    h ^= h >> 29;
+  }
+  for (; k < len; ++k) {
+    h ^= str_byte(bytes, off + k) << (8 * (k & 3));
+    h *= 0x9e3779b97f4a7c15ULL;
+    h ^= h >> 29;
+  }
+  return hash64(h ^ hash64(static_cast<uint64_t>(ikey) + 0x13198a2e03707344ULL));
+}
+
+__device__ __forceinline__ bool str_equal(const uint8_t* bytes, int64_t oa, int64_t ob, int64_t len) {
+  int64_t k = 0;
+  for (; k + 4 <= len; k += 4)
+    if (str_word(bytes, oa + k) != str_word(bytes, ob + k)) return false;
+  for (; k < len; ++k)
+    if (bytes[oa + k] != bytes[ob + k]) return false;
+  return true;
+}
+
+__device__ __forceinline__ int64_t str_ikey(const StrGroupParams& p, int64_t row) {
+  return p.ikey ? load_elem(p.ikey, p.ikey_type, row) : 0;
+}
+
+constexpr uint64_t kStrEmpty = ~0ULL;
+
+// The slot index of row `row` (claiming an empty slot if its key is new), or
+// -1 if the table is full.
+__device__ __forceinline__ int64_t str_slot(const StrGroupParams& p, int64_t row) {
+  int64_t off, len;
+  str_span(p, row, off, len);
+  const int64_t ik = str_ikey(p, row);
+  const uint64_t h = str_hash(p.bytes, off, len, ik);
+  const uint64_t mine = (static_cast<uint64_t>(static_cast<uint32_t>(h >> 32)) << 32) |
+                        static_cast<uint32_t>(row);
+  uint64_t s = h & p.mask;
+  for (uint64_t probes = 0; probes <= p.mask; ++probes) {
+    uint64_t* w = p.slots + s * p.words;
+    uint64_t cur = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == kStrEmpty) {
+      const unsigned long long prev =
+          atomicCAS(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(kStrEmpty),
+                    static_cast<unsigned long long>(mine));
+      if (prev == kStrEmpty) return static_cast<int64_t>(s);
+      cur = prev;
+    }
+    if ((cur >> 32) == (mine >> 32)) {
+      const int64_t other = static_cast<int64_t>(static_cast<uint32_t>(cur));
+      int64_t ooff, olen;
+      str_span(p, other, ooff, olen);
+      if (olen == len && str_ikey(p, other) == ik && str_equal(p.bytes, off, ooff, len))
+        return static_cast<int64_t>(s);
+    }
+    s = (s + 1) & p.mask;
+  }
+  atomicOr(p.overflow, 1);
+  return -1;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(v, off, kWave);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ int64_t wave_min_i64(int64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int64_t o = __shfl_xor(v, off, kWave);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ int64_t wave_max_i64(int64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int64_t o = __shfl_xor(v, off, kWave);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Adds `cnt` rows with first row `first` and accumulator inputs acc[] to slot s.
+__device__ __forceinline__ void str_update(const StrGroupParams& p, int64_t s, uint64_t cnt,
+                                           uint64_t first, const int64_t* acc) {
+  uint64_t* w = p.slots + s * p.words;
+  atomicAdd(reinterpret_cast<unsigned long long*>(w + 1), static_cast<unsigned long long>(cnt));
+  atomicMin(reinterpret_cast<unsigned long long*>(w + 2), static_cast<unsigned long long>(first));
+#pragma unroll
+  for (int a = 0; a < kMaxAcc; ++a) {
+    if (a >= p.ap.nacc) break;
+    uint64_t* x = w + 3 + a;
+    if (p.ap.kind[a] == kAccSum)
+      atomicAdd(reinterpret_cast<unsigned long long*>(x), static_cast<unsigned long long>(acc[a]));
+    else if (p.ap.kind[a] == kAccMin)
+      atomicMin(reinterpret_cast<long long*>(x), static_cast<long long>(acc[a]));
+    else
+      atomicMax(reinterpret_cast<long long*>(x), static_cast<long long>(acc[a]));
+  }
+}
+
+__global__ void __launch_bounds__(kStrThreads) str_init_kernel(StrGroupParams p) {
+  const uint64_t total = (p.mask + 1) * static_cast<uint64_t>(p.words);
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kStrThreads + threadIdx.x; i < total;
+       i += static_cast<uint64_t>(gridDim.x) * kStrThreads) {
+    const int w = static_cast<int>(i % p.words);
+    uint64_t v = 0;
+    if (w == 0 || w == 2) v = kStrEmpty;
+    else if (w >= 3) v = acc_identity(p.ap.kind[w - 3]);
+    p.slots[i] = v;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *p.overflow = 0;
+    *p.d_groups = 0;
+  }
+}
+
+__global__ void __launch_bounds__(kStrThreads) str_agg_kernel(StrGroupParams p) {
+  const int lane = lane_id();
+  const uint64_t n = static_cast<uint64_t>(p.n);
+  // the loop bound is uniform per wave (whole waves run the ballots below)
+  const uint64_t step = static_cast<uint64_t>(gridDim.x) * kStrThreads;
+  for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * kStrThreads + threadIdx.x - lane;
+       base < n; base += step) {
+    const uint64_t row = base + lane;
+    const bool live = row < n;
+    int64_t slot = -1;
+    int64_t acc[kMaxAcc];
+#pragma unroll
+    for (int a = 0; a < kMaxAcc; ++a) acc[a] = 0;
+    if (live) {
+      slot = str_slot(p, static_cast<int64_t>(row));
+#pragma unroll
+      for (int a = 0; a < kMaxAcc; ++a)
+        if (a < p.ap.nacc)
+          acc[a] = load_elem(p.val[p.ap.col[a]], p.val_type[p.ap.col[a]], static_cast<int64_t>(row));
+    }
+    // wave-aggregated updates while the leading lane's slot is shared
+    uint64_t todo = ballot(live && slot >= 0);
+    while (todo) {
+      const int leader = __ffsll(static_cast<long long>(todo)) - 1;
+      const int64_t s = __shfl(slot, leader, kWave);
+      const bool in = ((todo >> lane) & 1ULL) && slot == s;
+      const uint64_t members = ballot(in);
+      if (popc64(members) < 2) break;
+      const uint64_t first = wave_min_u64(in ? row : ~0ULL);
+      int64_t red[kMaxAcc];
+#pragma unroll
+      for (int a = 0; a < kMaxAcc; ++a) {
+        if (a >= p.ap.nacc) break;
+        const int kind = p.ap.kind[a];
+        if (kind == kAccSum) red[a] = static_cast<int64_t>(wave_sum_u64(in ? static_cast<uint64_t>(acc[a]) : 0ULL));
+        else if (kind == kAccMin) red[a] = wave_min_i64(in ? acc[a] : INT64_MAX);
+        else red[a] = wave_max_i64(in ? acc[a] : INT64_MIN);
+      }
+      if (lane == leader) str_update(p, s, popc64(members), first, red);
+      todo &= ~members;
+    }
+    // the rest: one slot per lane
+    if ((todo >> lane) & 1ULL) str_update(p, slot, 1, row, acc);
+  }
+}
+
+__global__ void __launch_bounds__(kStrThreads) str_final_kernel(StrGroupParams p) {
+  const int lane = lane_id();
+  const uint64_t slots = p.mask + 1;
+  const uint64_t step = static_cast<uint64_t>(gridDim.x) * kStrThreads;
+  for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * kStrThreads + threadIdx.x - lane;
+       base < slots; base += step) {
+    const uint64_t s = base + lane;
+    const uint64_t* w = p.slots + (s < slots ? s : 0) * p.words;
+    const bool used = s < slots && w[0] != kStrEmpty;
+    const uint64_t m = ballot(used);
+    if (m == 0) continue;
+    unsigned long long at = 0;
+    if (lane == __ffsll(static_cast<long long>(m)) - 1)
+      at = atomicAdd(p.d_groups, static_cast<unsigned long long>(popc64(m)));
+    at = __shfl(at, __ffsll(static_cast<long long>(m)) - 1, kWave);
+    if (!used) continue;
+    const int64_t g = static_cast<int64_t>(at + rank_below(m));
+    if (g >= p.cap) continue;
+    const uint64_t cnt = w[1];
+    const uint32_t first = static_cast<uint32_t>(w[2]);
+    p.out_rows[g] = first;
+    if (p.ikey && p.out_ikey) store_elem(p.out_ikey, p.ikey_type, g, str_ikey(p, first));
+    for (int a = 0; a < p.naggs; ++a) {
+      int64_t v;
+      if (p.agg_op[a] == 1) {  // COUNT
+        v = static_cast<int64_t>(cnt);
+      } else if (p.agg_op[a] == 4) {  // AVG: one binary64 division of the exact values
+        const double q = static_cast<double>(static_cast<int64_t>(w[3 + p.agg_acc[a]])) /
+                         static_cast<double>(cnt);
+        v = __double_as_longlong(q);
+      } else {
+        v = static_cast<int64_t>(w[3 + p.agg_acc[a]]);
+      }
+      static_cast<int64_t*>(p.out_aggs[a])[g] = v;
+    }
+  }
+}
+
+__global__ void str_overflow_kernel(StrGroupParams p) {
+  if (*p.overflow) *p.d_groups = static_cast<unsigned long long>(-1LL);
+}
+
+}  // namespace
+
+void launch_groupby_str(const StrGroupParams& p, hipStream_t s) {
+  {
+    ProfileScope ps(kKFill, s);
+    const uint64_t total = (p.mask + 1) * static_cast<uint64_t>(p.words);
+    uint64_t blocks = (total + kStrThreads - 1) / kStrThreads;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(str_init_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kStrThreads), 0, s,
+                       p);
+  }
+  {
+    ProfileScope ps(kKGroupAgg, s);
+    if (p.n > 0) {
+      uint64_t blocks = (static_cast<uint64_t>(p.n) + kStrThreads - 1) / kStrThreads;
+      const uint64_t limit = static_cast<uint64_t>(device_info().cu_count) * 16;
+      if (blocks > limit) blocks = limit;
+      hipLaunchKernelGGL(str_agg_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kStrThreads), 0,
+                         s, p);
+    }
+  }
+  {
+    ProfileScope ps(kKFinalize, s);
+    uint64_t blocks = (p.mask + 1 + kStrThreads - 1) / kStrThreads;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(str_final_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kStrThreads), 0,
+                       s, p);
+    hipLaunchKernelGGL(str_overflow_kernel, dim3(1), dim3(1), 0, s, p);
+  }
+}
+
+}  // namespace rel

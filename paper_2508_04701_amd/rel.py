@@ -24,6 +24,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librel.so")
 
 REL_OK, REL_EINVAL, REL_ENOMEM, REL_ECAPACITY, REL_EDEVICE, REL_EUNSUPPORTED = range(6)
+REL_F64 = 4
 DTYPES = {torch.int8: 1, torch.int32: 2, torch.int64: 3}
 TORCH_DTYPE = {1: torch.int8, 2: torch.int32, 3: torch.int64}
 CMP = {"lt": 0, "le": 1, "gt": 2, "ge": 3, "eq": 4, "ne": 5, "range": 6}
@@ -77,6 +78,11 @@ class PipelineDesc(ctypes.Structure):
                 ("max_groups", ctypes.c_int64), ("tuning", ctypes.POINTER(Tuning))]
 
 
+class Strings(ctypes.Structure):
+    _fields_ = [("offsets", ctypes.c_void_p), ("bytes", ctypes.c_void_p), ("codes", ctypes.c_void_p),
+                ("len", ctypes.c_int64), ("n_strings", ctypes.c_int64)]
+
+
 class Outputs(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p * MAX_KEYS), ("aggs", ctypes.c_void_p * MAX_AGGS),
                 ("cap", ctypes.c_int64), ("d_groups", ctypes.c_void_p)]
@@ -120,6 +126,16 @@ SIGNATURES = {
     "rel_pipeline_sync": (_I, [_P, _P, _P, _S, _P, _P]),
     "rel_autotune": (_I, [_P, _I, ctypes.c_char_p]),
     "rel_autotune_lookup": (_I, [ctypes.c_char_p, _P, _P, _P]),
+    "rel_bloom_bytes": (_S, [_L, ctypes.c_int32]),
+    "rel_bloom_build": (_I, [_P, _P, _S, _P]),
+    "rel_bloom_filter": (_I, [_P, _P, _S, _P, _L, _P, _P, _S, _P]),
+    "rel_gather": (_I, [_P, _I, _P, _L, _P, _P]),
+    "rel_topn_ws": (_S, [_L, _L]),
+    "rel_topn": (_I, [_P, ctypes.c_int32, ctypes.c_int32, _P, _I, _L, _L, _P, _P, _P, _S, _P]),
+    "rel_groupby_str_ws": (_S, [_L, _I, _P]),
+    "rel_groupby_str": (_I, [_P, _P, _P, _I, _P, _I, _P, _P, _P, _L, _P, _L, _P, _S, _P]),
+    "rel_pipeline_stream_ws": (_S, [_P, _L]),
+    "rel_pipeline_stream": (_I, [_P, _L, _P, _P, _S, _P]),
 }
 
 _lib = None
@@ -175,6 +191,7 @@ def column(t: torch.Tensor, idx: torch.Tensor | None = None) -> Column:
 
 
 TUNE_NO_DIRECT = 1
+TUNE_BLOOM = 2
 
 
 def tuning(load_factor=0.0, block=0, grid=0, lds_slots=0, dim_lds_bytes=0,
@@ -246,6 +263,81 @@ def filter(cols, preds, idx=None) -> torch.Tensor:
                                  out.numel(), _addr(d_count), _addr(ws), ws.numel(), _stream(),
                                  ctypes.byref(cnt)))
     return out[:cnt.value]
+
+
+# ------------------------------------------------------------- Bloom filter
+
+def bloom_bytes(n_keys: int, bits_per_key: int = 0) -> int:
+    return int(lib().rel_bloom_bytes(n_keys, bits_per_key))
+
+
+def bloom_build(keys: torch.Tensor, bits_per_key: int = 0, idx=None) -> torch.Tensor:
+    """Blocked Bloom filter (uint8 device tensor) over the keys."""
+    _require_gpu(keys)
+    n = idx.numel() if idx is not None else keys.numel()
+    f = workspace(bloom_bytes(n, bits_per_key), keys.device)
+    c = column(keys, idx)
+    _check(lib().rel_bloom_build(ctypes.byref(c), _addr(f), f.numel(), _stream()))
+    return f
+
+
+def bloom_filter_async(keys, filt, out, d_count, ws, idx=None):
+    c = column(keys, idx)
+    _check(lib().rel_bloom_filter(ctypes.byref(c), _addr(filt), filt.numel(), _addr(out),
+                                  out.numel(), _addr(d_count), _addr(ws), ws.numel(), _stream()))
+
+
+def bloom_filter(keys: torch.Tensor, filt: torch.Tensor, idx=None) -> torch.Tensor:
+    """Row ids (ascending) of the keys that may be in the filter."""
+    _require_gpu(keys)
+    n = idx.numel() if idx is not None else keys.numel()
+    out = torch.empty(max(1, n), dtype=torch.int32, device=keys.device)
+    d_count = torch.zeros(1, dtype=torch.int64, device=keys.device)
+    ws = workspace(filter_ws(n), keys.device)
+    bloom_filter_async(keys, filt, out, d_count, ws, idx)
+    return out[:_count(d_count)]
+
+
+# ------------------------------------------------------ late materialisation
+
+def gather_async(cols, ids, out, n=None):
+    """out[c][i] = cols[c][ids[i]] for i < n (default: all of ids)."""
+    n = ids.numel() if n is None else n
+    cc = _arr(Column, [column(c) for c in cols])
+    oo = _arr(ctypes.c_void_p, [o.data_ptr() for o in out])
+    _check(lib().rel_gather(cc, len(cols), _addr(ids), n, oo, _stream()))
+
+
+def gather(cols, ids):
+    """Columns materialised at the row ids (each in its own dtype)."""
+    _require_gpu(*cols)
+    out = [torch.empty(ids.numel(), dtype=c.dtype, device=c.device) for c in cols]
+    if ids.numel():
+        gather_async(cols, ids, out)
+    return out
+
+
+def topn_ws(n: int, limit: int) -> int:
+    return int(lib().rel_topn_ws(n, limit))
+
+
+def topn_async(order, keys, limit, out, d_count, ws, desc=True):
+    n = order.numel()
+    ck = _arr(Column, [column(k) for k in keys])
+    ot = REL_F64 if order.dtype == torch.float64 else DTYPES[order.dtype]
+    _check(lib().rel_topn(_addr(order), ot, 1 if desc else 0, ck, len(keys), n, limit, _addr(out),
+                          _addr(d_count), _addr(ws), ws.numel(), _stream()))
+
+
+def topn(order: torch.Tensor, keys, limit: int, desc: bool = True) -> torch.Tensor:
+    """Row positions of the first `limit` rows ordered by `order` (int64 or
+    float64; descending by default), ties by the key tuple, then position."""
+    _require_gpu(order, *keys)
+    out = torch.empty(max(1, limit), dtype=torch.int32, device=order.device)
+    d_count = torch.zeros(1, dtype=torch.int64, device=order.device)
+    ws = workspace(topn_ws(order.numel(), limit), order.device)
+    topn_async(order, keys, limit, out, d_count, ws, desc)
+    return out[:_count(d_count)]
 
 
 # ----------------------------------------------------------------- hash join
@@ -344,15 +436,69 @@ def groupby_agg(keys, vals, aggs, max_groups: int | None = None, key_idx=None, v
         return [k[:ng.value] for k in out_keys], [a[:ng.value] for a in out_aggs]
 
 
+# ------------------------------------------------------- string group-by
+
+def strings(offsets: torch.Tensor, data: torch.Tensor, codes: torch.Tensor | None = None) -> Strings:
+    """A string column (Arrow layout: int64 offsets, uint8 bytes), optionally
+    dictionary-encoded by int32 codes."""
+    if offsets.dtype != torch.int64 or data.dtype != torch.uint8:
+        raise TypeError("strings need int64 offsets and uint8 bytes")
+    ns = offsets.numel() - 1
+    n = codes.numel() if codes is not None else ns
+    return Strings(_addr(offsets), data.data_ptr() if data.numel() else _addr(offsets),
+                   _addr(codes) if codes is not None else None, n, ns)
+
+
+def groupby_str_ws(aggs, max_groups: int) -> int:
+    return int(lib().rel_groupby_str_ws(max_groups, len(aggs), _aggs(aggs)))
+
+
+def groupby_str(offsets, data, vals, aggs, ikey=None, codes=None, max_groups: int | None = None):
+    """(first row ids, int keys or None, aggregate columns) per distinct
+    (string, int key); order unspecified."""
+    _require_gpu(offsets, data, *vals)
+    dev = offsets.device
+    st = strings(offsets, data, codes)
+    n = st.len
+    max_groups = max(1, n) if max_groups is None else max_groups
+    ws = workspace(groupby_str_ws(aggs, max_groups), dev)
+    cv = _arr(Column, [column(v) for v in vals])
+    ck = column(ikey) if ikey is not None else None
+    d_groups = torch.zeros(1, dtype=torch.int64, device=dev)
+    cap = max(1, min(max_groups, max(1, n)))
+    while True:
+        rows = torch.empty(cap, dtype=torch.int32, device=dev)
+        iks = torch.empty(cap, dtype=ikey.dtype, device=dev) if ikey is not None else None
+        out_aggs = [torch.empty(cap, dtype=torch.float64 if op == "avg" else torch.int64, device=dev)
+                    for op, _ in aggs]
+        oa = _arr(ctypes.c_void_p, [o.data_ptr() for o in out_aggs])
+        _check(lib().rel_groupby_str(ctypes.byref(st), ctypes.byref(ck) if ck is not None else None,
+                                     cv, len(vals), _aggs(aggs), len(aggs), _addr(rows),
+                                     _addr(iks) if iks is not None else None, oa, cap,
+                                     _addr(d_groups), max_groups, _addr(ws), ws.numel(), _stream()))
+        ng = _count(d_groups)
+        if ng < 0:
+            raise RelError(REL_ECAPACITY, f"more than max_groups={max_groups} groups")
+        if ng <= cap:
+            return rows[:ng], (iks[:ng] if iks is not None else None), [a[:ng] for a in out_aggs]
+        cap = ng
+
+
 # ------------------------------------------------------------------ pipeline
 
 class Plan:
     """A fused plan bound to its inputs and output buffers (no workspace)."""
 
     def __init__(self, fact, preds, dims, keys, aggs, max_groups: int, t: Tuning | None = None,
-                 out_cap: int | None = None):
-        _require_gpu(*fact)
-        dev = fact[0].device
+                 out_cap: int | None = None, host_fact: bool = False):
+        if host_fact:
+            # fact columns in (pinned) host memory, streamed by rel_pipeline_stream
+            if not torch.cuda.is_available():
+                raise RuntimeError("the relational kernels need a ROCm GPU; none is visible")
+            dev = dims[0]["key"].device if dims else torch.device("cuda", torch.cuda.current_device())
+        else:
+            _require_gpu(*fact)
+            dev = fact[0].device
         self.device = dev
         self._keep = [fact, dims]
         self.aggs = aggs
@@ -477,6 +623,29 @@ class PreparedBatch:
         return [p.result() for p in self.plans]
 
 
+class StreamedPipeline(Plan):
+    """A fused plan over fact columns in host memory (pinned CPU tensors),
+    streamed through the device in chunks by rel_pipeline_stream."""
+
+    def __init__(self, fact, preds, dims, keys, aggs, max_groups: int, chunk_rows: int,
+                 t: Tuning | None = None):
+        for c in fact:
+            if c.is_cuda:
+                raise ValueError("streamed fact columns live in host memory")
+        super().__init__(fact, preds, dims, keys, aggs, max_groups, t, host_fact=True)
+        self.chunk_rows = chunk_rows
+        nbytes = lib().rel_pipeline_stream_ws(ctypes.byref(self.desc), chunk_rows)
+        if nbytes == 0:
+            _check(lib().rel_pipeline_stream(ctypes.byref(self.desc), chunk_rows, None, None, 0,
+                                             None))
+        self.ws = workspace(nbytes, self.device)
+
+    def launch(self):
+        _check(lib().rel_pipeline_stream(ctypes.byref(self.desc), self.chunk_rows,
+                                         ctypes.byref(self.outputs), _addr(self.ws),
+                                         self.ws.numel(), _stream()))
+
+
 def pipeline(fact, preds, dims, keys, aggs, max_groups: int, t: Tuning | None = None):
     """Runs the fused plan and returns (key columns, aggregate columns)."""
     return PreparedPipeline(fact, preds, dims, keys, aggs, max_groups, t).run()
@@ -501,7 +670,7 @@ def stream_read(t: torch.Tensor) -> int:
 
 # ------------------------------------------------------------------ profiling
 
-KERNEL_CLASSES = 9
+KERNEL_CLASSES = 12
 
 
 def profile_enable(on: bool = True):

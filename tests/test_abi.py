@@ -263,3 +263,79 @@ def test_filter_noalloc_validation():
     # beyond the static scratch's 131040 tile states: rejected before any HIP call
     assert call(1_073_479_680 + 1) == rel.REL_ECAPACITY
     assert b"static scratch" in L.rel_last_error()
+
+
+def test_bloom_validation_and_sizes():
+    L = rel.lib()
+    P = ctypes.c_void_p
+    assert L.rel_bloom_bytes(0, 0) == 32
+    assert L.rel_bloom_bytes(1000, 16) == 32 * 64  # 1000*16/256 = 62.5 -> 64 blocks
+    assert L.rel_bloom_bytes(1000, 3) == 0 and L.rel_bloom_bytes(-1, 0) == 0
+    c = rel.Column(0x1000, None, 100, 2, 0)
+    assert L.rel_bloom_build(ctypes.byref(c), P(0x2010), 64, None) == rel.REL_EINVAL  # misaligned
+    assert L.rel_bloom_build(ctypes.byref(c), P(0x2000), 96, None) == rel.REL_EINVAL  # 3 blocks
+    assert L.rel_bloom_build(ctypes.byref(c), P(0), 64, None) == rel.REL_EINVAL
+    need = L.rel_filter_ws(100)
+    assert L.rel_bloom_filter(ctypes.byref(c), P(0x2000), 64, P(0x3000), 100, P(0x4000),
+                              P(0x10000), need - 1, None) == rel.REL_ENOMEM
+    assert L.rel_bloom_filter(ctypes.byref(c), P(0x2000), 64, P(0x3000), 100, P(0),
+                              P(0x10000), need, None) == rel.REL_EINVAL
+    plain = L.rel_hash_join_ws(3, 1_000_000, None)
+    bloom = L.rel_hash_join_ws(3, 1_000_000, ctypes.byref(rel.tuning(flags=rel.TUNE_BLOOM)))
+    assert bloom >= plain + L.rel_bloom_bytes(1_000_000, 16)
+    t = rel.tuning(flags=8)
+    assert L.rel_hash_join_ws(3, 1000, ctypes.byref(t)) == 0  # unknown flag bit
+
+
+def test_gather_and_topn_validation():
+    L = rel.lib()
+    P = ctypes.c_void_p
+    c = (rel.Column * 1)(rel.Column(0x1000, None, 100, 2, 0))
+    outs = (ctypes.c_void_p * 1)(0x5000)
+    assert L.rel_gather(c, 0, P(0x2000), 10, outs, None) == rel.REL_EINVAL
+    assert L.rel_gather(c, 1, P(0), 10, outs, None) == rel.REL_EINVAL
+    ci = (rel.Column * 1)(rel.Column(0x1000, 0x3000, 100, 2, 0))
+    assert L.rel_gather(ci, 1, P(0x2000), 10, outs, None) == rel.REL_EINVAL
+    assert L.rel_topn_ws(1000, 1025) == 0 and L.rel_topn_ws(1000, 10) > 0
+    ws = L.rel_topn_ws(1000, 10)
+    assert L.rel_topn(P(0x1000), 3, 1, None, 0, 1000, 1025, P(0x2000), P(0x3000), P(0x10000), ws,
+                      None) == rel.REL_EINVAL
+    assert L.rel_topn(P(0x1000), 2, 1, None, 0, 1000, 10, P(0x2000), P(0x3000), P(0x10000), ws,
+                      None) == rel.REL_EINVAL  # int32 order column
+    assert L.rel_topn(P(0x1004), 3, 1, None, 0, 1000, 10, P(0x2000), P(0x3000), P(0x10000), ws,
+                      None) == rel.REL_EINVAL  # misaligned order
+    assert L.rel_topn(P(0x1000), 4, 1, None, 0, 1000, 10, P(0x2000), P(0x3000), P(0x10000),
+                      ws - 1, None) == rel.REL_ENOMEM
+    short = (rel.Column * 1)(rel.Column(0x1000, None, 999, 3, 0))
+    assert L.rel_topn(P(0x1000), 3, 1, short, 1, 1000, 10, P(0x2000), P(0x3000), P(0x10000), ws,
+                      None) == rel.REL_EINVAL  # key shorter than the table
+
+
+def test_binding_sizes_profile_arrays_like_the_header():
+    """rel_profile_read writes REL_K_COUNT entries: the binding's arrays must
+    be that long (a shorter one would be overwritten)."""
+    text = open(HEADER).read()
+    count = int(re.search(r"REL_K_COUNT\s*=\s*(\d+)", text).group(1))
+    assert rel.KERNEL_CLASSES == count
+    names = {rel.lib().rel_kernel_name(k).decode() for k in range(count)}
+    assert "unknown" not in names and len(names) == count
+
+
+def test_pipeline_stream_validation():
+    L = rel.lib()
+    P = ctypes.c_void_p
+    fact = (rel.Column * 1)(rel.Column(0x1000, None, 10_000, 2, 0))
+    aggs = (rel.Agg * 1)(rel.Agg(1, 0))
+    d = rel.PipelineDesc(ctypes.cast(fact, ctypes.POINTER(rel.Column)), 1, None, 0, None, 0, None,
+                         0, ctypes.cast(aggs, ctypes.POINTER(rel.Agg)), 1, 1, None)
+    assert L.rel_pipeline_stream_ws(ctypes.byref(d), 1000) == 0  # not a multiple of 2048
+    ws = L.rel_pipeline_stream_ws(ctypes.byref(d), 4096)
+    assert ws >= L.rel_pipeline_ws(ctypes.byref(d)) + 2 * 4096 * 4
+    o = rel.Outputs()
+    o.aggs[0] = 0x5000
+    o.cap = 1
+    o.d_groups = 0x6000
+    assert L.rel_pipeline_stream(ctypes.byref(d), 3000, ctypes.byref(o), P(0x10000), ws,
+                                 None) == rel.REL_EINVAL
+    assert L.rel_pipeline_stream(ctypes.byref(d), 4096, ctypes.byref(o), P(0x10000), ws - 1,
+                                 None) == rel.REL_ENOMEM

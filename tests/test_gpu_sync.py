@@ -50,7 +50,8 @@ def test_hash_join_sync_capacity_and_retry():
     ob = torch.empty(7, dtype=torch.int32, device="cuda")
     op = torch.empty(7, dtype=torch.int32, device="cuda")
     d = torch.zeros(1, dtype=torch.int64, device="cuda")
-    cb, cp = rel.column(dev(b)), rel.column(dev(p))
+    db, dp = dev(b), dev(p)  # kept alive while the columns point into them
+    cb, cp = rel.column(db), rel.column(dp)
     total = ctypes.c_int64()
     st = rel.lib().rel_hash_join_sync(ctypes.byref(cb), ctypes.byref(cp), rel._addr(ob),
                                       rel._addr(op), 7, rel._addr(d), None, rel._addr(ws),
