@@ -598,7 +598,7 @@ def bench_strings(args, torch, datagen, rel, kernel_ms, line) -> dict:
         dval = torch.from_numpy(val).cuda()
         del codes, val
         mg = nd
-        ws = rel.workspace(rel.groupby_str_ws(aggs, mg))
+        ws = rel.workspace(rel.groupby_str_ws(aggs, mg, 0 if plain else nd))
         st = rel.strings(doff, ddata, dcodes)
         cv = rel._arr(rel.Column, [rel.column(dval)])
         rows = torch.empty(mg, dtype=torch.int32, device="cuda")

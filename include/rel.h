@@ -320,9 +320,10 @@ typedef struct {
   int64_t n_strings;
 } rel_strings;
 
-/* Workspace bytes for rel_groupby_str with at most max_groups groups (0 for
- * invalid arguments). */
-size_t rel_groupby_str_ws(int64_t max_groups, int naggs, const rel_agg* aggs);
+/* Workspace bytes for rel_groupby_str with at most max_groups groups over a
+ * column whose dictionary holds n_dict strings (0 without codes; with codes,
+ * n_dict = the column's n_strings); 0 for invalid arguments. */
+size_t rel_groupby_str_ws(int64_t max_groups, int64_t n_dict, int naggs, const rel_agg* aggs);
 
 /* Hash group-by on a string key (Section 4.2 reports the cost of string
  * group keys on ClickBench), optionally with an integer key beside it (a

@@ -1544,20 +1544,41 @@ namespace rel {
 namespace {
 
 struct StrLayout {
-  uint64_t cap = 0;
+  uint64_t cap = 0, dict_cap = 0;
   int words = 0;
-  size_t slots_off = 0, overflow_off = 0, end = 0;
+  size_t slots_off = 0, overflow_off = 0, dict_off = 0, canon_off = 0, end = 0;
 };
 
-StrLayout str_layout(int64_t max_groups, int nacc) {
+// Group table of 2 x max_groups slots (at least 64); with a dictionary of
+// n_dict entries, its string table (2 x n_dict claim words) and the
+// canonical id of every entry.
+StrLayout str_layout(int64_t max_groups, int64_t n_dict, int nacc) {
   StrLayout L;
   uint64_t want = static_cast<uint64_t>(max_groups > 0 ? max_groups : 1) * 2;
   L.cap = next_pow2(want < 64 ? 64 : want);
   L.words = 3 + nacc;
   L.slots_off = 0;
   L.overflow_off = align_up(L.cap * L.words * 8);
-  L.end = L.overflow_off + kAlign;
+  L.dict_off = L.overflow_off + kAlign;
+  L.end = L.dict_off;
+  if (n_dict > 0) {
+    const uint64_t dw = static_cast<uint64_t>(n_dict) * 2;
+    L.dict_cap = next_pow2(dw < 64 ? 64 : dw);
+    L.canon_off = align_up(L.dict_off + L.dict_cap * 8);
+    L.end = L.canon_off + static_cast<size_t>(n_dict) * 4;
+  }
   return L;
+}
+
+// LDS pre-aggregation entries per workgroup: a power of two within a 32 KB
+// table (16 + 8 x nacc bytes an entry), no more than the group table has
+// slots, none when slot indices would not fit the table's 32-bit keys.
+int32_t str_lds_slots(uint64_t cap, int nacc) {
+  if (cap > (1ULL << 31)) return 0;
+  uint64_t k = 2048;
+  while (k > 256 && k * (16 + 8 * static_cast<uint64_t>(nacc)) > 32768) k >>= 1;
+  if (k > cap) k = cap;
+  return static_cast<int32_t>(k);
 }
 
 }  // namespace
@@ -1565,12 +1586,13 @@ StrLayout str_layout(int64_t max_groups, int nacc) {
 
 extern "C" {
 
-size_t rel_groupby_str_ws(int64_t max_groups, int naggs, const rel_agg* aggs) {
-  if (max_groups < 0 || max_groups > kMaxRows || naggs < 1 || naggs > REL_MAX_AGGS || !aggs)
+size_t rel_groupby_str_ws(int64_t max_groups, int64_t n_dict, int naggs, const rel_agg* aggs) {
+  if (max_groups < 0 || max_groups > kMaxRows || n_dict < 0 || n_dict > kMaxRows || naggs < 1 ||
+      naggs > REL_MAX_AGGS || !aggs)
     return 0;
   GroupPlan gp;
   if (group_plan(0, nullptr, naggs, aggs, gp) != REL_OK) return 0;
-  return align_up(str_layout(max_groups, gp.ap.nacc).end);
+  return align_up(str_layout(max_groups, n_dict, gp.ap.nacc).end);
 }
 
 rel_status rel_groupby_str(const rel_strings* key, const rel_column* ikey, const rel_column* vals,
@@ -1610,7 +1632,9 @@ rel_status rel_groupby_str(const rel_strings* key, const rel_column* ikey, const
   GroupPlan gp;
   st = group_plan(0, nullptr, naggs, aggs, gp);
   if (st) return st;
-  const StrLayout L = str_layout(max_groups, gp.ap.nacc);
+  if (key->n_strings > kMaxRows) return fail(REL_EINVAL, "string group-by: too many strings");
+  const int64_t n_dict = key->codes ? key->n_strings : 0;
+  const StrLayout L = str_layout(max_groups, n_dict, gp.ap.nacc);
   st = check_ws(ws, ws_bytes, align_up(L.end));
   if (st) return st;
   unsigned char* w = static_cast<unsigned char*>(ws);
@@ -1633,6 +1657,13 @@ rel_status rel_groupby_str(const rel_strings* key, const rel_column* ikey, const
   p.mask = L.cap - 1;
   p.words = L.words;
   p.overflow = reinterpret_cast<int32_t*>(w + L.overflow_off);
+  p.n_dict = n_dict;
+  if (n_dict > 0) {
+    p.dict_slots = reinterpret_cast<uint64_t*>(w + L.dict_off);
+    p.dict_mask = L.dict_cap - 1;
+    p.canon = reinterpret_cast<uint32_t*>(w + L.canon_off);
+  }
+  p.lds_slots = str_lds_slots(L.cap, gp.ap.nacc);
   p.naggs = naggs;
   for (int a = 0; a < naggs; ++a) {
     p.agg_op[a] = aggs[a].op;

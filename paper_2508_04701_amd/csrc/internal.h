@@ -143,6 +143,11 @@ struct StrGroupParams {
   const uint8_t* bytes;
   const int32_t* codes;  // NULL: row i is string i
   int64_t n;
+  int64_t n_dict;         // dictionary entries (codes only)
+  uint64_t* dict_slots;   // claim words of the dictionary's string table
+  uint64_t dict_mask;
+  uint32_t* canon;        // canonical id of each dictionary entry
+  int32_t lds_slots;      // LDS pre-aggregation entries (0 or a power of two)
   const void* ikey;      // NULL: no integer key
   int32_t ikey_type;
   const void* val[8];

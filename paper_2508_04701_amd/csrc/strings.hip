@@ -6,20 +6,29 @@
 // codes[i]); either way the group key is the string's bytes, so equal
 // strings under different codes fall into one group.
 //
-// Slots of the open-addressing table (words of 64 bits): [0] the claim word
-// (32-bit string hash << 32 | the row whose insert claimed the slot), [1]
-// COUNT, [2] the smallest row id of the group, then the accumulators. A
-// slot's key is the claiming row's string (and integer key): a row that
-// meets a claim word of equal hash compares its string with the claiming
-// row's, so hash collisions never merge groups. Claim word and claiming row
-// are one 64-bit CAS, so a reader never waits for a second store.
+// Slots of the open-addressing table (words of 64 bits): [0] the claim word,
+// [1] COUNT, [2] the smallest row id of the group, then the accumulators.
+// The claim word packs a 32-bit key tag over the row whose insert claimed the
+// slot, in one 64-bit CAS (a reader never waits for a second store). Arrow
+// layout: the tag is 32 bits of the string's hash, and a row that meets an
+// equal tag compares its string (and integer key) with the claiming row's,
+// so hash collisions never merge groups. Dictionary layout: the tag is the
+// canonical dictionary id itself (below), exact by construction; only an
+// integer key, if any, is compared through the claiming row.
 //
-// Wave-aggregated updates: lanes whose rows landed in the same slot combine
-// their contributions with wave reductions and one lane issues the atomics.
-// A wave walks its distinct slots from the first active lane on while the
-// leading lane's slot is shared; the lanes left over (all in slots of their
-// own) then update directly, so few distinct keys cost one atomic per key
-// and wave, and many cost no more than plain atomics.
+// Dictionary-encoded columns are canonicalised first: one pass over the
+// dictionary gives every entry the id of an entry with equal bytes (the one
+// whose insert claimed the string's slot in a table of the dictionary's
+// strings), so a row's key is then the integer pair (canonical id, integer
+// key) and the per-row work has no string hashing or comparison.
+//
+// Pre-aggregation in LDS: each workgroup keeps a small direct-mapped table
+// keyed by global slot index; a row whose slot has (or claims) one of its
+// two LDS candidates updates LDS with shared-memory atomics, any other row
+// updates the global slot. The LDS tables are added into their global
+// slots when the workgroup ends, so a hot key costs one set of global
+// atomics per workgroup instead of one per row (same-address global atomics
+// serialise, and a Zipf-skewed key column sends most rows to a few slots).
 
 #include "internal.h"
 
@@ -117,29 +126,70 @@ __device__ __forceinline__ int64_t str_slot(const StrGroupParams& p, int64_t row
   return -1;
 }
 
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint64_t o = __shfl_xor(v, off, kWave);
-    v = o < v ? o : v;
+// Canonical id of every dictionary entry: the entry whose insert claimed
+// the entry's string in a table of the dictionary's strings (claim word:
+// 32-bit string hash << 32 | entry). The table holds at least twice as many
+// slots as entries, so every probe sequence ends.
+__global__ void __launch_bounds__(kStrThreads) dict_canon_kernel(StrGroupParams p) {
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * kStrThreads + threadIdx.x; e < p.n_dict;
+       e += static_cast<int64_t>(gridDim.x) * kStrThreads) {
+    const int64_t off = p.offsets[e];
+    const int64_t len = p.offsets[e + 1] - off;
+    const uint64_t h = str_hash(p.bytes, off, len, 0);
+    const uint64_t mine = (h >> 32 << 32) | static_cast<uint32_t>(e);
+    uint32_t canon = static_cast<uint32_t>(e);
+    uint64_t s = h & p.dict_mask;
+    for (uint64_t probes = 0; probes <= p.dict_mask; ++probes) {
+      uint64_t* w = p.dict_slots + s;
+      uint64_t cur = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (cur == kStrEmpty) {
+        const unsigned long long prev =
+            atomicCAS(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(kStrEmpty),
+                      static_cast<unsigned long long>(mine));
+        if (prev == kStrEmpty) break;
+        cur = prev;
+      }
+      if ((cur >> 32) == (mine >> 32)) {
+        const int64_t other = static_cast<int64_t>(static_cast<uint32_t>(cur));
+        const int64_t ooff = p.offsets[other];
+        if (p.offsets[other + 1] - ooff == len && str_equal(p.bytes, off, ooff, len)) {
+          canon = static_cast<uint32_t>(other);
+          break;
+        }
+      }
+      s = (s + 1) & p.dict_mask;
+    }
+    p.canon[e] = canon;
   }
-  return v;
 }
-__device__ __forceinline__ int64_t wave_min_i64(int64_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const int64_t o = __shfl_xor(v, off, kWave);
-    v = o < v ? o : v;
+
+// The slot index of dictionary-encoded row `row`, keyed by (canonical id,
+// integer key), claiming an empty slot if the key is new; -1 if the table is
+// full. Canonical ids and row ids stay below 2^32 - 1, so a claim word never
+// equals the empty pattern.
+__device__ __forceinline__ int64_t dict_slot(const StrGroupParams& p, int64_t row) {
+  const uint32_t c = p.canon[p.codes[row]];
+  const int64_t ik = str_ikey(p, row);
+  const uint64_t h =
+      hash64((static_cast<uint64_t>(c) << 32 | c) ^ hash64(static_cast<uint64_t>(ik) + 0x13198a2e03707344ULL));
+  const uint64_t mine = (static_cast<uint64_t>(c) << 32) | static_cast<uint32_t>(row);
+  uint64_t s = h & p.mask;
+  for (uint64_t probes = 0; probes <= p.mask; ++probes) {
+    uint64_t* w = p.slots + s * p.words;
+    uint64_t cur = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == kStrEmpty) {
+      const unsigned long long prev =
+          atomicCAS(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(kStrEmpty),
+                    static_cast<unsigned long long>(mine));
+      if (prev == kStrEmpty) return static_cast<int64_t>(s);
+      cur = prev;
+    }
+    if ((cur >> 32) == c && (!p.ikey || str_ikey(p, static_cast<uint32_t>(cur)) == ik))
+      return static_cast<int64_t>(s);
+    s = (s + 1) & p.mask;
   }
-  return v;
-}
-__device__ __forceinline__ int64_t wave_max_i64(int64_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const int64_t o = __shfl_xor(v, off, kWave);
-    v = o > v ? o : v;
-  }
-  return v;
+  atomicOr(p.overflow, 1);
+  return -1;
 }
 
 // Adds `cnt` rows with first row `first` and accumulator inputs acc[] to slot s.
@@ -177,49 +227,79 @@ __global__ void __launch_bounds__(kStrThreads) str_init_kernel(StrGroupParams p)
   }
 }
 
+constexpr uint32_t kLdsEmpty = ~0u;
+
+// LDS pre-aggregation table of a workgroup (K entries): COUNT (K words),
+// accumulators (nacc x K words), global slot index (K), smallest row (K).
+struct StrLds {
+  uint64_t* cnt;
+  uint64_t* acc;
+  uint32_t* key;
+  uint32_t* first;
+};
+
+template <bool kDict>
 __global__ void __launch_bounds__(kStrThreads) str_agg_kernel(StrGroupParams p) {
-  const int lane = lane_id();
+  extern __shared__ uint64_t str_lds[];
+  const uint32_t K = static_cast<uint32_t>(p.lds_slots);
+  const int nacc = p.ap.nacc;
+  StrLds t;
+  t.cnt = str_lds;
+  t.acc = str_lds + K;
+  t.key = reinterpret_cast<uint32_t*>(str_lds + static_cast<uint64_t>(K) * (1 + nacc));
+  t.first = t.key + K;
+  for (uint32_t i = threadIdx.x; i < K; i += kStrThreads) {
+    t.cnt[i] = 0;
+    t.key[i] = kLdsEmpty;
+    t.first[i] = kLdsEmpty;
+    for (int a = 0; a < nacc; ++a) t.acc[a * K + i] = acc_identity(p.ap.kind[a]);
+  }
+  __syncthreads();
+
   const uint64_t n = static_cast<uint64_t>(p.n);
-  // the loop bound is uniform per wave (whole waves run the ballots below)
   const uint64_t step = static_cast<uint64_t>(gridDim.x) * kStrThreads;
-  for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * kStrThreads + threadIdx.x - lane;
-       base < n; base += step) {
-    const uint64_t row = base + lane;
-    const bool live = row < n;
-    int64_t slot = -1;
+  for (uint64_t row = static_cast<uint64_t>(blockIdx.x) * kStrThreads + threadIdx.x; row < n;
+       row += step) {
+    const int64_t slot = kDict ? dict_slot(p, static_cast<int64_t>(row))
+                               : str_slot(p, static_cast<int64_t>(row));
+    if (slot < 0) continue;
     int64_t acc[kMaxAcc];
 #pragma unroll
-    for (int a = 0; a < kMaxAcc; ++a) acc[a] = 0;
-    if (live) {
-      slot = str_slot(p, static_cast<int64_t>(row));
+    for (int a = 0; a < kMaxAcc; ++a)
+      acc[a] = a < nacc ? load_elem(p.val[p.ap.col[a]], p.val_type[p.ap.col[a]], static_cast<int64_t>(row))
+                        : 0;
+    bool done = false;
+    if (K != 0) {
+      const uint32_t s32 = static_cast<uint32_t>(slot);
+      for (uint32_t probe = 0; probe < 2 && !done; ++probe) {
+        const uint32_t i = (s32 + probe) & (K - 1);
+        uint32_t cur = __hip_atomic_load(&t.key[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (cur == kLdsEmpty) {
+          cur = atomicCAS(&t.key[i], kLdsEmpty, s32);
+          if (cur == kLdsEmpty) cur = s32;
+        }
+        if (cur == s32) {
+          atomicAdd(reinterpret_cast<unsigned long long*>(&t.cnt[i]), 1ULL);
+          atomicMin(&t.first[i], static_cast<uint32_t>(row));
 #pragma unroll
-      for (int a = 0; a < kMaxAcc; ++a)
-        if (a < p.ap.nacc)
-          acc[a] = load_elem(p.val[p.ap.col[a]], p.val_type[p.ap.col[a]], static_cast<int64_t>(row));
-    }
-    // wave-aggregated updates while the leading lane's slot is shared
-    uint64_t todo = ballot(live && slot >= 0);
-    while (todo) {
-      const int leader = __ffsll(static_cast<long long>(todo)) - 1;
-      const int64_t s = __shfl(slot, leader, kWave);
-      const bool in = ((todo >> lane) & 1ULL) && slot == s;
-      const uint64_t members = ballot(in);
-      if (popc64(members) < 2) break;
-      const uint64_t first = wave_min_u64(in ? row : ~0ULL);
-      int64_t red[kMaxAcc];
-#pragma unroll
-      for (int a = 0; a < kMaxAcc; ++a) {
-        if (a >= p.ap.nacc) break;
-        const int kind = p.ap.kind[a];
-        if (kind == kAccSum) red[a] = static_cast<int64_t>(wave_sum_u64(in ? static_cast<uint64_t>(acc[a]) : 0ULL));
-        else if (kind == kAccMin) red[a] = wave_min_i64(in ? acc[a] : INT64_MAX);
-        else red[a] = wave_max_i64(in ? acc[a] : INT64_MIN);
+          for (int a = 0; a < kMaxAcc; ++a)
+            if (a < nacc) lds_acc_update(&t.acc[a * K + i], p.ap.kind[a], acc[a]);
+          done = true;
+        }
       }
-      if (lane == leader) str_update(p, s, popc64(members), first, red);
-      todo &= ~members;
     }
-    // the rest: one slot per lane
-    if ((todo >> lane) & 1ULL) str_update(p, slot, 1, row, acc);
+    if (!done) str_update(p, slot, 1, row, acc);
+  }
+
+  // the workgroup's LDS table into the global slots
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < K; i += kStrThreads) {
+    const uint32_t key = t.key[i];
+    if (key == kLdsEmpty) continue;
+    int64_t acc[kMaxAcc];
+#pragma unroll
+    for (int a = 0; a < kMaxAcc; ++a) acc[a] = a < nacc ? static_cast<int64_t>(t.acc[a * K + i]) : 0;
+    str_update(p, key, t.cnt[i], t.first[i], acc);
   }
 }
 
@@ -267,6 +347,22 @@ __global__ void str_overflow_kernel(StrGroupParams p) {
 
 }  // namespace
 
+template <bool kDict>
+void launch_str_agg(const StrGroupParams& p, hipStream_t s) {
+  const size_t lds = static_cast<size_t>(p.lds_slots) * (16 + 8 * static_cast<size_t>(p.ap.nacc));
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, str_agg_kernel<kDict>, kStrThreads, lds) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  // every workgroup flushes its whole LDS table once: as many as are resident
+  uint64_t blocks = (static_cast<uint64_t>(p.n) + kStrThreads - 1) / kStrThreads;
+  const uint64_t limit = static_cast<uint64_t>(device_info().cu_count) * per_cu;
+  if (blocks > limit) blocks = limit;
+  hipLaunchKernelGGL(str_agg_kernel<kDict>, dim3(static_cast<unsigned>(blocks)), dim3(kStrThreads), lds,
+                     s, p);
+}
+
 void launch_groupby_str(const StrGroupParams& p, hipStream_t s) {
   {
     ProfileScope ps(kKFill, s);
@@ -276,14 +372,20 @@ void launch_groupby_str(const StrGroupParams& p, hipStream_t s) {
     hipLaunchKernelGGL(str_init_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kStrThreads), 0, s,
                        p);
   }
+  if (p.codes && p.n > 0) launch_fill64(p.dict_slots, p.dict_mask + 1, kStrEmpty, s);
   {
     ProfileScope ps(kKGroupAgg, s);
     if (p.n > 0) {
-      uint64_t blocks = (static_cast<uint64_t>(p.n) + kStrThreads - 1) / kStrThreads;
-      const uint64_t limit = static_cast<uint64_t>(device_info().cu_count) * 16;
-      if (blocks > limit) blocks = limit;
-      hipLaunchKernelGGL(str_agg_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kStrThreads), 0,
-                         s, p);
+      if (p.codes) {
+        uint64_t blocks = (static_cast<uint64_t>(p.n_dict) + kStrThreads - 1) / kStrThreads;
+        if (blocks > 8192) blocks = 8192;
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL(dict_canon_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kStrThreads), 0,
+                           s, p);
+        launch_str_agg<true>(p, s);
+      } else {
+        launch_str_agg<false>(p, s);
+      }
     }
   }
   {

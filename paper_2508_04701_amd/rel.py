@@ -132,7 +132,7 @@ SIGNATURES = {
     "rel_gather": (_I, [_P, _I, _P, _L, _P, _P]),
     "rel_topn_ws": (_S, [_L, _L]),
     "rel_topn": (_I, [_P, ctypes.c_int32, ctypes.c_int32, _P, _I, _L, _L, _P, _P, _P, _S, _P]),
-    "rel_groupby_str_ws": (_S, [_L, _I, _P]),
+    "rel_groupby_str_ws": (_S, [_L, _L, _I, _P]),
     "rel_groupby_str": (_I, [_P, _P, _P, _I, _P, _I, _P, _P, _P, _L, _P, _L, _P, _S, _P]),
     "rel_pipeline_stream_ws": (_S, [_P, _L]),
     "rel_pipeline_stream": (_I, [_P, _L, _P, _P, _S, _P]),
@@ -449,8 +449,10 @@ def strings(offsets: torch.Tensor, data: torch.Tensor, codes: torch.Tensor | Non
                    _addr(codes) if codes is not None else None, n, ns)
 
 
-def groupby_str_ws(aggs, max_groups: int) -> int:
-    return int(lib().rel_groupby_str_ws(max_groups, len(aggs), _aggs(aggs)))
+def groupby_str_ws(aggs, max_groups: int, n_dict: int = 0) -> int:
+    """Workspace bytes; n_dict = the dictionary's string count for a
+    dictionary-encoded column, 0 otherwise."""
+    return int(lib().rel_groupby_str_ws(max_groups, n_dict, len(aggs), _aggs(aggs)))
 
 
 def groupby_str(offsets, data, vals, aggs, ikey=None, codes=None, max_groups: int | None = None):
@@ -461,7 +463,7 @@ def groupby_str(offsets, data, vals, aggs, ikey=None, codes=None, max_groups: in
     st = strings(offsets, data, codes)
     n = st.len
     max_groups = max(1, n) if max_groups is None else max_groups
-    ws = workspace(groupby_str_ws(aggs, max_groups), dev)
+    ws = workspace(groupby_str_ws(aggs, max_groups, st.n_strings if codes is not None else 0), dev)
     cv = _arr(Column, [column(v) for v in vals])
     ck = column(ikey) if ikey is not None else None
     d_groups = torch.zeros(1, dtype=torch.int64, device=dev)

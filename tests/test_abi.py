@@ -339,3 +339,28 @@ def test_pipeline_stream_validation():
                                  None) == rel.REL_EINVAL
     assert L.rel_pipeline_stream(ctypes.byref(d), 4096, ctypes.byref(o), P(0x10000), ws - 1,
                                  None) == rel.REL_ENOMEM
+
+
+def test_string_groupby_validation_and_workspace():
+    L = rel.lib()
+    P = ctypes.c_void_p
+    aggs = (rel.Agg * 1)(rel.Agg(1, 0))
+    assert L.rel_groupby_str_ws(100, -1, 1, aggs) == 0
+    assert L.rel_groupby_str_ws(-1, 0, 1, aggs) == 0
+    plain = L.rel_groupby_str_ws(100, 0, 1, aggs)
+    dicted = L.rel_groupby_str_ws(100, 1000, 1, aggs)
+    assert 0 < plain < dicted
+    # the dictionary's string table (2 x 1000 claim words, rounded up to a
+    # power of two) and one canonical id per entry
+    assert dicted - plain >= 2048 * 8 + 1000 * 4
+    vals = (rel.Column * 1)(rel.Column(0x1000, None, 500, 3, 0))
+    cnt = P(0x9000)
+
+    def call(st, ws_bytes):
+        return L.rel_groupby_str(ctypes.byref(st), None, vals, 1, aggs, 1, P(0x2000), None,
+                                 (P * 1)(0x3000), 100, cnt, 100, P(0x10000), ws_bytes, None)
+
+    coded = rel.Strings(0x4000, 0x5000, 0x6000, 500, 1000)
+    # a workspace sized without the dictionary is too small for its codes
+    assert call(coded, plain) == rel.REL_ENOMEM
+    assert call(rel.Strings(0x4000, 0x5000, None, 500, 1000), plain) == rel.REL_EINVAL

@@ -2,8 +2,8 @@
 and dictionary-encoded columns (a dictionary holding the same string under
 several codes must still give one group), an integer key beside the string,
 empty strings, strings longer than a wave's worth of words, every start
-alignment of the byte offsets, heavy skew (wave-aggregated updates) and the
-group bound; groups compared after sorting by (string, integer key), with
+alignment of the byte offsets, heavy skew (hot keys pre-aggregated in LDS,
+the rest straight to the global table) and the group bound; groups compared after sorting by (string, integer key), with
 the smallest row id of each group exact."""
 
 import numpy as np
@@ -107,4 +107,33 @@ def test_string_groupby_too_many_groups():
     v = np.arange(5000, dtype=np.int64)
     with pytest.raises(rel.RelError) as e:
         rel.groupby_str(dev(off), dev(data), [dev(v)], [("count", None)], max_groups=10)
+    assert e.value.status == rel.REL_ECAPACITY
+
+
+def test_string_groupby_dictionary_zipf_many_groups():
+    """Dictionary codes drawn by Zipf rank over 60k entries that repeat
+    strings: more distinct slots than a workgroup's LDS table holds, so rows
+    take both the LDS and the global update path."""
+    announce("string group-by dictionary zipf")
+    r = np.random.default_rng(7)
+    d_off, d_data = make_strings(r, 60_000, 7, alphabet=5)
+    n = 2_000_000
+    codes = (np.minimum(r.zipf(1.1, size=n), 60_000) - 1).astype(np.int32)
+    v0 = r.integers(-10**9, 10**9, size=n).astype(np.int64)
+    v1 = r.integers(-1000, 1000, size=n).astype(np.int64)
+    got = rel.groupby_str(dev(d_off), dev(d_data), [dev(v0), dev(v1)], AGGS, codes=dev(codes))
+    off, data = expand(d_off, d_data, codes)
+    want = oracle.groupby_str(off, data, [v0, v1], AGGS)
+    check(got, want, AGGS, "dictionary zipf")
+
+
+def test_string_groupby_dictionary_too_many_groups():
+    announce("string group-by dictionary bound")
+    r = np.random.default_rng(8)
+    off, data = make_strings(r, 5000, 20)
+    codes = np.arange(5000, dtype=np.int32)[::-1].copy()
+    v = np.arange(5000, dtype=np.int64)
+    with pytest.raises(rel.RelError) as e:
+        rel.groupby_str(dev(off), dev(data), [dev(v)], [("count", None)], codes=dev(codes),
+                        max_groups=10)
     assert e.value.status == rel.REL_ECAPACITY
