@@ -14,15 +14,18 @@
 //    (ascending or descending), ties broken by the key tuple and then the row
 //    position, so that the answer is unique. Every row becomes a composite
 //    sort key (order word, key words, row) of order-preserving unsigned
-//    integers. Phase one: each workgroup walks a contiguous range of rows in
-//    chunks of P (the power of two >= N, at most 1024), keeps the P smallest
-//    keys seen so far as a sorted list in LDS, and merges a chunk in only
-//    when one of its keys beats the list's current last entry (bitonic sort
-//    of the chunk, element-wise minimum against the reversed list, bitonic
-//    merge). Then rounds of merges, each workgroup folding up to kTopFanIn
-//    lists the same way (skipping a list whose first entry does not beat
-//    the last one kept), until one workgroup writes the first N row
-//    positions in order.
+//    integers. Phase one: each workgroup walks a contiguous range of rows
+//    and keeps the P smallest keys seen so far (P: the power of two >= N, at
+//    most 1024) as a sorted list in LDS. The list's last entry is a running
+//    threshold: a row whose order word is above it cannot enter the list, so
+//    most rows cost one 8-byte load and one compare; the others are appended
+//    to a P-entry candidate buffer in LDS, which, when full (and once at the
+//    end), is sorted (bitonic) and merged into the list (element-wise
+//    minimum against the reversed list, bitonic merge), lowering the
+//    threshold. Then rounds of merges, each workgroup folding up to
+//    kTopFanIn sorted lists the same way (without the sort; a list whose
+//    first entry does not beat the last one kept is skipped), until one
+//    workgroup writes the first N row positions in order.
 
 #include "internal.h"
 
@@ -78,24 +81,12 @@ __device__ __forceinline__ uint64_t sortable_f64(uint64_t bits) {
   return (bits & 0x8000000000000000ULL) ? ~bits : (bits | 0x8000000000000000ULL);
 }
 
-// Composite key of row r: the order word (inverted for descending order),
-// the two key words, the row position.
-__device__ __forceinline__ void top_item(const TopNParams& p, uint32_t r, uint64_t& a, uint64_t& b,
-                                         uint64_t& c) {
-  uint64_t o;
-  if (p.order_is_double) o = sortable_f64(static_cast<const uint64_t*>(p.order)[r]);
-  else o = sortable_i64(static_cast<const int64_t*>(p.order)[r]);
-  a = p.desc ? ~o : o;
-  b = p.nkeys > 0 ? sortable_i64(load_elem(p.keys[0], p.key_type[0], r)) : 0;
-  c = p.nkeys > 1 ? sortable_i64(load_elem(p.keys[1], p.key_type[1], r)) : 0;
-}
-
 struct TopLds {
   uint64_t a[2 * kTopMax];
   uint64_t b[2 * kTopMax];
   uint64_t c[2 * kTopMax];
   uint32_t row[2 * kTopMax];
-  int32_t any;
+  int32_t cnt;  // candidates appended to [P, 2P) (may overshoot P)
 };
 
 __device__ __forceinline__ bool item_less(const TopLds& s, int i, int j) {
@@ -145,10 +136,11 @@ __device__ __forceinline__ void set_empty(TopLds& s, int i) {
   s.row[i] = 0xFFFFFFFFu;
 }
 
-// Merges the P entries at [P, 2P) (a chunk, unsorted) into the sorted list
-// at [0, P): afterwards [0, P) holds the P smallest of both, sorted.
-__device__ __forceinline__ void merge_chunk(TopLds& s, int P) {
-  bitonic_sort(s, P, P);
+// Merges the P entries at [P, 2P) (a chunk, sorted already when `sorted`)
+// into the sorted list at [0, P): afterwards [0, P) holds the P smallest of
+// both, sorted.
+__device__ __forceinline__ void merge_chunk(TopLds& s, int P, bool sorted) {
+  if (!sorted) bitonic_sort(s, P, P);
   // element-wise minimum of the list and the reversed chunk: a bitonic
   // sequence holding the P smallest entries of the two
   for (int i = threadIdx.x; i < P; i += kTopThreads) {
@@ -174,26 +166,66 @@ __global__ void __launch_bounds__(kTopThreads) topn_local_kernel(TopNParams p) {
   int64_t end = begin + p.span;
   if (end > p.n) end = p.n;
   for (int i = threadIdx.x; i < P; i += kTopThreads) set_empty(s, i);
+  if (threadIdx.x == 0) s.cnt = 0;
   __syncthreads();
-  for (int64_t c0 = begin; c0 < end; c0 += P) {
-    // the chunk's keys, and whether any of them beats the list's last entry
-    if (threadIdx.x == 0) s.any = 0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < P; i += kTopThreads) {
-      const int64_t r = c0 + i;
-      const int k = P + i;
+  const uint64_t* ord = static_cast<const uint64_t*>(p.order);
+  constexpr int kRows = 4;  // rows per thread and step, lane-strided (coalesced)
+  for (int64_t c0 = begin; c0 < end; c0 += kTopThreads * kRows) {
+    uint64_t a[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int64_t r = c0 + k * kTopThreads + threadIdx.x;
+      a[k] = ~0ULL;
       if (r < end) {
-        top_item(p, static_cast<uint32_t>(r), s.a[k], s.b[k], s.c[k]);
-        s.row[k] = static_cast<uint32_t>(r);
-        if (item_less(s, k, P - 1)) s.any = 1;
-      } else {
-        set_empty(s, k);
+        const uint64_t o = p.order_is_double ? sortable_f64(ord[r]) : sortable_i64(static_cast<int64_t>(ord[r]));
+        a[k] = p.desc ? ~o : o;
       }
     }
-    __syncthreads();
-    if (s.any) merge_chunk(s, P);
-    __syncthreads();
+    // rows whose order word does not exceed the threshold are candidates
+    // (equal words are decided by the full key when merged)
+    uint64_t thr = s.a[P - 1];
+    uint32_t pend = 0;
+#pragma unroll
+    for (int k = 0; k < kRows; ++k)
+      if (c0 + k * kTopThreads + threadIdx.x < end && a[k] <= thr) pend |= 1u << k;
+    while (true) {
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) {
+        if (!((pend >> k) & 1u)) continue;
+        const int pos = atomicAdd(&s.cnt, 1);
+        if (pos >= P) break;  // buffer full: the rest waits for the merge
+        const int64_t r = c0 + k * kTopThreads + threadIdx.x;
+        const int e = P + pos;
+        s.a[e] = a[k];
+        s.b[e] = p.nkeys > 0 ? sortable_i64(load_elem(p.keys[0], p.key_type[0], r)) : 0;
+        s.c[e] = p.nkeys > 1 ? sortable_i64(load_elem(p.keys[1], p.key_type[1], r)) : 0;
+        s.row[e] = static_cast<uint32_t>(r);
+        pend &= ~(1u << k);
+      }
+      __syncthreads();
+      const int placed = s.cnt;
+      // no thread may append for the next step before every thread has read
+      // the count
+      __syncthreads();
+      if (placed < P) break;  // every candidate placed (block-uniform)
+      merge_chunk(s, P, false);
+      __syncthreads();
+      if (threadIdx.x == 0) s.cnt = 0;
+      thr = s.a[P - 1];
+#pragma unroll
+      for (int k = 0; k < kRows; ++k)
+        if (a[k] > thr) pend &= ~(1u << k);
+      __syncthreads();
+    }
   }
+  // the partly filled buffer
+  const int left = s.cnt;
+  if (left > 0) {
+    for (int i = left + threadIdx.x; i < P; i += kTopThreads) set_empty(s, P + i);
+    __syncthreads();
+    merge_chunk(s, P, false);
+  }
+  __syncthreads();
   const int64_t out = static_cast<int64_t>(blockIdx.x) * P;
   const TopBuf& dst = p.buf[0];
   for (int i = threadIdx.x; i < P; i += kTopThreads) {
@@ -231,7 +263,7 @@ __global__ void __launch_bounds__(kTopThreads) topn_merge_kernel(TopNParams p, i
     __syncthreads();
     // a sorted list whose first entry does not beat the last kept one
     // brings nothing
-    if (item_less(s, P, P - 1)) merge_chunk(s, P);
+    if (item_less(s, P, P - 1)) merge_chunk(s, P, true);
     __syncthreads();
   }
   if (last) {
