@@ -774,15 +774,18 @@ __device__ __forceinline__ void spec_update(const PipelineParams& p, uint64_t pk
 }
 
 // process_row for spec S: hash-table dims without duplicate keys, so every
-// probe is resumable and stops at its first match.
+// probe stops at its first match. A probe that meets a full bucket reads the
+// next one in place (a specialised plan's dims are built at load factors
+// that keep such runs short), so rows are never queued twice.
 template <int D0, int D1, int S>
-__device__ __forceinline__ bool spec_row(const PipelineParams& p, int64_t r, int32_t fk0,
-                                         int32_t fk1, uint32_t& st0, uint32_t& st1,
-                                         uint64_t* lg, const GroupTable& gt, uint32_t acode) {
+__device__ __forceinline__ void spec_row(const PipelineParams& p, int64_t r, int32_t fk0,
+                                         int32_t fk1, uint64_t* lg, const GroupTable& gt,
+                                         uint32_t acode) {
   typedef RowSpec<S> R;
+  uint32_t st0 = 0, st1 = 0;
   uint4 q0 = make_uint4(0, 0, 0, 0), q1 = make_uint4(0, 0, 0, 0);
-  if constexpr (D0 != kNone) q0 = probe_load<D0>(p.dim[0], fk0, st0);
-  if constexpr (D1 != kNone) q1 = probe_load<D1>(p.dim[1], fk1, st1);
+  if constexpr (D0 != kNone) q0 = probe_load<D0>(p.dim[0], fk0, 0);
+  if constexpr (D1 != kNone) q1 = probe_load<D1>(p.dim[1], fk1, 0);
   // fact keys and the value, gathered while the probe reads are in flight
   int64_t f0 = 0, f1 = 0, v = 0;
   if constexpr (R::k0 == kKF8 || R::k0 == kKF32) f0 = spec_key<R::k0>(p, 0, r, 0, 0);
@@ -790,14 +793,18 @@ __device__ __forceinline__ bool spec_row(const PipelineParams& p, int64_t r, int
   if constexpr (R::value) v = p.spec_val[r];
   uint32_t v0 = 0, v1 = 0;
   int m0 = 1, m1 = 1;
-  if constexpr (D0 != kNone) m0 = probe_examine<D0>(p.dim[0], fk0, q0, st0, v0);
-  if constexpr (D1 != kNone) m1 = probe_examine<D1>(p.dim[1], fk1, q1, st1, v1);
-  if (m0 == 0 || m1 == 0) return false;
-  if ((m0 | m1) & 2) return true;
+  if constexpr (D0 != kNone) {
+    m0 = probe_examine<D0>(p.dim[0], fk0, q0, st0, v0);
+    while (m0 == 2) m0 = probe_examine<D0>(p.dim[0], fk0, probe_load<D0>(p.dim[0], fk0, st0), st0, v0);
+  }
+  if constexpr (D1 != kNone) {
+    m1 = probe_examine<D1>(p.dim[1], fk1, q1, st1, v1);
+    while (m1 == 2) m1 = probe_examine<D1>(p.dim[1], fk1, probe_load<D1>(p.dim[1], fk1, st1), st1, v1);
+  }
+  if (m0 == 0 || m1 == 0) return;
   const int64_t k0 = (R::k0 == kKF8 || R::k0 == kKF32) ? f0 : spec_key<R::k0>(p, 0, r, v0, v1);
   const int64_t k1 = (R::k1 == kKF8 || R::k1 == kKF32) ? f1 : spec_key<R::k1>(p, 1, r, v0, v1);
   spec_update(p, spec_pack<S>(p.g.kp, k0, k1), v, lg, gt, acode);
-  return false;
 }
 
 // direct_row for spec S.
@@ -1038,8 +1045,8 @@ __device__ __forceinline__ void spec_load4(const int32_t* c, int64_t r0, int64_t
   }
 }
 
-// Processes the top `take` (<= 64) rows of the wave's queue under spec S;
-// rows whose probes continue are written back. Returns the new queue length.
+// Processes the top `take` (<= 64) rows of the wave's queue under spec S,
+// one per lane. Returns the new queue length.
 template <int D0, int D1, int S>
 __device__ __forceinline__ uint32_t spec_drain(const PipelineParams& p, unsigned char* wq,
                                                uint32_t queued, uint32_t take, int lane,
@@ -1049,37 +1056,16 @@ __device__ __forceinline__ uint32_t spec_drain(const PipelineParams& p, unsigned
   const bool mine = static_cast<uint32_t>(lane) < take;
   int64_t r = 0;
   int32_t fk0 = 0, fk1 = 0;
-  uint32_t st0 = 0, st1 = 0;
   if (mine) {
     const uint32_t i = base + lane;
     r = static_cast<uint32_t>(qget<D0, D1, kQRow>(wq, i));
-    if constexpr (D0 != kNone) {
-      fk0 = static_cast<int32_t>(qget<D0, D1, kQFk0>(wq, i));
-      st0 = static_cast<uint32_t>(qget<D0, D1, kQSt0>(wq, i));
-    }
-    if constexpr (D1 != kNone) {
-      fk1 = static_cast<int32_t>(qget<D0, D1, kQFk1>(wq, i));
-      st1 = static_cast<uint32_t>(qget<D0, D1, kQSt1>(wq, i));
-    }
+    if constexpr (D0 != kNone) fk0 = static_cast<int32_t>(qget<D0, D1, kQFk0>(wq, i));
+    if constexpr (D1 != kNone) fk1 = static_cast<int32_t>(qget<D0, D1, kQFk1>(wq, i));
   }
   __builtin_amdgcn_wave_barrier();
-  bool again = false;
-  if (mine) again = spec_row<D0, D1, S>(p, r, fk0, fk1, st0, st1, lg, gt, acode);
-  const uint64_t b = ballot(again);
-  if (again) {
-    const uint32_t at = base + rank_below(b);
-    qput<D0, D1, kQRow>(wq, at, r);
-    if constexpr (D0 != kNone) {
-      qput<D0, D1, kQFk0>(wq, at, fk0);
-      qput<D0, D1, kQSt0>(wq, at, st0);
-    }
-    if constexpr (D1 != kNone) {
-      qput<D0, D1, kQFk1>(wq, at, fk1);
-      qput<D0, D1, kQSt1>(wq, at, st1);
-    }
-  }
+  if (mine) spec_row<D0, D1, S>(p, r, fk0, fk1, lg, gt, acode);
   __builtin_amdgcn_wave_barrier();
-  return base + popc64(b);
+  return base;
 }
 
 // One of four register values by a wave-uniform index (no indexed
@@ -1155,14 +1141,8 @@ __device__ __forceinline__ void spec_tiles(const PipelineParams& p, int64_t tile
     if (pass) {
       const uint32_t at = queued + rank_below(b);
       qput<D0, D1, kQRow>(wq, at, r0 + e);
-      if constexpr (D0 != kNone) {
-        qput<D0, D1, kQFk0>(wq, at, pick4(fk0, e));
-        qput<D0, D1, kQSt0>(wq, at, 0);
-      }
-      if constexpr (D1 != kNone) {
-        qput<D0, D1, kQFk1>(wq, at, pick4(fk1, e));
-        qput<D0, D1, kQSt1>(wq, at, 0);
-      }
+      if constexpr (D0 != kNone) qput<D0, D1, kQFk0>(wq, at, pick4(fk0, e));
+      if constexpr (D1 != kNone) qput<D0, D1, kQFk1>(wq, at, pick4(fk1, e));
     }
     queued += popc64(b);
     ++e;
