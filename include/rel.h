@@ -178,7 +178,7 @@ rel_status rel_filter(const rel_column* cols, int ncols, const rel_pred* preds, 
  * the library holds per GPU (1 MiB, kept until the process ends); the first
  * call on a device looks up its address, later calls allocate nothing
  * (no hipMalloc, no hipFree, no allocating library routine).
- *   n (the columns' len) at most 1,073,479,680 rows.
+ *   n (the columns' len) at most 2,146,959,360 rows.
  * Every call on a GPU shares that GPU's array, and each call clears the part
  * it uses first: calls that may overlap in time on one GPU (other streams,
  * other threads) race and must be serialised by the caller.

@@ -1,7 +1,7 @@
 // Selection with ordered stream compaction, one pass over the columns.
 //
-// A workgroup of 512 threads takes one tile of 8192 rows. Thread t of the
-// tile reads rows (j * 2048 + 4 t .. + 3) for j = 0..3, so every column read
+// A workgroup of 512 threads takes one tile of 16384 rows. Thread t of the
+// tile reads rows (j * 2048 + 4 t .. + 3) for j = 0..7, so every column read
 // is a coalesced 16-byte-per-lane vector load. Each passing row sets one bit;
 // per chunk a wave64 ballot per row position gives the wave's count (popcount)
 // and each lane's rank (mbcnt), which places every passing row id at its
@@ -11,7 +11,7 @@
 // 64-bit word with agent-scope atomics, so the eight XCD L2 caches never hold
 // a stale state. Tiles are numbered by an atomic ticket in launch order, so
 // every tile that a look-back waits on has already started and will publish.
-// The ids of a tile are staged in LDS and written with coalesced stores.
+// Each lane then writes its passing rows' ids straight to their positions.
 
 #include <mutex>
 
@@ -50,6 +50,9 @@ hipError_t filter_scratch(void** ptr) {
 
 namespace {
 
+typedef int32_t v4i32 __attribute__((ext_vector_type(4)));
+typedef int64_t v2i64 __attribute__((ext_vector_type(2)));
+
 constexpr uint64_t kFlagAgg = 1ULL << 62;
 constexpr uint64_t kFlagPrefix = 2ULL << 62;
 constexpr uint64_t kValueMask = (1ULL << 62) - 1;
@@ -79,7 +82,14 @@ __device__ __forceinline__ uint32_t eval_chunk(const FilterParams& p, int64_t r0
 
 // A whole tile of plain columns: per term, the loads of the thread's four
 // chunks are issued together (the type and alignment tests are uniform), and
-// only then compared.
+// only then compared. Each column byte is read once: non-temporal loads keep
+// the stream from displacing reused lines in the caches.
+__device__ __forceinline__ uint32_t holds4(const FilterTerm& t, int64_t a, int64_t b, int64_t c,
+                                           int64_t d) {
+  return (term_holds(t.op, a, t.lo, t.hi) ? 1u : 0u) | (term_holds(t.op, b, t.lo, t.hi) ? 2u : 0u) |
+         (term_holds(t.op, c, t.lo, t.hi) ? 4u : 0u) | (term_holds(t.op, d, t.lo, t.hi) ? 8u : 0u);
+}
+
 __device__ __forceinline__ void eval_whole(const FilterParams& p, int64_t r0,
                                            uint32_t bits[kFilterChunks]) {
   constexpr int64_t kChunk = kFilterThreads * 4;
@@ -87,50 +97,45 @@ __device__ __forceinline__ void eval_whole(const FilterParams& p, int64_t r0,
   for (int j = 0; j < kFilterChunks; ++j) bits[j] = 0xFu;
   for (int t = 0; t < p.nterms; ++t) {
     const FilterTerm& term = p.term[t];
-    int64_t v[kFilterChunks][4];
     if (term.vec && term.type == kI32) {
       const int32_t* d = static_cast<const int32_t*>(term.data) + r0;
-      int4 x[kFilterChunks];
+      v4i32 x[kFilterChunks];
 #pragma unroll
-      for (int j = 0; j < kFilterChunks; ++j) x[j] = *reinterpret_cast<const int4*>(d + j * kChunk);
+      for (int j = 0; j < kFilterChunks; ++j)
+        x[j] = __builtin_nontemporal_load(reinterpret_cast<const v4i32*>(d + j * kChunk));
 #pragma unroll
-      for (int j = 0; j < kFilterChunks; ++j) {
-        v[j][0] = x[j].x; v[j][1] = x[j].y; v[j][2] = x[j].z; v[j][3] = x[j].w;
-      }
+      for (int j = 0; j < kFilterChunks; ++j) bits[j] &= holds4(term, x[j].x, x[j].y, x[j].z, x[j].w);
     } else if (term.vec && term.type == kI64) {
+      // four chunks at a time (eight would hold 64 registers of loaded data)
       const int64_t* d = static_cast<const int64_t*>(term.data) + r0;
-      longlong2 a[kFilterChunks], b[kFilterChunks];
 #pragma unroll
-      for (int j = 0; j < kFilterChunks; ++j) {
-        a[j] = reinterpret_cast<const longlong2*>(d + j * kChunk)[0];
-        b[j] = reinterpret_cast<const longlong2*>(d + j * kChunk)[1];
-      }
+      for (int g = 0; g < kFilterChunks; g += 4) {
+        v2i64 a[4], b[4];
 #pragma unroll
-      for (int j = 0; j < kFilterChunks; ++j) {
-        v[j][0] = a[j].x; v[j][1] = a[j].y; v[j][2] = b[j].x; v[j][3] = b[j].y;
+        for (int j = 0; j < 4; ++j) {
+          a[j] = __builtin_nontemporal_load(reinterpret_cast<const v2i64*>(d + (g + j) * kChunk));
+          b[j] = __builtin_nontemporal_load(reinterpret_cast<const v2i64*>(d + (g + j) * kChunk) + 1);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bits[g + j] &= holds4(term, a[j].x, a[j].y, b[j].x, b[j].y);
       }
     } else if (term.vec) {
       const int8_t* d = static_cast<const int8_t*>(term.data) + r0;
       int32_t w[kFilterChunks];
 #pragma unroll
-      for (int j = 0; j < kFilterChunks; ++j) w[j] = *reinterpret_cast<const int32_t*>(d + j * kChunk);
-#pragma unroll
-      for (int j = 0; j < kFilterChunks; ++j) {
-        v[j][0] = static_cast<int8_t>(w[j]); v[j][1] = static_cast<int8_t>(w[j] >> 8);
-        v[j][2] = static_cast<int8_t>(w[j] >> 16); v[j][3] = static_cast<int8_t>(w[j] >> 24);
-      }
-    } else {
+      for (int j = 0; j < kFilterChunks; ++j)
+        w[j] = __builtin_nontemporal_load(reinterpret_cast<const int32_t*>(d + j * kChunk));
 #pragma unroll
       for (int j = 0; j < kFilterChunks; ++j)
+        bits[j] &= holds4(term, static_cast<int8_t>(w[j]), static_cast<int8_t>(w[j] >> 8),
+                          static_cast<int8_t>(w[j] >> 16), static_cast<int8_t>(w[j] >> 24));
+    } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[j][e] = load_elem(term.data, term.type, r0 + j * kChunk + e);
-    }
-#pragma unroll
-    for (int j = 0; j < kFilterChunks; ++j) {
-      uint32_t m = 0;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) m |= term_holds(term.op, v[j][e], term.lo, term.hi) ? (1u << e) : 0u;
-      bits[j] &= m;
+      for (int j = 0; j < kFilterChunks; ++j) {
+        const int64_t q = r0 + j * kChunk;
+        bits[j] &= holds4(term, load_elem(term.data, term.type, q), load_elem(term.data, term.type, q + 1),
+                          load_elem(term.data, term.type, q + 2), load_elem(term.data, term.type, q + 3));
+      }
     }
   }
 }
@@ -168,8 +173,10 @@ __device__ __forceinline__ uint32_t bloom_chunk(const FilterParams& p, int64_t r
   return bits;
 }
 
+// kPlain: no selection vector and no Bloom filter (its own register
+// allocation, without the registers those paths need).
+template <bool kPlain>
 __global__ void __launch_bounds__(kFilterThreads) filter_kernel(FilterParams p) {
-  __shared__ uint32_t s_rows[kFilterTile];
   __shared__ uint32_t s_wave_total[kFilterChunks][kFilterThreads / kWave];
   __shared__ int64_t s_tile;
   __shared__ uint64_t s_excl;
@@ -184,14 +191,14 @@ __global__ void __launch_bounds__(kFilterThreads) filter_kernel(FilterParams p) 
   const int64_t base = tile * kFilterTile;
 
   uint32_t bits[kFilterChunks];
-  if (!p.idx && base + kFilterTile <= p.n) {
+  if ((kPlain || !p.idx) && base + kFilterTile <= p.n) {
     eval_whole(p, base + tid * 4, bits);
   } else {
 #pragma unroll
     for (int j = 0; j < kFilterChunks; ++j)
       bits[j] = eval_chunk(p, base + j * (kFilterThreads * 4) + tid * 4);
   }
-  if (p.bloom.words) {
+  if (!kPlain && p.bloom.words) {
 #pragma unroll
     for (int j = 0; j < kFilterChunks; ++j)
       bits[j] = bloom_chunk(p, base + j * (kFilterThreads * 4) + tid * 4, bits[j]);
@@ -253,25 +260,23 @@ __global__ void __launch_bounds__(kFilterThreads) filter_kernel(FilterParams p) 
     if (lane == 0) s_excl = excl;
   }
 
-  // Stage row ids in LDS at their tile positions.
+  __syncthreads();
+  // Each lane writes its passing rows' ids at their output positions; a
+  // wave's stores of one row position land in a few consecutive lines.
+  const uint64_t excl = s_excl;
 #pragma unroll
   for (int j = 0; j < kFilterChunks; ++j) {
     if (bits[j] == 0) continue;
     const int64_t r0 = base + j * (kFilterThreads * 4) + tid * 4;
-    uint32_t off = chunk_base[j] + lane_prefix[j];
+    uint64_t pos = excl + chunk_base[j] + lane_prefix[j];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       if ((bits[j] >> e) & 1u) {
-        s_rows[off++] = p.idx ? p.idx[r0 + e] : static_cast<uint32_t>(r0 + e);
+        if (static_cast<int64_t>(pos) < p.cap)
+          p.out[pos] = (!kPlain && p.idx) ? p.idx[r0 + e] : static_cast<uint32_t>(r0 + e);
+        ++pos;
       }
     }
-  }
-  __syncthreads();
-
-  const uint64_t excl = s_excl;
-  for (uint32_t i = tid; i < total; i += kFilterThreads) {
-    uint64_t pos = excl + i;
-    if (static_cast<int64_t>(pos) < p.cap) p.out[pos] = s_rows[i];
   }
   if (tile == p.ntiles - 1 && tid == 0) *p.d_count = static_cast<long long>(excl + total);
 }
@@ -280,8 +285,12 @@ __global__ void __launch_bounds__(kFilterThreads) filter_kernel(FilterParams p) 
 
 void launch_filter(const FilterParams& p, hipStream_t s) {
   ProfileScope ps(kKFilter, s);
-  hipLaunchKernelGGL(filter_kernel, dim3(static_cast<unsigned>(p.ntiles)), dim3(kFilterThreads), 0,
-                     s, p);
+  if (!p.idx && !p.bloom.words)
+    hipLaunchKernelGGL(filter_kernel<true>, dim3(static_cast<unsigned>(p.ntiles)), dim3(kFilterThreads),
+                       0, s, p);
+  else
+    hipLaunchKernelGGL(filter_kernel<false>, dim3(static_cast<unsigned>(p.ntiles)),
+                       dim3(kFilterThreads), 0, s, p);
 }
 
 }  // namespace rel

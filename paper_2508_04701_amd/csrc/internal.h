@@ -48,7 +48,7 @@ hipError_t launch_stream_read(const void* data, uint64_t bytes, unsigned long lo
 // --------------------------------------------------------------- filter
 
 constexpr int kFilterThreads = 512;
-constexpr int kFilterChunks = 4;                               // chunks of 4 rows per thread
+constexpr int kFilterChunks = 8;                               // chunks of 4 rows per thread
 constexpr int kFilterTile = kFilterThreads * 4 * kFilterChunks;  // rows per tile
 
 struct FilterTerm {
@@ -81,8 +81,8 @@ struct FilterParams {
 void launch_filter(const FilterParams& p, hipStream_t s);
 
 // Static scratch of the allocation-free filter: the ticket word's 256-byte
-// block plus one tile-state word per 8192-row tile. 1 MiB holds the states
-// of 131040 tiles, i.e. up to 1,073,479,680 rows.
+// block plus one tile-state word per 16384-row tile. 1 MiB holds the states
+// of 131040 tiles, i.e. up to 2,146,959,360 rows.
 constexpr size_t kFilterScratchBytes = size_t(1) << 20;
 constexpr int64_t kFilterNoallocMaxRows =
     static_cast<int64_t>((kFilterScratchBytes - 256) / 8) * kFilterTile;

@@ -72,7 +72,7 @@ def test_filter_validation():
 def test_workspace_sizes():
     L = rel.lib()
     assert L.rel_filter_ws(0) >= 256 + 8
-    assert L.rel_filter_ws(600_000_000) >= 8 * (600_000_000 // 8192)  # a state word per tile
+    assert L.rel_filter_ws(600_000_000) >= 8 * (600_000_000 // 16384)  # a state word per tile
     small = L.rel_hash_join_ws(2, 10_000, None)
     big = L.rel_hash_join_ws(2, 1_000_000, None)
     assert 0 < small < big
@@ -261,7 +261,7 @@ def test_filter_noalloc_validation():
 
     assert call(10, d_count=0) == rel.REL_EINVAL
     # beyond the static scratch's 131040 tile states: rejected before any HIP call
-    assert call(1_073_479_680 + 1) == rel.REL_ECAPACITY
+    assert call(2_146_959_360 + 1) == rel.REL_ECAPACITY
     assert b"static scratch" in L.rel_last_error()
 
 
