@@ -791,7 +791,8 @@ def bench_serve(args, torch, datagen, rel) -> dict:
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
 
     modes = {"one_at_a_time": dict(max_slots=1, max_batch=1, lanes=1),
-             "continuous": dict(max_slots=64, max_batch=16, lanes=2)}
+             "continuous": dict(max_slots=64, max_batch=16, lanes=args.serve_lanes,
+                                open_lane_at=args.serve_open_at)}
 
     def run(mode, arrivals, count):
         srv = serve.Server(arena_bytes, arena_ptr=arena.data_ptr(), **modes[mode])
@@ -869,6 +870,10 @@ def main() -> int:
     ap.add_argument("--serve-pool", type=int, default=96)
     ap.add_argument("--serve-arena-gb", type=int, default=64)
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[0.5, 0.8, 1.2, 2.0])
+    ap.add_argument("--serve-lanes", type=int, default=2,
+                    help="continuous mode: batches in flight at once")
+    ap.add_argument("--serve-open-at", type=int, default=1,
+                    help="continuous mode: backlog that opens a further lane while one is busy")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")

@@ -522,8 +522,9 @@ rel_status rel_autotune_lookup(const char* cache_path, const rel_pipeline_desc* 
  * queries are submitted as fused plans over device columns that stay
  * allocated, wait in a FIFO, and are admitted as lanes, query slots and
  * workspace bytes free up. Whenever a lane is free, a scheduler thread packs
- * the oldest waiting queries of one shape (as in rel_pipeline_batch) into a
- * batch, takes its workspace from the arena (first fit) and launches it, so
+ * the oldest waiting queries of one shape (as in rel_pipeline_batch) and one
+ * max_groups class (up to 4096, up to 65536, more) into a batch, takes its
+ * workspace from the arena (first fit) and launches it, so
  * that queries arriving while others run are batched and overlap them on the
  * device. A query completes once its batch has finished and its results are
  * in the host buffers given at submission; then its slot, lane and bytes are

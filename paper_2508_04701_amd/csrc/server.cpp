@@ -77,14 +77,19 @@ struct PlanCopy {
   }
 };
 
-// Plans batch together when they share the kernel variant: dim count, and
-// per dim the key type and payload presence.
+// Plans batch together when they share the kernel variant (dim count, and
+// per dim the key type and payload presence) and a group-count class (up to
+// 4096, up to 65536, more): a batch lasts as long as its slowest instance,
+// and a plan whose groups overflow the LDS tables runs several times longer
+// than one whose groups fit, so mixing them would hold the fast plans back
+// and slow the large one by the others' work.
 uint32_t shape_of(const rel_pipeline_desc& d) {
   uint32_t s = static_cast<uint32_t>(d.n_dims);
   for (int k = 0; k < d.n_dims; ++k)
     s |= (static_cast<uint32_t>(d.dims[k].key.type) << (4 + 8 * k)) |
          ((d.dims[k].has_payload ? 1u : 0u) << (7 + 8 * k));
-  return s;
+  const uint32_t cls = d.max_groups > 65536 ? 2u : (d.max_groups > 4096 ? 1u : 0u);
+  return s | (cls << 24);
 }
 
 struct Query {

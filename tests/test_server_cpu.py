@@ -160,12 +160,12 @@ def star(seed, n=3000):
     return fk, date, price, dim_key, region
 
 
-def query(data, lo, w, payload=True):
+def query(data, lo, w, payload=True, max_groups=64):
     fk, date, price, dim_key, region = data
     dims = [dict(fk=0, key=dim_key, payload=region if payload else None)]
     keys = [("dim", 0)] if payload else []
     return HostPlan([fk, date, price], [(1, "range", lo, lo + w)], dims, keys,
-                    [("sum", 2), ("count", None)], 64)
+                    [("sum", 2), ("count", None)], max_groups)
 
 
 def make_server(ex, arena_bytes=1 << 30, max_slots=64, max_batch=8, lanes=2, open_lane_at=0):
@@ -278,6 +278,27 @@ def test_shapes_are_never_mixed_in_a_batch():
     assert len(got) == 24
     for _, _, b, _, _ in ex.launches:
         assert len({p.desc.dims[0].has_payload for p in b}) == 1
+    check_results(plans)
+
+
+def test_group_classes_are_never_mixed_in_a_batch():
+    """Plans of one kernel shape but with max_groups in different classes
+    (up to 4096, up to 65536, more) go to different batches."""
+    data = star(4)
+    classes = [64, 5000, 100_000]
+    plans = [query(data, 50 * i, 400, max_groups=classes[i % 3]) for i in range(18)]
+    ex = OracleExecutor(plans, lanes=1, delay=0.003)
+    srv = make_server(ex, max_batch=6, lanes=1)
+    for p in plans:
+        srv.submit(p)
+    got = wait_all(srv, len(plans))
+    srv.close()
+    assert not ex.errors, ex.errors
+    assert len(got) == 18
+    cls = lambda g: 0 if g <= 4096 else (1 if g <= 65536 else 2)
+    assert any(len(b) > 1 for _, _, b, _, _ in ex.launches), "some batching happened"
+    for _, _, b, _, _ in ex.launches:
+        assert len({cls(p.desc.max_groups) for p in b}) == 1
     check_results(plans)
 
 
