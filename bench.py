@@ -514,9 +514,9 @@ def bench_ops(args, torch, datagen, rel) -> dict:
 
 
 def bench_bloom(args, torch, datagen, rel, kernel_ms, line) -> dict:
-    """Predicate transfer on a join with few partners: 10M unique int64 build
-    keys, 400M probe keys of which 5% are build keys and the rest draws from
-    the whole int64 range. The hash join with and without the Bloom filter
+    """Predicate transfer on a join with few partners: --bloom-build unique
+    int64 build keys (1M by default), --bloom-probe probe keys (400M) of which
+    5% are build keys and the rest draws from the whole int64 range. The hash join with and without the Bloom filter
     in front of its table walk, and the filter alone (rel_bloom_filter: the
     probe rows that may have a partner)."""
     seed = datagen.SEED0 + 6
