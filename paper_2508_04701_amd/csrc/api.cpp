@@ -62,6 +62,26 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Workspace of rel_filter (the bitmap path): per tile of kFilterTile rows its
+// selection bitmap (kFilterTile / 32 words) and its count (padded to whole
+// groups of kFilterGroupTiles), and per group its offset.
+struct FilterLayout {
+  int64_t tiles = 1;
+  size_t bitmap_off = 0, count_off = 0, offset_off = 0, end = 0;
+};
+
+FilterLayout filter_layout(int64_t n) {
+  FilterLayout L;
+  L.tiles = n > 0 ? (n + kFilterTile - 1) / kFilterTile : 1;
+  const size_t t = static_cast<size_t>(L.tiles);
+  const size_t groups = (t + kFilterGroupTiles - 1) / kFilterGroupTiles;
+  L.bitmap_off = 0;
+  L.count_off = align_up(t * (kFilterTile / 32) * 4);
+  L.offset_off = L.count_off + align_up(groups * kFilterGroupTiles * 4);
+  L.end = L.offset_off + align_up(groups * 8);
+  return L;
+}
+
 uint64_t next_pow2(uint64_t v) {
   uint64_t p = 1;
   while (p < v) p <<= 1;
@@ -1233,15 +1253,28 @@ rel_status rel_stream_read(const void* data, int64_t bytes, uint64_t* d_xor, voi
 
 // ------------------------------------------------------------------ filter
 
-size_t rel_filter_ws(int64_t n) {
-  int64_t tiles = n > 0 ? (n + kFilterTile - 1) / kFilterTile : 1;
-  return align_up(kAlign + static_cast<size_t>(tiles) * 8);
-}
+size_t rel_filter_ws(int64_t n) { return rel::filter_layout(n).end; }
 
 }  // extern "C"
 
 namespace rel {
 namespace {
+
+// Tile states of the single-pass (look-back) filter: the ticket's block and
+// one word per tile (the allocation-free filter's static scratch).
+size_t filter_state_bytes(int64_t n) {
+  const int64_t tiles = n > 0 ? (n + kFilterTile - 1) / kFilterTile : 1;
+  return align_up(kAlign + static_cast<size_t>(tiles) * 8);
+}
+
+// Points p at the bitmap path's workspace (filter_layout(p.n) bytes at w).
+void filter_bind_marked(FilterParams& p, unsigned char* w) {
+  const FilterLayout L = filter_layout(p.n);
+  p.ntiles = L.tiles;
+  p.bitmap = reinterpret_cast<uint32_t*>(w + L.bitmap_off);
+  p.tile_count = reinterpret_cast<uint32_t*>(w + L.count_off);
+  p.group_offset = reinterpret_cast<uint64_t*>(w + L.offset_off);
+}
 
 rel_status filter_check(const rel_column* cols, int ncols, const rel_pred* preds, int npreds,
                         rel_rowid* out, int64_t out_cap, int64_t* d_count) {
@@ -1266,10 +1299,12 @@ rel_status filter_check(const rel_column* cols, int ncols, const rel_pred* preds
   return REL_OK;
 }
 
-// Enqueues the filter with its tile states at w (rel_filter_ws(n) bytes).
+// Enqueues the filter: with `marked`, the bitmap path over a workspace of
+// rel_filter_ws(n) bytes at w; else the single pass with its tile states at
+// w (filter_state_bytes(n) bytes).
 rel_status filter_enqueue(const rel_column* cols, const rel_pred* preds, int npreds,
                           rel_rowid* out, int64_t out_cap, int64_t* d_count, unsigned char* w,
-                          hipStream_t s) {
+                          bool marked, hipStream_t s) {
   const int64_t n = cols[0].len;
   FilterParams p;
   std::memset(&p, 0, sizeof p);
@@ -1288,6 +1323,11 @@ rel_status filter_enqueue(const rel_column* cols, const rel_pred* preds, int npr
   p.out = out;
   p.cap = out_cap;
   p.d_count = reinterpret_cast<long long*>(d_count);
+  if (marked) {
+    filter_bind_marked(p, w);
+    launch_filter_marked(p, s);
+    return after_launch(s, "filter");
+  }
   p.ticket = reinterpret_cast<uint32_t*>(w);
   p.tile_state = reinterpret_cast<uint64_t*>(w + kAlign);
   p.ntiles = n > 0 ? (n + kFilterTile - 1) / kFilterTile : 1;
@@ -1310,7 +1350,7 @@ rel_status rel_filter(const rel_column* cols, int ncols, const rel_pred* preds, 
   st = check_ws(ws, ws_bytes, rel_filter_ws(cols[0].len));
   if (st) return st;
   return filter_enqueue(cols, preds, npreds, out, out_cap, d_count,
-                        static_cast<unsigned char*>(ws), static_cast<hipStream_t>(stream));
+                        static_cast<unsigned char*>(ws), true, static_cast<hipStream_t>(stream));
 }
 
 rel_status rel_filter_noalloc(const rel_column* cols, int ncols, const rel_pred* preds,
@@ -1319,7 +1359,7 @@ rel_status rel_filter_noalloc(const rel_column* cols, int ncols, const rel_pred*
   g_error.clear();
   rel_status st = filter_check(cols, ncols, preds, npreds, out, out_cap, d_count);
   if (st) return st;
-  const size_t need = rel_filter_ws(cols[0].len);
+  const size_t need = filter_state_bytes(cols[0].len);
   if (need > kFilterScratchBytes)
     return fail(REL_ECAPACITY,
                 "filter_noalloc: %lld rows need %zu bytes of tile state, the static scratch "
@@ -1330,7 +1370,8 @@ rel_status rel_filter_noalloc(const rel_column* cols, int ncols, const rel_pred*
   hipError_t e = filter_scratch(&scratch);
   if (e != hipSuccess) return fail(REL_EDEVICE, "filter_noalloc: %s", hipGetErrorString(e));
   return filter_enqueue(cols, preds, npreds, out, out_cap, d_count,
-                        static_cast<unsigned char*>(scratch), static_cast<hipStream_t>(stream));
+                        static_cast<unsigned char*>(scratch), false,
+                        static_cast<hipStream_t>(stream));
 }
 
 // ---------------------------------------------------------- Bloom filters
@@ -1405,16 +1446,13 @@ rel_status rel_bloom_filter(const rel_column* probe_keys, const void* filter, si
   p.out = out;
   p.cap = out_cap;
   p.d_count = reinterpret_cast<long long*>(d_count);
-  p.ticket = reinterpret_cast<uint32_t*>(w);
-  p.tile_state = reinterpret_cast<uint64_t*>(w + kAlign);
-  p.ntiles = n > 0 ? (n + kFilterTile - 1) / kFilterTile : 1;
   p.bloom.words = static_cast<const uint32_t*>(filter);
   p.bloom.bmask = filter_bytes / 32 - 1;
   p.bloom_keys = probe_keys->data;
   p.bloom_type = probe_keys->type;
   p.bloom_vec = (reinterpret_cast<uintptr_t>(probe_keys->data) % 16) == 0;
-  launch_fill64(reinterpret_cast<uint64_t*>(w), (kAlign + p.ntiles * 8) / 8, 0, s);
-  launch_filter(p, s);
+  filter_bind_marked(p, w);
+  launch_filter_marked(p, s);
   return after_launch(s, "bloom filter");
 }
 

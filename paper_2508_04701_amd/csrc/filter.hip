@@ -14,6 +14,7 @@
 // Each lane then writes its passing rows' ids straight to their positions.
 
 #include <mutex>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -137,6 +138,25 @@ __device__ __forceinline__ void eval_whole(const FilterParams& p, int64_t r0,
                           load_elem(term.data, term.type, q + 2), load_elem(term.data, term.type, q + 3));
       }
     }
+  }
+}
+
+// eval_whole for plans whose terms all read 16-byte aligned int32 columns:
+// the one load shape, so the kernel that uses it keeps few registers.
+__device__ __forceinline__ void eval_whole_i32(const FilterParams& p, int64_t r0,
+                                               uint32_t bits[kFilterChunks]) {
+  constexpr int64_t kChunk = kFilterThreads * 4;
+#pragma unroll
+  for (int j = 0; j < kFilterChunks; ++j) bits[j] = 0xFu;
+  for (int t = 0; t < p.nterms; ++t) {
+    const FilterTerm& term = p.term[t];
+    const int32_t* d = static_cast<const int32_t*>(term.data) + r0;
+    v4i32 x[kFilterChunks];
+#pragma unroll
+    for (int j = 0; j < kFilterChunks; ++j)
+      x[j] = __builtin_nontemporal_load(reinterpret_cast<const v4i32*>(d + j * kChunk));
+#pragma unroll
+    for (int j = 0; j < kFilterChunks; ++j) bits[j] &= holds4(term, x[j].x, x[j].y, x[j].z, x[j].w);
   }
 }
 
@@ -281,7 +301,197 @@ __global__ void __launch_bounds__(kFilterThreads) filter_kernel(FilterParams p) 
   if (tile == p.ntiles - 1 && tid == 0) *p.d_count = static_cast<long long>(excl + total);
 }
 
+// ------------------------------------------------ selection bitmap path
+//
+// rel_filter with a workspace: three passes instead of one with a look-back
+// chain. (1) Mark: each workgroup evaluates one tile of rows exactly as above
+// and writes the tile's selection bitmap (bit r of word w = row 32 w + r of
+// the tile) and its count; no ticket, no look-back, so workgroups never wait
+// on each other and the pass streams the columns. (2) Scan: one workgroup
+// turns the tile counts into exclusive offsets and the total. (3) Expand:
+// each workgroup reads its tile's bitmap (2 KB instead of the columns),
+// places the set bits' row ids in LDS at their ranks and writes them out with
+// coalesced stores.
+
+constexpr int kTileWords = kFilterTile / 32;  // bitmap words per tile
+
+// kMode 2: every term an aligned int32 column, no selection vector, no Bloom
+// term; 1: no selection vector and no Bloom term; 0: anything.
+template <int kMode>
+__global__ void __launch_bounds__(kFilterThreads) filter_mark_kernel(FilterParams p) {
+  constexpr bool kPlain = kMode > 0;
+  __shared__ uint32_t s_wave[kFilterThreads / kWave];
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int64_t tile = blockIdx.x;
+  const int64_t base = tile * kFilterTile;
+  uint32_t bits[kFilterChunks];
+  if (kMode == 2 && base + kFilterTile <= p.n) {
+    eval_whole_i32(p, base + tid * 4, bits);
+  } else if (kMode != 2 && (kPlain || !p.idx) && base + kFilterTile <= p.n) {
+    eval_whole(p, base + tid * 4, bits);
+  } else {
+#pragma unroll
+    for (int j = 0; j < kFilterChunks; ++j)
+      bits[j] = eval_chunk(p, base + j * (kFilterThreads * 4) + tid * 4);
+  }
+  if (!kPlain && p.bloom.words) {
+#pragma unroll
+    for (int j = 0; j < kFilterChunks; ++j)
+      bits[j] = bloom_chunk(p, base + j * (kFilterThreads * 4) + tid * 4, bits[j]);
+  }
+  // eight lanes' four-row nibbles make one word of 32 consecutive rows
+  uint32_t* words = p.bitmap + tile * kTileWords;
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int j = 0; j < kFilterChunks; ++j) {
+    uint32_t x = bits[j] << (4 * (lane & 7));
+    x |= __shfl_xor(x, 1, kWave);
+    x |= __shfl_xor(x, 2, kWave);
+    x |= __shfl_xor(x, 4, kWave);
+    if ((lane & 7) == 0) words[j * (kFilterThreads * 4 / 32) + tid / 8] = x;
+    cnt += __popc(bits[j]);
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, kWave);
+  if (lane == 0) s_wave[tid / kWave] = cnt;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kFilterThreads / kWave; ++w) t += s_wave[w];
+    p.tile_count[tile] = t;
+  }
+}
+
+constexpr int kScanThreads = 1024;
+
+// Exclusive offsets of groups of kFilterGroupTiles tiles (one workgroup:
+// each step, thread g sums one group's counts with 16-byte loads, and the
+// step's sums are scanned across the block), and the total.
+__global__ void __launch_bounds__(kScanThreads) filter_scan_kernel(FilterParams p) {
+  __shared__ uint64_t s_wave[kScanThreads / kWave];
+  __shared__ uint64_t s_carry;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int64_t nt = p.ntiles;
+  const int64_t ng = (nt + kFilterGroupTiles - 1) / kFilterGroupTiles;
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  for (int64_t g0 = 0; g0 < ng; g0 += kScanThreads) {
+    const int64_t g = g0 + tid;
+    uint64_t sum = 0;
+    if (g < ng) {
+      const int64_t t0 = g * kFilterGroupTiles;
+      if (t0 + kFilterGroupTiles <= nt) {
+        const uint4* c = reinterpret_cast<const uint4*>(p.tile_count + t0);
+        uint4 v[kFilterGroupTiles / 4];
+#pragma unroll
+        for (int i = 0; i < kFilterGroupTiles / 4; ++i) v[i] = c[i];
+#pragma unroll
+        for (int i = 0; i < kFilterGroupTiles / 4; ++i) sum += v[i].x + v[i].y + v[i].z + v[i].w;
+      } else {
+        for (int64_t t = t0; t < nt; ++t) sum += p.tile_count[t];
+      }
+    }
+    uint64_t x = sum;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t lo = __shfl_up(static_cast<uint32_t>(x), off, kWave);
+      const uint32_t hi = __shfl_up(static_cast<uint32_t>(x >> 32), off, kWave);
+      if (lane >= off) x += static_cast<uint64_t>(hi) << 32 | lo;
+    }
+    if (lane == kWave - 1) s_wave[tid / kWave] = x;
+    __syncthreads();
+    uint64_t before = s_carry;
+    uint64_t step = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / kWave; ++w) {
+      if (w < tid / kWave) before += s_wave[w];
+      step += s_wave[w];
+    }
+    if (g < ng) p.group_offset[g] = before + x - sum;
+    __syncthreads();
+    if (tid == 0) s_carry += step;
+    __syncthreads();
+  }
+  if (tid == 0) *p.d_count = static_cast<long long>(s_carry);
+}
+
+// Row ids are staged in LDS as their 16-bit offsets within the tile (32 KB,
+// so four workgroups fit a CU), or whole when a selection vector maps them.
+template <bool kIdx>
+__global__ void __launch_bounds__(kFilterThreads) filter_expand_kernel(FilterParams p) {
+  typedef typename std::conditional<kIdx, uint32_t, uint16_t>::type Staged;
+  __shared__ Staged s_rows[kFilterTile];
+  __shared__ uint32_t s_wave[kFilterThreads / kWave];
+  __shared__ uint64_t s_first;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wave = tid / kWave;
+  const int64_t tile = blockIdx.x;
+  const uint32_t w = p.bitmap[tile * kTileWords + tid];
+  const uint32_t c = __popc(w);
+  uint32_t x = c;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  if (lane == kWave - 1) s_wave[wave] = x;
+  __syncthreads();
+  uint32_t at = x - c;
+  uint32_t total = 0;
+#pragma unroll
+  for (int v = 0; v < kFilterThreads / kWave; ++v) {
+    if (v < wave) at += s_wave[v];
+    total += s_wave[v];
+  }
+  if (wave == 0) {
+    // the tile's offset: its group's, plus the counts of the group's earlier tiles
+    const int64_t t0 = tile / kFilterGroupTiles * kFilterGroupTiles;
+    uint32_t c0 = 0;
+    for (int64_t t = t0 + lane; t < tile; t += kWave) c0 += p.tile_count[t];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) c0 += __shfl_xor(c0, off, kWave);
+    if (lane == 0) s_first = p.group_offset[tile / kFilterGroupTiles] + c0;
+  }
+  const int64_t tile_row0 = tile * kFilterTile;
+  const uint32_t local0 = static_cast<uint32_t>(tid) * 32;
+  for (uint32_t m = w; m != 0; m &= m - 1) {
+    const uint32_t local = local0 + (__ffs(m) - 1);
+    if constexpr (kIdx) s_rows[at++] = p.idx[tile_row0 + local];
+    else s_rows[at++] = static_cast<Staged>(local);
+  }
+  __syncthreads();
+  const uint64_t first = s_first;
+  for (uint32_t i = tid; i < total; i += kFilterThreads) {
+    const uint64_t pos = first + i;
+    if (static_cast<int64_t>(pos) < p.cap)
+      p.out[pos] = kIdx ? static_cast<uint32_t>(s_rows[i])
+                        : static_cast<uint32_t>(tile_row0) + static_cast<uint32_t>(s_rows[i]);
+  }
+}
+
 }  // namespace
+
+void launch_filter_marked(const FilterParams& p, hipStream_t s) {
+  ProfileScope ps(kKFilter, s);
+  const dim3 grid(static_cast<unsigned>(p.ntiles));
+  bool all_i32 = true;
+  for (int t = 0; t < p.nterms; ++t) all_i32 = all_i32 && p.term[t].type == kI32 && p.term[t].vec;
+  if (!p.idx && !p.bloom.words && all_i32)
+    hipLaunchKernelGGL(filter_mark_kernel<2>, grid, dim3(kFilterThreads), 0, s, p);
+  else if (!p.idx && !p.bloom.words)
+    hipLaunchKernelGGL(filter_mark_kernel<1>, grid, dim3(kFilterThreads), 0, s, p);
+  else
+    hipLaunchKernelGGL(filter_mark_kernel<0>, grid, dim3(kFilterThreads), 0, s, p);
+  hipLaunchKernelGGL(filter_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, p);
+  if (p.idx)
+    hipLaunchKernelGGL(filter_expand_kernel<true>, grid, dim3(kFilterThreads), 0, s, p);
+  else
+    hipLaunchKernelGGL(filter_expand_kernel<false>, grid, dim3(kFilterThreads), 0, s, p);
+}
 
 void launch_filter(const FilterParams& p, hipStream_t s) {
   ProfileScope ps(kKFilter, s);

@@ -50,6 +50,7 @@ hipError_t launch_stream_read(const void* data, uint64_t bytes, unsigned long lo
 constexpr int kFilterThreads = 512;
 constexpr int kFilterChunks = 8;                               // chunks of 4 rows per thread
 constexpr int kFilterTile = kFilterThreads * 4 * kFilterChunks;  // rows per tile
+constexpr int kFilterGroupTiles = 64;  // tiles per offset group of the bitmap path
 
 struct FilterTerm {
   const void* data;
@@ -67,9 +68,12 @@ struct FilterParams {
   uint32_t* out;
   int64_t cap;
   long long* d_count;
-  uint64_t* tile_state;  // one word per tile, zeroed
-  uint32_t* ticket;      // zeroed
+  uint64_t* tile_state;  // one word per tile, zeroed (look-back path)
+  uint32_t* ticket;      // zeroed (look-back path)
   int64_t ntiles;
+  uint32_t* bitmap;        // bitmap path: kFilterTile / 32 words per tile
+  uint32_t* tile_count;    // bitmap path: passing rows per tile
+  uint64_t* group_offset;  // bitmap path: exclusive prefix per kFilterGroupTiles tiles
   // Optional semi-join reduction: a row also needs its key (bloom_keys,
   // gathered through idx like the terms' columns) to pass the Bloom filter.
   BloomDesc bloom;       // words == NULL: none
@@ -78,7 +82,12 @@ struct FilterParams {
   int32_t bloom_vec;     // bloom_keys is 16-byte aligned
 };
 
+// Single pass with a decoupled look-back over ticketed tiles (tile_state,
+// ticket): the allocation-free filter's path.
 void launch_filter(const FilterParams& p, hipStream_t s);
+// Selection bitmap, tile counts and offsets (bitmap, tile_count,
+// tile_offset): mark, scan and expand passes.
+void launch_filter_marked(const FilterParams& p, hipStream_t s);
 
 // Static scratch of the allocation-free filter: the ticket word's 256-byte
 // block plus one tile-state word per 16384-row tile. 1 MiB holds the states
