@@ -430,6 +430,15 @@ __global__ void __launch_bounds__(kFilterThreads) filter_expand_kernel(FilterPar
   const int lane = lane_id();
   const int wave = tid / kWave;
   const int64_t tile = blockIdx.x;
+  // the tile's offset: its group's, plus the counts of the group's earlier
+  // tiles (wave 0 reads them together with the bitmap words)
+  const int64_t t0 = tile / kFilterGroupTiles * kFilterGroupTiles;
+  uint32_t c0 = 0;
+  uint64_t g0 = 0;
+  if (wave == 0) {
+    if (t0 + lane < tile) c0 = p.tile_count[t0 + lane];
+    if (lane == 0) g0 = p.group_offset[tile / kFilterGroupTiles];
+  }
   const uint32_t w = p.bitmap[tile * kTileWords + tid];
   const uint32_t c = __popc(w);
   uint32_t x = c;
@@ -439,6 +448,11 @@ __global__ void __launch_bounds__(kFilterThreads) filter_expand_kernel(FilterPar
     if (lane >= off) x += y;
   }
   if (lane == kWave - 1) s_wave[wave] = x;
+  if (wave == 0) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) c0 += __shfl_xor(c0, off, kWave);
+    if (lane == 0) s_first = g0 + c0;
+  }
   __syncthreads();
   uint32_t at = x - c;
   uint32_t total = 0;
@@ -446,15 +460,6 @@ __global__ void __launch_bounds__(kFilterThreads) filter_expand_kernel(FilterPar
   for (int v = 0; v < kFilterThreads / kWave; ++v) {
     if (v < wave) at += s_wave[v];
     total += s_wave[v];
-  }
-  if (wave == 0) {
-    // the tile's offset: its group's, plus the counts of the group's earlier tiles
-    const int64_t t0 = tile / kFilterGroupTiles * kFilterGroupTiles;
-    uint32_t c0 = 0;
-    for (int64_t t = t0 + lane; t < tile; t += kWave) c0 += p.tile_count[t];
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) c0 += __shfl_xor(c0, off, kWave);
-    if (lane == 0) s_first = p.group_offset[tile / kFilterGroupTiles] + c0;
   }
   const int64_t tile_row0 = tile * kFilterTile;
   const uint32_t local0 = static_cast<uint32_t>(tid) * 32;
