@@ -1585,12 +1585,12 @@ namespace {
 struct StrLayout {
   uint64_t cap = 0, dict_cap = 0;
   int words = 0;
-  size_t slots_off = 0, overflow_off = 0, dict_off = 0, canon_off = 0, end = 0;
+  size_t slots_off = 0, overflow_off = 0, dict_off = 0, canon_off = 0, slot_of_off = 0, end = 0;
 };
 
 // Group table of 2 x max_groups slots (at least 64); with a dictionary of
-// n_dict entries, its string table (2 x n_dict claim words) and the
-// canonical id of every entry.
+// n_dict entries, its string table (2 x n_dict claim words), the canonical
+// id of every entry and the group slot of every entry.
 StrLayout str_layout(int64_t max_groups, int64_t n_dict, int nacc) {
   StrLayout L;
   uint64_t want = static_cast<uint64_t>(max_groups > 0 ? max_groups : 1) * 2;
@@ -1604,7 +1604,8 @@ StrLayout str_layout(int64_t max_groups, int64_t n_dict, int nacc) {
     const uint64_t dw = static_cast<uint64_t>(n_dict) * 2;
     L.dict_cap = next_pow2(dw < 64 ? 64 : dw);
     L.canon_off = align_up(L.dict_off + L.dict_cap * 8);
-    L.end = L.canon_off + static_cast<size_t>(n_dict) * 4;
+    L.slot_of_off = align_up(L.canon_off + static_cast<size_t>(n_dict) * 4);
+    L.end = L.slot_of_off + static_cast<size_t>(n_dict) * 4;
   }
   return L;
 }
@@ -1701,6 +1702,7 @@ rel_status rel_groupby_str(const rel_strings* key, const rel_column* ikey, const
     p.dict_slots = reinterpret_cast<uint64_t*>(w + L.dict_off);
     p.dict_mask = L.dict_cap - 1;
     p.canon = reinterpret_cast<uint32_t*>(w + L.canon_off);
+    p.slot_of = reinterpret_cast<uint32_t*>(w + L.slot_of_off);
   }
   p.lds_slots = str_lds_slots(L.cap, gp.ap.nacc);
   p.naggs = naggs;

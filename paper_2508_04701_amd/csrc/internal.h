@@ -156,6 +156,7 @@ struct StrGroupParams {
   uint64_t* dict_slots;   // claim words of the dictionary's string table
   uint64_t dict_mask;
   uint32_t* canon;        // canonical id of each dictionary entry
+  uint32_t* slot_of;      // group slot of each dictionary entry (no integer key)
   int32_t lds_slots;      // LDS pre-aggregation entries (0 or a power of two)
   const void* ikey;      // NULL: no integer key
   int32_t ikey_type;

@@ -20,7 +20,10 @@
 // dictionary gives every entry the id of an entry with equal bytes (the one
 // whose insert claimed the string's slot in a table of the dictionary's
 // strings), so a row's key is then the integer pair (canonical id, integer
-// key) and the per-row work has no string hashing or comparison.
+// key) and the per-row work has no string hashing or comparison. Without an
+// integer key, when the group table has room for every dictionary string,
+// the slots are claimed per canonical entry up front and a row only reads
+// its entry's slot.
 //
 // Pre-aggregation in LDS: each workgroup keeps a small direct-mapped table
 // keyed by global slot index; a row whose slot has (or claims) one of its
@@ -192,6 +195,41 @@ __device__ __forceinline__ int64_t dict_slot(const StrGroupParams& p, int64_t ro
   return -1;
 }
 
+// Without an integer key, and with room in the group table for every
+// string of the dictionary, rows need no probe at all: the group slot of each
+// canonical entry is claimed once up front, every entry learns its string's
+// slot, and a row's slot is one read, slot_of[codes[row]]. Slots of
+// dictionary strings that no row uses keep COUNT 0 and are not groups.
+__global__ void __launch_bounds__(kStrThreads) dict_claim_kernel(StrGroupParams p) {
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * kStrThreads + threadIdx.x; e < p.n_dict;
+       e += static_cast<int64_t>(gridDim.x) * kStrThreads) {
+    const uint32_t c = p.canon[e];
+    if (c != static_cast<uint32_t>(e)) continue;  // not the canonical entry of its string
+    const uint64_t h = hash64(static_cast<uint64_t>(c) << 32 | c);
+    const uint64_t mine = static_cast<uint64_t>(c) << 32;
+    uint64_t slot = h & p.mask;
+    // at least twice as many slots as dictionary entries: every run ends
+    for (uint64_t probes = 0; probes <= p.mask; ++probes) {
+      uint64_t* w = p.slots + slot * p.words;
+      const unsigned long long prev =
+          atomicCAS(reinterpret_cast<unsigned long long*>(w), static_cast<unsigned long long>(kStrEmpty),
+                    static_cast<unsigned long long>(mine));
+      if (prev == kStrEmpty) break;
+      slot = (slot + 1) & p.mask;
+    }
+    p.slot_of[e] = static_cast<uint32_t>(slot);
+  }
+}
+
+// Every other entry takes the slot of its string's canonical entry.
+__global__ void __launch_bounds__(kStrThreads) dict_alias_kernel(StrGroupParams p) {
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * kStrThreads + threadIdx.x; e < p.n_dict;
+       e += static_cast<int64_t>(gridDim.x) * kStrThreads) {
+    const uint32_t c = p.canon[e];
+    if (c != static_cast<uint32_t>(e)) p.slot_of[e] = p.slot_of[c];
+  }
+}
+
 // Adds `cnt` rows with first row `first` and accumulator inputs acc[] to slot s.
 __device__ __forceinline__ void str_update(const StrGroupParams& p, int64_t s, uint64_t cnt,
                                            uint64_t first, const int64_t* acc) {
@@ -238,7 +276,10 @@ struct StrLds {
   uint32_t* first;
 };
 
-template <bool kDict>
+// kMode 0: Arrow strings (hash and compare bytes); 1: dictionary codes,
+// keyed by (canonical id, integer key); 2: dictionary codes with the slots
+// claimed up front (no integer key).
+template <int kMode>
 __global__ void __launch_bounds__(kStrThreads) str_agg_kernel(StrGroupParams p) {
   extern __shared__ uint64_t str_lds[];
   const uint32_t K = static_cast<uint32_t>(p.lds_slots);
@@ -260,8 +301,9 @@ __global__ void __launch_bounds__(kStrThreads) str_agg_kernel(StrGroupParams p) 
   const uint64_t step = static_cast<uint64_t>(gridDim.x) * kStrThreads;
   for (uint64_t row = static_cast<uint64_t>(blockIdx.x) * kStrThreads + threadIdx.x; row < n;
        row += step) {
-    const int64_t slot = kDict ? dict_slot(p, static_cast<int64_t>(row))
-                               : str_slot(p, static_cast<int64_t>(row));
+    const int64_t slot = kMode == 2 ? static_cast<int64_t>(p.slot_of[p.codes[row]])
+                       : kMode == 1 ? dict_slot(p, static_cast<int64_t>(row))
+                                    : str_slot(p, static_cast<int64_t>(row));
     if (slot < 0) continue;
     int64_t acc[kMaxAcc];
 #pragma unroll
@@ -311,7 +353,8 @@ __global__ void __launch_bounds__(kStrThreads) str_final_kernel(StrGroupParams p
        base < slots; base += step) {
     const uint64_t s = base + lane;
     const uint64_t* w = p.slots + (s < slots ? s : 0) * p.words;
-    const bool used = s < slots && w[0] != kStrEmpty;
+    // a slot claimed for a dictionary string that no row uses has COUNT 0
+    const bool used = s < slots && w[0] != kStrEmpty && w[1] != 0;
     const uint64_t m = ballot(used);
     if (m == 0) continue;
     unsigned long long at = 0;
@@ -347,11 +390,11 @@ __global__ void str_overflow_kernel(StrGroupParams p) {
 
 }  // namespace
 
-template <bool kDict>
+template <int kMode>
 void launch_str_agg(const StrGroupParams& p, hipStream_t s) {
   const size_t lds = static_cast<size_t>(p.lds_slots) * (16 + 8 * static_cast<size_t>(p.ap.nacc));
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, str_agg_kernel<kDict>, kStrThreads, lds) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, str_agg_kernel<kMode>, kStrThreads, lds) !=
           hipSuccess ||
       per_cu < 1)
     per_cu = 1;
@@ -359,7 +402,7 @@ void launch_str_agg(const StrGroupParams& p, hipStream_t s) {
   uint64_t blocks = (static_cast<uint64_t>(p.n) + kStrThreads - 1) / kStrThreads;
   const uint64_t limit = static_cast<uint64_t>(device_info().cu_count) * per_cu;
   if (blocks > limit) blocks = limit;
-  hipLaunchKernelGGL(str_agg_kernel<kDict>, dim3(static_cast<unsigned>(blocks)), dim3(kStrThreads), lds,
+  hipLaunchKernelGGL(str_agg_kernel<kMode>, dim3(static_cast<unsigned>(blocks)), dim3(kStrThreads), lds,
                      s, p);
 }
 
@@ -382,9 +425,17 @@ void launch_groupby_str(const StrGroupParams& p, hipStream_t s) {
         if (blocks < 1) blocks = 1;
         hipLaunchKernelGGL(dict_canon_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kStrThreads), 0,
                            s, p);
-        launch_str_agg<true>(p, s);
+        if (!p.ikey && static_cast<uint64_t>(p.n_dict) * 2 <= p.mask + 1) {
+          hipLaunchKernelGGL(dict_claim_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kStrThreads),
+                             0, s, p);
+          hipLaunchKernelGGL(dict_alias_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kStrThreads),
+                             0, s, p);
+          launch_str_agg<2>(p, s);
+        } else {
+          launch_str_agg<1>(p, s);
+        }
       } else {
-        launch_str_agg<false>(p, s);
+        launch_str_agg<0>(p, s);
       }
     }
   }

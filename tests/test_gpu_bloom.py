@@ -42,7 +42,8 @@ def check_filter(build, probe, got, bits_per_key=16):
 
 
 @pytest.mark.parametrize("dtype", [np.int32, np.int64])
-@pytest.mark.parametrize("nb,npr", [(0, 1000), (1, 1), (1000, 8191), (1000, 8193), (50_000, 600_001)])
+@pytest.mark.parametrize("nb,npr", [(0, 1000), (1, 1), (1000, 8191), (1000, 8193), (50_000, 600_001),
+                                    (100_000, 2_100_001)])
 def test_bloom_filter_semi_join_reduction(dtype, nb, npr):
     announce("bloom filter", dtype.__name__, nb, npr)
     r = np.random.default_rng(nb * 7 + npr)

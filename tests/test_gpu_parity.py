@@ -80,6 +80,29 @@ def test_filter_selection_vectors():
         assert np.array_equal(rowids(got), want), name
 
 
+@pytest.mark.parametrize("n", [64 * 16384, 64 * 16384 + 1, 3_000_017])
+def test_filter_across_offset_groups(n):
+    """Sizes at and past one group of 64 tiles (16384 rows each), whose
+    offsets the scan pass sums per group: ids must stay ascending and exact
+    across group boundaries, with a ragged last tile; two int32 terms (the
+    int32-only mark kernel) and an int64 term (the general one)."""
+    announce("filter offset groups", n)
+    r = rng(n % 1000)
+    a = r.integers(0, 1000, size=n).astype(np.int32)
+    b = r.integers(-50, 50, size=n).astype(np.int32)
+    c = r.integers(-(10**12), 10**12, size=n).astype(np.int64)
+    for cols, terms in (([a, b], [(0, "lt", 300), (1, "ge", -10)]),
+                        ([a, c], [(0, "range", 100, 900), (1, "lt", 0)])):
+        got = rel.filter([dev(x) for x in cols], terms)
+        want = oracle.filter(cols, terms)
+        assert np.array_equal(rowids(got), want), terms
+    # through a selection vector longer than one group of tiles
+    sel = r.permutation(n)[: n * 2 // 3].astype(np.uint32)
+    got = rel.filter([dev(a), dev(b)], [(0, "lt", 500)], idx=dev(sel.view(np.int32)))
+    want = oracle.filter([a, b], [(0, "lt", 500)], sel=sel)
+    assert np.array_equal(rowids(got), want), "selection vector"
+
+
 def test_filter_output_capacity():
     announce("filter capacity")
     r = rng(9)
