@@ -734,6 +734,24 @@ void plan_params(const rel_pipeline_desc* d, const PipeLayout& L, unsigned char*
 // Units per work item of the batched phases.
 constexpr uint64_t kFillChunk = 32768;   // words
 constexpr uint64_t kBuildChunk = 8192;   // build rows
+
+// Bits of a direct-table slice that one workgroup sets in LDS during a batch
+// build: 2^20 (128 KB) when a workgroup may hold that much, else the largest
+// power of two that fits.
+// Parts of a dim's build rows that the workgroups of one direct-table slice
+// split between them (at most 512k rows each).
+uint64_t slice_parts(uint64_t rows) {
+  const uint64_t per = uint64_t(1) << 19;
+  const uint64_t parts = (rows + per - 1) / per;
+  return parts < 1 ? 1 : parts;
+}
+
+uint32_t direct_slice_bits() {
+  uint64_t bits = 1u << 20;
+  const uint64_t lds_bits = static_cast<uint64_t>(device_info().lds_per_block) * 8;
+  while (bits > 32 * 1024 && bits > lds_bits) bits >>= 1;
+  return static_cast<uint32_t>(bits);
+}
 constexpr uint64_t kSlotChunk = 16384;   // group slots (a multiple of the finalize chunk, 2048)
 constexpr int kMaxChunkTiles = 8;
 constexpr int kMaxBatch = 1 << 16;
@@ -753,8 +771,9 @@ struct BatchLayout {
   std::vector<PipeLayout> L;
   std::vector<size_t> base;
   size_t off_plans, off_builds, off_fins, off_fill, off_build_items, off_tile_items;
-  size_t off_merge_items, off_fin_items, blob;
-  uint64_t nfill, nbuild, ntile, nmerge, nfin;
+  size_t off_merge_items, off_fin_items, off_slice_items, blob;
+  uint64_t nfill, nbuild, ntile, nmerge, nfin, nslice;
+  uint32_t slice_bits;  // direct-table slice of the second build pass
   int chunk_tiles;
   size_t end;
 };
@@ -783,7 +802,8 @@ rel_status check_batch(const rel_pipeline_desc* d, int n) {
 rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
   B.L.resize(n);
   B.base.resize(n);
-  B.nfill = B.nbuild = B.ntile = B.nmerge = B.nfin = 0;
+  B.nfill = B.nbuild = B.ntile = B.nmerge = B.nfin = B.nslice = 0;
+  B.slice_bits = direct_slice_bits();
   uint64_t tiles = 0;
   for (int i = 0; i < n; ++i) tiles += ceil_div(static_cast<uint64_t>(d[i].fact[0].len), kPipeTile);
   const rel_tuning* t0 = d[0].tuning;
@@ -805,8 +825,11 @@ rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
     off = B.L[i].end;
     for (int k = 0; k < d[i].n_dims; ++k) {
       B.nfill += ceil_div(map_words(B.L[i].dim[k], d[i].dims[k].key.type), kFillChunk) + 1;
-      if (B.L[i].dim[k].direct_cap)
+      if (B.L[i].dim[k].direct_cap) {
         B.nfill += 1 + ceil_div(B.L[i].dim[k].direct_cap / 64, kFillChunk);
+        B.nslice += ceil_div(B.L[i].dim[k].direct_cap, B.slice_bits) *
+                    slice_parts(static_cast<uint64_t>(d[i].dims[k].key.len));
+      }
       B.nbuild += ceil_div(static_cast<uint64_t>(d[i].dims[k].key.len), kBuildChunk);
     }
     const GroupLayout& g = B.L[i].group;
@@ -817,7 +840,8 @@ rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
     B.nfin += ceil_div(d[i].n_keys == 0 ? 1 : g.cap + 1, kSlotChunk);
   }
   const uint64_t most = 0xFFFFFFFFull;
-  if (B.nfill > most || B.nbuild > most || B.ntile > most || B.nmerge > most || B.nfin > most)
+  if (B.nfill > most || B.nbuild > most || B.ntile > most || B.nmerge > most || B.nfin > most ||
+      B.nslice > most)
     return fail(REL_EUNSUPPORTED, "batch: more than 2^32 - 1 work items in a phase");
   size_t h = kAlign;  // the counter
   B.off_plans = h;
@@ -836,6 +860,8 @@ rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
   h = align_up(h + B.nmerge * sizeof(BatchItem));
   B.off_fin_items = h;
   h = align_up(h + B.nfin * sizeof(BatchItem));
+  B.off_slice_items = h;
+  h = align_up(h + B.nslice * sizeof(BatchItem));
   B.blob = h;
   for (int i = 0; i < n; ++i) {
     rel_status st = pipeline_layout(&d[i], B.L[i], true, B.blob + B.base[i]);
@@ -908,12 +934,13 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
   MapBuildParams* builds = reinterpret_cast<MapBuildParams*>(host + B.off_builds);
   FinalizeParams* fins = reinterpret_cast<FinalizeParams*>(host + B.off_fins);
   std::vector<FillItem> fill;
-  std::vector<BatchItem> build_items, tile_items, merge_items, fin_items;
+  std::vector<BatchItem> build_items, tile_items, merge_items, fin_items, slice_items;
   fill.reserve(B.nfill);
   build_items.reserve(B.nbuild);
   tile_items.reserve(B.ntile);
   merge_items.reserve(B.nmerge);
   fin_items.reserve(B.nfin);
+  slice_items.reserve(B.nslice);
   uint32_t group_lds[kLdsClasses] = {};
   std::vector<int> cls(n);
   for (int i = 0; i < n; ++i) {
@@ -939,6 +966,16 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
       if (m.direct_cap) {
         push_fill(fill, reinterpret_cast<uint64_t*>(m.dstate), 2, kFillConst, kDirectStateInit, i);
         push_fill(fill, reinterpret_cast<uint64_t*>(m.dbits), m.direct_cap / 64, kFillConst, 0, i);
+        const uint64_t parts = slice_parts(static_cast<uint64_t>(d[i].dims[k].key.len));
+        for (uint64_t lo = 0; lo < m.direct_cap; lo += B.slice_bits)
+          for (uint64_t part = 0; part < parts; ++part) {
+            BatchItem it;
+            it.inst = i;
+            it.aux = k;
+            it.begin = lo;
+            it.end = part << 32 | parts;  // part `part` of `parts` of the build rows
+            slice_items.push_back(it);
+          }
       }
       push_items(build_items, i, k, static_cast<uint64_t>(d[i].dims[k].key.len), kBuildChunk);
     }
@@ -987,6 +1024,7 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
   std::memcpy(host + B.off_tile_items, tile_items.data(), tile_items.size() * sizeof(BatchItem));
   std::memcpy(host + B.off_merge_items, merge_items.data(), merge_items.size() * sizeof(BatchItem));
   std::memcpy(host + B.off_fin_items, fin_items.data(), fin_items.size() * sizeof(BatchItem));
+  std::memcpy(host + B.off_slice_items, slice_items.data(), slice_items.size() * sizeof(BatchItem));
   shape = plans[0];
   std::memset(&bp, 0, sizeof bp);
   bp.plans = reinterpret_cast<const PipelineParams*>(w + B.off_plans);
@@ -997,11 +1035,14 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
   bp.tile_items = reinterpret_cast<const BatchItem*>(w + B.off_tile_items);
   bp.merge_items = reinterpret_cast<const BatchItem*>(w + B.off_merge_items);
   bp.fin_items = reinterpret_cast<const BatchItem*>(w + B.off_fin_items);
+  bp.slice_items = reinterpret_cast<const BatchItem*>(w + B.off_slice_items);
   bp.nfill = static_cast<uint32_t>(fill.size());
   bp.nbuild = static_cast<uint32_t>(build_items.size());
   bp.ntile = static_cast<uint32_t>(class_end[0]);
   bp.nmerge = static_cast<uint32_t>(merge_items.size());
   bp.nfin = static_cast<uint32_t>(fin_items.size());
+  bp.nslice = static_cast<uint32_t>(slice_items.size());
+  bp.slice_bits = B.slice_bits;
   bp.lds_bytes = lds_bytes[0];
   bp.group_lds_bytes = group_lds[0];
   bp.counter = reinterpret_cast<unsigned long long*>(w);

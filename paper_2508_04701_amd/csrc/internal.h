@@ -549,7 +549,9 @@ struct BatchParams {
   const BatchItem* tile_items;
   const BatchItem* merge_items;
   const BatchItem* fin_items;
-  uint32_t nfill, nbuild, ntile, nmerge, nfin;
+  const BatchItem* slice_items;  // direct-table slices: begin = first bit, aux = dim
+  uint32_t nfill, nbuild, ntile, nmerge, nfin, nslice;
+  uint32_t slice_bits;           // bits of a direct-table slice (a power of two)
   uint32_t lds_bytes;        // dynamic LDS of the fused pass (same for every plan)
   uint32_t group_lds_bytes;  // LDS group table bytes of the largest plan
   unsigned long long* counter;  // fused-pass item counter, zero at the start

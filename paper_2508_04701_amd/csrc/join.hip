@@ -320,6 +320,128 @@ __global__ void __launch_bounds__(256) batch_build_kernel(BatchParams b, int pas
   }
 }
 
+// Build pass 2 of a batch, one workgroup per slice item: bits [lo, lo +
+// slice_bits) of one dim's direct table, set in LDS from one part of the
+// dim's build rows. The workgroup reads its part's keys and takes those that
+// fall in its slice: an LDS atomic OR per key (its old value shows a
+// duplicate) instead of a device-scope one. A slice built from one part is
+// written out with plain stores (slices are disjoint and word-aligned); the
+// parts of a split slice OR their non-zero words into the table, and a bit
+// that another part had already set is a duplicate too.
+constexpr int kSliceThreads = 1024;
+
+__global__ void __launch_bounds__(kSliceThreads) batch_direct_slice_kernel(BatchParams b) {
+  extern __shared__ uint32_t sbits[];
+  const BatchItem& it = batch_at(b.slice_items, blockIdx.x);
+  const MapBuildParams& p = batch_at(b.builds, 2 * static_cast<uint64_t>(it.inst) + it.aux);
+  const MapDesc& m = p.map;
+  const uint64_t range = direct_range(m);
+  if (range == 0 || range > m.direct_cap) return;  // no direct table for this dim
+  const uint64_t lo = it.begin;
+  if (lo >= range) return;
+  const uint64_t hi = lo + b.slice_bits < range ? lo + b.slice_bits : range;
+  const uint32_t words = static_cast<uint32_t>((hi - lo + 31) / 32);
+  for (uint32_t w = threadIdx.x; w < words; w += kSliceThreads) sbits[w] = 0;
+  __syncthreads();
+  const int32_t kmin = m.dstate[kDKmin];
+  const int32_t pmin = m.dstate[kDPmin];
+  const int width = p.val_col ? direct_width(pmin, m.dstate[kDPmax]) : 0;
+  // rows [r_lo, r_hi) of the dim: part `part` of `nparts`
+  const uint32_t part = static_cast<uint32_t>(it.end >> 32);
+  const uint32_t nparts = static_cast<uint32_t>(it.end);
+  const uint64_t rows = static_cast<uint64_t>(p.n);
+  const uint64_t r_lo = rows * part / nparts;
+  const uint64_t n = rows * (part + 1) / nparts;
+  // one key of the slice: its bit (the old word shows a duplicate) and payload
+  auto take = [&](uint64_t row, int64_t key) {
+    const uint64_t k = static_cast<uint64_t>(static_cast<uint32_t>(key - kmin));
+    if (k < lo || k >= hi) return;
+    const uint32_t off = static_cast<uint32_t>(k - lo);
+    const uint32_t bit = 1u << (off & 31);
+    const uint32_t old = atomicOr(&sbits[off >> 5], bit);
+    if (old & bit) {
+      *m.dup = 1;
+      return;
+    }
+    if (width == 0) return;
+    const uint32_t v = static_cast<uint32_t>(load_elem(p.val_col, p.val_type, static_cast<int64_t>(row))) -
+                       static_cast<uint32_t>(pmin);
+    if (width == 1) static_cast<uint8_t*>(m.dvals)[k] = static_cast<uint8_t>(v);
+    else if (width == 2) static_cast<uint16_t*>(m.dvals)[k] = static_cast<uint16_t>(v);
+    else static_cast<uint32_t*>(m.dvals)[k] = v;
+  };
+  if (!p.idx && p.type == kI32 && reinterpret_cast<uintptr_t>(p.keys) % 16 == 0) {
+    // every slice reads all the keys: 16-byte loads, four per lane in flight
+    // (plain loads: the dim's other slices read the same lines)
+    typedef int32_t v4 __attribute__((ext_vector_type(4)));
+    const v4* k4 = static_cast<const v4*>(p.keys);
+    // whole 16-byte groups of the part; the rows before the first and after
+    // the last one singly
+    const uint64_t g_lo = (r_lo + 3) / 4;
+    const uint64_t n4 = n / 4 > g_lo ? n / 4 : g_lo;
+    for (uint64_t r = r_lo + threadIdx.x; r < 4 * g_lo && r < n; r += kSliceThreads)
+      take(r, static_cast<const int32_t*>(p.keys)[r]);
+    constexpr int U = 4;
+    // int32 payloads come with the keys, four per load, so that a key of the
+    // slice needs no further read
+    const bool pvec = width != 0 && p.val_type == kI32 && reinterpret_cast<uintptr_t>(p.val_col) % 16 == 0;
+    const v4* v4p = static_cast<const v4*>(p.val_col);
+    for (uint64_t q = g_lo + threadIdx.x; q < n4; q += U * kSliceThreads) {
+      v4 x[U], y[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint64_t at = q + static_cast<uint64_t>(u) * kSliceThreads;
+        x[u] = at < n4 ? k4[at] : v4{0, 0, 0, 0};
+        y[u] = (pvec && at < n4) ? v4p[at] : v4{0, 0, 0, 0};
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint64_t at = q + static_cast<uint64_t>(u) * kSliceThreads;
+        if (at >= n4) continue;
+        const int32_t key[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+        const int32_t pay[4] = {y[u].x, y[u].y, y[u].z, y[u].w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (!pvec) {
+            take(4 * at + e, key[e]);
+            continue;
+          }
+          const uint64_t k = static_cast<uint64_t>(static_cast<uint32_t>(key[e] - kmin));
+          if (k < lo || k >= hi) continue;
+          const uint32_t off = static_cast<uint32_t>(k - lo);
+          const uint32_t bit = 1u << (off & 31);
+          if (atomicOr(&sbits[off >> 5], bit) & bit) {
+            *m.dup = 1;
+            continue;
+          }
+          const uint32_t v = static_cast<uint32_t>(pay[e]) - static_cast<uint32_t>(pmin);
+          if (width == 1) static_cast<uint8_t*>(m.dvals)[k] = static_cast<uint8_t>(v);
+          else if (width == 2) static_cast<uint16_t*>(m.dvals)[k] = static_cast<uint16_t>(v);
+          else static_cast<uint32_t*>(m.dvals)[k] = v;
+        }
+      }
+    }
+    for (uint64_t r = 4 * n4 + threadIdx.x; r < n; r += kSliceThreads)
+      take(r, static_cast<const int32_t*>(p.keys)[r]);
+  } else {
+    for (uint64_t i = r_lo + threadIdx.x; i < n; i += kSliceThreads) {
+      const uint64_t row = p.idx ? p.idx[i] : i;
+      take(row, load_elem(p.keys, p.type, static_cast<int64_t>(row)));
+    }
+  }
+  __syncthreads();
+  uint32_t* out = m.dbits + lo / 32;
+  if (nparts == 1) {
+    for (uint32_t w = threadIdx.x; w < words; w += kSliceThreads) out[w] = sbits[w];
+  } else {
+    for (uint32_t w = threadIdx.x; w < words; w += kSliceThreads) {
+      const uint32_t mine = sbits[w];
+      if (mine == 0) continue;
+      if (atomicOr(out + w, mine) & mine) *m.dup = 1;
+    }
+  }
+}
+
 // One workgroup per fill item.
 __global__ void __launch_bounds__(256) batch_fill_kernel(BatchParams b) {
   const FillItem& f = batch_at(b.fill, blockIdx.x);
@@ -562,8 +684,17 @@ void launch_batch_fill(const BatchParams& b, hipStream_t s) {
 void launch_batch_build(const BatchParams& b, hipStream_t s) {
   if (b.nbuild == 0) return;
   ProfileScope ps(kKMapBuild, s);
-  for (int pass = 0; pass < 3; ++pass)
-    hipLaunchKernelGGL(batch_build_kernel, dim3(b.nbuild), dim3(256), 0, s, b, pass);
+  hipLaunchKernelGGL(batch_build_kernel, dim3(b.nbuild), dim3(256), 0, s, b, 0);
+  if (b.nslice > 0) {
+    const size_t lds = static_cast<size_t>(b.slice_bits) / 8;
+    static size_t allowed = 0;
+    if (allowed < lds &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(batch_direct_slice_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) == hipSuccess)
+      allowed = lds;
+    hipLaunchKernelGGL(batch_direct_slice_kernel, dim3(b.nslice), dim3(kSliceThreads), lds, s, b);
+  }
+  hipLaunchKernelGGL(batch_build_kernel, dim3(b.nbuild), dim3(256), 0, s, b, 2);
 }
 
 void launch_map_probe(const MapProbeParams& p, int grid, int block, hipStream_t s) {
