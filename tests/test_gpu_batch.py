@@ -305,3 +305,28 @@ def test_native_autotuner_records_and_lookups(tmp_path):
     torch.cuda.synchronize()
     for i, (spec, plan) in enumerate(zip(specs, b.plans)):
         assert_groups(plan.result(), oracle_of(spec), AGGS, f"native-tuned instance {i}")
+
+
+def test_batch_direct_tables_built_in_slices_and_parts():
+    """Dims large enough that the direct-table build splits the key range
+    into several LDS slices and the build rows into several parts: unique
+    keys (a direct table), and the same keys with one key repeated in another
+    part (the parts' merge must see the duplicate, so the dim falls back to
+    its hash table and the repeated key's rows are counted twice)."""
+    announce("batch direct slices")
+    r = np.random.default_rng(77)
+    nb = 1_300_000  # three parts of the build rows; two slices of bits
+    # keys with gaps in their range, so that probes read the bitmap
+    keys = (r.choice(1_800_000, size=nb, replace=False) + 5).astype(np.int32)
+    grp = r.integers(0, 40, size=nb).astype(np.int32)
+    dup_keys = keys.copy()
+    dup_keys[1_200_000] = dup_keys[10]  # rows in the first and the last part
+    npr = 600_000
+    pk = r.integers(0, 1_800_010, size=npr).astype(np.int32)
+    pv = r.integers(-1000, 1000, size=npr).astype(np.int64)
+    specs = []
+    for k in (keys, dup_keys):
+        specs.append(([pk, pv], [], [dict(fk=0, key=k, payload=grp)], [("dim", 0)], AGGS, 64))
+    b = run_batch(specs)
+    for i, (spec, plan) in enumerate(zip(specs, b.plans)):
+        assert_groups(plan.result(), oracle_of(spec), AGGS, f"instance {i}")
