@@ -27,6 +27,7 @@ import json
 import os
 import platform
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -236,7 +237,9 @@ def bench_batch(args, torch, datagen, rel) -> dict:
     side's group attribute): 256 sequential rel_pipeline calls, one
     rel_pipeline_batch launch sequence and its captured graph, on the same
     resident inputs, first with default tuning, then with per-instance
-    records from the autotuner. Results must be identical throughout."""
+    records from the autotuners (the single-plan tuner's for the sequential
+    calls, the batch tuner's for the batch). Results must be identical
+    throughout."""
     from paper_2508_04701_amd import autotune
 
     seed = datagen.SEED0 + 4
@@ -273,13 +276,21 @@ def bench_batch(args, torch, datagen, rel) -> dict:
         o = torch.argsort(k[0])
         return [k[0][o]] + [x[o] for x in a]
 
-    def measure(tunings, chunk=0):
+    def measure(tunings, chunk=0, batch_tunings=None):
+        # the sequential calls take the single-plan tuner's records, the batch
+        # the batch tuner's (each tuned on its own execution path)
+        batch_tunings = tunings if batch_tunings is None else batch_tunings
         singles = [rel.PreparedPipeline(f, [], dm, [("dim", 0)], aggs, g, t)
                    for (f, dm, g), t in zip(inputs, tunings)]
-        t_first = rel.tuning(chunk_tiles=chunk) if tunings[0] is None else \
-            rel.tuning(**{**{k: getattr(tunings[0], k) for k in autotune.FIELDS}, "chunk_tiles": chunk})
+        # chunk_tiles and grid are batch-wide (taken from the first plan): the
+        # first plan's record keeps its other fields, not its grid, which was
+        # chosen for that plan running alone
+        t0b = batch_tunings[0]
+        t_first = rel.tuning(chunk_tiles=chunk) if t0b is None else \
+            rel.tuning(**{**{k: getattr(t0b, k) for k in autotune.FIELDS},
+                          "chunk_tiles": chunk, "grid": 0})
         plans = [rel.Plan(f, [], dm, [("dim", 0)], aggs, g, t_first if i == 0 else t)
-                 for i, ((f, dm, g), t) in enumerate(zip(inputs, tunings))]
+                 for i, ((f, dm, g), t) in enumerate(zip(inputs, batch_tunings))]
         batch = rel.PreparedBatch(plans)
 
         def sequential():
@@ -318,14 +329,17 @@ def bench_batch(args, torch, datagen, rel) -> dict:
     log(f"batch default: {default['sequential_ms']:.1f} ms sequential, "
         f"{default['batched_ms']:.1f} ms batched, {default['graph_ms']:.1f} ms graph")
 
-    # autotuner: one record per size bucket, tuned on its median instance
-    # (probe side cut to at most 8M rows)
+    # autotuners: one record per size bucket, tuned on its median instance
+    # (probe side cut to at most 8M rows), for the single-plan path
+    # (rel_pipeline calls) and, natively, for the batched path (rel_autotune:
+    # each candidate timed as a one-plan batch)
     t0 = time.perf_counter()
     cache = autotune.Cache()
     by_bucket = {}
     for i, (f, dm, g) in enumerate(inputs):
         b = autotune.plan_bucket(f[0].numel(), [dm[0]["key"].numel()], g)
         by_bucket.setdefault(b, []).append(i)
+    samples = []
     for b, members in by_bucket.items():
         members.sort(key=lambda i: inputs[i][0][0].numel())
         f, dm, g = inputs[members[len(members) // 2]]
@@ -334,12 +348,21 @@ def bench_batch(args, torch, datagen, rel) -> dict:
         rec = autotune.tune_plan(lambda t: rel.PreparedPipeline(sample, [], dm, [("dim", 0)],
                                                                 aggs, g, t))
         cache.put(autotune.cache_key("join_groupby", b), rec)
+        samples.append(rel.Plan(sample, [], dm, [("dim", 0)], aggs, g))
     tune_s = time.perf_counter() - t0
     tunings = [autotune.tuning_for(cache, "join_groupby", f[0].numel(), [dm[0]["key"].numel()], g)
                for f, dm, g in inputs]
+    t0 = time.perf_counter()
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "batch_tune.json")
+        autotune.tune_batch_plans(samples, path)
+        batch_tunings = [autotune.lookup(path, rel.Plan(f, [], dm, [("dim", 0)], aggs, g))
+                         for f, dm, g in inputs]
+    tune_batch_s = time.perf_counter() - t0
+    del samples
     best = None
     for chunk in args.batch_chunks:
-        res, got, same = measure(tunings, chunk)
+        res, got, same = measure(tunings, chunk, batch_tunings)
         same = same and all(all(torch.equal(u, v) for u, v in zip(x, y)) for x, y in zip(got, ref))
         res["chunk_tiles"] = chunk
         res["identical_results"] = same
@@ -358,7 +381,7 @@ def bench_batch(args, torch, datagen, rel) -> dict:
         "instances": len(shapes), "probe_rows": n_probe, "build_rows": n_build,
         "default": {**default, "identical_results": same_default},
         "tuned": best,
-        "autotune": {"buckets": len(by_bucket), "seconds": tune_s},
+        "autotune": {"buckets": len(by_bucket), "seconds": tune_s, "batch_seconds": tune_batch_s},
         "batched_rows_per_s": n_probe / (best_ms * 1e-3),
         "sequential_rows_per_s": n_probe / (best["sequential_ms"] * 1e-3),
         "speedup_vs_sequential": best["sequential_ms"] / best_ms,

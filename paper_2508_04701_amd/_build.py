@@ -22,7 +22,7 @@ ARCH = "gfx950"
 
 SOURCES = ["api.cpp", "autotune.cpp", "profile.cpp", "server.cpp", "filter.hip", "join.hip", "groupby.hip", "partition.hip",
            "pipeline.hip",
-           "pipeline_batch.hip", "stream.hip", "bloom.hip", "late.hip", "strings.hip"]
+           "pipeline_batch.hip", "records.hip", "stream.hip", "bloom.hip", "late.hip", "strings.hip"]
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -5,8 +5,9 @@ rel_autotune (tune_batch_plans here): the candidates vary the global
 group-table replicas, the LDS group table (off, 1024 or 4096 slots: the
 workgroup's LDS shape, which sets how many workgroups share a CU), the
 group-table load factor, the fan-out of an instance over the persistent
-workgroups (fact tiles per work item) and the block shape (one or two
-workgroups per CU); rel_autotune_lookup reads a record back (lookup here).
+workgroups (fact tiles per work item), the block shape (one or two
+workgroups per CU) and the spilled-row records (none, or 16 or 256
+partitions); rel_autotune_lookup reads a record back (lookup here).
 For the standalone group-by (tune_groupby) the candidates vary the partition
 fan-out (single pass, automatic, 2048 to 16384 partitions) and the first
 scatter's LDS table. Records persist as JSON keyed by (GPU architecture,

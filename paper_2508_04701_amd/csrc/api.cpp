@@ -764,19 +764,115 @@ uint64_t map_words(const MapLayout& m, int32_t key_type) {
   return m.slot_bytes == 4 ? m.cap / 2 : m.cap;
 }
 
+// Spilled-row records of one batched plan (see RecDesc): the partitions,
+// the record and aggregation-table sizes, and the regions' offsets (from the
+// end of the uploaded block).
+struct RecLayout {
+  uint32_t parts = 0;  // 0: no records
+  uint32_t agg_parts = 0, words = 0, nitems = 0, agg_slots = 0;
+  size_t recs = 0, parted = 0, counts = 0, item_n = 0, part_begin = 0;
+};
+
+// Workspace bound of a batch's records: plans are given records in order
+// while their regions fit; the spilled rows of the others use device-scope
+// atomics.
+constexpr uint64_t kRecordBudget = 32ull << 30;
+
 // The workspace of a batch: first a block uploaded from the host in one
 // copy (the fused-pass counter, then the per-instance kernel parameters and
-// the work-item lists), then each instance's dim and group tables.
+// the work-item lists), then each instance's dim and group tables, then the
+// record regions and the aggregation pieces.
 struct BatchLayout {
   std::vector<PipeLayout> L;
   std::vector<size_t> base;
+  std::vector<RecLayout> rec;
   size_t off_plans, off_builds, off_fins, off_fill, off_build_items, off_tile_items;
   size_t off_merge_items, off_fin_items, off_slice_items, blob;
+  size_t off_pieces;  // from the end of the uploaded block
   uint64_t nfill, nbuild, ntile, nmerge, nfin, nslice;
+  uint64_t piece_cap;
+  uint32_t rec_plans, agg_lds_bytes;
   uint32_t slice_bits;  // direct-table slice of the second build pass
   int chunk_tiles;
   size_t end;
 };
+
+// LDS group tables above this size leave room for one fused-pass workgroup
+// per CU; a plan that needs one takes records instead (on the 256-instance
+// batch, its plans of 1025-2048 groups: 4.4 ms at one workgroup per CU, the
+// batch 1.4 ms faster with records).
+constexpr uint64_t kRecTableBytes = 65536;
+
+// Records for a batched plan when its rows would spill from the fused
+// pass's LDS table (more groups than half its slots) or its table exceeds
+// kRecTableBytes, its accumulators read
+// at most two value columns (gathered with the probes), its group count
+// needs at most kMaxRecParts partitions of an aggregation table and
+// tuning.fanout is not -1. The aggregation table holds as many slots as fit
+// kRecAggLds; an aggregation partition is sized for half of them (fanout > 0
+// sets their count, clamped to [1, kMaxRecParts]). The fused pass and the
+// scatter split each into partitions of their own up to kMinRecParts.
+RecLayout rec_plan(const rel_pipeline_desc* d, const PipeLayout& L, int chunk_tiles) {
+  RecLayout R;
+  const rel_tuning* t = d->tuning;
+  const int fan = t ? t->fanout : 0;
+  if (fan < 0 || d->n_keys == 0 || d->max_groups < 1) return R;
+  const bool spills = 2 * static_cast<uint64_t>(d->max_groups) > static_cast<uint64_t>(L.lds_slots);
+  const bool one_per_cu = static_cast<uint64_t>(L.lds_slots) * L.gp.words * 8 > kRecTableBytes;
+  if (!spills && !one_per_cu) return R;
+  const uint64_t n = static_cast<uint64_t>(d->fact[0].len);
+  if (n == 0 || n > (1ull << 31)) return R;
+  int cols[2] = {-1, -1}, ncols = 0;
+  for (int a = 0; a < L.gp.ap.nacc; ++a) {
+    const int c = L.gp.ap.col[a];
+    if (c == cols[0] || c == cols[1]) continue;
+    if (ncols == 2) return R;
+    cols[ncols++] = c;
+  }
+  uint32_t slots = 1;
+  while (static_cast<uint64_t>(slots) * 2 * L.gp.words * 8 <= kRecAggLds) slots *= 2;
+  uint64_t parts;
+  if (fan > 0) {
+    parts = static_cast<uint64_t>(fan) > kMaxRecParts ? kMaxRecParts : static_cast<uint64_t>(fan);
+  } else {
+    parts = next_pow2(ceil_div(2 * static_cast<uint64_t>(d->max_groups), slots));
+    if (parts > kMaxRecParts) return R;
+  }
+  R.agg_parts = static_cast<uint32_t>(parts < 1 ? 1 : parts);
+  R.parts = R.agg_parts < kMinRecParts ? kMinRecParts : R.agg_parts;
+  R.words = 1 + ncols;
+  R.nitems = static_cast<uint32_t>(ceil_div(ceil_div(n, kPipeTile), chunk_tiles));
+  R.agg_slots = slots;
+  return R;
+}
+
+// The description a plan with records is laid out with: unless its tuning
+// sets one, no LDS group table in the fused pass (its groups are well
+// beyond the table, so most rows would walk a full probe window and spill
+// anyway, and the table costs resident workgroups: on the 256-instance
+// batch's plans above 2048 groups, fused pass 27.0 -> 5.6 ms for 4.7 ->
+// 11.9 ms of record passes), and one global table whatever the tuning
+// (only the aggregation pass's merges reach it, once per key and piece, so
+// copies would only add fill and merge work).
+struct RecPlanDesc {
+  rel_pipeline_desc d;
+  rel_tuning t;
+  explicit RecPlanDesc(const rel_pipeline_desc& src) : d(src) {
+    std::memset(&t, 0, sizeof t);
+    if (src.tuning) t = *src.tuning;
+    if (t.lds_slots == 0) t.lds_slots = -1;
+    t.replicas = 1;
+    d.tuning = &t;
+  }
+};
+
+// Record bytes of R over n fact rows.
+uint64_t rec_bytes(const RecLayout& R, uint64_t n, int chunk_tiles) {
+  const uint64_t item_rows = static_cast<uint64_t>(chunk_tiles) * kPipeTile;
+  return align_up(R.nitems * item_rows * R.words * 8) + align_up(n * R.words * 8) +
+         align_up(static_cast<uint64_t>(R.parts) * R.nitems * 4) + align_up(R.nitems * 4ull) +
+         align_up((R.parts + 1) * 4ull);
+}
 
 // Instances of one batch must share the kernel variant: the same number of
 // dims, and per dim the same key type and payload presence.
@@ -818,9 +914,24 @@ rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
   // instance tables after the uploaded block, whose size depends on the item
   // counts: lay the tables out from 0 first, count, then shift
   size_t off = 0;
+  B.rec.assign(n, RecLayout());
+  uint64_t rec_total = 0;
   for (int i = 0; i < n; ++i) {
     rel_status st = pipeline_layout(&d[i], B.L[i], true, off);
     if (st) return fail(st, "batch plan %d: %s", i, g_error.c_str());
+    // records within kRecordBudget; such a plan is then laid out again
+    // without the fused pass's LDS table and with one global table
+    RecLayout R = rec_plan(&d[i], B.L[i], B.chunk_tiles);
+    if (R.parts) {
+      const uint64_t bytes = rec_bytes(R, static_cast<uint64_t>(d[i].fact[0].len), B.chunk_tiles);
+      if (rec_total + bytes <= kRecordBudget) {
+        rec_total += bytes;
+        B.rec[i] = R;
+        RecPlanDesc rd(d[i]);
+        st = pipeline_layout(&rd.d, B.L[i], true, off);
+        if (st) return fail(st, "batch plan %d: %s", i, g_error.c_str());
+      }
+    }
     B.base[i] = off;
     off = B.L[i].end;
     for (int k = 0; k < d[i].n_dims; ++k) {
@@ -839,6 +950,35 @@ rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
     if (g.replicas > 1) B.nmerge += ceil_div((g.replicas - 1) * (g.cap + 1), kSlotChunk);
     B.nfin += ceil_div(d[i].n_keys == 0 ? 1 : g.cap + 1, kSlotChunk);
   }
+  // record regions after the tables
+  B.rec_plans = 0;
+  B.agg_lds_bytes = 0;
+  B.piece_cap = 0;
+  for (int i = 0; i < n; ++i) {
+    RecLayout& R = B.rec[i];
+    if (R.parts == 0) continue;
+    const uint64_t rows = static_cast<uint64_t>(d[i].fact[0].len);
+    off = align_up(off);
+    const uint64_t item_rows = static_cast<uint64_t>(B.chunk_tiles) * kPipeTile;
+    R.recs = off;
+    off += align_up(R.nitems * item_rows * R.words * 8);
+    R.parted = off;
+    off += align_up(rows * R.words * 8);
+    R.counts = off;
+    off += align_up(static_cast<uint64_t>(R.parts) * R.nitems * 4);
+    R.item_n = off;
+    off += align_up(R.nitems * 4ull);
+    R.part_begin = off;
+    off += align_up((R.parts + 1) * 4ull);
+    ++B.rec_plans;
+    const uint32_t agg = R.agg_slots * B.L[i].gp.words * 8;
+    if (agg > B.agg_lds_bytes) B.agg_lds_bytes = agg;
+    B.piece_cap += ceil_div(rows, kRecPiece) + R.agg_parts;
+  }
+  off = align_up(off);
+  B.off_pieces = off;
+  off += align_up(B.piece_cap * sizeof(RecPiece));
+  if (B.piece_cap > 0xFFFFFFFFull) return fail(REL_EUNSUPPORTED, "batch: too many record pieces");
   const uint64_t most = 0xFFFFFFFFull;
   if (B.nfill > most || B.nbuild > most || B.ntile > most || B.nmerge > most || B.nfin > most ||
       B.nslice > most)
@@ -864,7 +1004,8 @@ rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
   h = align_up(h + B.nslice * sizeof(BatchItem));
   B.blob = h;
   for (int i = 0; i < n; ++i) {
-    rel_status st = pipeline_layout(&d[i], B.L[i], true, B.blob + B.base[i]);
+    RecPlanDesc rd(d[i]);
+    rel_status st = pipeline_layout(B.rec[i].parts ? &rd.d : &d[i], B.L[i], true, B.blob + B.base[i]);
     if (st) return st;
     B.base[i] += B.blob;
   }
@@ -1011,12 +1152,32 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
     }
     class_end[c] = tile_items.size();
   }
-  // one LDS layout per class: its largest group table, then the queues
+  // one LDS layout per class: its largest group table, then the queues, then
+  // (plans with records) the partition histogram
   uint32_t lds_bytes[kLdsClasses] = {};
+  unsigned char* tables = w + B.blob;
   for (int i = 0; i < n; ++i) {
     plans[i].lds_group_offset = 0;
     plans[i].queue_offset = group_lds[cls[i]];
     plans[i].lds_bytes = group_lds[cls[i]] + (kPipeThreads / kWave) * plans[i].queue_stride;
+    const RecLayout& R = B.rec[i];
+    RecDesc& rd = plans[i].rec;
+    std::memset(&rd, 0, sizeof rd);
+    if (R.parts) {
+      rd.recs = reinterpret_cast<uint64_t*>(tables + R.recs);
+      rd.parted = reinterpret_cast<uint64_t*>(tables + R.parted);
+      rd.counts = reinterpret_cast<uint32_t*>(tables + R.counts);
+      rd.item_n = reinterpret_cast<uint32_t*>(tables + R.item_n);
+      rd.part_begin = reinterpret_cast<uint32_t*>(tables + R.part_begin);
+      rd.parts = R.parts;
+      rd.agg_parts = R.agg_parts;
+      rd.words = R.words;
+      rd.nitems = R.nitems;
+      rd.item_tiles = static_cast<uint32_t>(B.chunk_tiles);
+      rd.agg_slots = R.agg_slots;
+      rd.lds_offset = (plans[i].lds_bytes + 15) / 16 * 16;
+      plans[i].lds_bytes = rd.lds_offset + (R.parts + 1) * 4;
+    }
     if (plans[i].lds_bytes > lds_bytes[cls[i]]) lds_bytes[cls[i]] = plans[i].lds_bytes;
   }
   std::memcpy(host + B.off_fill, fill.data(), fill.size() * sizeof(FillItem));
@@ -1046,6 +1207,15 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
   bp.lds_bytes = lds_bytes[0];
   bp.group_lds_bytes = group_lds[0];
   bp.counter = reinterpret_cast<unsigned long long*>(w);
+  bp.nplans = static_cast<uint32_t>(n);
+  bp.ntile_all = static_cast<uint32_t>(tile_items.size());
+  bp.rec_plans = B.rec_plans;
+  bp.agg_lds_bytes = B.agg_lds_bytes;
+  bp.piece_cap = static_cast<uint32_t>(B.piece_cap);
+  bp.pieces = reinterpret_cast<RecPiece*>(tables + B.off_pieces);
+  // counters after the four fused-pass classes' in the zeroed first block
+  bp.npieces = reinterpret_cast<unsigned long long*>(w) + kLdsClasses;
+  bp.agg_counter = reinterpret_cast<unsigned long long*>(w) + kLdsClasses + 1;
   for (int c = 0; c < kLdsClasses; ++c) {
     const size_t begin = c == 0 ? 0 : class_end[c - 1];
     fused[c] = bp;
@@ -1073,6 +1243,7 @@ rel_status batch_enqueue(const BatchLayout& B, const BatchParams& bp,
       return fail(REL_EDEVICE, "batch: fused kernel launch (%u bytes of LDS): %s",
                   fused[c].lds_bytes, hipGetErrorString(e));
   }
+  launch_batch_records(bp, s);
   launch_batch_merge(bp, s);
   launch_batch_finalize(bp, s);
   return after_launch(s, "batch");

@@ -315,9 +315,10 @@ std::string compact(const Json& o) {
   return s + "}";
 }
 
-// Load factor, fan-out (fact tiles per work item of a batch instance),
+// Load factor, work split (fact tiles per work item of a batch instance),
 // block shape (resident workgroups: the LDS group table's size, or a fixed
-// number of workgroups per CU) and global group-table copies.
+// number of workgroups per CU), global group-table copies, and the fan-out
+// of a batched plan's spilled-row records (their partitions, or none).
 std::vector<rel_tuning> candidates(int cu) {
   std::vector<rel_tuning> c;
   auto add = [&](std::initializer_list<std::pair<const char*, double>> fields) {
@@ -341,6 +342,11 @@ std::vector<rel_tuning> candidates(int cu) {
   add({{"chunk_tiles", 16}});
   add({{"grid", static_cast<double>(cu)}});
   add({{"grid", static_cast<double>(2 * cu)}});
+  // spilled rows of batched plans: device atomics instead of records, or
+  // records over fewer or more partitions than the default
+  add({{"fanout", -1}});
+  add({{"fanout", 16}});
+  add({{"fanout", 256}});
   return c;
 }
 

@@ -59,6 +59,11 @@ __device__ __forceinline__ void lds_add_u64(uint64_t* p, uint64_t v) {
   __atomic_fetch_add((LdsU64*)p, v, __ATOMIC_RELAXED);
 }
 
+__device__ __forceinline__ uint32_t lds_fetch_add_u32(uint32_t* p, uint32_t v) {
+  typedef __attribute__((address_space(3))) uint32_t LdsU32;
+  return __atomic_fetch_add((LdsU32*)p, v, __ATOMIC_RELAXED);
+}
+
 __device__ __forceinline__ void global_add_u64(uint64_t* p, uint64_t v) {
   typedef __attribute__((address_space(1))) uint64_t GlobalU64;
   __hip_atomic_fetch_add((GlobalU64*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -25,6 +25,13 @@ __device__ __forceinline__ uint32_t lds_hash(uint64_t pk) {
   return hash32(static_cast<uint32_t>(pk) ^ hash32(static_cast<uint32_t>(pk >> 32) + 0x9e3779b9u));
 }
 
+// Partition of packed key pk among `parts` (a power of two): the top bits of
+// its LDS hash, so that an LDS table indexed by the low bits spreads one
+// partition's keys over all its slots.
+__device__ __forceinline__ uint32_t rec_part(uint64_t pk, uint32_t parts) {
+  return static_cast<uint32_t>((static_cast<uint64_t>(lds_hash(pk)) * parts) >> 32);
+}
+
 // Index of the LDS slot holding (or newly claimed for) packed key pk, or -1
 // when the key is the sentinel pattern, there is no LDS table, or no slot is
 // free within the probe window.

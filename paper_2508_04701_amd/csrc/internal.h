@@ -462,6 +462,38 @@ struct PipeDim {
 // kResolved | slot: found at that slot).
 enum QueueField : int { kQRow = 0, kQFk0, kQFk1, kQSt0, kQSt1, kQueueFields };
 
+// Spilled-row records of a batched plan (hash grouping, Section 4.2, for
+// group counts beyond the LDS table): a row of the fused pass that finds no
+// LDS slot is written out as a record of `words` 64-bit words (its packed
+// group key, then the early value columns) instead of updating the global
+// table with device-scope atomics. A scan turns the per-(partition, item)
+// counts into offsets, a scatter groups the records by partition (the top
+// bits of the key's LDS hash), and an aggregation pass folds each partition,
+// in pieces, into an LDS table that then merges into the global table with
+// one update per key. parts == 0: the plan's spilled rows use atomics.
+struct RecDesc {
+  uint64_t* recs;         // item j's records start at word j * item_tiles * kPipeTile * words
+  uint64_t* parted;       // the records in partition order
+  uint32_t* counts;       // [parts][nitems] records per (partition, item), then their offsets
+  uint32_t* item_n;       // records of each item
+  uint32_t* part_begin;   // parts + 1 offsets into parted
+  uint32_t parts;         // a power of two, at most kMaxRecParts; 0 = off
+  uint32_t agg_parts;     // partitions the aggregation pass folds one by one: runs of
+                          // parts / agg_parts consecutive partitions (the top bits agree)
+  uint32_t words;         // 64-bit words per record (2 or 3; 1 = COUNT only)
+  uint32_t nitems;        // fused-pass items of the plan
+  uint32_t item_tiles;    // fact tiles per item
+  uint32_t lds_offset;    // fused pass: byte offset of the LDS histogram (parts + 1 words)
+  uint32_t agg_slots;     // LDS table slots of the aggregation pass (a power of two)
+};
+
+constexpr uint32_t kMaxRecParts = 256;
+// At least this many partitions in the fused pass and the scatter, so that
+// the lanes of a wave rarely count into the same LDS word.
+constexpr uint32_t kMinRecParts = 16;
+constexpr uint32_t kRecPiece = 1u << 18;  // records per aggregation work item
+constexpr uint32_t kRecAggLds = 65536;     // bound on the aggregation pass's LDS table
+
 struct PipelineParams {
   const void* fact[8];
   int32_t fact_type[8];
@@ -496,6 +528,7 @@ struct PipelineParams {
   uint32_t queue_stride;
   uint32_t field_offset[kQueueFields];
   int32_t field_wide[kQueueFields];   // 8-byte (1) or 4-byte (0) elements
+  RecDesc rec;                        // batched plans only
 };
 
 constexpr int kPipeThreads = 512;
@@ -524,6 +557,11 @@ struct BatchItem {
   uint32_t inst;
   uint32_t aux;
   uint64_t begin, end;
+};
+
+// Records [begin, end) of partition `part` of plan `inst`'s records.
+struct RecPiece {
+  uint32_t inst, part, begin, end;
 };
 
 enum FillKind : int32_t { kFillConst = 0, kFillPairs = 1, kFillGroup = 2 };
@@ -555,6 +593,15 @@ struct BatchParams {
   uint32_t lds_bytes;        // dynamic LDS of the fused pass (same for every plan)
   uint32_t group_lds_bytes;  // LDS group table bytes of the largest plan
   unsigned long long* counter;  // fused-pass item counter, zero at the start
+  // spilled-row records: every plan, every fused-pass item (all classes),
+  // the aggregation pieces the scan lists, and the aggregation pass's LDS
+  uint32_t nplans, ntile_all;
+  uint32_t rec_plans;           // plans with records (0: the record passes are skipped)
+  uint32_t agg_lds_bytes;
+  uint32_t piece_cap;           // bound on the pieces the scan lists
+  RecPiece* pieces;
+  unsigned long long* npieces;  // written by the scan, zero at the start
+  unsigned long long* agg_counter;  // zero at the start
 };
 
 // Reference to element i of a batch array: read through the constant address
@@ -572,6 +619,8 @@ void launch_batch_build(const BatchParams& b, hipStream_t s);
 // the persistent grid by occupancy. Returns the first failing HIP status.
 hipError_t launch_batch_pipeline(const BatchParams& b, const PipelineParams& shape, int grid,
                                  hipStream_t s);
+// The record passes (scan, scatter, aggregation) of the plans with records.
+void launch_batch_records(const BatchParams& b, hipStream_t s);
 void launch_batch_merge(const BatchParams& b, hipStream_t s);
 void launch_batch_finalize(const BatchParams& b, hipStream_t s);
 

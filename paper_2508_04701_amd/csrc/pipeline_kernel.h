@@ -568,9 +568,41 @@ __device__ __forceinline__ uint32_t acc_code(const PipelineParams& p) {
   return c;
 }
 
+// Writes row r's update of group pk as a record (batched plans with
+// records; see RecDesc): the active lanes take consecutive places in the
+// item's record run (one LDS atomic per wave on the item's count) and count
+// the record in its partition's LDS histogram entry. The item is the run of
+// item_tiles tiles that holds row r.
+__device__ __forceinline__ void spill_record(const PipelineParams& p, int64_t r, uint64_t pk,
+                                             int64_t va, int64_t vb, uint64_t* lg) {
+  const RecDesc& rd = p.rec;
+  uint32_t* hist = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(lg) + rd.lds_offset);
+  const uint64_t m = ballot(true);
+  const uint32_t rank = rank_below(m);
+  uint32_t base = 0;
+  if (rank == 0) base = lds_fetch_add_u32(hist + rd.parts, popc64(m));
+  base = __builtin_amdgcn_readfirstlane(base);
+  lds_fetch_add_u32(hist + rec_part(pk, rd.parts), 1u);
+  const uint32_t tile = static_cast<uint32_t>(static_cast<uint64_t>(r) / kPipeTile);
+  const uint64_t at = static_cast<uint64_t>(tile - tile % rd.item_tiles) * kPipeTile + base + rank;
+  uint64_t* w = rd.recs + at * rd.words;
+  if (rd.words == 2) {
+    typedef uint64_t v2u64 __attribute__((ext_vector_type(2)));
+    v2u64 x;
+    x.x = pk;
+    x.y = static_cast<uint64_t>(va);
+    __builtin_nontemporal_store(x, reinterpret_cast<v2u64*>(w));
+  } else {
+    __builtin_nontemporal_store(pk, w);
+    if (rd.words > 1) __builtin_nontemporal_store(static_cast<uint64_t>(va), w + 1);
+    if (rd.words > 2) __builtin_nontemporal_store(static_cast<uint64_t>(vb), w + 2);
+  }
+}
+
 // Adds row r to group pk (va, vb: the early-gathered value columns; acode:
 // acc_code(p)): one branch per row, the workgroup's LDS table or its global
-// replica.
+// replica (or, kRec and a plan with records, a record).
+template <bool kRec = false>
 __device__ __forceinline__ void update_group(const PipelineParams& p, int64_t r, uint64_t pk,
                                              int64_t va, int64_t vb, uint64_t* lg,
                                              const GroupTable& gt, uint32_t acode) {
@@ -589,6 +621,12 @@ __device__ __forceinline__ void update_group(const PipelineParams& p, int64_t r,
       lds_acc_update(s + 2 + a, static_cast<int>(c & 3u), v);
     }
   } else {
+    if constexpr (kRec) {
+      if (p.rec.parts) {
+        spill_record(p, r, pk, va, vb, lg);
+        return;
+      }
+    }
     uint64_t* gs = group_slot(gt, pk);
     if (!gs) return;
     global_add_u64(gs + 1, 1);
@@ -613,7 +651,7 @@ __device__ __forceinline__ void update_group(const PipelineParams& p, int64_t r,
 
 // One queued row: probe the dims and update the row's group. Returns true
 // when the row has to go back to the queue (a resumable probe continues).
-template <int D0, int D1>
+template <int D0, int D1, bool kRec = false>
 __device__ __forceinline__ bool process_row(const PipelineParams& p, int64_t r, int64_t fk0,
                                             int64_t fk1, uint32_t& st0, uint32_t& st1,
                                             const void* ld0, const void* ld1, uint64_t* lg,
@@ -672,7 +710,7 @@ __device__ __forceinline__ bool process_row(const PipelineParams& p, int64_t r, 
   if (multi) return false;  // several dim matches: left to the enumeration pass
   if (p.g.kp.nkeys > 0 && p.key_src[0] != 0) k0 = static_cast<int32_t>(p.key_src[0] == 1 ? v0 : v1);
   if (p.g.kp.nkeys > 1 && p.key_src[1] != 0) k1 = static_cast<int32_t>(p.key_src[1] == 1 ? v0 : v1);
-  update_group(p, r, pack_keys(p.g.kp, k0, k1), va, vb, lg, gt, acode);
+  update_group<kRec>(p, r, pack_keys(p.g.kp, k0, k1), va, vb, lg, gt, acode);
   return false;
 }
 
@@ -830,7 +868,7 @@ __device__ __forceinline__ void spec_direct_row(const PipelineParams& p, int64_t
 
 // Processes the top `take` (<= 64) rows of the wave's queue, one per lane;
 // rows whose probes continue are written back. Returns the new queue length.
-template <int D0, int D1>
+template <int D0, int D1, bool kRec = false>
 __device__ __forceinline__ uint32_t drain(const PipelineParams& p, unsigned char* wq,
                                           uint32_t queued, uint32_t take, int lane,
                                           const void* ld0, const void* ld1, uint64_t* lg,
@@ -856,8 +894,8 @@ __device__ __forceinline__ uint32_t drain(const PipelineParams& p, unsigned char
   __builtin_amdgcn_wave_barrier();
   bool again = false;
   if (mine)
-    again = process_row<D0, D1>(p, r, fk0, fk1, st0, st1, ld0, ld1, lg, gt, limit0, limit1, dv0,
-                                dv1, acode);
+    again = process_row<D0, D1, kRec>(p, r, fk0, fk1, st0, st1, ld0, ld1, lg, gt, limit0, limit1,
+                                      dv0, dv1, acode);
   const uint64_t b = ballot(again);
   if (again) {
     const uint32_t at = base + rank_below(b);
@@ -935,7 +973,7 @@ __device__ __forceinline__ void drain_direct(const PipelineParams& p, const unsi
 // predicate column (two tiles ahead) and the foreign keys, queues the passing
 // rows per wave and drains them in full-lane batches. Returns with the
 // wave's queue empty.
-template <int D0, int D1, bool kDirect, int S = 0>
+template <int D0, int D1, bool kDirect, int S = 0, bool kRec = false>
 __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile, int64_t end,
                                           int64_t step, unsigned char* wq, int lane,
                                           const void* ld0, const void* ld1, uint64_t* lg,
@@ -1010,8 +1048,8 @@ __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile,
         }
       } else {
         while (queued >= kWave)
-          queued = drain<D0, D1>(p, wq, queued, kWave, lane, ld0, ld1, lg, gt, limit0, limit1,
-                                 dv0, dv1, acode);
+          queued = drain<D0, D1, kRec>(p, wq, queued, kWave, lane, ld0, ld1, lg, gt, limit0,
+                                       limit1, dv0, dv1, acode);
       }
     }
   }
@@ -1020,8 +1058,8 @@ __device__ __forceinline__ void run_tiles(const PipelineParams& p, int64_t tile,
     if (queued > 0) drain_direct<D0, D1, S>(p, wq, 0, queued, lane, lg, gt, dv0, dv1, acode);
   } else {
     while (queued > 0)
-      queued = drain<D0, D1>(p, wq, queued, queued < kWave ? queued : kWave, lane, ld0, ld1, lg,
-                             gt, limit0, limit1, dv0, dv1, acode);
+      queued = drain<D0, D1, kRec>(p, wq, queued, queued < kWave ? queued : kWave, lane, ld0, ld1,
+                                   lg, gt, limit0, limit1, dv0, dv1, acode);
   }
 }
 
@@ -1450,13 +1488,24 @@ __attribute__((amdgpu_waves_per_eu(kBatchWaves<D0, D1>))) batch_fused_kernel(Bat
     const PipelineParams& p = batch_at(b.plans, it.inst);
     unsigned char* wq = lds + p.queue_offset + (threadIdx.x / kWave) * p.queue_stride;
     if (p.lds_slots > 0) lds_group_init(lg, p.lds_slots, p.g);
+    const uint32_t parts = p.rec.parts;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(lds + p.rec.lds_offset);
+    if (parts)
+      for (uint32_t q = threadIdx.x; q <= parts; q += blockDim.x) hist[q] = 0;
     __syncthreads();
     const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
-    run_tiles<D0, D1, false>(p, it.begin, it.end, 1, wq, lane, nullptr, nullptr, lg, gt,
-                             match_limit<D0>(p.dim[0]), match_limit<D1>(p.dim[1]));
+    run_tiles<D0, D1, false, 0, true>(p, it.begin, it.end, 1, wq, lane, nullptr, nullptr, lg, gt,
+                                      match_limit<D0>(p.dim[0]), match_limit<D1>(p.dim[1]));
     __syncthreads();
-    if (p.lds_slots > 0) {
-      lds_group_flush(lg, p.lds_slots, p.g);
+    if (p.lds_slots > 0 || parts) {
+      if (p.lds_slots > 0) lds_group_flush(lg, p.lds_slots, p.g);
+      if (parts) {
+        // the item's record count per partition, partition-major
+        const uint32_t j = static_cast<uint32_t>(it.begin / p.rec.item_tiles);
+        for (uint32_t q = threadIdx.x; q < parts; q += blockDim.x)
+          p.rec.counts[static_cast<uint64_t>(q) * p.rec.nitems + j] = hist[q];
+        if (threadIdx.x == 0) p.rec.item_n[j] = hist[parts];
+      }
       __syncthreads();
     }
   }

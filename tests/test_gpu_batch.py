@@ -279,10 +279,11 @@ def test_autotuner_groupby_fanout_candidates_agree():
 
 def test_native_autotuner_records_and_lookups(tmp_path):
     """rel_autotune through the C-ABI: every candidate (load factor, fan-out,
-    block shape, LDS group table, replicas) returns the same groups (it
-    fails otherwise), one record per bucket lands in the JSON cache with all
-    fifteen candidates timed, rel_autotune_lookup returns it, and a batch
-    whose instances carry the looked-up records equals the oracle."""
+    block shape, LDS group table, replicas, record partitions) returns the
+    same groups (it fails otherwise), one record per bucket lands in the
+    JSON cache with all eighteen candidates timed, rel_autotune_lookup
+    returns it, and a batch whose instances carry the looked-up records
+    equals the oracle."""
     import json
 
     from paper_2508_04701_amd import autotune
@@ -297,7 +298,7 @@ def test_native_autotuner_records_and_lookups(tmp_path):
     assert len(keys) == len({autotune.plan_bucket(len(s[0][0]), [len(s[2][0]["key"])], s[5])
                              for s in specs})
     for k in keys:
-        assert len(recs[k]["candidates"]) == 15 and recs[k]["ms"] > 0
+        assert len(recs[k]["candidates"]) == 18 and recs[k]["ms"] > 0
     tuned = [device_plan(s, autotune.lookup(path, p)) for s, p in zip(specs, plans)]
     assert all(autotune.lookup(path, p) is not None for p in plans)
     b = rel.PreparedBatch(tuned)
@@ -330,3 +331,76 @@ def test_batch_direct_tables_built_in_slices_and_parts():
     b = run_batch(specs)
     for i, (spec, plan) in enumerate(zip(specs, b.plans)):
         assert_groups(plan.result(), oracle_of(spec), AGGS, f"instance {i}")
+
+
+def record_specs(seed):
+    """Join + group-by plans whose groups outgrow the fused pass's LDS table,
+    so that their spilled rows go through the record passes: uniform groups
+    from 3k to 150k, Zipf-skewed groups, records of one, two and three words
+    (COUNT only; one value column; two value columns), a plan with three
+    value columns (no records: its spilled rows use atomics), a plan whose
+    probes all miss, and one with no probe rows."""
+    r = np.random.default_rng(seed)
+    specs = []
+
+    def plan(n_build, n_probe, groups, aggs, grp=None, miss=False, ncols=1):
+        keys = r.permutation(n_build).astype(np.int32)
+        if grp is None:
+            grp = r.integers(0, groups, size=n_build).astype(np.int32)
+        lo = n_build + 10 if miss else 0
+        pk = r.integers(lo, lo + int(n_build * 1.1) + 1, size=n_probe).astype(np.int32)
+        vals = [r.integers(-10**6, 10**6, size=n_probe).astype(np.int64) for _ in range(ncols)]
+        specs.append(([pk] + vals, [], [dict(fk=0, key=keys, payload=grp)], [("dim", 0)], aggs,
+                      max(1, groups)))
+
+    plan(200_000, 300_000, 3_000, AGGS)
+    plan(400_000, 500_001, 40_000, AGGS)
+    plan(600_000, 700_000, 150_000, [("sum", 1), ("count", None)])
+    zipf = (datagen.zipf_ranks(seed, 9, 60_000, 1.1, 300_000) - 1).astype(np.int32)
+    plan(300_000, 400_000, 60_000, AGGS, grp=zipf)
+    plan(100_000, 200_000, 20_000, [("count", None)])
+    plan(100_000, 250_000, 30_000, [("sum", 1), ("max", 2), ("avg", 2)], ncols=2)
+    plan(100_000, 150_000, 30_000, [("sum", 1), ("min", 2), ("max", 3)], ncols=3)
+    plan(50_000, 100_000, 10_000, AGGS, miss=True)
+    plan(50_000, 0, 10_000, AGGS)
+    return specs
+
+
+def run_tuned(specs, tunings):
+    b = rel.PreparedBatch([device_plan(s, t) for s, t in zip(specs, tunings)])
+    b.launch()
+    torch.cuda.synchronize()
+    return b
+
+
+@pytest.mark.parametrize("fanout", [0, 4, -1])
+def test_batch_spilled_rows_as_records(fanout):
+    """Rows that find no LDS group slot become records, grouped by partition
+    and folded per partition in LDS (fanout 0: partitions sized for the
+    aggregation table; 4: far fewer, so most keys of a partition miss its
+    LDS table and update the global table directly; -1: no records, device
+    atomics): every plan equals the oracle."""
+    announce("batch records", fanout)
+    specs = record_specs(1212)
+    t = rel.tuning(fanout=fanout)
+    b = run_tuned(specs, [t] * len(specs))
+    for i, (spec, plan) in enumerate(zip(specs, b.plans)):
+        assert_groups(plan.result(), oracle_of(spec), spec[4], f"fanout {fanout} plan {i}")
+
+
+def test_batch_records_graph_replays():
+    """The record passes inside a captured graph: their counters and piece
+    list start from zero on every replay."""
+    announce("batch records graph")
+    specs = record_specs(1313)[:4]
+    b = rel.PreparedBatch([device_plan(s) for s in specs])
+    b.capture()
+    want = [oracle_of(s) for s in specs]
+    for rep in range(3):
+        b.launch_graph()
+        torch.cuda.synchronize()
+        for i, plan in enumerate(b.plans):
+            assert_groups(plan.result(), want[i], specs[i][4], f"replay {rep} plan {i}")
+        x = torch.arange(1 << 20, device="cuda", dtype=torch.int64)
+        assert int(x.sum().item()) == (1 << 20) * ((1 << 20) - 1) // 2
+    b.release()
