@@ -239,7 +239,8 @@ def bench_batch(args, torch, datagen, rel) -> dict:
     resident inputs, first with default tuning, then with per-instance
     records from the autotuners (the single-plan tuner's for the sequential
     calls, the batch tuner's for the batch). Results must be identical
-    throughout."""
+    throughout. With --batch-per-instance the instances above 2048 groups
+    are also timed one at a time, each as a one-plan batch."""
     from paper_2508_04701_amd import autotune
 
     seed = datagen.SEED0 + 4
@@ -329,6 +330,40 @@ def bench_batch(args, torch, datagen, rel) -> dict:
     log(f"batch default: {default['sequential_ms']:.1f} ms sequential, "
         f"{default['batched_ms']:.1f} ms batched, {default['graph_ms']:.1f} ms graph")
 
+    # (--batch-per-instance) the instances above 2048 groups one at a time,
+    # each as a one-plan batch with default tuning (their spilled rows go
+    # through the record passes): device time summed over the batch's
+    # kernel classes (HIP events around each launch, so host gaps between
+    # launches do not count)
+    above_2k = None
+    if args.batch_per_instance:
+        per_inst = []
+        for (f, dm, g), shp in zip(inputs, shapes):
+            if shp["n_groups"] <= 2048:
+                continue
+            one = rel.PreparedBatch([rel.Plan(f, [], dm, [("dim", 0)], aggs, g)])
+            one.launch()
+            torch.cuda.synchronize()
+            rel.profile_read()
+            rel.profile_enable(True)
+            for _ in range(3):
+                one.launch()
+            torch.cuda.synchronize()
+            rel.profile_enable(False)
+            ms = sum(v[0] for v in rel.profile_read().values()) / 3
+            one.release()
+            del one
+            per_inst.append([shp["n_groups"], shp["n_probe"], round(ms, 4)])
+        rates = sorted(r / (ms * 1e-3) for _, r, ms in per_inst)
+        above_2k = {"instances": len(per_inst),
+                    "rows_per_s": {"min": rates[0], "median": rates[len(rates) // 2],
+                                   "max": rates[-1]} if rates else None,
+                    "per_instance": per_inst}
+        if rates:
+            log(f"batch: {len(per_inst)} instances above 2048 groups alone: "
+                f"{rates[0] / 1e9:.2f}-{rates[-1] / 1e9:.1f} G rows/s (median "
+                f"{rates[len(rates) // 2] / 1e9:.1f})")
+
     # autotuners: one record per size bucket, tuned on its median instance
     # (probe side cut to at most 8M rows), for the single-plan path
     # (rel_pipeline calls) and, natively, for the batched path (rel_autotune:
@@ -380,6 +415,7 @@ def bench_batch(args, torch, datagen, rel) -> dict:
                     f"probe 10k-50M, groups 8-100k",
         "instances": len(shapes), "probe_rows": n_probe, "build_rows": n_build,
         "default": {**default, "identical_results": same_default},
+        **({"above_2k_groups_alone": above_2k} if above_2k else {}),
         "tuned": best,
         "autotune": {"buckets": len(by_bucket), "seconds": tune_s, "batch_seconds": tune_batch_s},
         "batched_rows_per_s": n_probe / (best_ms * 1e-3),
@@ -867,6 +903,8 @@ def main() -> int:
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--batch-chunks", type=int, nargs="*", default=[0, 2])
+    ap.add_argument("--batch-per-instance", action="store_true",
+                    help="also time each batched instance above 2048 groups alone")
     ap.add_argument("--tune-cache-out", default=None,
                     help="write the autotuner records of the batched section to this JSON file")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")

@@ -122,7 +122,9 @@ typedef struct {
                             (a group-by over at least 1M rows whose groups do not fit the
                             single pass's LDS table, with as many partitions as keep each
                             one's keys within an LDS table; a join whose slot array exceeds
-                            64 MB, one partition per 128 KB range of slots); -1 = never */
+                            64 MB, one partition per 128 KB range of slots); -1 = never.
+                            rel_pipeline_batch: partitions of a plan's spilled-row records
+                            (see there; -1 = no records) */
 } rel_tuning;
 
 /* rel_tuning.flags: keep dims of rel_pipeline in their hash tables even when
@@ -449,11 +451,27 @@ size_t rel_pipeline_batch_ws(const rel_pipeline_desc* d, int n);
  * the items of all plans in order from a device counter, so that one large
  * plan is spread over the chip and many small ones share it. Results are
  * identical to n rel_pipeline calls.
+ * Spilled rows (hash grouping, Section 4.2): a grouped plan whose groups do
+ * not fit the fused pass's LDS table at half load (or would need a table
+ * over 64 KB), whose aggregates read at most two value columns and whose
+ * fact table has at most 2^31 rows writes each row that finds no LDS slot
+ * as a 16-to-24-byte record rather than updating the global table with
+ * device-scope atomics; the records are grouped by partition of the key
+ * hash and folded, partition by partition, in LDS, then merged into the
+ * global table once per key. Such a plan runs its fused pass without an
+ * LDS table (unless tuning.lds_slots sets one) and with one global table.
+ * tuning.fanout: -1 keeps the atomics; 0 sizes the partitions for the
+ * aggregation pass's LDS table (at most 256 partitions: plans needing more
+ * keep the atomics); a power of two sets the partition count (clamped to
+ * 256). Record regions take 2 x (rows x record bytes) of ws per plan, in
+ * plan order while the batch's records fit 32 GiB; later plans keep the
+ * atomics.
  *   d, n     1..65536 plans of one shape: the same number of dims, and for
  *            each dim the same key type and payload presence. Per-plan
- *            tuning (load factor, LDS group slots) is honoured; grid and
- *            chunk_tiles come from d[0].tuning. Dim tables are always read
- *            from HBM (no LDS copies, no compact sets).
+ *            tuning (load factor, LDS group slots, replicas, fanout) is
+ *            honoured; grid and chunk_tiles come from d[0].tuning. Dim
+ *            tables are always read from HBM (no LDS copies, no compact
+ *            sets).
  *   o        n outputs, as for rel_pipeline.
  *   ws       rel_pipeline_batch_ws(d, n) bytes.
  * The call builds the plans' kernel parameters and work lists on the host
@@ -466,7 +484,7 @@ rel_status rel_pipeline_batch(const rel_pipeline_desc* d, int n, const rel_outpu
                               size_t ws_bytes, void* stream);
 
 /* A batch captured once as a HIP graph (descriptor upload from pinned host
- * memory owned by the graph, then the six launches), for replay with one
+ * memory owned by the graph, then the batch's launches), for replay with one
  * hipGraphLaunch. Inputs, outputs and ws are bound at capture: they must
  * stay allocated, and their contents at each launch are the inputs. */
 typedef struct rel_graph rel_graph;
