@@ -769,8 +769,8 @@ uint64_t map_words(const MapLayout& m, int32_t key_type) {
 // end of the uploaded block).
 struct RecLayout {
   uint32_t parts = 0;  // 0: no records
-  uint32_t agg_parts = 0, words = 0, nitems = 0, agg_slots = 0;
-  size_t recs = 0, parted = 0, counts = 0, item_n = 0, part_begin = 0;
+  uint32_t agg_parts = 0, words = 0, nitems = 0, agg_slots = 0, narrow = 0;
+  size_t recs = 0, parted = 0, rkeys = 0, pkeys = 0, counts = 0, item_n = 0, part_begin = 0;
 };
 
 // Workspace bound of a batch's records: plans are given records in order
@@ -841,6 +841,14 @@ RecLayout rec_plan(const rel_pipeline_desc* d, const PipeLayout& L, int chunk_ti
   R.agg_parts = static_cast<uint32_t>(parts < 1 ? 1 : parts);
   R.parts = R.agg_parts < kMinRecParts ? kMinRecParts : R.agg_parts;
   R.words = 1 + ncols;
+  // 12-byte records when the packed key fits 32 bits and one value column
+  // is carried (see RecDesc)
+  const GroupKeyPack& kp = L.gp.kp;
+  auto bits = [](int32_t t) { return t == REL_I8 ? 8 : (t == REL_I32 ? 32 : 64); };
+  if (R.words == 2) {
+    if (kp.nkeys == 1 && bits(kp.type[0]) <= 32) R.narrow = 1;
+    else if (kp.nkeys == 2 && bits(kp.type[0]) + bits(kp.type[1]) <= 32) R.narrow = 2;
+  }
   R.nitems = static_cast<uint32_t>(ceil_div(ceil_div(n, kPipeTile), chunk_tiles));
   R.agg_slots = slots;
   return R;
@@ -866,11 +874,16 @@ struct RecPlanDesc {
   }
 };
 
-// Record bytes of R over n fact rows.
+// Record bytes of R over n fact rows: the fused pass's runs, the
+// partitioned copy (each as 64-bit words, or for narrow records value words
+// and 32-bit keys), the counts, the item sizes and the partition offsets.
 uint64_t rec_bytes(const RecLayout& R, uint64_t n, int chunk_tiles) {
   const uint64_t item_rows = static_cast<uint64_t>(chunk_tiles) * kPipeTile;
-  return align_up(R.nitems * item_rows * R.words * 8) + align_up(n * R.words * 8) +
-         align_up(static_cast<uint64_t>(R.parts) * R.nitems * 4) + align_up(R.nitems * 4ull) +
+  const uint64_t run = R.nitems * item_rows;
+  const uint64_t words = R.narrow ? 1 : R.words;
+  uint64_t b = align_up(run * words * 8) + align_up(n * words * 8);
+  if (R.narrow) b += align_up(run * 4) + align_up(n * 4);
+  return b + align_up(static_cast<uint64_t>(R.parts) * R.nitems * 4) + align_up(R.nitems * 4ull) +
          align_up((R.parts + 1) * 4ull);
 }
 
@@ -960,10 +973,17 @@ rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
     const uint64_t rows = static_cast<uint64_t>(d[i].fact[0].len);
     off = align_up(off);
     const uint64_t item_rows = static_cast<uint64_t>(B.chunk_tiles) * kPipeTile;
+    const uint64_t words = R.narrow ? 1 : R.words;
     R.recs = off;
-    off += align_up(R.nitems * item_rows * R.words * 8);
+    off += align_up(R.nitems * item_rows * words * 8);
     R.parted = off;
-    off += align_up(rows * R.words * 8);
+    off += align_up(rows * words * 8);
+    if (R.narrow) {
+      R.rkeys = off;
+      off += align_up(R.nitems * item_rows * 4);
+      R.pkeys = off;
+      off += align_up(rows * 4);
+    }
     R.counts = off;
     off += align_up(static_cast<uint64_t>(R.parts) * R.nitems * 4);
     R.item_n = off;
@@ -1166,6 +1186,11 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
     if (R.parts) {
       rd.recs = reinterpret_cast<uint64_t*>(tables + R.recs);
       rd.parted = reinterpret_cast<uint64_t*>(tables + R.parted);
+      if (R.narrow) {
+        rd.rkeys = reinterpret_cast<uint32_t*>(tables + R.rkeys);
+        rd.pkeys = reinterpret_cast<uint32_t*>(tables + R.pkeys);
+        rd.narrow = R.narrow;
+      }
       rd.counts = reinterpret_cast<uint32_t*>(tables + R.counts);
       rd.item_n = reinterpret_cast<uint32_t*>(tables + R.item_n);
       rd.part_begin = reinterpret_cast<uint32_t*>(tables + R.part_begin);

@@ -32,6 +32,12 @@ __device__ __forceinline__ uint32_t rec_part(uint64_t pk, uint32_t parts) {
   return static_cast<uint32_t>((static_cast<uint64_t>(lds_hash(pk)) * parts) >> 32);
 }
 
+// Packed key of a narrow record's 32 key bits (see RecDesc).
+__device__ __forceinline__ uint64_t narrow_key(uint32_t k, uint32_t narrow) {
+  return narrow == 1 ? static_cast<uint64_t>(static_cast<int64_t>(static_cast<int32_t>(k)))
+                     : static_cast<uint64_t>(k);
+}
+
 // Index of the LDS slot holding (or newly claimed for) packed key pk, or -1
 // when the key is the sentinel pattern, there is no LDS table, or no slot is
 // free within the probe window.

@@ -474,6 +474,14 @@ enum QueueField : int { kQRow = 0, kQFk0, kQFk1, kQSt0, kQSt1, kQueueFields };
 struct RecDesc {
   uint64_t* recs;         // item j's records start at word j * item_tiles * kPipeTile * words
   uint64_t* parted;       // the records in partition order
+  // Narrow records (narrow != 0, words == 2): the key's low 32 bits in their
+  // own arrays (rkeys beside recs, pkeys beside parted; recs and parted then
+  // hold the value word alone), 12 bytes a record; the packed key is the
+  // 32 bits sign-extended (narrow 1: one int8 or int32 key) or zero-extended
+  // (narrow 2: two keys of at most 32 bits together).
+  uint32_t* rkeys;
+  uint32_t* pkeys;
+  uint32_t narrow;
   uint32_t* counts;       // [parts][nitems] records per (partition, item), then their offsets
   uint32_t* item_n;       // records of each item
   uint32_t* part_begin;   // parts + 1 offsets into parted

@@ -585,6 +585,11 @@ __device__ __forceinline__ void spill_record(const PipelineParams& p, int64_t r,
   lds_fetch_add_u32(hist + rec_part(pk, rd.parts), 1u);
   const uint32_t tile = static_cast<uint32_t>(static_cast<uint64_t>(r) / kPipeTile);
   const uint64_t at = static_cast<uint64_t>(tile - tile % rd.item_tiles) * kPipeTile + base + rank;
+  if (rd.narrow) {
+    __builtin_nontemporal_store(static_cast<uint32_t>(pk), rd.rkeys + at);
+    __builtin_nontemporal_store(static_cast<uint64_t>(va), rd.recs + at);
+    return;
+  }
   uint64_t* w = rd.recs + at * rd.words;
   if (rd.words == 2) {
     typedef uint64_t v2u64 __attribute__((ext_vector_type(2)));

@@ -178,15 +178,77 @@ __global__ void __launch_bounds__(kRecScatterThreads) rec_scatter_kernel(BatchPa
   __syncthreads();
   const uint32_t words = p.rec.words;
   const uint64_t run = static_cast<uint64_t>(j) * p.rec.item_tiles * kPipeTile;
-  if (words == 2) {
-    // chunks of kScatterChunk records, sorted by partition in LDS and then
-    // written out in order, so that each partition's run of the chunk is
-    // stored by consecutive lanes
-    __shared__ v2u64 stage[kScatterChunk];
-    __shared__ uint32_t cnt[kMaxRecParts];   // chunk histogram, then its offsets
-    __shared__ uint32_t gbase[kMaxRecParts];  // place of stage[s] of partition q: gbase[q] + s
-    __shared__ uint32_t s_wave[kRecScatterThreads / kWave];
-    constexpr int kPer = kScatterChunk / kRecScatterThreads;
+  // chunks of kScatterChunk records, sorted by partition in LDS and then
+  // written out in order, so that each partition's run of the chunk is
+  // stored by consecutive lanes
+  __shared__ v2u64 stage[kScatterChunk];
+  __shared__ uint32_t cnt[kMaxRecParts];   // chunk histogram, then its offsets
+  __shared__ uint32_t gbase[kMaxRecParts];  // place of stage[s] of partition q: gbase[q] + s
+  __shared__ uint32_t s_wave[kRecScatterThreads / kWave];
+  constexpr int kPer = kScatterChunk / kRecScatterThreads;
+  if (p.rec.narrow) {
+    // narrow records: the keys staged in the first quarter of the buffer,
+    // the values in the second half
+    uint32_t* stage_k = reinterpret_cast<uint32_t*>(stage);
+    uint64_t* stage_v = reinterpret_cast<uint64_t*>(stage) + kScatterChunk;
+    const uint32_t narrow = p.rec.narrow;
+    const uint32_t* ksrc = p.rec.rkeys + run;
+    const uint64_t* vsrc = p.rec.recs + run;
+    uint32_t* kdst = p.rec.pkeys;
+    uint64_t* vdst = p.rec.parted;
+    for (uint32_t c0 = 0; c0 < n; c0 += kScatterChunk) {
+      const uint32_t m = n - c0 < kScatterChunk ? n - c0 : kScatterChunk;
+      for (uint32_t q = threadIdx.x; q < parts; q += blockDim.x) cnt[q] = 0;
+      uint32_t xk[kPer];
+      uint64_t xv[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const uint32_t i = u * blockDim.x + threadIdx.x;
+        if (i < m) {
+          xk[u] = __builtin_nontemporal_load(ksrc + c0 + i);
+          xv[u] = __builtin_nontemporal_load(vsrc + c0 + i);
+        }
+      }
+      __syncthreads();
+      uint32_t qq[kPer], rank[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const uint32_t i = u * blockDim.x + threadIdx.x;
+        if (i < m) {
+          qq[u] = rec_part(narrow_key(xk[u], narrow), parts);
+          rank[u] = lds_fetch_add_u32(cnt + qq[u], 1u);
+        }
+      }
+      __syncthreads();
+      const uint32_t c = threadIdx.x < parts ? cnt[threadIdx.x] : 0u;
+      uint32_t total = 0;
+      const uint32_t off = block_exclusive(c, s_wave, total);
+      if (threadIdx.x < parts) {
+        const uint32_t at = cur[threadIdx.x];
+        cur[threadIdx.x] = at + c;
+        gbase[threadIdx.x] = at - off;  // modulo 2^32: at + (s - off) for s >= off
+        cnt[threadIdx.x] = off;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const uint32_t i = u * blockDim.x + threadIdx.x;
+        if (i < m) {
+          const uint32_t at = cnt[qq[u]] + rank[u];
+          stage_k[at] = xk[u];
+          stage_v[at] = xv[u];
+        }
+      }
+      __syncthreads();
+      for (uint32_t s2 = threadIdx.x; s2 < m; s2 += blockDim.x) {
+        const uint32_t k = stage_k[s2];
+        const uint32_t at = gbase[rec_part(narrow_key(k, narrow), parts)] + s2;
+        kdst[at] = k;
+        vdst[at] = stage_v[s2];
+      }
+      __syncthreads();
+    }
+  } else if (words == 2) {
     const v2u64* src = reinterpret_cast<const v2u64*>(p.rec.recs) + run;
     v2u64* dst = reinterpret_cast<v2u64*>(p.rec.parted);
     for (uint32_t c0 = 0; c0 < n; c0 += kScatterChunk) {
@@ -302,7 +364,45 @@ __global__ void __launch_bounds__(kRecAggThreads) rec_agg_kernel(BatchParams b) 
     const uint32_t acode = pipe::acc_code(p);
     const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
     const uint32_t rw = p.rec.words;
-    if (rw == 2) {
+    if (p.rec.narrow) {
+      // the next step's records are loaded while this step's are folded
+      const uint32_t narrow = p.rec.narrow;
+      const uint32_t* ks = p.rec.pkeys;
+      const uint64_t* vs = p.rec.parted;
+      const uint32_t step = kRecUnroll * blockDim.x;
+      uint32_t xk[kRecUnroll], yk[kRecUnroll];
+      uint64_t xv[kRecUnroll], yv[kRecUnroll];
+      uint32_t i0 = pc.begin + threadIdx.x;
+#pragma unroll
+      for (int u = 0; u < kRecUnroll; ++u) {
+        const uint32_t i = i0 + u * blockDim.x;
+        if (i < pc.end) {
+          xk[u] = __builtin_nontemporal_load(ks + i);
+          xv[u] = __builtin_nontemporal_load(vs + i);
+        }
+      }
+      for (; i0 < pc.end; i0 += step) {
+        const uint32_t i1 = i0 + step;
+#pragma unroll
+        for (int u = 0; u < kRecUnroll; ++u) {
+          const uint32_t i = i1 + u * blockDim.x;
+          if (i < pc.end) {
+            yk[u] = __builtin_nontemporal_load(ks + i);
+            yv[u] = __builtin_nontemporal_load(vs + i);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kRecUnroll; ++u)
+          if (i0 + u * blockDim.x < pc.end)
+            rec_update(p, narrow_key(xk[u], narrow), static_cast<int64_t>(xv[u]), 0, lt, slots,
+                       words, gt, acode);
+#pragma unroll
+        for (int u = 0; u < kRecUnroll; ++u) {
+          xk[u] = yk[u];
+          xv[u] = yv[u];
+        }
+      }
+    } else if (rw == 2) {
       // the next step's records are loaded while this step's are folded
       const v2u64* src = reinterpret_cast<const v2u64*>(p.rec.parted);
       const uint32_t step = kRecUnroll * blockDim.x;

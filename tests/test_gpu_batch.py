@@ -339,18 +339,26 @@ def record_specs(seed):
     from 3k to 150k, Zipf-skewed groups, records of one, two and three words
     (COUNT only; one value column; two value columns), a plan with three
     value columns (no records: its spilled rows use atomics), a plan whose
-    probes all miss, and one with no probe rows."""
+    probes all miss, one with no probe rows, and two int8 group keys (a dim
+    attribute and a fact column, negative values included) whose packed key
+    takes 16 bits."""
     r = np.random.default_rng(seed)
     specs = []
 
-    def plan(n_build, n_probe, groups, aggs, grp=None, miss=False, ncols=1):
+    def plan(n_build, n_probe, groups, aggs, grp=None, miss=False, ncols=1, int8_keys=False):
         keys = r.permutation(n_build).astype(np.int32)
         if grp is None:
             grp = r.integers(0, groups, size=n_build).astype(np.int32)
         lo = n_build + 10 if miss else 0
         pk = r.integers(lo, lo + int(n_build * 1.1) + 1, size=n_probe).astype(np.int32)
         vals = [r.integers(-10**6, 10**6, size=n_probe).astype(np.int64) for _ in range(ncols)]
-        specs.append(([pk] + vals, [], [dict(fk=0, key=keys, payload=grp)], [("dim", 0)], aggs,
+        group_keys = [("dim", 0)]
+        fact = [pk] + vals
+        if int8_keys:
+            grp = r.integers(-128, 128, size=n_build).astype(np.int8)
+            fact.append(r.integers(-128, 128, size=n_probe).astype(np.int8))
+            group_keys = [("dim", 0), ("fact", len(fact) - 1)]
+        specs.append((fact, [], [dict(fk=0, key=keys, payload=grp)], group_keys, aggs,
                       max(1, groups)))
 
     plan(200_000, 300_000, 3_000, AGGS)
@@ -363,6 +371,7 @@ def record_specs(seed):
     plan(100_000, 150_000, 30_000, [("sum", 1), ("min", 2), ("max", 3)], ncols=3)
     plan(50_000, 100_000, 10_000, AGGS, miss=True)
     plan(50_000, 0, 10_000, AGGS)
+    plan(200_000, 400_000, 65_536, AGGS, int8_keys=True)
     return specs
 
 
