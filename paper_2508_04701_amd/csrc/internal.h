@@ -499,7 +499,7 @@ constexpr uint32_t kMaxRecParts = 256;
 // At least this many partitions in the fused pass and the scatter, so that
 // the lanes of a wave rarely count into the same LDS word.
 constexpr uint32_t kMinRecParts = 16;
-constexpr uint32_t kRecPiece = 1u << 18;  // records per aggregation work item
+constexpr uint32_t kRecPiece = 1u << 17;  // records per aggregation work item
 constexpr uint32_t kRecAggLds = 65536;     // bound on the aggregation pass's LDS table
 
 struct PipelineParams {
