@@ -753,7 +753,10 @@ uint32_t direct_slice_bits() {
   return static_cast<uint32_t>(bits);
 }
 constexpr uint64_t kSlotChunk = 16384;   // group slots (a multiple of the finalize chunk, 2048)
-constexpr int kMaxChunkTiles = 8;
+#ifndef REL_MAXCHUNK
+#define REL_MAXCHUNK 32
+#endif
+constexpr int kMaxChunkTiles = REL_MAXCHUNK;
 constexpr int kMaxBatch = 1 << 16;
 
 uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }

@@ -1466,6 +1466,43 @@ hipError_t launch_fused(const PipelineParams& p, int grid, hipStream_t s) {
 }
 
 // ------------------------------------------------------------ batched plans
+
+// Rows in place: with no predicate every row of a tile is processed, so the
+// row queue's compaction buys nothing. Each thread takes its own four rows
+// of a tile and issues their value loads and payload reads together before
+// any update, one memory round trip per tile instead of one per queued
+// 64-row batch. For batched plans whose one dim resolved to a direct table.
+template <int D0>
+__device__ __forceinline__ void inplace_tiles(const PipelineParams& p, int64_t tile, int64_t end,
+                                              uint64_t* lg, const GroupTable& gt) {
+  const DirectView dv0 = dim_direct<D0>(p.dim[0]);
+  const uint32_t acode = acc_code(p);
+  const int64_t n = p.n;
+  const int nkeys = p.g.kp.nkeys;
+  const bool fkey0 = nkeys > 0 && p.key_src[0] == 0;
+  const bool fkey1 = nkeys > 1 && p.key_src[1] == 0;
+  for (; tile < end; ++tile) {
+    const int64_t r0 = tile * static_cast<int64_t>(kPipeTile) + threadIdx.x * 4;
+    typename KeyOf<D0>::T fk[4];
+    load_keys4<D0>(p, p.dim[0].fk_col, r0, fk);
+    int64_t va[4] = {0, 0, 0, 0}, vb[4] = {0, 0, 0, 0}, f0[4] = {0, 0, 0, 0}, f1[4] = {0, 0, 0, 0};
+    if (p.early_col[0] >= 0) load_col4(p, p.early_col[0], r0, va);
+    if (p.early_col[1] >= 0) load_col4(p, p.early_col[1], r0, vb);
+    if (fkey0) load_col4(p, p.key_col[0], r0, f0);
+    if (fkey1) load_col4(p, p.key_col[1], r0, f1);
+    uint32_t v0[4] = {0, 0, 0, 0};
+    bool ok[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ok[e] = r0 + e < n && direct_probe(dv0, fk[e], v0[e]);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (!ok[e]) continue;
+      const int64_t k0 = fkey0 ? f0[e] : static_cast<int32_t>(v0[e]);
+      const int64_t k1 = fkey1 ? f1[e] : static_cast<int32_t>(v0[e]);
+      update_group<true>(p, r0 + e, pack_keys(p.g.kp, k0, k1), va[e], vb[e], lg, gt, acode);
+    }
+  }
+}
 //
 // Persistent workgroups take (instance, tile range) items from the batch's
 // device counter and walk the tiles of that instance's plan exactly as the
@@ -1499,8 +1536,16 @@ __attribute__((amdgpu_waves_per_eu(kBatchWaves<D0, D1>))) batch_fused_kernel(Bat
       for (uint32_t q = threadIdx.x; q <= parts; q += blockDim.x) hist[q] = 0;
     __syncthreads();
     const GroupTable gt = group_replica(p.g, blockIdx.x % p.g.replicas);
-    run_tiles<D0, D1, false, 0, true>(p, it.begin, it.end, 1, wq, lane, nullptr, nullptr, lg, gt,
-                                      match_limit<D0>(p.dim[0]), match_limit<D1>(p.dim[1]));
+    bool done = false;
+    if constexpr (D1 == kNone && kDirectable<D0>) {
+      if (p.nterms == 0 && dim_direct<D0>(p.dim[0]).mode) {
+        inplace_tiles<D0>(p, it.begin, it.end, lg, gt);
+        done = true;
+      }
+    }
+    if (!done)
+      run_tiles<D0, D1, false, 0, true>(p, it.begin, it.end, 1, wq, lane, nullptr, nullptr, lg,
+                                        gt, match_limit<D0>(p.dim[0]), match_limit<D1>(p.dim[1]));
     __syncthreads();
     if (p.lds_slots > 0 || parts) {
       if (p.lds_slots > 0) lds_group_flush(lg, p.lds_slots, p.g);
