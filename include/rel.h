@@ -455,15 +455,15 @@ size_t rel_pipeline_batch_ws(const rel_pipeline_desc* d, int n);
  * not fit the fused pass's LDS table at half load (or would need a table
  * over 64 KB), whose aggregates read at most two value columns and whose
  * fact table has at most 2^31 rows writes each row that finds no LDS slot
- * as a 16-to-24-byte record rather than updating the global table with
+ * as a record of 12 to 24 bytes rather than updating the global table with
  * device-scope atomics; the records are grouped by partition of the key
  * hash and folded, partition by partition, in LDS, then merged into the
  * global table once per key. Such a plan runs its fused pass without an
  * LDS table (unless tuning.lds_slots sets one) and with one global table.
  * tuning.fanout: -1 keeps the atomics; 0 sizes the partitions for the
- * aggregation pass's LDS table (at most 256 partitions: plans needing more
+ * aggregation pass's LDS table (at most 1024 partitions: plans needing more
  * keep the atomics); a power of two sets the partition count (clamped to
- * 256). Record regions take 2 x (rows x record bytes) of ws per plan, in
+ * 1024). Record regions take 2 x (rows x record bytes) of ws per plan, in
  * plan order while the batch's records fit 32 GiB; later plans keep the
  * atomics.
  *   d, n     1..65536 plans of one shape: the same number of dims, and for

@@ -495,7 +495,7 @@ struct RecDesc {
   uint32_t agg_slots;     // LDS table slots of the aggregation pass (a power of two)
 };
 
-constexpr uint32_t kMaxRecParts = 256;
+constexpr uint32_t kMaxRecParts = 1024;
 // At least this many partitions in the fused pass and the scatter, so that
 // the lanes of a wave rarely count into the same LDS word.
 constexpr uint32_t kMinRecParts = 16;

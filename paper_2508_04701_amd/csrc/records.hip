@@ -25,6 +25,8 @@
 // The aggregates are exact integer sums, minima and maxima, so the record
 // order does not change the results.
 
+#include <type_traits>
+
 #include "pipeline_kernel.h"
 
 namespace rel {
@@ -39,9 +41,7 @@ constexpr int kRecProbe = 32;  // LDS probe window of the aggregation table
 // chunk is one contiguous store run (on the 256-instance batch: 1024 records
 // 7.7 ms of record passes, 2048 7.2, 4096 6.7, 8192 6.7).
 constexpr uint32_t kScatterChunk = 4096;
-static_assert(kScatterChunk % kRecScatterThreads == 0, "whole records per thread");
-static_assert(kMaxRecParts <= kRecScatterThreads, "one partition per thread in the scatter's offsets");
-static_assert(kMaxRecParts <= 256, "partition numbers fit a byte");
+static_assert(kMaxRecParts <= 65536, "partition numbers fit 16 bits");
 constexpr int kRecUnroll = 4;  // records per thread and step of the aggregation
 
 typedef uint64_t v2u64 __attribute__((ext_vector_type(2)));
@@ -167,8 +167,140 @@ __global__ void __launch_bounds__(kRecScanThreads) rec_scan_kernel(BatchParams b
   }
 }
 
+// Record forms the scatter moves: narrow (32-bit key and value word in two
+// arrays) and two-word (key and value word side by side).
+struct NarrowRecs {
+  static constexpr uint32_t kChunk = kScatterChunk;
+  uint32_t k;
+  uint64_t v;
+};
+struct WideRecs {
+  static constexpr uint32_t kChunk = kScatterChunk * 3 / 4;  // 16 bytes a record
+  v2u64 x;
+};
+
+// LDS of the scatter: the staged chunk (48 KB: narrow keys then values, or
+// two-word records), each staged record's partition, the partitions' running
+// places and a chunk's histogram, offsets and write bases.
+struct ScatterLds {
+  uint64_t stage[kScatterChunk * 3 / 2];
+  uint16_t part[kScatterChunk];
+  uint32_t cur[kMaxRecParts];
+  uint32_t cnt[kMaxRecParts];
+  uint32_t wave[kRecScatterThreads / kWave];
+};
+
+// Records [0, n) of one item run (src), scattered to their partitions' places
+// (dst) a chunk at a time: a histogram over the chunk, its offsets, the
+// records placed in LDS in partition order, then written out in that order so
+// that each partition's share of the chunk is stored by consecutive lanes.
+// Each thread owns partitions [tid * per, tid * per + per) of the offsets.
+template <typename R>
+__device__ __forceinline__ void scatter_chunks(ScatterLds& L, const RecDesc& rd, uint64_t run,
+                                               uint32_t n) {
+  constexpr uint32_t kC = R::kChunk;
+  constexpr int kPer = kC / kRecScatterThreads;
+  static_assert(kC % kRecScatterThreads == 0, "whole records per thread");
+  const uint32_t parts = rd.parts;
+  const uint32_t narrow = rd.narrow;
+  const uint32_t per = (parts + kRecScatterThreads - 1) / kRecScatterThreads;
+  constexpr uint32_t kMaxPer = (kMaxRecParts + kRecScatterThreads - 1) / kRecScatterThreads;
+  const uint32_t q_lo = threadIdx.x * per;
+  uint32_t* stage_k = reinterpret_cast<uint32_t*>(L.stage);
+  uint64_t* stage_v = L.stage + kC / 2;
+  v2u64* stage_x = reinterpret_cast<v2u64*>(L.stage);
+  for (uint32_t c0 = 0; c0 < n; c0 += kC) {
+    const uint32_t m = n - c0 < kC ? n - c0 : kC;
+    for (uint32_t q = threadIdx.x; q < parts; q += blockDim.x) L.cnt[q] = 0;
+    R x[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const uint32_t i = u * blockDim.x + threadIdx.x;
+      if (i < m) {
+        if constexpr (std::is_same_v<R, NarrowRecs>) {
+          x[u].k = __builtin_nontemporal_load(rd.rkeys + run + c0 + i);
+          x[u].v = __builtin_nontemporal_load(rd.recs + run + c0 + i);
+        } else {
+          x[u].x = __builtin_nontemporal_load(reinterpret_cast<const v2u64*>(rd.recs) + run + c0 + i);
+        }
+      }
+    }
+    __syncthreads();
+    uint32_t qq[kPer], rank[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const uint32_t i = u * blockDim.x + threadIdx.x;
+      if (i < m) {
+        uint64_t pk;
+        if constexpr (std::is_same_v<R, NarrowRecs>) pk = narrow_key(x[u].k, narrow);
+        else pk = x[u].x.x;
+        qq[u] = rec_part(pk, parts);
+        rank[u] = lds_fetch_add_u32(L.cnt + qq[u], 1u);
+      }
+    }
+    __syncthreads();
+    // offsets over the partitions, and each partition's write base
+    uint32_t c[kMaxPer], sum = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < kMaxPer; ++e) {
+      const uint32_t q = q_lo + e;
+      c[e] = (e < per && q < parts) ? L.cnt[q] : 0u;
+      sum += c[e];
+    }
+    uint32_t total = 0;
+    uint32_t off = block_exclusive(sum, L.wave, total);
+    uint32_t base[kMaxPer];
+#pragma unroll
+    for (uint32_t e = 0; e < kMaxPer; ++e) {
+      const uint32_t q = q_lo + e;
+      base[e] = 0;
+      if (e < per && q < parts) {
+        const uint32_t at = L.cur[q];
+        L.cur[q] = at + c[e];
+        base[e] = at - off;  // modulo 2^32: at + (s - off) for s >= off
+        L.cnt[q] = off;
+        off += c[e];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const uint32_t i = u * blockDim.x + threadIdx.x;
+      if (i < m) {
+        const uint32_t at = L.cnt[qq[u]] + rank[u];
+        if constexpr (std::is_same_v<R, NarrowRecs>) {
+          stage_k[at] = x[u].k;
+          stage_v[at] = x[u].v;
+        } else {
+          stage_x[at] = x[u].x;
+        }
+        L.part[at] = static_cast<uint16_t>(qq[u]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t e = 0; e < kMaxPer; ++e) {
+      const uint32_t q = q_lo + e;
+      if (e < per && q < parts) L.cnt[q] = base[e];
+    }
+    __syncthreads();
+    // plain stores: a partition's run fills its lines from several chunks,
+    // which L2 merges before they reach HBM
+    for (uint32_t s2 = threadIdx.x; s2 < m; s2 += blockDim.x) {
+      const uint32_t at = L.cnt[L.part[s2]] + s2;
+      if constexpr (std::is_same_v<R, NarrowRecs>) {
+        rd.pkeys[at] = stage_k[s2];
+        rd.parted[at] = stage_v[s2];
+      } else {
+        reinterpret_cast<v2u64*>(rd.parted)[at] = stage_x[s2];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void __launch_bounds__(kRecScatterThreads) rec_scatter_kernel(BatchParams b) {
-  __shared__ uint32_t cur[kMaxRecParts];
+  __shared__ __attribute__((aligned(16))) ScatterLds L;
   const BatchItem& it = batch_at(b.tile_items, blockIdx.x);
   const PipelineParams& p = batch_at(b.plans, it.inst);
   const uint32_t parts = p.rec.parts;
@@ -178,136 +310,21 @@ __global__ void __launch_bounds__(kRecScatterThreads) rec_scatter_kernel(BatchPa
   if (n == 0) return;
   const uint32_t nitems = p.rec.nitems;
   for (uint32_t q = threadIdx.x; q < parts; q += blockDim.x)
-    cur[q] = p.rec.counts[static_cast<uint64_t>(q) * nitems + j];
+    L.cur[q] = p.rec.counts[static_cast<uint64_t>(q) * nitems + j];
   __syncthreads();
   const uint32_t words = p.rec.words;
   const uint64_t run = static_cast<uint64_t>(j) * p.rec.item_tiles * kPipeTile;
-  // chunks of kScatterChunk records, sorted by partition in LDS and then
-  // written out in order, so that each partition's run of the chunk is
-  // stored by consecutive lanes
-  __shared__ v2u64 stage[kScatterChunk];
-  __shared__ uint32_t cnt[kMaxRecParts];   // chunk histogram, then its offsets
-  __shared__ uint32_t gbase[kMaxRecParts];  // place of stage[s] of partition q: gbase[q] + s
-  __shared__ uint32_t s_wave[kRecScatterThreads / kWave];
-  __shared__ uint8_t stage_q[kScatterChunk];  // partition of stage[s] (parts <= 256)
-  constexpr int kPer = kScatterChunk / kRecScatterThreads;
   if (p.rec.narrow) {
-    // narrow records: the keys staged in the first quarter of the buffer,
-    // the values in the second half
-    uint32_t* stage_k = reinterpret_cast<uint32_t*>(stage);
-    uint64_t* stage_v = reinterpret_cast<uint64_t*>(stage) + kScatterChunk;
-    const uint32_t narrow = p.rec.narrow;
-    const uint32_t* ksrc = p.rec.rkeys + run;
-    const uint64_t* vsrc = p.rec.recs + run;
-    uint32_t* kdst = p.rec.pkeys;
-    uint64_t* vdst = p.rec.parted;
-    for (uint32_t c0 = 0; c0 < n; c0 += kScatterChunk) {
-      const uint32_t m = n - c0 < kScatterChunk ? n - c0 : kScatterChunk;
-      for (uint32_t q = threadIdx.x; q < parts; q += blockDim.x) cnt[q] = 0;
-      uint32_t xk[kPer];
-      uint64_t xv[kPer];
-#pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const uint32_t i = u * blockDim.x + threadIdx.x;
-        if (i < m) {
-          xk[u] = __builtin_nontemporal_load(ksrc + c0 + i);
-          xv[u] = __builtin_nontemporal_load(vsrc + c0 + i);
-        }
-      }
-      __syncthreads();
-      uint32_t qq[kPer], rank[kPer];
-#pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const uint32_t i = u * blockDim.x + threadIdx.x;
-        if (i < m) {
-          qq[u] = rec_part(narrow_key(xk[u], narrow), parts);
-          rank[u] = lds_fetch_add_u32(cnt + qq[u], 1u);
-        }
-      }
-      __syncthreads();
-      const uint32_t c = threadIdx.x < parts ? cnt[threadIdx.x] : 0u;
-      uint32_t total = 0;
-      const uint32_t off = block_exclusive(c, s_wave, total);
-      if (threadIdx.x < parts) {
-        const uint32_t at = cur[threadIdx.x];
-        cur[threadIdx.x] = at + c;
-        gbase[threadIdx.x] = at - off;  // modulo 2^32: at + (s - off) for s >= off
-        cnt[threadIdx.x] = off;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const uint32_t i = u * blockDim.x + threadIdx.x;
-        if (i < m) {
-          const uint32_t at = cnt[qq[u]] + rank[u];
-          stage_k[at] = xk[u];
-          stage_v[at] = xv[u];
-          stage_q[at] = static_cast<uint8_t>(qq[u]);
-        }
-      }
-      __syncthreads();
-      for (uint32_t s2 = threadIdx.x; s2 < m; s2 += blockDim.x) {
-        const uint32_t at = gbase[stage_q[s2]] + s2;
-        kdst[at] = stage_k[s2];
-        vdst[at] = stage_v[s2];
-      }
-      __syncthreads();
-    }
+    scatter_chunks<NarrowRecs>(L, p.rec, run, n);
   } else if (words == 2) {
-    const v2u64* src = reinterpret_cast<const v2u64*>(p.rec.recs) + run;
-    v2u64* dst = reinterpret_cast<v2u64*>(p.rec.parted);
-    for (uint32_t c0 = 0; c0 < n; c0 += kScatterChunk) {
-      const uint32_t m = n - c0 < kScatterChunk ? n - c0 : kScatterChunk;
-      for (uint32_t q = threadIdx.x; q < parts; q += blockDim.x) cnt[q] = 0;
-      v2u64 x[kPer];
-#pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const uint32_t i = u * blockDim.x + threadIdx.x;
-        if (i < m) x[u] = __builtin_nontemporal_load(src + c0 + i);
-      }
-      __syncthreads();
-      uint32_t qq[kPer], rank[kPer];
-#pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const uint32_t i = u * blockDim.x + threadIdx.x;
-        if (i < m) {
-          qq[u] = rec_part(x[u].x, parts);
-          rank[u] = lds_fetch_add_u32(cnt + qq[u], 1u);
-        }
-      }
-      __syncthreads();
-      const uint32_t c = threadIdx.x < parts ? cnt[threadIdx.x] : 0u;
-      uint32_t total = 0;
-      const uint32_t off = block_exclusive(c, s_wave, total);
-      if (threadIdx.x < parts) {
-        const uint32_t at = cur[threadIdx.x];
-        cur[threadIdx.x] = at + c;
-        gbase[threadIdx.x] = at - off;  // modulo 2^32: at + (s - off) for s >= off
-        cnt[threadIdx.x] = off;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const uint32_t i = u * blockDim.x + threadIdx.x;
-        if (i < m) {
-          const uint32_t at = cnt[qq[u]] + rank[u];
-          stage[at] = x[u];
-          stage_q[at] = static_cast<uint8_t>(qq[u]);
-        }
-      }
-      __syncthreads();
-      for (uint32_t s2 = threadIdx.x; s2 < m; s2 += blockDim.x) {
-        dst[gbase[stage_q[s2]] + s2] = stage[s2];
-      }
-      __syncthreads();
-    }
+    scatter_chunks<WideRecs>(L, p.rec, run, n);
   } else {
     const uint64_t* src = p.rec.recs + run * words;
     uint64_t* dst = p.rec.parted;
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
       const uint64_t* x = src + static_cast<uint64_t>(i) * words;
       const uint64_t pk = x[0];
-      const uint32_t at = lds_fetch_add_u32(cur + rec_part(pk, parts), 1u);
+      const uint32_t at = lds_fetch_add_u32(L.cur + rec_part(pk, parts), 1u);
       uint64_t* y = dst + static_cast<uint64_t>(at) * words;
       y[0] = pk;
       for (uint32_t w = 1; w < words; ++w) y[w] = x[w];

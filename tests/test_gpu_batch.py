@@ -336,12 +336,12 @@ def test_batch_direct_tables_built_in_slices_and_parts():
 def record_specs(seed):
     """Join + group-by plans whose groups outgrow the fused pass's LDS table,
     so that their spilled rows go through the record passes: uniform groups
-    from 3k to 150k, Zipf-skewed groups, records of one, two and three words
+    from 3k to 600k, Zipf-skewed groups, records of one, two and three words
     (COUNT only; one value column; two value columns), a plan with three
     value columns (no records: its spilled rows use atomics), a plan whose
-    probes all miss, one with no probe rows, and two int8 group keys (a dim
+    probes all miss, one with no probe rows, two int8 group keys (a dim
     attribute and a fact column, negative values included) whose packed key
-    takes 16 bits."""
+    takes 16 bits, and 600k groups over 1024 partitions."""
     r = np.random.default_rng(seed)
     specs = []
 
@@ -364,6 +364,7 @@ def record_specs(seed):
     plan(200_000, 300_000, 3_000, AGGS)
     plan(400_000, 500_001, 40_000, AGGS)
     plan(600_000, 700_000, 150_000, [("sum", 1), ("count", None)])
+    plan(1_000_000, 1_200_000, 600_000, [("sum", 1), ("count", None)])  # 1024 partitions
     zipf = (datagen.zipf_ranks(seed, 9, 60_000, 1.1, 300_000) - 1).astype(np.int32)
     plan(300_000, 400_000, 60_000, AGGS, grp=zipf)
     plan(100_000, 200_000, 20_000, [("count", None)])
