@@ -812,8 +812,9 @@ constexpr uint64_t kRecTableBytes = 65536;
 // at most two value columns (gathered with the probes), its group count
 // needs at most kMaxRecParts partitions of an aggregation table and
 // tuning.fanout is not -1. The aggregation table holds as many slots as fit
-// kRecAggLds; an aggregation partition is sized for half of them (fanout > 0
-// sets their count, clamped to [1, kMaxRecParts]). The fused pass and the
+// kRecAggLds; an aggregation partition is sized for half of them, at most
+// kAutoRecParts of them (fanout > 0 sets their count, clamped to [1,
+// kMaxRecParts]). The fused pass and the
 // scatter split each into partitions of their own up to kMinRecParts.
 RecLayout rec_plan(const rel_pipeline_desc* d, const PipeLayout& L, int chunk_tiles) {
   RecLayout R;
@@ -839,7 +840,7 @@ RecLayout rec_plan(const rel_pipeline_desc* d, const PipeLayout& L, int chunk_ti
     parts = static_cast<uint64_t>(fan) > kMaxRecParts ? kMaxRecParts : static_cast<uint64_t>(fan);
   } else {
     parts = next_pow2(ceil_div(2 * static_cast<uint64_t>(d->max_groups), slots));
-    if (parts > kMaxRecParts) return R;
+    if (parts > kAutoRecParts) return R;
   }
   R.agg_parts = static_cast<uint32_t>(parts < 1 ? 1 : parts);
   R.parts = R.agg_parts < kMinRecParts ? kMinRecParts : R.agg_parts;

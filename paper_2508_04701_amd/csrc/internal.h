@@ -495,12 +495,13 @@ struct RecDesc {
   uint32_t agg_slots;     // LDS table slots of the aggregation pass (a power of two)
 };
 
-// Plans needing more partitions keep the atomics: with 1024 partitions over
-// 200M fact rows the count array holds 3.1M entries, and its one-workgroup
-// scan alone took 3.6 ms (a served 1M-group query at 1% selectivity: 4.9 ms
-// with records, 1.1 ms with atomics). The scatter and the scan handle up to
-// 1024.
-constexpr uint32_t kMaxRecParts = 256;
+constexpr uint32_t kMaxRecParts = 1024;
+// Bound on the partitions a plan takes by default (tuning.fanout may ask for
+// up to kMaxRecParts); plans needing more keep the atomics: with 1024
+// partitions over 200M fact rows the count array holds 3.1M entries, and its
+// one-workgroup scan alone took 3.6 ms (a served 1M-group query at 1%
+// selectivity: 4.9 ms with records, 1.1 ms with atomics).
+constexpr uint32_t kAutoRecParts = 256;
 // At least this many partitions in the fused pass and the scatter, so that
 // the lanes of a wave rarely count into the same LDS word.
 constexpr uint32_t kMinRecParts = 16;

@@ -341,7 +341,8 @@ def record_specs(seed):
     value columns (no records: its spilled rows use atomics), a plan whose
     probes all miss, one with no probe rows, two int8 group keys (a dim
     attribute and a fact column, negative values included) whose packed key
-    takes 16 bits, and 600k groups over 1024 partitions."""
+    takes 16 bits, and 600k groups (more partitions than records take by
+    default: atomics, unless the tuning asks for 1024)."""
     r = np.random.default_rng(seed)
     specs = []
 
@@ -364,7 +365,7 @@ def record_specs(seed):
     plan(200_000, 300_000, 3_000, AGGS)
     plan(400_000, 500_001, 40_000, AGGS)
     plan(600_000, 700_000, 150_000, [("sum", 1), ("count", None)])
-    plan(1_000_000, 1_200_000, 600_000, [("sum", 1), ("count", None)])  # 1024 partitions
+    plan(1_000_000, 1_200_000, 600_000, [("sum", 1), ("count", None)])  # beyond 256 partitions
     zipf = (datagen.zipf_ranks(seed, 9, 60_000, 1.1, 300_000) - 1).astype(np.int32)
     plan(300_000, 400_000, 60_000, AGGS, grp=zipf)
     plan(100_000, 200_000, 20_000, [("count", None)])
@@ -383,13 +384,14 @@ def run_tuned(specs, tunings):
     return b
 
 
-@pytest.mark.parametrize("fanout", [0, 4, -1])
+@pytest.mark.parametrize("fanout", [0, 4, 1024, -1])
 def test_batch_spilled_rows_as_records(fanout):
     """Rows that find no LDS group slot become records, grouped by partition
     and folded per partition in LDS (fanout 0: partitions sized for the
     aggregation table; 4: far fewer, so most keys of a partition miss its
-    LDS table and update the global table directly; -1: no records, device
-    atomics): every plan equals the oracle."""
+    LDS table and update the global table directly; 1024: the most, several
+    per scatter thread; -1: no records, device atomics): every plan equals
+    the oracle."""
     announce("batch records", fanout)
     specs = record_specs(1212)
     t = rel.tuning(fanout=fanout)
