@@ -461,7 +461,7 @@ size_t rel_pipeline_batch_ws(const rel_pipeline_desc* d, int n);
  * global table once per key. Such a plan runs its fused pass without an
  * LDS table (unless tuning.lds_slots sets one) and with one global table.
  * tuning.fanout: -1 keeps the atomics; 0 sizes the partitions for the
- * aggregation pass's LDS table (at most 256 partitions: plans needing more
+ * aggregation pass's LDS table (at most 1024 partitions: plans needing more
  * keep the atomics); a power of two sets the partition count (clamped to
  * 1024). Record regions take 2 x (rows x record bytes) of ws per plan, in
  * plan order while the batch's records fit 32 GiB; later plans keep the

@@ -774,6 +774,7 @@ struct RecLayout {
   uint32_t parts = 0;  // 0: no records
   uint32_t agg_parts = 0, words = 0, nitems = 0, agg_slots = 0, narrow = 0;
   size_t recs = 0, parted = 0, rkeys = 0, pkeys = 0, counts = 0, item_n = 0, part_begin = 0;
+  size_t cursor = 0;
 };
 
 // Workspace bound of a batch's records: plans are given records in order
@@ -812,9 +813,8 @@ constexpr uint64_t kRecTableBytes = 65536;
 // at most two value columns (gathered with the probes), its group count
 // needs at most kMaxRecParts partitions of an aggregation table and
 // tuning.fanout is not -1. The aggregation table holds as many slots as fit
-// kRecAggLds; an aggregation partition is sized for half of them, at most
-// kAutoRecParts of them (fanout > 0 sets their count, clamped to [1,
-// kMaxRecParts]). The fused pass and the
+// kRecAggLds; an aggregation partition is sized for half of them (fanout > 0
+// sets their count, clamped to [1, kMaxRecParts]). The fused pass and the
 // scatter split each into partitions of their own up to kMinRecParts.
 RecLayout rec_plan(const rel_pipeline_desc* d, const PipeLayout& L, int chunk_tiles) {
   RecLayout R;
@@ -840,7 +840,7 @@ RecLayout rec_plan(const rel_pipeline_desc* d, const PipeLayout& L, int chunk_ti
     parts = static_cast<uint64_t>(fan) > kMaxRecParts ? kMaxRecParts : static_cast<uint64_t>(fan);
   } else {
     parts = next_pow2(ceil_div(2 * static_cast<uint64_t>(d->max_groups), slots));
-    if (parts > kAutoRecParts) return R;
+    if (parts > kMaxRecParts) return R;
   }
   R.agg_parts = static_cast<uint32_t>(parts < 1 ? 1 : parts);
   R.parts = R.agg_parts < kMinRecParts ? kMinRecParts : R.agg_parts;
@@ -888,7 +888,7 @@ uint64_t rec_bytes(const RecLayout& R, uint64_t n, int chunk_tiles) {
   uint64_t b = align_up(run * words * 8) + align_up(n * words * 8);
   if (R.narrow) b += align_up(run * 4) + align_up(n * 4);
   return b + align_up(static_cast<uint64_t>(R.parts) * R.nitems * 4) + align_up(R.nitems * 4ull) +
-         align_up((R.parts + 1) * 4ull);
+         align_up((R.parts + 1) * 4ull) + align_up(R.parts * 4ull);
 }
 
 // Instances of one batch must share the kernel variant: the same number of
@@ -944,6 +944,7 @@ rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
       if (rec_total + bytes <= kRecordBudget) {
         rec_total += bytes;
         B.rec[i] = R;
+        B.nfill += 1;  // the partition cursors
         RecPlanDesc rd(d[i]);
         st = pipeline_layout(&rd.d, B.L[i], true, off);
         if (st) return fail(st, "batch plan %d: %s", i, g_error.c_str());
@@ -994,6 +995,8 @@ rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
     off += align_up(R.nitems * 4ull);
     R.part_begin = off;
     off += align_up((R.parts + 1) * 4ull);
+    R.cursor = off;
+    off += align_up(R.parts * 4ull);
     ++B.rec_plans;
     const uint32_t agg = R.agg_slots * B.L[i].gp.words * 8;
     if (agg > B.agg_lds_bytes) B.agg_lds_bytes = agg;
@@ -1148,6 +1151,9 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
     push_fill(fill, g.slots, g.replicas * (g.cap + 1) * g.words, kFillGroup, 0, i);
     push_fill(fill, reinterpret_cast<uint64_t*>(g.overflow), 1, kFillConst, 0, i);
     push_fill(fill, reinterpret_cast<uint64_t*>(g.d_groups), 1, kFillConst, 0, i);
+    if (B.rec[i].parts)
+      push_fill(fill, reinterpret_cast<uint64_t*>(w + B.blob + B.rec[i].cursor),
+                (B.rec[i].parts + 1) / 2, kFillConst, 0, i);
     if (g.replicas > 1) push_items(merge_items, i, 0, (g.replicas - 1) * (g.cap + 1), kSlotChunk);
     push_items(fin_items, i, 0, d[i].n_keys == 0 ? 1 : g.cap + 1, kSlotChunk);
   }
@@ -1198,6 +1204,7 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
       rd.counts = reinterpret_cast<uint32_t*>(tables + R.counts);
       rd.item_n = reinterpret_cast<uint32_t*>(tables + R.item_n);
       rd.part_begin = reinterpret_cast<uint32_t*>(tables + R.part_begin);
+      rd.cursor = reinterpret_cast<uint32_t*>(tables + R.cursor);
       rd.parts = R.parts;
       rd.agg_parts = R.agg_parts;
       rd.words = R.words;

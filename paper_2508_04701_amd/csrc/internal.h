@@ -482,9 +482,12 @@ struct RecDesc {
   uint32_t* rkeys;
   uint32_t* pkeys;
   uint32_t narrow;
-  uint32_t* counts;       // [parts][nitems] records per (partition, item), then their offsets
+  uint32_t* counts;       // [nitems][parts] records per (item, partition)
   uint32_t* item_n;       // records of each item
   uint32_t* part_begin;   // parts + 1 offsets into parted
+  uint32_t* cursor;       // parts words, zero at the start: each partition's record total
+                          // (the fused pass adds each item's), then its next free place
+                          // in parted (set by the scan, taken by the scatter's atomics)
   uint32_t parts;         // a power of two, at most kMaxRecParts; 0 = off
   uint32_t agg_parts;     // partitions the aggregation pass folds one by one: runs of
                           // parts / agg_parts consecutive partitions (the top bits agree)
@@ -496,12 +499,6 @@ struct RecDesc {
 };
 
 constexpr uint32_t kMaxRecParts = 1024;
-// Bound on the partitions a plan takes by default (tuning.fanout may ask for
-// up to kMaxRecParts); plans needing more keep the atomics: with 1024
-// partitions over 200M fact rows the count array holds 3.1M entries, and its
-// one-workgroup scan alone took 3.6 ms (a served 1M-group query at 1%
-// selectivity: 4.9 ms with records, 1.1 ms with atomics).
-constexpr uint32_t kAutoRecParts = 256;
 // At least this many partitions in the fused pass and the scatter, so that
 // the lanes of a wave rarely count into the same LDS word.
 constexpr uint32_t kMinRecParts = 16;

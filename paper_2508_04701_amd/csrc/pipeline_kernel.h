@@ -1550,10 +1550,15 @@ __attribute__((amdgpu_waves_per_eu(kBatchWaves<D0, D1>))) batch_fused_kernel(Bat
     if (p.lds_slots > 0 || parts) {
       if (p.lds_slots > 0) lds_group_flush(lg, p.lds_slots, p.g);
       if (parts) {
-        // the item's record count per partition, partition-major
+        // the item's record count per partition, added to the partition's
+        // total
         const uint32_t j = static_cast<uint32_t>(it.begin / p.rec.item_tiles);
-        for (uint32_t q = threadIdx.x; q < parts; q += blockDim.x)
-          p.rec.counts[static_cast<uint64_t>(q) * p.rec.nitems + j] = hist[q];
+        uint32_t* row = p.rec.counts + static_cast<uint64_t>(j) * parts;
+        for (uint32_t q = threadIdx.x; q < parts; q += blockDim.x) {
+          const uint32_t c = hist[q];
+          row[q] = c;
+          if (c) atomicAdd(p.rec.cursor + q, c);
+        }
         if (threadIdx.x == 0) p.rec.item_n[j] = hist[parts];
       }
       __syncthreads();

@@ -4,14 +4,16 @@
 // (packed key, then the early value columns) into its item's run and counted
 // it per partition; see RecDesc. Then, for every plan with records:
 //
-//   scan      one workgroup per plan: the [partition][item] counts become
-//             the offsets of each item's records within its partition, in
-//             partition-major order, and each aggregation partition (a run
-//             of consecutive partitions whose keys fit one LDS table) is cut
-//             into pieces of at most kRecPiece records, appended to the
-//             batch's piece list (one atomic per plan);
-//   scatter   one workgroup per fused-pass item: the item's records go to
-//             their partition's range at the item's offset, sorted by
+//   scan      one workgroup per plan: the partitions' record totals (which
+//             the fused pass summed, one atomic per item and partition)
+//             become their places in partition-major order, and each
+//             aggregation partition (a run of consecutive partitions whose
+//             keys fit one LDS table) is cut into pieces of at most
+//             kRecPiece records, appended to the batch's piece list (one
+//             atomic per plan);
+//   scatter   one workgroup per fused-pass item: the item reserves its share
+//             of each partition with one atomic on the partition's cursor
+//             and its records go there, sorted by
 //             partition in LDS a chunk at a time so that each partition's
 //             share of a chunk is written by consecutive lanes (order within
 //             a partition is arbitrary);
@@ -81,63 +83,16 @@ __global__ void __launch_bounds__(kRecScanThreads) rec_scan_kernel(BatchParams b
   const PipelineParams& p = batch_at(b.plans, blockIdx.x);
   const uint32_t parts = p.rec.parts;
   if (parts == 0) return;
-  const uint32_t nitems = p.rec.nitems;
-  uint32_t* counts = p.rec.counts;
   uint32_t* pb = p.rec.part_begin;
-  // each thread takes a contiguous segment of the [partition][item] counts,
-  // a multiple of four words long (the array is 256-byte aligned), read and
-  // written in 16-byte vectors, eight in flight
-  const uint64_t n = static_cast<uint64_t>(parts) * nitems;
-  const uint64_t per = ((n + blockDim.x - 1) / blockDim.x + 3) & ~uint64_t(3);
-  uint64_t lo = static_cast<uint64_t>(threadIdx.x) * per;
-  if (lo > n) lo = n;
-  const uint64_t hi = lo + per < n ? lo + per : n;
-  const uint64_t hv = lo + ((hi - lo) & ~uint64_t(3));  // end of the whole vectors
-  const uint4* cv = reinterpret_cast<const uint4*>(counts);
-  uint32_t sum = 0;
-  uint64_t i = lo;
-  for (; i + 32 <= hv; i += 32) {
-    uint4 x[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) x[u] = cv[i / 4 + u];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) sum += x[u].x + x[u].y + x[u].z + x[u].w;
-  }
-  for (; i < hv; i += 4) {
-    const uint4 x = cv[i / 4];
-    sum += x.x + x.y + x.z + x.w;
-  }
-  for (; i < hi; ++i) sum += counts[i];
+  // the partitions' places: an exclusive prefix sum of their totals, each
+  // also the partition's first free place (parts <= blockDim.x)
+  const uint32_t c = threadIdx.x < parts ? p.rec.cursor[threadIdx.x] : 0u;
   uint32_t total = 0;
-  uint32_t run = block_exclusive(sum, s_wave, total);
-  // the first element of each partition's row records where it begins
-  uint64_t row_at = (lo + nitems - 1) / nitems * nitems;
-  auto step = [&](uint64_t at, uint32_t c) {
-    if (at == row_at) {
-      pb[at / nitems] = run;
-      row_at += nitems;
-    }
-    const uint32_t off = run;
-    run += c;
-    return off;
-  };
-  uint4* ov = reinterpret_cast<uint4*>(counts);
-  for (i = lo; i + 32 <= hv; i += 32) {
-    uint4 x[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) x[u] = cv[i / 4 + u];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const uint64_t at = i + 4 * u;
-      uint4 o;
-      o.x = step(at, x[u].x);
-      o.y = step(at + 1, x[u].y);
-      o.z = step(at + 2, x[u].z);
-      o.w = step(at + 3, x[u].w);
-      ov[at / 4] = o;
-    }
+  const uint32_t at = block_exclusive(c, s_wave, total);
+  if (threadIdx.x < parts) {
+    pb[threadIdx.x] = at;
+    p.rec.cursor[threadIdx.x] = at;
   }
-  for (; i < hi; ++i) counts[i] = step(i, counts[i]);
   if (threadIdx.x == 0) pb[parts] = total;
   __syncthreads();
   // pieces of kRecPiece records, aggregation partition by aggregation
@@ -308,9 +263,13 @@ __global__ void __launch_bounds__(kRecScatterThreads) rec_scatter_kernel(BatchPa
   const uint32_t j = static_cast<uint32_t>(it.begin / p.rec.item_tiles);
   const uint32_t n = p.rec.item_n[j];
   if (n == 0) return;
-  const uint32_t nitems = p.rec.nitems;
-  for (uint32_t q = threadIdx.x; q < parts; q += blockDim.x)
-    L.cur[q] = p.rec.counts[static_cast<uint64_t>(q) * nitems + j];
+  // the item's place in each partition: one atomic on the partition's
+  // cursor per partition the item has records of
+  const uint32_t* row = p.rec.counts + static_cast<uint64_t>(j) * parts;
+  for (uint32_t q = threadIdx.x; q < parts; q += blockDim.x) {
+    const uint32_t c = row[q];
+    L.cur[q] = c ? atomicAdd(p.rec.cursor + q, c) : 0u;
+  }
   __syncthreads();
   const uint32_t words = p.rec.words;
   const uint64_t run = static_cast<uint64_t>(j) * p.rec.item_tiles * kPipeTile;

@@ -341,8 +341,7 @@ def record_specs(seed):
     value columns (no records: its spilled rows use atomics), a plan whose
     probes all miss, one with no probe rows, two int8 group keys (a dim
     attribute and a fact column, negative values included) whose packed key
-    takes 16 bits, and 600k groups (more partitions than records take by
-    default: atomics, unless the tuning asks for 1024)."""
+    takes 16 bits, and 600k groups over 1024 partitions."""
     r = np.random.default_rng(seed)
     specs = []
 
@@ -365,7 +364,7 @@ def record_specs(seed):
     plan(200_000, 300_000, 3_000, AGGS)
     plan(400_000, 500_001, 40_000, AGGS)
     plan(600_000, 700_000, 150_000, [("sum", 1), ("count", None)])
-    plan(1_000_000, 1_200_000, 600_000, [("sum", 1), ("count", None)])  # beyond 256 partitions
+    plan(1_000_000, 1_200_000, 600_000, [("sum", 1), ("count", None)])  # 1024 partitions
     zipf = (datagen.zipf_ranks(seed, 9, 60_000, 1.1, 300_000) - 1).astype(np.int32)
     plan(300_000, 400_000, 60_000, AGGS, grp=zipf)
     plan(100_000, 200_000, 20_000, [("count", None)])
