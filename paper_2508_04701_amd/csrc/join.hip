@@ -206,28 +206,56 @@ __device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
 __device__ __forceinline__ void range_rows(const MapBuildParams& p, uint64_t base, uint64_t end,
                                            uint64_t stride) {
   if (p.map.direct_cap == 0) return;
-  for (; base < end; base += stride) {
-    const uint64_t i = base + threadIdx.x;
-    int32_t kmin = INT32_MAX, kmax = INT32_MIN, pmin = INT32_MAX, pmax = INT32_MIN;
-    if (i < end) {
-      const int64_t r = p.idx ? static_cast<int64_t>(p.idx[i]) : static_cast<int64_t>(i);
-      kmin = kmax = static_cast<int32_t>(load_elem(p.keys, p.type, r));
-      if (p.val_col) pmin = pmax = static_cast<int32_t>(load_elem(p.val_col, p.val_type, r));
+  // each lane folds its rows in registers (four loads in flight per step);
+  // the wave then reduces once and publishes with at most four atomics
+  int32_t kmin = INT32_MAX, kmax = INT32_MIN, pmin = INT32_MAX, pmax = INT32_MIN;
+  const bool pay = p.val_col != nullptr;
+  auto row = [&](uint64_t i) {
+    return p.idx ? static_cast<int64_t>(p.idx[i]) : static_cast<int64_t>(i);
+  };
+  uint64_t i = base + threadIdx.x;
+  for (; i + 3 * stride < end; i += 4 * stride) {
+    int32_t k[4], v[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) k[u] = static_cast<int32_t>(load_elem(p.keys, p.type, row(i + u * stride)));
+    if (pay) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        v[u] = static_cast<int32_t>(load_elem(p.val_col, p.val_type, row(i + u * stride)));
     }
-    kmin = wave_min_i32(kmin);
-    kmax = wave_max_i32(kmax);
-    if (p.val_col) {
-      pmin = wave_min_i32(pmin);
-      pmax = wave_max_i32(pmax);
-    }
-    if (lane_id() == 0) {
-      int32_t* st = p.map.dstate;
-      if (kmin < st[kDKmin]) atomicMin(st + kDKmin, kmin);
-      if (kmax > st[kDKmax]) atomicMax(st + kDKmax, kmax);
-      if (p.val_col) {
-        if (pmin < st[kDPmin]) atomicMin(st + kDPmin, pmin);
-        if (pmax > st[kDPmax]) atomicMax(st + kDPmax, pmax);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      kmin = k[u] < kmin ? k[u] : kmin;
+      kmax = k[u] > kmax ? k[u] : kmax;
+      if (pay) {
+        pmin = v[u] < pmin ? v[u] : pmin;
+        pmax = v[u] > pmax ? v[u] : pmax;
       }
+    }
+  }
+  for (; i < end; i += stride) {
+    const int32_t k = static_cast<int32_t>(load_elem(p.keys, p.type, row(i)));
+    kmin = k < kmin ? k : kmin;
+    kmax = k > kmax ? k : kmax;
+    if (pay) {
+      const int32_t v = static_cast<int32_t>(load_elem(p.val_col, p.val_type, row(i)));
+      pmin = v < pmin ? v : pmin;
+      pmax = v > pmax ? v : pmax;
+    }
+  }
+  kmin = wave_min_i32(kmin);
+  kmax = wave_max_i32(kmax);
+  if (pay) {
+    pmin = wave_min_i32(pmin);
+    pmax = wave_max_i32(pmax);
+  }
+  if (lane_id() == 0 && kmin <= kmax) {
+    int32_t* st = p.map.dstate;
+    if (kmin < st[kDKmin]) atomicMin(st + kDKmin, kmin);
+    if (kmax > st[kDKmax]) atomicMax(st + kDKmax, kmax);
+    if (pay) {
+      if (pmin < st[kDPmin]) atomicMin(st + kDPmin, pmin);
+      if (pmax > st[kDPmax]) atomicMax(st + kDPmax, pmax);
     }
   }
 }
