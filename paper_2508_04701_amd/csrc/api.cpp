@@ -791,9 +791,13 @@ struct BatchLayout {
   std::vector<size_t> base;
   std::vector<RecLayout> rec;
   size_t off_plans, off_builds, off_fins, off_fill, off_build_items, off_tile_items;
-  size_t off_merge_items, off_fin_items, off_slice_items, blob;
+  size_t off_merge_items, off_fin_items, off_slice_items, off_win_items, blob;
   size_t off_pieces;  // from the end of the uploaded block
-  uint64_t nfill, nbuild, ntile, nmerge, nfin, nslice;
+  uint64_t nfill, nbuild, ntile, nmerge, nfin, nslice, nwin;
+  // windowed direct-table builds (2 per plan: dim d of plan i at 2i + d):
+  // windows (0: not windowed) and region offsets from the end of the block
+  std::vector<uint32_t> win_n;
+  std::vector<size_t> win_pairs, win_cursor, win_begin;
   uint64_t piece_cap;
   uint32_t rec_plans, agg_lds_bytes;
   uint32_t slice_bits;  // direct-table slice of the second build pass
@@ -915,7 +919,11 @@ rel_status check_batch(const rel_pipeline_desc* d, int n) {
 rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
   B.L.resize(n);
   B.base.resize(n);
-  B.nfill = B.nbuild = B.ntile = B.nmerge = B.nfin = B.nslice = 0;
+  B.nfill = B.nbuild = B.ntile = B.nmerge = B.nfin = B.nslice = B.nwin = 0;
+  B.win_n.assign(2 * static_cast<size_t>(n), 0);
+  B.win_pairs.assign(2 * static_cast<size_t>(n), 0);
+  B.win_cursor.assign(2 * static_cast<size_t>(n), 0);
+  B.win_begin.assign(2 * static_cast<size_t>(n), 0);
   B.slice_bits = direct_slice_bits();
   uint64_t tiles = 0;
   for (int i = 0; i < n; ++i) tiles += ceil_div(static_cast<uint64_t>(d[i].fact[0].len), kPipeTile);
@@ -956,8 +964,16 @@ rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
       B.nfill += ceil_div(map_words(B.L[i].dim[k], d[i].dims[k].key.type), kFillChunk) + 1;
       if (B.L[i].dim[k].direct_cap) {
         B.nfill += 1 + ceil_div(B.L[i].dim[k].direct_cap / 64, kFillChunk);
-        B.nslice += ceil_div(B.L[i].dim[k].direct_cap, B.slice_bits) *
-                    slice_parts(static_cast<uint64_t>(d[i].dims[k].key.len));
+        // dims with payloads are built by windows when they have few enough
+        const uint64_t wins = ceil_div(B.L[i].dim[k].direct_cap, kWinKeys);
+        if (d[i].dims[k].has_payload && wins <= kMaxWins) {
+          B.win_n[2 * i + k] = static_cast<uint32_t>(wins);
+          B.nwin += wins;
+          B.nfill += 1;  // the window cursors
+        } else {
+          B.nslice += ceil_div(B.L[i].dim[k].direct_cap, B.slice_bits) *
+                      slice_parts(static_cast<uint64_t>(d[i].dims[k].key.len));
+        }
       }
       B.nbuild += ceil_div(static_cast<uint64_t>(d[i].dims[k].key.len), kBuildChunk);
     }
@@ -1002,13 +1018,27 @@ rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
     if (agg > B.agg_lds_bytes) B.agg_lds_bytes = agg;
     B.piece_cap += ceil_div(rows, kRecPiece) + R.agg_parts;
   }
+  // window regions: the grouped pairs, the cursors, the offsets
+  for (int i = 0; i < n; ++i) {
+    for (int k = 0; k < d[i].n_dims; ++k) {
+      const uint32_t wins = B.win_n[2 * i + k];
+      if (wins == 0) continue;
+      off = align_up(off);
+      B.win_pairs[2 * i + k] = off;
+      off += align_up(static_cast<uint64_t>(d[i].dims[k].key.len) * 8);
+      B.win_cursor[2 * i + k] = off;
+      off += align_up(wins * 4ull);
+      B.win_begin[2 * i + k] = off;
+      off += align_up((wins + 1) * 4ull);
+    }
+  }
   off = align_up(off);
   B.off_pieces = off;
   off += align_up(B.piece_cap * sizeof(RecPiece));
   if (B.piece_cap > 0xFFFFFFFFull) return fail(REL_EUNSUPPORTED, "batch: too many record pieces");
   const uint64_t most = 0xFFFFFFFFull;
   if (B.nfill > most || B.nbuild > most || B.ntile > most || B.nmerge > most || B.nfin > most ||
-      B.nslice > most)
+      B.nslice > most || B.nwin > most)
     return fail(REL_EUNSUPPORTED, "batch: more than 2^32 - 1 work items in a phase");
   size_t h = kAlign;  // the counter
   B.off_plans = h;
@@ -1029,6 +1059,8 @@ rel_status batch_layout(const rel_pipeline_desc* d, int n, BatchLayout& B) {
   h = align_up(h + B.nfin * sizeof(BatchItem));
   B.off_slice_items = h;
   h = align_up(h + B.nslice * sizeof(BatchItem));
+  B.off_win_items = h;
+  h = align_up(h + B.nwin * sizeof(BatchItem));
   B.blob = h;
   for (int i = 0; i < n; ++i) {
     RecPlanDesc rd(d[i]);
@@ -1102,13 +1134,14 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
   MapBuildParams* builds = reinterpret_cast<MapBuildParams*>(host + B.off_builds);
   FinalizeParams* fins = reinterpret_cast<FinalizeParams*>(host + B.off_fins);
   std::vector<FillItem> fill;
-  std::vector<BatchItem> build_items, tile_items, merge_items, fin_items, slice_items;
+  std::vector<BatchItem> build_items, tile_items, merge_items, fin_items, slice_items, win_items;
   fill.reserve(B.nfill);
   build_items.reserve(B.nbuild);
   tile_items.reserve(B.ntile);
   merge_items.reserve(B.nmerge);
   fin_items.reserve(B.nfin);
   slice_items.reserve(B.nslice);
+  win_items.reserve(B.nwin);
   uint32_t group_lds[kLdsClasses] = {};
   std::vector<int> cls(n);
   for (int i = 0; i < n; ++i) {
@@ -1134,6 +1167,26 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
       if (m.direct_cap) {
         push_fill(fill, reinterpret_cast<uint64_t*>(m.dstate), 2, kFillConst, kDirectStateInit, i);
         push_fill(fill, reinterpret_cast<uint64_t*>(m.dbits), m.direct_cap / 64, kFillConst, 0, i);
+      }
+      const uint32_t wins = B.win_n[2 * i + k];
+      MapBuildParams& bw = builds[2 * i + k];
+      bw.nwin = wins;
+      if (wins) {
+        unsigned char* tables = w + B.blob;
+        bw.wpairs = reinterpret_cast<uint64_t*>(tables + B.win_pairs[2 * i + k]);
+        bw.wcursor = reinterpret_cast<uint32_t*>(tables + B.win_cursor[2 * i + k]);
+        bw.wbegin = reinterpret_cast<uint32_t*>(tables + B.win_begin[2 * i + k]);
+        push_fill(fill, reinterpret_cast<uint64_t*>(bw.wcursor), (wins + 1) / 2, kFillConst, 0, i);
+        for (uint32_t wi = 0; wi < wins; ++wi) {
+          BatchItem it;
+          it.inst = i;
+          it.aux = k;
+          it.begin = wi;
+          it.end = wi + 1;
+          win_items.push_back(it);
+        }
+      }
+      if (m.direct_cap && !wins) {
         const uint64_t parts = slice_parts(static_cast<uint64_t>(d[i].dims[k].key.len));
         for (uint64_t lo = 0; lo < m.direct_cap; lo += B.slice_bits)
           for (uint64_t part = 0; part < parts; ++part) {
@@ -1222,6 +1275,7 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
   std::memcpy(host + B.off_merge_items, merge_items.data(), merge_items.size() * sizeof(BatchItem));
   std::memcpy(host + B.off_fin_items, fin_items.data(), fin_items.size() * sizeof(BatchItem));
   std::memcpy(host + B.off_slice_items, slice_items.data(), slice_items.size() * sizeof(BatchItem));
+  std::memcpy(host + B.off_win_items, win_items.data(), win_items.size() * sizeof(BatchItem));
   shape = plans[0];
   std::memset(&bp, 0, sizeof bp);
   bp.plans = reinterpret_cast<const PipelineParams*>(w + B.off_plans);
@@ -1233,12 +1287,14 @@ void batch_blob(const rel_pipeline_desc* d, int n, const rel_outputs* o, const B
   bp.merge_items = reinterpret_cast<const BatchItem*>(w + B.off_merge_items);
   bp.fin_items = reinterpret_cast<const BatchItem*>(w + B.off_fin_items);
   bp.slice_items = reinterpret_cast<const BatchItem*>(w + B.off_slice_items);
+  bp.win_items = reinterpret_cast<const BatchItem*>(w + B.off_win_items);
   bp.nfill = static_cast<uint32_t>(fill.size());
   bp.nbuild = static_cast<uint32_t>(build_items.size());
   bp.ntile = static_cast<uint32_t>(class_end[0]);
   bp.nmerge = static_cast<uint32_t>(merge_items.size());
   bp.nfin = static_cast<uint32_t>(fin_items.size());
   bp.nslice = static_cast<uint32_t>(slice_items.size());
+  bp.nwin = static_cast<uint32_t>(win_items.size());
   bp.slice_bits = B.slice_bits;
   bp.lds_bytes = lds_bytes[0];
   bp.group_lds_bytes = group_lds[0];

@@ -283,7 +283,18 @@ struct MapBuildParams {
   int64_t n;
   const void* val_col;
   int32_t val_type;
+  // Batched builds of direct tables with payloads (nwin > 0): the rows are
+  // first grouped by window of kWinKeys keys, so that each window's bits and
+  // payloads are set in LDS and written out whole (see launch_batch_build).
+  uint64_t* wpairs;   // n (key, payload) pairs, window by window
+  uint32_t* wcursor;  // nwin: rows per window (zero at the start), then its next free place
+  uint32_t* wbegin;   // nwin + 1 offsets into wpairs
+  uint32_t nwin;
 };
+
+constexpr uint32_t kWinBits = 14;
+constexpr uint32_t kWinKeys = 1u << kWinBits;
+constexpr uint32_t kMaxWins = 4096;  // windows of one dim (larger tables use slices)
 
 void launch_map_init(const MapDesc& m, hipStream_t s);
 // Three passes: key (and payload) ranges, the direct table if the range
@@ -599,7 +610,8 @@ struct BatchParams {
   const BatchItem* merge_items;
   const BatchItem* fin_items;
   const BatchItem* slice_items;  // direct-table slices: begin = first bit, aux = dim
-  uint32_t nfill, nbuild, ntile, nmerge, nfin, nslice;
+  const BatchItem* win_items;    // direct-table windows: begin = window, aux = dim
+  uint32_t nfill, nbuild, ntile, nmerge, nfin, nslice, nwin;
   uint32_t slice_bits;           // bits of a direct-table slice (a power of two)
   uint32_t lds_bytes;        // dynamic LDS of the fused pass (same for every plan)
   uint32_t group_lds_bytes;  // LDS group table bytes of the largest plan

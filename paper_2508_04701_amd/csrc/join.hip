@@ -348,6 +348,172 @@ __global__ void __launch_bounds__(256) batch_build_kernel(BatchParams b, int pas
   }
 }
 
+// Windowed direct-table builds of a batch (dims with payloads and at most
+// kMaxWins windows of kWinKeys keys): the payloads of a slice build were
+// random 1-4 byte stores, each its own memory transaction. Instead the build
+// rows are grouped by window first (count, place, scatter: the same totals
+// and per-item reservations as the pipeline's records), and then one
+// workgroup per window sets its bits and payloads in LDS and writes both out
+// in order.
+
+// Whether build params p hold a windowed direct table this batch builds.
+__device__ __forceinline__ bool windowed(const MapBuildParams& p) {
+  if (p.nwin == 0) return false;
+  const uint64_t range = direct_range(p.map);
+  return range != 0 && range <= p.map.direct_cap;
+}
+
+__device__ __forceinline__ int64_t build_row(const MapBuildParams& p, uint64_t i) {
+  return p.idx ? static_cast<int64_t>(p.idx[i]) : static_cast<int64_t>(i);
+}
+
+// Rows per window of one build item, added to the windows' totals.
+__global__ void __launch_bounds__(256) batch_win_count_kernel(BatchParams b) {
+  __shared__ uint32_t hist[kMaxWins];
+  const BatchItem& it = batch_at(b.build_items, blockIdx.x);
+  const MapBuildParams& p = batch_at(b.builds, 2 * static_cast<uint64_t>(it.inst) + it.aux);
+  if (!windowed(p)) return;
+  const int32_t kmin = p.map.dstate[kDKmin];
+  const uint32_t nwin = p.nwin;
+  for (uint32_t w = threadIdx.x; w < nwin; w += blockDim.x) hist[w] = 0;
+  __syncthreads();
+  for (uint64_t i = it.begin + threadIdx.x; i < it.end; i += blockDim.x) {
+    const int32_t key = static_cast<int32_t>(load_elem(p.keys, p.type, build_row(p, i)));
+    atomicAdd(hist + (static_cast<uint32_t>(key - kmin) >> kWinBits), 1u);
+  }
+  __syncthreads();
+  for (uint32_t w = threadIdx.x; w < nwin; w += blockDim.x)
+    if (hist[w]) atomicAdd(p.wcursor + w, hist[w]);
+}
+
+// One workgroup per dim: the windows' places (an exclusive prefix sum of
+// their totals), each also the window's first free place.
+constexpr int kWinScanThreads = 1024;
+constexpr uint32_t kWinPer = kMaxWins / kWinScanThreads;
+
+__global__ void __launch_bounds__(kWinScanThreads) batch_win_scan_kernel(BatchParams b) {
+  __shared__ uint32_t s_wave[kWinScanThreads / kWave];
+  const MapBuildParams& p = batch_at(b.builds, blockIdx.x);
+  if (!windowed(p)) return;
+  const uint32_t nwin = p.nwin;
+  const uint32_t w0 = threadIdx.x * kWinPer;
+  uint32_t c[kWinPer], sum = 0;
+#pragma unroll
+  for (uint32_t e = 0; e < kWinPer; ++e) {
+    c[e] = w0 + e < nwin ? p.wcursor[w0 + e] : 0u;
+    sum += c[e];
+  }
+  // exclusive prefix over the workgroup
+  const int lane = lane_id();
+  const int wave = threadIdx.x / kWave;
+  uint32_t incl = sum;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t t = __shfl_up(incl, off, kWave);
+    if (lane >= off) incl += t;
+  }
+  if (lane == kWave - 1) s_wave[wave] = incl;
+  __syncthreads();
+  uint32_t at = incl - sum, total = 0;
+  for (int w = 0; w < kWinScanThreads / kWave; ++w) {
+    if (w < wave) at += s_wave[w];
+    total += s_wave[w];
+  }
+#pragma unroll
+  for (uint32_t e = 0; e < kWinPer; ++e) {
+    if (w0 + e < nwin) {
+      p.wbegin[w0 + e] = at;
+      p.wcursor[w0 + e] = at;
+    }
+    at += c[e];
+  }
+  if (threadIdx.x == 0) p.wbegin[nwin] = total;
+}
+
+// The rows of one build item to their windows: a histogram, one atomic per
+// window on its cursor for the item's share, then one LDS atomic per row for
+// its place. Pairs are (key, payload) as two 32-bit halves.
+__global__ void __launch_bounds__(256) batch_win_scatter_kernel(BatchParams b) {
+  __shared__ uint32_t cur[kMaxWins];
+  const BatchItem& it = batch_at(b.build_items, blockIdx.x);
+  const MapBuildParams& p = batch_at(b.builds, 2 * static_cast<uint64_t>(it.inst) + it.aux);
+  if (!windowed(p)) return;
+  const int32_t kmin = p.map.dstate[kDKmin];
+  const uint32_t nwin = p.nwin;
+  for (uint32_t w = threadIdx.x; w < nwin; w += blockDim.x) cur[w] = 0;
+  __syncthreads();
+  for (uint64_t i = it.begin + threadIdx.x; i < it.end; i += blockDim.x) {
+    const int32_t key = static_cast<int32_t>(load_elem(p.keys, p.type, build_row(p, i)));
+    atomicAdd(cur + (static_cast<uint32_t>(key - kmin) >> kWinBits), 1u);
+  }
+  __syncthreads();
+  for (uint32_t w = threadIdx.x; w < nwin; w += blockDim.x) {
+    const uint32_t c = cur[w];
+    cur[w] = c ? atomicAdd(p.wcursor + w, c) : 0u;
+  }
+  __syncthreads();
+  for (uint64_t i = it.begin + threadIdx.x; i < it.end; i += blockDim.x) {
+    const int64_t r = build_row(p, i);
+    const int32_t key = static_cast<int32_t>(load_elem(p.keys, p.type, r));
+    const int32_t pay = static_cast<int32_t>(load_elem(p.val_col, p.val_type, r));
+    const uint32_t at = atomicAdd(cur + (static_cast<uint32_t>(key - kmin) >> kWinBits), 1u);
+    p.wpairs[at] = static_cast<uint64_t>(static_cast<uint32_t>(key)) |
+                   static_cast<uint64_t>(static_cast<uint32_t>(pay)) << 32;
+  }
+}
+
+// One workgroup per window: its keys' bits (an LDS atomic OR each; a bit
+// already set is a duplicate) and narrowed payloads, set in LDS from the
+// window's pairs and written out in order (windows are disjoint and
+// word-aligned; the bitmap was zero-filled).
+constexpr int kWinThreads = 256;
+
+__global__ void __launch_bounds__(kWinThreads) batch_win_build_kernel(BatchParams b) {
+  __shared__ uint32_t bits[kWinKeys / 32];
+  __shared__ uint32_t vals[kWinKeys];
+  const BatchItem& it = batch_at(b.win_items, blockIdx.x);
+  const MapBuildParams& p = batch_at(b.builds, 2 * static_cast<uint64_t>(it.inst) + it.aux);
+  if (!windowed(p)) return;
+  const MapDesc& m = p.map;
+  const uint64_t range = direct_range(m);
+  const uint32_t w = static_cast<uint32_t>(it.begin);
+  const uint64_t lo = static_cast<uint64_t>(w) << kWinBits;
+  if (lo >= range) return;
+  const uint32_t span = static_cast<uint32_t>(range - lo < kWinKeys ? range - lo : kWinKeys);
+  const uint32_t begin = p.wbegin[w], end = p.wbegin[w + 1];
+  if (begin == end) return;
+  const int32_t kmin = m.dstate[kDKmin];
+  const int32_t pmin = m.dstate[kDPmin];
+  const int width = direct_width(pmin, m.dstate[kDPmax]);
+  const uint32_t words = (span + 31) / 32;
+  for (uint32_t t = threadIdx.x; t < words; t += blockDim.x) bits[t] = 0;
+  __syncthreads();
+  for (uint32_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
+    const uint64_t pr = p.wpairs[i];
+    const uint32_t off = static_cast<uint32_t>(static_cast<int32_t>(pr) - kmin) - static_cast<uint32_t>(lo);
+    const uint32_t bit = 1u << (off & 31);
+    if (atomicOr(bits + (off >> 5), bit) & bit) {
+      *m.dup = 1;
+      continue;
+    }
+    vals[off] = static_cast<uint32_t>(static_cast<int32_t>(pr >> 32)) - static_cast<uint32_t>(pmin);
+  }
+  __syncthreads();
+  uint32_t* out = m.dbits + (lo >> 5);
+  for (uint32_t t = threadIdx.x; t < words; t += blockDim.x) out[t] = bits[t];
+  // payloads of absent keys are whatever LDS held: the bitmap hides them
+  if (width == 1) {
+    uint8_t* d = static_cast<uint8_t*>(m.dvals) + lo;
+    for (uint32_t t = threadIdx.x; t < span; t += blockDim.x) d[t] = static_cast<uint8_t>(vals[t]);
+  } else if (width == 2) {
+    uint16_t* d = static_cast<uint16_t*>(m.dvals) + lo;
+    for (uint32_t t = threadIdx.x; t < span; t += blockDim.x) d[t] = static_cast<uint16_t>(vals[t]);
+  } else {
+    uint32_t* d = static_cast<uint32_t*>(m.dvals) + lo;
+    for (uint32_t t = threadIdx.x; t < span; t += blockDim.x) d[t] = vals[t];
+  }
+}
+
 // Build pass 2 of a batch, one workgroup per slice item: bits [lo, lo +
 // slice_bits) of one dim's direct table, set in LDS from one part of the
 // dim's build rows. The workgroup reads its part's keys and takes those that
@@ -365,6 +531,7 @@ __global__ void __launch_bounds__(kSliceThreads) batch_direct_slice_kernel(Batch
   const MapDesc& m = p.map;
   const uint64_t range = direct_range(m);
   if (range == 0 || range > m.direct_cap) return;  // no direct table for this dim
+  if (p.nwin) return;                              // built by windows
   const uint64_t lo = it.begin;
   if (lo >= range) return;
   const uint64_t hi = lo + b.slice_bits < range ? lo + b.slice_bits : range;
@@ -713,6 +880,12 @@ void launch_batch_build(const BatchParams& b, hipStream_t s) {
   if (b.nbuild == 0) return;
   ProfileScope ps(kKMapBuild, s);
   hipLaunchKernelGGL(batch_build_kernel, dim3(b.nbuild), dim3(256), 0, s, b, 0);
+  if (b.nwin > 0) {
+    hipLaunchKernelGGL(batch_win_count_kernel, dim3(b.nbuild), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(batch_win_scan_kernel, dim3(2 * b.nplans), dim3(kWinScanThreads), 0, s, b);
+    hipLaunchKernelGGL(batch_win_scatter_kernel, dim3(b.nbuild), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(batch_win_build_kernel, dim3(b.nwin), dim3(kWinThreads), 0, s, b);
+  }
   if (b.nslice > 0) {
     const size_t lds = static_cast<size_t>(b.slice_bits) / 8;
     static size_t allowed = 0;

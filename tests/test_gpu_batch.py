@@ -309,11 +309,13 @@ def test_native_autotuner_records_and_lookups(tmp_path):
 
 
 def test_batch_direct_tables_built_in_slices_and_parts():
-    """Dims large enough that the direct-table build splits the key range
-    into several LDS slices and the build rows into several parts: unique
-    keys (a direct table), and the same keys with one key repeated in another
-    part (the parts' merge must see the duplicate, so the dim falls back to
-    its hash table and the repeated key's rows are counted twice)."""
+    """Dims large enough that the direct-table build spreads over many LDS
+    workgroups: with payloads, windows of 16k keys (the rows grouped by
+    window first); membership only, slices of the key range split over parts
+    of the build rows. Unique keys (a direct table), and the same keys with
+    one key repeated in another part (the duplicate must be seen, so the dim
+    falls back to its hash table and the repeated key's rows are counted
+    twice)."""
     announce("batch direct slices")
     r = np.random.default_rng(77)
     nb = 1_300_000  # three parts of the build rows; two slices of bits
@@ -331,6 +333,13 @@ def test_batch_direct_tables_built_in_slices_and_parts():
     b = run_batch(specs)
     for i, (spec, plan) in enumerate(zip(specs, b.plans)):
         assert_groups(plan.result(), oracle_of(spec), AGGS, f"instance {i}")
+    # membership-only dims: slices and parts
+    aggs = [("count", None), ("sum", 1), ("min", 1)]
+    specs = [([pk, pv], [], [dict(fk=0, key=k, payload=None)], [], aggs, 1)
+             for k in (keys, dup_keys)]
+    b = run_batch(specs)
+    for i, (spec, plan) in enumerate(zip(specs, b.plans)):
+        assert_groups(plan.result(), oracle_of(spec), aggs, f"membership instance {i}")
 
 
 def record_specs(seed):
