@@ -733,7 +733,6 @@ void plan_params(const rel_pipeline_desc* d, const PipeLayout& L, unsigned char*
 
 // Units per work item of the batched phases.
 constexpr uint64_t kFillChunk = 32768;   // words
-constexpr uint64_t kBuildChunk = 8192;   // build rows
 
 // Bits of a direct-table slice that one workgroup sets in LDS during a batch
 // build: 2^20 (128 KB) when a workgroup may hold that much, else the largest

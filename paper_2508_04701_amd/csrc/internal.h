@@ -292,6 +292,7 @@ struct MapBuildParams {
   uint32_t nwin;
 };
 
+constexpr uint64_t kBuildChunk = 8192;  // build rows per batch build item
 constexpr uint32_t kWinBits = 14;
 constexpr uint32_t kWinKeys = 1u << kWinBits;
 constexpr uint32_t kMaxWins = 4096;  // windows of one dim (larger tables use slices)

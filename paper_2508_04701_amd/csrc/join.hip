@@ -430,36 +430,98 @@ __global__ void __launch_bounds__(kWinScanThreads) batch_win_scan_kernel(BatchPa
   if (threadIdx.x == 0) p.wbegin[nwin] = total;
 }
 
-// The rows of one build item to their windows: a histogram, one atomic per
-// window on its cursor for the item's share, then one LDS atomic per row for
-// its place. Pairs are (key, payload) as two 32-bit halves.
-__global__ void __launch_bounds__(256) batch_win_scatter_kernel(BatchParams b) {
-  __shared__ uint32_t cur[kMaxWins];
+// The rows of one build item to their windows: a histogram (each row's
+// rank within its window from the LDS atomic), one atomic per window on its
+// cursor for the item's share, then the pairs placed in LDS in window order
+// and written out in that order, so that each window's share of the item is
+// stored by consecutive lanes. Pairs are (key, payload) as two 32-bit halves.
+constexpr int kWinScatterThreads = 1024;
+constexpr int kWinRows = static_cast<int>(kBuildChunk) / kWinScatterThreads;
+static_assert(kBuildChunk % kWinScatterThreads == 0, "whole rows per thread");
+constexpr uint32_t kWinOwn = kMaxWins / kWinScatterThreads;  // windows per thread in the offsets
+
+struct WinScatterLds {
+  uint64_t stage[kBuildChunk];
+  uint16_t win[kBuildChunk];
+  uint32_t cur[kMaxWins];  // counts, then offsets within the item, then write bases
+  uint32_t wave[kWinScatterThreads / kWave];
+};
+
+__global__ void __launch_bounds__(kWinScatterThreads) batch_win_scatter_kernel(BatchParams b) {
+  __shared__ __attribute__((aligned(16))) WinScatterLds L;
   const BatchItem& it = batch_at(b.build_items, blockIdx.x);
   const MapBuildParams& p = batch_at(b.builds, 2 * static_cast<uint64_t>(it.inst) + it.aux);
   if (!windowed(p)) return;
   const int32_t kmin = p.map.dstate[kDKmin];
   const uint32_t nwin = p.nwin;
-  for (uint32_t w = threadIdx.x; w < nwin; w += blockDim.x) cur[w] = 0;
-  __syncthreads();
-  for (uint64_t i = it.begin + threadIdx.x; i < it.end; i += blockDim.x) {
-    const int32_t key = static_cast<int32_t>(load_elem(p.keys, p.type, build_row(p, i)));
-    atomicAdd(cur + (static_cast<uint32_t>(key - kmin) >> kWinBits), 1u);
+  const uint32_t m = static_cast<uint32_t>(it.end - it.begin);  // <= kBuildChunk
+  for (uint32_t w = threadIdx.x; w < nwin; w += blockDim.x) L.cur[w] = 0;
+  uint64_t x[kWinRows];
+  uint32_t wq[kWinRows], rank[kWinRows];
+#pragma unroll
+  for (int u = 0; u < kWinRows; ++u) {
+    const uint32_t i = u * blockDim.x + threadIdx.x;
+    if (i < m) {
+      const int64_t r = build_row(p, it.begin + i);
+      const int32_t key = static_cast<int32_t>(load_elem(p.keys, p.type, r));
+      const int32_t pay = static_cast<int32_t>(load_elem(p.val_col, p.val_type, r));
+      x[u] = static_cast<uint64_t>(static_cast<uint32_t>(key)) |
+             static_cast<uint64_t>(static_cast<uint32_t>(pay)) << 32;
+      wq[u] = static_cast<uint32_t>(key - kmin) >> kWinBits;
+    }
   }
   __syncthreads();
-  for (uint32_t w = threadIdx.x; w < nwin; w += blockDim.x) {
-    const uint32_t c = cur[w];
-    cur[w] = c ? atomicAdd(p.wcursor + w, c) : 0u;
+#pragma unroll
+  for (int u = 0; u < kWinRows; ++u)
+    if (u * blockDim.x + threadIdx.x < m) rank[u] = lds_fetch_add_u32(L.cur + wq[u], 1u);
+  __syncthreads();
+  // offsets within the item and the global write bases, windows
+  // [tid * kWinOwn, tid * kWinOwn + kWinOwn) per thread
+  const uint32_t w0 = threadIdx.x * kWinOwn;
+  uint32_t c[kWinOwn], sum = 0;
+#pragma unroll
+  for (uint32_t e = 0; e < kWinOwn; ++e) {
+    c[e] = w0 + e < nwin ? L.cur[w0 + e] : 0u;
+    sum += c[e];
+  }
+  const int lane = lane_id();
+  const int wave = threadIdx.x / kWave;
+  uint32_t incl = sum;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t t = __shfl_up(incl, off, kWave);
+    if (lane >= off) incl += t;
+  }
+  if (lane == kWave - 1) L.wave[wave] = incl;
+  __syncthreads();
+  uint32_t off = incl - sum;
+  for (int w = 0; w < wave; ++w) off += L.wave[w];
+  uint32_t base[kWinOwn];
+#pragma unroll
+  for (uint32_t e = 0; e < kWinOwn; ++e) {
+    base[e] = 0;
+    if (w0 + e < nwin) {
+      if (c[e]) base[e] = atomicAdd(p.wcursor + w0 + e, c[e]) - off;  // modulo 2^32
+      L.cur[w0 + e] = off;
+      off += c[e];
+    }
   }
   __syncthreads();
-  for (uint64_t i = it.begin + threadIdx.x; i < it.end; i += blockDim.x) {
-    const int64_t r = build_row(p, i);
-    const int32_t key = static_cast<int32_t>(load_elem(p.keys, p.type, r));
-    const int32_t pay = static_cast<int32_t>(load_elem(p.val_col, p.val_type, r));
-    const uint32_t at = atomicAdd(cur + (static_cast<uint32_t>(key - kmin) >> kWinBits), 1u);
-    p.wpairs[at] = static_cast<uint64_t>(static_cast<uint32_t>(key)) |
-                   static_cast<uint64_t>(static_cast<uint32_t>(pay)) << 32;
+#pragma unroll
+  for (int u = 0; u < kWinRows; ++u) {
+    if (u * blockDim.x + threadIdx.x < m) {
+      const uint32_t at = L.cur[wq[u]] + rank[u];
+      L.stage[at] = x[u];
+      L.win[at] = static_cast<uint16_t>(wq[u]);
+    }
   }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t e = 0; e < kWinOwn; ++e)
+    if (w0 + e < nwin) L.cur[w0 + e] = base[e];
+  __syncthreads();
+  for (uint32_t s2 = threadIdx.x; s2 < m; s2 += blockDim.x)
+    p.wpairs[L.cur[L.win[s2]] + s2] = L.stage[s2];
 }
 
 // One workgroup per window: its keys' bits (an LDS atomic OR each; a bit
@@ -883,7 +945,7 @@ void launch_batch_build(const BatchParams& b, hipStream_t s) {
   if (b.nwin > 0) {
     hipLaunchKernelGGL(batch_win_count_kernel, dim3(b.nbuild), dim3(256), 0, s, b);
     hipLaunchKernelGGL(batch_win_scan_kernel, dim3(2 * b.nplans), dim3(kWinScanThreads), 0, s, b);
-    hipLaunchKernelGGL(batch_win_scatter_kernel, dim3(b.nbuild), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(batch_win_scatter_kernel, dim3(b.nbuild), dim3(kWinScatterThreads), 0, s, b);
     hipLaunchKernelGGL(batch_win_build_kernel, dim3(b.nwin), dim3(kWinThreads), 0, s, b);
   }
   if (b.nslice > 0) {
