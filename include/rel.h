@@ -464,7 +464,7 @@ size_t rel_pipeline_batch_ws(const rel_pipeline_desc* d, int n);
  * aggregation pass's LDS table (at most 1024 partitions: plans needing more
  * keep the atomics); a power of two sets the partition count (clamped to
  * 1024). Record regions take 2 x (rows x record bytes) of ws per plan, in
- * plan order while the batch's records fit 32 GiB; later plans keep the
+ * plan order while the batch's records fit 64 GiB; later plans keep the
  * atomics.
  *   d, n     1..65536 plans of one shape: the same number of dims, and for
  *            each dim the same key type and payload presence. Per-plan
