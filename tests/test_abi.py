@@ -364,3 +364,51 @@ def test_string_groupby_validation_and_workspace():
     # a workspace sized without the dictionary is too small for its codes
     assert call(coded, plain) == rel.REL_ENOMEM
     assert call(rel.Strings(0x4000, 0x5000, None, 500, 1000), plain) == rel.REL_EINVAL
+
+
+def _group_plan(fact_len, max_groups, t=None):
+    """One join + group-by description (int32 foreign keys into a 1000-key
+    dim with an int32 payload as the group key, SUM of an int64 column and
+    COUNT) over fake device addresses: workspace sizing reads no data."""
+    fact = (rel.Column * 2)(col(fact_len, 2), col(fact_len, 3, data=0x2000))
+    dims = (rel.Dim * 1)(rel.Dim(0, 1, col(1000, 2, data=0x3000), col(1000, 2, data=0x4000)))
+    keys = (rel.KeyRef * 1)(rel.KeyRef(1, 0))
+    aggs = (rel.Agg * 2)(rel.Agg(0, 1), rel.Agg(1, 0))
+    d = rel.PipelineDesc(ctypes.cast(fact, ctypes.POINTER(rel.Column)), 2, None, 0,
+                         ctypes.cast(dims, ctypes.POINTER(rel.Dim)), 1,
+                         ctypes.cast(keys, ctypes.POINTER(rel.KeyRef)), 1,
+                         ctypes.cast(aggs, ctypes.POINTER(rel.Agg)), 2, max_groups,
+                         ctypes.pointer(t) if t is not None else None)
+    return d, [fact, dims, keys, aggs, t]
+
+
+def test_batch_record_workspace():
+    """A batched plan whose groups outgrow the LDS table takes two record
+    regions of 12 bytes a row (32-bit keys, one value column): the fused
+    pass's runs and the partitioned copy. tuning.fanout -1 takes none, and
+    records stop once a batch's regions would pass 64 GiB."""
+    L = rel.lib()
+    rows = 10_000_000
+    d, keep = _group_plan(rows, 100_000)
+    off_t = rel.tuning(fanout=-1)
+    d_off, keep2 = _group_plan(rows, 100_000, off_t)
+    with_rec = L.rel_pipeline_batch_ws(ctypes.byref(d), 1)
+    without = L.rel_pipeline_batch_ws(ctypes.byref(d_off), 1)
+    assert with_rec > 0 and without > 0
+    extra = with_rec - without
+    assert 2 * rows * 12 <= extra <= 2 * rows * 12 + (64 << 20), extra
+    # few groups: the LDS table holds them, no records
+    small, keep3 = _group_plan(rows, 100)
+    small_off, keep4 = _group_plan(rows, 100, off_t)
+    assert L.rel_pipeline_batch_ws(ctypes.byref(small), 1) == \
+        L.rel_pipeline_batch_ws(ctypes.byref(small_off), 1)
+    # the 64 GiB bound: a 2^31-row plan's records (about 51.5 GB) fit once
+    big = 1 << 31
+    descs = (rel.PipelineDesc * 2)()
+    b0, k0 = _group_plan(big, 100_000)
+    b1, k1 = _group_plan(big, 100_000)
+    descs[0], descs[1] = b0, b1
+    one = L.rel_pipeline_batch_ws(descs, 1)
+    two = L.rel_pipeline_batch_ws(descs, 2)
+    assert one > 2 * big * 12
+    assert two - one < 2 * big * 12  # the second plan keeps the atomics
