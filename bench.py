@@ -408,20 +408,26 @@ def bench_batch(args, torch, datagen, rel) -> dict:
             best = res
     if args.tune_cache_out:
         cache.save(args.tune_cache_out)
+    # the top-level figures come from the faster configuration, default or
+    # tuned, each against its own sequential calls
+    tuned = best
+    top, top_from = (default, "default") if min(default["batched_ms"], default["graph_ms"]) <= \
+        min(tuned["batched_ms"], tuned["graph_ms"]) else (tuned, "tuned")
     alg = 12 * n_probe + 8 * n_build
-    best_ms = min(best["batched_ms"], best["graph_ms"])
+    best_ms = min(top["batched_ms"], top["graph_ms"])
     return {
         "workload": f"{len(shapes)} join+group-by instances, log-uniform build 1k-4M, "
                     f"probe 10k-50M, groups 8-100k",
         "instances": len(shapes), "probe_rows": n_probe, "build_rows": n_build,
         "default": {**default, "identical_results": same_default},
         **({"above_2k_groups_alone": above_2k} if above_2k else {}),
-        "tuned": best,
+        "tuned": tuned,
         "autotune": {"buckets": len(by_bucket), "seconds": tune_s, "batch_seconds": tune_batch_s},
+        "top_level_from": top_from,
         "batched_rows_per_s": n_probe / (best_ms * 1e-3),
-        "sequential_rows_per_s": n_probe / (best["sequential_ms"] * 1e-3),
-        "speedup_vs_sequential": best["sequential_ms"] / best_ms,
-        "identical_results": same_default and best["identical_results"],
+        "sequential_rows_per_s": n_probe / (top["sequential_ms"] * 1e-3),
+        "speedup_vs_sequential": top["sequential_ms"] / best_ms,
+        "identical_results": same_default and tuned["identical_results"],
         "algorithmic_bytes": alg, "hbm_frac_step": alg / (best_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
     }
 
