@@ -377,9 +377,18 @@ __global__ void __launch_bounds__(256) batch_win_count_kernel(BatchParams b) {
   const uint32_t nwin = p.nwin;
   for (uint32_t w = threadIdx.x; w < nwin; w += blockDim.x) hist[w] = 0;
   __syncthreads();
-  for (uint64_t i = it.begin + threadIdx.x; i < it.end; i += blockDim.x) {
-    const int32_t key = static_cast<int32_t>(load_elem(p.keys, p.type, build_row(p, i)));
-    atomicAdd(hist + (static_cast<uint32_t>(key - kmin) >> kWinBits), 1u);
+  // four rows per thread and step, their loads in flight together
+  for (uint64_t i0 = it.begin + threadIdx.x; i0 < it.end; i0 += 4 * blockDim.x) {
+    int32_t key[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint64_t i = i0 + u * blockDim.x;
+      key[u] = i < it.end ? static_cast<int32_t>(load_elem(p.keys, p.type, build_row(p, i))) : kmin;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + u * blockDim.x < it.end)
+        atomicAdd(hist + (static_cast<uint32_t>(key[u] - kmin) >> kWinBits), 1u);
   }
   __syncthreads();
   for (uint32_t w = threadIdx.x; w < nwin; w += blockDim.x)
@@ -550,15 +559,27 @@ __global__ void __launch_bounds__(kWinThreads) batch_win_build_kernel(BatchParam
   const uint32_t words = (span + 31) / 32;
   for (uint32_t t = threadIdx.x; t < words; t += blockDim.x) bits[t] = 0;
   __syncthreads();
-  for (uint32_t i = begin + threadIdx.x; i < end; i += blockDim.x) {
-    const uint64_t pr = p.wpairs[i];
-    const uint32_t off = static_cast<uint32_t>(static_cast<int32_t>(pr) - kmin) - static_cast<uint32_t>(lo);
-    const uint32_t bit = 1u << (off & 31);
-    if (atomicOr(bits + (off >> 5), bit) & bit) {
-      *m.dup = 1;
-      continue;
+  // four pairs per thread and step, their loads in flight together
+  constexpr int kU = 4;
+  for (uint32_t i0 = begin + threadIdx.x; i0 < end; i0 += kU * blockDim.x) {
+    uint64_t pr[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t i = i0 + u * blockDim.x;
+      if (i < end) pr[u] = __builtin_nontemporal_load(p.wpairs + i);
     }
-    vals[off] = static_cast<uint32_t>(static_cast<int32_t>(pr >> 32)) - static_cast<uint32_t>(pmin);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (i0 + u * blockDim.x >= end) continue;
+      const uint32_t off =
+          static_cast<uint32_t>(static_cast<int32_t>(pr[u]) - kmin) - static_cast<uint32_t>(lo);
+      const uint32_t bit = 1u << (off & 31);
+      if (atomicOr(bits + (off >> 5), bit) & bit) {
+        *m.dup = 1;
+        continue;
+      }
+      vals[off] = static_cast<uint32_t>(static_cast<int32_t>(pr[u] >> 32)) - static_cast<uint32_t>(pmin);
+    }
   }
   __syncthreads();
   uint32_t* out = m.dbits + (lo >> 5);
