@@ -424,3 +424,16 @@ def test_batch_records_graph_replays():
         x = torch.arange(1 << 20, device="cuda", dtype=torch.int64)
         assert int(x.sum().item()) == (1 << 20) * ((1 << 20) - 1) // 2
     b.release()
+
+
+def test_batch_records_beside_an_lds_table():
+    """A tuning that keeps an LDS group table (1024 slots) for plans with
+    records: rows whose groups hold an LDS slot are flushed from it, the
+    others become records, and both reach the one global table. Uniform and
+    Zipf-skewed groups (the hot ones stay in LDS)."""
+    announce("batch records with an LDS table")
+    specs = record_specs(1414)[:4]
+    t = rel.tuning(lds_slots=1024)
+    b = run_tuned(specs, [t] * len(specs))
+    for i, (spec, plan) in enumerate(zip(specs, b.plans)):
+        assert_groups(plan.result(), oracle_of(spec), spec[4], f"plan {i}")
