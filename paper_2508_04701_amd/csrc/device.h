@@ -425,6 +425,26 @@ __device__ __forceinline__ int cset_bucket_count(uint4 q, uint32_t target, bool&
   return n;
 }
 
+// Whether one 16-byte bucket holds `target` at displacement d (for probes
+// that stop at the first match), with `open` as above. The eight entries are
+// compared as 16-bit pairs: the minimum of entry ^ target is zero exactly
+// when some entry equals the target, and the maximum of the entries is
+// kCsetEmpty exactly when one is empty (stored entries are at most
+// (kCsetMaxDisp << 14) | 0x3FFF, below it).
+typedef unsigned short U16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ U16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(U16x2, v); }
+__device__ __forceinline__ bool cset_bucket_has(uint4 q, uint32_t target, bool& open) {
+  static_assert(((static_cast<uint32_t>(kCsetMaxDisp) << 14) | 0x3FFFu) < kCsetEmpty);
+  const uint32_t t2 = target * 0x10001u;
+  const U16x2 m = __builtin_elementwise_min(
+      __builtin_elementwise_min(as_u16x2(q.x ^ t2), as_u16x2(q.y ^ t2)),
+      __builtin_elementwise_min(as_u16x2(q.z ^ t2), as_u16x2(q.w ^ t2)));
+  const U16x2 e = __builtin_elementwise_max(__builtin_elementwise_max(as_u16x2(q.x), as_u16x2(q.y)),
+                                            __builtin_elementwise_max(as_u16x2(q.z), as_u16x2(q.w)));
+  open = (e.x == kCsetEmpty) | (e.y == kCsetEmpty);
+  return (m.x == 0) | (m.y == 0);
+}
+
 // Cursor over the matches of one key: `pos` walks the probe chain (or the
 // out-of-band list when `oob`); next() yields one match per call.
 struct MapCursor {

@@ -488,7 +488,7 @@ __device__ __forceinline__ int probe_examine(const PipeDim& d, int64_t key, uint
     uint32_t r;
     cset_split(c, static_cast<int32_t>(key), b0, r);
     bool open;
-    if (cset_bucket_count(q, (st << 14) | r, open) > 0) {
+    if (cset_bucket_has(q, (st << 14) | r, open)) {
       st = kResolved;
       return 1;
     }

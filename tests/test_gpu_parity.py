@@ -618,6 +618,48 @@ def test_pipeline_large_membership_dim():
     assert_groups(got, want, aggs, "compact set")
 
 
+@pytest.mark.parametrize("dim_lds", [-1, 0])
+def test_pipeline_unique_compact_set_star_shape(dim_lds):
+    """The star plan's shape (date predicate, a membership dim, a payload dim,
+    keys from the payload and an int8 column, four aggregates over one int64
+    column) with a unique 900k-key membership dim in hash tables: the plan
+    runs the specialised kernel, whose compact-set probe tests a bucket's
+    eight entries at once. 40 crafted keys share one home bucket, so probes
+    walk the displaced entries and the overflow set; fact keys mix members,
+    non-members and the crafted keys. With the default dim LDS budget the
+    1000-key payload dim is copied into LDS and the general kernel runs."""
+    announce("pipeline unique compact set, star shape", dim_lds)
+    r = rng(32)
+    nd = 900_000
+    crafted = []
+    for rem in range(40):
+        k = _fmix32_inverse((777 << 14) | rem)
+        crafted.append(k - 2**32 if k >= 2**31 else k)
+    keys = r.choice(2**31 - 1, size=nd + 200, replace=False).astype(np.int64) - 2**30
+    keys = np.setdiff1d(keys, np.array(crafted, np.int64))[:nd]
+    r.shuffle(keys)
+    dim_a = np.concatenate([keys, np.array(crafted, np.int64)]).astype(np.int32)
+    nb = 1000
+    dim_b = r.choice(2**31 - 1, size=nb, replace=False).astype(np.int32)
+    region = r.integers(0, 5, size=nb).astype(np.int32)
+    n = 300_001
+    fk_a = np.concatenate([r.choice(dim_a, size=n - 3000), r.integers(-2**31, 2**31 - 1, size=2000),
+                           np.repeat(np.array(crafted, np.int64), 25)]).astype(np.int32)
+    r.shuffle(fk_a)
+    fk_b = r.choice(dim_b, size=n)
+    fk_b[r.random(n) < 0.05] = -7  # not a dim-B key
+    date = r.integers(0, 2557, size=n).astype(np.int32)
+    price = r.integers(-10**9, 10**9, size=n).astype(np.int64)
+    flag = r.integers(0, 3, size=n).astype(np.int8)
+    fact = [fk_a, fk_b, date, price, flag]
+    dims = [dict(fk=0, key=dim_a, payload=None), dict(fk=1, key=dim_b, payload=region)]
+    aggs = [("sum", 3), ("count", None), ("avg", 3), ("min", 3), ("max", 3)]
+    t = rel.tuning(flags=rel.TUNE_NO_DIRECT, dim_lds_bytes=dim_lds)
+    got, want = run_both(fact, [(2, "lt", 2000)], dims, [("dim", 1), ("fact", 4)], aggs,
+                         max_groups=64, t=t)
+    assert_groups(got, want, aggs, "unique compact set")
+
+
 def _direct_case(r, name, n_dim=20_000, n_fact=150_000):
     """A dim with int32 keys laid out to reach one path of the direct
     tables: the full key range, a partial range (presence bitmap), payload
